@@ -1,0 +1,169 @@
+/*
+ * nb_oracle.c -- FP64 brute-force reference for the short-range nonbonded
+ * energy, forces, virial and parameter gradients.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the GPU library is
+ * checked against.  Only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark may load it.  It shares no code, header or constant generator
+ * with the GPU library.
+ *
+ * What it computes (ACEMD paper, section 3: the non-bonded force term is the
+ * full Lennard-Jones plus electrostatic interaction of every atom pair within the
+ * cutoff R, with bonded pairs excluded; long-range electrostatics use PME, whose
+ * short-range part is the Ewald real-space term):
+ *
+ *   d_ij = x_i - x_j - L * rint((x_i - x_j) / L)      per dimension (minimum image)
+ *   a pair (i != j) counts iff |d_ij|^2 < R^2 and (i, j) is not excluded, where an
+ *   exclusion listed in either atom's row excludes the pair both ways
+ *   sigma_ij = (sigma_ti + sigma_tj) / 2,  eps_ij = sqrt(eps_ti * eps_tj)
+ *   u_ij = 4 eps_ij [(sigma_ij/r)^12 - (sigma_ij/r)^6] + k_e q_i q_j erfc(beta r) / r
+ *   F_i  = sum_j f_ij d_ij with
+ *   f_ij = 24 eps_ij [2 (sigma_ij/r)^12 - (sigma_ij/r)^6] / r^2
+ *        + k_e q_i q_j [erfc(beta r) / r^3 + (2 beta / sqrt(pi)) exp(-beta^2 r^2) / r^2]
+ *
+ * The evaluation is "row" based and deliberately plain: for every requested atom
+ * i it loops over all N atoms j (an O(N) row, O(N^2) overall), so forces on a
+ * subset of atoms (the sampled mode used for million-atom boxes) come from the
+ * same code as a full evaluation.  Per-row outputs:
+ *
+ *   force[i]  = F_i
+ *   energy[i] = (1/2) sum_j u_ij                        (per-atom energy split)
+ *   phi[i]    = sum_j k_e q_j erfc(beta r)/r             (= dE/dq_i)
+ *   a_sig[i]  = sum_j (1/2) du_ij/dsigma_ij              (sum over t_i = t gives dE/dsigma_t)
+ *   b_eps[i]  = sum_j (1/2) u^LJ_ij                      (sum over t_i = t, / eps_t gives dE/deps_t)
+ *   virial    = (1/2) sum_rows sum_j d_ij (x) F_ij       (9 entries, row-major a,b)
+ *
+ * Everything is IEEE double with libm erfc/exp; no fast-math.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Symmetric closure of the exclusion CSR: row i of the result lists every j with
+ * j in row(i) or i in row(j).  Returns 0 on success, -1 on bad input. */
+static int sym_exclusions(int64_t n, const int32_t *off, const int32_t *idx,
+                          int64_t **s_off_out, int32_t **s_idx_out) {
+  int64_t *cnt = calloc((size_t)n + 1, sizeof(int64_t));
+  if (!cnt) return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    if (off[i + 1] < off[i]) { free(cnt); return -1; }
+    for (int64_t k = off[i]; k < off[i + 1]; ++k) {
+      int64_t j = idx[k];
+      if (j < 0 || j >= n) { free(cnt); return -1; }
+      cnt[i + 1]++;
+      cnt[j + 1]++;
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+  int32_t *s_idx = malloc(sizeof(int32_t) * (size_t)(cnt[n] > 0 ? cnt[n] : 1));
+  int64_t *fill = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  if (!s_idx || !fill) { free(cnt); free(s_idx); free(fill); return -1; }
+  for (int64_t i = 0; i < n; ++i) fill[i] = cnt[i];
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = off[i]; k < off[i + 1]; ++k) {
+      int64_t j = idx[k];
+      s_idx[fill[i]++] = (int32_t)j;
+      s_idx[fill[j]++] = (int32_t)i;
+    }
+  free(fill);
+  *s_off_out = cnt;
+  *s_idx_out = s_idx;
+  return 0;
+}
+
+int nbo_rows(int64_t n, const double *pos, const double *q, const int32_t *type,
+             int32_t ntypes, const double *sigma, const double *eps,
+             const int32_t *excl_off, const int32_t *excl_idx, const double *box,
+             double cutoff, double beta, double ke,
+             int64_t n_rows, const int64_t *rows,
+             double *force, double *energy, double *phi, double *a_sig, double *b_eps,
+             double *virial, double *e_lj_out, double *e_c_out, int64_t *pair_count_out,
+             int nthreads) {
+  if (n < 0 || ntypes <= 0 || cutoff <= 0.0 || beta < 0.0) return -1;
+  for (int a = 0; a < 3; ++a)
+    if (!(box[a] > 0.0) || !(cutoff < 0.5 * box[a])) return -2;
+  for (int64_t i = 0; i < n; ++i)
+    if (type[i] < 0 || type[i] >= ntypes) return -3;
+  int64_t *s_off = NULL;
+  int32_t *s_idx = NULL;
+  if (sym_exclusions(n, excl_off, excl_idx, &s_off, &s_idx) != 0) return -4;
+  const int64_t m = rows ? n_rows : n;
+  const double rc2 = cutoff * cutoff;
+  const double two_over_sqrt_pi = 2.0 / sqrt(acos(-1.0));
+  double e_lj = 0.0, e_c = 0.0;
+  double vir[9] = {0};
+  int64_t pairs = 0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+
+#pragma omp parallel reduction(+ : e_lj, e_c, pairs) reduction(+ : vir[:9])
+  {
+    /* stamp[j] == row + 1 marks j as excluded from the current row. */
+    int64_t *stamp = calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t r = 0; r < m; ++r) {
+      const int64_t i = rows ? rows[r] : r;
+      for (int64_t k = s_off[i]; k < s_off[i + 1]; ++k) stamp[s_idx[k]] = i + 1;
+      double f[3] = {0, 0, 0};
+      double ei = 0.0, ph = 0.0, as = 0.0, be = 0.0;
+      for (int64_t j = 0; j < n; ++j) {
+        if (j == i || stamp[j] == i + 1) continue;
+        double d[3];
+        for (int a = 0; a < 3; ++a) {
+          double t = pos[3 * i + a] - pos[3 * j + a];
+          d[a] = t - box[a] * rint(t / box[a]);
+        }
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (!(r2 < rc2)) continue;
+        const double r = sqrt(r2);
+        /* Lennard-Jones 12-6 with Lorentz-Berthelot combination. */
+        const double sij = 0.5 * (sigma[type[i]] + sigma[type[j]]);
+        const double eij = sqrt(eps[type[i]] * eps[type[j]]);
+        const double s2 = (sij * sij) / r2;
+        const double s6 = s2 * s2 * s2;
+        const double s12 = s6 * s6;
+        const double u_lj = 4.0 * eij * (s12 - s6);
+        const double f_lj = 24.0 * eij * (2.0 * s12 - s6) / r2;
+        /* d u_lj / d sigma_ij = (4 eps / sigma)(12 s^12 - 6 s^6); zero if sigma_ij = 0. */
+        const double du_dsig = sij > 0.0 ? 4.0 * eij * (12.0 * s12 - 6.0 * s6) / sij : 0.0;
+        /* Ewald real-space Coulomb. */
+        const double erfc_br = erfc(beta * r);
+        const double u_c = ke * q[i] * q[j] * erfc_br / r;
+        const double f_c = ke * q[i] * q[j] *
+                           (erfc_br / (r2 * r) + beta * two_over_sqrt_pi * exp(-beta * beta * r2) / r2);
+        const double fs = f_lj + f_c;
+        for (int a = 0; a < 3; ++a) f[a] += fs * d[a];
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) vir[3 * a + b] += 0.5 * d[a] * fs * d[b];
+        ei += 0.5 * (u_lj + u_c);
+        e_lj += 0.5 * u_lj;
+        e_c += 0.5 * u_c;
+        ph += ke * q[j] * erfc_br / r;
+        as += 0.5 * du_dsig;
+        be += 0.5 * u_lj;
+        pairs += 1;
+      }
+      if (force) for (int a = 0; a < 3; ++a) force[3 * r + a] = f[a];
+      if (energy) energy[r] = ei;
+      if (phi) phi[r] = ph;
+      if (a_sig) a_sig[r] = as;
+      if (b_eps) b_eps[r] = be;
+    }
+    free(stamp);
+  }
+  if (virial) for (int k = 0; k < 9; ++k) virial[k] = vir[k];
+  if (e_lj_out) *e_lj_out = e_lj;
+  if (e_c_out) *e_c_out = e_c;
+  /* Every unordered pair was visited from both of its atoms when all rows ran. */
+  if (pair_count_out) *pair_count_out = rows ? pairs : pairs / 2;
+  free(s_off);
+  free(s_idx);
+  return 0;
+}

@@ -1,0 +1,126 @@
+"""FP64 CPU oracle for the short-range nonbonded hot path (ctypes wrapper of nb_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg may use this module; the GPU library never does.  It shares no
+code with the GPU library.
+
+The definitions it evaluates are written out in ``nb_oracle.c`` (ACEMD paper,
+section 3: cutoff Lennard-Jones plus electrostatics with bonded exclusions, the
+electrostatics being the real-space part of the Ewald/PME split).  Parameter
+gradients follow from the per-atom partial sums the C code returns:
+
+    dE/dq_i     = phi_i
+    dE/dsigma_t = sum_{i: t_i = t} a_i
+    dE/deps_t   = (1/eps_t) sum_{i: t_i = t} b_i      (0 where eps_t = 0: the derivative
+                                                     of sqrt(eps_t eps_j) is unbounded there)
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nb_oracle.c")
+_LIB = os.path.join(_HERE, "libnb_oracle.so")
+
+# Coulomb constant e^2 N_A / (4 pi eps0) in kJ mol^-1 A e^-2, from the CODATA 2018
+# exact values of e and N_A and the recommended eps0.
+_E = 1.602176634e-19
+_NA = 6.02214076e23
+_EPS0 = 8.8541878128e-12
+COULOMB_K = _E * _E / (4.0 * np.pi * _EPS0) * 1e10 * _NA / 1e3
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library with gcc (OpenMP, -O2, IEEE arithmetic)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.nbo_rows.restype = ctypes.c_int
+        lib.nbo_rows.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int32, P, P, P, P, P,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_int64, P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def evaluate(pos, charge, types, sigma, eps, excl_offset, excl_index, box, cutoff, beta,
+             ke: float = COULOMB_K, rows: Optional[np.ndarray] = None, nthreads: int = 0) -> dict:
+    """Evaluate the brute-force sums for every atom (rows=None) or for the atoms in ``rows``.
+
+    Inputs are promoted to float64; pass exactly the values the device computes with.
+    Returns per-row arrays (force [m,3], energy [m], phi [m], a_sig [m], b_eps [m]) and
+    totals over the evaluated rows (virial [3,3], e_lj, e_c, energy_total, pairs).  With
+    rows=None also the per-type gradients dsigma [T] and deps [T].
+    """
+    lib = _load()
+    pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
+    n = pos.shape[0]
+    q = np.ascontiguousarray(charge, np.float64)
+    t = np.ascontiguousarray(types, np.int32)
+    sig = np.ascontiguousarray(sigma, np.float64)
+    ep = np.ascontiguousarray(eps, np.float64)
+    eo = np.ascontiguousarray(excl_offset, np.int32)
+    ei = np.ascontiguousarray(excl_index, np.int32)
+    if ei.size == 0:
+        ei = np.zeros(1, np.int32)
+    bx = np.ascontiguousarray(box, np.float64).reshape(3)
+    r = None if rows is None else np.ascontiguousarray(rows, np.int64)
+    m = n if r is None else r.shape[0]
+    force = np.zeros((m, 3))
+    energy = np.zeros(m)
+    phi = np.zeros(m)
+    a_sig = np.zeros(m)
+    b_eps = np.zeros(m)
+    vir = np.zeros(9)
+    e_lj = ctypes.c_double()
+    e_c = ctypes.c_double()
+    npairs = ctypes.c_int64()
+    rc = lib.nbo_rows(n, _ptr(pos), _ptr(q), _ptr(t), int(sig.shape[0]), _ptr(sig), _ptr(ep),
+                      _ptr(eo), _ptr(ei), _ptr(bx), float(cutoff), float(beta), float(ke),
+                      m, _ptr(r), _ptr(force), _ptr(energy), _ptr(phi), _ptr(a_sig), _ptr(b_eps),
+                      _ptr(vir), ctypes.byref(e_lj), ctypes.byref(e_c), ctypes.byref(npairs),
+                      int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the input (code {rc})")
+    out = dict(force=force, energy=energy, phi=phi, a_sig=a_sig, b_eps=b_eps,
+               virial=vir.reshape(3, 3), e_lj=e_lj.value, e_c=e_c.value,
+               energy_total=e_lj.value + e_c.value, pairs=int(npairs.value))
+    if r is None:
+        T = sig.shape[0]
+        dsig = np.zeros(T)
+        bsum = np.zeros(T)
+        np.add.at(dsig, t, a_sig)
+        np.add.at(bsum, t, b_eps)
+        deps = np.where(ep > 0, bsum / np.where(ep > 0, ep, 1.0), 0.0)
+        out.update(dsigma=dsig, deps=deps)
+    return out
+
+
+def evaluate_system(system, rows=None, nthreads: int = 0, ke: float = COULOMB_K) -> dict:
+    """``evaluate`` on an object with the fields of ``systems.System``."""
+    return evaluate(system.pos, system.charge, system.type, system.sigma, system.eps,
+                    system.excl_offset, system.excl_index, system.box, system.cutoff,
+                    system.beta, ke=ke, rows=rows, nthreads=nthreads)

@@ -1,0 +1,370 @@
+"""Seeded synthetic workloads: TIP3P-like water boxes with and without a bead-chain solute.
+
+This module only builds inputs (positions, charges, Lennard-Jones type tables and
+exclusion lists).  It holds none of the nonbonded arithmetic, so both the HIP
+library's tests and the CPU oracle may take their inputs from it.
+
+The paper measures on biomolecular systems solvated in TIP3P water (DHFR, apoA1,
+Villin; section 5, Tables 3-5) that are not reproduced here.  These generators
+build stand-ins with the same density, charge model and exclusion structure:
+
+* water: rigid TIP3P-like geometry (O-H 0.9572 A, H-O-H 104.52 deg), charges
+  O -0.834 e and H +0.417 e, Lennard-Jones on O only (sigma 3.15061 A,
+  epsilon 0.6364 kJ/mol), intramolecular O-H1, O-H2, H1-H2 exclusions;
+* solute: a self-avoiding bead chain (bond 1.5 A) with random charges shifted to
+  a net charge of zero, eight Lennard-Jones types drawn from sigma U[2.5, 3.8] A
+  and epsilon U[0.1, 0.9] kJ/mol, and 1-2 / 1-3 exclusions (section 3 describes
+  the bonded exclusions the pair kernel must skip).
+
+Atoms are molecule-contiguous (solute first, then O, H1, H2 per water), so every
+exclusion sits within a small index window.  Units: Angstrom, e, kJ/mol.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+# Water model.
+OH_BOND = 0.9572
+HOH_ANGLE_DEG = 104.52
+Q_O = -0.834
+Q_H = 0.417
+SIGMA_O = 3.15061
+EPS_O = 0.6364
+MASS_WATER = 15.999 + 2 * 1.008  # g/mol
+MASS_BEAD = 14.027  # g/mol (CH2-like united atom; the chain recipe names no mass)
+AVOGADRO = 6.02214076e23
+
+# Type table shared by every system: 0 = water O, 1 = water H, 2..9 = solute.
+TYPE_O = 0
+TYPE_H = 1
+N_SOLUTE_TYPES = 8
+N_TYPES = 2 + N_SOLUTE_TYPES
+
+BOND = 1.5
+MIN_13 = 2.0
+MIN_BEAD = 3.0
+MIN_WATER_BEAD = 2.5
+
+
+@dataclasses.dataclass
+class System:
+    """One periodic system.  Arrays are numpy, positions in float64."""
+
+    name: str
+    pos: np.ndarray  # [N, 3] float64, wrapped into [0, L)
+    charge: np.ndarray  # [N] float64 (e)
+    type: np.ndarray  # [N] int32
+    sigma: np.ndarray  # [T] float64 (A)
+    eps: np.ndarray  # [T] float64 (kJ/mol)
+    excl_offset: np.ndarray  # [N+1] int32, CSR rows (both directions listed)
+    excl_index: np.ndarray  # [n_excl] int32, sorted within each row
+    box: np.ndarray  # [3] float64
+    cutoff: float
+    beta: float
+    seed: int
+    n_solute: int = 0
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    def rounded(self, dtype) -> "System":
+        """Copy whose positions and charges are rounded to ``dtype`` and promoted back.
+
+        The oracle is always given exactly the values the device receives.
+        """
+        s = dataclasses.replace(self)
+        s.pos = self.pos.astype(dtype).astype(np.float64)
+        s.charge = self.charge.astype(dtype).astype(np.float64)
+        return s
+
+
+def _random_rotations(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Uniform random rotation matrices from normalised Gaussian quaternions."""
+    qv = rng.standard_normal((n, 4))
+    qv /= np.linalg.norm(qv, axis=1, keepdims=True)
+    w, x, y, z = qv.T
+    r = np.empty((n, 3, 3))
+    r[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    r[:, 0, 1] = 2 * (x * y - z * w)
+    r[:, 0, 2] = 2 * (x * z + y * w)
+    r[:, 1, 0] = 2 * (x * y + z * w)
+    r[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    r[:, 1, 2] = 2 * (y * z - x * w)
+    r[:, 2, 0] = 2 * (x * z - y * w)
+    r[:, 2, 1] = 2 * (y * z + x * w)
+    r[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return r
+
+
+def _water_sites(rng: np.random.Generator, oxygens: np.ndarray) -> np.ndarray:
+    """[M,3] oxygen positions -> [3M,3] O,H1,H2 positions with random orientation."""
+    half = math.radians(HOH_ANGLE_DEG) / 2
+    local = np.array(
+        [[0.0, 0.0, 0.0],
+         [OH_BOND * math.sin(half), 0.0, OH_BOND * math.cos(half)],
+         [-OH_BOND * math.sin(half), 0.0, OH_BOND * math.cos(half)]]
+    )
+    rot = _random_rotations(rng, oxygens.shape[0])
+    atoms = oxygens[:, None, :] + np.einsum("mij,aj->mai", rot, local)
+    return atoms.reshape(-1, 3)
+
+
+def _type_table(rng: np.random.Generator):
+    sig = np.empty(N_TYPES)
+    eps = np.empty(N_TYPES)
+    sig[TYPE_O], eps[TYPE_O] = SIGMA_O, EPS_O
+    sig[TYPE_H], eps[TYPE_H] = 0.0, 0.0
+    sig[2:] = rng.uniform(2.5, 3.8, N_SOLUTE_TYPES)
+    eps[2:] = rng.uniform(0.1, 0.9, N_SOLUTE_TYPES)
+    return sig, eps
+
+
+def _minimage(d: np.ndarray, box: np.ndarray) -> np.ndarray:
+    return d - box * np.rint(d / box)
+
+
+class _Grid:
+    """Bucket grid for neighbour queries while placing beads (generator only)."""
+
+    def __init__(self, box: np.ndarray, width: float):
+        self.box = box
+        self.n = np.maximum((box // width).astype(int), 1)
+        self.w = box / self.n
+        self.cells = {}
+
+    def key(self, p):
+        c = np.floor(np.mod(p, self.box) / self.w).astype(int) % self.n
+        return (int(c[0]), int(c[1]), int(c[2]))
+
+    def add(self, idx, p):
+        self.cells.setdefault(self.key(p), []).append(idx)
+
+    def remove(self, idx, p):
+        self.cells[self.key(p)].remove(idx)
+
+    def near(self, p):
+        c = self.key(p)
+        seen = set()
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    k = ((c[0] + dx) % self.n[0], (c[1] + dy) % self.n[1], (c[2] + dz) % self.n[2])
+                    if k in seen:
+                        continue
+                    seen.add(k)
+                    yield from self.cells.get(k, ())
+
+
+def _chain(rng: np.random.Generator, n_beads: int, box: np.ndarray) -> np.ndarray:
+    """Self-avoiding bead chain: bond BOND, 1-3 distance >= MIN_13, other pairs >= MIN_BEAD."""
+    if n_beads == 0:
+        return np.zeros((0, 3))
+    grid = _Grid(box, MIN_BEAD)
+    pos = np.zeros((n_beads, 3))
+    pos[0] = rng.uniform(0, 1, 3) * box
+    grid.add(0, pos[0])
+    k = 1
+    fails = 0
+    while k < n_beads:
+        ok = False
+        for _ in range(64):
+            u = rng.standard_normal(3)
+            u /= np.linalg.norm(u)
+            p = pos[k - 1] + BOND * u
+            if k >= 2 and np.linalg.norm(_minimage(p - pos[k - 2], box)) < MIN_13:
+                continue
+            clash = False
+            for j in grid.near(p):
+                if j >= k - 2:
+                    continue
+                if np.linalg.norm(_minimage(p - pos[j], box)) < MIN_BEAD:
+                    clash = True
+                    break
+            if not clash:
+                ok = True
+                break
+        if ok:
+            pos[k] = p
+            grid.add(k, p)
+            k += 1
+            fails = 0
+        else:
+            # Trapped: back off a few beads and regrow.
+            fails += 1
+            back = min(k - 1, 4 * fails)
+            for j in range(k - back, k):
+                grid.remove(j, pos[j])
+            k -= back
+    return np.mod(pos, box)
+
+
+def _free_sites(n_side: int, box: np.ndarray, beads: np.ndarray) -> np.ndarray:
+    a = box / n_side
+    g = (np.arange(n_side) + 0.5)
+    sites = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3) * a
+    if beads.shape[0] == 0:
+        return sites
+    keep = np.ones(sites.shape[0], dtype=bool)
+    for start in range(0, beads.shape[0], 256):
+        b = beads[start:start + 256]
+        d = _minimage(sites[:, None, :] - b[None, :, :], box)
+        keep &= (np.einsum("sbk,sbk->sb", d, d) >= MIN_WATER_BEAD ** 2).all(axis=1)
+    return sites[keep]
+
+
+def _exclusions_csr(n: int, pairs: np.ndarray):
+    """Undirected pairs [P,2] -> CSR listing every pair in both rows, rows sorted."""
+    if pairs.size == 0:
+        return np.zeros(n + 1, np.int32), np.zeros(0, np.int32)
+    a = np.concatenate([pairs[:, 0], pairs[:, 1]])
+    b = np.concatenate([pairs[:, 1], pairs[:, 0]])
+    order = np.lexsort((b, a))
+    a, b = a[order], b[order]
+    off = np.zeros(n + 1, np.int64)
+    np.add.at(off, a + 1, 1)
+    return np.cumsum(off).astype(np.int32), b.astype(np.int32)
+
+
+def _assemble(name, seed, box, beads, bead_q, bead_t, waters_o, rng, sig, eps, cutoff, beta):
+    n_s = beads.shape[0]
+    n_w = waters_o.shape[0]
+    wat = _water_sites(rng, waters_o)
+    pos = np.mod(np.concatenate([beads, wat]), box)
+    q = np.concatenate([bead_q, np.tile([Q_O, Q_H, Q_H], n_w)])
+    t = np.concatenate([bead_t, np.tile([TYPE_O, TYPE_H, TYPE_H], n_w)]).astype(np.int32)
+    pairs = []
+    if n_s > 1:
+        i = np.arange(n_s - 1)
+        pairs.append(np.stack([i, i + 1], 1))
+    if n_s > 2:
+        i = np.arange(n_s - 2)
+        pairs.append(np.stack([i, i + 2], 1))
+    if n_w:
+        o = n_s + 3 * np.arange(n_w)
+        pairs += [np.stack([o, o + 1], 1), np.stack([o, o + 2], 1), np.stack([o + 1, o + 2], 1)]
+    pairs = np.concatenate(pairs) if pairs else np.zeros((0, 2), np.int64)
+    off, idx = _exclusions_csr(pos.shape[0], pairs)
+    return System(name=name, pos=pos, charge=q, type=t, sigma=sig.copy(), eps=eps.copy(),
+                  excl_offset=off, excl_index=idx, box=np.asarray(box, float), cutoff=float(cutoff),
+                  beta=float(beta), seed=seed, n_solute=n_s)
+
+
+def water_lattice(n_side: int, spacing: float, seed: int, cutoff: float, beta: float,
+                  n_waters: Optional[int] = None, name: str = "water") -> System:
+    """Waters with O on an n_side^3 lattice ((i+1/2)*spacing); optionally a random subset."""
+    rng = np.random.default_rng(seed)
+    sig, eps = _type_table(rng)
+    L = n_side * spacing
+    box = np.array([L, L, L])
+    g = (np.arange(n_side) + 0.5) * spacing
+    sites = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    if n_waters is not None and n_waters < sites.shape[0]:
+        sites = sites[np.sort(rng.choice(sites.shape[0], n_waters, replace=False))]
+    return _assemble(name, seed, box, np.zeros((0, 3)), np.zeros(0), np.zeros(0, np.int32), sites,
+                     rng, sig, eps, cutoff, beta)
+
+
+def solvated_chain(L: float, n_beads: int, n_waters: int, seed: int, cutoff: float, beta: float,
+                   n_side: Optional[int] = None, type_seed: Optional[int] = None,
+                   name: str = "chain+water") -> System:
+    """A self-avoiding bead chain in a cubic box, then waters on free lattice sites."""
+    rng = np.random.default_rng(seed)
+    trng = rng if type_seed is None else np.random.default_rng(type_seed)
+    sig, eps = _type_table(trng)
+    box = np.array([L, L, L], float)
+    beads = _chain(rng, n_beads, box)
+    q = rng.uniform(-0.5, 0.5, n_beads)
+    if n_beads:
+        q -= q.mean()
+    t = rng.integers(2, 2 + N_SOLUTE_TYPES, n_beads).astype(np.int32)
+    if n_side is None:
+        n_side = max(1, math.ceil(n_waters ** (1 / 3)))
+        while True:
+            free = _free_sites(n_side, box, beads)
+            if free.shape[0] >= n_waters:
+                break
+            n_side += 1
+    else:
+        free = _free_sites(n_side, box, beads)
+        if free.shape[0] < n_waters:
+            raise ValueError("not enough free lattice sites for the requested waters")
+    chosen = free[np.sort(rng.choice(free.shape[0], n_waters, replace=False))]
+    return _assemble(name, seed, box, beads, q, t, chosen, rng, sig, eps, cutoff, beta)
+
+
+# --- the five workloads -----------------------------------------------------------------
+
+def config1(seed: int = 1) -> System:
+    """216 waters (648 atoms) on a 6^3 lattice of 3.1 A, L = 18.6 A, rc 9 A, beta 0.34 /A."""
+    return water_lattice(6, 3.1, seed, 9.0, 0.34, name="water216")
+
+
+def config2(seed: int = 2) -> System:
+    """23,600 atoms, L = 60 A: a 2,000-bead chain plus 7,200 waters; rc 9 A, beta 0.34 /A."""
+    return solvated_chain(60.0, 2000, 7200, seed, 9.0, 0.34, n_side=22, name="chain2000+water7200")
+
+
+def config3(seed: int = 3) -> System:
+    """The 23.6k-atom chain-plus-water system used for gradients (same recipe as config 2)."""
+    s = solvated_chain(60.0, 2000, 7200, seed, 9.0, 0.34, n_side=22, name="chain2000+water7200")
+    return s
+
+
+def config4(seed: int = 4, n_systems: int = 64) -> List[System]:
+    """Uneven replicas: N log-uniform in [3000, 30000], density 0.95-1.05 g/cm^3,
+    solute fraction U[0, 0.1]; rc 9 A, beta 0.34 /A.  All share one type table."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(n_systems):
+        n_b = int(round(math.exp(rng.uniform(math.log(3000), math.log(30000)))))
+        frac = rng.uniform(0.0, 0.10)
+        n_s = int(round(frac * n_b))
+        n_w = int(round((n_b - n_s) / 3))
+        rho = rng.uniform(0.95, 1.05)
+        mass = n_w * MASS_WATER + n_s * MASS_BEAD
+        L = (mass / AVOGADRO / rho) ** (1 / 3) * 1e8
+        sub_seed = int(rng.integers(0, 2**31 - 1))
+        out.append(solvated_chain(L, n_s, n_w, sub_seed, 9.0, 0.34, type_seed=seed,
+                                  name=f"replica{b}"))
+    return out
+
+
+def config5(seed: int = 5) -> System:
+    """333,333 waters (999,999 atoms) on a random subset of a 70^3 lattice, L = 215 A,
+    rc 12 A, beta 0.26 /A."""
+    return water_lattice(70, 215.0 / 70, seed, 12.0, 0.26, n_waters=333_333, name="water333k")
+
+
+def water_box(n_waters: int, L: float, seed: int, cutoff: float = 9.0, beta: float = 0.34) -> System:
+    """Water at the lattice density closest to n_waters in an L box (for scans and tests)."""
+    n_side = max(1, math.ceil(n_waters ** (1 / 3)))
+    return water_lattice(n_side, L / n_side, seed, cutoff, beta, n_waters=n_waters,
+                         name=f"water{n_waters}")
+
+
+def concat_systems(systems: List[System]):
+    """Pack systems back to back (batch layout): returns a dict of concatenated arrays."""
+    offs = np.zeros(len(systems) + 1, np.int64)
+    offs[1:] = np.cumsum([s.n for s in systems])
+    excl_off = [np.zeros(1, np.int64)]
+    base = 0
+    for s in systems:
+        excl_off.append(s.excl_offset[1:].astype(np.int64) + base)
+        base += int(s.excl_offset[-1])
+    return dict(
+        atom_offset=offs,
+        pos=np.concatenate([s.pos for s in systems]),
+        charge=np.concatenate([s.charge for s in systems]),
+        type=np.concatenate([s.type for s in systems]),
+        excl_offset=np.concatenate(excl_off).astype(np.int32),
+        excl_index=np.concatenate([s.excl_index for s in systems]).astype(np.int32),
+        box=np.stack([s.box for s in systems]),
+        sigma=systems[0].sigma,
+        eps=systems[0].eps,
+    )
