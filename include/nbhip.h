@@ -1,0 +1,171 @@
+/*
+ * nbhip.h -- C ABI of the MI355X (gfx950) short-range nonbonded library.
+ *
+ * The library evaluates, for one or more periodic systems packed back to back,
+ * the short-range nonbonded interaction of the ACEMD paper (section 3): every
+ * atom pair closer than the cutoff R, not excluded as a bonded pair, interacts
+ * through a Lennard-Jones 12-6 term and the real-space part of the Ewald (PME)
+ * electrostatics, under minimum-image periodic boundaries:
+ *
+ *   u_ij = 4 eps_ij [(sigma_ij/r)^12 - (sigma_ij/r)^6] + k_e q_i q_j erfc(beta r)/r,
+ *   sigma_ij = (sigma_ti + sigma_tj)/2,  eps_ij = sqrt(eps_ti eps_tj),
+ *
+ * with the cutoff test r < R strict and no shift or switch.  Atoms are first
+ * binned into a cell list (section 3: one thread per atom computes its cell;
+ * cells a fraction of R wide), then a pair kernel visits the neighbouring cells.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked [device] are HIP device pointers; [host] are host pointers.
+ *   - The caller owns every buffer.  The library allocates no device memory and
+ *     keeps no device state between calls; all of its scratch lives in the
+ *     caller's workspace (size from nb_workspace_bytes).
+ *   - Every call only enqueues work on `stream` and returns; the only call that
+ *     synchronises is nb_read_status.
+ *   - Problems visible on the host are reported by the return code before any
+ *     work is enqueued; the message is available from nb_last_error().
+ *     Problems only visible on the device set bits in a status word inside the
+ *     workspace (NB_STATUS_*), read with nb_read_status.
+ *   - No C++ exception, abort or exit crosses this interface.
+ *   - Units: Angstrom, elementary charge, kJ/mol.
+ */
+#ifndef NBHIP_H
+#define NBHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NB_OK = 0,
+  NB_ERR_ARG = 1,        /* null pointer, negative or inconsistent size, bad option */
+  NB_ERR_BOX = 2,        /* a box length <= 0 or not finite, or R >= min(L)/2 */
+  NB_ERR_WORKSPACE = 3,  /* workspace NULL, misaligned or smaller than nb_workspace_bytes */
+  NB_ERR_HIP = 4,        /* a HIP runtime call failed; see nb_last_error */
+  NB_ERR_CAPACITY = 5    /* a size exceeds what the 32-bit indexing of the library supports */
+} nb_status;
+
+/* Bits of the device status word (nb_read_status).  They accumulate from
+ * nb_build_cells onwards; nb_build_cells clears them. */
+#define NB_STATUS_NONFINITE_POS 0x1u  /* a position was NaN or infinite (atom binned to cell 0) */
+#define NB_STATUS_BAD_TYPE 0x2u       /* a type index outside [0, n_types) (treated as type 0) */
+#define NB_STATUS_BAD_EXCLUSION 0x4u  /* an exclusion row not monotone or an index outside the system */
+#define NB_STATUS_FAR_EXCLUSION 0x8u  /* informational: some exclusion is more than 64 atoms apart in index */
+
+typedef enum {
+  NB_FP64 = 0,  /* double-precision pair arithmetic from double positions */
+  NB_MIXED = 1  /* single-precision pair arithmetic, double accumulation and reductions */
+} nb_precision;
+
+/*
+ * A batch of B >= 1 independent systems packed back to back: system b owns atoms
+ * [atom_offset[b], atom_offset[b+1]) of every per-atom array.  A single box is the
+ * batch B = 1.
+ */
+typedef struct {
+  int32_t n_systems;          /* B >= 1 */
+  const int64_t *atom_offset; /* [host] B+1 entries, atom_offset[0] = 0, non-decreasing; N = atom_offset[B] */
+  const double *box;          /* [host] 3*B orthorhombic box lengths (Lx, Ly, Lz) per system */
+  const void *pos;            /* [device] N*3 coordinates x,y,z per atom; float or double per pos_is_f64.
+                                 Any real value is accepted: coordinates are wrapped into the box. */
+  int32_t pos_is_f64;         /* 0: pos and charge are float; 1: double */
+  const void *charge;         /* [device] N charges (e), same type as pos */
+  const int32_t *type;        /* [device] N Lennard-Jones type indices in [0, n_types) */
+  const double *lj_sigma;     /* [device] n_types sigma_t (A); shared by the whole batch */
+  const double *lj_eps;       /* [device] n_types eps_t (kJ/mol), >= 0 */
+  int32_t n_types;            /* 1 <= n_types <= NB_MAX_TYPES */
+  const int32_t *excl_offset; /* [device] N+1 CSR row offsets into excl_index (global over the batch) */
+  const int32_t *excl_index;  /* [device] excluded partners of each atom, as indices local to its system.
+                                 A pair listed in either atom's row is excluded both ways (section 3
+                                 stores bonded exclusions as per-atom bitmaps over index distance
+                                 |i-j| <= 64; larger distances take a slower path). */
+} nb_system;
+
+#define NB_MAX_TYPES 64
+
+/* Kernel variants for nb_params.kernel. */
+#define NB_KERNEL_AUTO 0    /* library default for the precision (or the tuned choice passed in) */
+#define NB_KERNEL_ATOM 1    /* one lane per i atom, full neighbour shell, j read through the cache */
+#define NB_KERNEL_CLUSTER 2 /* 8 x 8 atom-cluster tiles in LDS with in-wave compaction of pairs */
+
+typedef struct {
+  double cutoff;      /* R (A): 0 < R < min(L)/2 for every system */
+  double ewald_beta;  /* beta (1/A) >= 0; beta = 0 gives the bare truncated Coulomb term */
+  double coulomb_k;   /* k_e (kJ mol^-1 A e^-2), 1389.35457644382 for CODATA 2018 */
+  int32_t precision;  /* nb_precision */
+  int32_t cell_div_xy;/* cells per cutoff along x and y, 1..4 (0 = 2, the paper's R/2 bins) */
+  int32_t cell_div_z; /* cells per cutoff along z, 1..16 (0 = the kernel's default) */
+  int32_t kernel;     /* NB_KERNEL_* */
+} nb_params;
+
+/* Bytes of device workspace needed for this batch and these parameters.
+ * Host only; no HIP call.  The same (system, params) must be passed to every
+ * later call that uses the workspace. */
+nb_status nb_workspace_bytes(const nb_system *sys, const nb_params *params, size_t *bytes /*[host]*/);
+
+/* Cell list (section 3): wraps each atom into its box, converts it to 32-bit
+ * box-fraction fixed point, bins it into cells at least R/cell_div wide, and
+ * stores the atoms sorted by (system, cell, original index) -- a deterministic
+ * counting sort -- together with their charges, types and exclusion windows.
+ * The workspace then holds everything the pair kernels read: positions,
+ * charges, types and exclusions are captured at this call, so call it again
+ * after any of them changes.  `workspace` must be 256-byte aligned. */
+nb_status nb_build_cells(const nb_system *sys, const nb_params *params, void *workspace /*[device]*/,
+                         size_t workspace_bytes, hipStream_t stream);
+
+/* Forces F_i = -dE/dx_i [device, N*3 doubles, caller's atom order], and optionally
+ * the energy E_b [device, B doubles] and virial W_b = sum_{i<j} d_ij (x) F_ij
+ * [device, 9*B doubles, row-major] of every system.  Requires nb_build_cells on
+ * this workspace.  force must not be NULL; energy and virial may be NULL. */
+nb_status nb_nonbonded_forces(const nb_system *sys, const nb_params *params, void *workspace,
+                              size_t workspace_bytes, double *force, double *energy, double *virial,
+                              hipStream_t stream);
+
+/* Energy of every system [device, B doubles] and optionally the per-atom split
+ * E_i = (1/2) sum_j u_ij [device, N doubles, caller's order; may be NULL]. */
+nb_status nb_nonbonded_energy(const nb_system *sys, const nb_params *params, void *workspace,
+                              size_t workspace_bytes, double *energy, double *atom_energy,
+                              hipStream_t stream);
+
+/* Adjoint of E = sum_b g_b E_b with g = grad_energy [device, B doubles]:
+ *   grad_pos[i]    = g_b dE_b/dx_i = -g_b F_i            [device, N*3 doubles or NULL]
+ *   grad_charge[i] = g_b dE_b/dq_i = g_b sum_j k_e q_j erfc(beta r)/r   [device, N or NULL]
+ *   grad_sigma[t]  = sum_b g_b dE_b/dsigma_t              [device, n_types or NULL]
+ *   grad_eps[t]    = sum_b g_b dE_b/deps_t                [device, n_types or NULL]
+ * dE/deps_t is reported as 0 for a type with eps_t = 0, where the derivative of
+ * sqrt(eps_t eps_j) is unbounded.  Outputs are overwritten, not accumulated. */
+nb_status nb_nonbonded_backward(const nb_system *sys, const nb_params *params, void *workspace,
+                                size_t workspace_bytes, const double *grad_energy, double *grad_pos,
+                                double *grad_charge, double *grad_sigma, double *grad_eps,
+                                hipStream_t stream);
+
+/* Synchronises `stream` and returns the NB_STATUS_* bits accumulated in the workspace. */
+nb_status nb_read_status(const void *workspace, hipStream_t stream, uint32_t *flags /*[host]*/);
+
+/* Message for the last non-OK return on the calling thread ("" if none). */
+const char *nb_last_error(void);
+
+/* Internal arrays of a built workspace, as byte offsets from its start, for tests
+ * and debugging.  Host only.  See the library source for the record formats. */
+typedef struct {
+  int64_t n_atoms;
+  int64_t n_cells;          /* all systems */
+  int32_t dims[3];          /* grid of system 0 */
+  int64_t off_cell_start;   /* int32 [n_cells + 1] */
+  int64_t off_sorted_fixed; /* uint32 x4 [n_atoms]: fixed-point x, y, z and original index */
+  int64_t off_sorted_pos64; /* double x4 [n_atoms]: wrapped x, y, z, charge (FP64 data) */
+  int64_t off_excl_mask;    /* uint32 x4 [n_atoms], original order: exclusion window bits */
+  int64_t off_status;       /* uint32 status word */
+} nb_layout;
+
+nb_status nb_workspace_layout(const nb_system *sys, const nb_params *params, nb_layout *layout /*[host]*/);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBHIP_H */

@@ -1,0 +1,280 @@
+// C ABI of the nonbonded library: argument validation, the per-call plan and
+// workspace layout, and dispatch to the kernel launchers.  Host code only.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "nb_internal.h"
+
+namespace nb {
+
+namespace {
+thread_local std::string g_last_error;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+nb_status fail(nb_status code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+// Cells per dimension: the largest n with L/n >= R/k plus a margin of four
+// fixed-point units, so that atoms more than k cells apart (in fixed point) are
+// more than R apart in true coordinates.
+int64_t grid_dim(double L, double cutoff, int k) {
+  const double n = std::floor(k * L / (cutoff + 4.0 * L / 4294967296.0));
+  return n < 1.0 ? 1 : static_cast<int64_t>(n);
+}
+}  // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
+  if (!sys || !prm || !plan) return fail(NB_ERR_ARG, "null system, params or output pointer");
+  if (sys->n_systems < 1) return fail(NB_ERR_ARG, "n_systems must be >= 1");
+  if (!sys->atom_offset || !sys->box) return fail(NB_ERR_ARG, "atom_offset and box are required host arrays");
+  if (sys->pos_is_f64 != 0 && sys->pos_is_f64 != 1) return fail(NB_ERR_ARG, "pos_is_f64 must be 0 or 1");
+  if (sys->n_types < 1 || sys->n_types > NB_MAX_TYPES)
+    return fail(NB_ERR_ARG, "n_types must be in [1, NB_MAX_TYPES]");
+  if (!(prm->cutoff > 0.0) || !std::isfinite(prm->cutoff)) return fail(NB_ERR_ARG, "cutoff must be positive and finite");
+  if (!(prm->ewald_beta >= 0.0) || !std::isfinite(prm->ewald_beta)) return fail(NB_ERR_ARG, "ewald_beta must be >= 0 and finite");
+  if (!std::isfinite(prm->coulomb_k)) return fail(NB_ERR_ARG, "coulomb_k must be finite");
+  if (prm->precision != NB_FP64 && prm->precision != NB_MIXED) return fail(NB_ERR_ARG, "unknown precision");
+  if (prm->cell_div_xy < 0 || prm->cell_div_xy > 4) return fail(NB_ERR_ARG, "cell_div_xy must be in [0, 4]");
+  if (prm->cell_div_z < 0 || prm->cell_div_z > 16) return fail(NB_ERR_ARG, "cell_div_z must be in [0, 16]");
+  if (prm->kernel < NB_KERNEL_AUTO || prm->kernel > NB_KERNEL_CLUSTER) return fail(NB_ERR_ARG, "unknown kernel variant");
+
+  const int B = sys->n_systems;
+  if (sys->atom_offset[0] != 0) return fail(NB_ERR_ARG, "atom_offset[0] must be 0");
+  for (int b = 0; b < B; ++b)
+    if (sys->atom_offset[b + 1] < sys->atom_offset[b]) return fail(NB_ERR_ARG, "atom_offset must be non-decreasing");
+  const int64_t N = sys->atom_offset[B];
+  if (N > INT32_MAX / 2) return fail(NB_ERR_CAPACITY, "more atoms than 32-bit indexing supports");
+  if (N > 0 && (!sys->pos || !sys->charge || !sys->type || !sys->excl_offset || !sys->excl_index))
+    return fail(NB_ERR_ARG, "pos, charge, type, excl_offset and excl_index must be device pointers");
+  if (!sys->lj_sigma || !sys->lj_eps) return fail(NB_ERR_ARG, "lj_sigma and lj_eps are required");
+
+  Plan p;
+  p.B = B;
+  p.N = N;
+  p.T = sys->n_types;
+  p.precision = prm->precision;
+  p.kernel = prm->kernel == NB_KERNEL_AUTO ? NB_KERNEL_ATOM : prm->kernel;
+  p.div_xy = prm->cell_div_xy ? prm->cell_div_xy : 2;
+  p.div_z = prm->cell_div_z ? prm->cell_div_z : p.div_xy;
+  p.cutoff = prm->cutoff;
+  p.beta = prm->ewald_beta;
+  p.ke = prm->coulomb_k;
+  p.desc.resize(B);
+  int64_t cells = 0, blocks = 0, clusters = 0, columns = 0;
+  for (int b = 0; b < B; ++b) {
+    SysDesc &d = p.desc[b];
+    std::memset(&d, 0, sizeof(d));
+    const int div[3] = {p.div_xy, p.div_xy, p.div_z};
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+      const double L = sys->box[3 * b + a];
+      if (!(L > 0.0) || !std::isfinite(L))
+        return fail(NB_ERR_BOX, "box lengths must be positive and finite (system " + std::to_string(b) + ")");
+      if (!(prm->cutoff < 0.5 * L))
+        return fail(NB_ERR_BOX, "cutoff must be below half of every box length (system " + std::to_string(b) + ")");
+      const int64_t n = grid_dim(L, prm->cutoff, div[a]);
+      if (n > (1 << 20)) return fail(NB_ERR_CAPACITY, "cell grid too fine");
+      d.dims[a] = static_cast<int32_t>(n);
+      d.reach[a] = div[a];
+      d.box[a] = L;
+      d.inv_box[a] = 1.0 / L;
+      d.scale[a] = L / 4294967296.0;
+      d.scale2f[a] = static_cast<float>(d.scale[a] * d.scale[a]);
+      ncell *= n;
+    }
+    const int64_t nb = sys->atom_offset[b + 1] - sys->atom_offset[b];
+    d.atom_begin = static_cast<int32_t>(sys->atom_offset[b]);
+    d.atom_end = static_cast<int32_t>(sys->atom_offset[b + 1]);
+    d.cell_begin = static_cast<int32_t>(cells);
+    d.blk_begin = static_cast<int32_t>(blocks);
+    const int64_t ncol = static_cast<int64_t>(d.dims[0]) * d.dims[1];
+    d.col_begin = static_cast<int32_t>(columns);
+    d.clu_begin = static_cast<int32_t>(clusters);
+    clusters += (nb + 7) / 8 + ncol;  // upper bound: every column may end in a partial cluster
+    d.clu_end = static_cast<int32_t>(clusters);
+    columns += ncol;
+    cells += ncell;
+    blocks += (nb + kBlock - 1) / kBlock;
+    if (cells > INT32_MAX / 2 || clusters > INT32_MAX / 2)
+      return fail(NB_ERR_CAPACITY, "too many cells for 32-bit indexing");
+  }
+  p.n_cells = cells;
+  p.n_blocks = blocks;
+  p.n_clusters_max = clusters;
+  p.n_columns = columns;
+
+  Layout &l = p.lay;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  const size_t T2 = static_cast<size_t>(p.T) * p.T;
+  l.status = take(256);
+  l.desc = take(sizeof(SysDesc) * B);
+  l.tab64 = take(sizeof(TypePair64) * T2);
+  l.tab32 = take(sizeof(TypePair32) * T2);
+  l.cell_count = take(4 * static_cast<size_t>(cells));
+  l.cell_start = take(4 * static_cast<size_t>(cells + 1));
+  l.atom_cell = take(4 * static_cast<size_t>(N));
+  l.atom_slot = take(4 * static_cast<size_t>(N));
+  l.atom_fix = take(16 * static_cast<size_t>(N));
+  l.tmp = take(4 * static_cast<size_t>(N));
+  l.s_fix = take(16 * static_cast<size_t>(N));
+  l.s_pos64 = take(32 * static_cast<size_t>(N));
+  l.s_q32 = take(4 * static_cast<size_t>(N));
+  l.s_type = take(4 * static_cast<size_t>(N));
+  l.excl_mask = take(16 * static_cast<size_t>(N));
+  l.excl_far = take(4 * static_cast<size_t>(N));
+  l.partials = take(8 * kPart * static_cast<size_t>(blocks > 0 ? blocks : 1));
+  l.adj_partials = take(8 * 2 * static_cast<size_t>(p.T) * static_cast<size_t>(blocks > 0 ? blocks : 1));
+  l.clusters = take(0);
+  l.clu_bbox = take(0);
+  l.col_cluster = take(0);
+  l.total = o;
+  *plan = std::move(p);
+  return NB_OK;
+}
+
+Dev dev_view(const Plan &p, void *ws) {
+  char *base = static_cast<char *>(ws);
+  const Layout &l = p.lay;
+  Dev d;
+  d.status = reinterpret_cast<uint32_t *>(base + l.status);
+  d.desc = reinterpret_cast<SysDesc *>(base + l.desc);
+  d.B = p.B;
+  d.tab64 = reinterpret_cast<TypePair64 *>(base + l.tab64);
+  d.tab32 = reinterpret_cast<TypePair32 *>(base + l.tab32);
+  d.T = p.T;
+  d.cell_count = reinterpret_cast<int32_t *>(base + l.cell_count);
+  d.cell_start = reinterpret_cast<int32_t *>(base + l.cell_start);
+  d.n_cells = p.n_cells;
+  d.atom_cell = reinterpret_cast<int32_t *>(base + l.atom_cell);
+  d.atom_slot = reinterpret_cast<int32_t *>(base + l.atom_slot);
+  d.tmp = reinterpret_cast<int32_t *>(base + l.tmp);
+  d.atom_fix = reinterpret_cast<uint4 *>(base + l.atom_fix);
+  d.s_fix = reinterpret_cast<uint4 *>(base + l.s_fix);
+  d.s_pos64 = reinterpret_cast<double4 *>(base + l.s_pos64);
+  d.s_q32 = reinterpret_cast<float *>(base + l.s_q32);
+  d.s_type = reinterpret_cast<int32_t *>(base + l.s_type);
+  d.excl_mask = reinterpret_cast<uint4 *>(base + l.excl_mask);
+  d.excl_far = reinterpret_cast<uint32_t *>(base + l.excl_far);
+  d.partials = reinterpret_cast<double *>(base + l.partials);
+  d.adj_partials = reinterpret_cast<double *>(base + l.adj_partials);
+  d.N = p.N;
+  d.n_blocks = p.n_blocks;
+  return d;
+}
+
+}  // namespace nb
+
+using nb::fail;
+
+namespace {
+
+nb_status check_ws(const nb::Plan &p, const void *ws, size_t bytes) {
+  if (!ws) return fail(NB_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(NB_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (bytes < p.lay.total)
+    return fail(NB_ERR_WORKSPACE, "workspace too small: " + std::to_string(bytes) + " < " + std::to_string(p.lay.total));
+  return NB_OK;
+}
+
+nb_status hip_status(hipError_t e, const char *what) {
+  if (e == hipSuccess) return NB_OK;
+  return fail(NB_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+nb_status nb_workspace_bytes(const nb_system *sys, const nb_params *params, size_t *bytes) {
+  if (!bytes) return fail(NB_ERR_ARG, "bytes is NULL");
+  nb::Plan p;
+  nb_status st = nb::make_plan(sys, params, &p);
+  if (st != NB_OK) return st;
+  *bytes = p.lay.total;
+  return NB_OK;
+}
+
+nb_status nb_workspace_layout(const nb_system *sys, const nb_params *params, nb_layout *layout) {
+  if (!layout) return fail(NB_ERR_ARG, "layout is NULL");
+  nb::Plan p;
+  nb_status st = nb::make_plan(sys, params, &p);
+  if (st != NB_OK) return st;
+  layout->n_atoms = p.N;
+  layout->n_cells = p.n_cells;
+  for (int a = 0; a < 3; ++a) layout->dims[a] = p.desc[0].dims[a];
+  layout->off_cell_start = static_cast<int64_t>(p.lay.cell_start);
+  layout->off_sorted_fixed = static_cast<int64_t>(p.lay.s_fix);
+  layout->off_sorted_pos64 = static_cast<int64_t>(p.lay.s_pos64);
+  layout->off_excl_mask = static_cast<int64_t>(p.lay.excl_mask);
+  layout->off_status = static_cast<int64_t>(p.lay.status);
+  return NB_OK;
+}
+
+nb_status nb_build_cells(const nb_system *sys, const nb_params *params, void *workspace,
+                         size_t workspace_bytes, hipStream_t stream) {
+  nb::Plan p;
+  nb_status st = nb::make_plan(sys, params, &p);
+  if (st != NB_OK) return st;
+  if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
+  return hip_status(nb::launch_build(p, nb::dev_view(p, workspace), sys, stream), "nb_build_cells");
+}
+
+nb_status nb_nonbonded_forces(const nb_system *sys, const nb_params *params, void *workspace,
+                              size_t workspace_bytes, double *force, double *energy, double *virial,
+                              hipStream_t stream) {
+  nb::Plan p;
+  nb_status st = nb::make_plan(sys, params, &p);
+  if (st != NB_OK) return st;
+  if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
+  if (!force && p.N > 0) return fail(NB_ERR_ARG, "force must not be NULL");
+  return hip_status(nb::launch_forces(p, nb::dev_view(p, workspace), sys, force, energy, virial, stream),
+                    "nb_nonbonded_forces");
+}
+
+nb_status nb_nonbonded_energy(const nb_system *sys, const nb_params *params, void *workspace,
+                              size_t workspace_bytes, double *energy, double *atom_energy,
+                              hipStream_t stream) {
+  nb::Plan p;
+  nb_status st = nb::make_plan(sys, params, &p);
+  if (st != NB_OK) return st;
+  if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
+  if (!energy) return fail(NB_ERR_ARG, "energy must not be NULL");
+  return hip_status(nb::launch_energy(p, nb::dev_view(p, workspace), sys, energy, atom_energy, stream),
+                    "nb_nonbonded_energy");
+}
+
+nb_status nb_nonbonded_backward(const nb_system *sys, const nb_params *params, void *workspace,
+                                size_t workspace_bytes, const double *grad_energy, double *grad_pos,
+                                double *grad_charge, double *grad_sigma, double *grad_eps,
+                                hipStream_t stream) {
+  nb::Plan p;
+  nb_status st = nb::make_plan(sys, params, &p);
+  if (st != NB_OK) return st;
+  if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
+  if (!grad_energy) return fail(NB_ERR_ARG, "grad_energy must not be NULL");
+  return hip_status(nb::launch_backward(p, nb::dev_view(p, workspace), sys, grad_energy, grad_pos,
+                                        grad_charge, grad_sigma, grad_eps, stream),
+                    "nb_nonbonded_backward");
+}
+
+nb_status nb_read_status(const void *workspace, hipStream_t stream, uint32_t *flags) {
+  if (!workspace || !flags) return fail(NB_ERR_ARG, "workspace and flags are required");
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_status(e, "nb_read_status: stream synchronise");
+  e = hipMemcpy(flags, workspace, sizeof(uint32_t), hipMemcpyDeviceToHost);
+  return hip_status(e, "nb_read_status: copy");
+}
+
+const char *nb_last_error(void) { return nb::g_last_error.c_str(); }
+
+}  // extern "C"

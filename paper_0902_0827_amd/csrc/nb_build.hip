@@ -1,0 +1,246 @@
+// Cell-list construction (ACEMD paper, section 3: atoms are binned by their
+// coordinates, one thread per atom computing its cell, with atomic updates of
+// the cell array).  Here the cell array is a CSR built by a counting sort:
+//
+//   k_init      clear counters, masks and status; write descriptors and the type-pair table
+//   k_bin       per atom: box-fraction fixed point, cell id, atomic cell count (its slot),
+//               and the atom's exclusion row folded into 128-bit index windows
+//   k_scan      exclusive scan of the cell counts -> cell_start
+//   k_scatter   atom -> cell_start[cell] + slot (order inside a cell still arbitrary)
+//   k_finalize  rank inside the cell by original index (makes the sort stable and the
+//               result deterministic) and write the sorted per-atom records
+//
+// Positions become 32-bit box fractions u = floor(x/L * 2^32) mod 2^32, which wraps
+// every coordinate into the box; the 32-bit difference of two such values is the
+// minimum-image displacement in units of L/2^32.
+#include "nb_internal.h"
+
+namespace nb {
+
+namespace {
+
+constexpr double kTwo32 = 4294967296.0;
+
+struct DescChunk {
+  SysDesc d[kDescChunk];
+  int first, count;
+};
+
+__device__ inline int find_system(const SysDesc *desc, int B, int atom) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].atom_begin <= atom) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_put_desc(Dev d, DescChunk c) {
+  const int k = threadIdx.x;
+  if (k < c.count) d.desc[c.first + k] = c.d[k];
+}
+
+__global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, const double *__restrict__ eps) {
+  const int64_t tid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  if (tid < c.count) d.desc[c.first + tid] = c.d[tid];
+  if (tid == 0) d.status[0] = 0u;
+  for (int64_t k = tid; k < d.n_cells; k += stride) d.cell_count[k] = 0;
+  for (int64_t k = tid; k < d.N; k += stride) {
+    d.excl_mask[k] = make_uint4(0u, 0u, 0u, 0u);
+    d.excl_far[k] = 0u;
+  }
+  // Type-pair table, Lorentz-Berthelot: sigma_ij = (s_i + s_j)/2, eps_ij = sqrt(e_i e_j).
+  const int T = d.T;
+  for (int64_t k = tid; k < static_cast<int64_t>(T) * T; k += stride) {
+    const int ti = static_cast<int>(k / T), tj = static_cast<int>(k % T);
+    const double sij = 0.5 * (sigma[ti] + sigma[tj]);
+    const double eij = sqrt(fmax(eps[ti], 0.0) * fmax(eps[tj], 0.0));
+    const double s2 = sij * sij, s6 = s2 * s2 * s2;
+    TypePair64 p;
+    p.c6 = 4.0 * eij * s6;
+    p.c12 = 4.0 * eij * s6 * s6;
+    p.inv_sig = sij > 0.0 ? 1.0 / sij : 0.0;
+    p.pad = 0.0;
+    d.tab64[k] = p;
+    TypePair32 q;
+    q.c6 = static_cast<float>(p.c6);
+    q.c12 = static_cast<float>(p.c12);
+    q.inv_sig = static_cast<float>(p.inv_sig);
+    q.pad = 0.f;
+    d.tab32[k] = q;
+  }
+}
+
+__device__ inline void set_status(const Dev &d, uint32_t bit) { atomicOr(d.status, bit); }
+
+__device__ inline void window_set(const Dev &d, int atom, int delta) {
+  // delta in [-64, -1] -> bit delta + 64; delta in [1, 64] -> bit delta + 63.
+  const int bit = delta < 0 ? delta + kWindow : delta + kWindow - 1;
+  unsigned int *w = reinterpret_cast<unsigned int *>(&d.excl_mask[atom]);
+  atomicOr(&w[bit >> 5], 1u << (bit & 31));
+}
+
+template <typename Real>
+__global__ void k_bin(Dev d, const Real *__restrict__ pos, const int32_t *__restrict__ type,
+                      const int32_t *__restrict__ excl_off, const int32_t *__restrict__ excl_idx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.N) return;
+  const int b = find_system(d.desc, d.B, i);
+  const SysDesc &sd = d.desc[b];
+  uint32_t u[3];
+  bool finite = true;
+  for (int a = 0; a < 3; ++a) {
+    const double x = static_cast<double>(pos[3 * static_cast<int64_t>(i) + a]);
+    finite = finite && isfinite(x);
+    // One IEEE division and an exact power-of-two scaling; floor to int64 then keep 32 bits.
+    const double t = floor((x / sd.box[a]) * kTwo32);
+    u[a] = (isfinite(t) && fabs(t) < 9.0e18) ? static_cast<uint32_t>(static_cast<uint64_t>(static_cast<int64_t>(t)))
+                                             : 0u;
+  }
+  if (!finite) {
+    set_status(d, NB_STATUS_NONFINITE_POS);
+    u[0] = u[1] = u[2] = 0u;
+  }
+  int c[3];
+  for (int a = 0; a < 3; ++a)
+    c[a] = static_cast<int>((static_cast<uint64_t>(u[a]) * static_cast<uint64_t>(sd.dims[a])) >> 32);
+  const int cell = sd.cell_begin + (c[0] * sd.dims[1] + c[1]) * sd.dims[2] + c[2];
+  d.atom_cell[i] = cell;
+  d.atom_slot[i] = atomicAdd(&d.cell_count[cell], 1);
+  d.atom_fix[i] = make_uint4(u[0], u[1], u[2], static_cast<uint32_t>(b));
+  const int t = type[i];
+  if (t < 0 || t >= d.T) set_status(d, NB_STATUS_BAD_TYPE);
+
+  // Exclusions: a pair listed in either row excludes both ways, so each listed pair
+  // marks the windows of both atoms (section 3: bitmaps over |i - j| <= 64).
+  const int lo = excl_off[i], hi = excl_off[i + 1];
+  if (hi < lo) {
+    set_status(d, NB_STATUS_BAD_EXCLUSION);
+    return;
+  }
+  const int n_sys = sd.atom_end - sd.atom_begin;
+  for (int k = lo; k < hi; ++k) {
+    const int jl = excl_idx[k];
+    if (jl < 0 || jl >= n_sys) {
+      set_status(d, NB_STATUS_BAD_EXCLUSION);
+      continue;
+    }
+    const int j = sd.atom_begin + jl;
+    const int delta = j - i;
+    if (delta == 0) continue;
+    if (delta >= -kWindow && delta <= kWindow) {
+      window_set(d, i, delta);
+      window_set(d, j, -delta);
+    } else {
+      atomicOr(&d.excl_far[i], 1u);
+      atomicOr(&d.excl_far[j], 1u);
+      set_status(d, NB_STATUS_FAR_EXCLUSION);
+    }
+  }
+}
+
+// Exclusive scan of cell_count into cell_start (n_cells + 1 entries) by one
+// workgroup: each thread sums a contiguous chunk, the chunk sums are scanned in
+// LDS, then each thread writes its chunk.
+__global__ void __launch_bounds__(1024) k_scan(Dev d) {
+  __shared__ int sums[1024];
+  const int tid = threadIdx.x;
+  const int64_t n = d.n_cells;
+  const int64_t chunk = (n + 1023) / 1024;
+  const int64_t lo = tid * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  int s = 0;
+  for (int64_t k = lo; k < hi; ++k) s += d.cell_count[k];
+  sums[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = tid >= off ? sums[tid - off] : 0;
+    __syncthreads();
+    sums[tid] += v;
+    __syncthreads();
+  }
+  int run = sums[tid] - s;  // exclusive prefix of this chunk
+  for (int64_t k = lo; k < hi; ++k) {
+    const int c = d.cell_count[k];
+    d.cell_start[k] = run;
+    run += c;
+  }
+  if (tid == 1023) d.cell_start[n] = sums[1023];
+}
+
+__global__ void k_scatter(Dev d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.N) return;
+  d.tmp[d.cell_start[d.atom_cell[i]] + d.atom_slot[i]] = i;
+}
+
+template <typename Real>
+__global__ void k_finalize(Dev d, const Real *__restrict__ pos, const Real *__restrict__ charge,
+                           const int32_t *__restrict__ type, double sqrt_ke) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= d.N) return;
+  const int i = d.tmp[s];
+  const int cell = d.atom_cell[i];
+  const int lo = d.cell_start[cell], hi = d.cell_start[cell + 1];
+  int rank = 0;
+  for (int k = lo; k < hi; ++k) rank += d.tmp[k] < i;
+  const int dst = lo + rank;
+  const uint4 f = d.atom_fix[i];
+  d.s_fix[dst] = make_uint4(f.x, f.y, f.z, static_cast<uint32_t>(i));
+  const double q = static_cast<double>(charge[i]);
+  d.s_pos64[dst] = make_double4(static_cast<double>(pos[3 * static_cast<int64_t>(i)]),
+                                static_cast<double>(pos[3 * static_cast<int64_t>(i) + 1]),
+                                static_cast<double>(pos[3 * static_cast<int64_t>(i) + 2]), q);
+  d.s_q32[dst] = static_cast<float>(q * sqrt_ke);
+  int t = type[i];
+  d.s_type[dst] = (t < 0 || t >= d.T) ? 0 : t;
+}
+
+unsigned grid_for(int64_t n, int block) {
+  const int64_t g = (n + block - 1) / block;
+  return static_cast<unsigned>(g > 0 ? g : 1);
+}
+
+}  // namespace
+
+hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hipStream_t s) {
+  // Descriptors travel as kernel arguments (no host-to-device copy), kDescChunk per launch.
+  DescChunk first{};
+  first.first = 0;
+  first.count = plan.B < kDescChunk ? plan.B : kDescChunk;
+  for (int k = 0; k < first.count; ++k) first.d[k] = plan.desc[k];
+  const int64_t init_work = plan.N > plan.n_cells ? plan.N : plan.n_cells;
+  unsigned g_init = grid_for(init_work, kBlock);
+  if (g_init > 4096) g_init = 4096;
+  hipLaunchKernelGGL(k_init, dim3(g_init), dim3(kBlock), 0, s, d, first, sys->lj_sigma, sys->lj_eps);
+  for (int b0 = kDescChunk; b0 < plan.B; b0 += kDescChunk) {
+    DescChunk c{};
+    c.first = b0;
+    c.count = plan.B - b0 < kDescChunk ? plan.B - b0 : kDescChunk;
+    for (int k = 0; k < c.count; ++k) c.d[k] = plan.desc[b0 + k];
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, c);
+  }
+  if (plan.N == 0) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d);
+    return hipGetLastError();
+  }
+  const unsigned g = grid_for(plan.N, kBlock);
+  if (sys->pos_is_f64)
+    hipLaunchKernelGGL(k_bin<double>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const double *>(sys->pos),
+                       sys->type, sys->excl_offset, sys->excl_index);
+  else
+    hipLaunchKernelGGL(k_bin<float>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const float *>(sys->pos),
+                       sys->type, sys->excl_offset, sys->excl_index);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d);
+  hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kBlock), 0, s, d);
+  const double sqrt_ke = sqrt(plan.ke);
+  if (sys->pos_is_f64)
+    hipLaunchKernelGGL(k_finalize<double>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const double *>(sys->pos),
+                       static_cast<const double *>(sys->charge), sys->type, sqrt_ke);
+  else
+    hipLaunchKernelGGL(k_finalize<float>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const float *>(sys->pos),
+                       static_cast<const float *>(sys->charge), sys->type, sqrt_ke);
+  return hipGetLastError();
+}
+
+}  // namespace nb

@@ -1,0 +1,103 @@
+// Internal declarations of the nonbonded library: per-system descriptors, the
+// workspace layout and the argument block every kernel receives.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "nbhip.h"
+
+namespace nb {
+
+constexpr int kBlock = 256;           // threads per workgroup of the per-atom kernels
+constexpr int kWaves = kBlock / 64;   // wave64
+constexpr int kPart = 10;             // per-block partial sums: energy + 9 virial entries
+constexpr int kWindow = 64;           // exclusion bitmap reach in original index (section 3)
+constexpr int kDescChunk = 8;         // system descriptors carried by one initialisation launch
+
+// Per-system descriptor, resident in the workspace.  Sorted atoms of system b are
+// [atom_begin, atom_end) (the sort keeps systems in order), its cells are
+// [cell_begin, cell_begin + nx*ny*nz) and its per-atom-kernel blocks
+// [blk_begin, blk_begin + ceil(n_b / kBlock)).
+struct alignas(16) SysDesc {
+  int32_t atom_begin, atom_end, cell_begin, blk_begin;
+  int32_t dims[4];    // nx, ny, nz, (unused)
+  int32_t reach[4];   // stencil reach in cells per dimension
+  int32_t clu_begin, clu_end, col_begin, pad0;  // cluster and column ranges (cluster kernel)
+  double box[4];      // L per dimension
+  double inv_box[4];  // 1/L
+  double scale[4];    // L / 2^32: Angstrom per fixed-point unit
+  float scale2f[4];   // (L / 2^32)^2 in float, for squared distances from fixed-point deltas
+};
+
+// One entry of the type-pair table: u_LJ = c12/r^12 - c6/r^6 and
+// du/dsigma_ij = (12 c12/r^12 - 6 c6/r^6) * inv_sig.
+struct alignas(16) TypePair64 { double c6, c12, inv_sig, pad; };
+struct alignas(16) TypePair32 { float c6, c12, inv_sig, pad; };
+
+// Byte offsets into the workspace (all 256-aligned).
+struct Layout {
+  size_t status, desc, tab64, tab32, cell_count, cell_start, atom_cell, atom_slot, atom_fix, tmp;
+  size_t s_fix, s_pos64, s_q32, s_type, excl_mask, excl_far, partials, adj_partials;
+  size_t clusters, clu_bbox, col_cluster;
+  size_t total;
+};
+
+// Host-side plan derived from (system, params); recomputed by every call.
+struct Plan {
+  int B = 0;
+  int64_t N = 0;
+  int T = 0;
+  int precision = 0;
+  int kernel = 0;
+  int div_xy = 2, div_z = 2;
+  double cutoff = 0, beta = 0, ke = 0;
+  int64_t n_cells = 0, n_blocks = 0, n_clusters_max = 0, n_columns = 0;
+  std::vector<SysDesc> desc;
+  Layout lay{};
+};
+
+// Pointers into one workspace, passed by value to the kernels.
+struct Dev {
+  uint32_t *status;
+  SysDesc *desc;
+  int B;
+  TypePair64 *tab64;
+  TypePair32 *tab32;
+  int T;
+  int32_t *cell_count, *cell_start;
+  int64_t n_cells;
+  int32_t *atom_cell, *atom_slot, *tmp;
+  uint4 *atom_fix;   // original order: fixed-point x, y, z, system index
+  uint4 *s_fix;      // sorted: fixed-point x, y, z, original index
+  double4 *s_pos64;  // sorted: raw x, y, z (double), charge (double)
+  float *s_q32;      // sorted: charge * sqrt(k_e) in float
+  int32_t *s_type;   // sorted: type (clamped into range)
+  uint4 *excl_mask;  // original order: 128-bit exclusion window
+  uint32_t *excl_far;// original order: nonzero if the atom has an exclusion beyond the window
+  double *partials;      // [n_blocks][kPart]
+  double *adj_partials;  // [n_blocks][2 T]
+  int64_t N;
+  int64_t n_blocks;
+};
+
+// Host helpers (nb_api.cpp).
+nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan);
+Dev dev_view(const Plan &plan, void *ws);
+void set_error(const std::string &msg);
+
+// Launchers (nb_build.hip / nb_pair.hip); each returns hipSuccess or the first error.
+hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hipStream_t s);
+hipError_t launch_forces(const Plan &plan, const Dev &d, const nb_system *sys, double *force,
+                         double *energy, double *virial, hipStream_t s);
+hipError_t launch_energy(const Plan &plan, const Dev &d, const nb_system *sys, double *energy,
+                         double *atom_energy, hipStream_t s);
+hipError_t launch_backward(const Plan &plan, const Dev &d, const nb_system *sys,
+                           const double *grad_energy, double *grad_pos, double *grad_charge,
+                           double *grad_sigma, double *grad_eps, hipStream_t s);
+
+}  // namespace nb

@@ -1,0 +1,96 @@
+// Pair arithmetic shared by the pair kernels (device code only).
+//
+// For a pair at distance r (r^2 < R^2, not excluded) with type-pair coefficients
+// c6 = 4 eps_ij sigma_ij^6 and c12 = 4 eps_ij sigma_ij^12 and charge product qq
+// (k_e already folded in):
+//
+//   u      = c12/r^12 - c6/r^6 + qq erfc(beta r)/r
+//   f      = [12 c12/r^12 - 6 c6/r^6 + qq (erfc(beta r)/r + (2 beta/sqrt(pi)) exp(-beta^2 r^2))] / r^2
+//
+// so that the force on i from j is f * d_ij with d_ij = x_i - x_j (minimum image).
+// The adjoint also needs du/dsigma_ij = (12 c12/r^12 - 6 c6/r^6) / sigma_ij.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace nb {
+
+// erfc(x) = exp(-x^2) * t * P(t), t = 1/(1 + p x): Hastings' substitution (Abramowitz &
+// Stegun 7.1.26) refitted to degree 8 by minimax on relative error over [0, 6]
+// (gen_erfc_coeffs.py).  Fit error 6e-9; single-precision evaluation error ~3e-7.
+constexpr float kErfcP = 0.47047f;
+constexpr float kErfcC0 = 2.653190811e-01f;
+constexpr float kErfcC1 = 2.676810699e-01f;
+constexpr float kErfcC2 = 2.170464896e-01f;
+constexpr float kErfcC3 = 2.685938874e-01f;
+constexpr float kErfcC4 = -1.731834435e-01f;
+constexpr float kErfcC5 = 5.340760566e-01f;
+constexpr float kErfcC6 = -6.228106085e-01f;
+constexpr float kErfcC7 = 2.961506389e-01f;
+constexpr float kErfcC8 = -5.287316965e-02f;
+
+// exp(x^2) erfc(x) for x >= 0 in single precision.
+__device__ __forceinline__ float erfcx_f32(float x) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(kErfcP, x, 1.0f));
+  float p = kErfcC8;
+  p = fmaf(p, t, kErfcC7);
+  p = fmaf(p, t, kErfcC6);
+  p = fmaf(p, t, kErfcC5);
+  p = fmaf(p, t, kErfcC4);
+  p = fmaf(p, t, kErfcC3);
+  p = fmaf(p, t, kErfcC2);
+  p = fmaf(p, t, kErfcC1);
+  p = fmaf(p, t, kErfcC0);
+  return p * t;
+}
+
+struct PairF32 {
+  float u_lj, u_c, f, dudsig_lj;  // energies, force factor, (12 c12/r^12 - 6 c6/r^6)
+  float erfc_over_r;              // erfc(beta r)/r (for dE/dq)
+};
+
+// Single-precision pair terms.  beta, two_beta_sqrtpi = 2 beta/sqrt(pi) and
+// mb2l2e = -beta^2 log2(e) are per-call constants.
+__device__ __forceinline__ PairF32 pair_f32(float r2, float c6, float c12, float qq, float beta,
+                                            float two_beta_sqrtpi, float mb2l2e) {
+  PairF32 o;
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  const float rinv2 = rinv * rinv;
+  const float rinv6 = rinv2 * rinv2 * rinv2;
+  const float a = c12 * rinv6 * rinv6;
+  const float b = c6 * rinv6;
+  o.u_lj = a - b;
+  o.dudsig_lj = fmaf(12.0f, a, -6.0f * b);
+  const float r = r2 * rinv;
+  const float e = __builtin_amdgcn_exp2f(r2 * mb2l2e);  // exp(-beta^2 r^2)
+  const float erfc_br = erfcx_f32(beta * r) * e;
+  o.erfc_over_r = erfc_br * rinv;
+  o.u_c = qq * o.erfc_over_r;
+  o.f = fmaf(qq, fmaf(two_beta_sqrtpi, e, o.erfc_over_r), o.dudsig_lj) * rinv2;
+  return o;
+}
+
+struct PairF64 {
+  double u_lj, u_c, f, dudsig_lj, erfc_over_r;
+};
+
+// Double-precision pair terms with the device library's erfc and exp.
+__device__ __forceinline__ PairF64 pair_f64(double r2, double c6, double c12, double qq, double beta,
+                                            double two_beta_sqrtpi) {
+  PairF64 o;
+  const double r = sqrt(r2);
+  const double rinv = 1.0 / r;
+  const double rinv2 = rinv * rinv;
+  const double rinv6 = rinv2 * rinv2 * rinv2;
+  const double a = c12 * rinv6 * rinv6;
+  const double b = c6 * rinv6;
+  o.u_lj = a - b;
+  o.dudsig_lj = 12.0 * a - 6.0 * b;
+  const double erfc_br = erfc(beta * r);
+  o.erfc_over_r = erfc_br * rinv;
+  o.u_c = qq * o.erfc_over_r;
+  o.f = (o.dudsig_lj + qq * (o.erfc_over_r + two_beta_sqrtpi * exp(-beta * beta * r2))) * rinv2;
+  return o;
+}
+
+}  // namespace nb

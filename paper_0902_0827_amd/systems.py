@@ -162,60 +162,62 @@ class _Grid:
 
 
 def _chain(rng: np.random.Generator, n_beads: int, box: np.ndarray) -> np.ndarray:
-    """Self-avoiding bead chain: bond BOND, 1-3 distance >= MIN_13, other pairs >= MIN_BEAD."""
+    """Self-avoiding bead chain: bond BOND, 1-3 distance >= MIN_13, other pairs >= MIN_BEAD.
+
+    Each step draws a batch of candidate directions and keeps the first candidate that
+    satisfies every constraint (minimum image); a trapped chain backs off and regrows."""
     if n_beads == 0:
         return np.zeros((0, 3))
-    grid = _Grid(box, MIN_BEAD)
+    # Candidates lie BOND from the last bead, so neighbours within MIN_BEAD of a candidate
+    # are within MIN_BEAD + BOND of the last bead: the grid cells must be that wide.
+    grid = _Grid(box, MIN_BEAD + BOND)
     pos = np.zeros((n_beads, 3))
     pos[0] = rng.uniform(0, 1, 3) * box
     grid.add(0, pos[0])
     k = 1
     fails = 0
+    n_try = 32
     while k < n_beads:
-        ok = False
-        for _ in range(64):
-            u = rng.standard_normal(3)
-            u /= np.linalg.norm(u)
-            p = pos[k - 1] + BOND * u
-            if k >= 2 and np.linalg.norm(_minimage(p - pos[k - 2], box)) < MIN_13:
-                continue
-            clash = False
-            for j in grid.near(p):
-                if j >= k - 2:
-                    continue
-                if np.linalg.norm(_minimage(p - pos[j], box)) < MIN_BEAD:
-                    clash = True
-                    break
-            if not clash:
-                ok = True
-                break
-        if ok:
-            pos[k] = p
-            grid.add(k, p)
+        u = rng.standard_normal((n_try, 3))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        cand = pos[k - 1] + BOND * u
+        ok = np.ones(n_try, dtype=bool)
+        if k >= 2:
+            d13 = _minimage(cand - pos[k - 2], box)
+            ok &= np.einsum("ij,ij->i", d13, d13) >= MIN_13 ** 2
+        near = [j for j in grid.near(pos[k - 1]) if j < k - 2]
+        if near:
+            d = _minimage(cand[:, None, :] - pos[near][None, :, :], box)
+            ok &= (np.einsum("cnk,cnk->cn", d, d) >= MIN_BEAD ** 2).all(axis=1)
+        hit = np.flatnonzero(ok)
+        if hit.size:
+            pos[k] = cand[hit[0]]
+            grid.add(k, pos[k])
             k += 1
             fails = 0
         else:
-            # Trapped: back off a few beads and regrow.
             fails += 1
-            back = min(k - 1, 4 * fails)
-            for j in range(k - back, k):
-                grid.remove(j, pos[j])
-            k -= back
+            if fails % 2 == 0:
+                # Trapped: back off a few beads and regrow.
+                back = min(k - 1, 2 * fails)
+                for j in range(k - back, k):
+                    grid.remove(j, pos[j])
+                k -= back
     return np.mod(pos, box)
 
 
 def _free_sites(n_side: int, box: np.ndarray, beads: np.ndarray) -> np.ndarray:
+    """Lattice sites (i + 1/2) L / n_side whose minimum-image distance to every bead is
+    at least MIN_WATER_BEAD."""
     a = box / n_side
     g = (np.arange(n_side) + 0.5)
     sites = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3) * a
     if beads.shape[0] == 0:
         return sites
-    keep = np.ones(sites.shape[0], dtype=bool)
-    for start in range(0, beads.shape[0], 256):
-        b = beads[start:start + 256]
-        d = _minimage(sites[:, None, :] - b[None, :, :], box)
-        keep &= (np.einsum("sbk,sbk->sb", d, d) >= MIN_WATER_BEAD ** 2).all(axis=1)
-    return sites[keep]
+    from scipy.spatial import cKDTree
+    tree = cKDTree(np.mod(beads, box), boxsize=box)
+    dist, _ = tree.query(np.mod(sites, box), k=1)
+    return sites[dist >= MIN_WATER_BEAD]
 
 
 def _exclusions_csr(n: int, pairs: np.ndarray):

@@ -1,0 +1,109 @@
+"""Shared helpers for the GPU parity tests: run the HIP path through the C ABI and
+the oracle on exactly the same (rounded) inputs, and compare."""
+
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+
+from oracle import binning as OB
+from oracle import oracle as O
+from paper_0902_0827_amd import nbhip as H
+from paper_0902_0827_amd import systems as S
+
+
+def rel_rms(a, ref):
+    a = np.asarray(a, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    den = np.sqrt(np.mean(ref * ref))
+    return float(np.sqrt(np.mean((a - ref) ** 2)) / den) if den > 0 else float(np.abs(a - ref).max())
+
+
+def max_rel_atom(f, fref):
+    """max_i |dF_i| / |F_i| over atoms with |F_i| above 1e-3 of the RMS force."""
+    f = np.asarray(f).reshape(-1, 3)
+    fref = np.asarray(fref).reshape(-1, 3)
+    nrm = np.linalg.norm(fref, axis=1)
+    rms = np.sqrt(np.mean(nrm ** 2))
+    m = nrm > 1e-3 * rms
+    return float((np.linalg.norm(f - fref, axis=1)[m] / nrm[m]).max())
+
+
+def rounded(system, precision):
+    """The values the device computes with: FP32 inputs for the mixed path."""
+    return system.rounded(np.float32) if precision == H.NB_MIXED else system
+
+
+@functools.lru_cache(maxsize=None)
+def cached_config(k):
+    return {1: S.config1, 2: S.config2, 3: S.config3, 5: S.config5}[k]()
+
+
+def small_chain():
+    return S.solvated_chain(18.6, 30, 190, seed=11, cutoff=9.0, beta=0.34, name="small")
+
+
+def oracle_for(system, precision, rows=None):
+    return O.evaluate_system(rounded(system, precision), rows=rows, ke=H.COULOMB_K)
+
+
+def gpu_eval(systems, precision, cell_div_xy=0, cell_div_z=0, kernel=H.NB_KERNEL_AUTO, energy_call=False,
+             backward=False, grad_energy=None):
+    """Runs build_cells + forces (and optionally energy / backward) through the C ABI."""
+    import torch
+    systems = systems if isinstance(systems, (list, tuple)) else [systems]
+    dt = torch.float64 if precision == H.NB_FP64 else torch.float32
+    b = H.device_batch(systems, dtype=dt)
+    p = H.make_params(systems[0].cutoff, systems[0].beta, precision, cell_div_xy=cell_div_xy,
+                      cell_div_z=cell_div_z, kernel=kernel)
+    force, energy, vir, ws = H.evaluate(b, p)
+    out = dict(force=force.cpu().numpy(), energy=energy.cpu().numpy(), virial=vir.cpu().numpy(),
+               batch=b, params=p, ws=ws)
+    if energy_call:
+        e2 = torch.empty(b.n_systems, dtype=torch.float64, device="cuda")
+        ae = torch.empty(b.n_atoms, dtype=torch.float64, device="cuda")
+        H.nonbonded_energy(b, p, ws, e2, ae)
+        out.update(energy2=e2.cpu().numpy(), atom_energy=ae.cpu().numpy())
+    if backward:
+        g = torch.ones(b.n_systems, dtype=torch.float64, device="cuda") if grad_energy is None else \
+            torch.as_tensor(grad_energy, dtype=torch.float64, device="cuda")
+        T = b.sigma.shape[0]
+        gp = torch.empty((b.n_atoms, 3), dtype=torch.float64, device="cuda")
+        gq = torch.empty(b.n_atoms, dtype=torch.float64, device="cuda")
+        gs = torch.empty(T, dtype=torch.float64, device="cuda")
+        ge = torch.empty(T, dtype=torch.float64, device="cuda")
+        H.nonbonded_backward(b, p, ws, g, gp, gq, gs, ge)
+        out.update(grad_pos=gp.cpu().numpy(), grad_charge=gq.cpu().numpy(), grad_sigma=gs.cpu().numpy(),
+                   grad_eps=ge.cpu().numpy())
+    torch.cuda.synchronize()
+    out["status"] = H.read_status(ws)
+    return out
+
+
+def workspace_arrays(out):
+    """Views of the binning results inside a built workspace (host copies)."""
+    ws = out["ws"].cpu().numpy()
+    lay = H.workspace_layout(out["batch"], out["params"])
+    n = lay.n_atoms
+    cs = ws[lay.off_cell_start: lay.off_cell_start + 4 * (lay.n_cells + 1)].view(np.int32)
+    fx = ws[lay.off_sorted_fixed: lay.off_sorted_fixed + 16 * n].view(np.uint32).reshape(n, 4)
+    mk = ws[lay.off_excl_mask: lay.off_excl_mask + 16 * n].view(np.uint32).reshape(n, 4)
+    return dict(cell_start=cs, sorted_fixed=fx, excl_mask=mk)
+
+
+def oracle_binning(systems, precision, divs):
+    """Concatenated NumPy binning of every system of a batch (global cell ids / indices)."""
+    systems = systems if isinstance(systems, (list, tuple)) else [systems]
+    starts, orders, fixed = [np.zeros(1, np.int64)], [], []
+    atom0 = 0
+    base = 0
+    for s in systems:
+        r = OB.bin_system(rounded(s, precision).pos, s.box, s.cutoff, divs)
+        starts.append(r["cell_start"][1:] + base)
+        base += s.n
+        orders.append(r["order"] + atom0)
+        fixed.append(r["fixed"][r["order"]])
+        atom0 += s.n
+    return dict(cell_start=np.concatenate(starts), order=np.concatenate(orders),
+                sorted_fixed=np.concatenate(fixed) if fixed else np.zeros((0, 3), np.uint32))

@@ -1,0 +1,273 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 path 1e-12 relative RMS force error; mixed path 1e-5 (single-
+precision pair terms: per-pair relative error ~1e-7, see the erfc fit and the
+fixed-point positions); binning and exclusion windows bit-exact.
+"""
+
+import numpy as np
+import pytest
+
+import nbtest_util as U
+from paper_0902_0827_amd import nbhip as H
+from paper_0902_0827_amd import systems as S
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-5
+
+
+def _print_case(name, **kw):
+    print(f"[case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+@pytest.fixture(scope="module")
+def chain():
+    return U.small_chain()
+
+
+# --- binning: bit-exact ------------------------------------------------------------------
+
+@pytest.mark.parametrize("divs", [(2, 2), (2, 8), (1, 1), (3, 3), (2, 3)])
+@pytest.mark.parametrize("precision", [H.NB_MIXED, H.NB_FP64])
+def test_binning_is_the_stable_counting_sort(divs, precision, chain):
+    systems = [chain, U.cached_config(1), S.water_box(500, 25.0, seed=9)]
+    _print_case("binning", divs=divs, precision=precision)
+    out = U.gpu_eval(systems, precision, cell_div_xy=divs[0], cell_div_z=divs[1])
+    ws = U.workspace_arrays(out)
+    ref = U.oracle_binning(systems, precision, (divs[0], divs[0], divs[1]))
+    np.testing.assert_array_equal(ws["cell_start"], ref["cell_start"])
+    np.testing.assert_array_equal(ws["sorted_fixed"][:, 3], ref["order"])
+    np.testing.assert_array_equal(ws["sorted_fixed"][:, :3], ref["sorted_fixed"])
+    assert out["status"] == 0
+
+
+def test_binning_at_full_size_config2():
+    s = U.cached_config(2)
+    _print_case("binning-cfg2")
+    out = U.gpu_eval(s, H.NB_MIXED)
+    ws = U.workspace_arrays(out)
+    ref = U.oracle_binning([s], H.NB_MIXED, (2, 2, 2))
+    np.testing.assert_array_equal(ws["cell_start"], ref["cell_start"])
+    np.testing.assert_array_equal(ws["sorted_fixed"][:, 3], ref["order"])
+
+
+def test_exclusion_windows_are_exact(chain):
+    from oracle import binning as OB
+    systems = [chain, U.cached_config(1)]
+    out = U.gpu_eval(systems, H.NB_FP64)
+    ws = U.workspace_arrays(out)
+    cat = S.concat_systems(systems)
+    # the oracle takes global indices: shift each system's local partners
+    idx = cat["excl_index"].copy()
+    off = cat["excl_offset"]
+    base = np.repeat(np.repeat([0, chain.n], [chain.n, U.cached_config(1).n]), np.diff(off))
+    masks, far = OB.exclusion_windows(int(cat["atom_offset"][-1]), off, idx + base)
+    np.testing.assert_array_equal(ws["excl_mask"], masks)
+    assert not far.any()
+
+
+# --- forces, energies, virial --------------------------------------------------------------
+
+@pytest.mark.parametrize("which", ["cfg1", "chain", "cfg2"])
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+def test_forces_energy_virial_match_oracle(which, precision, chain):
+    s = {"cfg1": lambda: U.cached_config(1), "chain": lambda: chain, "cfg2": lambda: U.cached_config(2)}[which]()
+    _print_case("forces", which=which, precision=precision, n=s.n)
+    out = U.gpu_eval(s, precision, energy_call=True)
+    ref = U.oracle_for(s, precision)
+    tol = FP64_TOL if precision == H.NB_FP64 else MIXED_TOL
+    err = U.rel_rms(out["force"], ref["force"])
+    print(f"  rel_rms={err:.3e} max_rel_atom={U.max_rel_atom(out['force'], ref['force']):.3e}")
+    assert err <= tol
+    assert out["energy"][0] == pytest.approx(ref["energy_total"], rel=tol, abs=tol)
+    assert U.rel_rms(out["virial"][0], ref["virial"]) <= (1e-11 if precision == H.NB_FP64 else 1e-5)
+    assert U.rel_rms(out["atom_energy"], ref["energy"]) <= (1e-11 if precision == H.NB_FP64 else 1e-5)
+    assert out["energy2"][0] == out["energy"][0]  # the energy call sums the same terms in the same order
+    assert out["status"] == 0
+
+
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+def test_run_twice_is_bitwise_identical(precision, chain):
+    a = U.gpu_eval(chain, precision)
+    b = U.gpu_eval(chain, precision)
+    np.testing.assert_array_equal(a["force"], b["force"])
+    np.testing.assert_array_equal(a["energy"], b["energy"])
+    np.testing.assert_array_equal(a["virial"], b["virial"])
+
+
+def test_cell_grid_choice_does_not_change_fp64_result(chain):
+    ref = U.oracle_for(chain, H.NB_FP64)
+    for divs in [(1, 1), (2, 2), (2, 8), (3, 3), (4, 16)]:
+        out = U.gpu_eval(chain, H.NB_FP64, cell_div_xy=divs[0], cell_div_z=divs[1])
+        assert U.rel_rms(out["force"], ref["force"]) <= FP64_TOL, divs
+
+
+def test_relabelled_atoms_give_permuted_forces(chain):
+    rng = np.random.default_rng(3)
+    p = rng.permutation(chain.n)
+    inv = np.argsort(p)
+    rows = [[] for _ in range(chain.n)]
+    for i in range(chain.n):
+        for k in range(chain.excl_offset[i], chain.excl_offset[i + 1]):
+            rows[inv[i]].append(int(inv[chain.excl_index[k]]))
+    off = np.zeros(chain.n + 1, np.int32)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    idx = np.array([j for r in rows for j in sorted(r)], np.int32)
+    perm = S.System(**{**chain.__dict__})
+    perm.pos, perm.charge, perm.type = chain.pos[p], chain.charge[p], chain.type[p]
+    perm.excl_offset, perm.excl_index = off, idx
+    a = U.gpu_eval(chain, H.NB_FP64)
+    b = U.gpu_eval(perm, H.NB_FP64)
+    np.testing.assert_allclose(b["force"], a["force"][p], rtol=0, atol=1e-12 * np.abs(a["force"]).max())
+    # relabelling moves some exclusions beyond the 64-atom window: the far path is exercised
+    assert b["status"] == H.NB_STATUS_FAR_EXCLUSION
+
+
+# --- batches -------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+def test_batch_equals_each_system_alone(precision, chain):
+    systems = [S.water_box(300, 20.0, seed=1), chain, S.water_box(1200, 26.0, seed=2),
+               S.solvated_chain(30.0, 80, 800, seed=4, cutoff=9.0, beta=0.34)]
+    out = U.gpu_eval(systems, precision)
+    off = np.concatenate([[0], np.cumsum([s.n for s in systems])])
+    for k, s in enumerate(systems):
+        alone = U.gpu_eval(s, precision)
+        np.testing.assert_array_equal(out["force"][off[k]:off[k + 1]], alone["force"])
+        assert out["energy"][k] == alone["energy"][0]
+        np.testing.assert_array_equal(out["virial"][k], alone["virial"][0])
+
+
+# --- edge cases ----------------------------------------------------------------------------
+
+def test_tiny_and_empty_systems():
+    two = S.System(name="two", pos=np.array([[1.0, 1.0, 1.0], [4.0, 1.0, 1.5]]), charge=np.array([0.5, -0.5]),
+                   type=np.array([0, 0], np.int32), sigma=np.array([3.0]), eps=np.array([0.4]),
+                   excl_offset=np.zeros(3, np.int32), excl_index=np.zeros(0, np.int32),
+                   box=np.array([20.0, 21.0, 22.0]), cutoff=9.0, beta=0.3, seed=0)
+    empty = S.System(name="empty", pos=np.zeros((0, 3)), charge=np.zeros(0), type=np.zeros(0, np.int32),
+                     sigma=np.array([3.0]), eps=np.array([0.4]), excl_offset=np.zeros(1, np.int32),
+                     excl_index=np.zeros(0, np.int32), box=np.array([20.0, 20.0, 20.0]), cutoff=9.0,
+                     beta=0.3, seed=0)
+    out = U.gpu_eval([two, empty, two], H.NB_FP64)
+    ref = U.oracle_for(two, H.NB_FP64)
+    np.testing.assert_allclose(out["force"][:2], ref["force"], rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(out["force"][2:], ref["force"], rtol=1e-13, atol=1e-13)
+    assert out["energy"][1] == 0.0 and not out["virial"][1].any()
+
+
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+def test_positions_outside_the_box_are_wrapped(precision, chain):
+    moved = S.System(**{**chain.__dict__})
+    shift = np.zeros_like(chain.pos)
+    shift[::2] = chain.box * np.array([2, -3, 1])
+    shift[1::5] = -chain.box * np.array([1, 1, 4])
+    moved.pos = chain.pos + shift
+    out = U.gpu_eval(moved, precision)
+    ref = U.oracle_for(moved, precision)
+    assert U.rel_rms(out["force"], ref["force"]) <= (1e-11 if precision == H.NB_FP64 else MIXED_TOL)
+
+
+def test_device_status_bits():
+    s = S.water_box(200, 19.0, seed=5)
+    bad = S.System(**{**s.__dict__})
+    bad.pos = s.pos.copy()
+    bad.pos[7, 1] = np.nan
+    bad.type = s.type.copy()
+    bad.type[3] = 17
+    out = U.gpu_eval(bad, H.NB_FP64)
+    assert out["status"] & H.NB_STATUS_NONFINITE_POS
+    assert out["status"] & H.NB_STATUS_BAD_TYPE
+    bad2 = S.System(**{**s.__dict__})
+    bad2.excl_index = s.excl_index.copy()
+    bad2.excl_index[5] = 10 ** 6
+    out = U.gpu_eval(bad2, H.NB_FP64)
+    assert out["status"] & H.NB_STATUS_BAD_EXCLUSION
+
+
+# --- adjoint -------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+@pytest.mark.parametrize("which", ["chain", "cfg3"])
+def test_backward_matches_oracle_gradients(precision, which, chain):
+    s = chain if which == "chain" else U.cached_config(3)
+    _print_case("backward", which=which, precision=precision)
+    g = 1.7
+    out = U.gpu_eval(s, precision, backward=True, grad_energy=[g])
+    ref = U.oracle_for(s, precision)
+    tol = 1e-11 if precision == H.NB_FP64 else MIXED_TOL
+    assert U.rel_rms(out["grad_pos"], -g * ref["force"]) <= tol
+    assert U.rel_rms(out["grad_charge"], g * ref["phi"]) <= tol
+    present = np.unique(s.type)
+    lj = present[s.eps[present] > 0]
+    np.testing.assert_allclose(out["grad_sigma"][lj], g * ref["dsigma"][lj], rtol=tol * 10, atol=tol)
+    np.testing.assert_allclose(out["grad_eps"][lj], g * ref["deps"][lj], rtol=tol * 10, atol=tol)
+    assert np.all(out["grad_eps"][s.eps == 0] == 0.0)
+
+
+def test_autograd_function_and_fd_of_the_fp64_energy(chain):
+    b = H.device_batch([chain], dtype=torch.float64)
+    p = H.make_params(chain.cutoff, chain.beta, H.NB_FP64)
+    pos = b.pos.clone().requires_grad_(True)
+    q = b.charge.clone().requires_grad_(True)
+    sig = b.sigma.clone().requires_grad_(True)
+    eps = b.eps.clone().requires_grad_(True)
+    E = H.nonbonded_energy_autograd(pos, q, sig, eps, b, p)
+    E.sum().backward()
+    h = 1e-4
+
+    def energy(**kw):
+        args = dict(pos=b.pos, q=b.charge, sig=b.sigma, eps=b.eps)
+        args.update(kw)
+        with torch.no_grad():
+            return float(H.nonbonded_energy_autograd(args["pos"], args["q"], args["sig"], args["eps"], b, p)[0])
+
+    rng = np.random.default_rng(0)
+    n_ok = 0
+    for i in rng.choice(chain.n, 25, replace=False):
+        d = chain.pos - chain.pos[i]
+        d -= chain.box * np.rint(d / chain.box)
+        r = np.sqrt((d * d).sum(1))
+        if np.any(np.abs(r - chain.cutoff) <= 2 * h):
+            continue  # a probe would cross the hard cutoff
+        for a in range(3):
+            pp = b.pos.clone(); pp[i, a] += h
+            pm = b.pos.clone(); pm[i, a] -= h
+            fd = (energy(pos=pp) - energy(pos=pm)) / (2 * h)
+            assert fd == pytest.approx(float(pos.grad[i, a]), rel=1e-4, abs=1e-4)
+        n_ok += 1
+    assert n_ok >= 10
+    for t in np.unique(chain.type):
+        if chain.eps[t] <= 0:
+            continue
+        sp = b.sigma.clone(); sp[t] += h
+        sm = b.sigma.clone(); sm[t] -= h
+        assert (energy(sig=sp) - energy(sig=sm)) / (2 * h) == pytest.approx(float(sig.grad[t]), rel=1e-4, abs=1e-5)
+        ep = b.eps.clone(); ep[t] += h
+        em = b.eps.clone(); em[t] -= h
+        assert (energy(eps=ep) - energy(eps=em)) / (2 * h) == pytest.approx(float(eps.grad[t]), rel=1e-4, abs=1e-5)
+    for i in (0, 40, 300):
+        qp = b.charge.clone(); qp[i] += h
+        qm = b.charge.clone(); qm[i] -= h
+        assert (energy(q=qp) - energy(q=qm)) / (2 * h) == pytest.approx(float(q.grad[i]), rel=1e-5, abs=1e-6)
+
+
+# --- full-size configurations --------------------------------------------------------------
+
+def test_config5_mixed_against_sampled_oracle_and_fp64_gpu():
+    s = U.cached_config(5)
+    _print_case("cfg5", n=s.n)
+    mixed = U.gpu_eval(s, H.NB_MIXED)
+    fp64 = U.gpu_eval(s, H.NB_FP64)
+    err = U.rel_rms(mixed["force"], fp64["force"])
+    print(f"  mixed vs fp64 gpu rel_rms={err:.3e} max_rel_atom={U.max_rel_atom(mixed['force'], fp64['force']):.3e}")
+    assert err <= MIXED_TOL
+    rows = np.random.default_rng(5).choice(s.n, 96, replace=False)
+    ref32 = U.oracle_for(s, H.NB_MIXED, rows=rows)
+    ref64 = U.oracle_for(s, H.NB_FP64, rows=rows)
+    assert U.rel_rms(mixed["force"][rows], ref32["force"]) <= MIXED_TOL
+    assert U.rel_rms(fp64["force"][rows], ref64["force"]) <= FP64_TOL
