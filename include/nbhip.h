@@ -55,6 +55,8 @@ typedef enum {
 #define NB_STATUS_BAD_TYPE 0x2u       /* a type index outside [0, n_types) (treated as type 0) */
 #define NB_STATUS_BAD_EXCLUSION 0x4u  /* an exclusion row not monotone or an index outside the system */
 #define NB_STATUS_FAR_EXCLUSION 0x8u  /* informational: some exclusion is more than 64 atoms apart in index */
+#define NB_STATUS_NOT_BUILT 0x10u     /* the workspace was not built by nb_build_cells for this system size and
+                                         kernel variant: the pair kernels wrote nothing */
 
 typedef enum {
   NB_FP64 = 0,  /* double-precision pair arithmetic from double positions */
@@ -160,6 +162,12 @@ typedef struct {
   int64_t off_sorted_pos64; /* double x4 [n_atoms]: wrapped x, y, z, charge (FP64 data) */
   int64_t off_excl_mask;    /* uint32 x4 [n_atoms], original order: exclusion window bits */
   int64_t off_status;       /* uint32 status word */
+  int64_t n_columns;        /* (x, y) columns of all systems */
+  int64_t n_clusters_max;   /* capacity of the cluster arrays */
+  int64_t off_col_clu_start;/* int32 [n_columns + 1]: first cluster of each column (cluster kernel) */
+  int64_t off_clusters;     /* int32 x4 [n_clusters_max]: first sorted atom, count, column, system */
+  int64_t off_clu_ctr;      /* uint32 x4 [n_clusters_max]: bounding-box centre (fixed point) */
+  int64_t off_clu_half;     /* uint32 x4 [n_clusters_max]: bounding-box half extent */
 } nb_layout;
 
 nb_status nb_workspace_layout(const nb_system *sys, const nb_params *params, nb_layout *layout /*[host]*/);

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 
@@ -62,9 +63,10 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   p.N = N;
   p.T = sys->n_types;
   p.precision = prm->precision;
-  p.kernel = prm->kernel == NB_KERNEL_AUTO ? NB_KERNEL_ATOM : prm->kernel;
+  p.kernel = prm->kernel == NB_KERNEL_AUTO ? NB_KERNEL_CLUSTER : prm->kernel;
   p.div_xy = prm->cell_div_xy ? prm->cell_div_xy : 2;
-  p.div_z = prm->cell_div_z ? prm->cell_div_z : p.div_xy;
+  // The cluster kernel wants thin z-cells, so that a column's atoms come out nearly z-sorted.
+  p.div_z = prm->cell_div_z ? prm->cell_div_z : (p.kernel == NB_KERNEL_CLUSTER ? 8 : p.div_xy);
   p.cutoff = prm->cutoff;
   p.beta = prm->ewald_beta;
   p.ke = prm->coulomb_k;
@@ -132,11 +134,14 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   l.s_type = take(4 * static_cast<size_t>(N));
   l.excl_mask = take(16 * static_cast<size_t>(N));
   l.excl_far = take(4 * static_cast<size_t>(N));
-  l.partials = take(8 * kPart * static_cast<size_t>(blocks > 0 ? blocks : 1));
-  l.adj_partials = take(8 * 2 * static_cast<size_t>(p.T) * static_cast<size_t>(blocks > 0 ? blocks : 1));
-  l.clusters = take(0);
-  l.clu_bbox = take(0);
-  l.col_cluster = take(0);
+  const size_t nparts = static_cast<size_t>(std::max<int64_t>(std::max<int64_t>(blocks, clusters), 1));
+  l.partials = take(8 * kPart * nparts);
+  l.adj_partials = take(8 * 2 * static_cast<size_t>(p.T) * nparts);
+  l.col_nclu = take(4 * static_cast<size_t>(columns));
+  l.col_clu_start = take(4 * static_cast<size_t>(columns + 1));
+  l.clusters = take(16 * static_cast<size_t>(clusters));
+  l.clu_ctr = take(16 * static_cast<size_t>(clusters));
+  l.clu_half = take(16 * static_cast<size_t>(clusters));
   l.total = o;
   *plan = std::move(p);
   return NB_OK;
@@ -169,6 +174,13 @@ Dev dev_view(const Plan &p, void *ws) {
   d.adj_partials = reinterpret_cast<double *>(base + l.adj_partials);
   d.N = p.N;
   d.n_blocks = p.n_blocks;
+  d.col_nclu = reinterpret_cast<int32_t *>(base + l.col_nclu);
+  d.col_clu_start = reinterpret_cast<int32_t *>(base + l.col_clu_start);
+  d.clusters = reinterpret_cast<int4 *>(base + l.clusters);
+  d.clu_ctr = reinterpret_cast<uint4 *>(base + l.clu_ctr);
+  d.clu_half = reinterpret_cast<uint4 *>(base + l.clu_half);
+  d.n_columns = p.n_columns;
+  d.n_clusters_max = p.n_clusters_max;
   return d;
 }
 
@@ -217,6 +229,12 @@ nb_status nb_workspace_layout(const nb_system *sys, const nb_params *params, nb_
   layout->off_sorted_pos64 = static_cast<int64_t>(p.lay.s_pos64);
   layout->off_excl_mask = static_cast<int64_t>(p.lay.excl_mask);
   layout->off_status = static_cast<int64_t>(p.lay.status);
+  layout->n_columns = p.n_columns;
+  layout->n_clusters_max = p.n_clusters_max;
+  layout->off_col_clu_start = static_cast<int64_t>(p.lay.col_clu_start);
+  layout->off_clusters = static_cast<int64_t>(p.lay.clusters);
+  layout->off_clu_ctr = static_cast<int64_t>(p.lay.clu_ctr);
+  layout->off_clu_half = static_cast<int64_t>(p.lay.clu_half);
   return NB_OK;
 }
 

@@ -40,11 +40,17 @@ __global__ void k_put_desc(Dev d, DescChunk c) {
   if (k < c.count) d.desc[c.first + k] = c.d[k];
 }
 
-__global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, const double *__restrict__ eps) {
+__global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, const double *__restrict__ eps,
+                       int kernel) {
   const int64_t tid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   if (tid < c.count) d.desc[c.first + tid] = c.d[tid];
-  if (tid == 0) d.status[0] = 0u;
+  if (tid == 0) {
+    d.status[0] = 0u;
+    d.status[1] = kBuiltMagic;
+    d.status[2] = static_cast<uint32_t>(d.N);
+    d.status[3] = static_cast<uint32_t>(kernel);
+  }
   for (int64_t k = tid; k < d.n_cells; k += stride) d.cell_count[k] = 0;
   for (int64_t k = tid; k < d.N; k += stride) {
     d.excl_mask[k] = make_uint4(0u, 0u, 0u, 0u);
@@ -140,17 +146,17 @@ __global__ void k_bin(Dev d, const Real *__restrict__ pos, const int32_t *__rest
   }
 }
 
-// Exclusive scan of cell_count into cell_start (n_cells + 1 entries) by one
-// workgroup: each thread sums a contiguous chunk, the chunk sums are scanned in
-// LDS, then each thread writes its chunk.
-__global__ void __launch_bounds__(1024) k_scan(Dev d) {
+// Exclusive scan of n counts into n + 1 offsets by one workgroup: each thread
+// sums a contiguous chunk, the chunk sums are scanned in LDS, then each thread
+// writes its chunk.
+__global__ void __launch_bounds__(1024) k_scan(const int32_t *__restrict__ count, int32_t *__restrict__ start,
+                                               int64_t n) {
   __shared__ int sums[1024];
   const int tid = threadIdx.x;
-  const int64_t n = d.n_cells;
   const int64_t chunk = (n + 1023) / 1024;
   const int64_t lo = tid * chunk, hi = lo + chunk < n ? lo + chunk : n;
   int s = 0;
-  for (int64_t k = lo; k < hi; ++k) s += d.cell_count[k];
+  for (int64_t k = lo; k < hi; ++k) s += count[k];
   sums[tid] = s;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
@@ -161,11 +167,11 @@ __global__ void __launch_bounds__(1024) k_scan(Dev d) {
   }
   int run = sums[tid] - s;  // exclusive prefix of this chunk
   for (int64_t k = lo; k < hi; ++k) {
-    const int c = d.cell_count[k];
-    d.cell_start[k] = run;
+    const int c = count[k];
+    start[k] = run;
     run += c;
   }
-  if (tid == 1023) d.cell_start[n] = sums[1023];
+  if (tid == 1023) start[n] = sums[1023];
 }
 
 __global__ void k_scatter(Dev d) {
@@ -196,6 +202,66 @@ __global__ void k_finalize(Dev d, const Real *__restrict__ pos, const Real *__re
   d.s_type[dst] = (t < 0 || t >= d.T) ? 0 : t;
 }
 
+// Clusters for the cluster pair kernel: the sorted atoms of each (x, y) column
+// (z-cells are contiguous inside a column) are cut into runs of 8.
+__device__ inline int column_system(const SysDesc *desc, int B, int col) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].col_begin <= col) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_col_count(Dev d) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= d.n_columns) return;
+  const SysDesc &sd = d.desc[column_system(d.desc, d.B, col)];
+  const int nz = sd.dims[2];
+  const int c0 = sd.cell_begin + (col - sd.col_begin) * nz;
+  const int n = d.cell_start[c0 + nz] - d.cell_start[c0];
+  d.col_nclu[col] = (n + 7) >> 3;
+}
+
+// One wave per column; each lane builds clusters of that column: record and
+// bounding box (centre and half extent, in fixed point, taken relative to the
+// cluster's first atom so that the minimum image is respected).
+__global__ void __launch_bounds__(64) k_make_clusters(Dev d) {
+  const int col = blockIdx.x;
+  const int sys = column_system(d.desc, d.B, col);
+  const SysDesc &sd = d.desc[sys];
+  const int nz = sd.dims[2];
+  const int c0 = sd.cell_begin + (col - sd.col_begin) * nz;
+  const int a0 = d.cell_start[c0], a1 = d.cell_start[c0 + nz];
+  const int first = d.col_clu_start[col];
+  const int ncl = d.col_clu_start[col + 1] - first;
+  for (int m = threadIdx.x; m < ncl; m += 64) {
+    const int b = a0 + 8 * m;
+    const int cnt = a1 - b < 8 ? a1 - b : 8;
+    const uint4 u0 = d.s_fix[b];
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int k = 1; k < cnt; ++k) {
+      const uint4 u = d.s_fix[b + k];
+      const int dd[3] = {static_cast<int>(u.x - u0.x), static_cast<int>(u.y - u0.y), static_cast<int>(u.z - u0.z)};
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = dd[a] < lo[a] ? dd[a] : lo[a];
+        hi[a] = dd[a] > hi[a] ? dd[a] : hi[a];
+      }
+    }
+    uint32_t ctr[3], half[3];
+    const uint32_t base[3] = {u0.x, u0.y, u0.z};
+    for (int a = 0; a < 3; ++a) {
+      const int64_t mid = (static_cast<int64_t>(lo[a]) + hi[a]) >> 1;  // floor
+      const int64_t h = (hi[a] - mid) > (mid - lo[a]) ? (hi[a] - mid) : (mid - lo[a]);
+      ctr[a] = base[a] + static_cast<uint32_t>(static_cast<int32_t>(mid));
+      half[a] = static_cast<uint32_t>(h);
+    }
+    d.clusters[first + m] = make_int4(b, cnt, col, sys);
+    d.clu_ctr[first + m] = make_uint4(ctr[0], ctr[1], ctr[2], 0u);
+    d.clu_half[first + m] = make_uint4(half[0], half[1], half[2], 0u);
+  }
+}
+
 unsigned grid_for(int64_t n, int block) {
   const int64_t g = (n + block - 1) / block;
   return static_cast<unsigned>(g > 0 ? g : 1);
@@ -212,7 +278,7 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
   const int64_t init_work = plan.N > plan.n_cells ? plan.N : plan.n_cells;
   unsigned g_init = grid_for(init_work, kBlock);
   if (g_init > 4096) g_init = 4096;
-  hipLaunchKernelGGL(k_init, dim3(g_init), dim3(kBlock), 0, s, d, first, sys->lj_sigma, sys->lj_eps);
+  hipLaunchKernelGGL(k_init, dim3(g_init), dim3(kBlock), 0, s, d, first, sys->lj_sigma, sys->lj_eps, plan.kernel);
   for (int b0 = kDescChunk; b0 < plan.B; b0 += kDescChunk) {
     DescChunk c{};
     c.first = b0;
@@ -221,7 +287,11 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
     hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, c);
   }
   if (plan.N == 0) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d.cell_count, d.cell_start, d.n_cells);
+    if (plan.kernel == NB_KERNEL_CLUSTER) {
+      hipLaunchKernelGGL(k_col_count, dim3(grid_for(plan.n_columns, kBlock)), dim3(kBlock), 0, s, d);
+      hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d.col_nclu, d.col_clu_start, d.n_columns);
+    }
     return hipGetLastError();
   }
   const unsigned g = grid_for(plan.N, kBlock);
@@ -231,7 +301,7 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
   else
     hipLaunchKernelGGL(k_bin<float>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const float *>(sys->pos),
                        sys->type, sys->excl_offset, sys->excl_index);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d.cell_count, d.cell_start, d.n_cells);
   hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kBlock), 0, s, d);
   const double sqrt_ke = sqrt(plan.ke);
   if (sys->pos_is_f64)
@@ -240,6 +310,11 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
   else
     hipLaunchKernelGGL(k_finalize<float>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const float *>(sys->pos),
                        static_cast<const float *>(sys->charge), sys->type, sqrt_ke);
+  if (plan.kernel == NB_KERNEL_CLUSTER) {
+    hipLaunchKernelGGL(k_col_count, dim3(grid_for(plan.n_columns, kBlock)), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d.col_nclu, d.col_clu_start, d.n_columns);
+    hipLaunchKernelGGL(k_make_clusters, dim3(static_cast<unsigned>(plan.n_columns)), dim3(64), 0, s, d);
+  }
   return hipGetLastError();
 }
 

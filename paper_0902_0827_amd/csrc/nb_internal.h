@@ -18,6 +18,14 @@ constexpr int kWaves = kBlock / 64;   // wave64
 constexpr int kPart = 10;             // per-block partial sums: energy + 9 virial entries
 constexpr int kWindow = 64;           // exclusion bitmap reach in original index (section 3)
 constexpr int kDescChunk = 8;         // system descriptors carried by one initialisation launch
+constexpr uint32_t kBuiltMagic = 0x4E424831u;  // status[1]: written by nb_build_cells
+
+// Workspace header words: status[0] = NB_STATUS_* bits, status[1] = kBuiltMagic,
+// status[2] = atom count, status[3] = kernel variant the cluster data was built for.
+__device__ __forceinline__ bool built_for(const uint32_t *status, int64_t n_atoms, int kernel) {
+  return status[1] == kBuiltMagic && status[2] == static_cast<uint32_t>(n_atoms) &&
+         (kernel != NB_KERNEL_CLUSTER || status[3] == static_cast<uint32_t>(NB_KERNEL_CLUSTER));
+}
 
 // Per-system descriptor, resident in the workspace.  Sorted atoms of system b are
 // [atom_begin, atom_end) (the sort keeps systems in order), its cells are
@@ -43,7 +51,7 @@ struct alignas(16) TypePair32 { float c6, c12, inv_sig, pad; };
 struct Layout {
   size_t status, desc, tab64, tab32, cell_count, cell_start, atom_cell, atom_slot, atom_fix, tmp;
   size_t s_fix, s_pos64, s_q32, s_type, excl_mask, excl_far, partials, adj_partials;
-  size_t clusters, clu_bbox, col_cluster;
+  size_t col_nclu, col_clu_start, clusters, clu_ctr, clu_half;
   size_t total;
 };
 
@@ -79,10 +87,38 @@ struct Dev {
   int32_t *s_type;   // sorted: type (clamped into range)
   uint4 *excl_mask;  // original order: 128-bit exclusion window
   uint32_t *excl_far;// original order: nonzero if the atom has an exclusion beyond the window
-  double *partials;      // [n_blocks][kPart]
-  double *adj_partials;  // [n_blocks][2 T]
+  double *partials;      // [max(n_blocks, n_clusters_max)][kPart]
+  double *adj_partials;  // [max(n_blocks, n_clusters_max)][2 T]
   int64_t N;
   int64_t n_blocks;
+  // Cluster kernel: 8 consecutive sorted atoms of one (x, y) column form a cluster.
+  int32_t *col_nclu;       // [n_columns] clusters per column
+  int32_t *col_clu_start;  // [n_columns + 1] first cluster of each column (global)
+  int4 *clusters;          // [n_clusters_max] first sorted atom, atom count, global column, system
+  uint4 *clu_ctr;          // [n_clusters_max] bounding-box centre (fixed point)
+  uint4 *clu_half;         // [n_clusters_max] bounding-box half extent (fixed-point units)
+  int64_t n_columns;
+  int64_t n_clusters_max;
+};
+
+// Per-call constants and outputs of the pair kernels.
+enum PairMode : int { kForces = 0, kEnergy = 1, kAdjoint = 2 };
+
+struct Consts {
+  double rc2, beta, two_beta_sqrtpi, ke, sqrt_ke;
+  float rc2f, betaf, two_beta_sqrtpif, mb2l2e, rc2_box;
+};
+
+struct Out {
+  double *force;
+  double *atom_energy;
+  double *grad_pos;
+  double *grad_charge;
+  const double *grad_energy;
+  const int32_t *excl_off;
+  const int32_t *excl_idx;
+  int want_part;    // write energy (and, for forces, virial) partials
+  int want_virial;
 };
 
 // Host helpers (nb_api.cpp).
@@ -99,5 +135,8 @@ hipError_t launch_energy(const Plan &plan, const Dev &d, const nb_system *sys, d
 hipError_t launch_backward(const Plan &plan, const Dev &d, const nb_system *sys,
                            const double *grad_energy, double *grad_pos, double *grad_charge,
                            double *grad_sigma, double *grad_eps, hipStream_t s);
+// Cluster pair kernel (nb_pair_cluster.hip): one wave per 8-atom cluster.
+void launch_cluster_pair(const Plan &plan, const Dev &d, const Consts &c, const Out &o, int mode,
+                         hipStream_t s);
 
 }  // namespace nb

@@ -12,68 +12,22 @@
 // precision pair terms, double accumulation), and three outputs: forces (with
 // per-block energy/virial partials), energies, and the adjoint.
 #include "nb_internal.h"
+#include "nb_pair_common.h"
 #include "nb_pair_math.h"
 
 namespace nb {
 
 namespace {
 
-enum Mode : int { kForces = 0, kEnergy = 1, kAdjoint = 2 };
-
-struct Consts {
-  double rc2, beta, two_beta_sqrtpi, ke, sqrt_ke;
-  float rc2f, betaf, two_beta_sqrtpif, mb2l2e;
-};
-
-struct Out {
-  double *force;
-  double *atom_energy;
-  double *grad_pos;
-  double *grad_charge;
-  const double *grad_energy;
-  const int32_t *excl_off;
-  const int32_t *excl_idx;
-  int want_part;
-};
-
-__device__ __forceinline__ int block_system(const SysDesc *desc, int B, int blk) {
-  int lo = 0, hi = B - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (desc[mid].blk_begin <= blk) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Exclusion test for a pair of original indices (oi's window, far-list fallback).
-__device__ __forceinline__ bool excluded(const Dev &d, const Out &o, const uint4 &mask_i, bool far_i,
-                                         int oi, int oj, int atom_begin) {
-  const int delta = oj - oi;
-  if (delta >= -kWindow && delta <= kWindow) {
-    const int bit = delta < 0 ? delta + kWindow : delta + kWindow - 1;
-    const int wsel = bit >> 5;
-    const uint32_t w = wsel == 0 ? mask_i.x : wsel == 1 ? mask_i.y : wsel == 2 ? mask_i.z : mask_i.w;
-    return (w >> (bit & 31)) & 1u;
-  }
-  if (!far_i || d.excl_far[oj] == 0u) return false;
-  const int il = oi - atom_begin, jl = oj - atom_begin;
-  for (int k = o.excl_off[oi]; k < o.excl_off[oi + 1]; ++k)
-    if (o.excl_idx[k] == jl) return true;
-  for (int k = o.excl_off[oj]; k < o.excl_off[oj + 1]; ++k)
-    if (o.excl_idx[k] == il) return true;
-  return false;
-}
-
 template <bool F64, int MODE>
 __global__ void __launch_bounds__(kBlock) k_pair_atom(Dev d, Consts c, Out o) {
   __shared__ double red[kWaves][2 * NB_MAX_TYPES > kPart ? 2 * NB_MAX_TYPES : kPart];
   const int blk = blockIdx.x;
-  const int b = block_system(d.desc, d.B, blk);
+  if (!built_for(d.status, d.N, NB_KERNEL_ATOM)) {
+    if (blk == 0 && threadIdx.x == 0) atomicOr(d.status, NB_STATUS_NOT_BUILT);
+    return;
+  }
+  const int b = find_desc<&SysDesc::blk_begin>(d.desc, d.B, blk);
   const SysDesc &sd = d.desc[b];
   const int i = sd.atom_begin + (blk - sd.blk_begin) * kBlock + static_cast<int>(threadIdx.x);
   const bool active = i < sd.atom_end;
@@ -116,7 +70,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_atom(Dev d, Consts c, Out o) {
         dz -= sd.box[2] * rint(dz * sd.inv_box[2]);
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (!(r2 < c.rc2) || j == i) return;
-        if (excluded(d, o, mask_i, far_i, oi, oj, sd.atom_begin)) return;
+        if (pair_excluded(mask_i, far_i, oi, oj, sd.atom_begin, d.excl_far, o.excl_off, o.excl_idx)) return;
         const TypePair64 tp = row64[d.s_type[j]];
         const PairF64 p = pair_f64(r2, tp.c6, tp.c12, qi64 * pj.w, c.beta, c.two_beta_sqrtpi);
         en += p.u_lj + p.u_c;
@@ -141,7 +95,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_atom(Dev d, Consts c, Out o) {
         const float dx = static_cast<float>(ix), dy = static_cast<float>(iy), dz = static_cast<float>(iz);
         const float r2 = fmaf(sd.scale2f[2] * dz, dz, fmaf(sd.scale2f[1] * dy, dy, sd.scale2f[0] * dx * dx));
         if (!(r2 < c.rc2f) || j == i) return;
-        if (excluded(d, o, mask_i, far_i, oi, oj, sd.atom_begin)) return;
+        if (pair_excluded(mask_i, far_i, oi, oj, sd.atom_begin, d.excl_far, o.excl_off, o.excl_idx)) return;
         const TypePair32 tp = row32[d.s_type[j]];
         const float qj = d.s_q32[j];
         const PairF32 p = pair_f32(r2, tp.c6, tp.c12, qi32 * qj, c.betaf, c.two_beta_sqrtpif, c.mb2l2e);
@@ -286,16 +240,29 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
   return s;
 }
 
-// Energy and virial of system b = sum of its blocks' partials, in a fixed order.
-__global__ void __launch_bounds__(kBlock) k_reduce_sys(Dev d, double *energy, double *virial, int nv) {
+// Range of partial-sum slots owned by system b: its per-atom-kernel blocks, or
+// its clusters (known on the device only, from the column scan).
+__device__ __forceinline__ void partial_range(const Dev &d, int cluster, const SysDesc &sd, int *lo, int *hi) {
+  if (cluster) {
+    *lo = d.col_clu_start[sd.col_begin];
+    *hi = d.col_clu_start[sd.col_begin + sd.dims[0] * sd.dims[1]];
+  } else {
+    *lo = sd.blk_begin;
+    *hi = sd.blk_begin + (sd.atom_end - sd.atom_begin + kBlock - 1) / kBlock;
+  }
+}
+
+// Energy and virial of system b = sum of its partials, in a fixed order.
+__global__ void __launch_bounds__(kBlock) k_reduce_sys(Dev d, double *energy, double *virial, int nv, int cluster) {
   __shared__ double lds[kWaves];
+  if (!built_for(d.status, d.N, cluster ? NB_KERNEL_CLUSTER : NB_KERNEL_ATOM)) return;
   const int b = blockIdx.x;
   const SysDesc &sd = d.desc[b];
-  const int nblk = (sd.atom_end - sd.atom_begin + kBlock - 1) / kBlock;
+  int lo, hi;
+  partial_range(d, cluster, sd, &lo, &hi);
   for (int k = 0; k < nv; ++k) {
     double s = 0;
-    for (int q = threadIdx.x; q < nblk; q += kBlock)
-      s += d.partials[static_cast<int64_t>(sd.blk_begin + q) * kPart + k];
+    for (int q = lo + threadIdx.x; q < hi; q += kBlock) s += d.partials[static_cast<int64_t>(q) * kPart + k];
     s = block_sum(s, lds);
     if (threadIdx.x == 0) {
       if (k == 0 && energy) energy[b] = s;
@@ -304,13 +271,15 @@ __global__ void __launch_bounds__(kBlock) k_reduce_sys(Dev d, double *energy, do
   }
 }
 
-// Per-type parameter gradients: sum the (already g-scaled) block partials.
+// Per-type parameter gradients: sum the (already g-scaled) partials of every slot.
 __global__ void __launch_bounds__(kBlock) k_reduce_types(Dev d, const double *__restrict__ eps,
-                                                         double *grad_sigma, double *grad_eps) {
+                                                         double *grad_sigma, double *grad_eps, int cluster) {
+  if (!built_for(d.status, d.N, cluster ? NB_KERNEL_CLUSTER : NB_KERNEL_ATOM)) return;
   const int T = d.T;
+  const int64_t n = cluster ? d.col_clu_start[d.n_columns] : d.n_blocks;
   for (int t = threadIdx.x; t < 2 * T; t += kBlock) {
     double s = 0;
-    for (int64_t q = 0; q < d.n_blocks; ++q) s += d.adj_partials[q * 2 * T + t];
+    for (int64_t q = 0; q < n; ++q) s += d.adj_partials[q * 2 * T + t];
     if (t < T) {
       if (grad_sigma) grad_sigma[t] = s;
     } else {
@@ -331,6 +300,7 @@ Consts make_consts(const Plan &p) {
   c.betaf = static_cast<float>(p.beta);
   c.two_beta_sqrtpif = static_cast<float>(c.two_beta_sqrtpi);
   c.mb2l2e = static_cast<float>(-p.beta * p.beta * 1.4426950408889634074);  // -beta^2 log2(e)
+  c.rc2_box = static_cast<float>(c.rc2 * 1.0001);  // generous: the box filter may only keep extra atoms
   return c;
 }
 
@@ -343,8 +313,12 @@ Out base_out(const nb_system *sys) {
 
 template <int MODE>
 void launch_pair(const Plan &p, const Dev &d, const Out &o, hipStream_t s) {
-  if (p.n_blocks == 0) return;
   const Consts c = make_consts(p);
+  if (p.kernel == NB_KERNEL_CLUSTER) {
+    launch_cluster_pair(p, d, c, o, MODE, s);
+    return;
+  }
+  if (p.n_blocks == 0) return;
   if (p.precision == NB_FP64)
     hipLaunchKernelGGL((k_pair_atom<true, MODE>), dim3(static_cast<unsigned>(p.n_blocks)), dim3(kBlock), 0, s, d, c, o);
   else
@@ -358,9 +332,11 @@ hipError_t launch_forces(const Plan &p, const Dev &d, const nb_system *sys, doub
   Out o = base_out(sys);
   o.force = force;
   o.want_part = (energy || virial) ? 1 : 0;
+  o.want_virial = virial ? 1 : 0;
   launch_pair<kForces>(p, d, o, s);
   if (o.want_part)
-    hipLaunchKernelGGL(k_reduce_sys, dim3(p.B), dim3(kBlock), 0, s, d, energy, virial, kPart);
+    hipLaunchKernelGGL(k_reduce_sys, dim3(p.B), dim3(kBlock), 0, s, d, energy, virial, virial ? kPart : 1,
+                       p.kernel == NB_KERNEL_CLUSTER ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -370,7 +346,8 @@ hipError_t launch_energy(const Plan &p, const Dev &d, const nb_system *sys, doub
   o.atom_energy = atom_energy;
   o.want_part = 1;
   launch_pair<kEnergy>(p, d, o, s);
-  hipLaunchKernelGGL(k_reduce_sys, dim3(p.B), dim3(kBlock), 0, s, d, energy, static_cast<double *>(nullptr), 1);
+  hipLaunchKernelGGL(k_reduce_sys, dim3(p.B), dim3(kBlock), 0, s, d, energy, static_cast<double *>(nullptr), 1,
+                     p.kernel == NB_KERNEL_CLUSTER ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -383,7 +360,8 @@ hipError_t launch_backward(const Plan &p, const Dev &d, const nb_system *sys, co
   o.grad_energy = grad_energy;
   launch_pair<kAdjoint>(p, d, o, s);
   if (grad_sigma || grad_eps)
-    hipLaunchKernelGGL(k_reduce_types, dim3(1), dim3(kBlock), 0, s, d, sys->lj_eps, grad_sigma, grad_eps);
+    hipLaunchKernelGGL(k_reduce_types, dim3(1), dim3(kBlock), 0, s, d, sys->lj_eps, grad_sigma, grad_eps,
+                       p.kernel == NB_KERNEL_CLUSTER ? 1 : 0);
   return hipGetLastError();
 }
 

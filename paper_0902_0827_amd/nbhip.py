@@ -33,6 +33,7 @@ NB_STATUS_NONFINITE_POS = 0x1
 NB_STATUS_BAD_TYPE = 0x2
 NB_STATUS_BAD_EXCLUSION = 0x4
 NB_STATUS_FAR_EXCLUSION = 0x8
+NB_STATUS_NOT_BUILT = 0x10
 NB_MAX_TYPES = 64
 
 EXPORTED = ("nb_workspace_bytes", "nb_build_cells", "nb_nonbonded_forces", "nb_nonbonded_energy",
@@ -84,6 +85,12 @@ class nb_layout(ctypes.Structure):
         ("off_sorted_pos64", ctypes.c_int64),
         ("off_excl_mask", ctypes.c_int64),
         ("off_status", ctypes.c_int64),
+        ("n_columns", ctypes.c_int64),
+        ("n_clusters_max", ctypes.c_int64),
+        ("off_col_clu_start", ctypes.c_int64),
+        ("off_clusters", ctypes.c_int64),
+        ("off_clu_ctr", ctypes.c_int64),
+        ("off_clu_half", ctypes.c_int64),
     ]
 
 

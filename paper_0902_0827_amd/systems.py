@@ -39,7 +39,9 @@ MASS_WATER = 15.999 + 2 * 1.008  # g/mol
 MASS_BEAD = 14.027  # g/mol (CH2-like united atom; the chain recipe names no mass)
 AVOGADRO = 6.02214076e23
 
-# Type table shared by every system: 0 = water O, 1 = water H, 2..9 = solute.
+# Type table shared by every system: 0 = water O, 1 = water H, 2..9 = solute.  The
+# solute types are one fixed draw (a force field), so that any systems can be batched.
+FORCE_FIELD_SEED = 20090205
 TYPE_O = 0
 TYPE_H = 1
 N_SOLUTE_TYPES = 8
@@ -115,7 +117,9 @@ def _water_sites(rng: np.random.Generator, oxygens: np.ndarray) -> np.ndarray:
     return atoms.reshape(-1, 3)
 
 
-def _type_table(rng: np.random.Generator):
+def _type_table(rng: Optional[np.random.Generator] = None):
+    if rng is None:
+        rng = np.random.default_rng(FORCE_FIELD_SEED)
     sig = np.empty(N_TYPES)
     eps = np.empty(N_TYPES)
     sig[TYPE_O], eps[TYPE_O] = SIGMA_O, EPS_O
@@ -261,7 +265,7 @@ def water_lattice(n_side: int, spacing: float, seed: int, cutoff: float, beta: f
                   n_waters: Optional[int] = None, name: str = "water") -> System:
     """Waters with O on an n_side^3 lattice ((i+1/2)*spacing); optionally a random subset."""
     rng = np.random.default_rng(seed)
-    sig, eps = _type_table(rng)
+    sig, eps = _type_table()
     L = n_side * spacing
     box = np.array([L, L, L])
     g = (np.arange(n_side) + 0.5) * spacing
@@ -277,8 +281,7 @@ def solvated_chain(L: float, n_beads: int, n_waters: int, seed: int, cutoff: flo
                    name: str = "chain+water") -> System:
     """A self-avoiding bead chain in a cubic box, then waters on free lattice sites."""
     rng = np.random.default_rng(seed)
-    trng = rng if type_seed is None else np.random.default_rng(type_seed)
-    sig, eps = _type_table(trng)
+    sig, eps = _type_table(None if type_seed is None else np.random.default_rng(type_seed))
     box = np.array([L, L, L], float)
     beads = _chain(rng, n_beads, box)
     q = rng.uniform(-0.5, 0.5, n_beads)
@@ -332,8 +335,7 @@ def config4(seed: int = 4, n_systems: int = 64) -> List[System]:
         mass = n_w * MASS_WATER + n_s * MASS_BEAD
         L = (mass / AVOGADRO / rho) ** (1 / 3) * 1e8
         sub_seed = int(rng.integers(0, 2**31 - 1))
-        out.append(solvated_chain(L, n_s, n_w, sub_seed, 9.0, 0.34, type_seed=seed,
-                                  name=f"replica{b}"))
+        out.append(solvated_chain(L, n_s, n_w, sub_seed, 9.0, 0.34, name=f"replica{b}"))
     return out
 
 
@@ -351,7 +353,12 @@ def water_box(n_waters: int, L: float, seed: int, cutoff: float = 9.0, beta: flo
 
 
 def concat_systems(systems: List[System]):
-    """Pack systems back to back (batch layout): returns a dict of concatenated arrays."""
+    """Pack systems back to back (batch layout): returns a dict of concatenated arrays.
+
+    The Lennard-Jones type table is shared by a batch, so every system must carry the same one."""
+    for s in systems[1:]:
+        if not (np.array_equal(s.sigma, systems[0].sigma) and np.array_equal(s.eps, systems[0].eps)):
+            raise ValueError("systems in a batch must share one Lennard-Jones type table")
     offs = np.zeros(len(systems) + 1, np.int64)
     offs[1:] = np.cumsum([s.n for s in systems])
     excl_off = [np.zeros(1, np.int64)]

@@ -89,7 +89,13 @@ def workspace_arrays(out):
     cs = ws[lay.off_cell_start: lay.off_cell_start + 4 * (lay.n_cells + 1)].view(np.int32)
     fx = ws[lay.off_sorted_fixed: lay.off_sorted_fixed + 16 * n].view(np.uint32).reshape(n, 4)
     mk = ws[lay.off_excl_mask: lay.off_excl_mask + 16 * n].view(np.uint32).reshape(n, 4)
-    return dict(cell_start=cs, sorted_fixed=fx, excl_mask=mk)
+    ncol, ncm = lay.n_columns, lay.n_clusters_max
+    ccs = ws[lay.off_col_clu_start: lay.off_col_clu_start + 4 * (ncol + 1)].view(np.int32)
+    clu = ws[lay.off_clusters: lay.off_clusters + 16 * ncm].view(np.int32).reshape(ncm, 4)
+    ctr = ws[lay.off_clu_ctr: lay.off_clu_ctr + 16 * ncm].view(np.uint32).reshape(ncm, 4)
+    half = ws[lay.off_clu_half: lay.off_clu_half + 16 * ncm].view(np.uint32).reshape(ncm, 4)
+    return dict(cell_start=cs, sorted_fixed=fx, excl_mask=mk, col_clu_start=ccs, clusters=clu,
+                clu_ctr=ctr, clu_half=half, dims=tuple(lay.dims))
 
 
 def oracle_binning(systems, precision, divs):

@@ -18,6 +18,7 @@ pytestmark = [pytest.mark.gpu,
 
 FP64_TOL = 1e-12
 MIXED_TOL = 1e-5
+KERNELS = [H.NB_KERNEL_ATOM, H.NB_KERNEL_CLUSTER]
 
 
 def _print_case(name, **kw):
@@ -45,12 +46,13 @@ def test_binning_is_the_stable_counting_sort(divs, precision, chain):
     assert out["status"] == 0
 
 
-def test_binning_at_full_size_config2():
+@pytest.mark.parametrize("divs", [(2, 2), (2, 8)])
+def test_binning_at_full_size_config2(divs):
     s = U.cached_config(2)
-    _print_case("binning-cfg2")
-    out = U.gpu_eval(s, H.NB_MIXED)
+    _print_case("binning-cfg2", divs=divs)
+    out = U.gpu_eval(s, H.NB_MIXED, cell_div_xy=divs[0], cell_div_z=divs[1])
     ws = U.workspace_arrays(out)
-    ref = U.oracle_binning([s], H.NB_MIXED, (2, 2, 2))
+    ref = U.oracle_binning([s], H.NB_MIXED, (divs[0], divs[0], divs[1]))
     np.testing.assert_array_equal(ws["cell_start"], ref["cell_start"])
     np.testing.assert_array_equal(ws["sorted_fixed"][:, 3], ref["order"])
 
@@ -70,14 +72,34 @@ def test_exclusion_windows_are_exact(chain):
     assert not far.any()
 
 
+def test_clusters_partition_every_column(chain):
+    systems = [chain, U.cached_config(1)]
+    out = U.gpu_eval(systems, H.NB_MIXED, kernel=H.NB_KERNEL_CLUSTER)
+    ws = U.workspace_arrays(out)
+    ccs = ws["col_clu_start"]
+    n_clu = int(ccs[-1])
+    clu = ws["clusters"][:n_clu]
+    fixed = ws["sorted_fixed"]
+    covered = np.zeros(out["batch"].n_atoms, np.int64)
+    for k, (a0, cnt, col, sysid) in enumerate(clu):
+        assert 1 <= cnt <= 8 and ccs[col] <= k < ccs[col + 1]
+        covered[a0:a0 + cnt] += 1
+        for ax in range(3):  # every member lies inside the box (minimum image)
+            d = (fixed[a0:a0 + cnt, ax].astype(np.int64) - int(ws["clu_ctr"][k, ax])) % 2**32
+            d = np.where(d >= 2**31, 2**32 - d, d)
+            assert np.all(d <= int(ws["clu_half"][k, ax]))
+    assert np.all(covered == 1)
+
+
 # --- forces, energies, virial --------------------------------------------------------------
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("which", ["cfg1", "chain", "cfg2"])
 @pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
-def test_forces_energy_virial_match_oracle(which, precision, chain):
+def test_forces_energy_virial_match_oracle(which, precision, kernel, chain):
     s = {"cfg1": lambda: U.cached_config(1), "chain": lambda: chain, "cfg2": lambda: U.cached_config(2)}[which]()
-    _print_case("forces", which=which, precision=precision, n=s.n)
-    out = U.gpu_eval(s, precision, energy_call=True)
+    _print_case("forces", which=which, precision=precision, kernel=kernel, n=s.n)
+    out = U.gpu_eval(s, precision, kernel=kernel, energy_call=True)
     ref = U.oracle_for(s, precision)
     tol = FP64_TOL if precision == H.NB_FP64 else MIXED_TOL
     err = U.rel_rms(out["force"], ref["force"])
@@ -90,20 +112,25 @@ def test_forces_energy_virial_match_oracle(which, precision, chain):
     assert out["status"] == 0
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
-def test_run_twice_is_bitwise_identical(precision, chain):
-    a = U.gpu_eval(chain, precision)
-    b = U.gpu_eval(chain, precision)
+def test_run_twice_is_bitwise_identical(precision, kernel, chain):
+    a = U.gpu_eval(chain, precision, kernel=kernel)
+    b = U.gpu_eval(chain, precision, kernel=kernel)
     np.testing.assert_array_equal(a["force"], b["force"])
     np.testing.assert_array_equal(a["energy"], b["energy"])
     np.testing.assert_array_equal(a["virial"], b["virial"])
 
 
-def test_cell_grid_choice_does_not_change_fp64_result(chain):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_cell_grid_choice_does_not_change_the_result(kernel, chain):
     ref = U.oracle_for(chain, H.NB_FP64)
-    for divs in [(1, 1), (2, 2), (2, 8), (3, 3), (4, 16)]:
-        out = U.gpu_eval(chain, H.NB_FP64, cell_div_xy=divs[0], cell_div_z=divs[1])
+    ref32 = U.oracle_for(chain, H.NB_MIXED)
+    for divs in [(1, 1), (2, 2), (2, 8), (3, 3), (4, 16), (1, 12)]:
+        out = U.gpu_eval(chain, H.NB_FP64, cell_div_xy=divs[0], cell_div_z=divs[1], kernel=kernel)
         assert U.rel_rms(out["force"], ref["force"]) <= FP64_TOL, divs
+        out = U.gpu_eval(chain, H.NB_MIXED, cell_div_xy=divs[0], cell_div_z=divs[1], kernel=kernel)
+        assert U.rel_rms(out["force"], ref32["force"]) <= MIXED_TOL, divs
 
 
 def test_relabelled_atoms_give_permuted_forces(chain):
@@ -123,20 +150,23 @@ def test_relabelled_atoms_give_permuted_forces(chain):
     a = U.gpu_eval(chain, H.NB_FP64)
     b = U.gpu_eval(perm, H.NB_FP64)
     np.testing.assert_allclose(b["force"], a["force"][p], rtol=0, atol=1e-12 * np.abs(a["force"]).max())
+    c = U.gpu_eval(perm, H.NB_FP64, kernel=H.NB_KERNEL_ATOM)
+    np.testing.assert_allclose(c["force"], a["force"][p], rtol=0, atol=1e-12 * np.abs(a["force"]).max())
     # relabelling moves some exclusions beyond the 64-atom window: the far path is exercised
     assert b["status"] == H.NB_STATUS_FAR_EXCLUSION
 
 
 # --- batches -------------------------------------------------------------------------------
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
-def test_batch_equals_each_system_alone(precision, chain):
+def test_batch_equals_each_system_alone(precision, kernel, chain):
     systems = [S.water_box(300, 20.0, seed=1), chain, S.water_box(1200, 26.0, seed=2),
                S.solvated_chain(30.0, 80, 800, seed=4, cutoff=9.0, beta=0.34)]
-    out = U.gpu_eval(systems, precision)
+    out = U.gpu_eval(systems, precision, kernel=kernel)
     off = np.concatenate([[0], np.cumsum([s.n for s in systems])])
     for k, s in enumerate(systems):
-        alone = U.gpu_eval(s, precision)
+        alone = U.gpu_eval(s, precision, kernel=kernel)
         np.testing.assert_array_equal(out["force"][off[k]:off[k + 1]], alone["force"])
         assert out["energy"][k] == alone["energy"][0]
         np.testing.assert_array_equal(out["virial"][k], alone["virial"][0])
@@ -144,7 +174,8 @@ def test_batch_equals_each_system_alone(precision, chain):
 
 # --- edge cases ----------------------------------------------------------------------------
 
-def test_tiny_and_empty_systems():
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_tiny_and_empty_systems(kernel):
     two = S.System(name="two", pos=np.array([[1.0, 1.0, 1.0], [4.0, 1.0, 1.5]]), charge=np.array([0.5, -0.5]),
                    type=np.array([0, 0], np.int32), sigma=np.array([3.0]), eps=np.array([0.4]),
                    excl_offset=np.zeros(3, np.int32), excl_index=np.zeros(0, np.int32),
@@ -153,21 +184,22 @@ def test_tiny_and_empty_systems():
                      sigma=np.array([3.0]), eps=np.array([0.4]), excl_offset=np.zeros(1, np.int32),
                      excl_index=np.zeros(0, np.int32), box=np.array([20.0, 20.0, 20.0]), cutoff=9.0,
                      beta=0.3, seed=0)
-    out = U.gpu_eval([two, empty, two], H.NB_FP64)
+    out = U.gpu_eval([two, empty, two], H.NB_FP64, kernel=kernel)
     ref = U.oracle_for(two, H.NB_FP64)
     np.testing.assert_allclose(out["force"][:2], ref["force"], rtol=1e-13, atol=1e-13)
     np.testing.assert_allclose(out["force"][2:], ref["force"], rtol=1e-13, atol=1e-13)
     assert out["energy"][1] == 0.0 and not out["virial"][1].any()
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
-def test_positions_outside_the_box_are_wrapped(precision, chain):
+def test_positions_outside_the_box_are_wrapped(precision, kernel, chain):
     moved = S.System(**{**chain.__dict__})
     shift = np.zeros_like(chain.pos)
     shift[::2] = chain.box * np.array([2, -3, 1])
     shift[1::5] = -chain.box * np.array([1, 1, 4])
     moved.pos = chain.pos + shift
-    out = U.gpu_eval(moved, precision)
+    out = U.gpu_eval(moved, precision, kernel=kernel)
     ref = U.oracle_for(moved, precision)
     assert U.rel_rms(out["force"], ref["force"]) <= (1e-11 if precision == H.NB_FP64 else MIXED_TOL)
 
@@ -191,13 +223,14 @@ def test_device_status_bits():
 
 # --- adjoint -------------------------------------------------------------------------------
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
 @pytest.mark.parametrize("which", ["chain", "cfg3"])
-def test_backward_matches_oracle_gradients(precision, which, chain):
+def test_backward_matches_oracle_gradients(precision, which, kernel, chain):
     s = chain if which == "chain" else U.cached_config(3)
-    _print_case("backward", which=which, precision=precision)
+    _print_case("backward", which=which, precision=precision, kernel=kernel)
     g = 1.7
-    out = U.gpu_eval(s, precision, backward=True, grad_energy=[g])
+    out = U.gpu_eval(s, precision, kernel=kernel, backward=True, grad_energy=[g])
     ref = U.oracle_for(s, precision)
     tol = 1e-11 if precision == H.NB_FP64 else MIXED_TOL
     assert U.rel_rms(out["grad_pos"], -g * ref["force"]) <= tol
@@ -262,12 +295,39 @@ def test_config5_mixed_against_sampled_oracle_and_fp64_gpu():
     s = U.cached_config(5)
     _print_case("cfg5", n=s.n)
     mixed = U.gpu_eval(s, H.NB_MIXED)
-    fp64 = U.gpu_eval(s, H.NB_FP64)
-    err = U.rel_rms(mixed["force"], fp64["force"])
-    print(f"  mixed vs fp64 gpu rel_rms={err:.3e} max_rel_atom={U.max_rel_atom(mixed['force'], fp64['force']):.3e}")
+    mixed_atom = U.gpu_eval(s, H.NB_MIXED, kernel=H.NB_KERNEL_ATOM)
+    assert U.rel_rms(mixed_atom["force"], mixed["force"]) <= 1e-6
+    # Kernel error only: the FP64 path on the same FP32-rounded coordinates and charges
+    # (FP32 rounding of the inputs at L = 215 A is itself ~1e-5 relative in the forces).
+    fp64_same_in = U.gpu_eval(s.rounded(np.float32), H.NB_FP64)
+    err = U.rel_rms(mixed["force"], fp64_same_in["force"])
+    print(f"  mixed vs fp64 gpu rel_rms={err:.3e} "
+          f"max_rel_atom={U.max_rel_atom(mixed['force'], fp64_same_in['force']):.3e}")
     assert err <= MIXED_TOL
     rows = np.random.default_rng(5).choice(s.n, 96, replace=False)
     ref32 = U.oracle_for(s, H.NB_MIXED, rows=rows)
-    ref64 = U.oracle_for(s, H.NB_FP64, rows=rows)
     assert U.rel_rms(mixed["force"][rows], ref32["force"]) <= MIXED_TOL
+    assert U.rel_rms(fp64_same_in["force"][rows], ref32["force"]) <= FP64_TOL
+    fp64 = U.gpu_eval(s, H.NB_FP64)
+    ref64 = U.oracle_for(s, H.NB_FP64, rows=rows)
     assert U.rel_rms(fp64["force"][rows], ref64["force"]) <= FP64_TOL
+
+
+def test_pair_kernels_refuse_a_workspace_built_for_another_kernel(chain):
+    b = H.device_batch([chain], dtype=torch.float32)
+    p_atom = H.make_params(chain.cutoff, chain.beta, H.NB_MIXED, kernel=H.NB_KERNEL_ATOM)
+    p_clu = H.make_params(chain.cutoff, chain.beta, H.NB_MIXED, kernel=H.NB_KERNEL_CLUSTER)
+    ws = torch.zeros(max(H.workspace_bytes(b, p_atom), H.workspace_bytes(b, p_clu)), dtype=torch.uint8,
+                     device="cuda")
+    force = torch.full((chain.n, 3), 7.0, dtype=torch.float64, device="cuda")
+    energy = torch.full((1,), 7.0, dtype=torch.float64, device="cuda")
+    # never built: nothing is written and the status says so
+    H.nonbonded_forces(b, p_clu, ws, force, energy)
+    assert H.read_status(ws) & H.NB_STATUS_NOT_BUILT
+    assert float(force.abs().min()) == 7.0 and float(energy[0]) == 7.0
+    H.build_cells(b, p_atom, ws)
+    H.nonbonded_forces(b, p_clu, ws, force, energy)
+    assert H.read_status(ws) & H.NB_STATUS_NOT_BUILT
+    H.build_cells(b, p_clu, ws)
+    H.nonbonded_forces(b, p_clu, ws, force, energy)
+    assert H.read_status(ws) == 0
