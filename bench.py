@@ -74,7 +74,13 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--paths", choices=["both", "mixed"], default="both",
+                    help="time the FP64 GPU path beside the mixed one (default) or only the mixed one")
+    ap.add_argument("--kernel", choices=["auto", "atom", "cluster", "cluster_rq"], default="auto",
+                    help="pair-kernel variant of the mixed path (the FP64 path uses the same or its nearest)")
+    ap.add_argument("--cell-div", type=str, default="0,0", help="cells per cutoff 'xy,z' (0 = default)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for hardware-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the systems here are "
@@ -87,14 +93,29 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = 256 << 20  # bytes read and bytes written by each copy
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}))
+        return
     H.load_library()
     s = S.config2()
     log(f"[bench] workload {s.name}: N={s.n} L={s.box[0]} rc={s.cutoff} beta={s.beta}")
 
     results = {}
-    for prec_name, prec, dt in (("mixed", H.NB_MIXED, torch.float32), ("fp64", H.NB_FP64, torch.float64)):
+    paths = [("mixed", H.NB_MIXED, torch.float32)]
+    if args.paths == "both":
+        paths.append(("fp64", H.NB_FP64, torch.float64))
+    for prec_name, prec, dt in paths:
         b = H.device_batch([s], dtype=dt)
-        p = H.make_params(s.cutoff, s.beta, prec)
+        kern = {"auto": H.NB_KERNEL_AUTO, "atom": H.NB_KERNEL_ATOM, "cluster": H.NB_KERNEL_CLUSTER,
+                "cluster_rq": H.NB_KERNEL_CLUSTER_RQ}[args.kernel]
+        dxy, dz = (int(v) for v in args.cell_div.split(","))
+        p = H.make_params(s.cutoff, s.beta, prec, kernel=kern, cell_div_xy=dxy, cell_div_z=dz)
         ws = H.alloc_workspace(b, p)
         force = torch.empty((s.n, 3), dtype=torch.float64, device="cuda")
         energy = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -122,7 +143,7 @@ def main():
     t_cpu = []
     reps = 0
     t_start = time.perf_counter()
-    for prec_name, sys_in in (("mixed", s.rounded(np.float32)), ("fp64", s)):
+    for prec_name, sys_in in (("mixed", s.rounded(np.float32)), ("fp64", s))[:len(paths)]:
         t0 = time.perf_counter()
         ref[prec_name] = O.evaluate_system(sys_in, ke=H.COULOMB_K)
         t_cpu.append(time.perf_counter() - t0)
@@ -141,9 +162,9 @@ def main():
 
     pairs = ref["mixed"]["pairs"]
     m = results["mixed"]
-    f64 = results["fp64"]
+    f64 = results.get("fp64")
     err_m = rel_errors(m["force"], ref["mixed"]["force"])
-    err_d = rel_errors(f64["force"], ref["fp64"]["force"])
+    err_d = rel_errors(f64["force"], ref["fp64"]["force"]) if f64 else (None, None)
     achieved = pairs * FLOPS_PER_PAIR / m["pair_sec"] / 1e12
     out = {
         "metric": METRIC,
@@ -164,14 +185,15 @@ def main():
         "accuracy": {"rel_rms_force": err_m[0], "max_rel_force": err_m[1],
                      "energy_rel": abs(m["energy"] - ref["mixed"]["energy_total"]) / abs(ref["mixed"]["energy_total"])},
         "pairs_per_s": pairs / m["sec"],
-        "fp64_path": {"value": 1.0 / f64["sec"], "unit": "evals/s", "ms_per_step": f64["sec"] * 1e3,
-                      "forces_call_us": f64["pair_sec"] * 1e6, "rel_rms_force": err_d[0], "max_rel_force": err_d[1]},
+        "fp64_path": None if not f64 else {
+            "value": 1.0 / f64["sec"], "unit": "evals/s", "ms_per_step": f64["sec"] * 1e3,
+            "forces_call_us": f64["pair_sec"] * 1e6, "rel_rms_force": err_d[0], "max_rel_force": err_d[1]},
         "roofline": {"bound": "alu", "kernel": "pair kernel (nb_nonbonded_forces)",
                      "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
                      "launch_us": m["pair_sec"] * 1e6, "flops_per_pair": FLOPS_PER_PAIR},
         "cpu_baseline": cpu,
-        "status_bits": [m["status"], f64["status"]],
+        "status_bits": [r["status"] for r in results.values()],
     }
     print(json.dumps(out), flush=True)
 

@@ -92,7 +92,9 @@ typedef struct {
 /* Kernel variants for nb_params.kernel. */
 #define NB_KERNEL_AUTO 0    /* library default for the precision (or the tuned choice passed in) */
 #define NB_KERNEL_ATOM 1    /* one lane per i atom, full neighbour shell, j read through the cache */
-#define NB_KERNEL_CLUSTER 2 /* 8 x 8 atom-cluster tiles in LDS with in-wave compaction of pairs */
+#define NB_KERNEL_CLUSTER 2 /* 8-atom clusters x box-filtered j atoms staged in LDS, 8 x 8 pairs per step */
+#define NB_KERNEL_CLUSTER_RQ 3 /* as NB_KERNEL_CLUSTER, with in-cutoff pairs compacted per i atom before the
+                                  pair terms (single precision; the FP64 path runs NB_KERNEL_CLUSTER) */
 
 typedef struct {
   double cutoff;      /* R (A): 0 < R < min(L)/2 for every system */

@@ -46,7 +46,7 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   if (prm->precision != NB_FP64 && prm->precision != NB_MIXED) return fail(NB_ERR_ARG, "unknown precision");
   if (prm->cell_div_xy < 0 || prm->cell_div_xy > 4) return fail(NB_ERR_ARG, "cell_div_xy must be in [0, 4]");
   if (prm->cell_div_z < 0 || prm->cell_div_z > 16) return fail(NB_ERR_ARG, "cell_div_z must be in [0, 16]");
-  if (prm->kernel < NB_KERNEL_AUTO || prm->kernel > NB_KERNEL_CLUSTER) return fail(NB_ERR_ARG, "unknown kernel variant");
+  if (prm->kernel < NB_KERNEL_AUTO || prm->kernel > NB_KERNEL_CLUSTER_RQ) return fail(NB_ERR_ARG, "unknown kernel variant");
 
   const int B = sys->n_systems;
   if (sys->atom_offset[0] != 0) return fail(NB_ERR_ARG, "atom_offset[0] must be 0");
@@ -64,9 +64,10 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   p.T = sys->n_types;
   p.precision = prm->precision;
   p.kernel = prm->kernel == NB_KERNEL_AUTO ? NB_KERNEL_CLUSTER : prm->kernel;
+  if (p.kernel == NB_KERNEL_CLUSTER_RQ && p.precision == NB_FP64) p.kernel = NB_KERNEL_CLUSTER;
   p.div_xy = prm->cell_div_xy ? prm->cell_div_xy : 2;
   // The cluster kernel wants thin z-cells, so that a column's atoms come out nearly z-sorted.
-  p.div_z = prm->cell_div_z ? prm->cell_div_z : (p.kernel == NB_KERNEL_CLUSTER ? 8 : p.div_xy);
+  p.div_z = prm->cell_div_z ? prm->cell_div_z : (p.kernel == NB_KERNEL_ATOM ? p.div_xy : 8);
   p.cutoff = prm->cutoff;
   p.beta = prm->ewald_beta;
   p.ke = prm->coulomb_k;
@@ -142,6 +143,7 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   l.clusters = take(16 * static_cast<size_t>(clusters));
   l.clu_ctr = take(16 * static_cast<size_t>(clusters));
   l.clu_half = take(16 * static_cast<size_t>(clusters));
+  l.scan_tmp = take(4 * (2 * static_cast<size_t>(kMaxFusedGrid) + 2));
   l.total = o;
   *plan = std::move(p);
   return NB_OK;
@@ -172,6 +174,7 @@ Dev dev_view(const Plan &p, void *ws) {
   d.excl_far = reinterpret_cast<uint32_t *>(base + l.excl_far);
   d.partials = reinterpret_cast<double *>(base + l.partials);
   d.adj_partials = reinterpret_cast<double *>(base + l.adj_partials);
+  d.n_slots = std::max<int64_t>(std::max<int64_t>(p.n_blocks, p.n_clusters_max), 1);
   d.N = p.N;
   d.n_blocks = p.n_blocks;
   d.col_nclu = reinterpret_cast<int32_t *>(base + l.col_nclu);
@@ -181,6 +184,7 @@ Dev dev_view(const Plan &p, void *ws) {
   d.clu_half = reinterpret_cast<uint4 *>(base + l.clu_half);
   d.n_columns = p.n_columns;
   d.n_clusters_max = p.n_clusters_max;
+  d.scan_tmp = reinterpret_cast<int32_t *>(base + l.scan_tmp);
   return d;
 }
 

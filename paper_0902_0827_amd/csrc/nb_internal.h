@@ -18,13 +18,19 @@ constexpr int kWaves = kBlock / 64;   // wave64
 constexpr int kPart = 10;             // per-block partial sums: energy + 9 virial entries
 constexpr int kWindow = 64;           // exclusion bitmap reach in original index (section 3)
 constexpr int kDescChunk = 8;         // system descriptors carried by one initialisation launch
+constexpr int kMaxFusedGrid = 1024;   // workgroups of the single-launch cell-list build
 constexpr uint32_t kBuiltMagic = 0x4E424831u;  // status[1]: written by nb_build_cells
 
+// Kernel variants that read the cluster arrays built by nb_build_cells.
+__host__ __device__ __forceinline__ bool uses_clusters(int kernel) {
+  return kernel == NB_KERNEL_CLUSTER || kernel == NB_KERNEL_CLUSTER_RQ;
+}
+
 // Workspace header words: status[0] = NB_STATUS_* bits, status[1] = kBuiltMagic,
-// status[2] = atom count, status[3] = kernel variant the cluster data was built for.
-__device__ __forceinline__ bool built_for(const uint32_t *status, int64_t n_atoms, int kernel) {
+// status[2] = atom count, status[3] = 1 if the cluster arrays were built.
+__device__ __forceinline__ bool built_for(const uint32_t *status, int64_t n_atoms, bool need_clusters) {
   return status[1] == kBuiltMagic && status[2] == static_cast<uint32_t>(n_atoms) &&
-         (kernel != NB_KERNEL_CLUSTER || status[3] == static_cast<uint32_t>(NB_KERNEL_CLUSTER));
+         (!need_clusters || status[3] == 1u);
 }
 
 // Per-system descriptor, resident in the workspace.  Sorted atoms of system b are
@@ -51,7 +57,7 @@ struct alignas(16) TypePair32 { float c6, c12, inv_sig, pad; };
 struct Layout {
   size_t status, desc, tab64, tab32, cell_count, cell_start, atom_cell, atom_slot, atom_fix, tmp;
   size_t s_fix, s_pos64, s_q32, s_type, excl_mask, excl_far, partials, adj_partials;
-  size_t col_nclu, col_clu_start, clusters, clu_ctr, clu_half;
+  size_t col_nclu, col_clu_start, clusters, clu_ctr, clu_half, scan_tmp;
   size_t total;
 };
 
@@ -87,8 +93,9 @@ struct Dev {
   int32_t *s_type;   // sorted: type (clamped into range)
   uint4 *excl_mask;  // original order: 128-bit exclusion window
   uint32_t *excl_far;// original order: nonzero if the atom has an exclusion beyond the window
-  double *partials;      // [max(n_blocks, n_clusters_max)][kPart]
-  double *adj_partials;  // [max(n_blocks, n_clusters_max)][2 T]
+  double *partials;      // [kPart][n_slots]: per-block (or per-cluster) energy and virial sums
+  double *adj_partials;  // [2 T][n_slots]: per-block (or per-cluster) sigma / eps sums by type
+  int64_t n_slots;       // max(n_blocks, n_clusters_max)
   int64_t N;
   int64_t n_blocks;
   // Cluster kernel: 8 consecutive sorted atoms of one (x, y) column form a cluster.
@@ -99,6 +106,7 @@ struct Dev {
   uint4 *clu_half;         // [n_clusters_max] bounding-box half extent (fixed-point units)
   int64_t n_columns;
   int64_t n_clusters_max;
+  int32_t *scan_tmp;       // [2 kMaxFusedGrid + 2] block sums of the single-launch build
 };
 
 // Per-call constants and outputs of the pair kernels.

@@ -23,7 +23,7 @@ template <bool F64, int MODE>
 __global__ void __launch_bounds__(kBlock) k_pair_atom(Dev d, Consts c, Out o) {
   __shared__ double red[kWaves][2 * NB_MAX_TYPES > kPart ? 2 * NB_MAX_TYPES : kPart];
   const int blk = blockIdx.x;
-  if (!built_for(d.status, d.N, NB_KERNEL_ATOM)) {
+  if (!built_for(d.status, d.N, false)) {
     if (blk == 0 && threadIdx.x == 0) atomicOr(d.status, NB_STATUS_NOT_BUILT);
     return;
   }
@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_atom(Dev d, Consts c, Out o) {
       double s = 0;
       if (static_cast<int>(threadIdx.x) < nv)
         for (int w = 0; w < kWaves; ++w) s += red[w][threadIdx.x];
-      d.partials[static_cast<int64_t>(blk) * kPart + threadIdx.x] = s;
+      d.partials[static_cast<int64_t>(threadIdx.x) * d.n_slots + blk] = s;
     }
   } else {
     // Per-type sums of the sigma and eps partials: each wave reduces over the
@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_atom(Dev d, Consts c, Out o) {
       const int col = t < T ? t : NB_MAX_TYPES + (t - T);
       double s = 0;
       for (int w = 0; w < kWaves; ++w) s += red[w][col];
-      d.adj_partials[static_cast<int64_t>(blk) * 2 * T + t] = s;
+      d.adj_partials[static_cast<int64_t>(t) * d.n_slots + blk] = s;
     }
   }
 }
@@ -252,40 +252,62 @@ __device__ __forceinline__ void partial_range(const Dev &d, int cluster, const S
   }
 }
 
-// Energy and virial of system b = sum of its partials, in a fixed order.
-__global__ void __launch_bounds__(kBlock) k_reduce_sys(Dev d, double *energy, double *virial, int nv, int cluster) {
-  __shared__ double lds[kWaves];
-  if (!built_for(d.status, d.N, cluster ? NB_KERNEL_CLUSTER : NB_KERNEL_ATOM)) return;
+// Energy and virial of system b = sum of its partials, in a fixed order: each
+// thread sums a strided subset of slots (all NV components, independent loads in
+// flight), then waves and the block are combined in a fixed order.
+constexpr int kReduceBlock = 1024;
+
+template <int NV>
+__global__ void __launch_bounds__(kReduceBlock) k_reduce_sys(Dev d, double *energy, double *virial, int cluster) {
+  __shared__ double lds[kReduceBlock / 64][NV];
+  if (!built_for(d.status, d.N, cluster != 0)) return;
   const int b = blockIdx.x;
   const SysDesc &sd = d.desc[b];
   int lo, hi;
   partial_range(d, cluster, sd, &lo, &hi);
-  for (int k = 0; k < nv; ++k) {
-    double s = 0;
-    for (int q = lo + threadIdx.x; q < hi; q += kBlock) s += d.partials[static_cast<int64_t>(q) * kPart + k];
-    s = block_sum(s, lds);
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  for (int q = lo + threadIdx.x; q < hi; q += kReduceBlock) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] += d.partials[static_cast<int64_t>(k) * d.n_slots + q];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double s = wave_sum(acc[k]);
+    if (lane == 0) lds[wave][k] = s;
+  }
+  __syncthreads();
+  if (static_cast<int>(threadIdx.x) < NV) {
+    double s = 0.0;
+    for (int w = 0; w < kReduceBlock / 64; ++w) s += lds[w][threadIdx.x];
     if (threadIdx.x == 0) {
-      if (k == 0 && energy) energy[b] = s;
-      if (k > 0 && virial) virial[9 * b + (k - 1)] = s;
+      if (energy) energy[b] = s;
+    } else if (virial) {
+      virial[9 * b + (threadIdx.x - 1)] = s;
     }
   }
 }
 
-// Per-type parameter gradients: sum the (already g-scaled) partials of every slot.
+// Per-type parameter gradients: sum the (already g-scaled) partials of every slot;
+// one workgroup per (sigma or eps, type) entry, fixed reduction order.
 __global__ void __launch_bounds__(kBlock) k_reduce_types(Dev d, const double *__restrict__ eps,
                                                          double *grad_sigma, double *grad_eps, int cluster) {
-  if (!built_for(d.status, d.N, cluster ? NB_KERNEL_CLUSTER : NB_KERNEL_ATOM)) return;
+  __shared__ double lds[kWaves];
+  if (!built_for(d.status, d.N, cluster != 0)) return;
   const int T = d.T;
+  const int t = blockIdx.x;  // 0 .. 2T-1
   const int64_t n = cluster ? d.col_clu_start[d.n_columns] : d.n_blocks;
-  for (int t = threadIdx.x; t < 2 * T; t += kBlock) {
-    double s = 0;
-    for (int64_t q = 0; q < n; ++q) s += d.adj_partials[q * 2 * T + t];
-    if (t < T) {
-      if (grad_sigma) grad_sigma[t] = s;
-    } else {
-      const int tt = t - T;
-      if (grad_eps) grad_eps[tt] = eps[tt] > 0.0 ? s / eps[tt] : 0.0;
-    }
+  double s = 0;
+  for (int64_t q = threadIdx.x; q < n; q += kBlock) s += d.adj_partials[static_cast<int64_t>(t) * d.n_slots + q];
+  s = block_sum(s, lds);
+  if (threadIdx.x != 0) return;
+  if (t < T) {
+    if (grad_sigma) grad_sigma[t] = s;
+  } else {
+    const int tt = t - T;
+    if (grad_eps) grad_eps[tt] = eps[tt] > 0.0 ? s / eps[tt] : 0.0;
   }
 }
 
@@ -314,7 +336,7 @@ Out base_out(const nb_system *sys) {
 template <int MODE>
 void launch_pair(const Plan &p, const Dev &d, const Out &o, hipStream_t s) {
   const Consts c = make_consts(p);
-  if (p.kernel == NB_KERNEL_CLUSTER) {
+  if (uses_clusters(p.kernel)) {
     launch_cluster_pair(p, d, c, o, MODE, s);
     return;
   }
@@ -334,9 +356,11 @@ hipError_t launch_forces(const Plan &p, const Dev &d, const nb_system *sys, doub
   o.want_part = (energy || virial) ? 1 : 0;
   o.want_virial = virial ? 1 : 0;
   launch_pair<kForces>(p, d, o, s);
-  if (o.want_part)
-    hipLaunchKernelGGL(k_reduce_sys, dim3(p.B), dim3(kBlock), 0, s, d, energy, virial, virial ? kPart : 1,
-                       p.kernel == NB_KERNEL_CLUSTER ? 1 : 0);
+  if (o.want_part) {
+    const int cl = uses_clusters(p.kernel) ? 1 : 0;
+    if (virial) hipLaunchKernelGGL(k_reduce_sys<kPart>, dim3(p.B), dim3(kReduceBlock), 0, s, d, energy, virial, cl);
+    else hipLaunchKernelGGL(k_reduce_sys<1>, dim3(p.B), dim3(kReduceBlock), 0, s, d, energy, virial, cl);
+  }
   return hipGetLastError();
 }
 
@@ -346,8 +370,8 @@ hipError_t launch_energy(const Plan &p, const Dev &d, const nb_system *sys, doub
   o.atom_energy = atom_energy;
   o.want_part = 1;
   launch_pair<kEnergy>(p, d, o, s);
-  hipLaunchKernelGGL(k_reduce_sys, dim3(p.B), dim3(kBlock), 0, s, d, energy, static_cast<double *>(nullptr), 1,
-                     p.kernel == NB_KERNEL_CLUSTER ? 1 : 0);
+  hipLaunchKernelGGL(k_reduce_sys<1>, dim3(p.B), dim3(kReduceBlock), 0, s, d, energy, static_cast<double *>(nullptr),
+                     uses_clusters(p.kernel) ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -360,8 +384,8 @@ hipError_t launch_backward(const Plan &p, const Dev &d, const nb_system *sys, co
   o.grad_energy = grad_energy;
   launch_pair<kAdjoint>(p, d, o, s);
   if (grad_sigma || grad_eps)
-    hipLaunchKernelGGL(k_reduce_types, dim3(1), dim3(kBlock), 0, s, d, sys->lj_eps, grad_sigma, grad_eps,
-                       p.kernel == NB_KERNEL_CLUSTER ? 1 : 0);
+    hipLaunchKernelGGL(k_reduce_types, dim3(2 * p.T), dim3(kBlock), 0, s, d, sys->lj_eps, grad_sigma, grad_eps,
+                       uses_clusters(p.kernel) ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -19,6 +19,8 @@
 //      the end.  Every atom's sums live in one wave: no atomics, deterministic.
 //
 // Full shell (every pair is evaluated from both sides), as in the paper.
+#include <type_traits>
+
 #include "nb_pair_common.h"
 #include "nb_pair_math.h"
 
@@ -29,6 +31,9 @@ namespace {
 constexpr int kRing = 128;    // ring buffer of staged j atoms (power of two)
 constexpr int kTabLds = 16;   // type tables up to 16 x 16 are copied to LDS
 constexpr int kFlush = 32;    // groups between single -> double flushes of the sums
+constexpr int kXcds = 8;      // MI355X: 8 accelerator complex dies, each with its own L2
+constexpr int kMaxRuns = 2 * 9 * 9;  // up to 9 x 9 neighbour columns, <= 2 z-runs each
+constexpr int kRowQ = 32;     // per-row queue of in-cutoff pairs (row-compacted variant)
 
 __device__ __forceinline__ uint32_t uabs_diff(uint32_t a, uint32_t b) {
   const int32_t d = static_cast<int32_t>(a - b);
@@ -53,6 +58,7 @@ struct RingLds<false> {
   uint4 fix[kRing];    // fixed-point x, y, z, original index
   float2 qt[kRing];    // q * sqrt(k_e), type (as int bits)
   TypePair32 tab[kTabLds * kTabLds];
+  int2 runs[kMaxRuns];
 };
 
 template <>
@@ -60,22 +66,35 @@ struct RingLds<true> {
   double4 pos[kRing];  // x, y, z, q
   int2 meta[kRing];    // original index, type
   TypePair64 tab[kTabLds * kTabLds];
+  int2 runs[kMaxRuns];
 };
 
-template <bool F64, int MODE>
+// Row queues of the row-compacted variant: for each of the 8 i atoms, the pairs
+// found inside the cutoff (displacement in fixed-point units, r^2, q'_j, type).
+struct RowQLds {
+  float4 d[8][kRowQ];
+  float2 qt[8][kRowQ];
+};
+struct NoRowQ {};
+
+template <bool F64, int MODE, bool TABLDS, bool ROWQ>
 __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
+  static_assert(!(F64 && ROWQ), "row compaction is built for the single-precision path");
   __shared__ RingLds<F64> L;
-  const int I = blockIdx.x;
-  if (!built_for(d.status, d.N, NB_KERNEL_CLUSTER)) {
-    if (I == 0 && threadIdx.x == 0) atomicOr(d.status, NB_STATUS_NOT_BUILT);
+  __shared__ typename std::conditional<ROWQ, RowQLds, NoRowQ>::type RQ;
+  // Workgroups are dealt to the 8 XCDs round robin; give each XCD a contiguous
+  // range of clusters (neighbouring columns) so that its L2 holds their j atoms.
+  const int per_xcd = static_cast<int>(gridDim.x) / kXcds;
+  const int I = static_cast<int>(blockIdx.x % kXcds) * per_xcd + static_cast<int>(blockIdx.x / kXcds);
+  if (!built_for(d.status, d.N, true)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(d.status, NB_STATUS_NOT_BUILT);
     return;
   }
   const int n_clu = d.col_clu_start[d.n_columns];
   if (I >= n_clu) return;  // the grid is sized by an upper bound on the cluster count
   const int lane = threadIdx.x, ii = lane >> 3, jj = lane & 7;
   const int T = d.T;
-  const bool tab_lds = T <= kTabLds;
-  if (tab_lds) {
+  if constexpr (TABLDS) {
     for (int k = lane; k < T * T; k += 64) {
       if constexpr (F64) L.tab[k] = d.tab64[k];
       else L.tab[k] = d.tab32[k];
@@ -128,6 +147,55 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
 
   uint32_t head = 0, tail = 0;  // wave-uniform ring positions
 
+  // Single-precision pair terms for row ii's atom, added to the lane's sums.  With
+  // v false every contribution is exactly zero (no branch: the lanes stay converged).
+  auto accum32 = [&](float r2f, float dxf, float dyf, float dzf, float qj, int tj, bool v) {
+    if constexpr (!F64) {
+      TypePair32 tp;
+      const int tjv = v ? tj : 0;
+      if constexpr (TABLDS) tp = L.tab[ti * T + tjv];
+      else tp = d.tab32[ti * T + tjv];
+      const float qjv = v ? qj : 0.f;
+      const PairF32 p = pair_f32(v ? r2f : 1.0f, v ? tp.c6 : 0.f, v ? tp.c12 : 0.f, qi32 * qjv, c.betaf,
+                                 c.two_beta_sqrtpif, c.mb2l2e);
+      sen += p.u_lj + p.u_c;
+      if constexpr (MODE != kEnergy) {
+        const float ex = v ? dxf : 0.f, ey = v ? dyf : 0.f, ez = v ? dzf : 0.f;
+        const float gx = p.f * ex, gy = p.f * ey, gz = p.f * ez;
+        sfx += gx;
+        sfy += gy;
+        sfz += gz;
+        if constexpr (MODE == kForces) {
+          if (o.want_virial) {
+            swxx = fmaf(gx, ex, swxx); swxy = fmaf(gx, ey, swxy); swxz = fmaf(gx, ez, swxz);
+            swyy = fmaf(gy, ey, swyy); swyz = fmaf(gy, ez, swyz); swzz = fmaf(gz, ez, swzz);
+          }
+        }
+      }
+      if constexpr (MODE == kAdjoint) {
+        sphi = fmaf(qjv, p.erfc_over_r, sphi);
+        sasig = fmaf(p.dudsig_lj, tp.inv_sig, sasig);
+        sbeps += p.u_lj;
+      }
+    }
+  };
+
+  // Row queues (row-compacted variant): per-lane copies of row ii's head and count.
+  int rstart = 0, rcount = 0;
+  auto round = [&]() {  // one pair per lane from its row's queue
+    if constexpr (ROWQ) {
+      const int avail = rcount < 8 ? rcount : 8;
+      const bool v = jj < avail;
+      const int q = (rstart + jj) & (kRowQ - 1);
+      const float4 e = RQ.d[ii][q];
+      const float2 qt = RQ.qt[ii][q];
+      accum32(e.w, e.x, e.y, e.z, qt.x, __float_as_int(qt.y), v);
+      rstart += avail;
+      rcount -= avail;
+      if (++groups >= kFlush) flush();
+    }
+  };
+
   // Evaluate pair (row ii's atom, ring entry head + jj) for navail <= 8 entries.
   auto process_group = [&](int navail) {
     const int slot = static_cast<int>((head + jj) & (kRing - 1));
@@ -173,7 +241,9 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
     }
     if (hit) {
       if constexpr (F64) {
-        const TypePair64 tp = tab_lds ? L.tab[ti * T + tj] : d.tab64[ti * T + tj];
+        TypePair64 tp;
+        if constexpr (TABLDS) tp = L.tab[ti * T + tj];
+        else tp = d.tab64[ti * T + tj];
         const PairF64 p = pair_f64(r2d, tp.c6, tp.c12, qi64 * pj64.w, c.beta, c.two_beta_sqrtpi);
         en += p.u_lj + p.u_c;
         if constexpr (MODE != kEnergy) {
@@ -192,90 +262,144 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
           asig += p.dudsig_lj * tp.inv_sig;
           beps += p.u_lj;
         }
-      } else {
-        const TypePair32 tp = tab_lds ? L.tab[ti * T + tj] : d.tab32[ti * T + tj];
-        const PairF32 p = pair_f32(r2f, tp.c6, tp.c12, qi32 * qj, c.betaf, c.two_beta_sqrtpif, c.mb2l2e);
-        sen += p.u_lj + p.u_c;
-        if constexpr (MODE != kEnergy) {
-          const float gx = p.f * dxf, gy = p.f * dyf, gz = p.f * dzf;
-          sfx += gx;
-          sfy += gy;
-          sfz += gz;
-          if constexpr (MODE == kForces) {
-            if (o.want_virial) {
-              swxx = fmaf(gx, dxf, swxx); swxy = fmaf(gx, dyf, swxy); swxz = fmaf(gx, dzf, swxz);
-              swyy = fmaf(gy, dyf, swyy); swyz = fmaf(gy, dzf, swyz); swzz = fmaf(gz, dzf, swzz);
-            }
-          }
-        }
-        if constexpr (MODE == kAdjoint) {
-          sphi = fmaf(qj, p.erfc_over_r, sphi);
-          sasig = fmaf(p.dudsig_lj, tp.inv_sig, sasig);
-          sbeps += p.u_lj;
-        }
+      } else if constexpr (!ROWQ) {
+        accum32(r2f, dxf, dyf, dzf, qj, tj, true);
+      }
+    }
+    if constexpr (ROWQ) {
+      // Compact this group's in-cutoff pairs into the rows' queues ...
+      const uint64_t hm = __ballot(hit);
+      const uint32_t rowbits = static_cast<uint32_t>(hm >> (8 * ii)) & 0xFFu;
+      const int before = __popc(rowbits & ((1u << jj) - 1u));
+      if (hit) {
+        const int q = (rstart + rcount + before) & (kRowQ - 1);
+        RQ.d[ii][q] = make_float4(dxf, dyf, dzf, r2f);
+        RQ.qt[ii][q] = make_float2(qj, __int_as_float(tj));
+      }
+      rcount += __popc(rowbits);
+      // ... and evaluate 8 per row once every row with an atom has 8, or when a
+      // queue could not take another group.
+      for (;;) {
+        const bool overfull = __ballot(rcount > kRowQ - 8) != 0;
+        const bool waiting = __ballot(ivalid && rcount < 8) != 0;
+        if ((!overfull && waiting) || __ballot(rcount > 0) == 0) break;
+        __syncthreads();
+        round();
       }
     }
     head += static_cast<uint32_t>(navail);
-    if (++groups >= kFlush) flush();
-  };
-
-  // Stage the atoms [a0, a1) of one column window: box filter, compact into the ring.
-  auto stage_run = [&](int a0, int a1) {
-    for (int base = a0; base < a1; base += 64) {
-      const int a = base + lane;
-      const bool valid = a < a1;
-      const int aa = valid ? a : a0;
-      const uint4 fj = d.s_fix[aa];
-      const int tj = d.s_type[aa];
-      double4 pj64 = make_double4(0, 0, 0, 0);
-      float qj = 0.f;
-      if constexpr (F64) pj64 = d.s_pos64[aa];
-      else qj = d.s_q32[aa];
-      const bool keep = valid && box_dist2(fj, ctr, half, sd) < c.rc2_box;
-      const uint64_t m = __ballot(keep);
-      const uint32_t below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
-      const int slot = static_cast<int>((tail + below) & (kRing - 1));
-      __syncthreads();  // earlier ring reads are complete before slots are reused
-      if (keep) {
-        if constexpr (F64) {
-          L.pos[slot] = pj64;
-          L.meta[slot] = make_int2(static_cast<int>(fj.w), tj);
-        } else {
-          L.fix[slot] = fj;
-          L.qt[slot] = make_float2(qj, __int_as_float(tj));
-        }
-      }
-      __syncthreads();
-      tail += static_cast<uint32_t>(__popcll(m));
-      while (tail - head >= 8u) process_group(8);
+    if constexpr (!ROWQ) {
+      if (++groups >= kFlush) flush();
     }
   };
 
-  for (int ox = 0; ox < xn; ++ox) {
+  // Neighbour-column windows as runs [a0, a1) of sorted atoms, two slots per column
+  // (a z-window that wraps around the box is two runs; an unused slot is empty).
+  const int ncol = xn * yn;
+  for (int k = lane; k < ncol; k += 64) {
+    const int ox = k / yn, oy = k - (k / yn) * yn;
     int x = allx ? ox : cx - kx + ox;
     x += x < 0 ? nx : (x >= nx ? -nx : 0);
-    for (int oy = 0; oy < yn; ++oy) {
-      int y = ally ? oy : cy - ky + oy;
-      y += y < 0 ? ny : (y >= ny ? -ny : 0);
-      const int cb = sd.cell_begin + (x * ny + y) * nz;
-      if (allz) {
-        stage_run(d.cell_start[cb], d.cell_start[cb + nz]);
+    int y = ally ? oy : cy - ky + oy;
+    y += y < 0 ? ny : (y >= ny ? -ny : 0);
+    const int cb = sd.cell_begin + (x * ny + y) * nz;
+    int2 r0, r1 = make_int2(0, 0);
+    if (allz) {
+      r0 = make_int2(d.cell_start[cb], d.cell_start[cb + nz]);
+    } else {
+      const int z0 = cz0 - kz, z1 = cz1 + kz + 1;  // [z0, z1)
+      if (z0 < 0) {
+        r0 = make_int2(d.cell_start[cb + z0 + nz], d.cell_start[cb + nz]);
+        r1 = make_int2(d.cell_start[cb], d.cell_start[cb + z1]);
+      } else if (z1 > nz) {
+        r0 = make_int2(d.cell_start[cb + z0], d.cell_start[cb + nz]);
+        r1 = make_int2(d.cell_start[cb], d.cell_start[cb + z1 - nz]);
       } else {
-        const int z0 = cz0 - kz, z1 = cz1 + kz + 1;  // [z0, z1)
-        if (z0 < 0) {
-          stage_run(d.cell_start[cb + z0 + nz], d.cell_start[cb + nz]);
-          stage_run(d.cell_start[cb], d.cell_start[cb + z1]);
-        } else if (z1 > nz) {
-          stage_run(d.cell_start[cb + z0], d.cell_start[cb + nz]);
-          stage_run(d.cell_start[cb], d.cell_start[cb + z1 - nz]);
-        } else {
-          stage_run(d.cell_start[cb + z0], d.cell_start[cb + z1]);
-        }
+        r0 = make_int2(d.cell_start[cb + z0], d.cell_start[cb + z1]);
       }
     }
+    L.runs[2 * k] = r0;
+    L.runs[2 * k + 1] = r1;
+  }
+  __syncthreads();
+  const int nruns = 2 * ncol;
+
+  // Walk the runs 64 atoms at a time; the next chunk's loads are issued before the
+  // current chunk is filtered and evaluated, to hide their latency.
+  int base = 0, end = 0;
+  auto seek = [&](int rr) {  // first non-empty run at or after rr; sets base/end
+    while (rr < nruns) {
+      const int2 q = L.runs[rr];
+      if (q.x < q.y) {
+        base = q.x;
+        end = q.y;
+        return rr;
+      }
+      ++rr;
+    }
+    return rr;
+  };
+  auto load = [&](int b0, int e0, uint4 &f, int &t, float &q, double4 &p, bool &v) {
+    const int a = b0 + lane;
+    v = a < e0;
+    const int aa = v ? a : b0;
+    f = d.s_fix[aa];
+    t = d.s_type[aa];
+    if constexpr (F64) p = d.s_pos64[aa];
+    else q = d.s_q32[aa];
+  };
+  uint4 fj = make_uint4(0u, 0u, 0u, 0u);
+  int tj = 0;
+  float qj = 0.f;
+  double4 pj64 = make_double4(0, 0, 0, 0);
+  bool valid = false;
+  int r = seek(0);
+  if (r < nruns) load(base, end, fj, tj, qj, pj64, valid);
+  while (r < nruns) {
+    int nr = r;
+    if (base + 64 < end) base += 64;
+    else nr = seek(r + 1);
+    uint4 fj_n = fj;
+    int tj_n = tj;
+    float qj_n = qj;
+    double4 pj64_n = pj64;
+    bool valid_n = false;
+    if (nr < nruns) load(base, end, fj_n, tj_n, qj_n, pj64_n, valid_n);
+
+    // Box filter, then compact the survivors into the ring.
+    const bool keep = valid && box_dist2(fj, ctr, half, sd) < c.rc2_box;
+    const uint64_t m = __ballot(keep);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+    const int slot = static_cast<int>((tail + below) & (kRing - 1));
+    __syncthreads();  // earlier ring reads are complete before slots are reused
+    if (keep) {
+      if constexpr (F64) {
+        L.pos[slot] = pj64;
+        L.meta[slot] = make_int2(static_cast<int>(fj.w), tj);
+      } else {
+        L.fix[slot] = fj;
+        L.qt[slot] = make_float2(qj, __int_as_float(tj));
+      }
+    }
+    __syncthreads();
+    tail += static_cast<uint32_t>(__popcll(m));
+    while (tail - head >= 8u) process_group(8);
+
+    r = nr;
+    fj = fj_n;
+    tj = tj_n;
+    qj = qj_n;
+    pj64 = pj64_n;
+    valid = valid_n;
   }
   if (tail != head) process_group(static_cast<int>(tail - head));
+  if constexpr (ROWQ) {
+    while (__ballot(rcount > 0)) {
+      __syncthreads();
+      round();
+    }
+  }
   flush();
 
   if constexpr (!F64) {
@@ -301,7 +425,7 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
         const double s = wave_sum(v[k]);
         if (lane == k) mine = s;
       }
-      if (lane < kPart) d.partials[static_cast<int64_t>(I) * kPart + lane] = lane < nv ? mine : 0.0;
+      if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + I] = lane < nv ? mine : 0.0;
     }
   }
 
@@ -352,31 +476,39 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
       left &= ~__ballot(mine);
     }
     if (lane < T) {
-      d.adj_partials[static_cast<int64_t>(I) * 2 * T + lane] = keep_a;
-      d.adj_partials[static_cast<int64_t>(I) * 2 * T + T + lane] = keep_b;
+      d.adj_partials[static_cast<int64_t>(lane) * d.n_slots + I] = keep_a;
+      d.adj_partials[static_cast<int64_t>(T + lane) * d.n_slots + I] = keep_b;
     }
   }
 }
 
 }  // namespace
 
+template <bool F64, bool TABLDS, bool ROWQ>
+void launch_cluster_mode(int mode, dim3 grid, hipStream_t s, const Dev &d, const Consts &c, const Out &o) {
+  if (mode == kForces)
+    hipLaunchKernelGGL((k_pair_cluster<F64, kForces, TABLDS, ROWQ>), grid, dim3(64), 0, s, d, c, o);
+  else if (mode == kEnergy)
+    hipLaunchKernelGGL((k_pair_cluster<F64, kEnergy, TABLDS, ROWQ>), grid, dim3(64), 0, s, d, c, o);
+  else
+    hipLaunchKernelGGL((k_pair_cluster<F64, kAdjoint, TABLDS, ROWQ>), grid, dim3(64), 0, s, d, c, o);
+}
+
 void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out &o, int mode, hipStream_t s) {
   if (p.n_clusters_max == 0 || p.N == 0) return;
-  const dim3 grid(static_cast<unsigned>(p.n_clusters_max)), block(64);
-  const bool f64 = p.precision == NB_FP64;
-  switch (mode) {
-    case kForces:
-      if (f64) hipLaunchKernelGGL((k_pair_cluster<true, kForces>), grid, block, 0, s, d, c, o);
-      else hipLaunchKernelGGL((k_pair_cluster<false, kForces>), grid, block, 0, s, d, c, o);
-      break;
-    case kEnergy:
-      if (f64) hipLaunchKernelGGL((k_pair_cluster<true, kEnergy>), grid, block, 0, s, d, c, o);
-      else hipLaunchKernelGGL((k_pair_cluster<false, kEnergy>), grid, block, 0, s, d, c, o);
-      break;
-    default:
-      if (f64) hipLaunchKernelGGL((k_pair_cluster<true, kAdjoint>), grid, block, 0, s, d, c, o);
-      else hipLaunchKernelGGL((k_pair_cluster<false, kAdjoint>), grid, block, 0, s, d, c, o);
-      break;
+  const int64_t g = (p.n_clusters_max + kXcds - 1) / kXcds * kXcds;  // a multiple of the XCD count
+  const dim3 grid(static_cast<unsigned>(g));
+  const bool tab = p.T <= kTabLds;
+  const bool rowq = p.kernel == NB_KERNEL_CLUSTER_RQ;
+  if (p.precision == NB_FP64) {
+    if (tab) launch_cluster_mode<true, true, false>(mode, grid, s, d, c, o);
+    else launch_cluster_mode<true, false, false>(mode, grid, s, d, c, o);
+  } else if (rowq) {
+    if (tab) launch_cluster_mode<false, true, true>(mode, grid, s, d, c, o);
+    else launch_cluster_mode<false, false, true>(mode, grid, s, d, c, o);
+  } else {
+    if (tab) launch_cluster_mode<false, true, false>(mode, grid, s, d, c, o);
+    else launch_cluster_mode<false, false, false>(mode, grid, s, d, c, o);
   }
 }
 

@@ -18,7 +18,7 @@ pytestmark = [pytest.mark.gpu,
 
 FP64_TOL = 1e-12
 MIXED_TOL = 1e-5
-KERNELS = [H.NB_KERNEL_ATOM, H.NB_KERNEL_CLUSTER]
+KERNELS = [H.NB_KERNEL_ATOM, H.NB_KERNEL_CLUSTER, H.NB_KERNEL_CLUSTER_RQ]
 
 
 def _print_case(name, **kw):
@@ -32,11 +32,14 @@ def chain():
 
 # --- binning: bit-exact ------------------------------------------------------------------
 
+@pytest.mark.parametrize("build", ["fused", "phased"])
 @pytest.mark.parametrize("divs", [(2, 2), (2, 8), (1, 1), (3, 3), (2, 3)])
 @pytest.mark.parametrize("precision", [H.NB_MIXED, H.NB_FP64])
-def test_binning_is_the_stable_counting_sort(divs, precision, chain):
+def test_binning_is_the_stable_counting_sort(divs, precision, build, chain, monkeypatch):
+    # the cell list is built by one cooperative launch, or by one launch per phase
+    monkeypatch.setenv("NBHIP_BUILD", build)
     systems = [chain, U.cached_config(1), S.water_box(500, 25.0, seed=9)]
-    _print_case("binning", divs=divs, precision=precision)
+    _print_case("binning", divs=divs, precision=precision, build=build)
     out = U.gpu_eval(systems, precision, cell_div_xy=divs[0], cell_div_z=divs[1])
     ws = U.workspace_arrays(out)
     ref = U.oracle_binning(systems, precision, (divs[0], divs[0], divs[1]))
@@ -72,7 +75,9 @@ def test_exclusion_windows_are_exact(chain):
     assert not far.any()
 
 
-def test_clusters_partition_every_column(chain):
+@pytest.mark.parametrize("build", ["fused", "phased"])
+def test_clusters_partition_every_column(build, chain, monkeypatch):
+    monkeypatch.setenv("NBHIP_BUILD", build)
     systems = [chain, U.cached_config(1)]
     out = U.gpu_eval(systems, H.NB_MIXED, kernel=H.NB_KERNEL_CLUSTER)
     ws = U.workspace_arrays(out)
@@ -108,7 +113,9 @@ def test_forces_energy_virial_match_oracle(which, precision, kernel, chain):
     assert out["energy"][0] == pytest.approx(ref["energy_total"], rel=tol, abs=tol)
     assert U.rel_rms(out["virial"][0], ref["virial"]) <= (1e-11 if precision == H.NB_FP64 else 1e-5)
     assert U.rel_rms(out["atom_energy"], ref["energy"]) <= (1e-11 if precision == H.NB_FP64 else 1e-5)
-    assert out["energy2"][0] == out["energy"][0]  # the energy call sums the same terms in the same order
+    # the energy call sums the same pairs in the same order; only the compiler's fusing of
+    # multiply-adds may differ between the two kernels
+    assert out["energy2"][0] == pytest.approx(out["energy"][0], rel=1e-12 if precision == H.NB_FP64 else 1e-7)
     assert out["status"] == 0
 
 
@@ -331,3 +338,22 @@ def test_pair_kernels_refuse_a_workspace_built_for_another_kernel(chain):
     H.build_cells(b, p_clu, ws)
     H.nonbonded_forces(b, p_clu, ws, force, energy)
     assert H.read_status(ws) == 0
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+def test_many_types_use_the_global_type_table(precision, kernel, chain):
+    # 20 types: more than the cluster kernel keeps in LDS
+    rng = np.random.default_rng(8)
+    s = S.System(**{**chain.__dict__})
+    s.sigma = np.concatenate([chain.sigma, rng.uniform(2.5, 3.8, 10)])
+    s.eps = np.concatenate([chain.eps, rng.uniform(0.1, 0.9, 10)])
+    s.type = chain.type.copy()
+    s.type[:chain.n_solute] = rng.integers(2, 20, chain.n_solute)
+    out = U.gpu_eval(s, precision, kernel=kernel, backward=True)
+    ref = U.oracle_for(s, precision)
+    tol = FP64_TOL if precision == H.NB_FP64 else MIXED_TOL
+    assert U.rel_rms(out["force"], ref["force"]) <= tol
+    lj = np.unique(s.type)
+    lj = lj[s.eps[lj] > 0]
+    np.testing.assert_allclose(out["grad_sigma"][lj], ref["dsigma"][lj], rtol=max(tol * 10, 1e-10), atol=tol)
