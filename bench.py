@@ -76,8 +76,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", choices=["both", "mixed"], default="both",
                     help="time the FP64 GPU path beside the mixed one (default) or only the mixed one")
-    ap.add_argument("--kernel", choices=["auto", "atom", "cluster", "cluster_rq"], default="auto",
-                    help="pair-kernel variant of the mixed path (the FP64 path uses the same or its nearest)")
+    ap.add_argument("--kernel", choices=["auto", "atom", "cluster"], default="auto",
+                    help="pair-kernel variant (both paths)")
+    ap.add_argument("--split", type=int, default=0, help="cluster kernel: waves per cluster (0 = default)")
+    ap.add_argument("--cluster-size", type=int, default=0, help="cluster kernel: atoms per cluster, 4 or 8")
     ap.add_argument("--cell-div", type=str, default="0,0", help="cells per cutoff 'xy,z' (0 = default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for hardware-counter calibration)")
@@ -112,10 +114,10 @@ def main():
         paths.append(("fp64", H.NB_FP64, torch.float64))
     for prec_name, prec, dt in paths:
         b = H.device_batch([s], dtype=dt)
-        kern = {"auto": H.NB_KERNEL_AUTO, "atom": H.NB_KERNEL_ATOM, "cluster": H.NB_KERNEL_CLUSTER,
-                "cluster_rq": H.NB_KERNEL_CLUSTER_RQ}[args.kernel]
+        kern = {"auto": H.NB_KERNEL_AUTO, "atom": H.NB_KERNEL_ATOM, "cluster": H.NB_KERNEL_CLUSTER}[args.kernel]
         dxy, dz = (int(v) for v in args.cell_div.split(","))
-        p = H.make_params(s.cutoff, s.beta, prec, kernel=kern, cell_div_xy=dxy, cell_div_z=dz)
+        p = H.make_params(s.cutoff, s.beta, prec, kernel=kern, cell_div_xy=dxy, cell_div_z=dz, split=args.split,
+                          cluster_size=args.cluster_size)
         ws = H.alloc_workspace(b, p)
         force = torch.empty((s.n, 3), dtype=torch.float64, device="cuda")
         energy = torch.empty(1, dtype=torch.float64, device="cuda")

@@ -92,9 +92,7 @@ typedef struct {
 /* Kernel variants for nb_params.kernel. */
 #define NB_KERNEL_AUTO 0    /* library default for the precision (or the tuned choice passed in) */
 #define NB_KERNEL_ATOM 1    /* one lane per i atom, full neighbour shell, j read through the cache */
-#define NB_KERNEL_CLUSTER 2 /* 8-atom clusters x box-filtered j atoms staged in LDS, 8 x 8 pairs per step */
-#define NB_KERNEL_CLUSTER_RQ 3 /* as NB_KERNEL_CLUSTER, with in-cutoff pairs compacted per i atom before the
-                                  pair terms (single precision; the FP64 path runs NB_KERNEL_CLUSTER) */
+#define NB_KERNEL_CLUSTER 2 /* 4- or 8-atom clusters x box-filtered j atoms staged in LDS, 64 pairs per step */
 
 typedef struct {
   double cutoff;      /* R (A): 0 < R < min(L)/2 for every system */
@@ -104,6 +102,8 @@ typedef struct {
   int32_t cell_div_xy;/* cells per cutoff along x and y, 1..4 (0 = 2, the paper's R/2 bins) */
   int32_t cell_div_z; /* cells per cutoff along z, 1..16 (0 = the kernel's default) */
   int32_t kernel;     /* NB_KERNEL_* */
+  int32_t split;      /* cluster kernel: waves sharing one cluster's neighbour columns, 1..4 (0 = 1) */
+  int32_t cluster_size; /* cluster kernel: atoms per i-cluster, 4 or 8 (0 = 8 mixed, 4 FP64) */
 } nb_params;
 
 /* Bytes of device workspace needed for this batch and these parameters.
@@ -165,11 +165,8 @@ typedef struct {
   int64_t off_excl_mask;    /* uint32 x4 [n_atoms], original order: exclusion window bits */
   int64_t off_status;       /* uint32 status word */
   int64_t n_columns;        /* (x, y) columns of all systems */
-  int64_t n_clusters_max;   /* capacity of the cluster arrays */
+  int64_t n_clusters_max;   /* upper bound on the number of clusters */
   int64_t off_col_clu_start;/* int32 [n_columns + 1]: first cluster of each column (cluster kernel) */
-  int64_t off_clusters;     /* int32 x4 [n_clusters_max]: first sorted atom, count, column, system */
-  int64_t off_clu_ctr;      /* uint32 x4 [n_clusters_max]: bounding-box centre (fixed point) */
-  int64_t off_clu_half;     /* uint32 x4 [n_clusters_max]: bounding-box half extent */
 } nb_layout;
 
 nb_status nb_workspace_layout(const nb_system *sys, const nb_params *params, nb_layout *layout /*[host]*/);

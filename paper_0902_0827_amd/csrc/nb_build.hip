@@ -5,7 +5,8 @@
 //   k_init      clear counters, masks and status; write descriptors and the type-pair table
 //   k_bin       per atom: box-fraction fixed point, cell id, atomic cell count (its slot),
 //               and the atom's exclusion row folded into 128-bit index windows
-//   k_scan      exclusive scan of the cell counts -> cell_start
+//   k_scan      exclusive scan of the cell counts -> cell_start; for the cluster kernels
+//               also the clusters per (x, y) column and their scan -> col_clu_start
 //   k_scatter   atom -> cell_start[cell] + slot (order inside a cell still arbitrary)
 //   k_finalize  rank inside the cell by original index (makes the sort stable and the
 //               result deterministic) and write the sorted per-atom records
@@ -14,15 +15,10 @@
 // every coordinate into the box; the 32-bit difference of two such values is the
 // minimum-image displacement in units of L/2^32.
 //
-// The phases normally run as one cooperative launch (k_build_fused) with grid-wide
-// synchronisation between them, since on a 23k-atom box each phase is a few
-// microseconds of work and separate launches would cost more than the work; the
-// per-phase kernels remain for grids too large to be co-resident.
-#include <hip/hip_cooperative_groups.h>
-
-#include <cstdlib>
-#include <cstring>
-
+// Each phase depends on the whole previous one, so each is its own launch: a
+// single cooperative launch with grid-wide synchronisation between the phases was
+// measured slower on MI355X (a device-wide barrier across the 8 XCDs costs more
+// than a kernel boundary).
 #include "nb_internal.h"
 
 namespace nb {
@@ -30,6 +26,8 @@ namespace nb {
 namespace {
 
 constexpr double kTwo32 = 4294967296.0;
+constexpr int kScanBlock = 1024;
+constexpr int kScanPer = 16;  // consecutive counts per thread and pass of k_scan
 
 struct DescChunk {
   SysDesc d[kDescChunk];
@@ -45,13 +43,24 @@ __device__ inline int find_system(const SysDesc *desc, int B, int atom) {
   return lo;
 }
 
+__device__ inline int column_system(const SysDesc *desc, int B, int col) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].col_begin <= col) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 __global__ void k_put_desc(Dev d, DescChunk c) {
   const int k = threadIdx.x;
   if (k < c.count) d.desc[c.first + k] = c.d[k];
 }
 
-__device__ inline void init_body(const Dev &d, const DescChunk &c, const double *__restrict__ sigma,
-                                 const double *__restrict__ eps, int kernel, int64_t tid, int64_t stride) {
+__global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, const double *__restrict__ eps,
+                       int kernel) {
+  const int64_t tid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   if (tid < c.count) d.desc[c.first + tid] = c.d[tid];
   if (tid == 0) {
     d.status[0] = 0u;
@@ -86,12 +95,6 @@ __device__ inline void init_body(const Dev &d, const DescChunk &c, const double 
   }
 }
 
-__global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, const double *__restrict__ eps,
-                       int kernel) {
-  const int64_t tid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  init_body(d, c, sigma, eps, kernel, tid, static_cast<int64_t>(gridDim.x) * blockDim.x);
-}
-
 __device__ inline void set_status(const Dev &d, uint32_t bit) { atomicOr(d.status, bit); }
 
 __device__ inline void window_set(const Dev &d, int atom, int delta) {
@@ -102,8 +105,10 @@ __device__ inline void window_set(const Dev &d, int atom, int delta) {
 }
 
 template <typename Real>
-__device__ inline void bin_body(const Dev &d, int i, const Real *__restrict__ pos, const int32_t *__restrict__ type,
-                                const int32_t *__restrict__ excl_off, const int32_t *__restrict__ excl_idx) {
+__global__ void k_bin(Dev d, const Real *__restrict__ pos, const int32_t *__restrict__ type,
+                      const int32_t *__restrict__ excl_off, const int32_t *__restrict__ excl_idx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.N) return;
   const int b = find_system(d.desc, d.B, i);
   const SysDesc &sd = d.desc[b];
   uint32_t u[3];
@@ -158,54 +163,95 @@ __device__ inline void bin_body(const Dev &d, int i, const Real *__restrict__ po
   }
 }
 
-template <typename Real>
-__global__ void k_bin(Dev d, const Real *__restrict__ pos, const int32_t *__restrict__ type,
-                      const int32_t *__restrict__ excl_off, const int32_t *__restrict__ excl_idx) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < d.N) bin_body(d, i, pos, type, excl_off, excl_idx);
-}
-
-// Exclusive scan of n counts into n + 1 offsets by one workgroup: each thread
-// sums a contiguous chunk, the chunk sums are scanned in LDS, then each thread
-// writes its chunk.
-__global__ void __launch_bounds__(1024) k_scan(const int32_t *__restrict__ count, int32_t *__restrict__ start,
-                                               int64_t n) {
-  __shared__ int sums[1024];
-  const int tid = threadIdx.x;
-  const int64_t chunk = (n + 1023) / 1024;
-  const int64_t lo = tid * chunk, hi = lo + chunk < n ? lo + chunk : n;
-  int s = 0;
-  for (int64_t k = lo; k < hi; ++k) s += count[k];
-  sums[tid] = s;
+// Exclusive scan of the workgroup's values v (returns this thread's prefix; *total
+// the sum of all).
+__device__ inline int block_excl_scan(int v, int *lds, int *total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) lds[wave] = x;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int v = tid >= off ? sums[tid - off] : 0;
-    __syncthreads();
-    sums[tid] += v;
-    __syncthreads();
+  int before = 0, all = 0;
+  for (int w = 0; w < kScanBlock / 64; ++w) {
+    const int s = lds[w];
+    before += w < wave ? s : 0;
+    all += s;
   }
-  int run = sums[tid] - s;  // exclusive prefix of this chunk
-  for (int64_t k = lo; k < hi; ++k) {
-    const int c = count[k];
-    start[k] = run;
-    run += c;
-  }
-  if (tid == 1023) start[n] = sums[1023];
+  __syncthreads();
+  *total = all;
+  return x - v + before;
 }
 
-__device__ inline void scatter_body(const Dev &d, int i) {
-  d.tmp[d.cell_start[d.atom_cell[i]] + d.atom_slot[i]] = i;
+// Exclusive scan of count(0 .. n-1) into start[0, n] by this workgroup; each
+// thread takes kScanPer consecutive entries per pass.
+template <typename Count>
+__device__ inline void scan_array(Count count, int32_t *start, int64_t n, int *lds) {
+  int run = 0;
+  if (n <= 0) {
+    if (threadIdx.x == 0) start[0] = 0;
+    return;
+  }
+  for (int64_t base = 0; base < n; base += static_cast<int64_t>(kScanBlock) * kScanPer) {
+    const int64_t k0 = base + static_cast<int64_t>(threadIdx.x) * kScanPer;
+    int v[kScanPer];
+    int sum = 0;
+    // Unconditional loads (indices clamped into range) so that all of them are in
+    // flight at once; out-of-range entries are then zeroed.
+#pragma unroll
+    for (int m = 0; m < kScanPer; ++m) {
+      const int64_t k = k0 + m < n ? k0 + m : n - 1;
+      v[m] = count(k);
+    }
+#pragma unroll
+    for (int m = 0; m < kScanPer; ++m) {
+      v[m] = k0 + m < n ? v[m] : 0;
+      sum += v[m];
+    }
+    int tot;
+    int pre = block_excl_scan(sum, lds, &tot) + run;
+#pragma unroll
+    for (int m = 0; m < kScanPer; ++m) {
+      if (k0 + m < n) start[k0 + m] = pre;
+      pre += v[m];
+    }
+    run += tot;
+  }
+  if (threadIdx.x == 0) start[n] = run;
+}
+
+// One workgroup: cell_start from the cell counts, then (cluster kernel) the number
+// of K-atom clusters of every (x, y) column and their scan.
+__global__ void __launch_bounds__(kScanBlock) k_scan(Dev d, int clusters, int K) {
+  __shared__ int lds[kScanBlock / 64];
+  const int32_t *cnt = d.cell_count;
+  scan_array([cnt](int64_t k) { return static_cast<int>(cnt[k]); }, d.cell_start, d.n_cells, lds);
+  if (!clusters) return;
+  __syncthreads();  // cell_start is visible to the whole workgroup
+  const Dev dd = d;
+  scan_array(
+      [dd, K](int64_t col) {
+        const SysDesc &sd = dd.desc[column_system(dd.desc, dd.B, static_cast<int>(col))];
+        const int nz = sd.dims[2];
+        const int c0 = sd.cell_begin + (static_cast<int>(col) - sd.col_begin) * nz;
+        return (dd.cell_start[c0 + nz] - dd.cell_start[c0] + K - 1) / K;
+      },
+      d.col_clu_start, d.n_columns, lds);
 }
 
 __global__ void k_scatter(Dev d) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < d.N) scatter_body(d, i);
+  if (i >= d.N) return;
+  d.tmp[d.cell_start[d.atom_cell[i]] + d.atom_slot[i]] = i;
 }
 
 template <typename Real>
-__device__ inline void finalize_body(const Dev &d, int s, const Real *__restrict__ pos,
-                                     const Real *__restrict__ charge, const int32_t *__restrict__ type,
-                                     double sqrt_ke) {
+__global__ void k_finalize(Dev d, const Real *__restrict__ pos, const Real *__restrict__ charge,
+                           const int32_t *__restrict__ type, double sqrt_ke) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= d.N) return;
   const int i = d.tmp[s];
   const int cell = d.atom_cell[i];
   const int lo = d.cell_start[cell], hi = d.cell_start[cell + 1];
@@ -223,229 +269,9 @@ __device__ inline void finalize_body(const Dev &d, int s, const Real *__restrict
   d.s_type[dst] = (t < 0 || t >= d.T) ? 0 : t;
 }
 
-template <typename Real>
-__global__ void k_finalize(Dev d, const Real *__restrict__ pos, const Real *__restrict__ charge,
-                           const int32_t *__restrict__ type, double sqrt_ke) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < d.N) finalize_body(d, s, pos, charge, type, sqrt_ke);
-}
-
-// Clusters for the cluster pair kernel: the sorted atoms of each (x, y) column
-// (z-cells are contiguous inside a column) are cut into runs of 8.
-__device__ inline int column_system(const SysDesc *desc, int B, int col) {
-  int lo = 0, hi = B - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (desc[mid].col_begin <= col) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-__device__ inline int col_nclu_of(const Dev &d, int col) {
-  const SysDesc &sd = d.desc[column_system(d.desc, d.B, col)];
-  const int nz = sd.dims[2];
-  const int c0 = sd.cell_begin + (col - sd.col_begin) * nz;
-  const int n = d.cell_start[c0 + nz] - d.cell_start[c0];
-  return (n + 7) >> 3;
-}
-
-__global__ void k_col_count(Dev d) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col < d.n_columns) d.col_nclu[col] = col_nclu_of(d, col);
-}
-
-// Cluster k (global index): its column by binary search of col_clu_start, then
-// record and bounding box (centre and half extent, in fixed point, taken relative
-// to the cluster's first atom so that the minimum image is respected).
-__device__ inline void cluster_body(const Dev &d, int k) {
-  int lo = 0, hi = static_cast<int>(d.n_columns) - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (d.col_clu_start[mid] <= k) lo = mid; else hi = mid - 1;
-  }
-  const int col = lo;
-  const int sys = column_system(d.desc, d.B, col);
-  const SysDesc &sd = d.desc[sys];
-  const int nz = sd.dims[2];
-  const int c0 = sd.cell_begin + (col - sd.col_begin) * nz;
-  const int a1 = d.cell_start[c0 + nz];
-  const int b = d.cell_start[c0] + 8 * (k - d.col_clu_start[col]);
-  const int cnt = a1 - b < 8 ? a1 - b : 8;
-  const uint4 u0 = d.s_fix[b];
-  int lo3[3] = {0, 0, 0}, hi3[3] = {0, 0, 0};
-  for (int m = 1; m < cnt; ++m) {
-    const uint4 u = d.s_fix[b + m];
-    const int dd[3] = {static_cast<int>(u.x - u0.x), static_cast<int>(u.y - u0.y), static_cast<int>(u.z - u0.z)};
-    for (int a = 0; a < 3; ++a) {
-      lo3[a] = dd[a] < lo3[a] ? dd[a] : lo3[a];
-      hi3[a] = dd[a] > hi3[a] ? dd[a] : hi3[a];
-    }
-  }
-  uint32_t ctr[3], half[3];
-  const uint32_t base[3] = {u0.x, u0.y, u0.z};
-  for (int a = 0; a < 3; ++a) {
-    const int64_t mid = (static_cast<int64_t>(lo3[a]) + hi3[a]) >> 1;  // floor
-    const int64_t h = (hi3[a] - mid) > (mid - lo3[a]) ? (hi3[a] - mid) : (mid - lo3[a]);
-    ctr[a] = base[a] + static_cast<uint32_t>(static_cast<int32_t>(mid));
-    half[a] = static_cast<uint32_t>(h);
-  }
-  d.clusters[k] = make_int4(b, cnt, col, sys);
-  d.clu_ctr[k] = make_uint4(ctr[0], ctr[1], ctr[2], 0u);
-  d.clu_half[k] = make_uint4(half[0], half[1], half[2], 0u);
-}
-
-__global__ void k_make_clusters(Dev d) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < d.col_clu_start[d.n_columns]) cluster_body(d, k);
-}
-
-// Exclusive scan helpers for a 256-thread workgroup.
-constexpr int kFusedBlock = 256;
-
-__device__ inline int block_excl_scan(int v, int *lds, int *total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int x = v;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  if (lane == 63) lds[wave] = x;
-  __syncthreads();
-  int before = 0, all = 0;
-  for (int w = 0; w < kFusedBlock / 64; ++w) {
-    before += w < wave ? lds[w] : 0;
-    all += lds[w];
-  }
-  __syncthreads();
-  *total = all;
-  return x - v + before;
-}
-
-// Exclusive scan of count[0, n) into start[0, n] by this one workgroup.
-__device__ inline void block_scan_array(const int32_t *count, int32_t *start, int64_t n, int *lds) {
-  int run = 0;
-  for (int64_t base = 0; base < n; base += kFusedBlock) {
-    const int64_t k = base + threadIdx.x;
-    const int v = k < n ? count[k] : 0;
-    int tot;
-    const int e = block_excl_scan(v, lds, &tot);
-    if (k < n) start[k] = run + e;
-    run += tot;
-  }
-  if (threadIdx.x == 0) start[n] = run;
-}
-
-// The whole cell-list build in one cooperative launch.
-template <typename Real>
-__global__ void __launch_bounds__(kFusedBlock) k_build_fused(Dev d, DescChunk c, const Real *__restrict__ pos,
-                                                             const Real *__restrict__ charge,
-                                                             const int32_t *__restrict__ type,
-                                                             const int32_t *__restrict__ excl_off,
-                                                             const int32_t *__restrict__ excl_idx,
-                                                             const double *__restrict__ sigma,
-                                                             const double *__restrict__ eps, int kernel,
-                                                             double sqrt_ke) {
-  namespace cg = cooperative_groups;
-  cg::grid_group grid = cg::this_grid();
-  __shared__ int lds[kFusedBlock / 64];
-  const int G = gridDim.x;
-  const int64_t tid = blockIdx.x * static_cast<int64_t>(kFusedBlock) + threadIdx.x;
-  const int64_t nthr = static_cast<int64_t>(G) * kFusedBlock;
-
-  init_body(d, c, sigma, eps, kernel, tid, nthr);
-  grid.sync();
-  for (int64_t i = tid; i < d.N; i += nthr) bin_body(d, static_cast<int>(i), pos, type, excl_off, excl_idx);
-  grid.sync();
-  // Cell scan in three steps: chunk sums, scan of the chunk sums, chunk scans.
-  const int64_t chunk = (d.n_cells + G - 1) / G;
-  const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < d.n_cells ? lo + chunk : d.n_cells;
-  {
-    int sum = 0;
-    for (int64_t k = lo + threadIdx.x; k < hi; k += kFusedBlock) sum += d.cell_count[k];
-    int tot;
-    block_excl_scan(sum, lds, &tot);
-    if (threadIdx.x == 0) d.scan_tmp[blockIdx.x] = tot;
-  }
-  grid.sync();
-  if (blockIdx.x == 0) block_scan_array(d.scan_tmp, d.scan_tmp + kMaxFusedGrid, G, lds);
-  grid.sync();
-  {
-    int run = d.scan_tmp[kMaxFusedGrid + blockIdx.x];
-    for (int64_t base = lo; base < hi; base += kFusedBlock) {
-      const int64_t k = base + threadIdx.x;
-      const int v = k < hi ? d.cell_count[k] : 0;
-      int tot;
-      const int e = block_excl_scan(v, lds, &tot);
-      if (k < hi) d.cell_start[k] = run + e;
-      run += tot;
-    }
-    if (blockIdx.x == G - 1 && threadIdx.x == 0) d.cell_start[d.n_cells] = static_cast<int32_t>(d.N);
-  }
-  grid.sync();
-  for (int64_t i = tid; i < d.N; i += nthr) scatter_body(d, static_cast<int>(i));
-  const bool clusters = uses_clusters(kernel);
-  if (clusters && blockIdx.x == G - 1) {
-    // one workgroup: clusters per column and their scan
-    for (int64_t col = threadIdx.x; col < d.n_columns; col += kFusedBlock)
-      d.col_nclu[col] = col_nclu_of(d, static_cast<int>(col));
-    __syncthreads();
-    block_scan_array(d.col_nclu, d.col_clu_start, d.n_columns, lds);
-  }
-  grid.sync();
-  for (int64_t s = tid; s < d.N; s += nthr) finalize_body(d, static_cast<int>(s), pos, charge, type, sqrt_ke);
-  if (!clusters) return;
-  grid.sync();
-  const int n_clu = d.col_clu_start[d.n_columns];
-  for (int64_t k = tid; k < n_clu; k += nthr) cluster_body(d, static_cast<int>(k));
-}
-
 unsigned grid_for(int64_t n, int block) {
   const int64_t g = (n + block - 1) / block;
   return static_cast<unsigned>(g > 0 ? g : 1);
-}
-
-}  // namespace
-
-namespace {
-
-// Co-resident workgroups of the fused build on the current device (cached per device).
-int fused_grid_limit() {
-  static int cache[64] = {0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-  if (cache[dev] == 0) {
-    int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_build_fused<float>, kFusedBlock, 0) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-      (void)hipGetLastError();
-      return 0;
-    }
-    int per_cu64 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu64, k_build_fused<double>, kFusedBlock, 0) != hipSuccess)
-      per_cu64 = 0;
-    const int lim = (per_cu < per_cu64 ? per_cu : per_cu64) * cus;
-    cache[dev] = lim > 0 ? lim : -1;
-  }
-  return cache[dev] > 0 ? cache[dev] : 0;
-}
-
-template <typename Real>
-hipError_t launch_fused(const Plan &plan, const Dev &d, const DescChunk &first, const nb_system *sys, unsigned g,
-                        hipStream_t s) {
-  Dev dd = d;
-  DescChunk cc = first;
-  const Real *pos = static_cast<const Real *>(sys->pos);
-  const Real *charge = static_cast<const Real *>(sys->charge);
-  const int32_t *type = sys->type;
-  const int32_t *eo = sys->excl_offset;
-  const int32_t *ei = sys->excl_index;
-  const double *sig = sys->lj_sigma;
-  const double *eps = sys->lj_eps;
-  int kernel = plan.kernel;
-  double sqrt_ke = sqrt(plan.ke);
-  void *args[] = {&dd, &cc, &pos, &charge, &type, &eo, &ei, &sig, &eps, &kernel, &sqrt_ke};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_build_fused<Real>), dim3(g),
-                                    dim3(kFusedBlock), args, 0, s);
 }
 
 }  // namespace
@@ -456,6 +282,10 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
   first.first = 0;
   first.count = plan.B < kDescChunk ? plan.B : kDescChunk;
   for (int k = 0; k < first.count; ++k) first.d[k] = plan.desc[k];
+  const int64_t init_work = plan.N > plan.n_cells ? plan.N : plan.n_cells;
+  unsigned g_init = grid_for(init_work, kBlock);
+  if (g_init > 4096) g_init = 4096;
+  hipLaunchKernelGGL(k_init, dim3(g_init), dim3(kBlock), 0, s, d, first, sys->lj_sigma, sys->lj_eps, plan.kernel);
   for (int b0 = kDescChunk; b0 < plan.B; b0 += kDescChunk) {
     DescChunk c{};
     c.first = b0;
@@ -463,35 +293,9 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
     for (int k = 0; k < c.count; ++k) c.d[k] = plan.desc[b0 + k];
     hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, c);
   }
-
-  // Single cooperative launch when the grid can be co-resident (NBHIP_BUILD=phased
-  // selects one launch per phase instead).
-  const char *mode = getenv("NBHIP_BUILD");
-  const bool phased = mode && strcmp(mode, "phased") == 0;
-  if (plan.N > 0 && !phased) {
-    const int limit = fused_grid_limit();
-    const int64_t work = plan.N > plan.n_cells ? plan.N : plan.n_cells;
-    int64_t g = (work + kFusedBlock - 1) / kFusedBlock;
-    g = g < kMaxFusedGrid ? g : kMaxFusedGrid;
-    g = g < limit ? g : limit;
-    if (g >= 1 && first.count > 0) {
-      const hipError_t e = sys->pos_is_f64 ? launch_fused<double>(plan, d, first, sys, static_cast<unsigned>(g), s)
-                                           : launch_fused<float>(plan, d, first, sys, static_cast<unsigned>(g), s);
-      if (e == hipSuccess) return hipSuccess;
-      (void)hipGetLastError();  // fall back to one launch per phase
-    }
-  }
-
-  const int64_t init_work = plan.N > plan.n_cells ? plan.N : plan.n_cells;
-  unsigned g_init = grid_for(init_work, kBlock);
-  if (g_init > 4096) g_init = 4096;
-  hipLaunchKernelGGL(k_init, dim3(g_init), dim3(kBlock), 0, s, d, first, sys->lj_sigma, sys->lj_eps, plan.kernel);
+  const int clusters = uses_clusters(plan.kernel) ? 1 : 0;
   if (plan.N == 0) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d.cell_count, d.cell_start, d.n_cells);
-    if (uses_clusters(plan.kernel)) {
-      hipLaunchKernelGGL(k_col_count, dim3(grid_for(plan.n_columns, kBlock)), dim3(kBlock), 0, s, d);
-      hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d.col_nclu, d.col_clu_start, d.n_columns);
-    }
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, s, d, clusters, plan.cluster_size);
     return hipGetLastError();
   }
   const unsigned g = grid_for(plan.N, kBlock);
@@ -501,7 +305,7 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
   else
     hipLaunchKernelGGL(k_bin<float>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const float *>(sys->pos),
                        sys->type, sys->excl_offset, sys->excl_index);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d.cell_count, d.cell_start, d.n_cells);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, s, d, clusters, plan.cluster_size);
   hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kBlock), 0, s, d);
   const double sqrt_ke = sqrt(plan.ke);
   if (sys->pos_is_f64)
@@ -510,11 +314,6 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
   else
     hipLaunchKernelGGL(k_finalize<float>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const float *>(sys->pos),
                        static_cast<const float *>(sys->charge), sys->type, sqrt_ke);
-  if (uses_clusters(plan.kernel)) {
-    hipLaunchKernelGGL(k_col_count, dim3(grid_for(plan.n_columns, kBlock)), dim3(kBlock), 0, s, d);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d.col_nclu, d.col_clu_start, d.n_columns);
-    hipLaunchKernelGGL(k_make_clusters, dim3(grid_for(plan.n_clusters_max, kBlock)), dim3(kBlock), 0, s, d);
-  }
   return hipGetLastError();
 }
 

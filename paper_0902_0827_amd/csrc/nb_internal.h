@@ -18,13 +18,10 @@ constexpr int kWaves = kBlock / 64;   // wave64
 constexpr int kPart = 10;             // per-block partial sums: energy + 9 virial entries
 constexpr int kWindow = 64;           // exclusion bitmap reach in original index (section 3)
 constexpr int kDescChunk = 8;         // system descriptors carried by one initialisation launch
-constexpr int kMaxFusedGrid = 1024;   // workgroups of the single-launch cell-list build
 constexpr uint32_t kBuiltMagic = 0x4E424831u;  // status[1]: written by nb_build_cells
 
-// Kernel variants that read the cluster arrays built by nb_build_cells.
-__host__ __device__ __forceinline__ bool uses_clusters(int kernel) {
-  return kernel == NB_KERNEL_CLUSTER || kernel == NB_KERNEL_CLUSTER_RQ;
-}
+// Kernel variants that read the column cluster counts built by nb_build_cells.
+__host__ __device__ __forceinline__ bool uses_clusters(int kernel) { return kernel == NB_KERNEL_CLUSTER; }
 
 // Workspace header words: status[0] = NB_STATUS_* bits, status[1] = kBuiltMagic,
 // status[2] = atom count, status[3] = 1 if the cluster arrays were built.
@@ -57,7 +54,7 @@ struct alignas(16) TypePair32 { float c6, c12, inv_sig, pad; };
 struct Layout {
   size_t status, desc, tab64, tab32, cell_count, cell_start, atom_cell, atom_slot, atom_fix, tmp;
   size_t s_fix, s_pos64, s_q32, s_type, excl_mask, excl_far, partials, adj_partials;
-  size_t col_nclu, col_clu_start, clusters, clu_ctr, clu_half, scan_tmp;
+  size_t col_clu_start, part;
   size_t total;
 };
 
@@ -69,6 +66,8 @@ struct Plan {
   int precision = 0;
   int kernel = 0;
   int div_xy = 2, div_z = 2;
+  int split = 1;         // waves per cluster (cluster kernel)
+  int cluster_size = 4;  // atoms per cluster (cluster kernel): 4 or 8
   double cutoff = 0, beta = 0, ke = 0;
   int64_t n_cells = 0, n_blocks = 0, n_clusters_max = 0, n_columns = 0;
   std::vector<SysDesc> desc;
@@ -93,20 +92,16 @@ struct Dev {
   int32_t *s_type;   // sorted: type (clamped into range)
   uint4 *excl_mask;  // original order: 128-bit exclusion window
   uint32_t *excl_far;// original order: nonzero if the atom has an exclusion beyond the window
-  double *partials;      // [kPart][n_slots]: per-block (or per-cluster) energy and virial sums
-  double *adj_partials;  // [2 T][n_slots]: per-block (or per-cluster) sigma / eps sums by type
-  int64_t n_slots;       // max(n_blocks, n_clusters_max)
+  double *partials;      // [kPart][n_slots]: per-block (or per-wave) energy and virial sums
+  double *adj_partials;  // [2 T][n_slots]: per-block (or per-wave) sigma / eps sums by type
+  int64_t n_slots;       // max(n_blocks, cluster-kernel waves)
   int64_t N;
   int64_t n_blocks;
   // Cluster kernel: 8 consecutive sorted atoms of one (x, y) column form a cluster.
-  int32_t *col_nclu;       // [n_columns] clusters per column
   int32_t *col_clu_start;  // [n_columns + 1] first cluster of each column (global)
-  int4 *clusters;          // [n_clusters_max] first sorted atom, atom count, global column, system
-  uint4 *clu_ctr;          // [n_clusters_max] bounding-box centre (fixed point)
-  uint4 *clu_half;         // [n_clusters_max] bounding-box half extent (fixed-point units)
+  double4 *part;           // [split][N] per-wave shares of each sorted atom's force and energy (or dE/dq)
   int64_t n_columns;
   int64_t n_clusters_max;
-  int32_t *scan_tmp;       // [2 kMaxFusedGrid + 2] block sums of the single-launch build
 };
 
 // Per-call constants and outputs of the pair kernels.
@@ -143,8 +138,8 @@ hipError_t launch_energy(const Plan &plan, const Dev &d, const nb_system *sys, d
 hipError_t launch_backward(const Plan &plan, const Dev &d, const nb_system *sys,
                            const double *grad_energy, double *grad_pos, double *grad_charge,
                            double *grad_sigma, double *grad_eps, hipStream_t s);
-// Cluster pair kernel (nb_pair_cluster.hip): one wave per 8-atom cluster.
-void launch_cluster_pair(const Plan &plan, const Dev &d, const Consts &c, const Out &o, int mode,
-                         hipStream_t s);
+// Cluster pair kernel and its finishing pass (nb_pair_cluster.hip).
+void launch_cluster_pair(const Plan &plan, const Dev &d, const Consts &c, const Out &o, int mode, hipStream_t s,
+                         double *energy, double *virial, const double *eps, double *grad_sigma, double *grad_eps);
 
 }  // namespace nb

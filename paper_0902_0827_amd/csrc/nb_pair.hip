@@ -336,10 +336,6 @@ Out base_out(const nb_system *sys) {
 template <int MODE>
 void launch_pair(const Plan &p, const Dev &d, const Out &o, hipStream_t s) {
   const Consts c = make_consts(p);
-  if (uses_clusters(p.kernel)) {
-    launch_cluster_pair(p, d, c, o, MODE, s);
-    return;
-  }
   if (p.n_blocks == 0) return;
   if (p.precision == NB_FP64)
     hipLaunchKernelGGL((k_pair_atom<true, MODE>), dim3(static_cast<unsigned>(p.n_blocks)), dim3(kBlock), 0, s, d, c, o);
@@ -355,6 +351,10 @@ hipError_t launch_forces(const Plan &p, const Dev &d, const nb_system *sys, doub
   o.force = force;
   o.want_part = (energy || virial) ? 1 : 0;
   o.want_virial = virial ? 1 : 0;
+  if (uses_clusters(p.kernel)) {
+    launch_cluster_pair(p, d, make_consts(p), o, kForces, s, energy, virial, nullptr, nullptr, nullptr);
+    return hipGetLastError();
+  }
   launch_pair<kForces>(p, d, o, s);
   if (o.want_part) {
     const int cl = uses_clusters(p.kernel) ? 1 : 0;
@@ -369,6 +369,10 @@ hipError_t launch_energy(const Plan &p, const Dev &d, const nb_system *sys, doub
   Out o = base_out(sys);
   o.atom_energy = atom_energy;
   o.want_part = 1;
+  if (uses_clusters(p.kernel)) {
+    launch_cluster_pair(p, d, make_consts(p), o, kEnergy, s, energy, nullptr, nullptr, nullptr, nullptr);
+    return hipGetLastError();
+  }
   launch_pair<kEnergy>(p, d, o, s);
   hipLaunchKernelGGL(k_reduce_sys<1>, dim3(p.B), dim3(kReduceBlock), 0, s, d, energy, static_cast<double *>(nullptr),
                      uses_clusters(p.kernel) ? 1 : 0);
@@ -382,6 +386,10 @@ hipError_t launch_backward(const Plan &p, const Dev &d, const nb_system *sys, co
   o.grad_pos = grad_pos;
   o.grad_charge = grad_charge;
   o.grad_energy = grad_energy;
+  if (uses_clusters(p.kernel)) {
+    launch_cluster_pair(p, d, make_consts(p), o, kAdjoint, s, nullptr, nullptr, sys->lj_eps, grad_sigma, grad_eps);
+    return hipGetLastError();
+  }
   launch_pair<kAdjoint>(p, d, o, s);
   if (grad_sigma || grad_eps)
     hipLaunchKernelGGL(k_reduce_types, dim3(2 * p.T), dim3(kBlock), 0, s, d, sys->lj_eps, grad_sigma, grad_eps,

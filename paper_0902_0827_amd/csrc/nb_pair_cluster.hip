@@ -1,26 +1,29 @@
-// Cluster pair kernel: one wave (one 64-lane workgroup) per i-cluster of up to 8
-// consecutive sorted atoms of one (x, y) column; lane = (ii, jj) = (lane / 8, lane % 8).
+// Cluster pair kernel: waves own i-clusters of up to K consecutive sorted atoms of
+// one (x, y) column (K = 4 or 8); lane = (ii, jj) = (lane / J, lane % J), J = 64 / K.
 //
 // The paper's kernel (section 3) processes one cell per thread block and stages
 // every cell within R into shared memory, one thread per i atom.  Here, for a
-// 64-wide wavefront and ~10 atoms per cell, the wave instead owns 8 i atoms and
+// 64-wide wavefront and ~10 atoms per cell, a wave instead owns K i atoms and
 // streams the j atoms of the neighbouring columns:
 //
 //   1. stage: the atoms of each neighbouring column's z-window are read 64 at a
-//      time (coalesced), each tested against the i-cluster's bounding box; the
-//      survivors (those within R of the box) are compacted, ballot + mbcnt, into a
-//      ring buffer in LDS;
-//   2. pairs: whenever the ring holds 8 atoms, each lane evaluates the pair
+//      time (coalesced; the next chunk's loads are issued before the current one
+//      is used), each tested against the i-cluster's bounding box; the survivors
+//      (those within R of the box) are compacted, ballot + mbcnt, into a ring
+//      buffer in LDS;
+//   2. pairs: whenever the ring holds J atoms, each lane evaluates the pair
 //      (i atom ii, j atom jj), so all 64 lanes work on candidates that passed the
-//      box test (about 40% of them are inside R, against ~25% for a plain cell
-//      stencil);
-//   3. each row of 8 lanes accumulates its i atom's force, energy, virial (and
-//      adjoint sums) in registers; rows are reduced with cross-lane shuffles at
-//      the end.  Every atom's sums live in one wave: no atomics, deterministic.
+//      box test (on the 23.6k-atom box about 60% of them are inside R for K = 4,
+//      48% for K = 8, against ~25% for a plain cell stencil);
+//   3. each row of J lanes accumulates its i atom's sums in registers; rows are
+//      reduced with cross-lane shuffles at the end.
 //
+// A cluster's neighbour columns may be split over S waves (S = 1..4), which gives
+// the GPU S times more, shorter waves to interleave; each wave writes its part of
+// every atom's sums to its own slot, and k_finish adds the S parts in a fixed order,
+// converts to the caller's atom order and reduces energies, virials and per-type
+// sums.  Nothing is accumulated with atomics: results are deterministic.
 // Full shell (every pair is evaluated from both sides), as in the paper.
-#include <type_traits>
-
 #include "nb_pair_common.h"
 #include "nb_pair_math.h"
 
@@ -28,12 +31,12 @@ namespace nb {
 
 namespace {
 
-constexpr int kRing = 128;    // ring buffer of staged j atoms (power of two)
-constexpr int kTabLds = 16;   // type tables up to 16 x 16 are copied to LDS
-constexpr int kFlush = 32;    // groups between single -> double flushes of the sums
-constexpr int kXcds = 8;      // MI355X: 8 accelerator complex dies, each with its own L2
+constexpr int kRing = 128;           // ring buffer of staged j atoms (power of two)
+constexpr int kTabLds = 16;          // type tables up to 16 x 16 are copied to LDS
+constexpr int kFlush = 32;           // groups between single -> double flushes of the sums
+constexpr int kXcds = 8;             // MI355X: 8 accelerator complex dies, each with its own L2
 constexpr int kMaxRuns = 2 * 9 * 9;  // up to 9 x 9 neighbour columns, <= 2 z-runs each
-constexpr int kRowQ = 32;     // per-row queue of in-cutoff pairs (row-compacted variant)
+constexpr int kFinishBlock = 256;
 
 __device__ __forceinline__ uint32_t uabs_diff(uint32_t a, uint32_t b) {
   const int32_t d = static_cast<int32_t>(a - b);
@@ -42,12 +45,65 @@ __device__ __forceinline__ uint32_t uabs_diff(uint32_t a, uint32_t b) {
 
 // Squared distance (A^2, single precision) from a fixed-point point to a box given
 // by centre and half extents, with minimum image per dimension.
-__device__ __forceinline__ float box_dist2(const uint4 &p, const uint4 &ctr, const uint4 &half, const SysDesc &sd) {
+__device__ __forceinline__ float box_dist2(const uint4 &p, const uint4 &ctr, const uint4 &half, float s2x, float s2y,
+                                           float s2z) {
   const uint32_t ax = uabs_diff(p.x, ctr.x), ay = uabs_diff(p.y, ctr.y), az = uabs_diff(p.z, ctr.z);
   const float ex = static_cast<float>(ax > half.x ? ax - half.x : 0u);
   const float ey = static_cast<float>(ay > half.y ? ay - half.y : 0u);
   const float ez = static_cast<float>(az > half.z ? az - half.z : 0u);
-  return fmaf(sd.scale2f[2] * ez, ez, fmaf(sd.scale2f[1] * ey, ey, sd.scale2f[0] * ex * ex));
+  return fmaf(s2z * ez, ez, fmaf(s2y * ey, ey, s2x * ex * ex));
+}
+
+// Wave-uniform copies (scalar registers) of values read from memory.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ double uni(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(b)));
+  const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(b >> 32)));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15) (gfx9 encoding): every vector-memory load
+// issued so far has returned.
+__device__ __forceinline__ void wait_vm_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Min / max over the rows (lanes J apart) and sum over a row's J lanes.
+template <int J>
+__device__ __forceinline__ int shfl_rows_min(int v) {
+  for (int off = J; off < 64; off <<= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+template <int J>
+__device__ __forceinline__ int shfl_rows_max(int v) {
+  for (int off = J; off < 64; off <<= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+template <int J>
+__device__ __forceinline__ double row_sum(double v) {
+  for (int off = 1; off < J; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Index of the last column whose first cluster is <= k: a 64-way search, each lane
+// probing one position per round (two or three rounds for any practical grid).
+__device__ __forceinline__ int cluster_column(const int32_t *__restrict__ col_clu_start, int n_columns, int k) {
+  int lo = 0, hi = n_columns - 1;  // answer in [lo, hi]
+  const int lane = threadIdx.x & 63;
+  while (hi > lo) {
+    const int span = hi - lo + 1;
+    const int step = (span + 63) >> 6;
+    const int probe = lo + lane * step;
+    const bool le = probe <= hi && col_clu_start[probe] <= k;
+    const uint64_t m = __ballot(le);
+    const int last = 63 - __clzll(static_cast<long long>(m));  // lane 0 always passes
+    lo = lo + last * step;
+    const int nhi = lo + step - 1;
+    hi = nhi < hi ? nhi : hi;
+  }
+  return lo;
 }
 
 template <bool F64>
@@ -55,8 +111,8 @@ struct RingLds;
 
 template <>
 struct RingLds<false> {
-  uint4 fix[kRing];    // fixed-point x, y, z, original index
-  float2 qt[kRing];    // q * sqrt(k_e), type (as int bits)
+  uint4 fix[kRing];  // fixed-point x, y, z, original index
+  float2 qt[kRing];  // q * sqrt(k_e), type (as int bits)
   TypePair32 tab[kTabLds * kTabLds];
   int2 runs[kMaxRuns];
 };
@@ -69,30 +125,22 @@ struct RingLds<true> {
   int2 runs[kMaxRuns];
 };
 
-// Row queues of the row-compacted variant: for each of the 8 i atoms, the pairs
-// found inside the cutoff (displacement in fixed-point units, r^2, q'_j, type).
-struct RowQLds {
-  float4 d[8][kRowQ];
-  float2 qt[8][kRowQ];
-};
-struct NoRowQ {};
-
-template <bool F64, int MODE, bool TABLDS, bool ROWQ>
-__global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
-  static_assert(!(F64 && ROWQ), "row compaction is built for the single-precision path");
+template <bool F64, int MODE, bool TABLDS, int K>
+__global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int S) {
+  constexpr int J = 64 / K;  // j atoms per group (lanes per row)
   __shared__ RingLds<F64> L;
-  __shared__ typename std::conditional<ROWQ, RowQLds, NoRowQ>::type RQ;
   // Workgroups are dealt to the 8 XCDs round robin; give each XCD a contiguous
-  // range of clusters (neighbouring columns) so that its L2 holds their j atoms.
+  // range of waves (neighbouring clusters) so that its L2 holds their j atoms.
   const int per_xcd = static_cast<int>(gridDim.x) / kXcds;
-  const int I = static_cast<int>(blockIdx.x % kXcds) * per_xcd + static_cast<int>(blockIdx.x / kXcds);
+  const int w = static_cast<int>(blockIdx.x % kXcds) * per_xcd + static_cast<int>(blockIdx.x / kXcds);
   if (!built_for(d.status, d.N, true)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(d.status, NB_STATUS_NOT_BUILT);
     return;
   }
   const int n_clu = d.col_clu_start[d.n_columns];
+  const int I = w / S, part = w - (w / S) * S;
   if (I >= n_clu) return;  // the grid is sized by an upper bound on the cluster count
-  const int lane = threadIdx.x, ii = lane >> 3, jj = lane & 7;
+  const int lane = threadIdx.x, ii = lane / J, jj = lane % J;
   const int T = d.T;
   if constexpr (TABLDS) {
     for (int k = lane; k < T * T; k += 64) {
@@ -101,12 +149,34 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
     }
   }
 
-  const int4 rec = d.clusters[I];  // first atom, count, global column, system
-  const SysDesc &sd = d.desc[rec.w];
-  const uint4 ctr = d.clu_ctr[I], half = d.clu_half[I];
-  const int i = rec.x + ii;
-  const bool ivalid = ii < rec.y;
-  const int ia = ivalid ? i : rec.x;
+  // The cluster: its column, system, and atoms.
+  const int col = cluster_column(d.col_clu_start, static_cast<int>(d.n_columns), I);
+  int sys = 0;
+  {
+    int lo = 0, hi = d.B - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (d.desc[mid].col_begin <= col) lo = mid; else hi = mid - 1;
+    }
+    sys = lo;
+  }
+  const SysDesc &sd = d.desc[sys];
+  // Per-system constants as wave-uniform scalars: nothing in the pair loop below then
+  // waits on a vector-memory load (so the next chunk's loads stay in flight).
+  const float s2x = uni(sd.scale2f[0]), s2y = uni(sd.scale2f[1]), s2z = uni(sd.scale2f[2]);
+  const double bxx = uni(sd.box[0]), bxy = uni(sd.box[1]), bxz = uni(sd.box[2]);
+  const double ibx = uni(sd.inv_box[0]), iby = uni(sd.inv_box[1]), ibz = uni(sd.inv_box[2]);
+  const int atom_begin = uni(sd.atom_begin);
+  const int nx = uni(sd.dims[0]), ny = uni(sd.dims[1]), nz = uni(sd.dims[2]);
+  const int col_local = col - uni(sd.col_begin);
+  const int cell_begin = uni(sd.cell_begin);
+  const int cb0 = cell_begin + col_local * nz;
+  const int first = d.cell_start[cb0] + K * (I - d.col_clu_start[col]);
+  const int left = d.cell_start[cb0 + nz] - first;
+  const int count = left < K ? left : K;
+  const int i = first + ii;
+  const bool ivalid = ii < count;
+  const int ia = ivalid ? i : first;
   const uint4 fi = d.s_fix[ia];
   const int oi = static_cast<int>(fi.w);
   const uint4 mask_i = d.excl_mask[oi];
@@ -118,12 +188,32 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
   else qi32 = d.s_q32[ia];
   const double qi64 = F64 ? pi64.w * c.ke : 0.0;
 
-  const int nx = sd.dims[0], ny = sd.dims[1], nz = sd.dims[2];
-  const int kx = sd.reach[0], ky = sd.reach[1], kz = sd.reach[2];
-  const int col_local = rec.z - sd.col_begin;
+  // Bounding box of the cluster, relative to its first atom (minimum image).
+  uint4 ctr, half;
+  {
+    const uint4 u0 = make_uint4(__shfl(fi.x, 0, 64), __shfl(fi.y, 0, 64), __shfl(fi.z, 0, 64), 0u);
+    const int dx = static_cast<int>(fi.x - u0.x), dy = static_cast<int>(fi.y - u0.y),
+              dz = static_cast<int>(fi.z - u0.z);
+    // rows without an atom repeat the first atom (ia = first), so they do not widen the box
+    const int lox = shfl_rows_min<J>(dx), loy = shfl_rows_min<J>(dy), loz = shfl_rows_min<J>(dz);
+    const int hix = shfl_rows_max<J>(dx), hiy = shfl_rows_max<J>(dy), hiz = shfl_rows_max<J>(dz);
+    const int lo3[3] = {lox, loy, loz}, hi3[3] = {hix, hiy, hiz};
+    const uint32_t base[3] = {u0.x, u0.y, u0.z};
+    uint32_t cc[3], hh[3];
+    for (int a = 0; a < 3; ++a) {
+      const int64_t mid = (static_cast<int64_t>(lo3[a]) + hi3[a]) >> 1;  // floor
+      const int64_t h = (hi3[a] - mid) > (mid - lo3[a]) ? (hi3[a] - mid) : (mid - lo3[a]);
+      cc[a] = base[a] + static_cast<uint32_t>(static_cast<int32_t>(mid));
+      hh[a] = static_cast<uint32_t>(h);
+    }
+    ctr = make_uint4(cc[0], cc[1], cc[2], 0u);
+    half = make_uint4(hh[0], hh[1], hh[2], 0u);
+  }
+
+  const int kx = uni(sd.reach[0]), ky = uni(sd.reach[1]), kz = uni(sd.reach[2]);
   const int cx = col_local / ny, cy = col_local - (col_local / ny) * ny;
-  const int cz0 = static_cast<int>((static_cast<uint64_t>(d.s_fix[rec.x].z) * nz) >> 32);
-  const int cz1 = static_cast<int>((static_cast<uint64_t>(d.s_fix[rec.x + rec.y - 1].z) * nz) >> 32);
+  const int cz0 = static_cast<int>((static_cast<uint64_t>(d.s_fix[first].z) * nz) >> 32);
+  const int cz1 = static_cast<int>((static_cast<uint64_t>(d.s_fix[first + count - 1].z) * nz) >> 32);
   const bool allx = 2 * kx + 1 >= nx, ally = 2 * ky + 1 >= ny;
   const bool allz = (cz1 - cz0) + 2 * kz + 1 >= nz;
   const int xn = allx ? nx : 2 * kx + 1, yn = ally ? ny : 2 * ky + 1;
@@ -147,56 +237,7 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
 
   uint32_t head = 0, tail = 0;  // wave-uniform ring positions
 
-  // Single-precision pair terms for row ii's atom, added to the lane's sums.  With
-  // v false every contribution is exactly zero (no branch: the lanes stay converged).
-  auto accum32 = [&](float r2f, float dxf, float dyf, float dzf, float qj, int tj, bool v) {
-    if constexpr (!F64) {
-      TypePair32 tp;
-      const int tjv = v ? tj : 0;
-      if constexpr (TABLDS) tp = L.tab[ti * T + tjv];
-      else tp = d.tab32[ti * T + tjv];
-      const float qjv = v ? qj : 0.f;
-      const PairF32 p = pair_f32(v ? r2f : 1.0f, v ? tp.c6 : 0.f, v ? tp.c12 : 0.f, qi32 * qjv, c.betaf,
-                                 c.two_beta_sqrtpif, c.mb2l2e);
-      sen += p.u_lj + p.u_c;
-      if constexpr (MODE != kEnergy) {
-        const float ex = v ? dxf : 0.f, ey = v ? dyf : 0.f, ez = v ? dzf : 0.f;
-        const float gx = p.f * ex, gy = p.f * ey, gz = p.f * ez;
-        sfx += gx;
-        sfy += gy;
-        sfz += gz;
-        if constexpr (MODE == kForces) {
-          if (o.want_virial) {
-            swxx = fmaf(gx, ex, swxx); swxy = fmaf(gx, ey, swxy); swxz = fmaf(gx, ez, swxz);
-            swyy = fmaf(gy, ey, swyy); swyz = fmaf(gy, ez, swyz); swzz = fmaf(gz, ez, swzz);
-          }
-        }
-      }
-      if constexpr (MODE == kAdjoint) {
-        sphi = fmaf(qjv, p.erfc_over_r, sphi);
-        sasig = fmaf(p.dudsig_lj, tp.inv_sig, sasig);
-        sbeps += p.u_lj;
-      }
-    }
-  };
-
-  // Row queues (row-compacted variant): per-lane copies of row ii's head and count.
-  int rstart = 0, rcount = 0;
-  auto round = [&]() {  // one pair per lane from its row's queue
-    if constexpr (ROWQ) {
-      const int avail = rcount < 8 ? rcount : 8;
-      const bool v = jj < avail;
-      const int q = (rstart + jj) & (kRowQ - 1);
-      const float4 e = RQ.d[ii][q];
-      const float2 qt = RQ.qt[ii][q];
-      accum32(e.w, e.x, e.y, e.z, qt.x, __float_as_int(qt.y), v);
-      rstart += avail;
-      rcount -= avail;
-      if (++groups >= kFlush) flush();
-    }
-  };
-
-  // Evaluate pair (row ii's atom, ring entry head + jj) for navail <= 8 entries.
+  // Evaluate pair (row ii's atom, ring entry head + jj) for navail <= J entries.
   auto process_group = [&](int navail) {
     const int slot = static_cast<int>((head + jj) & (kRing - 1));
     const bool jv = jj < navail;
@@ -219,9 +260,9 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
       dxd = pi64.x - pj64.x;
       dyd = pi64.y - pj64.y;
       dzd = pi64.z - pj64.z;
-      dxd -= sd.box[0] * rint(dxd * sd.inv_box[0]);
-      dyd -= sd.box[1] * rint(dyd * sd.inv_box[1]);
-      dzd -= sd.box[2] * rint(dzd * sd.inv_box[2]);
+      dxd -= bxx * rint(dxd * ibx);
+      dyd -= bxy * rint(dyd * iby);
+      dzd -= bxz * rint(dzd * ibz);
       r2d = dxd * dxd + dyd * dyd + dzd * dzd;
       hit = ivalid && jv && r2d < c.rc2 && oi != oj;
     } else {
@@ -230,13 +271,13 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
       dxf = static_cast<float>(static_cast<int>(fi.x - fj.x));
       dyf = static_cast<float>(static_cast<int>(fi.y - fj.y));
       dzf = static_cast<float>(static_cast<int>(fi.z - fj.z));
-      r2f = fmaf(sd.scale2f[2] * dzf, dzf, fmaf(sd.scale2f[1] * dyf, dyf, sd.scale2f[0] * dxf * dxf));
+      r2f = fmaf(s2z * dzf, dzf, fmaf(s2y * dyf, dyf, s2x * dxf * dxf));
       hit = ivalid && jv && r2f < c.rc2f && oi != oj;
     }
     const int delta = oj - oi;
     const bool check = hit && (static_cast<unsigned>(delta + kWindow) <= 2u * kWindow || far_i);
     if (__ballot(check)) {
-      if (check && pair_excluded(mask_i, far_i, oi, oj, sd.atom_begin, d.excl_far, o.excl_off, o.excl_idx))
+      if (check && pair_excluded(mask_i, far_i, oi, oj, atom_begin, d.excl_far, o.excl_off, o.excl_idx))
         hit = false;
     }
     if (hit) {
@@ -262,35 +303,33 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
           asig += p.dudsig_lj * tp.inv_sig;
           beps += p.u_lj;
         }
-      } else if constexpr (!ROWQ) {
-        accum32(r2f, dxf, dyf, dzf, qj, tj, true);
-      }
-    }
-    if constexpr (ROWQ) {
-      // Compact this group's in-cutoff pairs into the rows' queues ...
-      const uint64_t hm = __ballot(hit);
-      const uint32_t rowbits = static_cast<uint32_t>(hm >> (8 * ii)) & 0xFFu;
-      const int before = __popc(rowbits & ((1u << jj) - 1u));
-      if (hit) {
-        const int q = (rstart + rcount + before) & (kRowQ - 1);
-        RQ.d[ii][q] = make_float4(dxf, dyf, dzf, r2f);
-        RQ.qt[ii][q] = make_float2(qj, __int_as_float(tj));
-      }
-      rcount += __popc(rowbits);
-      // ... and evaluate 8 per row once every row with an atom has 8, or when a
-      // queue could not take another group.
-      for (;;) {
-        const bool overfull = __ballot(rcount > kRowQ - 8) != 0;
-        const bool waiting = __ballot(ivalid && rcount < 8) != 0;
-        if ((!overfull && waiting) || __ballot(rcount > 0) == 0) break;
-        __syncthreads();
-        round();
+      } else {
+        TypePair32 tp;
+        if constexpr (TABLDS) tp = L.tab[ti * T + tj];
+        else tp = d.tab32[ti * T + tj];
+        const PairF32 p = pair_f32(r2f, tp.c6, tp.c12, qi32 * qj, c.betaf, c.two_beta_sqrtpif, c.mb2l2e);
+        sen += p.u_lj + p.u_c;
+        if constexpr (MODE != kEnergy) {
+          const float gx = p.f * dxf, gy = p.f * dyf, gz = p.f * dzf;
+          sfx += gx;
+          sfy += gy;
+          sfz += gz;
+          if constexpr (MODE == kForces) {
+            if (o.want_virial) {
+              swxx = fmaf(gx, dxf, swxx); swxy = fmaf(gx, dyf, swxy); swxz = fmaf(gx, dzf, swxz);
+              swyy = fmaf(gy, dyf, swyy); swyz = fmaf(gy, dzf, swyz); swzz = fmaf(gz, dzf, swzz);
+            }
+          }
+        }
+        if constexpr (MODE == kAdjoint) {
+          sphi = fmaf(qj, p.erfc_over_r, sphi);
+          sasig = fmaf(p.dudsig_lj, tp.inv_sig, sasig);
+          sbeps += p.u_lj;
+        }
       }
     }
     head += static_cast<uint32_t>(navail);
-    if constexpr (!ROWQ) {
-      if (++groups >= kFlush) flush();
-    }
+    if (++groups >= kFlush) flush();
   };
 
   // Neighbour-column windows as runs [a0, a1) of sorted atoms, two slots per column
@@ -302,7 +341,7 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
     x += x < 0 ? nx : (x >= nx ? -nx : 0);
     int y = ally ? oy : cy - ky + oy;
     y += y < 0 ? ny : (y >= ny ? -ny : 0);
-    const int cb = sd.cell_begin + (x * ny + y) * nz;
+    const int cb = cell_begin + (x * ny + y) * nz;
     int2 r0, r1 = make_int2(0, 0);
     if (allz) {
       r0 = make_int2(d.cell_start[cb], d.cell_start[cb + nz]);
@@ -322,13 +361,14 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
     L.runs[2 * k + 1] = r1;
   }
   __syncthreads();
-  const int nruns = 2 * ncol;
+  // This wave's share of the runs.
+  const int r_begin = (2 * ncol * part) / S, r_end = (2 * ncol * (part + 1)) / S;
 
   // Walk the runs 64 atoms at a time; the next chunk's loads are issued before the
   // current chunk is filtered and evaluated, to hide their latency.
   int base = 0, end = 0;
   auto seek = [&](int rr) {  // first non-empty run at or after rr; sets base/end
-    while (rr < nruns) {
+    while (rr < r_end) {
       const int2 q = L.runs[rr];
       if (q.x < q.y) {
         base = q.x;
@@ -353,9 +393,10 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
   float qj = 0.f;
   double4 pj64 = make_double4(0, 0, 0, 0);
   bool valid = false;
-  int r = seek(0);
-  if (r < nruns) load(base, end, fj, tj, qj, pj64, valid);
-  while (r < nruns) {
+  wait_vm_loads();  // the cluster's own data has arrived before the pair loop starts
+  int r = seek(r_begin);
+  if (r < r_end) load(base, end, fj, tj, qj, pj64, valid);
+  while (r < r_end) {
     int nr = r;
     if (base + 64 < end) base += 64;
     else nr = seek(r + 1);
@@ -364,10 +405,10 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
     float qj_n = qj;
     double4 pj64_n = pj64;
     bool valid_n = false;
-    if (nr < nruns) load(base, end, fj_n, tj_n, qj_n, pj64_n, valid_n);
+    if (nr < r_end) load(base, end, fj_n, tj_n, qj_n, pj64_n, valid_n);
 
     // Box filter, then compact the survivors into the ring.
-    const bool keep = valid && box_dist2(fj, ctr, half, sd) < c.rc2_box;
+    const bool keep = valid && box_dist2(fj, ctr, half, s2x, s2y, s2z) < c.rc2_box;
     const uint64_t m = __ballot(keep);
     const uint32_t below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
                                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
@@ -384,7 +425,7 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
     }
     __syncthreads();
     tail += static_cast<uint32_t>(__popcll(m));
-    while (tail - head >= 8u) process_group(8);
+    while (tail - head >= static_cast<uint32_t>(J)) process_group(J);
 
     r = nr;
     fj = fj_n;
@@ -394,12 +435,6 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
     valid = valid_n;
   }
   if (tail != head) process_group(static_cast<int>(tail - head));
-  if constexpr (ROWQ) {
-    while (__ballot(rcount > 0)) {
-      __syncthreads();
-      round();
-    }
-  }
   flush();
 
   if constexpr (!F64) {
@@ -414,7 +449,7 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
     phi *= c.ke;
   }
 
-  // Partial sums of the whole cluster (before the row reduction: a plain wave sum).
+  // Energy / virial sums of this wave (a plain wave sum, before the row reduction).
   if constexpr (MODE == kForces || MODE == kEnergy) {
     if (o.want_part) {
       const double v[kPart] = {0.5 * en, 0.5 * wxx, 0.5 * wxy, 0.5 * wxz, 0.5 * wxy, 0.5 * wyy,
@@ -425,46 +460,18 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
         const double s = wave_sum(v[k]);
         if (lane == k) mine = s;
       }
-      if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + I] = lane < nv ? mine : 0.0;
+      if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + w] = lane < nv ? mine : 0.0;
     }
-  }
-
-  // Per-atom results: reduce each row over its 8 lanes.
-  if constexpr (MODE == kForces) {
-    fx = row8_sum(fx);
-    fy = row8_sum(fy);
-    fz = row8_sum(fz);
-    if (jj == 0 && ivalid) {
-      o.force[3 * oi + 0] = fx;
-      o.force[3 * oi + 1] = fy;
-      o.force[3 * oi + 2] = fz;
-    }
-  }
-  if constexpr (MODE == kEnergy) {
-    en = row8_sum(en);
-    if (jj == 0 && ivalid && o.atom_energy) o.atom_energy[oi] = 0.5 * en;
   }
   if constexpr (MODE == kAdjoint) {
-    const double g = o.grad_energy[rec.w];
-    fx = row8_sum(fx);
-    fy = row8_sum(fy);
-    fz = row8_sum(fz);
-    phi = row8_sum(phi);
-    if (jj == 0 && ivalid) {
-      if (o.grad_pos) {
-        o.grad_pos[3 * oi + 0] = -g * fx;
-        o.grad_pos[3 * oi + 1] = -g * fy;
-        o.grad_pos[3 * oi + 2] = -g * fz;
-      }
-      if (o.grad_charge) o.grad_charge[oi] = g * phi;
-    }
-    // Per-type sums of the sigma / eps partials over the cluster's atoms.
-    const double a_l = 0.5 * g * asig, b_l = 0.5 * g * beps;
+    // Per-type sums of the sigma / eps partials over this wave's rows (scaled by the
+    // system's grad_energy in k_finish).
+    const double a_l = 0.5 * asig, b_l = 0.5 * beps;
     const int my_t = ivalid ? ti : -1;
     double keep_a = 0.0, keep_b = 0.0;
-    uint64_t left = __ballot(my_t >= 0);
-    while (left) {
-      const int lead = __ffsll(static_cast<unsigned long long>(left)) - 1;
+    uint64_t left_t = __ballot(my_t >= 0);
+    while (left_t) {
+      const int lead = __ffsll(static_cast<unsigned long long>(left_t)) - 1;
       const int tt = __shfl(my_t, lead, 64);
       const bool mine = my_t == tt;
       const double sa = wave_sum(mine ? a_l : 0.0);
@@ -473,43 +480,208 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o) {
         keep_a = sa;
         keep_b = sb;
       }
-      left &= ~__ballot(mine);
+      left_t &= ~__ballot(mine);
     }
     if (lane < T) {
-      d.adj_partials[static_cast<int64_t>(lane) * d.n_slots + I] = keep_a;
-      d.adj_partials[static_cast<int64_t>(T + lane) * d.n_slots + I] = keep_b;
+      d.adj_partials[static_cast<int64_t>(lane) * d.n_slots + w] = keep_a;
+      d.adj_partials[static_cast<int64_t>(T + lane) * d.n_slots + w] = keep_b;
     }
   }
+
+  // Per-atom sums of this wave's share: rows reduced over their J lanes.
+  fx = row_sum<J>(fx);
+  fy = row_sum<J>(fy);
+  fz = row_sum<J>(fz);
+  const double w4 = row_sum<J>(MODE == kAdjoint ? phi : en);
+  if (jj == 0 && ivalid) d.part[static_cast<int64_t>(part) * d.N + i] = make_double4(fx, fy, fz, w4);
+}
+
+// Energy (and virial) of system b: sum of the wave slots [lo, hi), in a fixed order.
+// Loads are unconditional (indices clamped) so that a thread's loads are all in flight.
+template <int NV>
+__device__ inline void sum_slots(const Dev &d, int64_t lo, int64_t hi, double *energy, double *virial, int b,
+                                 double (*lds)[kPart]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int kUnroll = 4;
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  for (int64_t q0 = lo + threadIdx.x; q0 < hi; q0 += kUnroll * kFinishBlock) {
+    double v[kUnroll][NV];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t q = q0 + u * kFinishBlock;
+      const int64_t qq = q < hi ? q : lo;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[u][k] = d.partials[static_cast<int64_t>(k) * d.n_slots + qq];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const bool in = q0 + u * kFinishBlock < hi;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) acc[k] += in ? v[u][k] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double s = wave_sum(acc[k]);
+    if (lane == 0) lds[wave][k] = s;
+  }
+  __syncthreads();
+  if (static_cast<int>(threadIdx.x) < NV) {
+    double s = 0.0;
+    for (int wv = 0; wv < kFinishBlock / 64; ++wv) s += lds[wv][threadIdx.x];
+    if (threadIdx.x == 0) {
+      if (energy) energy[b] = s;
+    } else if (virial) {
+      virial[9 * b + (threadIdx.x - 1)] = s;
+    }
+  }
+}
+
+// Per-atom outputs (sum of the S parts, in order), per-system energy / virial and
+// per-type gradients, in one launch: blocks [0, nA) take atoms, the next B blocks
+// take systems, the last 2T blocks (adjoint only) take types.
+template <int MODE>
+__global__ void __launch_bounds__(kFinishBlock) k_finish(Dev d, Out o, int S, int nA, double *energy, double *virial,
+                                                        int nv, const double *__restrict__ eps, double *grad_sigma,
+                                                        double *grad_eps) {
+  __shared__ double lds[kFinishBlock / 64][kPart];
+  if (!built_for(d.status, d.N, true)) return;
+  const int blk = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (blk < nA) {
+    const int i = blk * kFinishBlock + threadIdx.x;
+    if (i >= d.N) return;
+    double4 s = d.part[i];
+    for (int p = 1; p < S; ++p) {
+      const double4 q = d.part[static_cast<int64_t>(p) * d.N + i];
+      s.x += q.x;
+      s.y += q.y;
+      s.z += q.z;
+      s.w += q.w;
+    }
+    const int oi = static_cast<int>(d.s_fix[i].w);
+    if constexpr (MODE == kForces) {
+      o.force[3 * oi + 0] = s.x;
+      o.force[3 * oi + 1] = s.y;
+      o.force[3 * oi + 2] = s.z;
+    } else if constexpr (MODE == kEnergy) {
+      if (o.atom_energy) o.atom_energy[oi] = 0.5 * s.w;
+    } else {
+      int lo = 0, hi = d.B - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d.desc[mid].atom_begin <= i) lo = mid; else hi = mid - 1;
+      }
+      const double g = o.grad_energy[lo];
+      if (o.grad_pos) {
+        o.grad_pos[3 * oi + 0] = -g * s.x;
+        o.grad_pos[3 * oi + 1] = -g * s.y;
+        o.grad_pos[3 * oi + 2] = -g * s.z;
+      }
+      if (o.grad_charge) o.grad_charge[oi] = g * s.w;
+    }
+    return;
+  }
+  if (blk < nA + d.B) {
+    if (MODE == kAdjoint || nv == 0) return;
+    const int b = blk - nA;
+    const SysDesc &sd = d.desc[b];
+    const int64_t lo = static_cast<int64_t>(d.col_clu_start[sd.col_begin]) * S;
+    const int64_t hi = static_cast<int64_t>(d.col_clu_start[sd.col_begin + sd.dims[0] * sd.dims[1]]) * S;
+    if (nv == kPart) sum_slots<kPart>(d, lo, hi, energy, virial, b, lds);
+    else sum_slots<1>(d, lo, hi, energy, virial, b, lds);
+    return;
+  }
+  if constexpr (MODE == kAdjoint) {
+    // One (sigma or eps, type) entry: sum over every wave slot of every system,
+    // each scaled by its system's grad_energy.
+    const int T = d.T;
+    const int t = blk - nA - d.B;
+    if (t >= 2 * T) return;
+    double acc = 0.0;
+    for (int b = 0; b < d.B; ++b) {
+      const SysDesc &sd = d.desc[b];
+      const int64_t lo = static_cast<int64_t>(d.col_clu_start[sd.col_begin]) * S;
+      const int64_t hi = static_cast<int64_t>(d.col_clu_start[sd.col_begin + sd.dims[0] * sd.dims[1]]) * S;
+      double s = 0.0;
+      for (int64_t q0 = lo + threadIdx.x; q0 < hi; q0 += 4 * kFinishBlock) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t q = q0 + u * kFinishBlock;
+          v[u] = d.adj_partials[static_cast<int64_t>(t) * d.n_slots + (q < hi ? q : lo)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s += q0 + u * kFinishBlock < hi ? v[u] : 0.0;
+      }
+      acc += o.grad_energy[b] * s;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) lds[wave][0] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int wv = 0; wv < kFinishBlock / 64; ++wv) s += lds[wv][0];
+      if (t < T) {
+        if (grad_sigma) grad_sigma[t] = s;
+      } else if (grad_eps) {
+        grad_eps[t - T] = eps[t - T] > 0.0 ? s / eps[t - T] : 0.0;
+      }
+    }
+  }
+}
+
+template <bool F64, bool TABLDS, int K>
+void launch_cluster_mode(int mode, dim3 grid, hipStream_t s, const Dev &d, const Consts &c, const Out &o, int S) {
+  if (mode == kForces)
+    hipLaunchKernelGGL((k_pair_cluster<F64, kForces, TABLDS, K>), grid, dim3(64), 0, s, d, c, o, S);
+  else if (mode == kEnergy)
+    hipLaunchKernelGGL((k_pair_cluster<F64, kEnergy, TABLDS, K>), grid, dim3(64), 0, s, d, c, o, S);
+  else
+    hipLaunchKernelGGL((k_pair_cluster<F64, kAdjoint, TABLDS, K>), grid, dim3(64), 0, s, d, c, o, S);
+}
+
+template <bool F64, bool TABLDS>
+void launch_cluster_k(int K, int mode, dim3 grid, hipStream_t s, const Dev &d, const Consts &c, const Out &o, int S) {
+  if (K == 8) launch_cluster_mode<F64, TABLDS, 8>(mode, grid, s, d, c, o, S);
+  else launch_cluster_mode<F64, TABLDS, 4>(mode, grid, s, d, c, o, S);
 }
 
 }  // namespace
 
-template <bool F64, bool TABLDS, bool ROWQ>
-void launch_cluster_mode(int mode, dim3 grid, hipStream_t s, const Dev &d, const Consts &c, const Out &o) {
-  if (mode == kForces)
-    hipLaunchKernelGGL((k_pair_cluster<F64, kForces, TABLDS, ROWQ>), grid, dim3(64), 0, s, d, c, o);
-  else if (mode == kEnergy)
-    hipLaunchKernelGGL((k_pair_cluster<F64, kEnergy, TABLDS, ROWQ>), grid, dim3(64), 0, s, d, c, o);
-  else
-    hipLaunchKernelGGL((k_pair_cluster<F64, kAdjoint, TABLDS, ROWQ>), grid, dim3(64), 0, s, d, c, o);
-}
-
-void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out &o, int mode, hipStream_t s) {
-  if (p.n_clusters_max == 0 || p.N == 0) return;
-  const int64_t g = (p.n_clusters_max + kXcds - 1) / kXcds * kXcds;  // a multiple of the XCD count
-  const dim3 grid(static_cast<unsigned>(g));
-  const bool tab = p.T <= kTabLds;
-  const bool rowq = p.kernel == NB_KERNEL_CLUSTER_RQ;
-  if (p.precision == NB_FP64) {
-    if (tab) launch_cluster_mode<true, true, false>(mode, grid, s, d, c, o);
-    else launch_cluster_mode<true, false, false>(mode, grid, s, d, c, o);
-  } else if (rowq) {
-    if (tab) launch_cluster_mode<false, true, true>(mode, grid, s, d, c, o);
-    else launch_cluster_mode<false, false, true>(mode, grid, s, d, c, o);
-  } else {
-    if (tab) launch_cluster_mode<false, true, false>(mode, grid, s, d, c, o);
-    else launch_cluster_mode<false, false, false>(mode, grid, s, d, c, o);
+void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out &o, int mode, hipStream_t s,
+                         double *energy, double *virial, const double *eps, double *grad_sigma, double *grad_eps) {
+  if (p.N > 0 && p.n_clusters_max > 0) {
+    const int64_t waves = p.n_clusters_max * p.split;
+    const int64_t g = (waves + kXcds - 1) / kXcds * kXcds;  // a multiple of the XCD count
+    const dim3 grid(static_cast<unsigned>(g));
+    const bool tab = p.T <= kTabLds;
+    const int K = p.cluster_size;
+    if (p.precision == NB_FP64) {
+      if (tab) launch_cluster_k<true, true>(K, mode, grid, s, d, c, o, p.split);
+      else launch_cluster_k<true, false>(K, mode, grid, s, d, c, o, p.split);
+    } else {
+      if (tab) launch_cluster_k<false, true>(K, mode, grid, s, d, c, o, p.split);
+      else launch_cluster_k<false, false>(K, mode, grid, s, d, c, o, p.split);
+    }
   }
+  const int nA = static_cast<int>((p.N + kFinishBlock - 1) / kFinishBlock);
+  int nv = 0;
+  if (mode == kForces) nv = o.want_part ? (virial ? kPart : 1) : 0;
+  if (mode == kEnergy) nv = 1;
+  const int extra = mode == kAdjoint ? ((grad_sigma || grad_eps) ? 2 * p.T : 0) : 0;
+  const dim3 fg(static_cast<unsigned>(nA + p.B + extra));
+  if (mode == kForces)
+    hipLaunchKernelGGL(k_finish<kForces>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
+                       grad_sigma, grad_eps);
+  else if (mode == kEnergy)
+    hipLaunchKernelGGL(k_finish<kEnergy>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
+                       grad_sigma, grad_eps);
+  else
+    hipLaunchKernelGGL(k_finish<kAdjoint>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
+                       grad_sigma, grad_eps);
 }
 
 }  // namespace nb

@@ -28,7 +28,7 @@ COULOMB_K = 1389.35457644382
 
 NB_OK, NB_ERR_ARG, NB_ERR_BOX, NB_ERR_WORKSPACE, NB_ERR_HIP, NB_ERR_CAPACITY = range(6)
 NB_FP64, NB_MIXED = 0, 1
-NB_KERNEL_AUTO, NB_KERNEL_ATOM, NB_KERNEL_CLUSTER, NB_KERNEL_CLUSTER_RQ = 0, 1, 2, 3
+NB_KERNEL_AUTO, NB_KERNEL_ATOM, NB_KERNEL_CLUSTER = 0, 1, 2
 NB_STATUS_NONFINITE_POS = 0x1
 NB_STATUS_BAD_TYPE = 0x2
 NB_STATUS_BAD_EXCLUSION = 0x4
@@ -72,6 +72,8 @@ class nb_params(ctypes.Structure):
         ("cell_div_xy", ctypes.c_int32),
         ("cell_div_z", ctypes.c_int32),
         ("kernel", ctypes.c_int32),
+        ("split", ctypes.c_int32),
+        ("cluster_size", ctypes.c_int32),
     ]
 
 
@@ -88,9 +90,6 @@ class nb_layout(ctypes.Structure):
         ("n_columns", ctypes.c_int64),
         ("n_clusters_max", ctypes.c_int64),
         ("off_col_clu_start", ctypes.c_int64),
-        ("off_clusters", ctypes.c_int64),
-        ("off_clu_ctr", ctypes.c_int64),
-        ("off_clu_half", ctypes.c_int64),
     ]
 
 
@@ -140,9 +139,10 @@ def _stream(stream=None) -> int:
 
 
 def make_params(cutoff: float, beta: float, precision: int = NB_MIXED, coulomb_k: float = COULOMB_K,
-                cell_div_xy: int = 0, cell_div_z: int = 0, kernel: int = NB_KERNEL_AUTO) -> nb_params:
+                cell_div_xy: int = 0, cell_div_z: int = 0, kernel: int = NB_KERNEL_AUTO, split: int = 0,
+                cluster_size: int = 0) -> nb_params:
     return nb_params(float(cutoff), float(beta), float(coulomb_k), int(precision), int(cell_div_xy),
-                     int(cell_div_z), int(kernel))
+                     int(cell_div_z), int(kernel), int(split), int(cluster_size))
 
 
 @dataclass

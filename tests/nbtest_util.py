@@ -49,14 +49,17 @@ def oracle_for(system, precision, rows=None):
 
 
 def gpu_eval(systems, precision, cell_div_xy=0, cell_div_z=0, kernel=H.NB_KERNEL_AUTO, energy_call=False,
-             backward=False, grad_energy=None):
-    """Runs build_cells + forces (and optionally energy / backward) through the C ABI."""
+             backward=False, grad_energy=None, split=0, cluster_size=0):
+    """Runs build_cells + forces (and optionally energy / backward) through the C ABI.
+    kernel "cluster8" is the cluster kernel with 8-atom clusters."""
     import torch
+    if kernel == "cluster8":
+        kernel, cluster_size = H.NB_KERNEL_CLUSTER, 8
     systems = systems if isinstance(systems, (list, tuple)) else [systems]
     dt = torch.float64 if precision == H.NB_FP64 else torch.float32
     b = H.device_batch(systems, dtype=dt)
     p = H.make_params(systems[0].cutoff, systems[0].beta, precision, cell_div_xy=cell_div_xy,
-                      cell_div_z=cell_div_z, kernel=kernel)
+                      cell_div_z=cell_div_z, kernel=kernel, split=split, cluster_size=cluster_size)
     force, energy, vir, ws = H.evaluate(b, p)
     out = dict(force=force.cpu().numpy(), energy=energy.cpu().numpy(), virial=vir.cpu().numpy(),
                batch=b, params=p, ws=ws)
@@ -89,13 +92,10 @@ def workspace_arrays(out):
     cs = ws[lay.off_cell_start: lay.off_cell_start + 4 * (lay.n_cells + 1)].view(np.int32)
     fx = ws[lay.off_sorted_fixed: lay.off_sorted_fixed + 16 * n].view(np.uint32).reshape(n, 4)
     mk = ws[lay.off_excl_mask: lay.off_excl_mask + 16 * n].view(np.uint32).reshape(n, 4)
-    ncol, ncm = lay.n_columns, lay.n_clusters_max
+    ncol = lay.n_columns
     ccs = ws[lay.off_col_clu_start: lay.off_col_clu_start + 4 * (ncol + 1)].view(np.int32)
-    clu = ws[lay.off_clusters: lay.off_clusters + 16 * ncm].view(np.int32).reshape(ncm, 4)
-    ctr = ws[lay.off_clu_ctr: lay.off_clu_ctr + 16 * ncm].view(np.uint32).reshape(ncm, 4)
-    half = ws[lay.off_clu_half: lay.off_clu_half + 16 * ncm].view(np.uint32).reshape(ncm, 4)
-    return dict(cell_start=cs, sorted_fixed=fx, excl_mask=mk, col_clu_start=ccs, clusters=clu,
-                clu_ctr=ctr, clu_half=half, dims=tuple(lay.dims))
+    return dict(cell_start=cs, sorted_fixed=fx, excl_mask=mk, col_clu_start=ccs, dims=tuple(lay.dims),
+                n_clusters_max=lay.n_clusters_max)
 
 
 def oracle_binning(systems, precision, divs):

@@ -18,7 +18,7 @@ pytestmark = [pytest.mark.gpu,
 
 FP64_TOL = 1e-12
 MIXED_TOL = 1e-5
-KERNELS = [H.NB_KERNEL_ATOM, H.NB_KERNEL_CLUSTER, H.NB_KERNEL_CLUSTER_RQ]
+KERNELS = [H.NB_KERNEL_ATOM, H.NB_KERNEL_CLUSTER, "cluster8"]
 
 
 def _print_case(name, **kw):
@@ -32,14 +32,11 @@ def chain():
 
 # --- binning: bit-exact ------------------------------------------------------------------
 
-@pytest.mark.parametrize("build", ["fused", "phased"])
 @pytest.mark.parametrize("divs", [(2, 2), (2, 8), (1, 1), (3, 3), (2, 3)])
 @pytest.mark.parametrize("precision", [H.NB_MIXED, H.NB_FP64])
-def test_binning_is_the_stable_counting_sort(divs, precision, build, chain, monkeypatch):
-    # the cell list is built by one cooperative launch, or by one launch per phase
-    monkeypatch.setenv("NBHIP_BUILD", build)
+def test_binning_is_the_stable_counting_sort(divs, precision, chain):
     systems = [chain, U.cached_config(1), S.water_box(500, 25.0, seed=9)]
-    _print_case("binning", divs=divs, precision=precision, build=build)
+    _print_case("binning", divs=divs, precision=precision)
     out = U.gpu_eval(systems, precision, cell_div_xy=divs[0], cell_div_z=divs[1])
     ws = U.workspace_arrays(out)
     ref = U.oracle_binning(systems, precision, (divs[0], divs[0], divs[1]))
@@ -75,25 +72,43 @@ def test_exclusion_windows_are_exact(chain):
     assert not far.any()
 
 
-@pytest.mark.parametrize("build", ["fused", "phased"])
-def test_clusters_partition_every_column(build, chain, monkeypatch):
-    monkeypatch.setenv("NBHIP_BUILD", build)
+@pytest.mark.parametrize("K", [4, 8])
+def test_column_cluster_counts_are_exact(K, chain):
+    # clusters are K consecutive sorted atoms of one (x, y) column: per column
+    # ceil(count / K), scanned over the columns of every system in order
     systems = [chain, U.cached_config(1)]
-    out = U.gpu_eval(systems, H.NB_MIXED, kernel=H.NB_KERNEL_CLUSTER)
+    out = U.gpu_eval(systems, H.NB_MIXED, kernel=H.NB_KERNEL_CLUSTER, cluster_size=K)
     ws = U.workspace_arrays(out)
-    ccs = ws["col_clu_start"]
-    n_clu = int(ccs[-1])
-    clu = ws["clusters"][:n_clu]
-    fixed = ws["sorted_fixed"]
-    covered = np.zeros(out["batch"].n_atoms, np.int64)
-    for k, (a0, cnt, col, sysid) in enumerate(clu):
-        assert 1 <= cnt <= 8 and ccs[col] <= k < ccs[col + 1]
-        covered[a0:a0 + cnt] += 1
-        for ax in range(3):  # every member lies inside the box (minimum image)
-            d = (fixed[a0:a0 + cnt, ax].astype(np.int64) - int(ws["clu_ctr"][k, ax])) % 2**32
-            d = np.where(d >= 2**31, 2**32 - d, d)
-            assert np.all(d <= int(ws["clu_half"][k, ax]))
-    assert np.all(covered == 1)
+    ref = U.oracle_binning(systems, H.NB_MIXED, (2, 2, 8))
+    from oracle import binning as OB
+    per_col = []
+    cell0 = 0
+    for s in systems:
+        dims = OB.grid_dims(s.box, s.cutoff, (2, 2, 8))
+        nz = int(dims[2])
+        for c in range(int(dims[0] * dims[1])):
+            a0 = ref["cell_start"][cell0 + c * nz]
+            a1 = ref["cell_start"][cell0 + (c + 1) * nz]
+            per_col.append((a1 - a0 + K - 1) // K)
+        cell0 += int(np.prod(dims))
+    expect = np.concatenate([[0], np.cumsum(per_col)])
+    np.testing.assert_array_equal(ws["col_clu_start"], expect)
+    assert expect[-1] <= ws["n_clusters_max"]
+
+
+@pytest.mark.parametrize("K", [4, 8])
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+def test_split_and_cluster_size_give_the_same_forces(precision, K, chain):
+    ref = U.oracle_for(chain, precision)
+    tol = FP64_TOL if precision == H.NB_FP64 else MIXED_TOL
+    outs = [U.gpu_eval(chain, precision, kernel=H.NB_KERNEL_CLUSTER, split=k, cluster_size=K, backward=True)
+            for k in (1, 2, 3, 4)]
+    for o in outs:
+        assert U.rel_rms(o["force"], ref["force"]) <= tol
+        assert U.rel_rms(o["grad_charge"], ref["phi"]) <= tol
+        assert o["energy"][0] == pytest.approx(ref["energy_total"], rel=tol)
+    for o in outs[1:]:  # splitting only reorders sums
+        assert U.rel_rms(o["force"], outs[0]["force"]) <= (1e-13 if precision == H.NB_FP64 else 1e-6)
 
 
 # --- forces, energies, virial --------------------------------------------------------------
