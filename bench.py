@@ -13,6 +13,7 @@ oracle.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,36 +29,55 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak (dense)
 # Algorithmic FP32 work of one in-cutoff, non-excluded, unordered pair evaluated once
 # for force + energy + virial (FMA = 2 flops; rsqrt, reciprocal and exp2 not counted).
 FLOPS_PER_PAIR = 72
+# Counter summary (FETCH_SIZE / WRITE_SIZE, calibrated) of the default mixed pair kernel.
+PAIR_PROFILE = "pair_cluster8_23k_mixed_pmc.md"
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_steps(fn, steps, warmup, torch):
+def time_steps(fn, steps, warmup, torch, H):
+    """Wall time per step over exactly `steps` steps bracketed by device synchronisation,
+    per-step durations from HIP events between consecutive steps on the library's stream
+    (torch's current stream), and the pair kernel's own average duration from the
+    library's event hook around each pair-kernel launch inside the timed region."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    H.pair_timer_start(steps)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    ev[0].record()
+    for k in range(steps):
         fn()
+        ev[k + 1].record()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    sec = (time.perf_counter() - t0) / steps
+    pair_ms, launches = H.pair_timer_stop()
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]) * 1e-3
+    return dict(sec=sec, pair_sec=pair_ms * 1e-3 / max(launches, 1), pair_launches=launches,
+                median=float(np.median(per)), p10=float(np.percentile(per, 10)), p90=float(np.percentile(per, 90)))
 
 
-def time_with_events(fn, reps, torch):
-    """Average duration of fn's launches, bracketed by HIP events on torch's current
-    stream (the stream the library enqueues on)."""
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    fn()
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(reps):
-        fn()
-    stop.record()
-    stop.synchronize()
-    return start.elapsed_time(stop) / reps * 1e-3
+PAIR_SOURCES = ("nb_pair_cluster.hip", "nb_pair_math.h", "nb_pair_common.h", "nb_internal.h")
+
+
+def measured_traffic(profile):
+    """HBM bytes per pair-kernel launch from a committed counter summary, or None when
+    the pair-kernel sources have changed since those counters were taken."""
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    kv = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line and
+              line.split(": ", 1)[0] in ("source_sha256_16", "fetch_bytes_per_launch", "write_bytes_per_launch"))
+    h = hashlib.sha256()
+    for f in PAIR_SOURCES:
+        with open(os.path.join(ROOT, "paper_0902_0827_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if kv.get("source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
 
 
 def rel_errors(f, ref):
@@ -127,16 +147,13 @@ def main():
             H.build_cells(b, p, ws)
             H.nonbonded_forces(b, p, ws, force, energy, vir)
 
-        def pair_only():
-            H.nonbonded_forces(b, p, ws, force, energy, vir)
-
         steps = args.steps if prec == H.NB_MIXED else max(10, args.steps // 4)
-        sec = time_steps(step, steps, args.warmup, torch)
-        pair_sec = time_with_events(pair_only, steps, torch)
+        t = time_steps(step, steps, args.warmup, torch, H)
         torch.cuda.synchronize()
-        results[prec_name] = dict(sec=sec, pair_sec=pair_sec, steps=steps, force=force.cpu().numpy(),
-                                  energy=float(energy.cpu()[0]), status=H.read_status(ws))
-        log(f"[bench] {prec_name}: {sec * 1e3:.4f} ms/step, forces call {pair_sec * 1e6:.1f} us")
+        results[prec_name] = dict(t, steps=steps, force=force.cpu().numpy(), energy=float(energy.cpu()[0]),
+                                  status=H.read_status(ws))
+        log(f"[bench] {prec_name}: {t['sec'] * 1e3:.4f} ms/step (median {t['median'] * 1e3:.4f}), "
+            f"pair kernel {t['pair_sec'] * 1e6:.1f} us over {t['pair_launches']} launches")
 
     # FP64 oracle on the host: reference for the error columns and the CPU baseline.
     from oracle import oracle as O
@@ -168,6 +185,9 @@ def main():
     err_m = rel_errors(m["force"], ref["mixed"]["force"])
     err_d = rel_errors(f64["force"], ref["fp64"]["force"]) if f64 else (None, None)
     achieved = pairs * FLOPS_PER_PAIR / m["pair_sec"] / 1e12
+    default_kernel = args.kernel == "auto" and args.split in (0, 1) and args.cluster_size in (0, 8) and \
+        args.cell_div in ("0,0", "2,8")
+    traffic = measured_traffic(PAIR_PROFILE) if default_kernel else None
     out = {
         "metric": METRIC,
         "value": 1.0 / m["sec"],
@@ -176,6 +196,7 @@ def main():
         "steps": m["steps"],
         "warmup": args.warmup,
         "ms_per_step": m["sec"] * 1e3,
+        "step_ms_median_p10_p90": [m["median"] * 1e3, m["p10"] * 1e3, m["p90"] * 1e3],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -189,10 +210,10 @@ def main():
         "pairs_per_s": pairs / m["sec"],
         "fp64_path": None if not f64 else {
             "value": 1.0 / f64["sec"], "unit": "evals/s", "ms_per_step": f64["sec"] * 1e3,
-            "forces_call_us": f64["pair_sec"] * 1e6, "rel_rms_force": err_d[0], "max_rel_force": err_d[1]},
-        "roofline": {"bound": "alu", "kernel": "pair kernel (nb_nonbonded_forces)",
+            "pair_kernel_us": f64["pair_sec"] * 1e6, "rel_rms_force": err_d[0], "max_rel_force": err_d[1]},
+        "roofline": {"bound": "alu", "kernel": "cluster pair kernel (mixed, forces + energy + virial)",
                      "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
                      "launch_us": m["pair_sec"] * 1e6, "flops_per_pair": FLOPS_PER_PAIR},
         "cpu_baseline": cpu,
         "status_bits": [r["status"] for r in results.values()],

@@ -153,6 +153,17 @@ nb_status nb_read_status(const void *workspace, hipStream_t stream, uint32_t *fl
 /* Message for the last non-OK return on the calling thread ("" if none). */
 const char *nb_last_error(void);
 
+/* Pair-kernel timing, for benchmarks.  nb_pair_timer_start creates `capacity` pairs of
+ * HIP events (host call; HIP events only, no device memory) and from then on every
+ * nb_nonbonded_forces / _energy / _backward call records one pair on its stream
+ * immediately before and after its pair kernel (the launches that follow the first
+ * `capacity` are not recorded).  nb_pair_timer_stop waits for the recorded events,
+ * returns the summed kernel time in milliseconds and the number of recorded
+ * launches, and destroys the events.  Process-wide state: not for concurrent use
+ * from several threads.  capacity in [1, 65536]. */
+nb_status nb_pair_timer_start(int32_t capacity);
+nb_status nb_pair_timer_stop(double *total_ms /*[host]*/, int64_t *launches /*[host]*/);
+
 /* Internal arrays of a built workspace, as byte offsets from its start, for tests
  * and debugging.  Host only.  See the library source for the record formats. */
 typedef struct {

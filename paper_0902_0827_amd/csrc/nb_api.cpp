@@ -31,6 +31,8 @@ int64_t grid_dim(double L, double cutoff, int k) {
 }
 }  // namespace
 
+PairTimer g_pair_timer;
+
 void set_error(const std::string &msg) { g_last_error = msg; }
 
 nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
@@ -294,5 +296,54 @@ nb_status nb_read_status(const void *workspace, hipStream_t stream, uint32_t *fl
 }
 
 const char *nb_last_error(void) { return nb::g_last_error.c_str(); }
+
+nb_status nb_pair_timer_start(int32_t capacity) {
+  if (capacity < 1 || capacity > 65536) return fail(NB_ERR_ARG, "timer capacity must be in [1, 65536]");
+  nb::PairTimer &t = nb::g_pair_timer;
+  if (t.on) return fail(NB_ERR_ARG, "pair timer already started");
+  t.ev.clear();
+  t.used = 0;
+  for (int32_t k = 0; k < capacity; ++k) {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+      if (a) (void)hipEventDestroy(a);
+      for (auto &pr : t.ev) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+      }
+      t.ev.clear();
+      return hip_status(e, "nb_pair_timer_start: event create");
+    }
+    t.ev.emplace_back(a, b);
+  }
+  t.on = true;
+  return NB_OK;
+}
+
+nb_status nb_pair_timer_stop(double *total_ms, int64_t *launches) {
+  if (!total_ms || !launches) return fail(NB_ERR_ARG, "total_ms and launches are required");
+  nb::PairTimer &t = nb::g_pair_timer;
+  if (!t.on) return fail(NB_ERR_ARG, "pair timer not started");
+  t.on = false;
+  double sum = 0.0;
+  hipError_t err = hipSuccess;
+  for (size_t k = 0; k < t.used && err == hipSuccess; ++k) {
+    err = hipEventSynchronize(t.ev[k].second);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, t.ev[k].first, t.ev[k].second);
+    sum += ms;
+  }
+  for (auto &pr : t.ev) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  *total_ms = sum;
+  *launches = static_cast<int64_t>(t.used);
+  t.ev.clear();
+  t.used = 0;
+  return hip_status(err, "nb_pair_timer_stop");
+}
 
 }  // extern "C"

@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "nbhip.h"
@@ -128,6 +129,22 @@ struct Out {
 nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan);
 Dev dev_view(const Plan &plan, void *ws);
 void set_error(const std::string &msg);
+
+// Optional events around pair-kernel launches (nb_pair_timer_start / _stop).
+struct PairTimer {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t used = 0;
+};
+extern PairTimer g_pair_timer;
+inline void timer_before(hipStream_t s) {
+  if (g_pair_timer.on && g_pair_timer.used < g_pair_timer.ev.size())
+    (void)hipEventRecord(g_pair_timer.ev[g_pair_timer.used].first, s);
+}
+inline void timer_after(hipStream_t s) {
+  if (g_pair_timer.on && g_pair_timer.used < g_pair_timer.ev.size())
+    (void)hipEventRecord(g_pair_timer.ev[g_pair_timer.used++].second, s);
+}
 
 // Launchers (nb_build.hip / nb_pair.hip); each returns hipSuccess or the first error.
 hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hipStream_t s);

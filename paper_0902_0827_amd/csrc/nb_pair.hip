@@ -337,10 +337,12 @@ template <int MODE>
 void launch_pair(const Plan &p, const Dev &d, const Out &o, hipStream_t s) {
   const Consts c = make_consts(p);
   if (p.n_blocks == 0) return;
+  timer_before(s);
   if (p.precision == NB_FP64)
     hipLaunchKernelGGL((k_pair_atom<true, MODE>), dim3(static_cast<unsigned>(p.n_blocks)), dim3(kBlock), 0, s, d, c, o);
   else
     hipLaunchKernelGGL((k_pair_atom<false, MODE>), dim3(static_cast<unsigned>(p.n_blocks)), dim3(kBlock), 0, s, d, c, o);
+  timer_after(s);
 }
 
 }  // namespace

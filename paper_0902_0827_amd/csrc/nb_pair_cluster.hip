@@ -659,6 +659,7 @@ void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out
     const dim3 grid(static_cast<unsigned>(g));
     const bool tab = p.T <= kTabLds;
     const int K = p.cluster_size;
+    timer_before(s);
     if (p.precision == NB_FP64) {
       if (tab) launch_cluster_k<true, true>(K, mode, grid, s, d, c, o, p.split);
       else launch_cluster_k<true, false>(K, mode, grid, s, d, c, o, p.split);
@@ -666,6 +667,7 @@ void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out
       if (tab) launch_cluster_k<false, true>(K, mode, grid, s, d, c, o, p.split);
       else launch_cluster_k<false, false>(K, mode, grid, s, d, c, o, p.split);
     }
+    timer_after(s);
   }
   const int nA = static_cast<int>((p.N + kFinishBlock - 1) / kFinishBlock);
   int nv = 0;

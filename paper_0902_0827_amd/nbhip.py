@@ -37,7 +37,8 @@ NB_STATUS_NOT_BUILT = 0x10
 NB_MAX_TYPES = 64
 
 EXPORTED = ("nb_workspace_bytes", "nb_build_cells", "nb_nonbonded_forces", "nb_nonbonded_energy",
-            "nb_nonbonded_backward", "nb_read_status", "nb_last_error", "nb_workspace_layout")
+            "nb_nonbonded_backward", "nb_read_status", "nb_last_error", "nb_workspace_layout",
+            "nb_pair_timer_start", "nb_pair_timer_stop")
 
 
 class NbError(RuntimeError):
@@ -113,6 +114,8 @@ def load_library(path: str = LIB_PATH):
     lib.nb_nonbonded_backward.argtypes = [S, P, V, sz, V, V, V, V, V, V]
     lib.nb_read_status.argtypes = [V, V, ctypes.POINTER(ctypes.c_uint32)]
     lib.nb_workspace_layout.argtypes = [S, P, ctypes.POINTER(nb_layout)]
+    lib.nb_pair_timer_start.argtypes = [ctypes.c_int32]
+    lib.nb_pair_timer_stop.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTED:
         getattr(lib, name).restype = ctypes.c_int if name != "nb_last_error" else ctypes.c_char_p
     _lib = lib
@@ -266,6 +269,18 @@ def read_status(ws, stream=None) -> int:
     flags = ctypes.c_uint32()
     _check(lib.nb_read_status(_ptr(ws), _stream(stream), ctypes.byref(flags)))
     return int(flags.value)
+
+
+def pair_timer_start(capacity: int = 4096):
+    """Record HIP events around every following pair-kernel launch (up to `capacity`)."""
+    _check(load_library().nb_pair_timer_start(int(capacity)))
+
+
+def pair_timer_stop():
+    """Stop recording; returns (summed pair-kernel milliseconds, recorded launches)."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(load_library().nb_pair_timer_stop(ctypes.byref(ms), ctypes.byref(n)))
+    return float(ms.value), int(n.value)
 
 
 # --- convenience --------------------------------------------------------------------------

@@ -136,3 +136,12 @@ def test_workload_generators_have_the_documented_shapes():
     # every exclusion within the 64-atom index window
     rows = np.repeat(np.arange(s2.n), np.diff(s2.excl_offset))
     assert np.abs(s2.excl_index - rows).max() <= 2
+
+
+def test_pair_timer_argument_checks():
+    lib = H.load_library()
+    assert lib.nb_pair_timer_start(0) == H.NB_ERR_ARG
+    assert lib.nb_pair_timer_start(65537) == H.NB_ERR_ARG
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    assert lib.nb_pair_timer_stop(ctypes.byref(ms), ctypes.byref(n)) == H.NB_ERR_ARG  # never started
+    assert "not started" in H.last_error()
