@@ -98,7 +98,10 @@ def main():
                     help="time the FP64 GPU path beside the mixed one (default) or only the mixed one")
     ap.add_argument("--kernel", choices=["auto", "atom", "cluster"], default="auto",
                     help="pair-kernel variant (both paths)")
-    ap.add_argument("--split", type=int, default=0, help="cluster kernel: waves per cluster (0 = default)")
+    ap.add_argument("--split", type=int, default=0, help="cluster kernel: work items per cluster (0 = default)")
+    ap.add_argument("--schedule", choices=["auto", "static", "dynamic"], default="auto",
+                    help="cluster kernel: one item per wave, or persistent waves pulling items")
+    ap.add_argument("--wg-per-cu", type=int, default=0, help="dynamic schedule: resident workgroups per CU")
     ap.add_argument("--cluster-size", type=int, default=0, help="cluster kernel: atoms per cluster, 4 or 8")
     ap.add_argument("--cell-div", type=str, default="0,0", help="cells per cutoff 'xy,z' (0 = default)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -136,8 +139,9 @@ def main():
         b = H.device_batch([s], dtype=dt)
         kern = {"auto": H.NB_KERNEL_AUTO, "atom": H.NB_KERNEL_ATOM, "cluster": H.NB_KERNEL_CLUSTER}[args.kernel]
         dxy, dz = (int(v) for v in args.cell_div.split(","))
+        sched = {"auto": H.NB_SCHED_AUTO, "static": H.NB_SCHED_STATIC, "dynamic": H.NB_SCHED_DYNAMIC}[args.schedule]
         p = H.make_params(s.cutoff, s.beta, prec, kernel=kern, cell_div_xy=dxy, cell_div_z=dz, split=args.split,
-                          cluster_size=args.cluster_size)
+                          cluster_size=args.cluster_size, schedule=sched, wg_per_cu=args.wg_per_cu)
         ws = H.alloc_workspace(b, p)
         force = torch.empty((s.n, 3), dtype=torch.float64, device="cuda")
         energy = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -185,8 +189,8 @@ def main():
     err_m = rel_errors(m["force"], ref["mixed"]["force"])
     err_d = rel_errors(f64["force"], ref["fp64"]["force"]) if f64 else (None, None)
     achieved = pairs * FLOPS_PER_PAIR / m["pair_sec"] / 1e12
-    default_kernel = args.kernel == "auto" and args.split in (0, 1) and args.cluster_size in (0, 8) and \
-        args.cell_div in ("0,0", "2,8")
+    default_kernel = args.kernel == "auto" and args.split == 0 and args.cluster_size == 0 and \
+        args.cell_div == "0,0" and args.schedule == "auto" and args.wg_per_cu == 0
     traffic = measured_traffic(PAIR_PROFILE) if default_kernel else None
     out = {
         "metric": METRIC,

@@ -94,6 +94,10 @@ typedef struct {
 #define NB_KERNEL_ATOM 1    /* one lane per i atom, full neighbour shell, j read through the cache */
 #define NB_KERNEL_CLUSTER 2 /* 4- or 8-atom clusters x box-filtered j atoms staged in LDS, 64 pairs per step */
 
+#define NB_SCHED_AUTO 0
+#define NB_SCHED_STATIC 1  /* one work item per wave, a grid covering every item */
+#define NB_SCHED_DYNAMIC 2 /* persistent waves taking items from per-XCD atomic counters */
+
 typedef struct {
   double cutoff;      /* R (A): 0 < R < min(L)/2 for every system */
   double ewald_beta;  /* beta (1/A) >= 0; beta = 0 gives the bare truncated Coulomb term */
@@ -102,8 +106,11 @@ typedef struct {
   int32_t cell_div_xy;/* cells per cutoff along x and y, 1..4 (0 = 2, the paper's R/2 bins) */
   int32_t cell_div_z; /* cells per cutoff along z, 1..16 (0 = the kernel's default) */
   int32_t kernel;     /* NB_KERNEL_* */
-  int32_t split;      /* cluster kernel: waves sharing one cluster's neighbour columns, 1..4 (0 = 1) */
+  int32_t split;      /* cluster kernel: work items per cluster, each taking an equal share of
+                         its candidate j atoms, 1..8 (0 = 1) */
   int32_t cluster_size; /* cluster kernel: atoms per i-cluster, 4 or 8 (0 = 8 mixed, 4 FP64) */
+  int32_t schedule;   /* cluster kernel: NB_SCHED_* (0 = dynamic) */
+  int32_t wg_per_cu;  /* dynamic schedule: resident one-wave workgroups per compute unit, 1..32 (0 = 16) */
 } nb_params;
 
 /* Bytes of device workspace needed for this batch and these parameters.

@@ -49,7 +49,9 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   if (prm->cell_div_xy < 0 || prm->cell_div_xy > 4) return fail(NB_ERR_ARG, "cell_div_xy must be in [0, 4]");
   if (prm->cell_div_z < 0 || prm->cell_div_z > 16) return fail(NB_ERR_ARG, "cell_div_z must be in [0, 16]");
   if (prm->kernel < NB_KERNEL_AUTO || prm->kernel > NB_KERNEL_CLUSTER) return fail(NB_ERR_ARG, "unknown kernel variant");
-  if (prm->split < 0 || prm->split > 4) return fail(NB_ERR_ARG, "split must be in [0, 4]");
+  if (prm->split < 0 || prm->split > 8) return fail(NB_ERR_ARG, "split must be in [0, 8]");
+  if (prm->schedule < NB_SCHED_AUTO || prm->schedule > NB_SCHED_DYNAMIC) return fail(NB_ERR_ARG, "unknown schedule");
+  if (prm->wg_per_cu < 0 || prm->wg_per_cu > 32) return fail(NB_ERR_ARG, "wg_per_cu must be in [0, 32]");
   if (prm->cluster_size != 0 && prm->cluster_size != 4 && prm->cluster_size != 8)
     return fail(NB_ERR_ARG, "cluster_size must be 0, 4 or 8");
 
@@ -70,6 +72,8 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   p.precision = prm->precision;
   p.kernel = prm->kernel == NB_KERNEL_AUTO ? NB_KERNEL_CLUSTER : prm->kernel;
   p.split = prm->split ? prm->split : 1;
+  p.schedule = prm->schedule == NB_SCHED_STATIC ? NB_SCHED_STATIC : NB_SCHED_DYNAMIC;
+  p.wg_per_cu = prm->wg_per_cu ? prm->wg_per_cu : 16;
   // Measured on the 23.6k-atom box: 8-atom clusters are faster for FP32 pair math, 4-atom
   // clusters (fewer wasted out-of-range pairs per FP64 evaluation) for the FP64 path.
   p.cluster_size = prm->cluster_size ? prm->cluster_size : (p.precision == NB_MIXED ? 8 : 4);
@@ -149,6 +153,7 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   l.adj_partials = take(8 * 2 * static_cast<size_t>(p.T) * nparts);
   l.col_clu_start = take(4 * static_cast<size_t>(columns + 1));
   l.part = take(32 * static_cast<size_t>(N) * static_cast<size_t>(p.split));
+  l.queue = take(4 * static_cast<size_t>(kXcds * kQueueStride));
   l.total = o;
   *plan = std::move(p);
   return NB_OK;
@@ -186,6 +191,7 @@ Dev dev_view(const Plan &p, void *ws) {
   d.part = reinterpret_cast<double4 *>(base + l.part);
   d.n_columns = p.n_columns;
   d.n_clusters_max = p.n_clusters_max;
+  d.queue = reinterpret_cast<uint32_t *>(base + l.queue);
   return d;
 }
 

@@ -68,6 +68,7 @@ __global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, con
     d.status[2] = static_cast<uint32_t>(d.N);
     d.status[3] = uses_clusters(kernel) ? 1u : 0u;
   }
+  if (tid < kXcds) d.queue[tid * kQueueStride] = 0u;
   for (int64_t k = tid; k < d.n_cells; k += stride) d.cell_count[k] = 0;
   for (int64_t k = tid; k < d.N; k += stride) {
     d.excl_mask[k] = make_uint4(0u, 0u, 0u, 0u);

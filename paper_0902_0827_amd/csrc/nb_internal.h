@@ -19,6 +19,8 @@ constexpr int kWaves = kBlock / 64;   // wave64
 constexpr int kPart = 10;             // per-block partial sums: energy + 9 virial entries
 constexpr int kWindow = 64;           // exclusion bitmap reach in original index (section 3)
 constexpr int kDescChunk = 8;         // system descriptors carried by one initialisation launch
+constexpr int kXcds = 8;          // MI355X: 8 accelerator complex dies, each with its own L2
+constexpr int kQueueStride = 16;  // uint32 per work counter (one 64-byte line each)
 constexpr uint32_t kBuiltMagic = 0x4E424831u;  // status[1]: written by nb_build_cells
 
 // Kernel variants that read the column cluster counts built by nb_build_cells.
@@ -55,7 +57,7 @@ struct alignas(16) TypePair32 { float c6, c12, inv_sig, pad; };
 struct Layout {
   size_t status, desc, tab64, tab32, cell_count, cell_start, atom_cell, atom_slot, atom_fix, tmp;
   size_t s_fix, s_pos64, s_q32, s_type, excl_mask, excl_far, partials, adj_partials;
-  size_t col_clu_start, part;
+  size_t col_clu_start, part, queue;
   size_t total;
 };
 
@@ -67,8 +69,10 @@ struct Plan {
   int precision = 0;
   int kernel = 0;
   int div_xy = 2, div_z = 2;
-  int split = 1;         // waves per cluster (cluster kernel)
-  int cluster_size = 4;  // atoms per cluster (cluster kernel): 4 or 8
+  int split = 1;         // work items per cluster (cluster kernel)
+  int cluster_size = 8;  // atoms per cluster (cluster kernel): 4 or 8
+  int schedule = 2;      // NB_SCHED_STATIC or NB_SCHED_DYNAMIC (cluster kernel)
+  int wg_per_cu = 16;    // resident one-wave workgroups per compute unit (dynamic schedule)
   double cutoff = 0, beta = 0, ke = 0;
   int64_t n_cells = 0, n_blocks = 0, n_clusters_max = 0, n_columns = 0;
   std::vector<SysDesc> desc;
@@ -103,6 +107,7 @@ struct Dev {
   double4 *part;           // [split][N] per-wave shares of each sorted atom's force and energy (or dE/dq)
   int64_t n_columns;
   int64_t n_clusters_max;
+  uint32_t *queue;         // [kXcds * kQueueStride] work counters of the dynamic schedule
 };
 
 // Per-call constants and outputs of the pair kernels.

@@ -24,6 +24,10 @@
 // converts to the caller's atom order and reduces energies, virials and per-type
 // sums.  Nothing is accumulated with atomics: results are deterministic.
 // Full shell (every pair is evaluated from both sides), as in the paper.
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "nb_pair_common.h"
 #include "nb_pair_math.h"
 
@@ -33,8 +37,6 @@ namespace {
 
 constexpr int kRing = 128;           // ring buffer of staged j atoms (power of two)
 constexpr int kTabLds = 16;          // type tables up to 16 x 16 are copied to LDS
-constexpr int kFlush = 32;           // groups between single -> double flushes of the sums
-constexpr int kXcds = 8;             // MI355X: 8 accelerator complex dies, each with its own L2
 constexpr int kMaxRuns = 2 * 9 * 9;  // up to 9 x 9 neighbour columns, <= 2 z-runs each
 constexpr int kFinishBlock = 256;
 
@@ -107,393 +109,501 @@ __device__ __forceinline__ int cluster_column(const int32_t *__restrict__ col_cl
 }
 
 template <bool F64>
-struct RingLds;
+struct WaveLds;
 
 template <>
-struct RingLds<false> {
+struct WaveLds<false> {
   uint4 fix[kRing];  // fixed-point x, y, z, original index
   float2 qt[kRing];  // q * sqrt(k_e), type (as int bits)
-  TypePair32 tab[kTabLds * kTabLds];
-  int2 runs[kMaxRuns];
+  int2 runs[kMaxRuns + 1];  // non-empty candidate runs: (first sorted atom, first candidate position)
 };
 
 template <>
-struct RingLds<true> {
+struct WaveLds<true> {
   double4 pos[kRing];  // x, y, z, q
   int2 meta[kRing];    // original index, type
-  TypePair64 tab[kTabLds * kTabLds];
-  int2 runs[kMaxRuns];
+  int2 runs[kMaxRuns + 1];  // non-empty candidate runs: (first sorted atom, first candidate position)
 };
 
+template <bool F64>
+struct TabLds {
+  TypePair32 tab[kTabLds * kTabLds];
+};
+
+template <>
+struct TabLds<true> {
+  TypePair64 tab[kTabLds * kTabLds];
+};
+
+// Orders this wave's LDS accesses (one wave's LDS operations execute in issue order;
+// this only stops the compiler from moving them across the point).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Accelerator complex die (XCD) of the executing wave, from the XCC_ID hardware
+// register; only used to pick a work queue, so any value is correct.
+__device__ __forceinline__ int xcd_id() {
+  return static_cast<int>(__builtin_amdgcn_s_getreg((20) | (0 << 6) | (15 << 11))) & (kXcds - 1);
+}
+
+// Work item m = (cluster m / Q, part m % Q): part q evaluates the cluster's i atoms
+// against the q-th of Q equal shares of its candidate j atoms (the atoms of the
+// neighbouring columns' z-windows, in run order).  Items of one cluster are
+// consecutive, and the clusters of one (x, y) column are consecutive, so that a range
+// of items is a compact region of space.
+//
+// The items are cut into 8 contiguous ranges, one per XCD (workgroups are dealt to
+// the XCDs round robin, and each XCD has its own L2).  Every wave (one per workgroup)
+// first takes one item of its XCD's range by its workgroup index.  With the static
+// schedule the grid covers every item and that is all.  With the dynamic schedule the
+// grid is what fits on the GPU at once and each range continues through an atomic
+// counter: a wave that finishes takes the next item of its own XCD's range, requested
+// while the previous item is evaluated, and once that range is exhausted the next
+// item of another XCD's range, so that the load evens out however the item costs
+// vary.  Each item writes its own output slots: the result does not depend on which
+// wave took which item.
 template <bool F64, int MODE, bool TABLDS, int K>
-__global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int S) {
+__global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   constexpr int J = 64 / K;  // j atoms per group (lanes per row)
-  __shared__ RingLds<F64> L;
-  // Workgroups are dealt to the 8 XCDs round robin; give each XCD a contiguous
-  // range of waves (neighbouring clusters) so that its L2 holds their j atoms.
-  const int per_xcd = static_cast<int>(gridDim.x) / kXcds;
-  const int w = static_cast<int>(blockIdx.x % kXcds) * per_xcd + static_cast<int>(blockIdx.x / kXcds);
+  __shared__ TabLds<F64> TL;
+  __shared__ WaveLds<F64> L;
+  const int lane = static_cast<int>(threadIdx.x);
   if (!built_for(d.status, d.N, true)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(d.status, NB_STATUS_NOT_BUILT);
     return;
   }
-  const int n_clu = d.col_clu_start[d.n_columns];
-  const int I = w / S, part = w - (w / S) * S;
-  if (I >= n_clu) return;  // the grid is sized by an upper bound on the cluster count
-  const int lane = threadIdx.x, ii = lane / J, jj = lane % J;
+  const int ii = lane / J, jj = lane % J;
   const int T = d.T;
   if constexpr (TABLDS) {
     for (int k = lane; k < T * T; k += 64) {
-      if constexpr (F64) L.tab[k] = d.tab64[k];
-      else L.tab[k] = d.tab32[k];
+      if constexpr (F64) TL.tab[k] = d.tab64[k];
+      else TL.tab[k] = d.tab32[k];
     }
+    wave_lds_sync();
   }
+  const int n_clu = uni(d.col_clu_start[d.n_columns]);
+  const int M = n_clu * Q;
+  auto range_lo = [M](int x) { return static_cast<int>((static_cast<int64_t>(M) * x) / kXcds); };
+  const int per = static_cast<int>(gridDim.x) / kXcds;  // static items per range (grid: multiple of 8)
+  const int bx = static_cast<int>(blockIdx.x) & (kXcds - 1);
+  int m = range_lo(bx) + static_cast<int>(blockIdx.x) / kXcds;
+  if (m >= range_lo(bx + 1)) m = -1;
 
-  // The cluster: its column, system, and atoms.
-  const int col = cluster_column(d.col_clu_start, static_cast<int>(d.n_columns), I);
-  int sys = 0;
-  {
-    int lo = 0, hi = d.B - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (d.desc[mid].col_begin <= col) lo = mid; else hi = mid - 1;
-    }
-    sys = lo;
-  }
-  const SysDesc &sd = d.desc[sys];
-  // Per-system constants as wave-uniform scalars: nothing in the pair loop below then
-  // waits on a vector-memory load (so the next chunk's loads stay in flight).
-  const float s2x = uni(sd.scale2f[0]), s2y = uni(sd.scale2f[1]), s2z = uni(sd.scale2f[2]);
-  const double bxx = uni(sd.box[0]), bxy = uni(sd.box[1]), bxz = uni(sd.box[2]);
-  const double ibx = uni(sd.inv_box[0]), iby = uni(sd.inv_box[1]), ibz = uni(sd.inv_box[2]);
-  const int atom_begin = uni(sd.atom_begin);
-  const int nx = uni(sd.dims[0]), ny = uni(sd.dims[1]), nz = uni(sd.dims[2]);
-  const int col_local = col - uni(sd.col_begin);
-  const int cell_begin = uni(sd.cell_begin);
-  const int cb0 = cell_begin + col_local * nz;
-  const int first = d.cell_start[cb0] + K * (I - d.col_clu_start[col]);
-  const int left = d.cell_start[cb0 + nz] - first;
-  const int count = left < K ? left : K;
-  const int i = first + ii;
-  const bool ivalid = ii < count;
-  const int ia = ivalid ? i : first;
-  const uint4 fi = d.s_fix[ia];
-  const int oi = static_cast<int>(fi.w);
-  const uint4 mask_i = d.excl_mask[oi];
-  const bool far_i = d.excl_far[oi] != 0u;
-  const int ti = d.s_type[ia];
-  double4 pi64 = make_double4(0, 0, 0, 0);
-  float qi32 = 0.f;
-  if constexpr (F64) pi64 = d.s_pos64[ia];
-  else qi32 = d.s_q32[ia];
-  const double qi64 = F64 ? pi64.w * c.ke : 0.0;
-
-  // Bounding box of the cluster, relative to its first atom (minimum image).
-  uint4 ctr, half;
-  {
-    const uint4 u0 = make_uint4(__shfl(fi.x, 0, 64), __shfl(fi.y, 0, 64), __shfl(fi.z, 0, 64), 0u);
-    const int dx = static_cast<int>(fi.x - u0.x), dy = static_cast<int>(fi.y - u0.y),
-              dz = static_cast<int>(fi.z - u0.z);
-    // rows without an atom repeat the first atom (ia = first), so they do not widen the box
-    const int lox = shfl_rows_min<J>(dx), loy = shfl_rows_min<J>(dy), loz = shfl_rows_min<J>(dz);
-    const int hix = shfl_rows_max<J>(dx), hiy = shfl_rows_max<J>(dy), hiz = shfl_rows_max<J>(dz);
-    const int lo3[3] = {lox, loy, loz}, hi3[3] = {hix, hiy, hiz};
-    const uint32_t base[3] = {u0.x, u0.y, u0.z};
-    uint32_t cc[3], hh[3];
-    for (int a = 0; a < 3; ++a) {
-      const int64_t mid = (static_cast<int64_t>(lo3[a]) + hi3[a]) >> 1;  // floor
-      const int64_t h = (hi3[a] - mid) > (mid - lo3[a]) ? (hi3[a] - mid) : (mid - lo3[a]);
-      cc[a] = base[a] + static_cast<uint32_t>(static_cast<int32_t>(mid));
-      hh[a] = static_cast<uint32_t>(h);
-    }
-    ctr = make_uint4(cc[0], cc[1], cc[2], 0u);
-    half = make_uint4(hh[0], hh[1], hh[2], 0u);
-  }
-
-  const int kx = uni(sd.reach[0]), ky = uni(sd.reach[1]), kz = uni(sd.reach[2]);
-  const int cx = col_local / ny, cy = col_local - (col_local / ny) * ny;
-  const int cz0 = static_cast<int>((static_cast<uint64_t>(d.s_fix[first].z) * nz) >> 32);
-  const int cz1 = static_cast<int>((static_cast<uint64_t>(d.s_fix[first + count - 1].z) * nz) >> 32);
-  const bool allx = 2 * kx + 1 >= nx, ally = 2 * ky + 1 >= ny;
-  const bool allz = (cz1 - cz0) + 2 * kz + 1 >= nz;
-  const int xn = allx ? nx : 2 * kx + 1, yn = ally ? ny : 2 * ky + 1;
-
-  // Per-lane sums for row ii's atom: single precision for a bounded number of
-  // groups (mixed path), flushed into double.
-  double fx = 0, fy = 0, fz = 0, en = 0, wxx = 0, wxy = 0, wxz = 0, wyy = 0, wyz = 0, wzz = 0;
-  double phi = 0, asig = 0, beps = 0;
-  float sfx = 0, sfy = 0, sfz = 0, sen = 0, swxx = 0, swxy = 0, swxz = 0, swyy = 0, swyz = 0, swzz = 0;
-  float sphi = 0, sasig = 0, sbeps = 0;
-  int groups = 0;
-  auto flush = [&]() {
-    if constexpr (!F64) {
-      fx += sfx; fy += sfy; fz += sfz; en += sen;
-      wxx += swxx; wxy += swxy; wxz += swxz; wyy += swyy; wyz += swyz; wzz += swzz;
-      phi += sphi; asig += sasig; beps += sbeps;
-      sfx = sfy = sfz = sen = swxx = swxy = swxz = swyy = swyz = swzz = sphi = sasig = sbeps = 0.f;
-    }
-    groups = 0;
+  // Dynamic items: queue x hands out range_lo(x) + per + counter_x.
+  const int home = dynamic ? xcd_id() : 0;
+  uint32_t closed = 0;  // queues known to be exhausted (wave-uniform bit mask)
+  for (int x = 0; x < kXcds; ++x)  // ranges the static round covers entirely have no dynamic items
+    if (!dynamic || range_lo(x) + per >= range_lo(x + 1)) closed |= 1u << x;
+  auto request = [&](int x) -> uint32_t {
+    uint32_t got = 0;
+    if (lane == 0) got = atomicAdd(&d.queue[x * kQueueStride], 1u);
+    return got;
   };
+  auto item_of = [&](int x, uint32_t got) -> int {
+    const int g = uni(static_cast<int>(got));
+    const int it = range_lo(x) + per + g;
+    return (g >= 0 && it < range_lo(x + 1)) ? it : -1;
+  };
+  // Next item once the speculative request on the home queue has failed: probe every
+  // counter (one load per lane), mark the exhausted ones, request from the nearest open
+  // queue.  Each round returns an item or closes at least one queue: at most 8 rounds.
+  auto steal = [&]() -> int {
+    while (closed != 0xFFu) {
+      uint32_t v = 0;
+      if (lane < kXcds) v = __hip_atomic_load(&d.queue[lane * kQueueStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const bool open = lane < kXcds && range_lo(lane) + per + static_cast<int>(v) < range_lo(lane + 1);
+      closed |= static_cast<uint32_t>(~__ballot(open)) & 0xFFu;
+      if (closed == 0xFFu) break;
+      int x = home;
+      while (closed & (1u << x)) x = (x + 1) & (kXcds - 1);
+      const int it = item_of(x, request(x));
+      if (it >= 0) return it;
+      closed |= 1u << x;
+    }
+    return -1;
+  };
+  uint32_t pending = 0;
+  bool have_pending = false;
 
-  uint32_t head = 0, tail = 0;  // wave-uniform ring positions
+  while (m >= 0) {
+    const int I = m / Q, part = m - (m / Q) * Q;
 
-  // Evaluate pair (row ii's atom, ring entry head + jj) for navail <= J entries.
-  auto process_group = [&](int navail) {
-    const int slot = static_cast<int>((head + jj) & (kRing - 1));
-    const bool jv = jj < navail;
-    int oj, tj;
-    if constexpr (F64) {
-      const int2 m = L.meta[slot];
-      oj = m.x;
-      tj = m.y;
-    } else {
-      oj = static_cast<int>(L.fix[slot].w);
-      tj = __float_as_int(L.qt[slot].y);
+    // The cluster: its column, system, and atoms.
+    const int col = cluster_column(d.col_clu_start, static_cast<int>(d.n_columns), I);
+    int sys = 0;
+    {
+      int lo = 0, hi = d.B - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d.desc[mid].col_begin <= col) lo = mid; else hi = mid - 1;
+      }
+      sys = lo;
     }
-    bool hit;
-    float r2f = 0.f, dxf = 0.f, dyf = 0.f, dzf = 0.f;
-    double r2d = 0.0, dxd = 0.0, dyd = 0.0, dzd = 0.0;
-    double4 pj64;
-    float qj = 0.f;
-    if constexpr (F64) {
-      pj64 = L.pos[slot];
-      dxd = pi64.x - pj64.x;
-      dyd = pi64.y - pj64.y;
-      dzd = pi64.z - pj64.z;
-      dxd -= bxx * rint(dxd * ibx);
-      dyd -= bxy * rint(dyd * iby);
-      dzd -= bxz * rint(dzd * ibz);
-      r2d = dxd * dxd + dyd * dyd + dzd * dzd;
-      hit = ivalid && jv && r2d < c.rc2 && oi != oj;
-    } else {
-      const uint4 fj = L.fix[slot];
-      qj = L.qt[slot].x;
-      dxf = static_cast<float>(static_cast<int>(fi.x - fj.x));
-      dyf = static_cast<float>(static_cast<int>(fi.y - fj.y));
-      dzf = static_cast<float>(static_cast<int>(fi.z - fj.z));
-      r2f = fmaf(s2z * dzf, dzf, fmaf(s2y * dyf, dyf, s2x * dxf * dxf));
-      hit = ivalid && jv && r2f < c.rc2f && oi != oj;
+    const SysDesc &sd = d.desc[sys];
+    // Per-system constants as wave-uniform scalars: nothing in the pair loop below then
+    // waits on a vector-memory load (so the next chunk's loads stay in flight).
+    const float s2x = uni(sd.scale2f[0]), s2y = uni(sd.scale2f[1]), s2z = uni(sd.scale2f[2]);
+    const double bxx = uni(sd.box[0]), bxy = uni(sd.box[1]), bxz = uni(sd.box[2]);
+    const double ibx = uni(sd.inv_box[0]), iby = uni(sd.inv_box[1]), ibz = uni(sd.inv_box[2]);
+    const int atom_begin = uni(sd.atom_begin);
+    const int nx = uni(sd.dims[0]), ny = uni(sd.dims[1]), nz = uni(sd.dims[2]);
+    const int col_local = col - uni(sd.col_begin);
+    const int cell_begin = uni(sd.cell_begin);
+    const int cb0 = cell_begin + col_local * nz;
+    const int first = uni(d.cell_start[cb0] + K * (I - d.col_clu_start[col]));
+    const int left = uni(d.cell_start[cb0 + nz]) - first;
+    const int count = left < K ? left : K;
+    const int i = first + ii;
+    const bool ivalid = ii < count;
+    const int ia = ivalid ? i : first;
+    const uint4 fi = d.s_fix[ia];
+    const int oi = static_cast<int>(fi.w);
+    const uint4 mask_i = d.excl_mask[oi];
+    const bool far_i = d.excl_far[oi] != 0u;
+    const int ti = d.s_type[ia];
+    double4 pi64 = make_double4(0, 0, 0, 0);
+    float qi32 = 0.f;
+    if constexpr (F64) pi64 = d.s_pos64[ia];
+    else qi32 = d.s_q32[ia];
+    const double qi64 = F64 ? pi64.w * c.ke : 0.0;
+
+    // Bounding box of the cluster, relative to its first atom (minimum image).
+    uint4 ctr, half;
+    {
+      const uint4 u0 = make_uint4(__shfl(fi.x, 0, 64), __shfl(fi.y, 0, 64), __shfl(fi.z, 0, 64), 0u);
+      const int dx = static_cast<int>(fi.x - u0.x), dy = static_cast<int>(fi.y - u0.y),
+                dz = static_cast<int>(fi.z - u0.z);
+      // rows without an atom repeat the first atom (ia = first), so they do not widen the box
+      const int lox = shfl_rows_min<J>(dx), loy = shfl_rows_min<J>(dy), loz = shfl_rows_min<J>(dz);
+      const int hix = shfl_rows_max<J>(dx), hiy = shfl_rows_max<J>(dy), hiz = shfl_rows_max<J>(dz);
+      const int lo3[3] = {lox, loy, loz}, hi3[3] = {hix, hiy, hiz};
+      const uint32_t base3[3] = {u0.x, u0.y, u0.z};
+      uint32_t cc[3], hh[3];
+      for (int a = 0; a < 3; ++a) {
+        const int64_t mid = (static_cast<int64_t>(lo3[a]) + hi3[a]) >> 1;  // floor
+        const int64_t h = (hi3[a] - mid) > (mid - lo3[a]) ? (hi3[a] - mid) : (mid - lo3[a]);
+        cc[a] = base3[a] + static_cast<uint32_t>(static_cast<int32_t>(mid));
+        hh[a] = static_cast<uint32_t>(h);
+      }
+      ctr = make_uint4(cc[0], cc[1], cc[2], 0u);
+      half = make_uint4(hh[0], hh[1], hh[2], 0u);
     }
-    const int delta = oj - oi;
-    const bool check = hit && (static_cast<unsigned>(delta + kWindow) <= 2u * kWindow || far_i);
-    if (__ballot(check)) {
-      if (check && pair_excluded(mask_i, far_i, oi, oj, atom_begin, d.excl_far, o.excl_off, o.excl_idx))
-        hit = false;
-    }
-    if (hit) {
-      if constexpr (F64) {
-        TypePair64 tp;
-        if constexpr (TABLDS) tp = L.tab[ti * T + tj];
-        else tp = d.tab64[ti * T + tj];
-        const PairF64 p = pair_f64(r2d, tp.c6, tp.c12, qi64 * pj64.w, c.beta, c.two_beta_sqrtpi);
-        en += p.u_lj + p.u_c;
-        if constexpr (MODE != kEnergy) {
-          fx += p.f * dxd;
-          fy += p.f * dyd;
-          fz += p.f * dzd;
-        }
-        if constexpr (MODE == kForces) {
-          if (o.want_virial) {
-            wxx += p.f * dxd * dxd; wxy += p.f * dxd * dyd; wxz += p.f * dxd * dzd;
-            wyy += p.f * dyd * dyd; wyz += p.f * dyd * dzd; wzz += p.f * dzd * dzd;
+
+    const int kx = uni(sd.reach[0]), ky = uni(sd.reach[1]), kz = uni(sd.reach[2]);
+    const int cx = col_local / ny, cy = col_local - (col_local / ny) * ny;
+    const int cz0 = static_cast<int>((static_cast<uint64_t>(__shfl(fi.z, 0, 64)) * nz) >> 32);
+    const int cz1 = static_cast<int>((static_cast<uint64_t>(__shfl(fi.z, (count - 1) * J, 64)) * nz) >> 32);
+    const bool allx = 2 * kx + 1 >= nx, ally = 2 * ky + 1 >= ny;
+    const bool allz = (cz1 - cz0) + 2 * kz + 1 >= nz;
+    const int xn = allx ? nx : 2 * kx + 1, yn = ally ? ny : 2 * ky + 1;
+
+    // Neighbour-column windows as runs [a0, a1) of sorted atoms (a z-window that wraps
+    // around the box is two runs), listed without the empty ones as (a0, position of
+    // a0 among all candidates) in LDS.  Candidate p then lies in the run r with
+    // runs[r].y <= p < runs[r + 1].y, at sorted index runs[r].x + p - runs[r].y.
+    const int ncol = xn * yn;
+    int nrun = 0, total = 0;  // wave-uniform
+    wave_lds_sync();  // the previous item's reads of the runs are complete
+    for (int k0 = 0; k0 < ncol; k0 += 64) {
+      const int k = k0 + lane;
+      int2 r0 = make_int2(0, 0), r1 = make_int2(0, 0);
+      if (k < ncol) {
+        const int ox = k / yn, oy = k - (k / yn) * yn;
+        int x = allx ? ox : cx - kx + ox;
+        x += x < 0 ? nx : (x >= nx ? -nx : 0);
+        int y = ally ? oy : cy - ky + oy;
+        y += y < 0 ? ny : (y >= ny ? -ny : 0);
+        const int cb = cell_begin + (x * ny + y) * nz;
+        if (allz) {
+          r0 = make_int2(d.cell_start[cb], d.cell_start[cb + nz]);
+        } else {
+          const int z0 = cz0 - kz, z1 = cz1 + kz + 1;  // [z0, z1)
+          if (z0 < 0) {
+            r0 = make_int2(d.cell_start[cb + z0 + nz], d.cell_start[cb + nz]);
+            r1 = make_int2(d.cell_start[cb], d.cell_start[cb + z1]);
+          } else if (z1 > nz) {
+            r0 = make_int2(d.cell_start[cb + z0], d.cell_start[cb + nz]);
+            r1 = make_int2(d.cell_start[cb], d.cell_start[cb + z1 - nz]);
+          } else {
+            r0 = make_int2(d.cell_start[cb + z0], d.cell_start[cb + z1]);
           }
         }
-        if constexpr (MODE == kAdjoint) {
-          phi += pj64.w * p.erfc_over_r;
-          asig += p.dudsig_lj * tp.inv_sig;
-          beps += p.u_lj;
-        }
+      }
+      const int n0 = r0.y - r0.x, n1 = r1.y - r1.x;
+      int cnt_tot, len_tot;
+      const int slot = nrun + wave_excl_scan_int((n0 > 0) + (n1 > 0), &cnt_tot);
+      const int pos = total + wave_excl_scan_int(n0 + n1, &len_tot);
+      if (n0 > 0) L.runs[slot] = make_int2(r0.x, pos);
+      if (n1 > 0) L.runs[slot + (n0 > 0)] = make_int2(r1.x, pos + n0);
+      nrun += cnt_tot;
+      total += len_tot;
+    }
+    if (lane == 0) L.runs[nrun] = make_int2(0, total);  // sentinel
+    // This item's share of the candidates, [lo_c, hi_c).
+    const int lo_c = static_cast<int>((static_cast<int64_t>(total) * part) / Q);
+    const int hi_c = static_cast<int>((static_cast<int64_t>(total) * (part + 1)) / Q);
+    wave_lds_sync();  // the runs are visible to every lane
+
+    // Per-lane sums for row ii's atom.  Mixed path: single precision over this item
+    // (one lane sees every J-th candidate of the item: a few dozen pairs in practice),
+    // converted to double for the row and item reductions.  FP64 path: double.
+    double fx = 0, fy = 0, fz = 0, en = 0, wxx = 0, wxy = 0, wxz = 0, wyy = 0, wyz = 0, wzz = 0;
+    double phi = 0, asig = 0, beps = 0;
+    float sfx = 0, sfy = 0, sfz = 0, sen = 0, swxx = 0, swxy = 0, swxz = 0, swyy = 0, swyz = 0, swzz = 0;
+    float sphi = 0, sasig = 0, sbeps = 0;
+    auto flush = [&]() {
+      if constexpr (!F64) {
+        fx = sfx; fy = sfy; fz = sfz; en = sen;
+        wxx = swxx; wxy = swxy; wxz = swxz; wyy = swyy; wyz = swyz; wzz = swzz;
+        phi = sphi; asig = sasig; beps = sbeps;
+      }
+    };
+
+    uint32_t head = 0, tail = 0;  // wave-uniform ring positions
+
+    // Evaluate pair (row ii's atom, ring entry head + jj) for navail <= J entries.
+    auto process_group = [&](int navail) {
+      const int slot = static_cast<int>((head + jj) & (kRing - 1));
+      const bool jv = jj < navail;
+      int oj, tj;
+      if constexpr (F64) {
+        const int2 mt = L.meta[slot];
+        oj = mt.x;
+        tj = mt.y;
       } else {
-        TypePair32 tp;
-        if constexpr (TABLDS) tp = L.tab[ti * T + tj];
-        else tp = d.tab32[ti * T + tj];
-        const PairF32 p = pair_f32(r2f, tp.c6, tp.c12, qi32 * qj, c.betaf, c.two_beta_sqrtpif, c.mb2l2e);
-        sen += p.u_lj + p.u_c;
-        if constexpr (MODE != kEnergy) {
-          const float gx = p.f * dxf, gy = p.f * dyf, gz = p.f * dzf;
-          sfx += gx;
-          sfy += gy;
-          sfz += gz;
+        oj = static_cast<int>(L.fix[slot].w);
+        tj = __float_as_int(L.qt[slot].y);
+      }
+      bool hit;
+      float r2f = 0.f, dxf = 0.f, dyf = 0.f, dzf = 0.f;
+      double r2d = 0.0, dxd = 0.0, dyd = 0.0, dzd = 0.0;
+      double4 pj64;
+      float qj = 0.f;
+      if constexpr (F64) {
+        pj64 = L.pos[slot];
+        dxd = pi64.x - pj64.x;
+        dyd = pi64.y - pj64.y;
+        dzd = pi64.z - pj64.z;
+        dxd -= bxx * rint(dxd * ibx);
+        dyd -= bxy * rint(dyd * iby);
+        dzd -= bxz * rint(dzd * ibz);
+        r2d = dxd * dxd + dyd * dyd + dzd * dzd;
+        hit = ivalid && jv && r2d < c.rc2 && oi != oj;
+      } else {
+        const uint4 fj = L.fix[slot];
+        qj = L.qt[slot].x;
+        dxf = static_cast<float>(static_cast<int>(fi.x - fj.x));
+        dyf = static_cast<float>(static_cast<int>(fi.y - fj.y));
+        dzf = static_cast<float>(static_cast<int>(fi.z - fj.z));
+        r2f = fmaf(s2z * dzf, dzf, fmaf(s2y * dyf, dyf, s2x * dxf * dxf));
+        hit = ivalid && jv && r2f < c.rc2f && oi != oj;
+      }
+      const int delta = oj - oi;
+      const bool check = hit && (static_cast<unsigned>(delta + kWindow) <= 2u * kWindow || far_i);
+      if (__ballot(check)) {
+        if (check && pair_excluded(mask_i, far_i, oi, oj, atom_begin, d.excl_far, o.excl_off, o.excl_idx))
+          hit = false;
+      }
+      if (hit) {
+        if constexpr (F64) {
+          TypePair64 tp;
+          if constexpr (TABLDS) tp = TL.tab[ti * T + tj];
+          else tp = d.tab64[ti * T + tj];
+          const PairF64 p = pair_f64(r2d, tp.c6, tp.c12, qi64 * pj64.w, c.beta, c.two_beta_sqrtpi);
+          en += p.u_lj + p.u_c;
+          if constexpr (MODE != kEnergy) {
+            fx += p.f * dxd;
+            fy += p.f * dyd;
+            fz += p.f * dzd;
+          }
           if constexpr (MODE == kForces) {
             if (o.want_virial) {
-              swxx = fmaf(gx, dxf, swxx); swxy = fmaf(gx, dyf, swxy); swxz = fmaf(gx, dzf, swxz);
-              swyy = fmaf(gy, dyf, swyy); swyz = fmaf(gy, dzf, swyz); swzz = fmaf(gz, dzf, swzz);
+              wxx += p.f * dxd * dxd; wxy += p.f * dxd * dyd; wxz += p.f * dxd * dzd;
+              wyy += p.f * dyd * dyd; wyz += p.f * dyd * dzd; wzz += p.f * dzd * dzd;
             }
           }
-        }
-        if constexpr (MODE == kAdjoint) {
-          sphi = fmaf(qj, p.erfc_over_r, sphi);
-          sasig = fmaf(p.dudsig_lj, tp.inv_sig, sasig);
-          sbeps += p.u_lj;
+          if constexpr (MODE == kAdjoint) {
+            phi += pj64.w * p.erfc_over_r;
+            asig += p.dudsig_lj * tp.inv_sig;
+            beps += p.u_lj;
+          }
+        } else {
+          TypePair32 tp;
+          if constexpr (TABLDS) tp = TL.tab[ti * T + tj];
+          else tp = d.tab32[ti * T + tj];
+          const PairF32 p = pair_f32(r2f, tp.c6, tp.c12, qi32 * qj, c.betaf, c.two_beta_sqrtpif, c.mb2l2e);
+          sen += p.u_lj + p.u_c;
+          if constexpr (MODE != kEnergy) {
+            const float gx = p.f * dxf, gy = p.f * dyf, gz = p.f * dzf;
+            sfx += gx;
+            sfy += gy;
+            sfz += gz;
+            if constexpr (MODE == kForces) {
+              if (o.want_virial) {
+                swxx = fmaf(gx, dxf, swxx); swxy = fmaf(gx, dyf, swxy); swxz = fmaf(gx, dzf, swxz);
+                swyy = fmaf(gy, dyf, swyy); swyz = fmaf(gy, dzf, swyz); swzz = fmaf(gz, dzf, swzz);
+              }
+            }
+          }
+          if constexpr (MODE == kAdjoint) {
+            sphi = fmaf(qj, p.erfc_over_r, sphi);
+            sasig = fmaf(p.dudsig_lj, tp.inv_sig, sasig);
+            sbeps += p.u_lj;
+          }
         }
       }
-    }
-    head += static_cast<uint32_t>(navail);
-    if (++groups >= kFlush) flush();
-  };
+      head += static_cast<uint32_t>(navail);
+    };
 
-  // Neighbour-column windows as runs [a0, a1) of sorted atoms, two slots per column
-  // (a z-window that wraps around the box is two runs; an unused slot is empty).
-  const int ncol = xn * yn;
-  for (int k = lane; k < ncol; k += 64) {
-    const int ox = k / yn, oy = k - (k / yn) * yn;
-    int x = allx ? ox : cx - kx + ox;
-    x += x < 0 ? nx : (x >= nx ? -nx : 0);
-    int y = ally ? oy : cy - ky + oy;
-    y += y < 0 ? ny : (y >= ny ? -ny : 0);
-    const int cb = cell_begin + (x * ny + y) * nz;
-    int2 r0, r1 = make_int2(0, 0);
-    if (allz) {
-      r0 = make_int2(d.cell_start[cb], d.cell_start[cb + nz]);
+    // Walk this item's candidates 64 at a time; the next chunk's loads are issued
+    // before the current chunk is filtered and evaluated, to hide their latency.
+    int run0 = 0;  // wave-uniform: the run holding the next chunk's first candidate
+    auto load = [&](int P, uint4 &f, int &t, float &q, double4 &p, bool &v) {
+      while (L.runs[run0 + 1].y <= P) ++run0;
+      const int pos = P + lane;
+      v = pos < hi_c;
+      int r = run0;
+      int2 cur = L.runs[r];
+      if (v) {
+        while (L.runs[r + 1].y <= pos) cur = L.runs[++r];
+      }
+      const int aa = v ? cur.x + (pos - cur.y) : L.runs[run0].x + (P - L.runs[run0].y);
+      f = d.s_fix[aa];
+      t = d.s_type[aa];
+      if constexpr (F64) p = d.s_pos64[aa];
+      else q = d.s_q32[aa];
+    };
+    uint4 fj = make_uint4(0u, 0u, 0u, 0u);
+    int tj = 0;
+    float qj = 0.f;
+    double4 pj64 = make_double4(0, 0, 0, 0);
+    bool valid = false;
+    wait_vm_loads();  // the cluster's own data has arrived before the pair loop starts
+    int P = lo_c;
+    if (P < hi_c) load(P, fj, tj, qj, pj64, valid);
+    bool requested = false;
+    while (P < hi_c) {
+      const int Pn = P + 64;
+      uint4 fj_n = fj;
+      int tj_n = tj;
+      float qj_n = qj;
+      double4 pj64_n = pj64;
+      bool valid_n = false;
+      if (Pn < hi_c) {
+        load(Pn, fj_n, tj_n, qj_n, pj64_n, valid_n);
+      } else if (dynamic && !(closed & (1u << home))) {
+        // the next item, requested after this item's last loads (vector-memory waits
+        // complete in issue order, so an earlier request would hold up the chunks)
+        pending = request(home);
+        have_pending = true;
+        requested = true;
+      }
+
+      // Box filter, then compact the survivors into the ring.
+      const bool keep = valid && box_dist2(fj, ctr, half, s2x, s2y, s2z) < c.rc2_box;
+      const uint64_t mk = __ballot(keep);
+      const uint32_t below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mk >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mk), 0u));
+      const int slot = static_cast<int>((tail + below) & (kRing - 1));
+      wave_lds_sync();  // earlier ring reads are complete before slots are reused
+      if (keep) {
+        if constexpr (F64) {
+          L.pos[slot] = pj64;
+          L.meta[slot] = make_int2(static_cast<int>(fj.w), tj);
+        } else {
+          L.fix[slot] = fj;
+          L.qt[slot] = make_float2(qj, __int_as_float(tj));
+        }
+      }
+      wave_lds_sync();
+      tail += static_cast<uint32_t>(__popcll(mk));
+      while (tail - head >= static_cast<uint32_t>(J)) process_group(J);
+
+      P = Pn;
+      fj = fj_n;
+      tj = tj_n;
+      qj = qj_n;
+      pj64 = pj64_n;
+      valid = valid_n;
+    }
+    if (tail != head) process_group(static_cast<int>(tail - head));
+    flush();
+    if (dynamic && !requested && !(closed & (1u << home))) {  // an item without candidates
+      pending = request(home);
+      have_pending = true;
+    }
+
+    if constexpr (!F64) {
+      // fixed-point units -> Angstrom; phi carries one sqrt(k_e) from q'_j.
+      fx *= sd.scale[0];
+      fy *= sd.scale[1];
+      fz *= sd.scale[2];
+      wxx *= sd.scale[0] * sd.scale[0]; wxy *= sd.scale[0] * sd.scale[1]; wxz *= sd.scale[0] * sd.scale[2];
+      wyy *= sd.scale[1] * sd.scale[1]; wyz *= sd.scale[1] * sd.scale[2]; wzz *= sd.scale[2] * sd.scale[2];
+      phi *= c.sqrt_ke;
     } else {
-      const int z0 = cz0 - kz, z1 = cz1 + kz + 1;  // [z0, z1)
-      if (z0 < 0) {
-        r0 = make_int2(d.cell_start[cb + z0 + nz], d.cell_start[cb + nz]);
-        r1 = make_int2(d.cell_start[cb], d.cell_start[cb + z1]);
-      } else if (z1 > nz) {
-        r0 = make_int2(d.cell_start[cb + z0], d.cell_start[cb + nz]);
-        r1 = make_int2(d.cell_start[cb], d.cell_start[cb + z1 - nz]);
-      } else {
-        r0 = make_int2(d.cell_start[cb + z0], d.cell_start[cb + z1]);
+      phi *= c.ke;
+    }
+
+    // Energy / virial sums of this item (a plain wave sum, before the row reduction).
+    if constexpr (MODE == kForces || MODE == kEnergy) {
+      if (o.want_part) {
+        const double v[kPart] = {0.5 * en, 0.5 * wxx, 0.5 * wxy, 0.5 * wxz, 0.5 * wxy, 0.5 * wyy,
+                                 0.5 * wyz, 0.5 * wxz, 0.5 * wyz, 0.5 * wzz};
+        const int nv = (MODE == kForces && o.want_virial) ? kPart : 1;
+        double mine = 0.0;
+        for (int k = 0; k < nv; ++k) {
+          const double s = wave_sum(v[k]);
+          if (lane == k) mine = s;
+        }
+        if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + m] = lane < nv ? mine : 0.0;
       }
     }
-    L.runs[2 * k] = r0;
-    L.runs[2 * k + 1] = r1;
-  }
-  __syncthreads();
-  // This wave's share of the runs.
-  const int r_begin = (2 * ncol * part) / S, r_end = (2 * ncol * (part + 1)) / S;
-
-  // Walk the runs 64 atoms at a time; the next chunk's loads are issued before the
-  // current chunk is filtered and evaluated, to hide their latency.
-  int base = 0, end = 0;
-  auto seek = [&](int rr) {  // first non-empty run at or after rr; sets base/end
-    while (rr < r_end) {
-      const int2 q = L.runs[rr];
-      if (q.x < q.y) {
-        base = q.x;
-        end = q.y;
-        return rr;
+    if constexpr (MODE == kAdjoint) {
+      // Per-type sums of the sigma / eps partials over this item's rows (scaled by the
+      // system's grad_energy in k_finish).
+      const double a_l = 0.5 * asig, b_l = 0.5 * beps;
+      const int my_t = ivalid ? ti : -1;
+      double keep_a = 0.0, keep_b = 0.0;
+      uint64_t left_t = __ballot(my_t >= 0);
+      while (left_t) {
+        const int lead = __ffsll(static_cast<unsigned long long>(left_t)) - 1;
+        const int tt = __shfl(my_t, lead, 64);
+        const bool mine = my_t == tt;
+        const double sa = wave_sum(mine ? a_l : 0.0);
+        const double sb = wave_sum(mine ? b_l : 0.0);
+        if (lane == tt) {
+          keep_a = sa;
+          keep_b = sb;
+        }
+        left_t &= ~__ballot(mine);
       }
-      ++rr;
-    }
-    return rr;
-  };
-  auto load = [&](int b0, int e0, uint4 &f, int &t, float &q, double4 &p, bool &v) {
-    const int a = b0 + lane;
-    v = a < e0;
-    const int aa = v ? a : b0;
-    f = d.s_fix[aa];
-    t = d.s_type[aa];
-    if constexpr (F64) p = d.s_pos64[aa];
-    else q = d.s_q32[aa];
-  };
-  uint4 fj = make_uint4(0u, 0u, 0u, 0u);
-  int tj = 0;
-  float qj = 0.f;
-  double4 pj64 = make_double4(0, 0, 0, 0);
-  bool valid = false;
-  wait_vm_loads();  // the cluster's own data has arrived before the pair loop starts
-  int r = seek(r_begin);
-  if (r < r_end) load(base, end, fj, tj, qj, pj64, valid);
-  while (r < r_end) {
-    int nr = r;
-    if (base + 64 < end) base += 64;
-    else nr = seek(r + 1);
-    uint4 fj_n = fj;
-    int tj_n = tj;
-    float qj_n = qj;
-    double4 pj64_n = pj64;
-    bool valid_n = false;
-    if (nr < r_end) load(base, end, fj_n, tj_n, qj_n, pj64_n, valid_n);
-
-    // Box filter, then compact the survivors into the ring.
-    const bool keep = valid && box_dist2(fj, ctr, half, s2x, s2y, s2z) < c.rc2_box;
-    const uint64_t m = __ballot(keep);
-    const uint32_t below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
-    const int slot = static_cast<int>((tail + below) & (kRing - 1));
-    __syncthreads();  // earlier ring reads are complete before slots are reused
-    if (keep) {
-      if constexpr (F64) {
-        L.pos[slot] = pj64;
-        L.meta[slot] = make_int2(static_cast<int>(fj.w), tj);
-      } else {
-        L.fix[slot] = fj;
-        L.qt[slot] = make_float2(qj, __int_as_float(tj));
+      if (lane < T) {
+        d.adj_partials[static_cast<int64_t>(lane) * d.n_slots + m] = keep_a;
+        d.adj_partials[static_cast<int64_t>(T + lane) * d.n_slots + m] = keep_b;
       }
     }
-    __syncthreads();
-    tail += static_cast<uint32_t>(__popcll(m));
-    while (tail - head >= static_cast<uint32_t>(J)) process_group(J);
 
-    r = nr;
-    fj = fj_n;
-    tj = tj_n;
-    qj = qj_n;
-    pj64 = pj64_n;
-    valid = valid_n;
-  }
-  if (tail != head) process_group(static_cast<int>(tail - head));
-  flush();
+    // Per-atom sums of this item: rows reduced over their J lanes.
+    fx = row_sum<J>(fx);
+    fy = row_sum<J>(fy);
+    fz = row_sum<J>(fz);
+    const double w4 = row_sum<J>(MODE == kAdjoint ? phi : en);
+    if (jj == 0 && ivalid) d.part[static_cast<int64_t>(part) * d.N + i] = make_double4(fx, fy, fz, w4);
 
-  if constexpr (!F64) {
-    // fixed-point units -> Angstrom; phi carries one sqrt(k_e) from q'_j.
-    fx *= sd.scale[0];
-    fy *= sd.scale[1];
-    fz *= sd.scale[2];
-    wxx *= sd.scale[0] * sd.scale[0]; wxy *= sd.scale[0] * sd.scale[1]; wxz *= sd.scale[0] * sd.scale[2];
-    wyy *= sd.scale[1] * sd.scale[1]; wyz *= sd.scale[1] * sd.scale[2]; wzz *= sd.scale[2] * sd.scale[2];
-    phi *= c.sqrt_ke;
-  } else {
-    phi *= c.ke;
-  }
-
-  // Energy / virial sums of this wave (a plain wave sum, before the row reduction).
-  if constexpr (MODE == kForces || MODE == kEnergy) {
-    if (o.want_part) {
-      const double v[kPart] = {0.5 * en, 0.5 * wxx, 0.5 * wxy, 0.5 * wxz, 0.5 * wxy, 0.5 * wyy,
-                               0.5 * wyz, 0.5 * wxz, 0.5 * wyz, 0.5 * wzz};
-      const int nv = (MODE == kForces && o.want_virial) ? kPart : 1;
-      double mine = 0.0;
-      for (int k = 0; k < nv; ++k) {
-        const double s = wave_sum(v[k]);
-        if (lane == k) mine = s;
+    m = -1;
+    if (dynamic) {
+      if (have_pending) {
+        m = item_of(home, pending);
+        have_pending = false;
+        if (m < 0) closed |= 1u << home;
       }
-      if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + w] = lane < nv ? mine : 0.0;
+      if (m < 0) m = steal();
     }
   }
-  if constexpr (MODE == kAdjoint) {
-    // Per-type sums of the sigma / eps partials over this wave's rows (scaled by the
-    // system's grad_energy in k_finish).
-    const double a_l = 0.5 * asig, b_l = 0.5 * beps;
-    const int my_t = ivalid ? ti : -1;
-    double keep_a = 0.0, keep_b = 0.0;
-    uint64_t left_t = __ballot(my_t >= 0);
-    while (left_t) {
-      const int lead = __ffsll(static_cast<unsigned long long>(left_t)) - 1;
-      const int tt = __shfl(my_t, lead, 64);
-      const bool mine = my_t == tt;
-      const double sa = wave_sum(mine ? a_l : 0.0);
-      const double sb = wave_sum(mine ? b_l : 0.0);
-      if (lane == tt) {
-        keep_a = sa;
-        keep_b = sb;
-      }
-      left_t &= ~__ballot(mine);
-    }
-    if (lane < T) {
-      d.adj_partials[static_cast<int64_t>(lane) * d.n_slots + w] = keep_a;
-      d.adj_partials[static_cast<int64_t>(T + lane) * d.n_slots + w] = keep_b;
-    }
-  }
-
-  // Per-atom sums of this wave's share: rows reduced over their J lanes.
-  fx = row_sum<J>(fx);
-  fy = row_sum<J>(fy);
-  fz = row_sum<J>(fz);
-  const double w4 = row_sum<J>(MODE == kAdjoint ? phi : en);
-  if (jj == 0 && ivalid) d.part[static_cast<int64_t>(part) * d.N + i] = make_double4(fx, fy, fz, w4);
 }
 
 // Energy (and virial) of system b: sum of the wave slots [lo, hi), in a fixed order.
@@ -547,6 +657,8 @@ __global__ void __launch_bounds__(kFinishBlock) k_finish(Dev d, Out o, int S, in
                                                         int nv, const double *__restrict__ eps, double *grad_sigma,
                                                         double *grad_eps) {
   __shared__ double lds[kFinishBlock / 64][kPart];
+  // The pair kernel is complete: its work counters start again from zero next time.
+  if (blockIdx.x == 0 && threadIdx.x < kXcds) d.queue[threadIdx.x * kQueueStride] = 0u;
   if (!built_for(d.status, d.N, true)) return;
   const int blk = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -633,20 +745,61 @@ __global__ void __launch_bounds__(kFinishBlock) k_finish(Dev d, Out o, int S, in
   }
 }
 
+// Compute units of the current device (cached per device).
+int compute_units() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+// Workgroups of a kernel that fit on one compute unit at once (cached per kernel and device).
+template <typename Query>
+int resident_workgroups(const void *kern, Query query) {
+  static std::mutex mu;
+  static std::map<std::pair<const void *, int>, int> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find({kern, dev});
+  if (it != cache.end()) return it->second;
+  int n = 0;
+  if (query(&n) != hipSuccess || n < 1) n = 1;
+  cache[{kern, dev}] = n;
+  return n;
+}
+
 template <bool F64, bool TABLDS, int K>
-void launch_cluster_mode(int mode, dim3 grid, hipStream_t s, const Dev &d, const Consts &c, const Out &o, int S) {
-  if (mode == kForces)
-    hipLaunchKernelGGL((k_pair_cluster<F64, kForces, TABLDS, K>), grid, dim3(64), 0, s, d, c, o, S);
-  else if (mode == kEnergy)
-    hipLaunchKernelGGL((k_pair_cluster<F64, kEnergy, TABLDS, K>), grid, dim3(64), 0, s, d, c, o, S);
-  else
-    hipLaunchKernelGGL((k_pair_cluster<F64, kAdjoint, TABLDS, K>), grid, dim3(64), 0, s, d, c, o, S);
+void launch_cluster_mode(int mode, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s, const Dev &d, const Consts &c,
+                         const Out &o, int Q) {
+  const dim3 block(64);
+  auto go = [&](auto kern) {
+    int64_t g = wgs;
+    if (dyn) {
+      // persistent grid: what fits on the device at once (at most wg_per_cu per CU)
+      const int fit = resident_workgroups(reinterpret_cast<const void *>(kern), [&](int *n) {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, kern, 64, 0);
+      });
+      g = std::min<int64_t>(g, static_cast<int64_t>(compute_units()) * std::min(fit, wg_per_cu));
+    }
+    g = std::max<int64_t>((g + kXcds - 1) / kXcds * kXcds, kXcds);  // a multiple of the XCD count
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(g)), block, 0, s, d, c, o, Q, dyn);
+  };
+  if (mode == kForces) go(k_pair_cluster<F64, kForces, TABLDS, K>);
+  else if (mode == kEnergy) go(k_pair_cluster<F64, kEnergy, TABLDS, K>);
+  else go(k_pair_cluster<F64, kAdjoint, TABLDS, K>);
 }
 
 template <bool F64, bool TABLDS>
-void launch_cluster_k(int K, int mode, dim3 grid, hipStream_t s, const Dev &d, const Consts &c, const Out &o, int S) {
-  if (K == 8) launch_cluster_mode<F64, TABLDS, 8>(mode, grid, s, d, c, o, S);
-  else launch_cluster_mode<F64, TABLDS, 4>(mode, grid, s, d, c, o, S);
+void launch_cluster_k(int K, int mode, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s, const Dev &d,
+                      const Consts &c, const Out &o, int Q) {
+  if (K == 8) launch_cluster_mode<F64, TABLDS, 8>(mode, wgs, dyn, wg_per_cu, s, d, c, o, Q);
+  else launch_cluster_mode<F64, TABLDS, 4>(mode, wgs, dyn, wg_per_cu, s, d, c, o, Q);
 }
 
 }  // namespace
@@ -654,18 +807,18 @@ void launch_cluster_k(int K, int mode, dim3 grid, hipStream_t s, const Dev &d, c
 void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out &o, int mode, hipStream_t s,
                          double *energy, double *virial, const double *eps, double *grad_sigma, double *grad_eps) {
   if (p.N > 0 && p.n_clusters_max > 0) {
-    const int64_t waves = p.n_clusters_max * p.split;
-    const int64_t g = (waves + kXcds - 1) / kXcds * kXcds;  // a multiple of the XCD count
-    const dim3 grid(static_cast<unsigned>(g));
+    const int64_t items = p.n_clusters_max * p.split;  // upper bound on the work items
+    const int64_t wgs = items;  // one wave per workgroup
+    const int dyn = p.schedule == NB_SCHED_DYNAMIC ? 1 : 0;
     const bool tab = p.T <= kTabLds;
     const int K = p.cluster_size;
     timer_before(s);
     if (p.precision == NB_FP64) {
-      if (tab) launch_cluster_k<true, true>(K, mode, grid, s, d, c, o, p.split);
-      else launch_cluster_k<true, false>(K, mode, grid, s, d, c, o, p.split);
+      if (tab) launch_cluster_k<true, true>(K, mode, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
+      else launch_cluster_k<true, false>(K, mode, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
     } else {
-      if (tab) launch_cluster_k<false, true>(K, mode, grid, s, d, c, o, p.split);
-      else launch_cluster_k<false, false>(K, mode, grid, s, d, c, o, p.split);
+      if (tab) launch_cluster_k<false, true>(K, mode, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
+      else launch_cluster_k<false, false>(K, mode, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
     }
     timer_after(s);
   }

@@ -22,6 +22,23 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+__device__ __forceinline__ int wave_sum_int(int v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Exclusive prefix sum over the wave's lanes; *total receives the sum of all lanes.
+__device__ __forceinline__ int wave_excl_scan_int(int v, int *total) {
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  int incl = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += u;
+  }
+  *total = __shfl(incl, 63, 64);
+  return incl - v;
+}
+
 // Sum over the 8 lanes of each group of 8 consecutive lanes.
 __device__ __forceinline__ double row8_sum(double v) {
   v += __shfl_xor(v, 1, 64);

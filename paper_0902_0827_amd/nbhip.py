@@ -28,6 +28,7 @@ COULOMB_K = 1389.35457644382
 
 NB_OK, NB_ERR_ARG, NB_ERR_BOX, NB_ERR_WORKSPACE, NB_ERR_HIP, NB_ERR_CAPACITY = range(6)
 NB_FP64, NB_MIXED = 0, 1
+NB_SCHED_AUTO, NB_SCHED_STATIC, NB_SCHED_DYNAMIC = 0, 1, 2
 NB_KERNEL_AUTO, NB_KERNEL_ATOM, NB_KERNEL_CLUSTER = 0, 1, 2
 NB_STATUS_NONFINITE_POS = 0x1
 NB_STATUS_BAD_TYPE = 0x2
@@ -75,6 +76,8 @@ class nb_params(ctypes.Structure):
         ("kernel", ctypes.c_int32),
         ("split", ctypes.c_int32),
         ("cluster_size", ctypes.c_int32),
+        ("schedule", ctypes.c_int32),
+        ("wg_per_cu", ctypes.c_int32),
     ]
 
 
@@ -143,9 +146,9 @@ def _stream(stream=None) -> int:
 
 def make_params(cutoff: float, beta: float, precision: int = NB_MIXED, coulomb_k: float = COULOMB_K,
                 cell_div_xy: int = 0, cell_div_z: int = 0, kernel: int = NB_KERNEL_AUTO, split: int = 0,
-                cluster_size: int = 0) -> nb_params:
+                cluster_size: int = 0, schedule: int = 0, wg_per_cu: int = 0) -> nb_params:
     return nb_params(float(cutoff), float(beta), float(coulomb_k), int(precision), int(cell_div_xy),
-                     int(cell_div_z), int(kernel), int(split), int(cluster_size))
+                     int(cell_div_z), int(kernel), int(split), int(cluster_size), int(schedule), int(wg_per_cu))
 
 
 @dataclass

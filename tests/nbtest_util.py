@@ -49,17 +49,21 @@ def oracle_for(system, precision, rows=None):
 
 
 def gpu_eval(systems, precision, cell_div_xy=0, cell_div_z=0, kernel=H.NB_KERNEL_AUTO, energy_call=False,
-             backward=False, grad_energy=None, split=0, cluster_size=0):
+             backward=False, grad_energy=None, split=0, cluster_size=0, schedule=0, wg_per_cu=0):
     """Runs build_cells + forces (and optionally energy / backward) through the C ABI.
-    kernel "cluster8" is the cluster kernel with 8-atom clusters."""
+    kernel "cluster8" is the cluster kernel with 8-atom clusters, "cluster4_static" the
+    cluster kernel with 4-atom clusters, two items per cluster and one item per wave."""
     import torch
     if kernel == "cluster8":
         kernel, cluster_size = H.NB_KERNEL_CLUSTER, 8
+    elif kernel == "cluster4_static":
+        kernel, cluster_size, split, schedule = H.NB_KERNEL_CLUSTER, 4, 2, H.NB_SCHED_STATIC
     systems = systems if isinstance(systems, (list, tuple)) else [systems]
     dt = torch.float64 if precision == H.NB_FP64 else torch.float32
     b = H.device_batch(systems, dtype=dt)
     p = H.make_params(systems[0].cutoff, systems[0].beta, precision, cell_div_xy=cell_div_xy,
-                      cell_div_z=cell_div_z, kernel=kernel, split=split, cluster_size=cluster_size)
+                      cell_div_z=cell_div_z, kernel=kernel, split=split, cluster_size=cluster_size,
+                      schedule=schedule, wg_per_cu=wg_per_cu)
     force, energy, vir, ws = H.evaluate(b, p)
     out = dict(force=force.cpu().numpy(), energy=energy.cpu().numpy(), virial=vir.cpu().numpy(),
                batch=b, params=p, ws=ws)

@@ -85,6 +85,10 @@ def test_layout_reports_the_grid():
     (lambda s, p: setattr(p, "precision", 7), H.NB_ERR_ARG),
     (lambda s, p: setattr(p, "cell_div_xy", 9), H.NB_ERR_ARG),
     (lambda s, p: setattr(p, "kernel", 99), H.NB_ERR_ARG),
+    (lambda s, p: setattr(p, "split", 9), H.NB_ERR_ARG),
+    (lambda s, p: setattr(p, "cluster_size", 6), H.NB_ERR_ARG),
+    (lambda s, p: setattr(p, "schedule", 3), H.NB_ERR_ARG),
+    (lambda s, p: setattr(p, "wg_per_cu", 33), H.NB_ERR_ARG),
     (lambda s, p: setattr(s, "n_types", 0), H.NB_ERR_ARG),
     (lambda s, p: setattr(s, "n_types", H.NB_MAX_TYPES + 1), H.NB_ERR_ARG),
     (lambda s, p: setattr(s, "n_systems", 0), H.NB_ERR_ARG),

@@ -18,7 +18,7 @@ pytestmark = [pytest.mark.gpu,
 
 FP64_TOL = 1e-12
 MIXED_TOL = 1e-5
-KERNELS = [H.NB_KERNEL_ATOM, H.NB_KERNEL_CLUSTER, "cluster8"]
+KERNELS = [H.NB_KERNEL_ATOM, H.NB_KERNEL_CLUSTER, "cluster8", "cluster4_static"]
 
 
 def _print_case(name, **kw):
@@ -102,13 +102,29 @@ def test_split_and_cluster_size_give_the_same_forces(precision, K, chain):
     ref = U.oracle_for(chain, precision)
     tol = FP64_TOL if precision == H.NB_FP64 else MIXED_TOL
     outs = [U.gpu_eval(chain, precision, kernel=H.NB_KERNEL_CLUSTER, split=k, cluster_size=K, backward=True)
-            for k in (1, 2, 3, 4)]
+            for k in (1, 2, 3, 4, 8)]
     for o in outs:
         assert U.rel_rms(o["force"], ref["force"]) <= tol
         assert U.rel_rms(o["grad_charge"], ref["phi"]) <= tol
         assert o["energy"][0] == pytest.approx(ref["energy_total"], rel=tol)
     for o in outs[1:]:  # splitting only reorders sums
         assert U.rel_rms(o["force"], outs[0]["force"]) <= (1e-13 if precision == H.NB_FP64 else 1e-6)
+
+
+@pytest.mark.parametrize("split", [1, 3, 8])
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+def test_schedules_and_residency_give_bitwise_identical_results(precision, split, chain):
+    """Every work item writes its own output slots, so neither the schedule (one item per
+    wave, or persistent waves taking items from per-XCD counters) nor the number of
+    resident workgroups may change a single bit; repeated dynamic runs neither."""
+    runs = [U.gpu_eval(chain, precision, kernel=H.NB_KERNEL_CLUSTER, split=split, schedule=sch, wg_per_cu=w,
+                       backward=True)
+            for sch, w in [(H.NB_SCHED_STATIC, 0), (H.NB_SCHED_DYNAMIC, 1), (H.NB_SCHED_DYNAMIC, 4),
+                           (H.NB_SCHED_DYNAMIC, 16), (H.NB_SCHED_DYNAMIC, 32), (H.NB_SCHED_DYNAMIC, 4)]]
+    for o in runs[1:]:
+        for key in ("force", "energy", "virial", "grad_pos", "grad_charge", "grad_sigma", "grad_eps"):
+            np.testing.assert_array_equal(o[key], runs[0][key], err_msg=key)
+        assert o["status"] == 0
 
 
 # --- forces, energies, virial --------------------------------------------------------------
