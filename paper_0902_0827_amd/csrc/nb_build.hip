@@ -9,7 +9,11 @@
 //               also the clusters per (x, y) column and their scan -> col_clu_start
 //   k_scatter   atom -> cell_start[cell] + slot (order inside a cell still arbitrary)
 //   k_finalize  rank inside the cell by original index (makes the sort stable and the
-//               result deterministic) and write the sorted per-atom records
+//               result deterministic) and write the sorted per-atom records (the raw
+//               double-precision positions only when the FP64 path will read them)
+//
+// When the cell counts fit in LDS, k_scan and k_scatter are one launch
+// (k_scan_scatter), each workgroup scanning the counts itself.
 //
 // Positions become 32-bit box fractions u = floor(x/L * 2^32) mod 2^32, which wraps
 // every coordinate into the box; the 32-bit difference of two such values is the
@@ -28,6 +32,7 @@ namespace {
 constexpr double kTwo32 = 4294967296.0;
 constexpr int kScanBlock = 1024;
 constexpr int kScanPer = 16;  // consecutive counts per thread and pass of k_scan
+constexpr int64_t kFuseCells = 16000;  // cell_start entries that k_scan_scatter keeps in LDS (64 KB)
 
 struct DescChunk {
   SysDesc d[kDescChunk];
@@ -58,7 +63,7 @@ __global__ void k_put_desc(Dev d, DescChunk c) {
 }
 
 __global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, const double *__restrict__ eps,
-                       int kernel) {
+                       int kernel, int f64) {
   const int64_t tid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   if (tid < c.count) d.desc[c.first + tid] = c.d[tid];
@@ -66,7 +71,7 @@ __global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, con
     d.status[0] = 0u;
     d.status[1] = kBuiltMagic;
     d.status[2] = static_cast<uint32_t>(d.N);
-    d.status[3] = uses_clusters(kernel) ? 1u : 0u;
+    d.status[3] = (uses_clusters(kernel) ? kBuiltClusters : 0u) | (f64 ? kBuiltF64 : 0u);
   }
   if (tid < kXcds) d.queue[tid * kQueueStride] = 0u;
   for (int64_t k = tid; k < d.n_cells; k += stride) d.cell_count[k] = 0;
@@ -164,82 +169,92 @@ __global__ void k_bin(Dev d, const Real *__restrict__ pos, const int32_t *__rest
   }
 }
 
-// Exclusive scan of the workgroup's values v (returns this thread's prefix; *total
-// the sum of all).
-__device__ inline int block_excl_scan(int v, int *lds, int *total) {
+// Exclusive scan of count(0 .. n-1) into store(k, prefix) for k < n and store(n, total),
+// by one workgroup of kScanBlock threads.  A pass covers kScanPer rows of kScanBlock
+// consecutive entries; thread t takes entry t of every row, so that the loads and the
+// stores are coalesced.  Each row is scanned by wave shuffles; the (row, wave) totals
+// are then scanned once (kScanPer * 16 values) to give every wave of every row its
+// offset.  lds holds kScanPer * kScanBlock / 64 ints.
+template <typename Count, typename Store>
+__device__ inline void block_scan(Count count, Store store, int64_t n, int *lds) {
+  constexpr int kW = kScanBlock / 64;  // waves
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int x = v;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  if (lane == 63) lds[wave] = x;
-  __syncthreads();
-  int before = 0, all = 0;
-  for (int w = 0; w < kScanBlock / 64; ++w) {
-    const int s = lds[w];
-    before += w < wave ? s : 0;
-    all += s;
-  }
-  __syncthreads();
-  *total = all;
-  return x - v + before;
-}
-
-// Exclusive scan of count(0 .. n-1) into start[0, n] by this workgroup; each
-// thread takes kScanPer consecutive entries per pass.
-template <typename Count>
-__device__ inline void scan_array(Count count, int32_t *start, int64_t n, int *lds) {
   int run = 0;
-  if (n <= 0) {
-    if (threadIdx.x == 0) start[0] = 0;
-    return;
-  }
   for (int64_t base = 0; base < n; base += static_cast<int64_t>(kScanBlock) * kScanPer) {
-    const int64_t k0 = base + static_cast<int64_t>(threadIdx.x) * kScanPer;
-    int v[kScanPer];
-    int sum = 0;
-    // Unconditional loads (indices clamped into range) so that all of them are in
-    // flight at once; out-of-range entries are then zeroed.
+    int v[kScanPer], ex[kScanPer];
 #pragma unroll
     for (int m = 0; m < kScanPer; ++m) {
-      const int64_t k = k0 + m < n ? k0 + m : n - 1;
-      v[m] = count(k);
+      const int64_t k = base + static_cast<int64_t>(m) * kScanBlock + threadIdx.x;
+      const int x = count(k < n ? k : n - 1);  // unconditional load, zeroed below
+      v[m] = k < n ? x : 0;
     }
 #pragma unroll
     for (int m = 0; m < kScanPer; ++m) {
-      v[m] = k0 + m < n ? v[m] : 0;
-      sum += v[m];
+      int incl = v[m];
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+      }
+      ex[m] = incl - v[m];
+      if (lane == 63) lds[m * kW + wave] = incl;
     }
-    int tot;
-    int pre = block_excl_scan(sum, lds, &tot) + run;
+    __syncthreads();
+    // exclusive scan of the kScanPer * kW totals, in (row, wave) order, by the first
+    // kScanPer * kW / 64 waves; their totals go to lds[kScanPer * kW + w]
+    constexpr int kT = kScanPer * kW;
+    int tot_all = 0;
+    {
+      int x = threadIdx.x < kT ? lds[threadIdx.x] : 0;
+      int incl = x;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+      }
+      __syncthreads();
+      if (threadIdx.x < kT) lds[threadIdx.x] = incl - x;
+      if (threadIdx.x < kT && lane == 63) lds[kT + wave] = incl;
+      __syncthreads();
+      int before = 0;
+      for (int w = 0; w < kT / 64; ++w) {
+        const int t = lds[kT + w];
+        before += w < wave ? t : 0;
+        tot_all += t;
+      }
+      __syncthreads();
+      if (threadIdx.x < kT) lds[threadIdx.x] += before;
+      __syncthreads();
+    }
 #pragma unroll
     for (int m = 0; m < kScanPer; ++m) {
-      if (k0 + m < n) start[k0 + m] = pre;
-      pre += v[m];
+      const int64_t k = base + static_cast<int64_t>(m) * kScanBlock + threadIdx.x;
+      if (k < n) store(k, run + lds[m * kW + wave] + ex[m]);
     }
-    run += tot;
+    run += tot_all;
+    __syncthreads();  // lds is reused by the next pass
   }
-  if (threadIdx.x == 0) start[n] = run;
+  if (threadIdx.x == 0) store(n, run);
 }
 
 // One workgroup: cell_start from the cell counts, then (cluster kernel) the number
 // of K-atom clusters of every (x, y) column and their scan.
 __global__ void __launch_bounds__(kScanBlock) k_scan(Dev d, int clusters, int K) {
-  __shared__ int lds[kScanBlock / 64];
+  __shared__ int lds[kScanPer * kScanBlock / 64 + kScanPer * kScanBlock / 64 / 64];
   const int32_t *cnt = d.cell_count;
-  scan_array([cnt](int64_t k) { return static_cast<int>(cnt[k]); }, d.cell_start, d.n_cells, lds);
+  int32_t *cstart = d.cell_start;
+  block_scan([cnt](int64_t k) { return static_cast<int>(cnt[k]); },
+             [cstart](int64_t k, int v) { cstart[k] = v; }, d.n_cells, lds);
   if (!clusters) return;
   __syncthreads();  // cell_start is visible to the whole workgroup
   const Dev dd = d;
-  scan_array(
+  int32_t *ccs = d.col_clu_start;
+  block_scan(
       [dd, K](int64_t col) {
         const SysDesc &sd = dd.desc[column_system(dd.desc, dd.B, static_cast<int>(col))];
         const int nz = sd.dims[2];
         const int c0 = sd.cell_begin + (static_cast<int>(col) - sd.col_begin) * nz;
         return (dd.cell_start[c0 + nz] - dd.cell_start[c0] + K - 1) / K;
       },
-      d.col_clu_start, d.n_columns, lds);
+      [ccs](int64_t k, int v) { ccs[k] = v; }, d.n_columns, lds);
 }
 
 __global__ void k_scatter(Dev d) {
@@ -250,7 +265,7 @@ __global__ void k_scatter(Dev d) {
 
 template <typename Real>
 __global__ void k_finalize(Dev d, const Real *__restrict__ pos, const Real *__restrict__ charge,
-                           const int32_t *__restrict__ type, double sqrt_ke) {
+                           const int32_t *__restrict__ type, double sqrt_ke, int f64) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= d.N) return;
   const int i = d.tmp[s];
@@ -262,12 +277,49 @@ __global__ void k_finalize(Dev d, const Real *__restrict__ pos, const Real *__re
   const uint4 f = d.atom_fix[i];
   d.s_fix[dst] = make_uint4(f.x, f.y, f.z, static_cast<uint32_t>(i));
   const double q = static_cast<double>(charge[i]);
-  d.s_pos64[dst] = make_double4(static_cast<double>(pos[3 * static_cast<int64_t>(i)]),
-                                static_cast<double>(pos[3 * static_cast<int64_t>(i) + 1]),
-                                static_cast<double>(pos[3 * static_cast<int64_t>(i) + 2]), q);
+  if (f64)  // the raw positions are read by the double-precision kernels only
+    d.s_pos64[dst] = make_double4(static_cast<double>(pos[3 * static_cast<int64_t>(i)]),
+                                  static_cast<double>(pos[3 * static_cast<int64_t>(i) + 1]),
+                                  static_cast<double>(pos[3 * static_cast<int64_t>(i) + 2]), q);
   d.s_q32[dst] = static_cast<float>(q * sqrt_ke);
   int t = type[i];
   d.s_type[dst] = (t < 0 || t >= d.T) ? 0 : t;
+}
+
+// Scan and scatter in one launch, for grids whose cell counts fit in LDS: every
+// workgroup scans all the counts itself (cheaper than a launch of its own at these
+// sizes) and places its atoms; workgroup 0 also stores cell_start and the column
+// cluster starts.
+__global__ void __launch_bounds__(kScanBlock) k_scan_scatter(Dev d, int clusters, int K) {
+  extern __shared__ int cs[];  // [n_cells + 1]
+  __shared__ int lds[kScanPer * kScanBlock / 64 + kScanPer * kScanBlock / 64 / 64];
+  // this workgroup's atoms (one per thread), loaded while the counts are scanned
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kScanBlock) + threadIdx.x;
+  const bool have = i < d.N;
+  const int cell = have ? d.atom_cell[i] : 0;
+  const int slot = have ? d.atom_slot[i] : 0;
+  const int32_t *cnt = d.cell_count;
+  int *csl = cs;
+  block_scan([cnt](int64_t k) { return static_cast<int>(cnt[k]); }, [csl](int64_t k, int v) { csl[k] = v; },
+             d.n_cells, lds);
+  __syncthreads();
+  if (have) d.tmp[cs[cell] + slot] = static_cast<int32_t>(i);
+  // cell_start: each workgroup stores a slice
+  const int64_t per = (d.n_cells + 1 + gridDim.x - 1) / gridDim.x;
+  const int64_t k0 = per * blockIdx.x, k1 = k0 + per < d.n_cells + 1 ? k0 + per : d.n_cells + 1;
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += kScanBlock) d.cell_start[k] = cs[k];
+  if (clusters && blockIdx.x == gridDim.x - 1) {
+    const Dev dd = d;
+    int32_t *ccs = d.col_clu_start;
+    block_scan(
+        [dd, K, csl](int64_t col) {
+          const SysDesc &sd = dd.desc[column_system(dd.desc, dd.B, static_cast<int>(col))];
+          const int nz = sd.dims[2];
+          const int c0 = sd.cell_begin + (static_cast<int>(col) - sd.col_begin) * nz;
+          return (csl[c0 + nz] - csl[c0] + K - 1) / K;
+        },
+        [ccs](int64_t k, int v) { ccs[k] = v; }, d.n_columns, lds);
+  }
 }
 
 unsigned grid_for(int64_t n, int block) {
@@ -286,7 +338,8 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
   const int64_t init_work = plan.N > plan.n_cells ? plan.N : plan.n_cells;
   unsigned g_init = grid_for(init_work, kBlock);
   if (g_init > 4096) g_init = 4096;
-  hipLaunchKernelGGL(k_init, dim3(g_init), dim3(kBlock), 0, s, d, first, sys->lj_sigma, sys->lj_eps, plan.kernel);
+  const int f64 = plan.precision == NB_FP64 ? 1 : 0;
+  hipLaunchKernelGGL(k_init, dim3(g_init), dim3(kBlock), 0, s, d, first, sys->lj_sigma, sys->lj_eps, plan.kernel, f64);
   for (int b0 = kDescChunk; b0 < plan.B; b0 += kDescChunk) {
     DescChunk c{};
     c.first = b0;
@@ -306,15 +359,21 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
   else
     hipLaunchKernelGGL(k_bin<float>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const float *>(sys->pos),
                        sys->type, sys->excl_offset, sys->excl_index);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, s, d, clusters, plan.cluster_size);
-  hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kBlock), 0, s, d);
+  if (plan.n_cells + 1 <= kFuseCells) {
+    const unsigned gs = grid_for(plan.N, kScanBlock);
+    hipLaunchKernelGGL(k_scan_scatter, dim3(gs), dim3(kScanBlock), 4 * static_cast<size_t>(plan.n_cells + 1), s, d,
+                       clusters, plan.cluster_size);
+  } else {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, s, d, clusters, plan.cluster_size);
+    hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kBlock), 0, s, d);
+  }
   const double sqrt_ke = sqrt(plan.ke);
   if (sys->pos_is_f64)
     hipLaunchKernelGGL(k_finalize<double>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const double *>(sys->pos),
-                       static_cast<const double *>(sys->charge), sys->type, sqrt_ke);
+                       static_cast<const double *>(sys->charge), sys->type, sqrt_ke, f64);
   else
     hipLaunchKernelGGL(k_finalize<float>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const float *>(sys->pos),
-                       static_cast<const float *>(sys->charge), sys->type, sqrt_ke);
+                       static_cast<const float *>(sys->charge), sys->type, sqrt_ke, f64);
   return hipGetLastError();
 }
 

@@ -27,10 +27,13 @@ constexpr uint32_t kBuiltMagic = 0x4E424831u;  // status[1]: written by nb_build
 __host__ __device__ __forceinline__ bool uses_clusters(int kernel) { return kernel == NB_KERNEL_CLUSTER; }
 
 // Workspace header words: status[0] = NB_STATUS_* bits, status[1] = kBuiltMagic,
-// status[2] = atom count, status[3] = 1 if the cluster arrays were built.
-__device__ __forceinline__ bool built_for(const uint32_t *status, int64_t n_atoms, bool need_clusters) {
+// status[2] = atom count, status[3] = what was built (kBuiltClusters | kBuiltF64).
+constexpr uint32_t kBuiltClusters = 1u;  // column cluster arrays (cluster kernel)
+constexpr uint32_t kBuiltF64 = 2u;       // double-precision sorted positions (FP64 kernels)
+__device__ __forceinline__ bool built_for(const uint32_t *status, int64_t n_atoms, bool need_clusters,
+                                          bool need_f64) {
   return status[1] == kBuiltMagic && status[2] == static_cast<uint32_t>(n_atoms) &&
-         (!need_clusters || status[3] == 1u);
+         (!need_clusters || (status[3] & kBuiltClusters)) && (!need_f64 || (status[3] & kBuiltF64));
 }
 
 // Per-system descriptor, resident in the workspace.  Sorted atoms of system b are

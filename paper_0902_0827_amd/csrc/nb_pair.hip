@@ -23,7 +23,7 @@ template <bool F64, int MODE>
 __global__ void __launch_bounds__(kBlock) k_pair_atom(Dev d, Consts c, Out o) {
   __shared__ double red[kWaves][2 * NB_MAX_TYPES > kPart ? 2 * NB_MAX_TYPES : kPart];
   const int blk = blockIdx.x;
-  if (!built_for(d.status, d.N, false)) {
+  if (!built_for(d.status, d.N, false, F64)) {
     if (blk == 0 && threadIdx.x == 0) atomicOr(d.status, NB_STATUS_NOT_BUILT);
     return;
   }
@@ -260,7 +260,7 @@ constexpr int kReduceBlock = 1024;
 template <int NV>
 __global__ void __launch_bounds__(kReduceBlock) k_reduce_sys(Dev d, double *energy, double *virial, int cluster) {
   __shared__ double lds[kReduceBlock / 64][NV];
-  if (!built_for(d.status, d.N, cluster != 0)) return;
+  if (!built_for(d.status, d.N, cluster != 0, false)) return;
   const int b = blockIdx.x;
   const SysDesc &sd = d.desc[b];
   int lo, hi;
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce_sys(Dev d, double *ener
 __global__ void __launch_bounds__(kBlock) k_reduce_types(Dev d, const double *__restrict__ eps,
                                                          double *grad_sigma, double *grad_eps, int cluster) {
   __shared__ double lds[kWaves];
-  if (!built_for(d.status, d.N, cluster != 0)) return;
+  if (!built_for(d.status, d.N, cluster != 0, false)) return;
   const int T = d.T;
   const int t = blockIdx.x;  // 0 .. 2T-1
   const int64_t n = cluster ? d.col_clu_start[d.n_columns] : d.n_blocks;

@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
   __shared__ TabLds<F64> TL;
   __shared__ WaveLds<F64> L;
   const int lane = static_cast<int>(threadIdx.x);
-  if (!built_for(d.status, d.N, true)) {
+  if (!built_for(d.status, d.N, true, F64)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(d.status, NB_STATUS_NOT_BUILT);
     return;
   }
@@ -262,6 +262,8 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
     const uint4 fi = d.s_fix[ia];
     const int oi = static_cast<int>(fi.w);
     const uint4 mask_i = d.excl_mask[oi];
+    const uint64_t mask_lo = (static_cast<uint64_t>(mask_i.y) << 32) | mask_i.x;
+    const uint64_t mask_hi = (static_cast<uint64_t>(mask_i.w) << 32) | mask_i.z;
     const bool far_i = d.excl_far[oi] != 0u;
     const int ti = d.s_type[ia];
     double4 pi64 = make_double4(0, 0, 0, 0);
@@ -401,11 +403,17 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
         r2f = fmaf(s2z * dzf, dzf, fmaf(s2y * dyf, dyf, s2x * dxf * dxf));
         hit = ivalid && jv && r2f < c.rc2f && oi != oj;
       }
+      // Exclusions: window bit of oi for |oj - oi| <= 64 (bits 0-63: oj - oi = -64..-1,
+      // bits 64-127: 1..64), tested without branches; pairs farther apart only for atoms
+      // that carry the far flag.
       const int delta = oj - oi;
-      const bool check = hit && (static_cast<unsigned>(delta + kWindow) <= 2u * kWindow || far_i);
-      if (__ballot(check)) {
-        if (check && pair_excluded(mask_i, far_i, oi, oj, atom_begin, d.excl_far, o.excl_off, o.excl_idx))
-          hit = false;
+      const bool inwin = static_cast<unsigned>(delta + kWindow) <= 2u * kWindow;
+      const uint64_t wbits = delta < 0 ? mask_lo : mask_hi;
+      const int wb = delta < 0 ? delta + kWindow : delta - 1;
+      if (inwin && ((wbits >> (wb & 63)) & 1u)) hit = false;
+      const bool far_check = hit && !inwin && far_i;
+      if (__ballot(far_check)) {
+        if (far_check && far_excluded(oi, oj, atom_begin, d.excl_far, o.excl_off, o.excl_idx)) hit = false;
       }
       if (hit) {
         if constexpr (F64) {
@@ -548,15 +556,16 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
       phi *= c.ke;
     }
 
-    // Energy / virial sums of this item (a plain wave sum, before the row reduction).
+    // Energy / virial sums of this item (a plain wave sum, before the row reduction),
+    // one entry at a time; lane k keeps entry k.
     if constexpr (MODE == kForces || MODE == kEnergy) {
       if (o.want_part) {
-        const double v[kPart] = {0.5 * en, 0.5 * wxx, 0.5 * wxy, 0.5 * wxz, 0.5 * wxy, 0.5 * wyy,
-                                 0.5 * wyz, 0.5 * wxz, 0.5 * wyz, 0.5 * wzz};
         const int nv = (MODE == kForces && o.want_virial) ? kPart : 1;
         double mine = 0.0;
         for (int k = 0; k < nv; ++k) {
-          const double s = wave_sum(v[k]);
+          const double x = k == 0 ? en : k == 1 ? wxx : (k == 2 || k == 4) ? wxy : (k == 3 || k == 7) ? wxz
+                         : k == 5 ? wyy : (k == 6 || k == 8) ? wyz : wzz;
+          const double s = wave_sum(0.5 * x);
           if (lane == k) mine = s;
         }
         if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + m] = lane < nv ? mine : 0.0;
@@ -587,12 +596,34 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
       }
     }
 
-    // Per-atom sums of this item: rows reduced over their J lanes.
+    // Per-atom sums of this item: rows reduced over their J lanes.  With one item
+    // per cluster they are final and go straight to the caller's arrays (original
+    // atom order); otherwise to this item's part, added up by k_finish.
     fx = row_sum<J>(fx);
     fy = row_sum<J>(fy);
     fz = row_sum<J>(fz);
     const double w4 = row_sum<J>(MODE == kAdjoint ? phi : en);
-    if (jj == 0 && ivalid) d.part[static_cast<int64_t>(part) * d.N + i] = make_double4(fx, fy, fz, w4);
+    if (jj == 0 && ivalid) {
+      if (Q == 1) {
+        if constexpr (MODE == kForces) {
+          o.force[3 * static_cast<int64_t>(oi) + 0] = fx;
+          o.force[3 * static_cast<int64_t>(oi) + 1] = fy;
+          o.force[3 * static_cast<int64_t>(oi) + 2] = fz;
+        } else if constexpr (MODE == kEnergy) {
+          if (o.atom_energy) o.atom_energy[oi] = 0.5 * w4;
+        } else {
+          const double g = o.grad_energy[sys];
+          if (o.grad_pos) {
+            o.grad_pos[3 * static_cast<int64_t>(oi) + 0] = -g * fx;
+            o.grad_pos[3 * static_cast<int64_t>(oi) + 1] = -g * fy;
+            o.grad_pos[3 * static_cast<int64_t>(oi) + 2] = -g * fz;
+          }
+          if (o.grad_charge) o.grad_charge[oi] = g * w4;
+        }
+      } else {
+        d.part[static_cast<int64_t>(part) * d.N + i] = make_double4(fx, fy, fz, w4);
+      }
+    }
 
     m = -1;
     if (dynamic) {
@@ -608,50 +639,35 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
 
 // Energy (and virial) of system b: sum of the wave slots [lo, hi), in a fixed order.
 // Loads are unconditional (indices clamped) so that a thread's loads are all in flight.
-template <int NV>
-__device__ inline void sum_slots(const Dev &d, int64_t lo, int64_t hi, double *energy, double *virial, int b,
-                                 double (*lds)[kPart]) {
+// Sum of one partial component over the wave slots [lo, hi), in a fixed order.
+// Loads are unconditional (indices clamped) so that a thread's loads are all in flight.
+__device__ inline double sum_component(const double *__restrict__ vals, int64_t lo, int64_t hi,
+                                       double (*lds)[kPart]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int kUnroll = 4;
-  double acc[NV];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  constexpr int kUnroll = 8;
+  double acc = 0.0;
   for (int64_t q0 = lo + threadIdx.x; q0 < hi; q0 += kUnroll * kFinishBlock) {
-    double v[kUnroll][NV];
+    double v[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int64_t q = q0 + u * kFinishBlock;
-      const int64_t qq = q < hi ? q : lo;
-#pragma unroll
-      for (int k = 0; k < NV; ++k) v[u][k] = d.partials[static_cast<int64_t>(k) * d.n_slots + qq];
+      v[u] = vals[q < hi ? q : lo];
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const bool in = q0 + u * kFinishBlock < hi;
-#pragma unroll
-      for (int k = 0; k < NV; ++k) acc[k] += in ? v[u][k] : 0.0;
-    }
+    for (int u = 0; u < kUnroll; ++u) acc += q0 + u * kFinishBlock < hi ? v[u] : 0.0;
   }
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    const double s = wave_sum(acc[k]);
-    if (lane == 0) lds[wave][k] = s;
-  }
+  const double s = wave_sum(acc);
+  if (lane == 0) lds[wave][0] = s;
   __syncthreads();
-  if (static_cast<int>(threadIdx.x) < NV) {
-    double s = 0.0;
-    for (int wv = 0; wv < kFinishBlock / 64; ++wv) s += lds[wv][threadIdx.x];
-    if (threadIdx.x == 0) {
-      if (energy) energy[b] = s;
-    } else if (virial) {
-      virial[9 * b + (threadIdx.x - 1)] = s;
-    }
-  }
+  double t = 0.0;
+  for (int wv = 0; wv < kFinishBlock / 64; ++wv) t += lds[wv][0];
+  return t;
 }
 
 // Per-atom outputs (sum of the S parts, in order), per-system energy / virial and
-// per-type gradients, in one launch: blocks [0, nA) take atoms, the next B blocks
-// take systems, the last 2T blocks (adjoint only) take types.
+// per-type gradients, in one launch: blocks [0, nA) take atoms, the next kPart B
+// blocks take (system, energy or virial entry), the last 2T blocks (adjoint only)
+// take types.
 template <int MODE>
 __global__ void __launch_bounds__(kFinishBlock) k_finish(Dev d, Out o, int S, int nA, double *energy, double *virial,
                                                         int nv, const double *__restrict__ eps, double *grad_sigma,
@@ -659,7 +675,7 @@ __global__ void __launch_bounds__(kFinishBlock) k_finish(Dev d, Out o, int S, in
   __shared__ double lds[kFinishBlock / 64][kPart];
   // The pair kernel is complete: its work counters start again from zero next time.
   if (blockIdx.x == 0 && threadIdx.x < kXcds) d.queue[threadIdx.x * kQueueStride] = 0u;
-  if (!built_for(d.status, d.N, true)) return;
+  if (!built_for(d.status, d.N, true, false)) return;
   const int blk = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (blk < nA) {
@@ -696,21 +712,27 @@ __global__ void __launch_bounds__(kFinishBlock) k_finish(Dev d, Out o, int S, in
     }
     return;
   }
-  if (blk < nA + d.B) {
-    if (MODE == kAdjoint || nv == 0) return;
-    const int b = blk - nA;
+  if (blk < nA + kPart * d.B) {
+    const int b = (blk - nA) / kPart, k = (blk - nA) % kPart;
+    if (MODE == kAdjoint || k >= nv) return;
     const SysDesc &sd = d.desc[b];
     const int64_t lo = static_cast<int64_t>(d.col_clu_start[sd.col_begin]) * S;
     const int64_t hi = static_cast<int64_t>(d.col_clu_start[sd.col_begin + sd.dims[0] * sd.dims[1]]) * S;
-    if (nv == kPart) sum_slots<kPart>(d, lo, hi, energy, virial, b, lds);
-    else sum_slots<1>(d, lo, hi, energy, virial, b, lds);
+    const double t = sum_component(d.partials + static_cast<int64_t>(k) * d.n_slots, lo, hi, lds);
+    if (threadIdx.x == 0) {
+      if (k == 0) {
+        if (energy) energy[b] = t;
+      } else if (virial) {
+        virial[9 * b + (k - 1)] = t;
+      }
+    }
     return;
   }
   if constexpr (MODE == kAdjoint) {
     // One (sigma or eps, type) entry: sum over every wave slot of every system,
     // each scaled by its system's grad_energy.
     const int T = d.T;
-    const int t = blk - nA - d.B;
+    const int t = blk - nA - kPart * d.B;
     if (t >= 2 * T) return;
     double acc = 0.0;
     for (int b = 0; b < d.B; ++b) {
@@ -822,12 +844,13 @@ void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out
     }
     timer_after(s);
   }
-  const int nA = static_cast<int>((p.N + kFinishBlock - 1) / kFinishBlock);
+  // with one item per cluster the pair kernel has written the per-atom outputs itself
+  const int nA = p.split == 1 ? 0 : static_cast<int>((p.N + kFinishBlock - 1) / kFinishBlock);
   int nv = 0;
   if (mode == kForces) nv = o.want_part ? (virial ? kPart : 1) : 0;
   if (mode == kEnergy) nv = 1;
   const int extra = mode == kAdjoint ? ((grad_sigma || grad_eps) ? 2 * p.T : 0) : 0;
-  const dim3 fg(static_cast<unsigned>(nA + p.B + extra));
+  const dim3 fg(static_cast<unsigned>(nA + kPart * p.B + extra));
   if (mode == kForces)
     hipLaunchKernelGGL(k_finish<kForces>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
                        grad_sigma, grad_eps);

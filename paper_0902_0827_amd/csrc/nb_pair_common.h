@@ -27,14 +27,19 @@ __device__ __forceinline__ int wave_sum_int(int v) {
   return v;
 }
 
+// Inclusive prefix sum over the wave's lanes.
+__device__ __forceinline__ int wave_incl_scan_int(int v) {
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
+  }
+  return v;
+}
+
 // Exclusive prefix sum over the wave's lanes; *total receives the sum of all lanes.
 __device__ __forceinline__ int wave_excl_scan_int(int v, int *total) {
-  const int lane = static_cast<int>(threadIdx.x) & 63;
-  int incl = v;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int u = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += u;
-  }
+  const int incl = wave_incl_scan_int(v);
   *total = __shfl(incl, 63, 64);
   return incl - v;
 }
@@ -62,6 +67,20 @@ __device__ __forceinline__ bool pair_excluded(const uint4 &mask_i, bool far_i, i
     return (w >> (bit & 31)) & 1u;
   }
   if (!far_i || excl_far[oj] == 0u) return false;
+  const int il = oi - atom_begin, jl = oj - atom_begin;
+  for (int k = excl_off[oi]; k < excl_off[oi + 1]; ++k)
+    if (excl_idx[k] == jl) return true;
+  for (int k = excl_off[oj]; k < excl_off[oj + 1]; ++k)
+    if (excl_idx[k] == il) return true;
+  return false;
+}
+
+// Exclusion beyond the bitmap window: the CSR rows of both atoms are searched (only
+// called for atoms that carry the far flag).
+__device__ __forceinline__ bool far_excluded(int oi, int oj, int atom_begin, const uint32_t *__restrict__ excl_far,
+                                             const int32_t *__restrict__ excl_off,
+                                             const int32_t *__restrict__ excl_idx) {
+  if (excl_far[oj] == 0u) return false;
   const int il = oi - atom_begin, jl = oj - atom_begin;
   for (int k = excl_off[oi]; k < excl_off[oi + 1]; ++k)
     if (excl_idx[k] == jl) return true;
