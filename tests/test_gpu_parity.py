@@ -5,12 +5,15 @@ precision pair terms: per-pair relative error ~1e-7, see the erfc fit and the
 fixed-point positions); binning and exclusion windows bit-exact.
 """
 
+import functools
+
 import numpy as np
 import pytest
 
 import nbtest_util as U
 from paper_0902_0827_amd import nbhip as H
 from paper_0902_0827_amd import systems as S
+from oracle import oracle as O
 
 torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu,
@@ -399,3 +402,71 @@ def test_many_types_use_the_global_type_table(precision, kernel, chain):
     lj = np.unique(s.type)
     lj = lj[s.eps[lj] > 0]
     np.testing.assert_allclose(out["grad_sigma"][lj], ref["dsigma"][lj], rtol=max(tol * 10, 1e-10), atol=tol)
+
+
+# --- the batched form: 64 uneven replicas in one launch ---------------------------------------
+
+@functools.lru_cache(maxsize=None)
+def _replicas():
+    return S.config4()
+
+
+def test_batch64_against_sampled_oracle_and_fp64_gpu():
+    """807,400 atoms in 64 boxes of 3k-30k atoms, one build and one forces call: forces
+    of 16 sampled atoms per replica against the FP64 oracle, every atom's mixed force
+    against the FP64 GPU path on the same rounded inputs, per-replica energies."""
+    systems = list(_replicas())
+    _print_case("batch64", n=sum(s.n for s in systems))
+    mixed = U.gpu_eval(systems, H.NB_MIXED)
+    rounded = [s.rounded(np.float32) for s in systems]
+    fp64 = U.gpu_eval(rounded, H.NB_FP64, energy_call=True)
+    assert mixed["status"] == 0 and fp64["status"] == 0
+    err = U.rel_rms(mixed["force"], fp64["force"])
+    print(f"  mixed vs fp64 gpu rel_rms={err:.3e}")
+    assert err <= MIXED_TOL
+    # A replica's real-space energy is a sum of per-atom energies of both signs that
+    # nearly cancel (totals of a few hundred kJ/mol against sums of |E_i| near 1e5), so
+    # the single-precision pair terms' error is bounded on the scale of the summands.
+    off = np.concatenate([[0], np.cumsum([s.n for s in systems])])
+    scale = np.array([np.abs(fp64["atom_energy"][off[k]:off[k + 1]]).sum() for k in range(len(systems))])
+    dev = np.abs(mixed["energy"] - fp64["energy"]) / scale
+    print(f"  energy |mixed - fp64| / sum|E_i| max={dev.max():.3e}")
+    assert dev.max() <= MIXED_TOL
+    rng = np.random.default_rng(4)
+    off = 0
+    num = den = 0.0
+    for s in rounded:
+        rows = np.sort(rng.choice(s.n, 16, replace=False))
+        ref = O.evaluate_system(s, rows=rows, ke=H.COULOMB_K)
+        assert U.rel_rms(fp64["force"][off + rows], ref["force"]) <= FP64_TOL
+        num += float(np.sum((mixed["force"][off + rows] - ref["force"]) ** 2))
+        den += float(np.sum(ref["force"] ** 2))
+        off += s.n
+    assert np.sqrt(num / den) <= MIXED_TOL
+
+
+@pytest.mark.parametrize("sched", [H.NB_SCHED_STATIC, H.NB_SCHED_DYNAMIC])
+def test_batch64_subset_equals_each_replica_alone(sched):
+    systems = list(_replicas())
+    order = np.argsort([s.n for s in systems])
+    pick = [systems[k] for k in (order[0], order[20], order[45], order[-1])]
+    out = U.gpu_eval(pick, H.NB_MIXED, schedule=sched, split=2)
+    off = np.concatenate([[0], np.cumsum([s.n for s in pick])])
+    for k, s in enumerate(pick):
+        alone = U.gpu_eval(s, H.NB_MIXED, schedule=sched, split=2)
+        np.testing.assert_array_equal(out["force"][off[k]:off[k + 1]], alone["force"])
+        assert out["energy"][k] == alone["energy"][0]
+
+
+def test_autotuner_choice_is_correct_and_cached(chain, tmp_path, monkeypatch):
+    from paper_0902_0827_amd import autotune as A
+    monkeypatch.setenv(A.CACHE_ENV, str(tmp_path / "tune.json"))
+    b = H.device_batch([chain], dtype=torch.float32)
+    p, rec = A.tune(b, chain.cutoff, chain.beta, H.NB_MIXED, reps=3, warmup=1, budget_s=20.0)
+    assert len(rec["tried"]) >= 5 and not rec.get("cached")
+    force, energy, vir, ws = H.evaluate(b, p)
+    ref = U.oracle_for(chain, H.NB_MIXED)
+    assert U.rel_rms(force.cpu().numpy(), ref["force"]) <= MIXED_TOL
+    assert H.read_status(ws) == 0
+    p2, rec2 = A.tune(b, chain.cutoff, chain.beta, H.NB_MIXED)
+    assert rec2.get("cached") and all(getattr(p2, k) == getattr(p, k) for k in A.PARAM_KEYS)
