@@ -38,6 +38,7 @@ namespace {
 constexpr int kRing = 128;           // ring buffer of staged j atoms (power of two)
 constexpr int kTabLds = 16;          // type tables up to 16 x 16 are copied to LDS
 constexpr int kMaxRuns = 2 * 9 * 9;  // up to 9 x 9 neighbour columns, <= 2 z-runs each
+constexpr int kRunPad = 4;           // sentinel entries after the last run
 constexpr int kFinishBlock = 256;
 
 __device__ __forceinline__ uint32_t uabs_diff(uint32_t a, uint32_t b) {
@@ -115,14 +116,14 @@ template <>
 struct WaveLds<false> {
   uint4 fix[kRing];  // fixed-point x, y, z, original index
   float2 qt[kRing];  // q * sqrt(k_e), type (as int bits)
-  int2 runs[kMaxRuns + 1];  // non-empty candidate runs: (first sorted atom, first candidate position)
+  int2 runs[kMaxRuns + kRunPad];  // non-empty candidate runs: (first sorted atom, first candidate position)
 };
 
 template <>
 struct WaveLds<true> {
   double4 pos[kRing];  // x, y, z, q
   int2 meta[kRing];    // original index, type
-  int2 runs[kMaxRuns + 1];  // non-empty candidate runs: (first sorted atom, first candidate position)
+  int2 runs[kMaxRuns + kRunPad];  // non-empty candidate runs: (first sorted atom, first candidate position)
 };
 
 template <bool F64>
@@ -343,7 +344,7 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
       nrun += cnt_tot;
       total += len_tot;
     }
-    if (lane == 0) L.runs[nrun] = make_int2(0, total);  // sentinel
+    if (lane < kRunPad) L.runs[nrun + lane] = make_int2(0, total);  // sentinels
     // This item's share of the candidates, [lo_c, hi_c).
     const int lo_c = static_cast<int>((static_cast<int64_t>(total) * part) / Q);
     const int hi_c = static_cast<int>((static_cast<int64_t>(total) * (part + 1)) / Q);
@@ -469,16 +470,25 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
     // Walk this item's candidates 64 at a time; the next chunk's loads are issued
     // before the current chunk is filtered and evaluated, to hide their latency.
     int run0 = 0;  // wave-uniform: the run holding the next chunk's first candidate
+    // A chunk of 64 candidates rarely spans more than three runs: the run entries
+    // run0 .. run0 + 3 are read at once (wave-uniform addresses) and each lane picks
+    // its run by comparisons; the rare lane beyond them walks on.  The next chunk
+    // starts in the run of this chunk's last lane or a later one.
     auto load = [&](int P, uint4 &f, int &t, float &q, double4 &p, bool &v) {
       while (L.runs[run0 + 1].y <= P) ++run0;
+      const int2 ra = L.runs[run0], rb = L.runs[run0 + 1], rc = L.runs[run0 + 2], rd = L.runs[run0 + 3];
       const int pos = P + lane;
       v = pos < hi_c;
       int r = run0;
-      int2 cur = L.runs[r];
-      if (v) {
+      int2 cur = ra;
+      if (pos >= rb.y) { cur = rb; r = run0 + 1; }
+      if (pos >= rc.y) { cur = rc; r = run0 + 2; }
+      if (pos >= rd.y) { cur = rd; r = run0 + 3; }
+      if (v && r == run0 + 3) {
         while (L.runs[r + 1].y <= pos) cur = L.runs[++r];
       }
-      const int aa = v ? cur.x + (pos - cur.y) : L.runs[run0].x + (P - L.runs[run0].y);
+      const int aa = v ? cur.x + (pos - cur.y) : ra.x + (P - ra.y);
+      run0 = __builtin_amdgcn_readlane(v ? r : run0, 63);
       f = d.s_fix[aa];
       t = d.s_type[aa];
       if constexpr (F64) p = d.s_pos64[aa];
@@ -560,15 +570,23 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
     // one entry at a time; lane k keeps entry k.
     if constexpr (MODE == kForces || MODE == kEnergy) {
       if (o.want_part) {
-        const int nv = (MODE == kForces && o.want_virial) ? kPart : 1;
         double mine = 0.0;
-        for (int k = 0; k < nv; ++k) {
-          const double x = k == 0 ? en : k == 1 ? wxx : (k == 2 || k == 4) ? wxy : (k == 3 || k == 7) ? wxz
-                         : k == 5 ? wyy : (k == 6 || k == 8) ? wyz : wzz;
-          const double s = wave_sum(0.5 * x);
-          if (lane == k) mine = s;
+        if (MODE == kForces && o.want_virial) {
+          // the seven distinct entries summed together, one butterfly step at a time
+          double v[7] = {0.5 * en, 0.5 * wxx, 0.5 * wxy, 0.5 * wxz, 0.5 * wyy, 0.5 * wyz, 0.5 * wzz};
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) v[k] += __shfl_xor(v[k], off, 64);
+          }
+          // entry order: energy, xx, xy, xz, yx, yy, yz, zx, zy, zz
+          mine = lane == 0 ? v[0] : lane == 1 ? v[1] : (lane == 2 || lane == 4) ? v[2]
+               : (lane == 3 || lane == 7) ? v[3] : lane == 5 ? v[4] : (lane == 6 || lane == 8) ? v[5] : v[6];
+          if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + m] = mine;
+        } else {
+          mine = wave_sum(0.5 * en);
+          if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + m] = lane == 0 ? mine : 0.0;
         }
-        if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + m] = lane < nv ? mine : 0.0;
       }
     }
     if constexpr (MODE == kAdjoint) {
