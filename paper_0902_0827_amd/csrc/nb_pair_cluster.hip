@@ -266,6 +266,7 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
     const uint64_t mask_lo = (static_cast<uint64_t>(mask_i.y) << 32) | mask_i.x;
     const uint64_t mask_hi = (static_cast<uint64_t>(mask_i.w) << 32) | mask_i.z;
     const bool far_i = d.excl_far[oi] != 0u;
+    const bool any_far = __ballot(ivalid && far_i) != 0;
     const int ti = d.s_type[ia];
     double4 pi64 = make_double4(0, 0, 0, 0);
     float qi32 = 0.f;
@@ -408,12 +409,13 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
       // bits 64-127: 1..64), tested without branches; pairs farther apart only for atoms
       // that carry the far flag.
       const int delta = oj - oi;
-      const bool inwin = static_cast<unsigned>(delta + kWindow) <= 2u * kWindow;
+      const uint32_t inwin = static_cast<unsigned>(delta + kWindow) <= 2u * kWindow ? 1u : 0u;
       const uint64_t wbits = delta < 0 ? mask_lo : mask_hi;
       const int wb = delta < 0 ? delta + kWindow : delta - 1;
-      if (inwin && ((wbits >> (wb & 63)) & 1u)) hit = false;
-      const bool far_check = hit && !inwin && far_i;
-      if (__ballot(far_check)) {
+      const uint32_t excluded = static_cast<uint32_t>(wbits >> (wb & 63)) & inwin;
+      hit = hit && (excluded & 1u) == 0u;
+      if (any_far) {  // wave-uniform: some atom of this cluster has an exclusion beyond the window
+        const bool far_check = hit && !inwin && far_i;
         if (far_check && far_excluded(oi, oj, atom_begin, d.excl_far, o.excl_off, o.excl_idx)) hit = false;
       }
       if (hit) {
