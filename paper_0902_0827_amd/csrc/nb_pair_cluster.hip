@@ -292,8 +292,9 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
         cc[a] = base3[a] + static_cast<uint32_t>(static_cast<int32_t>(mid));
         hh[a] = static_cast<uint32_t>(h);
       }
-      ctr = make_uint4(cc[0], cc[1], cc[2], 0u);
-      half = make_uint4(hh[0], hh[1], hh[2], 0u);
+      // wave-uniform (every row reduced to the same box): keep it in scalar registers
+      ctr = make_uint4(uni(static_cast<int>(cc[0])), uni(static_cast<int>(cc[1])), uni(static_cast<int>(cc[2])), 0u);
+      half = make_uint4(uni(static_cast<int>(hh[0])), uni(static_cast<int>(hh[1])), uni(static_cast<int>(hh[2])), 0u);
     }
 
     const int kx = uni(sd.reach[0]), ky = uni(sd.reach[1]), kz = uni(sd.reach[2]);
@@ -358,12 +359,10 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
     double phi = 0, asig = 0, beps = 0;
     float sfx = 0, sfy = 0, sfz = 0, sen = 0, swxx = 0, swxy = 0, swxz = 0, swyy = 0, swyz = 0, swzz = 0;
     float sphi = 0, sasig = 0, sbeps = 0;
-    auto flush = [&]() {
-      if constexpr (!F64) {
-        fx = sfx; fy = sfy; fz = sfz; en = sen;
-        wxx = swxx; wxy = swxy; wxz = swxz; wyy = swyy; wyz = swyz; wzz = swzz;
-        phi = sphi; asig = sasig; beps = sbeps;
-      }
+    // an accumulator as double: the FP64 path's own, or the mixed path's single-precision one
+    auto D = [&](double dv, float fv) -> double {
+      if constexpr (F64) return dv;
+      else return static_cast<double>(fv);
     };
 
     uint32_t head = 0, tail = 0;  // wave-uniform ring positions
@@ -550,51 +549,22 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
       valid = valid_n;
     }
     if (tail != head) process_group(static_cast<int>(tail - head));
-    flush();
     if (dynamic && !requested && !(closed & (1u << home))) {  // an item without candidates
       pending = request(home);
       have_pending = true;
     }
 
-    if constexpr (!F64) {
-      // fixed-point units -> Angstrom; phi carries one sqrt(k_e) from q'_j.
-      fx *= sd.scale[0];
-      fy *= sd.scale[1];
-      fz *= sd.scale[2];
-      wxx *= sd.scale[0] * sd.scale[0]; wxy *= sd.scale[0] * sd.scale[1]; wxz *= sd.scale[0] * sd.scale[2];
-      wyy *= sd.scale[1] * sd.scale[1]; wyz *= sd.scale[1] * sd.scale[2]; wzz *= sd.scale[2] * sd.scale[2];
-      phi *= c.sqrt_ke;
-    } else {
-      phi *= c.ke;
-    }
+    // Mixed path: fixed-point units -> Angstrom, and phi carries one sqrt(k_e) from q'_j.
+    // The single-precision sums become double only where they are reduced, so that
+    // few of them are live in double at a time.
+    const double scx = F64 ? 1.0 : uni(sd.scale[0]), scy = F64 ? 1.0 : uni(sd.scale[1]),
+                 scz = F64 ? 1.0 : uni(sd.scale[2]);
+    const double phi_scale = F64 ? c.ke : c.sqrt_ke;
 
-    // Energy / virial sums of this item (a plain wave sum, before the row reduction),
-    // one entry at a time; lane k keeps entry k.
-    if constexpr (MODE == kForces || MODE == kEnergy) {
-      if (o.want_part) {
-        double mine = 0.0;
-        if (MODE == kForces && o.want_virial) {
-          // the seven distinct entries summed together, one butterfly step at a time
-          double v[7] = {0.5 * en, 0.5 * wxx, 0.5 * wxy, 0.5 * wxz, 0.5 * wyy, 0.5 * wyz, 0.5 * wzz};
-#pragma unroll
-          for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-            for (int k = 0; k < 7; ++k) v[k] += __shfl_xor(v[k], off, 64);
-          }
-          // entry order: energy, xx, xy, xz, yx, yy, yz, zx, zy, zz
-          mine = lane == 0 ? v[0] : lane == 1 ? v[1] : (lane == 2 || lane == 4) ? v[2]
-               : (lane == 3 || lane == 7) ? v[3] : lane == 5 ? v[4] : (lane == 6 || lane == 8) ? v[5] : v[6];
-          if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + m] = mine;
-        } else {
-          mine = wave_sum(0.5 * en);
-          if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + m] = lane == 0 ? mine : 0.0;
-        }
-      }
-    }
     if constexpr (MODE == kAdjoint) {
       // Per-type sums of the sigma / eps partials over this item's rows (scaled by the
       // system's grad_energy in k_finish).
-      const double a_l = 0.5 * asig, b_l = 0.5 * beps;
+      const double a_l = 0.5 * D(asig, sasig), b_l = 0.5 * D(beps, sbeps);
       const int my_t = ivalid ? ti : -1;
       double keep_a = 0.0, keep_b = 0.0;
       uint64_t left_t = __ballot(my_t >= 0);
@@ -619,10 +589,10 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
     // Per-atom sums of this item: rows reduced over their J lanes.  With one item
     // per cluster they are final and go straight to the caller's arrays (original
     // atom order); otherwise to this item's part, added up by k_finish.
-    fx = row_sum<J>(fx);
-    fy = row_sum<J>(fy);
-    fz = row_sum<J>(fz);
-    const double w4 = row_sum<J>(MODE == kAdjoint ? phi : en);
+    fx = row_sum<J>(D(fx, sfx)) * scx;
+    fy = row_sum<J>(D(fy, sfy)) * scy;
+    fz = row_sum<J>(D(fz, sfz)) * scz;
+    const double w4 = MODE == kAdjoint ? row_sum<J>(D(phi, sphi)) * phi_scale : row_sum<J>(D(en, sen));
     if (jj == 0 && ivalid) {
       if (Q == 1) {
         if constexpr (MODE == kForces) {
@@ -645,6 +615,31 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
       }
     }
 
+    // Energy / virial sums of this item (a plain wave sum, before the row reduction),
+    // one entry at a time; lane k keeps entry k.
+    if constexpr (MODE == kForces || MODE == kEnergy) {
+      if (o.want_part) {
+        double mine = 0.0;
+        if (MODE == kForces && o.want_virial) {
+          // the seven distinct entries summed together, one butterfly step at a time
+          double v[7] = {0.5 * D(en, sen), 0.5 * scx * scx * D(wxx, swxx), 0.5 * scx * scy * D(wxy, swxy),
+                         0.5 * scx * scz * D(wxz, swxz), 0.5 * scy * scy * D(wyy, swyy),
+                         0.5 * scy * scz * D(wyz, swyz), 0.5 * scz * scz * D(wzz, swzz)};
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) v[k] += __shfl_xor(v[k], off, 64);
+          }
+          // entry order: energy, xx, xy, xz, yx, yy, yz, zx, zy, zz
+          mine = lane == 0 ? v[0] : lane == 1 ? v[1] : (lane == 2 || lane == 4) ? v[2]
+               : (lane == 3 || lane == 7) ? v[3] : lane == 5 ? v[4] : (lane == 6 || lane == 8) ? v[5] : v[6];
+          if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + m] = mine;
+        } else {
+          mine = wave_sum(0.5 * D(en, sen));
+          if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + m] = lane == 0 ? mine : 0.0;
+        }
+      }
+    }
     m = -1;
     if (dynamic) {
       if (have_pending) {
