@@ -170,52 +170,60 @@ __global__ void k_bin(Dev d, const Real *__restrict__ pos, const int32_t *__rest
 }
 
 // Exclusive scan of count(0 .. n-1) into store(k, prefix) for k < n and store(n, total),
-// by one workgroup of kScanBlock threads.  A pass covers kScanPer rows of kScanBlock
+// by one workgroup of kScanBlock threads.  A pass covers Rows rows of kScanBlock
 // consecutive entries; thread t takes entry t of every row, so that the loads and the
-// stores are coalesced.  Each row is scanned by wave shuffles; the (row, wave) totals
-// are then scanned once (kScanPer * 16 values) to give every wave of every row its
-// offset.  lds holds kScanPer * kScanBlock / 64 ints.
-template <typename Count, typename Store>
+// stores are coalesced.  Each row is scanned by wave shuffles (rows past n are
+// skipped); the (row, wave) totals are then scanned once to give every wave of every
+// row its offset.  lds holds block_scan_lds<Rows>() ints.
+template <int Rows>
+constexpr int block_scan_lds() {
+  return Rows * (kScanBlock / 64) + (Rows * (kScanBlock / 64) + 63) / 64;
+}
+
+template <int Rows, typename Count, typename Store>
 __device__ inline void block_scan(Count count, Store store, int64_t n, int *lds) {
   constexpr int kW = kScanBlock / 64;  // waves
+  constexpr int kT = Rows * kW;        // (row, wave) totals per pass
+  constexpr int kTW = (kT + 63) / 64;  // waves that scan them
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int run = 0;
-  for (int64_t base = 0; base < n; base += static_cast<int64_t>(kScanBlock) * kScanPer) {
-    int v[kScanPer], ex[kScanPer];
+  for (int64_t base = 0; base < n; base += static_cast<int64_t>(kScanBlock) * Rows) {
+    int v[Rows], ex[Rows];
 #pragma unroll
-    for (int m = 0; m < kScanPer; ++m) {
+    for (int m = 0; m < Rows; ++m) {
       const int64_t k = base + static_cast<int64_t>(m) * kScanBlock + threadIdx.x;
       const int x = count(k < n ? k : n - 1);  // unconditional load, zeroed below
       v[m] = k < n ? x : 0;
     }
 #pragma unroll
-    for (int m = 0; m < kScanPer; ++m) {
+    for (int m = 0; m < Rows; ++m) {
       int incl = v[m];
-      for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += y;
+      if (base + static_cast<int64_t>(m) * kScanBlock < n) {  // wave-uniform
+        for (int off = 1; off < 64; off <<= 1) {
+          const int y = __shfl_up(incl, off, 64);
+          if (lane >= off) incl += y;
+        }
       }
       ex[m] = incl - v[m];
       if (lane == 63) lds[m * kW + wave] = incl;
     }
     __syncthreads();
-    // exclusive scan of the kScanPer * kW totals, in (row, wave) order, by the first
-    // kScanPer * kW / 64 waves; their totals go to lds[kScanPer * kW + w]
-    constexpr int kT = kScanPer * kW;
     int tot_all = 0;
     {
       int x = threadIdx.x < kT ? lds[threadIdx.x] : 0;
       int incl = x;
-      for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += y;
+      if (wave < kTW) {
+        for (int off = 1; off < 64; off <<= 1) {
+          const int y = __shfl_up(incl, off, 64);
+          if (lane >= off) incl += y;
+        }
       }
       __syncthreads();
       if (threadIdx.x < kT) lds[threadIdx.x] = incl - x;
-      if (threadIdx.x < kT && lane == 63) lds[kT + wave] = incl;
+      if (wave < kTW && lane == 63) lds[kT + wave] = incl;
       __syncthreads();
       int before = 0;
-      for (int w = 0; w < kT / 64; ++w) {
+      for (int w = 0; w < kTW; ++w) {
         const int t = lds[kT + w];
         before += w < wave ? t : 0;
         tot_all += t;
@@ -225,7 +233,7 @@ __device__ inline void block_scan(Count count, Store store, int64_t n, int *lds)
       __syncthreads();
     }
 #pragma unroll
-    for (int m = 0; m < kScanPer; ++m) {
+    for (int m = 0; m < Rows; ++m) {
       const int64_t k = base + static_cast<int64_t>(m) * kScanBlock + threadIdx.x;
       if (k < n) store(k, run + lds[m * kW + wave] + ex[m]);
     }
@@ -235,26 +243,46 @@ __device__ inline void block_scan(Count count, Store store, int64_t n, int *lds)
   if (threadIdx.x == 0) store(n, run);
 }
 
+// Clusters of K atoms in column `col` (ceil of its atom count over K), from cell starts
+// held in `cs` (any address space).  A single system's descriptor is read once.
+struct ColumnClusters {
+  const SysDesc *desc;
+  int B, K;
+  int cell_begin0, col_begin0, nz0;
+  __device__ ColumnClusters(const Dev &d, int k) : desc(d.desc), B(d.B), K(k) {
+    cell_begin0 = d.desc[0].cell_begin;
+    col_begin0 = d.desc[0].col_begin;
+    nz0 = d.desc[0].dims[2];
+  }
+  template <typename Starts>
+  __device__ int operator()(const Starts &cs, int col) const {
+    int cb = cell_begin0, cbeg = col_begin0, nz = nz0;
+    if (B > 1) {
+      const SysDesc &sd = desc[column_system(desc, B, col)];
+      cb = sd.cell_begin;
+      cbeg = sd.col_begin;
+      nz = sd.dims[2];
+    }
+    const int c0 = cb + (col - cbeg) * nz;
+    return (cs[c0 + nz] - cs[c0] + K - 1) / K;
+  }
+};
+
 // One workgroup: cell_start from the cell counts, then (cluster kernel) the number
 // of K-atom clusters of every (x, y) column and their scan.
 __global__ void __launch_bounds__(kScanBlock) k_scan(Dev d, int clusters, int K) {
-  __shared__ int lds[kScanPer * kScanBlock / 64 + kScanPer * kScanBlock / 64 / 64];
+  __shared__ int lds[block_scan_lds<kScanPer>()];
   const int32_t *cnt = d.cell_count;
   int32_t *cstart = d.cell_start;
-  block_scan([cnt](int64_t k) { return static_cast<int>(cnt[k]); },
-             [cstart](int64_t k, int v) { cstart[k] = v; }, d.n_cells, lds);
+  block_scan<kScanPer>([cnt](int64_t k) { return static_cast<int>(cnt[k]); },
+                       [cstart](int64_t k, int v) { cstart[k] = v; }, d.n_cells, lds);
   if (!clusters) return;
   __syncthreads();  // cell_start is visible to the whole workgroup
-  const Dev dd = d;
+  const ColumnClusters cc(d, K);
+  const int32_t *cs = d.cell_start;
   int32_t *ccs = d.col_clu_start;
-  block_scan(
-      [dd, K](int64_t col) {
-        const SysDesc &sd = dd.desc[column_system(dd.desc, dd.B, static_cast<int>(col))];
-        const int nz = sd.dims[2];
-        const int c0 = sd.cell_begin + (static_cast<int>(col) - sd.col_begin) * nz;
-        return (dd.cell_start[c0 + nz] - dd.cell_start[c0] + K - 1) / K;
-      },
-      [ccs](int64_t k, int v) { ccs[k] = v; }, d.n_columns, lds);
+  block_scan<1>([cc, cs](int64_t col) { return cc(cs, static_cast<int>(col)); },
+                [ccs](int64_t k, int v) { ccs[k] = v; }, d.n_columns, lds);
 }
 
 __global__ void k_scatter(Dev d) {
@@ -292,16 +320,17 @@ __global__ void k_finalize(Dev d, const Real *__restrict__ pos, const Real *__re
 // cluster starts.
 __global__ void __launch_bounds__(kScanBlock) k_scan_scatter(Dev d, int clusters, int K) {
   extern __shared__ int cs[];  // [n_cells + 1]
-  __shared__ int lds[kScanPer * kScanBlock / 64 + kScanPer * kScanBlock / 64 / 64];
+  __shared__ int lds[block_scan_lds<kScanPer>()];
   // this workgroup's atoms (one per thread), loaded while the counts are scanned
   const int64_t i = blockIdx.x * static_cast<int64_t>(kScanBlock) + threadIdx.x;
   const bool have = i < d.N;
   const int cell = have ? d.atom_cell[i] : 0;
   const int slot = have ? d.atom_slot[i] : 0;
+  const ColumnClusters cc(d, K);
   const int32_t *cnt = d.cell_count;
   int *csl = cs;
-  block_scan([cnt](int64_t k) { return static_cast<int>(cnt[k]); }, [csl](int64_t k, int v) { csl[k] = v; },
-             d.n_cells, lds);
+  block_scan<kScanPer>([cnt](int64_t k) { return static_cast<int>(cnt[k]); },
+                       [csl](int64_t k, int v) { csl[k] = v; }, d.n_cells, lds);
   __syncthreads();
   if (have) d.tmp[cs[cell] + slot] = static_cast<int32_t>(i);
   // cell_start: each workgroup stores a slice
@@ -309,16 +338,9 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_scatter(Dev d, int clusters
   const int64_t k0 = per * blockIdx.x, k1 = k0 + per < d.n_cells + 1 ? k0 + per : d.n_cells + 1;
   for (int64_t k = k0 + threadIdx.x; k < k1; k += kScanBlock) d.cell_start[k] = cs[k];
   if (clusters && blockIdx.x == gridDim.x - 1) {
-    const Dev dd = d;
     int32_t *ccs = d.col_clu_start;
-    block_scan(
-        [dd, K, csl](int64_t col) {
-          const SysDesc &sd = dd.desc[column_system(dd.desc, dd.B, static_cast<int>(col))];
-          const int nz = sd.dims[2];
-          const int c0 = sd.cell_begin + (static_cast<int>(col) - sd.col_begin) * nz;
-          return (csl[c0 + nz] - csl[c0] + K - 1) / K;
-        },
-        [ccs](int64_t k, int v) { ccs[k] = v; }, d.n_columns, lds);
+    block_scan<1>([cc, csl](int64_t col) { return cc(csl, static_cast<int>(col)); },
+                  [ccs](int64_t k, int v) { ccs[k] = v; }, d.n_columns, lds);
   }
 }
 
