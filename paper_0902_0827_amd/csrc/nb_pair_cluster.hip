@@ -26,6 +26,8 @@
 // Full shell (every pair is evaluated from both sides), as in the paper.
 #include <map>
 #include <mutex>
+#include <tuple>
+#include <type_traits>
 #include <utility>
 
 #include "nb_pair_common.h"
@@ -126,15 +128,15 @@ struct WaveLds<true> {
   int2 runs[kMaxRuns + kRunPad];  // non-empty candidate runs: (first sorted atom, first candidate position)
 };
 
+// Type-pair table entry of each precision; the table is copied into dynamic LDS sized
+// for the system's own type count (T x T entries).
 template <bool F64>
-struct TabLds {
-  TypePair32 tab[kTabLds * kTabLds];
-};
+using TypePairT = std::conditional_t<F64, TypePair64, TypePair32>;
 
-template <>
-struct TabLds<true> {
-  TypePair64 tab[kTabLds * kTabLds];
-};
+template <bool F64>
+constexpr size_t tab_lds_bytes(int T) {
+  return static_cast<size_t>(T) * static_cast<size_t>(T) * sizeof(TypePairT<F64>);
+}
 
 // Orders this wave's LDS accesses (one wave's LDS operations execute in issue order;
 // this only stops the compiler from moving them across the point).
@@ -169,8 +171,9 @@ __device__ __forceinline__ int xcd_id() {
 template <bool F64, int MODE, bool TABLDS, int K>
 __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   constexpr int J = 64 / K;  // j atoms per group (lanes per row)
-  __shared__ TabLds<F64> TL;
+  extern __shared__ uint4 tab_lds[];  // [T * T] type pairs when TABLDS
   __shared__ WaveLds<F64> L;
+  TypePairT<F64> *const TL = reinterpret_cast<TypePairT<F64> *>(tab_lds);
   const int lane = static_cast<int>(threadIdx.x);
   if (!built_for(d.status, d.N, true, F64)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(d.status, NB_STATUS_NOT_BUILT);
@@ -180,8 +183,8 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
   const int T = d.T;
   if constexpr (TABLDS) {
     for (int k = lane; k < T * T; k += 64) {
-      if constexpr (F64) TL.tab[k] = d.tab64[k];
-      else TL.tab[k] = d.tab32[k];
+      if constexpr (F64) TL[k] = d.tab64[k];
+      else TL[k] = d.tab32[k];
     }
     wave_lds_sync();
   }
@@ -420,7 +423,7 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
       if (hit) {
         if constexpr (F64) {
           TypePair64 tp;
-          if constexpr (TABLDS) tp = TL.tab[ti * T + tj];
+          if constexpr (TABLDS) tp = TL[ti * T + tj];
           else tp = d.tab64[ti * T + tj];
           const PairF64 p = pair_f64(r2d, tp.c6, tp.c12, qi64 * pj64.w, c.beta, c.two_beta_sqrtpi);
           en += p.u_lj + p.u_c;
@@ -442,7 +445,7 @@ __global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int
           }
         } else {
           TypePair32 tp;
-          if constexpr (TABLDS) tp = TL.tab[ti * T + tj];
+          if constexpr (TABLDS) tp = TL[ti * T + tj];
           else tp = d.tab32[ti * T + tj];
           const PairF32 p = pair_f32(r2f, tp.c6, tp.c12, qi32 * qj, c.betaf, c.two_beta_sqrtpif, c.mb2l2e);
           sen += p.u_lj + p.u_c;
@@ -797,17 +800,18 @@ int compute_units() {
 
 // Workgroups of a kernel that fit on one compute unit at once (cached per kernel and device).
 template <typename Query>
-int resident_workgroups(const void *kern, Query query) {
+int resident_workgroups(const void *kern, size_t lds_bytes, Query query) {
   static std::mutex mu;
-  static std::map<std::pair<const void *, int>, int> cache;
+  static std::map<std::tuple<const void *, int, size_t>, int> cache;
   int dev = 0;
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lock(mu);
-  auto it = cache.find({kern, dev});
+  const auto key = std::make_tuple(kern, dev, lds_bytes);
+  auto it = cache.find(key);
   if (it != cache.end()) return it->second;
   int n = 0;
   if (query(&n) != hipSuccess || n < 1) n = 1;
-  cache[{kern, dev}] = n;
+  cache[key] = n;
   return n;
 }
 
@@ -815,17 +819,18 @@ template <bool F64, bool TABLDS, int K>
 void launch_cluster_mode(int mode, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s, const Dev &d, const Consts &c,
                          const Out &o, int Q) {
   const dim3 block(64);
+  const size_t lds = TABLDS ? tab_lds_bytes<F64>(d.T) : 0;
   auto go = [&](auto kern) {
     int64_t g = wgs;
     if (dyn) {
       // persistent grid: what fits on the device at once (at most wg_per_cu per CU)
-      const int fit = resident_workgroups(reinterpret_cast<const void *>(kern), [&](int *n) {
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, kern, 64, 0);
+      const int fit = resident_workgroups(reinterpret_cast<const void *>(kern), lds, [&](int *n) {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, kern, 64, lds);
       });
       g = std::min<int64_t>(g, static_cast<int64_t>(compute_units()) * std::min(fit, wg_per_cu));
     }
     g = std::max<int64_t>((g + kXcds - 1) / kXcds * kXcds, kXcds);  // a multiple of the XCD count
-    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(g)), block, 0, s, d, c, o, Q, dyn);
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(g)), block, lds, s, d, c, o, Q, dyn);
   };
   if (mode == kForces) go(k_pair_cluster<F64, kForces, TABLDS, K>);
   else if (mode == kEnergy) go(k_pair_cluster<F64, kEnergy, TABLDS, K>);
