@@ -73,8 +73,8 @@ __device__ __forceinline__ PairF32 pair_f32(float r2, float c6, float c12, float
 // erfc(x) = exp(-x^2) * g(x) in double precision, with g a polynomial of degree 24 in
 // s = (x - 3)/(x + 3), which maps x in [0, inf) onto [-1, 1): a Chebyshev interpolant
 // of g converted to monomial form (gen_erfc_coeffs.py --f64).  Relative error of g
-// below 4e-16 for 0 <= x <= 10 and below 3e-15 up to x = 30, with one branch-free
-// division and a Horner chain.
+// below 4e-16 for 0 <= x <= 10 and below 3e-15 up to x = 30, with one reciprocal (hardware
+// estimate and two Newton steps; x + 3 >= 3 has no special cases) and a Horner chain.
 static __constant__ double kErfcxS[25] = {
     1.79001151181389956e-01,
     -3.26233560043037163e-01,
@@ -109,7 +109,12 @@ __device__ __forceinline__ double erfcx_f64(double x) {
   using ConstF64 = const __attribute__((address_space(4))) double;
   ConstF64 *c = (ConstF64 *)(kErfcxS);  // generic -> constant address space
   asm volatile("" : "+s"(c));
-  const double s = (x - 3.0) / (x + 3.0);
+  // 1/(x + 3) from the hardware reciprocal and two Newton steps (x + 3 >= 3)
+  const double b = x + 3.0;
+  double y = __builtin_amdgcn_rcp(b);
+  y = fma(fma(-b, y, 1.0), y, y);
+  y = fma(fma(-b, y, 1.0), y, y);
+  const double s = (x - 3.0) * y;
   double p = c[24];
 #pragma unroll
   for (int k = 23; k >= 0; --k) p = fma(p, s, c[k]);
@@ -120,13 +125,18 @@ struct PairF64 {
   double u_lj, u_c, f, dudsig_lj, erfc_over_r;
 };
 
-// Double-precision pair terms: the device library's sqrt, division and exp, and
-// erfc from exp(-beta^2 r^2) (which the force needs anyway) times erfcx_f64.
+// Double-precision pair terms: 1/r from the hardware reciprocal square root refined by
+// Newton steps (each doubles the correct bits; two take it to double precision), the
+// device library's exp, and erfc from exp(-beta^2 r^2) (which the force needs anyway)
+// times erfcx_f64.
 __device__ __forceinline__ PairF64 pair_f64(double r2, double c6, double c12, double qq, double beta,
                                             double two_beta_sqrtpi) {
   PairF64 o;
-  const double r = sqrt(r2);
-  const double rinv = 1.0 / r;
+  // 1/r from the hardware reciprocal square root and two Newton steps (r2 > 0 here)
+  double rinv = __builtin_amdgcn_rsq(r2);
+  rinv = rinv * fma(-0.5 * r2, rinv * rinv, 1.5);
+  rinv = rinv * fma(-0.5 * r2, rinv * rinv, 1.5);
+  const double r = r2 * rinv;
   const double rinv2 = rinv * rinv;
   const double rinv6 = rinv2 * rinv2 * rinv2;
   const double a = c12 * rinv6 * rinv6;
