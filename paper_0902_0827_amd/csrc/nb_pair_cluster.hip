@@ -41,6 +41,9 @@ constexpr int kRing = 128;           // ring buffer of staged j atoms (power of 
 constexpr int kTabLds = 16;          // type tables up to 16 x 16 are copied to LDS
 constexpr int kMaxRuns = 2 * 9 * 9;  // up to 9 x 9 neighbour columns, <= 2 z-runs each
 constexpr int kRunPad = 4;           // sentinel entries after the last run
+// FP64 pair kernels: registers are allocated for 4 resident waves per SIMD (at most
+// 128 VGPRs, no spills); left alone the compiler takes 134 and 3 waves fit.
+constexpr int kF64WavesPerEu = 4;
 constexpr int kFinishBlock = 256;
 
 __device__ __forceinline__ uint32_t uabs_diff(uint32_t a, uint32_t b) {
@@ -169,7 +172,8 @@ __device__ __forceinline__ int xcd_id() {
 // vary.  Each item writes its own output slots: the result does not depend on which
 // wave took which item.
 template <bool F64, int MODE, bool TABLDS, int K>
-__global__ void __launch_bounds__(64) k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? kF64WavesPerEu : 1, 8)))
+k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   constexpr int J = 64 / K;  // j atoms per group (lanes per row)
   extern __shared__ uint4 tab_lds[];  // [T * T] type pairs when TABLDS
   __shared__ WaveLds<F64> L;

@@ -102,6 +102,15 @@ static __constant__ double kErfcxS[25] = {
     1.26390768337342988e-10,
     -1.04873117593991747e-10};
 
+// a * b + c with c in a scalar register pair: one v_fma_f64.  (Left to itself the
+// compiler copies c into the destination and uses the two-operand v_fmac_f64, three
+// instructions per step of a Horner chain whose coefficients come from scalar loads.)
+__device__ __forceinline__ double fma_s(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+
 __device__ __forceinline__ double erfcx_f64(double x) {
   // The coefficients are read from constant memory through a pointer the compiler
   // cannot treat as loop-invariant, so that they arrive by scalar loads where the
@@ -117,7 +126,7 @@ __device__ __forceinline__ double erfcx_f64(double x) {
   const double s = (x - 3.0) * y;
   double p = c[24];
 #pragma unroll
-  for (int k = 23; k >= 0; --k) p = fma(p, s, c[k]);
+  for (int k = 23; k >= 0; --k) p = fma_s(p, s, c[k]);
   return p;
 }
 
@@ -125,10 +134,38 @@ struct PairF64 {
   double u_lj, u_c, f, dudsig_lj, erfc_over_r;
 };
 
+// exp(-y) for finite y >= 0 in double precision (Cody and Waite's argument reduction):
+// y = n ln 2 + r with n = rint(y / ln 2) and |r| <= ln(2)/2, r formed with ln 2 split
+// into a double and its remainder; exp(-r) by its Taylor series to degree 13
+// (truncation error below 5e-18 relative), then exp(-y) = 2^-n exp(-r) by ldexp, which
+// also takes results below the normal range to denormals and zero.
+static __constant__ double kExpNegTaylor[14] = {
+    1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720, 1.0 / 5040, 1.0 / 40320, 1.0 / 362880,
+    1.0 / 3628800, 1.0 / 39916800, 1.0 / 479001600, 1.0 / 6227020800};
+constexpr double kLn2Hi = 0.6931471805599453;      // ln 2 rounded to double
+constexpr double kLn2Lo = 2.3190468138462996e-17;  // ln 2 - kLn2Hi
+constexpr double kInvLn2 = 1.4426950408889634;
+
+__device__ __forceinline__ double exp_neg_f64(double y) {
+  using ConstF64 = const __attribute__((address_space(4))) double;
+  ConstF64 *c = (ConstF64 *)(kExpNegTaylor);  // generic -> constant address space
+  asm volatile("" : "+s"(c));                 // scalar loads where used (as in erfcx_f64)
+  const double n = rint(y * kInvLn2);
+  double r = fma(-n, kLn2Hi, y);
+  r = fma(-n, kLn2Lo, r);  // y - n ln 2
+  const double m = -r;
+  double p = c[13];
+#pragma unroll
+  for (int k = 12; k >= 2; --k) p = fma_s(p, m, c[k]);
+  p = fma(p, m, 1.0);
+  p = fma(p, m, 1.0);
+  return ldexp(p, -static_cast<int>(n));
+}
+
 // Double-precision pair terms: 1/r from the hardware reciprocal square root refined by
-// Newton steps (each doubles the correct bits; two take it to double precision), the
-// device library's exp, and erfc from exp(-beta^2 r^2) (which the force needs anyway)
-// times erfcx_f64.
+// Newton steps (each doubles the correct bits; two take it to double precision),
+// exp(-beta^2 r^2) by exp_neg_f64, and erfc from that exponential (which the force
+// needs anyway) times erfcx_f64.
 __device__ __forceinline__ PairF64 pair_f64(double r2, double c6, double c12, double qq, double beta,
                                             double two_beta_sqrtpi) {
   PairF64 o;
@@ -143,7 +180,7 @@ __device__ __forceinline__ PairF64 pair_f64(double r2, double c6, double c12, do
   const double b = c6 * rinv6;
   o.u_lj = a - b;
   o.dudsig_lj = 12.0 * a - 6.0 * b;
-  const double e = exp(-beta * beta * r2);  // exp(-(beta r)^2)
+  const double e = exp_neg_f64(beta * beta * r2);  // exp(-(beta r)^2)
   const double erfc_br = erfcx_f64(beta * r) * e;
   o.erfc_over_r = erfc_br * rinv;
   o.u_c = qq * o.erfc_over_r;

@@ -62,3 +62,36 @@ def test_tables_give_erfc(x):
     s = (x - 3.0) / (x + 3.0)
     g = np.polynomial.polynomial.polyval(s, coef)
     assert abs(g * np.exp(-x * x) - float(mp.erfc(x))) <= 1e-15 * float(mp.erfc(x)) + 1e-300
+
+
+def test_exp_neg_reduction_and_taylor_table():
+    """exp(-y) = 2^-n exp(-r), y = n ln 2 + r, Taylor series of exp(-r) to degree 13,
+    with the constants of the kernel header, emulated in double precision."""
+    txt = _text()
+    init = txt[txt.index("kExpNegTaylor[14] = {"):]
+    init = init[init.index("{") + 1:init.index("};")]
+    coef = [eval(v.strip(), {}) for v in init.split(",")]  # literals such as 1.0 / 720
+    assert len(coef) == 14
+    for k, c in enumerate(coef):
+        assert c == float(1 / mp.factorial(k))
+    hi = float(re.search(r"kLn2Hi = ([0-9.eE+-]+);", txt).group(1))
+    lo = float(re.search(r"kLn2Lo = ([0-9.eE+-]+);", txt).group(1))
+    inv = float(re.search(r"kInvLn2 = ([0-9.eE+-]+);", txt).group(1))
+    mp.mp.dps = 40
+    assert abs(mp.mpf(hi) + mp.mpf(lo) - mp.log(2)) < mp.mpf(2) ** -110
+    def fma(a, b, c):  # one rounding of the exact a*b + c, as the hardware instruction
+        return float(mp.mpf(a) * mp.mpf(b) + mp.mpf(c))
+
+    worst = 0.0
+    for y in np.concatenate([np.linspace(0.0, 12.0, 601), [1e-12, 0.3465, 0.3466, 40.0, 700.0]]):
+        y = float(y)
+        n = float(np.rint(y * inv))
+        r = fma(-n, lo, fma(-n, hi, y))
+        m = -r
+        p = coef[13]
+        for c in reversed(coef[:13]):
+            p = fma(p, m, c)
+        v = np.ldexp(p, -int(n))
+        ref = mp.exp(-mp.mpf(float(y)))
+        worst = max(worst, abs(float((v - ref) / ref)))
+    assert worst < 4e-16, worst
