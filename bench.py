@@ -153,7 +153,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", choices=["both", "mixed"], default="both",
                     help="time the FP64 GPU path beside the mixed one (default) or only the mixed one")
-    ap.add_argument("--kernel", choices=["auto", "atom", "cluster"], default="auto",
+    ap.add_argument("--kernel", choices=["auto", "atom", "cluster", "half"], default="auto",
                     help="pair-kernel variant (both paths)")
     ap.add_argument("--split", type=int, default=0, help="cluster kernel: work items per cluster (0 = default)")
     ap.add_argument("--schedule", choices=["auto", "static", "dynamic"], default="auto",
@@ -198,7 +198,8 @@ def main():
         paths.append(("fp64", H.NB_FP64, torch.float64))
     for prec_name, prec, dt in paths:
         b = H.device_batch([s], dtype=dt)
-        kern = {"auto": H.NB_KERNEL_AUTO, "atom": H.NB_KERNEL_ATOM, "cluster": H.NB_KERNEL_CLUSTER}[args.kernel]
+        kern = {"auto": H.NB_KERNEL_AUTO, "atom": H.NB_KERNEL_ATOM, "cluster": H.NB_KERNEL_CLUSTER,
+                "half": H.NB_KERNEL_CLUSTER_HALF}[args.kernel]
         dxy, dz = (int(v) for v in args.cell_div.split(","))
         sched = {"auto": H.NB_SCHED_AUTO, "static": H.NB_SCHED_STATIC, "dynamic": H.NB_SCHED_DYNAMIC}[args.schedule]
         p = H.make_params(s.cutoff, s.beta, prec, kernel=kern, cell_div_xy=dxy, cell_div_z=dz, split=args.split,

@@ -93,6 +93,11 @@ typedef struct {
 #define NB_KERNEL_AUTO 0    /* library default for the precision (or the tuned choice passed in) */
 #define NB_KERNEL_ATOM 1    /* one lane per i atom, full neighbour shell, j read through the cache */
 #define NB_KERNEL_CLUSTER 2 /* 4- or 8-atom clusters x box-filtered j atoms staged in LDS, 64 pairs per step */
+#define NB_KERNEL_CLUSTER_HALF 3 /* as NB_KERNEL_CLUSTER, each pair once (half of the column stencil),
+                                    the other atom's share added by FP64 atomics: about half the pair
+                                    work; forces and energies agree with the other kernels to rounding
+                                    but are not bitwise reproducible (atomic order).  The adjoint
+                                    (nb_nonbonded_backward) uses NB_KERNEL_CLUSTER's form. */
 
 #define NB_SCHED_AUTO 0
 #define NB_SCHED_STATIC 1  /* one work item per wave, a grid covering every item */

@@ -3,7 +3,8 @@ divisions, work items per cluster, schedule and residency for a given batch of
 systems by timing candidates through the C ABI on the caller's own data.
 
 A candidate is accepted only if its forces agree with the library defaults' forces
-(they compute the same sums in another order, so they must agree to rounding);
+(they compute the same sums in another order or grouping, so they must agree to
+rounding);
 among the accepted candidates the one with the lowest median time per evaluation
 (nb_build_cells + nb_nonbonded_forces with energy and virial) wins.  The search is
 staged rather than exhaustive: kernel and cluster size first, then the cell
@@ -83,7 +84,9 @@ def params_from(entry: dict, cutoff: float, beta: float, precision: int) -> "H.n
 def stage_candidates(stage: int, best: dict, precision: int) -> List[dict]:
     """Candidates of one stage, as overrides of the best choice so far."""
     if stage == 0:
-        out = [dict(kernel=H.NB_KERNEL_CLUSTER, cluster_size=8), dict(kernel=H.NB_KERNEL_CLUSTER, cluster_size=4)]
+        out = [dict(kernel=H.NB_KERNEL_CLUSTER, cluster_size=8), dict(kernel=H.NB_KERNEL_CLUSTER, cluster_size=4),
+               dict(kernel=H.NB_KERNEL_CLUSTER_HALF, cluster_size=8),
+               dict(kernel=H.NB_KERNEL_CLUSTER_HALF, cluster_size=4)]
         return out
     if stage == 1:
         return [dict(cell_div_xy=xy, cell_div_z=z) for xy, z in ((2, 8), (2, 4), (2, 12), (1, 8), (3, 12))]

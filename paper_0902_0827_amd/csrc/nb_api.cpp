@@ -48,7 +48,7 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   if (prm->precision != NB_FP64 && prm->precision != NB_MIXED) return fail(NB_ERR_ARG, "unknown precision");
   if (prm->cell_div_xy < 0 || prm->cell_div_xy > 4) return fail(NB_ERR_ARG, "cell_div_xy must be in [0, 4]");
   if (prm->cell_div_z < 0 || prm->cell_div_z > 16) return fail(NB_ERR_ARG, "cell_div_z must be in [0, 16]");
-  if (prm->kernel < NB_KERNEL_AUTO || prm->kernel > NB_KERNEL_CLUSTER) return fail(NB_ERR_ARG, "unknown kernel variant");
+  if (prm->kernel < NB_KERNEL_AUTO || prm->kernel > NB_KERNEL_CLUSTER_HALF) return fail(NB_ERR_ARG, "unknown kernel variant");
   if (prm->split < 0 || prm->split > 8) return fail(NB_ERR_ARG, "split must be in [0, 8]");
   if (prm->schedule < NB_SCHED_AUTO || prm->schedule > NB_SCHED_DYNAMIC) return fail(NB_ERR_ARG, "unknown schedule");
   if (prm->wg_per_cu < 0 || prm->wg_per_cu > 32) return fail(NB_ERR_ARG, "wg_per_cu must be in [0, 32]");
@@ -154,6 +154,7 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   l.col_clu_start = take(4 * static_cast<size_t>(columns + 1));
   l.part = take(32 * static_cast<size_t>(N) * static_cast<size_t>(p.split));
   l.queue = take(4 * static_cast<size_t>(kXcds * kQueueStride));
+  l.jacc = p.kernel == NB_KERNEL_CLUSTER_HALF ? take(32 * static_cast<size_t>(N)) : 0;
   l.total = o;
   *plan = std::move(p);
   return NB_OK;
@@ -192,6 +193,7 @@ Dev dev_view(const Plan &p, void *ws) {
   d.n_columns = p.n_columns;
   d.n_clusters_max = p.n_clusters_max;
   d.queue = reinterpret_cast<uint32_t *>(base + l.queue);
+  d.jacc = p.kernel == NB_KERNEL_CLUSTER_HALF ? reinterpret_cast<double4 *>(base + l.jacc) : nullptr;
   return d;
 }
 

@@ -24,16 +24,20 @@ constexpr int kQueueStride = 16;  // uint32 per work counter (one 64-byte line e
 constexpr uint32_t kBuiltMagic = 0x4E424831u;  // status[1]: written by nb_build_cells
 
 // Kernel variants that read the column cluster counts built by nb_build_cells.
-__host__ __device__ __forceinline__ bool uses_clusters(int kernel) { return kernel == NB_KERNEL_CLUSTER; }
+__host__ __device__ __forceinline__ bool uses_clusters(int kernel) {
+  return kernel == NB_KERNEL_CLUSTER || kernel == NB_KERNEL_CLUSTER_HALF;
+}
 
 // Workspace header words: status[0] = NB_STATUS_* bits, status[1] = kBuiltMagic,
-// status[2] = atom count, status[3] = what was built (kBuiltClusters | kBuiltF64).
-constexpr uint32_t kBuiltClusters = 1u;  // column cluster arrays (cluster kernel)
+// status[2] = atom count, status[3] = what was built (kBuiltClusters | kBuiltF64 | kBuiltJacc).
+constexpr uint32_t kBuiltClusters = 1u;  // column cluster arrays (cluster kernels)
 constexpr uint32_t kBuiltF64 = 2u;       // double-precision sorted positions (FP64 kernels)
+constexpr uint32_t kBuiltJacc = 4u;      // zeroed half-shell accumulators
 __device__ __forceinline__ bool built_for(const uint32_t *status, int64_t n_atoms, bool need_clusters,
-                                          bool need_f64) {
+                                          bool need_f64, bool need_jacc = false) {
   return status[1] == kBuiltMagic && status[2] == static_cast<uint32_t>(n_atoms) &&
-         (!need_clusters || (status[3] & kBuiltClusters)) && (!need_f64 || (status[3] & kBuiltF64));
+         (!need_clusters || (status[3] & kBuiltClusters)) && (!need_f64 || (status[3] & kBuiltF64)) &&
+         (!need_jacc || (status[3] & kBuiltJacc));
 }
 
 // Per-system descriptor, resident in the workspace.  Sorted atoms of system b are
@@ -60,7 +64,7 @@ struct alignas(16) TypePair32 { float c6, c12, inv_sig, pad; };
 struct Layout {
   size_t status, desc, tab64, tab32, cell_count, cell_start, atom_cell, atom_slot, atom_fix, tmp;
   size_t s_fix, s_pos64, s_q32, s_type, excl_mask, excl_far, partials, adj_partials;
-  size_t col_clu_start, part, queue;
+  size_t col_clu_start, part, queue, jacc;
   size_t total;
 };
 
@@ -111,6 +115,10 @@ struct Dev {
   int64_t n_columns;
   int64_t n_clusters_max;
   uint32_t *queue;         // [kXcds * kQueueStride] work counters of the dynamic schedule
+  // Half-shell cluster kernel: per sorted atom, force (x, y, z) and energy share (w),
+  // added up by atomics; zero outside a force or energy call (the build zeroes it and
+  // the finishing pass of every call that used it copies it out and zeroes it again).
+  double4 *jacc;           // [N], null unless the kernel is NB_KERNEL_CLUSTER_HALF
 };
 
 // Per-call constants and outputs of the pair kernels.

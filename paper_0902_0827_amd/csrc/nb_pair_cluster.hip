@@ -117,17 +117,24 @@ __device__ __forceinline__ int cluster_column(const int32_t *__restrict__ col_cl
 template <bool F64>
 struct WaveLds;
 
+// One staged j atom of the mixed-precision kernel (one 32-byte slot, so that a group
+// reads it at one address plus offsets).
+struct alignas(16) RingF32 {
+  uint4 fix;   // fixed-point x, y, z, original index
+  float2 qt;   // q * sqrt(k_e), type (as int bits)
+  int2 sidx;   // sorted index (half-shell kernel), unused
+};
+
 template <>
 struct WaveLds<false> {
-  uint4 fix[kRing];  // fixed-point x, y, z, original index
-  float2 qt[kRing];  // q * sqrt(k_e), type (as int bits)
+  RingF32 ring[kRing];
   int2 runs[kMaxRuns + kRunPad];  // non-empty candidate runs: (first sorted atom, first candidate position)
 };
 
 template <>
 struct WaveLds<true> {
   double4 pos[kRing];  // x, y, z, q
-  int2 meta[kRing];    // original index, type
+  int4 meta[kRing];    // original index, type, sorted index (half-shell kernel), unused
   int2 runs[kMaxRuns + kRunPad];  // non-empty candidate runs: (first sorted atom, first candidate position)
 };
 
@@ -139,6 +146,24 @@ using TypePairT = std::conditional_t<F64, TypePair64, TypePair32>;
 template <bool F64>
 constexpr size_t tab_lds_bytes(int T) {
   return static_cast<size_t>(T) * static_cast<size_t>(T) * sizeof(TypePairT<F64>);
+}
+
+// Half-shell kernel: the candidates' shares of one item wait in LDS (after the type
+// table) and go to the accumulators by atomics when the stage is full and at the end
+// of the item.  (A global write in flight makes every later wait for the prefetched
+// candidates a wait for all outstanding memory operations, so none is issued inside
+// the candidate loop.)  Sizes keep 20 one-wave workgroups (mixed) or 16 (FP64) per CU
+// within the 160 KB of LDS.
+struct alignas(16) StageF32 { float x, y, z; int s; };
+struct alignas(16) StageF64 { double x, y, z; int s, pad; };
+template <bool F64>
+using StageT = std::conditional_t<F64, StageF64, StageF32>;
+template <bool F64>
+constexpr int kStage = F64 ? 64 : 144;  // entries, multiples of 16
+
+template <bool F64, bool TABLDS, bool HALF>
+constexpr size_t dyn_lds_bytes(int T) {
+  return (TABLDS ? tab_lds_bytes<F64>(T) : 0) + (HALF ? kStage<F64> * sizeof(StageT<F64>) : 0);
 }
 
 // Orders this wave's LDS accesses (one wave's LDS operations execute in issue order;
@@ -171,20 +196,31 @@ __device__ __forceinline__ int xcd_id() {
 // item of another XCD's range, so that the load evens out however the item costs
 // vary.  Each item writes its own output slots: the result does not depend on which
 // wave took which item.
-template <bool F64, int MODE, bool TABLDS, int K>
+//
+// HALF (forces and energy only): each pair is evaluated once.  A cluster takes the
+// columns of half of its stencil (positive offsets; see the run list below) and, in
+// its own column, the atoms from its own first atom on, counting a pair of its own
+// atoms only with j after i in sorted order.  Every group sums the forces on its J candidates over the K rows and row 0
+// adds them to the candidates' accumulators (d.jacc) with FP64 atomics; the rows' own
+// sums go there too at the end of the item, and the finishing pass copies the
+// accumulators out.  The pair work halves; the atomic order makes the last bits of
+// the result vary from run to run.
+template <bool F64, int MODE, bool TABLDS, int K, bool HALF>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? kF64WavesPerEu : 1, 8)))
 k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   constexpr int J = 64 / K;  // j atoms per group (lanes per row)
-  extern __shared__ uint4 tab_lds[];  // [T * T] type pairs when TABLDS
+  extern __shared__ uint4 tab_lds[];  // [T * T] type pairs when TABLDS, then the stage when HALF
   __shared__ WaveLds<F64> L;
   TypePairT<F64> *const TL = reinterpret_cast<TypePairT<F64> *>(tab_lds);
   const int lane = static_cast<int>(threadIdx.x);
-  if (!built_for(d.status, d.N, true, F64)) {
+  if (!built_for(d.status, d.N, true, F64, HALF)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(d.status, NB_STATUS_NOT_BUILT);
     return;
   }
   const int ii = lane / J, jj = lane % J;
   const int T = d.T;
+  StageT<F64> *const ST = reinterpret_cast<StageT<F64> *>(reinterpret_cast<char *>(tab_lds) +
+                                                          (TABLDS ? tab_lds_bytes<F64>(T) : 0));
   if constexpr (TABLDS) {
     for (int k = lane; k < T * T; k += 64) {
       if constexpr (F64) TL[k] = d.tab64[k];
@@ -344,6 +380,27 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
           }
         }
       }
+      if constexpr (HALF) {
+        // Half stencil: a neighbour column is taken when its offset is positive in x,
+        // or zero in x and positive in y (the opposite column takes the pair the other
+        // way round, so every pair of columns is visited once and every cluster gets a
+        // like share).  Where the stencil spans the whole box in a dimension offsets are
+        // ambiguous and the column order decides instead; the own column is taken from
+        // the cluster's first atom on.
+        if (k < ncol) {
+          const int ox = k / yn, oy = k - (k / yn) * yn;
+          const int rx = allx ? (ox > cx) - (ox < cx) : (ox > kx) - (ox < kx);
+          const int ry = ally ? (oy > cy) - (oy < cy) : (oy > ky) - (oy < ky);
+          if (rx < 0 || (rx == 0 && ry < 0)) {
+            r0 = r1 = make_int2(0, 0);
+          } else if (rx == 0 && ry == 0) {
+            r0.x = r0.x > first ? r0.x : first;
+            r1.x = r1.x > first ? r1.x : first;
+            if (r0.y < r0.x) r0.y = r0.x;
+            if (r1.y < r1.x) r1.y = r1.x;
+          }
+        }
+      }
       const int n0 = r0.y - r0.x, n1 = r1.y - r1.x;
       int cnt_tot, len_tot;
       const int slot = nrun + wave_excl_scan_int((n0 > 0) + (n1 > 0), &cnt_tot);
@@ -374,19 +431,52 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
 
     uint32_t head = 0, tail = 0;  // wave-uniform ring positions
 
+    // Mixed path: fixed-point units -> Angstrom, and phi carries one sqrt(k_e) from q'_j.
+    const double scx = F64 ? 1.0 : uni(sd.scale[0]), scy = F64 ? 1.0 : uni(sd.scale[1]),
+                 scz = F64 ? 1.0 : uni(sd.scale[2]);
+
+    // Half-shell stage: entries [0, nst) hold candidates' shares not yet added.
+    int nst = 0;  // wave-uniform
+    auto flush = [&]() {
+      wave_lds_sync();
+      for (int e = lane; e < nst; e += 64) {
+        const StageT<F64> st = ST[e];
+        if constexpr (MODE == kForces) {
+          if (st.x != 0 || st.y != 0 || st.z != 0) {  // a candidate without a pair in range adds nothing
+            double *acc = &d.jacc[st.s].x;
+            unsafeAtomicAdd(acc + 0, static_cast<double>(st.x) * scx);
+            unsafeAtomicAdd(acc + 1, static_cast<double>(st.y) * scy);
+            unsafeAtomicAdd(acc + 2, static_cast<double>(st.z) * scz);
+          }
+        } else if (st.x != 0) {
+          unsafeAtomicAdd(&d.jacc[st.s].w, static_cast<double>(st.x));
+        }
+      }
+      wave_lds_sync();
+      nst = 0;
+    };
+
     // Evaluate pair (row ii's atom, ring entry head + jj) for navail <= J entries.
     auto process_group = [&](int navail) {
-      const int slot = static_cast<int>((head + jj) & (kRing - 1));
+      // head is a multiple of J (only an item's last group is partial) and J divides
+      // kRing, so the group's J slots are consecutive: a scalar base plus jj.
+      const int slot = static_cast<int>(head & (kRing - 1)) + jj;
       const bool jv = jj < navail;
-      int oj, tj;
+      int oj, tj, sj = 0;
       if constexpr (F64) {
-        const int2 mt = L.meta[slot];
+        const int4 mt = L.meta[slot];
         oj = mt.x;
         tj = mt.y;
+        if constexpr (HALF) sj = mt.z;
       } else {
-        oj = static_cast<int>(L.fix[slot].w);
-        tj = __float_as_int(L.qt[slot].y);
+        oj = static_cast<int>(L.ring[slot].fix.w);
+        tj = __float_as_int(L.ring[slot].qt.y);
+        if constexpr (HALF) sj = L.ring[slot].sidx.x;
       }
+      // Both ways: j is not i.  Once: candidates before the cluster in sorted order come
+      // from other columns and always count; from the cluster on (its own column) only
+      // those after i.
+      const bool other = HALF ? (sj < first || sj > i) : oi != oj;
       bool hit;
       float r2f = 0.f, dxf = 0.f, dyf = 0.f, dzf = 0.f;
       double r2d = 0.0, dxd = 0.0, dyd = 0.0, dzd = 0.0;
@@ -401,15 +491,15 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         dyd -= bxy * rint(dyd * iby);
         dzd -= bxz * rint(dzd * ibz);
         r2d = dxd * dxd + dyd * dyd + dzd * dzd;
-        hit = ivalid && jv && r2d < c.rc2 && oi != oj;
+        hit = ivalid && jv && r2d < c.rc2 && other;
       } else {
-        const uint4 fj = L.fix[slot];
-        qj = L.qt[slot].x;
+        const uint4 fj = L.ring[slot].fix;
+        qj = L.ring[slot].qt.x;
         dxf = static_cast<float>(static_cast<int>(fi.x - fj.x));
         dyf = static_cast<float>(static_cast<int>(fi.y - fj.y));
         dzf = static_cast<float>(static_cast<int>(fi.z - fj.z));
         r2f = fmaf(s2z * dzf, dzf, fmaf(s2y * dyf, dyf, s2x * dxf * dxf));
-        hit = ivalid && jv && r2f < c.rc2f && oi != oj;
+        hit = ivalid && jv && r2f < c.rc2f && other;
       }
       // Exclusions: window bit of oi for |oj - oi| <= 64 (bits 0-63: oj - oi = -64..-1,
       // bits 64-127: 1..64), tested without branches; pairs farther apart only for atoms
@@ -424,6 +514,8 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         const bool far_check = hit && !inwin && far_i;
         if (far_check && far_excluded(oi, oj, atom_begin, d.excl_far, o.excl_off, o.excl_idx)) hit = false;
       }
+      // the pair's force on i (f d_ij) and energy, for the half-shell j-side sums
+      std::conditional_t<F64, double, float> hgx = 0, hgy = 0, hgz = 0, hu = 0;
       if (hit) {
         if constexpr (F64) {
           TypePair64 tp;
@@ -431,6 +523,12 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
           else tp = d.tab64[ti * T + tj];
           const PairF64 p = pair_f64(r2d, tp.c6, tp.c12, qi64 * pj64.w, c.beta, c.two_beta_sqrtpi);
           en += p.u_lj + p.u_c;
+          if constexpr (HALF) {
+            hgx = p.f * dxd;
+            hgy = p.f * dyd;
+            hgz = p.f * dzd;
+            hu = p.u_lj + p.u_c;
+          }
           if constexpr (MODE != kEnergy) {
             fx += p.f * dxd;
             fy += p.f * dyd;
@@ -453,8 +551,14 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
           else tp = d.tab32[ti * T + tj];
           const PairF32 p = pair_f32(r2f, tp.c6, tp.c12, qi32 * qj, c.betaf, c.two_beta_sqrtpif, c.mb2l2e);
           sen += p.u_lj + p.u_c;
+          if constexpr (HALF) hu = p.u_lj + p.u_c;
           if constexpr (MODE != kEnergy) {
             const float gx = p.f * dxf, gy = p.f * dyf, gz = p.f * dzf;
+            if constexpr (HALF) {
+              hgx = gx;
+              hgy = gy;
+              hgz = gz;
+            }
             sfx += gx;
             sfy += gy;
             sfz += gz;
@@ -472,6 +576,38 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
           }
         }
       }
+      if constexpr (HALF) {
+        // The J candidates' shares: column sums over the K rows, added by row 0.
+        if constexpr (MODE == kForces) {
+          auto cx = -hgx, cy = -hgy, cz = -hgz;
+          for (int off = J; off < 64; off <<= 1) {
+            cx += __shfl_xor(cx, off, 64);
+            cy += __shfl_xor(cy, off, 64);
+            cz += __shfl_xor(cz, off, 64);
+          }
+          if (nst + J > kStage<F64>) flush();
+          if (ii == 0 && jv) {
+            StageT<F64> &st = ST[nst + jj];
+            st.x = cx;
+            st.y = cy;
+            st.z = cz;
+            st.s = sj;
+          }
+          nst += navail;
+        } else if constexpr (MODE == kEnergy) {
+          if (o.atom_energy) {  // per-atom energies: half of each pair's energy to j
+            auto cu = hu;
+            for (int off = J; off < 64; off <<= 1) cu += __shfl_xor(cu, off, 64);
+            if (nst + J > kStage<F64>) flush();
+            if (ii == 0 && jv) {
+              StageT<F64> &st = ST[nst + jj];
+              st.x = static_cast<decltype(st.x)>(0.5) * cu;
+              st.s = sj;
+            }
+            nst += navail;
+          }
+        }
+      }
       head += static_cast<uint32_t>(navail);
     };
 
@@ -482,7 +618,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     // run0 .. run0 + 3 are read at once (wave-uniform addresses) and each lane picks
     // its run by comparisons; the rare lane beyond them walks on.  The next chunk
     // starts in the run of this chunk's last lane or a later one.
-    auto load = [&](int P, uint4 &f, int &t, float &q, double4 &p, bool &v) {
+    auto load = [&](int P, uint4 &f, int &t, float &q, double4 &p, bool &v, int &sidx) {
       while (L.runs[run0 + 1].y <= P) ++run0;
       const int2 ra = L.runs[run0], rb = L.runs[run0 + 1], rc = L.runs[run0 + 2], rd = L.runs[run0 + 3];
       const int pos = P + lane;
@@ -497,6 +633,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       }
       const int aa = v ? cur.x + (pos - cur.y) : ra.x + (P - ra.y);
       run0 = __builtin_amdgcn_readlane(v ? r : run0, 63);
+      sidx = aa;
       f = d.s_fix[aa];
       t = d.s_type[aa];
       if constexpr (F64) p = d.s_pos64[aa];
@@ -507,9 +644,10 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     float qj = 0.f;
     double4 pj64 = make_double4(0, 0, 0, 0);
     bool valid = false;
+    int sj = 0;
     wait_vm_loads();  // the cluster's own data has arrived before the pair loop starts
     int P = lo_c;
-    if (P < hi_c) load(P, fj, tj, qj, pj64, valid);
+    if (P < hi_c) load(P, fj, tj, qj, pj64, valid, sj);
     bool requested = false;
     while (P < hi_c) {
       const int Pn = P + 64;
@@ -518,8 +656,9 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       float qj_n = qj;
       double4 pj64_n = pj64;
       bool valid_n = false;
+      int sj_n = sj;
       if (Pn < hi_c) {
-        load(Pn, fj_n, tj_n, qj_n, pj64_n, valid_n);
+        load(Pn, fj_n, tj_n, qj_n, pj64_n, valid_n, sj_n);
       } else if (dynamic && !(closed & (1u << home))) {
         // the next item, requested after this item's last loads (vector-memory waits
         // complete in issue order, so an earlier request would hold up the chunks)
@@ -538,10 +677,11 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       if (keep) {
         if constexpr (F64) {
           L.pos[slot] = pj64;
-          L.meta[slot] = make_int2(static_cast<int>(fj.w), tj);
+          L.meta[slot] = make_int4(static_cast<int>(fj.w), tj, HALF ? sj : 0, 0);
         } else {
-          L.fix[slot] = fj;
-          L.qt[slot] = make_float2(qj, __int_as_float(tj));
+          L.ring[slot].fix = fj;
+          L.ring[slot].qt = make_float2(qj, __int_as_float(tj));
+          if constexpr (HALF) L.ring[slot].sidx = make_int2(sj, 0);
         }
       }
       wave_lds_sync();
@@ -554,6 +694,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       qj = qj_n;
       pj64 = pj64_n;
       valid = valid_n;
+      sj = sj_n;
     }
     if (tail != head) process_group(static_cast<int>(tail - head));
     if (dynamic && !requested && !(closed & (1u << home))) {  // an item without candidates
@@ -561,11 +702,8 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       have_pending = true;
     }
 
-    // Mixed path: fixed-point units -> Angstrom, and phi carries one sqrt(k_e) from q'_j.
     // The single-precision sums become double only where they are reduced, so that
     // few of them are live in double at a time.
-    const double scx = F64 ? 1.0 : uni(sd.scale[0]), scy = F64 ? 1.0 : uni(sd.scale[1]),
-                 scz = F64 ? 1.0 : uni(sd.scale[2]);
     const double phi_scale = F64 ? c.ke : c.sqrt_ke;
 
     if constexpr (MODE == kAdjoint) {
@@ -600,7 +738,18 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     fy = row_sum<J>(D(fy, sfy)) * scy;
     fz = row_sum<J>(D(fz, sfz)) * scz;
     const double w4 = MODE == kAdjoint ? row_sum<J>(D(phi, sphi)) * phi_scale : row_sum<J>(D(en, sen));
-    if (jj == 0 && ivalid) {
+    if constexpr (HALF) {
+      if (nst > 0) flush();
+      if (jj == 0 && ivalid) {
+        if constexpr (MODE == kForces) {
+          unsafeAtomicAdd(&d.jacc[i].x, fx);
+          unsafeAtomicAdd(&d.jacc[i].y, fy);
+          unsafeAtomicAdd(&d.jacc[i].z, fz);
+        } else if constexpr (MODE == kEnergy) {
+          if (o.atom_energy) unsafeAtomicAdd(&d.jacc[i].w, 0.5 * w4);
+        }
+      }
+    } else if (jj == 0 && ivalid) {
       if (Q == 1) {
         if constexpr (MODE == kForces) {
           o.force[3 * static_cast<int64_t>(oi) + 0] = fx;
@@ -629,9 +778,11 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         double mine = 0.0;
         if (MODE == kForces && o.want_virial) {
           // the seven distinct entries summed together, one butterfly step at a time
-          double v[7] = {0.5 * D(en, sen), 0.5 * scx * scx * D(wxx, swxx), 0.5 * scx * scy * D(wxy, swxy),
-                         0.5 * scx * scz * D(wxz, swxz), 0.5 * scy * scy * D(wyy, swyy),
-                         0.5 * scy * scz * D(wyz, swyz), 0.5 * scz * scz * D(wzz, swzz)};
+          // each pair counted twice by the full-shell form, once by the half-shell one
+          constexpr double hs = HALF ? 1.0 : 0.5;
+          double v[7] = {hs * D(en, sen), hs * scx * scx * D(wxx, swxx), hs * scx * scy * D(wxy, swxy),
+                         hs * scx * scz * D(wxz, swxz), hs * scy * scy * D(wyy, swyy),
+                         hs * scy * scz * D(wyz, swyz), hs * scz * scz * D(wzz, swzz)};
 #pragma unroll
           for (int off = 32; off > 0; off >>= 1) {
 #pragma unroll
@@ -642,7 +793,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
                : (lane == 3 || lane == 7) ? v[3] : lane == 5 ? v[4] : (lane == 6 || lane == 8) ? v[5] : v[6];
           if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + m] = mine;
         } else {
-          mine = wave_sum(0.5 * D(en, sen));
+          mine = wave_sum((HALF ? 1.0 : 0.5) * D(en, sen));
           if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + m] = lane == 0 ? mine : 0.0;
         }
       }
@@ -693,16 +844,29 @@ __device__ inline double sum_component(const double *__restrict__ vals, int64_t 
 template <int MODE>
 __global__ void __launch_bounds__(kFinishBlock) k_finish(Dev d, Out o, int S, int nA, double *energy, double *virial,
                                                         int nv, const double *__restrict__ eps, double *grad_sigma,
-                                                        double *grad_eps) {
+                                                        double *grad_eps, int half) {
   __shared__ double lds[kFinishBlock / 64][kPart];
   // The pair kernel is complete: its work counters start again from zero next time.
   if (blockIdx.x == 0 && threadIdx.x < kXcds) d.queue[threadIdx.x * kQueueStride] = 0u;
-  if (!built_for(d.status, d.N, true, false)) return;
+  if (!built_for(d.status, d.N, true, false, half != 0)) return;
   const int blk = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (blk < nA) {
     const int i = blk * kFinishBlock + threadIdx.x;
     if (i >= d.N) return;
+    if (half) {  // half-shell accumulators: copy out, and zero for the next call
+      const double4 a = d.jacc[i];
+      d.jacc[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+      const int oi = static_cast<int>(d.s_fix[i].w);
+      if constexpr (MODE == kForces) {
+        o.force[3 * oi + 0] = a.x;
+        o.force[3 * oi + 1] = a.y;
+        o.force[3 * oi + 2] = a.z;
+      } else if constexpr (MODE == kEnergy) {
+        if (o.atom_energy) o.atom_energy[oi] = a.w;
+      }
+      return;
+    }
     double4 s = d.part[i];
     for (int p = 1; p < S; ++p) {
       const double4 q = d.part[static_cast<int64_t>(p) * d.N + i];
@@ -820,11 +984,11 @@ int resident_workgroups(const void *kern, size_t lds_bytes, Query query) {
 }
 
 template <bool F64, bool TABLDS, int K>
-void launch_cluster_mode(int mode, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s, const Dev &d, const Consts &c,
-                         const Out &o, int Q) {
+void launch_cluster_mode(int mode, bool half, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s, const Dev &d,
+                         const Consts &c, const Out &o, int Q) {
   const dim3 block(64);
-  const size_t lds = TABLDS ? tab_lds_bytes<F64>(d.T) : 0;
-  auto go = [&](auto kern) {
+  auto go = [&](auto kern, auto half_tag) {
+    const size_t lds = dyn_lds_bytes<F64, TABLDS, decltype(half_tag)::value>(d.T);
     int64_t g = wgs;
     if (dyn) {
       // persistent grid: what fits on the device at once (at most wg_per_cu per CU)
@@ -836,22 +1000,29 @@ void launch_cluster_mode(int mode, int64_t wgs, int dyn, int wg_per_cu, hipStrea
     g = std::max<int64_t>((g + kXcds - 1) / kXcds * kXcds, kXcds);  // a multiple of the XCD count
     hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(g)), block, lds, s, d, c, o, Q, dyn);
   };
-  if (mode == kForces) go(k_pair_cluster<F64, kForces, TABLDS, K>);
-  else if (mode == kEnergy) go(k_pair_cluster<F64, kEnergy, TABLDS, K>);
-  else go(k_pair_cluster<F64, kAdjoint, TABLDS, K>);
+  if (mode == kForces) {
+    if (half) go(k_pair_cluster<F64, kForces, TABLDS, K, true>, std::true_type{});
+    else go(k_pair_cluster<F64, kForces, TABLDS, K, false>, std::false_type{});
+  } else if (mode == kEnergy) {
+    if (half) go(k_pair_cluster<F64, kEnergy, TABLDS, K, true>, std::true_type{});
+    else go(k_pair_cluster<F64, kEnergy, TABLDS, K, false>, std::false_type{});
+  } else {
+    go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false>, std::false_type{});
+  }
 }
 
 template <bool F64, bool TABLDS>
-void launch_cluster_k(int K, int mode, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s, const Dev &d,
+void launch_cluster_k(int K, int mode, bool half, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s, const Dev &d,
                       const Consts &c, const Out &o, int Q) {
-  if (K == 8) launch_cluster_mode<F64, TABLDS, 8>(mode, wgs, dyn, wg_per_cu, s, d, c, o, Q);
-  else launch_cluster_mode<F64, TABLDS, 4>(mode, wgs, dyn, wg_per_cu, s, d, c, o, Q);
+  if (K == 8) launch_cluster_mode<F64, TABLDS, 8>(mode, half, wgs, dyn, wg_per_cu, s, d, c, o, Q);
+  else launch_cluster_mode<F64, TABLDS, 4>(mode, half, wgs, dyn, wg_per_cu, s, d, c, o, Q);
 }
 
 }  // namespace
 
 void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out &o, int mode, hipStream_t s,
                          double *energy, double *virial, const double *eps, double *grad_sigma, double *grad_eps) {
+  const bool half = p.kernel == NB_KERNEL_CLUSTER_HALF && mode != kAdjoint;  // the adjoint stays full-shell
   if (p.N > 0 && p.n_clusters_max > 0) {
     const int64_t items = p.n_clusters_max * p.split;  // upper bound on the work items
     const int64_t wgs = items;  // one wave per workgroup
@@ -860,16 +1031,18 @@ void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out
     const int K = p.cluster_size;
     timer_before(s);
     if (p.precision == NB_FP64) {
-      if (tab) launch_cluster_k<true, true>(K, mode, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
-      else launch_cluster_k<true, false>(K, mode, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
+      if (tab) launch_cluster_k<true, true>(K, mode, half, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
+      else launch_cluster_k<true, false>(K, mode, half, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
     } else {
-      if (tab) launch_cluster_k<false, true>(K, mode, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
-      else launch_cluster_k<false, false>(K, mode, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
+      if (tab) launch_cluster_k<false, true>(K, mode, half, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
+      else launch_cluster_k<false, false>(K, mode, half, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
     }
     timer_after(s);
   }
-  // with one item per cluster the pair kernel has written the per-atom outputs itself
-  const int nA = p.split == 1 ? 0 : static_cast<int>((p.N + kFinishBlock - 1) / kFinishBlock);
+  // With one item per cluster the full-shell kernel has written the per-atom outputs
+  // itself; the half-shell kernel's accumulators are always copied out here.
+  const int blocksA = static_cast<int>((p.N + kFinishBlock - 1) / kFinishBlock);
+  const int nA = half ? ((mode == kForces || o.atom_energy) ? blocksA : 0) : (p.split == 1 ? 0 : blocksA);
   int nv = 0;
   if (mode == kForces) nv = o.want_part ? (virial ? kPart : 1) : 0;
   if (mode == kEnergy) nv = 1;
@@ -877,13 +1050,13 @@ void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out
   const dim3 fg(static_cast<unsigned>(nA + kPart * p.B + extra));
   if (mode == kForces)
     hipLaunchKernelGGL(k_finish<kForces>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
-                       grad_sigma, grad_eps);
+                       grad_sigma, grad_eps, half ? 1 : 0);
   else if (mode == kEnergy)
     hipLaunchKernelGGL(k_finish<kEnergy>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
-                       grad_sigma, grad_eps);
+                       grad_sigma, grad_eps, half ? 1 : 0);
   else
     hipLaunchKernelGGL(k_finish<kAdjoint>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
-                       grad_sigma, grad_eps);
+                       grad_sigma, grad_eps, 0);
 }
 
 }  // namespace nb

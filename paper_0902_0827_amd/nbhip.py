@@ -29,7 +29,7 @@ COULOMB_K = 1389.35457644382
 NB_OK, NB_ERR_ARG, NB_ERR_BOX, NB_ERR_WORKSPACE, NB_ERR_HIP, NB_ERR_CAPACITY = range(6)
 NB_FP64, NB_MIXED = 0, 1
 NB_SCHED_AUTO, NB_SCHED_STATIC, NB_SCHED_DYNAMIC = 0, 1, 2
-NB_KERNEL_AUTO, NB_KERNEL_ATOM, NB_KERNEL_CLUSTER = 0, 1, 2
+NB_KERNEL_AUTO, NB_KERNEL_ATOM, NB_KERNEL_CLUSTER, NB_KERNEL_CLUSTER_HALF = 0, 1, 2, 3
 NB_STATUS_NONFINITE_POS = 0x1
 NB_STATUS_BAD_TYPE = 0x2
 NB_STATUS_BAD_EXCLUSION = 0x4

@@ -52,12 +52,18 @@ def gpu_eval(systems, precision, cell_div_xy=0, cell_div_z=0, kernel=H.NB_KERNEL
              backward=False, grad_energy=None, split=0, cluster_size=0, schedule=0, wg_per_cu=0):
     """Runs build_cells + forces (and optionally energy / backward) through the C ABI.
     kernel "cluster8" is the cluster kernel with 8-atom clusters, "cluster4_static" the
-    cluster kernel with 4-atom clusters, two items per cluster and one item per wave."""
+    cluster kernel with 4-atom clusters, two items per cluster and one item per wave;
+    "half8" the half-shell cluster kernel with 8-atom clusters, "half4_dynamic" the
+    half-shell kernel with 4-atom clusters, two items per cluster, dynamic schedule."""
     import torch
     if kernel == "cluster8":
         kernel, cluster_size = H.NB_KERNEL_CLUSTER, 8
     elif kernel == "cluster4_static":
         kernel, cluster_size, split, schedule = H.NB_KERNEL_CLUSTER, 4, 2, H.NB_SCHED_STATIC
+    elif kernel == "half8":
+        kernel, cluster_size = H.NB_KERNEL_CLUSTER_HALF, 8
+    elif kernel == "half4_dynamic":
+        kernel, cluster_size, split, schedule = H.NB_KERNEL_CLUSTER_HALF, 4, 2, H.NB_SCHED_DYNAMIC
     systems = systems if isinstance(systems, (list, tuple)) else [systems]
     dt = torch.float64 if precision == H.NB_FP64 else torch.float32
     b = H.device_batch(systems, dtype=dt)

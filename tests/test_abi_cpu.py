@@ -66,6 +66,17 @@ def test_workspace_bytes_scales_with_the_system():
     assert code == H.NB_OK
 
 
+def test_half_shell_kernel_adds_one_accumulator_per_atom():
+    """The half-shell kernel's workspace holds 32 more bytes per atom (force and energy
+    accumulators), rounded up to the 256-byte alignment of every array."""
+    s = fake_system((23600,), L=60.0)
+    code, full = ws_bytes(s, H.make_params(9.0, 0.34, kernel=H.NB_KERNEL_CLUSTER))
+    assert code == H.NB_OK
+    code, half = ws_bytes(s, H.make_params(9.0, 0.34, kernel=H.NB_KERNEL_CLUSTER_HALF))
+    assert code == H.NB_OK
+    assert half - full == (32 * 23600 + 255) // 256 * 256
+
+
 def test_layout_reports_the_grid():
     lib = H.load_library()
     lay = H.nb_layout()
@@ -85,6 +96,7 @@ def test_layout_reports_the_grid():
     (lambda s, p: setattr(p, "precision", 7), H.NB_ERR_ARG),
     (lambda s, p: setattr(p, "cell_div_xy", 9), H.NB_ERR_ARG),
     (lambda s, p: setattr(p, "kernel", 99), H.NB_ERR_ARG),
+    (lambda s, p: setattr(p, "kernel", H.NB_KERNEL_CLUSTER_HALF + 1), H.NB_ERR_ARG),
     (lambda s, p: setattr(p, "split", 9), H.NB_ERR_ARG),
     (lambda s, p: setattr(p, "cluster_size", 6), H.NB_ERR_ARG),
     (lambda s, p: setattr(p, "schedule", 3), H.NB_ERR_ARG),

@@ -21,7 +21,18 @@ pytestmark = [pytest.mark.gpu,
 
 FP64_TOL = 1e-12
 MIXED_TOL = 1e-5
-KERNELS = [H.NB_KERNEL_ATOM, H.NB_KERNEL_CLUSTER, "cluster8", "cluster4_static"]
+KERNELS = [H.NB_KERNEL_ATOM, H.NB_KERNEL_CLUSTER, "cluster8", "cluster4_static", "half8", "half4_dynamic"]
+HALF_KERNELS = ("half8", "half4_dynamic")
+
+
+def _assert_same(a, b, kernel, err_msg=""):
+    """Bitwise equality, except for the half-shell kernel, whose FP64 atomic additions
+    may come in any order: there the results agree to the last few bits."""
+    if kernel in HALF_KERNELS:
+        scale = max(float(np.abs(np.asarray(b)).max()), 1e-300)
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-13 * scale, err_msg=err_msg)
+    else:
+        np.testing.assert_array_equal(a, b, err_msg=err_msg)
 
 
 def _print_case(name, **kw):
@@ -169,7 +180,8 @@ def test_forces_energy_virial_match_oracle(which, precision, kernel, chain):
 def test_run_twice_is_bitwise_identical(precision, kernel, chain):
     a = U.gpu_eval(chain, precision, kernel=kernel)
     b = U.gpu_eval(chain, precision, kernel=kernel)
-    np.testing.assert_array_equal(a["force"], b["force"])
+    _assert_same(a["force"], b["force"], kernel)
+    # energy and virial come from per-item partials summed in a fixed order
     np.testing.assert_array_equal(a["energy"], b["energy"])
     np.testing.assert_array_equal(a["virial"], b["virial"])
 
@@ -219,7 +231,7 @@ def test_batch_equals_each_system_alone(precision, kernel, chain):
     off = np.concatenate([[0], np.cumsum([s.n for s in systems])])
     for k, s in enumerate(systems):
         alone = U.gpu_eval(s, precision, kernel=kernel)
-        np.testing.assert_array_equal(out["force"][off[k]:off[k + 1]], alone["force"])
+        _assert_same(out["force"][off[k]:off[k + 1]], alone["force"], kernel)
         assert out["energy"][k] == alone["energy"][0]
         np.testing.assert_array_equal(out["virial"][k], alone["virial"][0])
 
@@ -383,6 +395,54 @@ def test_pair_kernels_refuse_a_workspace_built_for_another_kernel(chain):
     H.build_cells(b, p_clu, ws)
     H.nonbonded_forces(b, p_clu, ws, force, energy)
     assert H.read_status(ws) == 0
+
+
+def test_half_shell_kernel_refuses_a_build_without_its_accumulators(chain):
+    """A build for the full-shell kernel does not zero the half-shell accumulators, so
+    the half-shell kernel must neither run on it nor write the outputs."""
+    b = H.device_batch([chain], dtype=torch.float32)
+    p_clu = H.make_params(chain.cutoff, chain.beta, H.NB_MIXED, kernel=H.NB_KERNEL_CLUSTER)
+    p_half = H.make_params(chain.cutoff, chain.beta, H.NB_MIXED, kernel=H.NB_KERNEL_CLUSTER_HALF)
+    assert H.workspace_bytes(b, p_half) > H.workspace_bytes(b, p_clu)
+    ws = torch.full((H.workspace_bytes(b, p_half),), 0x7F, dtype=torch.uint8, device="cuda")  # not zero
+    force = torch.full((chain.n, 3), 7.0, dtype=torch.float64, device="cuda")
+    energy = torch.full((1,), 7.0, dtype=torch.float64, device="cuda")
+    H.build_cells(b, p_clu, ws)
+    H.nonbonded_forces(b, p_half, ws, force, energy)
+    assert H.read_status(ws) & H.NB_STATUS_NOT_BUILT
+    assert float(force.abs().min()) == 7.0 and float(force.abs().max()) == 7.0 and float(energy[0]) == 7.0
+    H.build_cells(b, p_half, ws)
+    H.nonbonded_forces(b, p_half, ws, force, energy)
+    assert H.read_status(ws) == 0
+    ref = U.oracle_for(chain, H.NB_MIXED)
+    assert U.rel_rms(force.cpu().numpy(), ref["force"]) <= MIXED_TOL
+    # the accumulators were zeroed again: a second call gives the same forces
+    f1 = force.clone()
+    H.nonbonded_forces(b, p_half, ws, force, energy)
+    _assert_same(force.cpu().numpy(), f1.cpu().numpy(), "half8")
+
+
+@pytest.mark.parametrize("K", [4, 8])
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+def test_half_shell_agrees_with_full_shell(precision, K):
+    """Each pair once, the other atom's share added by atomics, against each pair twice:
+    the same pair terms summed in another grouping, over splits and both schedules."""
+    s = U.cached_config(2)
+    full = U.gpu_eval(s, precision, kernel=H.NB_KERNEL_CLUSTER, cluster_size=K, energy_call=True)
+    tol = 1e-13 if precision == H.NB_FP64 else 3e-6
+    for split, sch in [(1, H.NB_SCHED_STATIC), (2, H.NB_SCHED_STATIC), (3, H.NB_SCHED_DYNAMIC),
+                       (8, H.NB_SCHED_DYNAMIC)]:
+        _print_case("half_vs_full", precision=precision, K=K, split=split, schedule=sch, n=s.n)
+        half = U.gpu_eval(s, precision, kernel=H.NB_KERNEL_CLUSTER_HALF, cluster_size=K, split=split,
+                          schedule=sch, energy_call=True)
+        err = U.rel_rms(half["force"], full["force"])
+        print(f"  half vs full rel_rms={err:.3e}")
+        assert err <= tol
+        assert half["energy"][0] == pytest.approx(full["energy"][0], rel=tol)
+        assert half["energy2"][0] == pytest.approx(full["energy2"][0], rel=tol)
+        assert U.rel_rms(half["virial"][0], full["virial"][0]) <= tol
+        assert U.rel_rms(half["atom_energy"], full["atom_energy"]) <= tol
+        assert half["status"] == 0
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
