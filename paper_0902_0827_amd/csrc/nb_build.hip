@@ -289,7 +289,10 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(Dev d, int clusters, int K)
 __global__ void k_scatter(Dev d) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.N) return;
-  d.tmp[d.cell_start[d.atom_cell[i]] + d.atom_slot[i]] = i;
+  const int cell = d.atom_cell[i];
+  const int c0 = d.cell_start[cell], c1 = d.cell_start[cell + 1];
+  d.tmp[c0 + d.atom_slot[i]] = i;
+  d.s_range[c0 + d.atom_slot[i]] = make_int2(c0, c1);  // for k_finalize, one load away
 }
 
 template <typename Real>
@@ -298,8 +301,8 @@ __global__ void k_finalize(Dev d, const Real *__restrict__ pos, const Real *__re
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= d.N) return;
   const int i = d.tmp[s];
-  const int cell = d.atom_cell[i];
-  const int lo = d.cell_start[cell], hi = d.cell_start[cell + 1];
+  const int2 cr = d.s_range[s];  // the cell's positions, stored by the scatter
+  const int lo = cr.x, hi = cr.y;
   int rank = 0;
   for (int k = lo; k < hi; ++k) rank += d.tmp[k] < i;
   const int dst = lo + rank;
@@ -333,7 +336,10 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_scatter(Dev d, int clusters
   block_scan<kScanPer>([cnt](int64_t k) { return static_cast<int>(cnt[k]); },
                        [csl](int64_t k, int v) { csl[k] = v; }, d.n_cells, lds);
   __syncthreads();
-  if (have) d.tmp[cs[cell] + slot] = static_cast<int32_t>(i);
+  if (have) {
+    d.tmp[cs[cell] + slot] = static_cast<int32_t>(i);
+    d.s_range[cs[cell] + slot] = make_int2(cs[cell], cs[cell + 1]);  // for k_finalize, one load away
+  }
   // cell_start: each workgroup stores a slice
   const int64_t per = (d.n_cells + 1 + gridDim.x - 1) / gridDim.x;
   const int64_t k0 = per * blockIdx.x, k1 = k0 + per < d.n_cells + 1 ? k0 + per : d.n_cells + 1;

@@ -62,7 +62,7 @@ struct alignas(16) TypePair32 { float c6, c12, inv_sig, pad; };
 
 // Byte offsets into the workspace (all 256-aligned).
 struct Layout {
-  size_t status, desc, tab64, tab32, cell_count, cell_start, atom_cell, atom_slot, atom_fix, tmp;
+  size_t status, desc, tab64, tab32, cell_count, cell_start, atom_cell, atom_slot, atom_fix, tmp, s_range;
   size_t s_fix, s_pos64, s_q32, s_type, excl_mask, excl_far, partials, adj_partials;
   size_t col_clu_start, part, queue, jacc;
   size_t total;
@@ -97,6 +97,7 @@ struct Dev {
   int32_t *cell_count, *cell_start;
   int64_t n_cells;
   int32_t *atom_cell, *atom_slot, *tmp;
+  int2 *s_range;     // sorted position (arrival order): the [start, end) of its atom's cell
   uint4 *atom_fix;   // original order: fixed-point x, y, z, system index
   uint4 *s_fix;      // sorted: fixed-point x, y, z, original index
   double4 *s_pos64;  // sorted: raw x, y, z (double), charge (double)
