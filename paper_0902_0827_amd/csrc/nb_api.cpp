@@ -12,6 +12,10 @@
 
 namespace nb {
 
+// At most this many clusters (about 6 per SIMD of the MI355X) take two work items per
+// cluster by default.
+constexpr int64_t kSmallClusterCount = 6144;
+
 namespace {
 thread_local std::string g_last_error;
 
@@ -71,7 +75,7 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   p.T = sys->n_types;
   p.precision = prm->precision;
   p.kernel = prm->kernel == NB_KERNEL_AUTO ? NB_KERNEL_CLUSTER : prm->kernel;
-  p.split = prm->split ? prm->split : 1;
+  p.split = prm->split;  // 0: chosen below from the cluster count
   p.schedule = prm->schedule == NB_SCHED_DYNAMIC ? NB_SCHED_DYNAMIC : NB_SCHED_STATIC;  // static measured faster
   p.wg_per_cu = prm->wg_per_cu ? prm->wg_per_cu : 16;
   // Measured on the 23.6k-atom box: 8-atom clusters are faster for FP32 pair math, 4-atom
@@ -125,6 +129,13 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   p.n_cells = cells;
   p.n_blocks = blocks;
   p.n_clusters_max = clusters;
+  // Default items per cluster: the cluster kernels run one item per wave, and the
+  // MI355X holds about 3 to 5 such waves per SIMD (1024 SIMDs).  With few clusters
+  // every wave starts at once and the kernel ends with the busiest SIMD; two items per
+  // cluster give the hardware pieces half as large to hand out (measured on the
+  // 23.6k-atom box: pair kernel 70.0 -> 67.9 us mixed, 131 -> 127 us FP64; three
+  // items are no better).  Large batches already have many items per SIMD.
+  if (p.split == 0) p.split = (uses_clusters(p.kernel) && clusters <= kSmallClusterCount) ? 2 : 1;
   p.n_columns = columns;
 
   Layout &l = p.lay;
