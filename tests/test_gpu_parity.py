@@ -220,6 +220,47 @@ def test_relabelled_atoms_give_permuted_forces(chain):
     assert b["status"] == H.NB_STATUS_FAR_EXCLUSION
 
 
+def _jittered_lattice(box, spacing, seed, cutoff, beta):
+    """Atoms on a jittered lattice in an orthorhombic box (no close contacts), two LJ
+    types, alternating charges, no exclusions."""
+    rng = np.random.default_rng(seed)
+    n = [int(L // spacing) for L in box]
+    g = np.stack(np.meshgrid(*[np.arange(k) for k in n], indexing="ij"), -1).reshape(-1, 3)
+    pos = (g + 0.5) * (np.asarray(box) / n) + rng.uniform(-0.3, 0.3, g.shape)
+    N = len(pos)
+    return S.System(name="lattice", pos=np.mod(pos, box), charge=np.where(np.arange(N) % 2 == 0, 0.41, -0.41),
+                    type=(rng.random(N) < 0.3).astype(np.int32), sigma=np.array([3.15, 2.5]),
+                    eps=np.array([0.63, 0.2]), excl_offset=np.zeros(N + 1, np.int32),
+                    excl_index=np.zeros(0, np.int32), box=np.asarray(box, np.float64), cutoff=cutoff,
+                    beta=beta, seed=seed)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+@pytest.mark.parametrize("cutoff,beta", [(9.0, 0.0), (7.0, 0.34), (12.0, 0.25)])
+def test_non_cubic_box_other_cutoffs_and_bare_coulomb(cutoff, beta, precision, kernel):
+    """A 30 x 36 x 42 A box (a different fixed-point scale per axis and a different cell
+    grid per axis), cutoffs of 7 and 12 A, and beta = 0 (the truncated bare Coulomb
+    term, erfc = 1)."""
+    s = _jittered_lattice((30.0, 36.0, 42.0), 2.5, seed=21, cutoff=cutoff, beta=beta)
+    _print_case("non_cubic", cutoff=cutoff, beta=beta, precision=precision, kernel=kernel, n=s.n)
+    out = U.gpu_eval(s, precision, kernel=kernel, energy_call=True)
+    ref = U.oracle_for(s, precision)
+    tol = FP64_TOL if precision == H.NB_FP64 else MIXED_TOL
+    err = U.rel_rms(out["force"], ref["force"])
+    # With beta = 0 the total is a small remainder of pair terms thousands of times
+    # larger, so the energy is judged on the scale of the per-atom energies.
+    scale = float(np.abs(ref["energy"]).sum())
+    e_err = abs(out["energy"][0] - ref["energy_total"]) / scale
+    v_err = U.rel_rms(out["virial"][0], ref["virial"])
+    print(f"  rel_rms={err:.3e} energy/sum|E_i|={e_err:.3e} virial={v_err:.3e}")
+    assert err <= tol
+    assert e_err <= tol
+    assert v_err <= (1e-11 if precision == H.NB_FP64 else 1e-5)
+    assert U.rel_rms(out["atom_energy"], ref["energy"]) <= (1e-11 if precision == H.NB_FP64 else 1e-5)
+    assert out["status"] == 0
+
+
 # --- batches -------------------------------------------------------------------------------
 
 @pytest.mark.parametrize("kernel", KERNELS)
