@@ -148,6 +148,7 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   l.tab32 = take(sizeof(TypePair32) * T2);
   l.cell_count = take(4 * static_cast<size_t>(cells));
   l.cell_start = take(4 * static_cast<size_t>(cells + 1));
+  l.scan_tiles = take(4 * static_cast<size_t>(cells / kScanTileCells + 1));
   l.atom_cell = take(4 * static_cast<size_t>(N));
   l.atom_slot = take(4 * static_cast<size_t>(N));
   l.atom_fix = take(16 * static_cast<size_t>(N));
@@ -184,6 +185,7 @@ Dev dev_view(const Plan &p, void *ws) {
   d.T = p.T;
   d.cell_count = reinterpret_cast<int32_t *>(base + l.cell_count);
   d.cell_start = reinterpret_cast<int32_t *>(base + l.cell_start);
+  d.scan_tiles = reinterpret_cast<int32_t *>(base + l.scan_tiles);
   d.n_cells = p.n_cells;
   d.atom_cell = reinterpret_cast<int32_t *>(base + l.atom_cell);
   d.atom_slot = reinterpret_cast<int32_t *>(base + l.atom_slot);

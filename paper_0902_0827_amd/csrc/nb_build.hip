@@ -33,11 +33,67 @@ constexpr double kTwo32 = 4294967296.0;
 constexpr int kScanBlock = 1024;
 constexpr int kScanPer = 16;  // consecutive counts per thread and pass of k_scan
 constexpr int64_t kFuseCells = 16000;  // cell_start entries that k_scan_scatter keeps in LDS (64 KB)
+static_assert(kScanBlock * kScanPer == kScanTileCells, "one pass of block_scan covers one scan tile");
+
+// A system descriptor as it travels in kernel arguments: the fields that cannot be
+// derived on the device (80 bytes instead of 176, so that 40 fit in one launch).
+struct alignas(8) PackedDesc {
+  int32_t atom_begin, atom_end, cell_begin, blk_begin;
+  int32_t dims[3], reach[3];
+  int32_t clu_begin, clu_end, col_begin, pad;
+  double box[3];
+};
+static_assert(sizeof(PackedDesc) == 80, "packed descriptor layout");
 
 struct DescChunk {
-  SysDesc d[kDescChunk];
+  PackedDesc d[kDescChunk];
   int first, count;
 };
+
+PackedDesc pack_desc(const SysDesc &s) {
+  PackedDesc p{};
+  p.atom_begin = s.atom_begin;
+  p.atom_end = s.atom_end;
+  p.cell_begin = s.cell_begin;
+  p.blk_begin = s.blk_begin;
+  for (int a = 0; a < 3; ++a) {
+    p.dims[a] = s.dims[a];
+    p.reach[a] = s.reach[a];
+    p.box[a] = s.box[a];
+  }
+  p.clu_begin = s.clu_begin;
+  p.clu_end = s.clu_end;
+  p.col_begin = s.col_begin;
+  return p;
+}
+
+// The full descriptor, with the derived fields computed by the same IEEE operations as
+// on the host (a correctly rounded division, an exact power-of-two scaling).
+__device__ SysDesc unpack_desc(const PackedDesc &p) {
+  SysDesc s;
+  s.atom_begin = p.atom_begin;
+  s.atom_end = p.atom_end;
+  s.cell_begin = p.cell_begin;
+  s.blk_begin = p.blk_begin;
+  for (int a = 0; a < 3; ++a) {
+    const double L = p.box[a];
+    s.dims[a] = p.dims[a];
+    s.reach[a] = p.reach[a];
+    s.box[a] = L;
+    s.inv_box[a] = 1.0 / L;
+    s.scale[a] = L / 4294967296.0;
+    s.scale2f[a] = static_cast<float>(s.scale[a] * s.scale[a]);
+  }
+  s.dims[3] = 0;
+  s.reach[3] = 0;
+  s.box[3] = s.inv_box[3] = s.scale[3] = 0.0;
+  s.scale2f[3] = 0.f;
+  s.clu_begin = p.clu_begin;
+  s.clu_end = p.clu_end;
+  s.col_begin = p.col_begin;
+  s.pad0 = 0;
+  return s;
+}
 
 __device__ inline int find_system(const SysDesc *desc, int B, int atom) {
   int lo = 0, hi = B - 1;
@@ -59,14 +115,14 @@ __device__ inline int column_system(const SysDesc *desc, int B, int col) {
 
 __global__ void k_put_desc(Dev d, DescChunk c) {
   const int k = threadIdx.x;
-  if (k < c.count) d.desc[c.first + k] = c.d[k];
+  if (k < c.count) d.desc[c.first + k] = unpack_desc(c.d[k]);
 }
 
 __global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, const double *__restrict__ eps,
                        int kernel, int f64) {
   const int64_t tid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  if (tid < c.count) d.desc[c.first + tid] = c.d[tid];
+  if (tid < c.count) d.desc[c.first + tid] = unpack_desc(c.d[tid]);
   if (tid == 0) {
     d.status[0] = 0u;
     d.status[1] = kBuiltMagic;
@@ -142,14 +198,20 @@ __global__ void k_bin(Dev d, const Real *__restrict__ pos, const int32_t *__rest
   const int t = type[i];
   if (t < 0 || t >= d.T) set_status(d, NB_STATUS_BAD_TYPE);
 
-  // Exclusions: a pair listed in either row excludes both ways, so each listed pair
-  // marks the windows of both atoms (section 3: bitmaps over |i - j| <= 64).
+  // Exclusions: a pair listed in either row excludes both ways (section 3: bitmaps over
+  // |i - j| <= 64).  The bits of this atom's own row are gathered in registers and added
+  // with one atomicOr per window word that has any; the partner's bit for this atom is
+  // set here only when the partner's row does not list this atom (else the partner sets
+  // it from its own row).  Exclusion lists usually name each pair from both sides, so
+  // this replaces four device-scope atomics per listed pair by about one per atom.
   const int lo = excl_off[i], hi = excl_off[i + 1];
   if (hi < lo) {
     set_status(d, NB_STATUS_BAD_EXCLUSION);
     return;
   }
   const int n_sys = sd.atom_end - sd.atom_begin;
+  const int il = i - sd.atom_begin;
+  uint32_t own0 = 0u, own1 = 0u, own2 = 0u, own3 = 0u;
   for (int k = lo; k < hi; ++k) {
     const int jl = excl_idx[k];
     if (jl < 0 || jl >= n_sys) {
@@ -160,14 +222,28 @@ __global__ void k_bin(Dev d, const Real *__restrict__ pos, const int32_t *__rest
     const int delta = j - i;
     if (delta == 0) continue;
     if (delta >= -kWindow && delta <= kWindow) {
-      window_set(d, i, delta);
-      window_set(d, j, -delta);
+      const int bit = delta < 0 ? delta + kWindow : delta + kWindow - 1;
+      const uint32_t m = 1u << (bit & 31);
+      const int ws = bit >> 5;
+      own0 |= ws == 0 ? m : 0u;
+      own1 |= ws == 1 ? m : 0u;
+      own2 |= ws == 2 ? m : 0u;
+      own3 |= ws == 3 ? m : 0u;
+      const int jlo = excl_off[j], jhi = excl_off[j + 1];
+      bool listed = false;
+      for (int q = jlo; q < jhi && !listed; ++q) listed = excl_idx[q] == il;
+      if (!listed) window_set(d, j, -delta);
     } else {
       atomicOr(&d.excl_far[i], 1u);
       atomicOr(&d.excl_far[j], 1u);
       set_status(d, NB_STATUS_FAR_EXCLUSION);
     }
   }
+  unsigned int *w = reinterpret_cast<unsigned int *>(&d.excl_mask[i]);
+  if (own0) atomicOr(&w[0], own0);
+  if (own1) atomicOr(&w[1], own1);
+  if (own2) atomicOr(&w[2], own2);
+  if (own3) atomicOr(&w[3], own3);
 }
 
 // Exclusive scan of count(0 .. n-1) into store(k, prefix) for k < n and store(n, total),
@@ -286,12 +362,95 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(Dev d, int clusters, int K)
                 [ccs](int64_t k, int v) { ccs[k] = v; }, d.n_columns, lds);
 }
 
-__global__ void k_scatter(Dev d) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Sum of v over the workgroup (kScanBlock threads), returned to every thread.
+__device__ inline int block_sum_int(int v, int *lds) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int t = 0;
+  for (int w = 0; w < kScanBlock / 64; ++w) t += lds[w];
+  __syncthreads();  // lds may be reused
+  return t;
+}
+
+// Cell scan of large grids, in two launches without inter-workgroup waiting: each
+// workgroup first sums its tile of kScanTileCells counts, then (next launch) adds up
+// the totals of the tiles before its own and scans its tile from there.
+__global__ void __launch_bounds__(kScanBlock) k_scan_tiles(Dev d) {
+  __shared__ int lds[kScanBlock / 64];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTileCells;
+  int acc = 0;
+#pragma unroll
+  for (int m = 0; m < kScanPer; ++m) {
+    const int64_t k = base + static_cast<int64_t>(m) * kScanBlock + threadIdx.x;
+    acc += k < d.n_cells ? d.cell_count[k] : 0;
+  }
+  acc = block_sum_int(acc, lds);
+  if (threadIdx.x == 0) d.scan_tiles[blockIdx.x] = acc;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_apply(Dev d) {
+  __shared__ int lds[block_scan_lds<kScanPer>()];
+  int pre = 0;
+  for (int t = threadIdx.x; t < static_cast<int>(blockIdx.x); t += kScanBlock) pre += d.scan_tiles[t];
+  pre = block_sum_int(pre, lds);
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTileCells;
+  const int64_t rest = d.n_cells - base;
+  const int64_t n = rest < kScanTileCells ? rest : kScanTileCells;
+  const bool last = blockIdx.x == gridDim.x - 1;  // writes cell_start[n_cells], the total
+  const int32_t *cnt = d.cell_count + base;
+  int32_t *cstart = d.cell_start + base;
+  block_scan<kScanPer>([cnt](int64_t k) { return static_cast<int>(cnt[k]); },
+                       [cstart, pre, n, last](int64_t k, int v) {
+                         if (k < n || last) cstart[k] = pre + v;
+                       },
+                       n, lds);
+}
+
+constexpr int kColSysLds = 2048;  // systems whose column ranges the column scan keeps in LDS
+
+// Scatter by arrival slot (large grids).  With the cluster kernel one more workgroup,
+// the last, scans the columns' cluster counts from the complete cell_start, 16 rows of
+// columns per pass; a column's system is found by a binary search over the systems'
+// first columns, held in LDS for batches of up to kColSysLds systems.
+__global__ void __launch_bounds__(kScanBlock) k_scatter(Dev d, int clusters, int K) {
+  if (clusters && blockIdx.x == gridDim.x - 1) {
+    __shared__ int lds[block_scan_lds<kScanPer>()];
+    __shared__ int sys_col[kColSysLds], sys_cell[kColSysLds], sys_nz[kColSysLds];
+    const int32_t *cs = d.cell_start;
+    int32_t *ccs = d.col_clu_start;
+    const int B = d.B;
+    if (B <= kColSysLds) {
+      for (int b = threadIdx.x; b < B; b += kScanBlock) {
+        sys_col[b] = d.desc[b].col_begin;
+        sys_cell[b] = d.desc[b].cell_begin;
+        sys_nz[b] = d.desc[b].dims[2];
+      }
+      __syncthreads();
+      auto count = [cs, B, K](int64_t colk) {
+        const int col = static_cast<int>(colk);
+        int lo = 0, hi = B - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (sys_col[mid] <= col) lo = mid; else hi = mid - 1;
+        }
+        const int nz = sys_nz[lo];
+        const int c0 = sys_cell[lo] + (col - sys_col[lo]) * nz;
+        return (cs[c0 + nz] - cs[c0] + K - 1) / K;
+      };
+      block_scan<kScanPer>(count, [ccs](int64_t k, int v) { ccs[k] = v; }, d.n_columns, lds);
+    } else {
+      const ColumnClusters cc(d, K);
+      block_scan<kScanPer>([cc, cs](int64_t col) { return cc(cs, static_cast<int>(col)); },
+                           [ccs](int64_t k, int v) { ccs[k] = v; }, d.n_columns, lds);
+    }
+    return;
+  }
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kScanBlock + threadIdx.x;
   if (i >= d.N) return;
   const int cell = d.atom_cell[i];
   const int c0 = d.cell_start[cell], c1 = d.cell_start[cell + 1];
-  d.tmp[c0 + d.atom_slot[i]] = i;
+  d.tmp[c0 + d.atom_slot[i]] = static_cast<int32_t>(i);
   d.s_range[c0 + d.atom_slot[i]] = make_int2(c0, c1);  // for k_finalize, one load away
 }
 
@@ -363,7 +522,7 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
   DescChunk first{};
   first.first = 0;
   first.count = plan.B < kDescChunk ? plan.B : kDescChunk;
-  for (int k = 0; k < first.count; ++k) first.d[k] = plan.desc[k];
+  for (int k = 0; k < first.count; ++k) first.d[k] = pack_desc(plan.desc[k]);
   const int64_t init_work = plan.N > plan.n_cells ? plan.N : plan.n_cells;
   unsigned g_init = grid_for(init_work, kBlock);
   if (g_init > 4096) g_init = 4096;
@@ -373,7 +532,7 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
     DescChunk c{};
     c.first = b0;
     c.count = plan.B - b0 < kDescChunk ? plan.B - b0 : kDescChunk;
-    for (int k = 0; k < c.count; ++k) c.d[k] = plan.desc[b0 + k];
+    for (int k = 0; k < c.count; ++k) c.d[k] = pack_desc(plan.desc[b0 + k]);
     hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, c);
   }
   const int clusters = uses_clusters(plan.kernel) ? 1 : 0;
@@ -393,8 +552,11 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
     hipLaunchKernelGGL(k_scan_scatter, dim3(gs), dim3(kScanBlock), 4 * static_cast<size_t>(plan.n_cells + 1), s, d,
                        clusters, plan.cluster_size);
   } else {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, s, d, clusters, plan.cluster_size);
-    hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kBlock), 0, s, d);
+    const unsigned tiles = static_cast<unsigned>((plan.n_cells + kScanTileCells - 1) / kScanTileCells);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kScanBlock), 0, s, d);
+    hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kScanBlock), 0, s, d);
+    const unsigned gs = grid_for(plan.N, kScanBlock) + static_cast<unsigned>(clusters);
+    hipLaunchKernelGGL(k_scatter, dim3(gs), dim3(kScanBlock), 0, s, d, clusters, plan.cluster_size);
   }
   const double sqrt_ke = sqrt(plan.ke);
   if (sys->pos_is_f64)

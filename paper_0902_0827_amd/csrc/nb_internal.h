@@ -18,10 +18,11 @@ constexpr int kBlock = 256;           // threads per workgroup of the per-atom k
 constexpr int kWaves = kBlock / 64;   // wave64
 constexpr int kPart = 10;             // per-block partial sums: energy + 9 virial entries
 constexpr int kWindow = 64;           // exclusion bitmap reach in original index (section 3)
-constexpr int kDescChunk = 8;         // system descriptors carried by one initialisation launch
+constexpr int kDescChunk = 40;        // system descriptors carried by one launch (packed, 80 bytes each)
 constexpr int kXcds = 8;          // MI355X: 8 accelerator complex dies, each with its own L2
 constexpr int kQueueStride = 16;  // uint32 per work counter (one 64-byte line each)
 constexpr uint32_t kBuiltMagic = 0x4E424831u;  // status[1]: written by nb_build_cells
+constexpr int kScanTileCells = 16384;  // cells per workgroup of the multi-workgroup cell scan
 
 // Kernel variants that read the column cluster counts built by nb_build_cells.
 __host__ __device__ __forceinline__ bool uses_clusters(int kernel) {
@@ -62,7 +63,7 @@ struct alignas(16) TypePair32 { float c6, c12, inv_sig, pad; };
 
 // Byte offsets into the workspace (all 256-aligned).
 struct Layout {
-  size_t status, desc, tab64, tab32, cell_count, cell_start, atom_cell, atom_slot, atom_fix, tmp, s_range;
+  size_t status, desc, tab64, tab32, cell_count, cell_start, atom_cell, atom_slot, atom_fix, tmp, s_range, scan_tiles;
   size_t s_fix, s_pos64, s_q32, s_type, excl_mask, excl_far, partials, adj_partials;
   size_t col_clu_start, part, queue, jacc;
   size_t total;
@@ -95,6 +96,7 @@ struct Dev {
   TypePair32 *tab32;
   int T;
   int32_t *cell_count, *cell_start;
+  int32_t *scan_tiles;  // per kScanTileCells cells: their count total (multi-workgroup scan)
   int64_t n_cells;
   int32_t *atom_cell, *atom_slot, *tmp;
   int2 *s_range;     // sorted position (arrival order): the [start, end) of its atom's cell

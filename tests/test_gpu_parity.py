@@ -60,13 +60,14 @@ def test_binning_is_the_stable_counting_sort(divs, precision, chain):
     assert out["status"] == 0
 
 
-@pytest.mark.parametrize("divs", [(2, 2), (2, 8), pytest.param((4, 16), marks=pytest.mark.skip(
+@pytest.mark.parametrize("divs", [(2, 2), (2, 8), (2, 16), (3, 12), pytest.param((4, 16), marks=pytest.mark.skip(
     reason="took a GPU memory fault under a cross-lane (DPP) variant of the wave scans that has since "
            "been removed; the cause was not shown, so the case stays off the GPU this round (the "
-           "separate-scan path is still covered by the one-million-atom test)"))])
+           "multi-workgroup scan is covered by (2, 16) and (3, 12) here and by the large tests)"))])
 def test_binning_at_full_size_config2(divs):
-    """(2, 2) and (2, 8) scan in the scatter launch (cell counts fit in LDS); (4, 16),
-    71,656 cells, takes the separate scan launch."""
+    """(2, 2) and (2, 8) scan in the scatter launch (cell counts fit in LDS); (2, 16),
+    17,914 cells, and (3, 12), 28,519 cells, take the multi-workgroup scan: two tiles of
+    16,384 cells, the second partial."""
     s = U.cached_config(2)
     _print_case("binning-cfg2", divs=divs)
     out = U.gpu_eval(s, H.NB_MIXED, cell_div_xy=divs[0], cell_div_z=divs[1])
@@ -95,6 +96,33 @@ def test_exclusion_windows_are_exact(chain):
     masks, far = OB.exclusion_windows(int(cat["atom_offset"][-1]), off, idx + base)
     np.testing.assert_array_equal(ws["excl_mask"], masks)
     assert not far.any()
+
+
+def test_exclusion_windows_from_one_sided_lists(chain):
+    """A pair listed in only one of its atoms' rows still excludes both ways: the
+    windows equal the oracle's union and the two-sided list's, and so do the forces."""
+    from oracle import binning as OB
+    rng = np.random.default_rng(7)
+    rows = [[] for _ in range(chain.n)]
+    for i in range(chain.n):
+        for k in range(chain.excl_offset[i], chain.excl_offset[i + 1]):
+            j = int(chain.excl_index[k])
+            if i < j or rng.random() < 0.5:  # always in the lower atom's row, half the time in both
+                rows[i].append(j)
+    off = np.zeros(chain.n + 1, np.int32)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    idx = np.array([j for r in rows for j in r], np.int32)
+    assert len(idx) < len(chain.excl_index)  # some pairs are now one-sided
+    one = S.System(**{**chain.__dict__})
+    one.excl_offset, one.excl_index = off, idx
+    for precision in (H.NB_FP64, H.NB_MIXED):
+        a = U.gpu_eval(chain, precision)
+        b = U.gpu_eval(one, precision)
+        masks, far = OB.exclusion_windows(one.n, off, idx)
+        np.testing.assert_array_equal(U.workspace_arrays(b)["excl_mask"], masks)
+        np.testing.assert_array_equal(U.workspace_arrays(b)["excl_mask"], U.workspace_arrays(a)["excl_mask"])
+        np.testing.assert_array_equal(b["force"], a["force"])
+        assert b["status"] == 0
 
 
 @pytest.mark.parametrize("K", [4, 8])
