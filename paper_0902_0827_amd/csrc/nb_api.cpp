@@ -153,7 +153,7 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   l.atom_slot = take(4 * static_cast<size_t>(N));
   l.atom_fix = take(16 * static_cast<size_t>(N));
   l.tmp = take(4 * static_cast<size_t>(N));
-  l.s_range = take(8 * static_cast<size_t>(N));
+  l.s_range = cells + 1 <= kFuseCells ? take(8 * static_cast<size_t>(N)) : 0;
   l.s_fix = take(16 * static_cast<size_t>(N));
   l.s_pos64 = take(32 * static_cast<size_t>(N));
   l.s_q32 = take(4 * static_cast<size_t>(N));
@@ -190,7 +190,7 @@ Dev dev_view(const Plan &p, void *ws) {
   d.atom_cell = reinterpret_cast<int32_t *>(base + l.atom_cell);
   d.atom_slot = reinterpret_cast<int32_t *>(base + l.atom_slot);
   d.tmp = reinterpret_cast<int32_t *>(base + l.tmp);
-  d.s_range = reinterpret_cast<int2 *>(base + l.s_range);
+  d.s_range = p.n_cells + 1 <= kFuseCells ? reinterpret_cast<int2 *>(base + l.s_range) : nullptr;
   d.atom_fix = reinterpret_cast<uint4 *>(base + l.atom_fix);
   d.s_fix = reinterpret_cast<uint4 *>(base + l.s_fix);
   d.s_pos64 = reinterpret_cast<double4 *>(base + l.s_pos64);

@@ -32,7 +32,6 @@ namespace {
 constexpr double kTwo32 = 4294967296.0;
 constexpr int kScanBlock = 1024;
 constexpr int kScanPer = 16;  // consecutive counts per thread and pass of k_scan
-constexpr int64_t kFuseCells = 16000;  // cell_start entries that k_scan_scatter keeps in LDS (64 KB)
 static_assert(kScanBlock * kScanPer == kScanTileCells, "one pass of block_scan covers one scan tile");
 
 // A system descriptor as it travels in kernel arguments: the fields that cannot be
@@ -252,30 +251,26 @@ __global__ void k_bin(Dev d, const Real *__restrict__ pos, const int32_t *__rest
 // stores are coalesced.  Each row is scanned by wave shuffles (rows past n are
 // skipped); the (row, wave) totals are then scanned once to give every wave of every
 // row its offset.  lds holds block_scan_lds<Rows>() ints.
-template <int Rows>
+template <int Rows, int Block = kScanBlock>
 constexpr int block_scan_lds() {
-  return Rows * (kScanBlock / 64) + (Rows * (kScanBlock / 64) + 63) / 64;
+  return Rows * (Block / 64) + (Rows * (Block / 64) + 63) / 64;
 }
 
-template <int Rows, typename Count, typename Store>
-__device__ inline void block_scan(Count count, Store store, int64_t n, int *lds) {
-  constexpr int kW = kScanBlock / 64;  // waves
+// One pass of block_scan: v[m] is entry base + m kScanBlock + threadIdx.x (zero past n).
+// Stores run + the exclusive prefix of each of the pass's entries below n and returns
+// the pass total.
+template <int Rows, int Block, typename Store>
+__device__ inline int scan_pass(const int (&v)[Rows], int64_t base, int64_t n, int run, Store store, int *lds) {
+  constexpr int kW = Block / 64;       // waves
   constexpr int kT = Rows * kW;        // (row, wave) totals per pass
   constexpr int kTW = (kT + 63) / 64;  // waves that scan them
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int run = 0;
-  for (int64_t base = 0; base < n; base += static_cast<int64_t>(kScanBlock) * Rows) {
-    int v[Rows], ex[Rows];
-#pragma unroll
-    for (int m = 0; m < Rows; ++m) {
-      const int64_t k = base + static_cast<int64_t>(m) * kScanBlock + threadIdx.x;
-      const int x = count(k < n ? k : n - 1);  // unconditional load, zeroed below
-      v[m] = k < n ? x : 0;
-    }
+  {
+    int ex[Rows];
 #pragma unroll
     for (int m = 0; m < Rows; ++m) {
       int incl = v[m];
-      if (base + static_cast<int64_t>(m) * kScanBlock < n) {  // wave-uniform
+      if (base + static_cast<int64_t>(m) * Block < n) {  // wave-uniform
         for (int off = 1; off < 64; off <<= 1) {
           const int y = __shfl_up(incl, off, 64);
           if (lane >= off) incl += y;
@@ -311,11 +306,26 @@ __device__ inline void block_scan(Count count, Store store, int64_t n, int *lds)
     }
 #pragma unroll
     for (int m = 0; m < Rows; ++m) {
-      const int64_t k = base + static_cast<int64_t>(m) * kScanBlock + threadIdx.x;
+      const int64_t k = base + static_cast<int64_t>(m) * Block + threadIdx.x;
       if (k < n) store(k, run + lds[m * kW + wave] + ex[m]);
     }
-    run += tot_all;
     __syncthreads();  // lds is reused by the next pass
+    return tot_all;
+  }
+}
+
+template <int Rows, int Block = kScanBlock, typename Count, typename Store>
+__device__ inline void block_scan(Count count, Store store, int64_t n, int *lds) {
+  int run = 0;
+  for (int64_t base = 0; base < n; base += static_cast<int64_t>(Block) * Rows) {
+    int v[Rows];
+#pragma unroll
+    for (int m = 0; m < Rows; ++m) {
+      const int64_t k = base + static_cast<int64_t>(m) * Block + threadIdx.x;
+      const int x = count(k < n ? k : n - 1);  // unconditional load, zeroed below
+      v[m] = k < n ? x : 0;
+    }
+    run += scan_pass<Rows, Block>(v, base, n, run, store, lds);
   }
   if (threadIdx.x == 0) store(n, run);
 }
@@ -409,59 +419,80 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply(Dev d) {
 
 constexpr int kColSysLds = 2048;  // systems whose column ranges the column scan keeps in LDS
 
-// Scatter by arrival slot (large grids).  With the cluster kernel one more workgroup,
-// the last, scans the columns' cluster counts from the complete cell_start, 16 rows of
-// columns per pass; a column's system is found by a binary search over the systems'
-// first columns, held in LDS for batches of up to kColSysLds systems.
-__global__ void __launch_bounds__(kScanBlock) k_scatter(Dev d, int clusters, int K) {
-  if (clusters && blockIdx.x == gridDim.x - 1) {
-    __shared__ int lds[block_scan_lds<kScanPer>()];
-    __shared__ int sys_col[kColSysLds], sys_cell[kColSysLds], sys_nz[kColSysLds];
-    const int32_t *cs = d.cell_start;
-    int32_t *ccs = d.col_clu_start;
+
+// Scatter by arrival slot (large grids).  With the cluster kernel the first
+// ceil(n_columns / kBlock) workgroups also write each column's cluster count into
+// col_clu_start (k_finalize scans it in place): a column's system is found by a binary
+// search over the systems' first columns, held in LDS for up to kColSysLds systems.
+__global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int clusters, int K) {
+  __shared__ int sys_col[kColSysLds], sys_cell[kColSysLds], sys_nz[kColSysLds];
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (clusters && static_cast<int64_t>(blockIdx.x) * kBlock < d.n_columns) {  // workgroup-uniform
     const int B = d.B;
+    const int col = static_cast<int>(t);
+    const bool in = t < d.n_columns;
+    int cb, cbeg, nz;
     if (B <= kColSysLds) {
-      for (int b = threadIdx.x; b < B; b += kScanBlock) {
+      for (int b = threadIdx.x; b < B; b += kBlock) {
         sys_col[b] = d.desc[b].col_begin;
         sys_cell[b] = d.desc[b].cell_begin;
         sys_nz[b] = d.desc[b].dims[2];
       }
       __syncthreads();
-      auto count = [cs, B, K](int64_t colk) {
-        const int col = static_cast<int>(colk);
-        int lo = 0, hi = B - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (sys_col[mid] <= col) lo = mid; else hi = mid - 1;
-        }
-        const int nz = sys_nz[lo];
-        const int c0 = sys_cell[lo] + (col - sys_col[lo]) * nz;
-        return (cs[c0 + nz] - cs[c0] + K - 1) / K;
-      };
-      block_scan<kScanPer>(count, [ccs](int64_t k, int v) { ccs[k] = v; }, d.n_columns, lds);
+      int lo = 0, hi = B - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sys_col[mid] <= col) lo = mid; else hi = mid - 1;
+      }
+      cb = sys_cell[lo];
+      cbeg = sys_col[lo];
+      nz = sys_nz[lo];
     } else {
-      const ColumnClusters cc(d, K);
-      block_scan<kScanPer>([cc, cs](int64_t col) { return cc(cs, static_cast<int>(col)); },
-                           [ccs](int64_t k, int v) { ccs[k] = v; }, d.n_columns, lds);
+      const SysDesc &sd = d.desc[in ? column_system(d.desc, B, col) : 0];
+      cb = sd.cell_begin;
+      cbeg = sd.col_begin;
+      nz = sd.dims[2];
     }
-    return;
+    if (in) {
+      const int c0 = cb + (col - cbeg) * nz;
+      d.col_clu_start[col] = (d.cell_start[c0 + nz] - d.cell_start[c0] + K - 1) / K;
+    }
   }
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * kScanBlock + threadIdx.x;
-  if (i >= d.N) return;
-  const int cell = d.atom_cell[i];
-  const int c0 = d.cell_start[cell], c1 = d.cell_start[cell + 1];
-  d.tmp[c0 + d.atom_slot[i]] = static_cast<int32_t>(i);
-  d.s_range[c0 + d.atom_slot[i]] = make_int2(c0, c1);  // for k_finalize, one load away
+  if (t >= d.N) return;
+  d.tmp[d.cell_start[d.atom_cell[t]] + d.atom_slot[t]] = static_cast<int32_t>(t);
 }
 
+// With col_scan (large grids, cluster kernel) the first workgroup turns the column
+// cluster counts written by k_scatter into their exclusive scan, in place, while the
+// others place the atoms.
 template <typename Real>
-__global__ void k_finalize(Dev d, const Real *__restrict__ pos, const Real *__restrict__ charge,
-                           const int32_t *__restrict__ type, double sqrt_ke, int f64) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kBlock) k_finalize(Dev d, const Real *__restrict__ pos,
+                                                    const Real *__restrict__ charge,
+                                                    const int32_t *__restrict__ type, double sqrt_ke, int f64,
+                                                    int have_range, int col_scan) {
+  if (col_scan && blockIdx.x == 0) {
+    __shared__ int lds[block_scan_lds<kScanPer, kBlock>()];
+    int32_t *ccs = d.col_clu_start;
+    block_scan<kScanPer, kBlock>([ccs](int64_t k) { return static_cast<int>(ccs[k]); },
+                                 [ccs](int64_t k, int v) { ccs[k] = v; }, d.n_columns, lds);
+    return;
+  }
+  const int s = (blockIdx.x - col_scan) * kBlock + threadIdx.x;
   if (s >= d.N) return;
   const int i = d.tmp[s];
-  const int2 cr = d.s_range[s];  // the cell's positions, stored by the scatter
-  const int lo = cr.x, hi = cr.y;
+  // The cell's positions: stored per position by the fused scatter (one load away), or
+  // looked up through the atom's cell.  (For large batches the extra scattered store
+  // costs more than the two dependent loads it saves.)
+  int lo, hi;
+  if (have_range) {
+    const int2 cr = d.s_range[s];
+    lo = cr.x;
+    hi = cr.y;
+  } else {
+    const int cell = d.atom_cell[i];
+    lo = d.cell_start[cell];
+    hi = d.cell_start[cell + 1];
+  }
   int rank = 0;
   for (int k = lo; k < hi; ++k) rank += d.tmp[k] < i;
   const int dst = lo + rank;
@@ -553,18 +584,21 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
                        clusters, plan.cluster_size);
   } else {
     const unsigned tiles = static_cast<unsigned>((plan.n_cells + kScanTileCells - 1) / kScanTileCells);
+    const unsigned gc = clusters ? grid_for(plan.n_columns, kBlock) : 0;  // column count workgroups
     hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kScanBlock), 0, s, d);
     hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kScanBlock), 0, s, d);
-    const unsigned gs = grid_for(plan.N, kScanBlock) + static_cast<unsigned>(clusters);
-    hipLaunchKernelGGL(k_scatter, dim3(gs), dim3(kScanBlock), 0, s, d, clusters, plan.cluster_size);
+    hipLaunchKernelGGL(k_scatter, dim3(g > gc ? g : gc), dim3(kBlock), 0, s, d, clusters, plan.cluster_size);
   }
   const double sqrt_ke = sqrt(plan.ke);
+  const int have_range = plan.n_cells + 1 <= kFuseCells ? 1 : 0;  // written by k_scan_scatter
+  const int col_scan = (!have_range && clusters) ? 1 : 0;           // column counts written by k_scatter
+  const unsigned gf = g + static_cast<unsigned>(col_scan);
   if (sys->pos_is_f64)
-    hipLaunchKernelGGL(k_finalize<double>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const double *>(sys->pos),
-                       static_cast<const double *>(sys->charge), sys->type, sqrt_ke, f64);
+    hipLaunchKernelGGL(k_finalize<double>, dim3(gf), dim3(kBlock), 0, s, d, static_cast<const double *>(sys->pos),
+                       static_cast<const double *>(sys->charge), sys->type, sqrt_ke, f64, have_range, col_scan);
   else
-    hipLaunchKernelGGL(k_finalize<float>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const float *>(sys->pos),
-                       static_cast<const float *>(sys->charge), sys->type, sqrt_ke, f64);
+    hipLaunchKernelGGL(k_finalize<float>, dim3(gf), dim3(kBlock), 0, s, d, static_cast<const float *>(sys->pos),
+                       static_cast<const float *>(sys->charge), sys->type, sqrt_ke, f64, have_range, col_scan);
   return hipGetLastError();
 }
 

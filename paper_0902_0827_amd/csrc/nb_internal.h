@@ -23,6 +23,7 @@ constexpr int kXcds = 8;          // MI355X: 8 accelerator complex dies, each wi
 constexpr int kQueueStride = 16;  // uint32 per work counter (one 64-byte line each)
 constexpr uint32_t kBuiltMagic = 0x4E424831u;  // status[1]: written by nb_build_cells
 constexpr int kScanTileCells = 16384;  // cells per workgroup of the multi-workgroup cell scan
+constexpr int64_t kFuseCells = 16000;  // at most this many cell_start entries: one fused scan-and-scatter launch (LDS)
 
 // Kernel variants that read the column cluster counts built by nb_build_cells.
 __host__ __device__ __forceinline__ bool uses_clusters(int kernel) {
@@ -99,7 +100,7 @@ struct Dev {
   int32_t *scan_tiles;  // per kScanTileCells cells: their count total (multi-workgroup scan)
   int64_t n_cells;
   int32_t *atom_cell, *atom_slot, *tmp;
-  int2 *s_range;     // sorted position (arrival order): the [start, end) of its atom's cell
+  int2 *s_range;     // sorted position (arrival order): the [start, end) of its atom's cell (fused build only)
   uint4 *atom_fix;   // original order: fixed-point x, y, z, system index
   uint4 *s_fix;      // sorted: fixed-point x, y, z, original index
   double4 *s_pos64;  // sorted: raw x, y, z (double), charge (double)
