@@ -5,15 +5,18 @@
 //   k_init      clear counters, masks and status; write descriptors and the type-pair table
 //   k_bin       per atom: box-fraction fixed point, cell id, atomic cell count (its slot),
 //               and the atom's exclusion row folded into 128-bit index windows
-//   k_scan      exclusive scan of the cell counts -> cell_start; for the cluster kernels
+//   scan        exclusive scan of the cell counts -> cell_start; for the cluster kernels
 //               also the clusters per (x, y) column and their scan -> col_clu_start
 //   k_scatter   atom -> cell_start[cell] + slot (order inside a cell still arbitrary)
 //   k_finalize  rank inside the cell by original index (makes the sort stable and the
 //               result deterministic) and write the sorted per-atom records (the raw
 //               double-precision positions only when the FP64 path will read them)
 //
-// When the cell counts fit in LDS, k_scan and k_scatter are one launch
-// (k_scan_scatter), each workgroup scanning the counts itself.
+// When the cell counts fit in LDS the scan and the scatter are one launch
+// (k_scan_scatter), each workgroup scanning the counts itself, and the last one the
+// columns.  Larger grids scan in two launches (k_scan_tiles, k_scan_apply); their
+// column counts are written by k_scatter and scanned by the first workgroup of
+// k_finalize.  Empty batches take k_scan (one workgroup).
 //
 // Positions become 32-bit box fractions u = floor(x/L * 2^32) mod 2^32, which wraps
 // every coordinate into the box; the 32-bit difference of two such values is the
@@ -31,7 +34,7 @@ namespace {
 
 constexpr double kTwo32 = 4294967296.0;
 constexpr int kScanBlock = 1024;
-constexpr int kScanPer = 16;  // consecutive counts per thread and pass of k_scan
+constexpr int kScanPer = 16;  // rows of kScanBlock counts per pass of block_scan
 static_assert(kScanBlock * kScanPer == kScanTileCells, "one pass of block_scan covers one scan tile");
 
 // A system descriptor as it travels in kernel arguments: the fields that cannot be

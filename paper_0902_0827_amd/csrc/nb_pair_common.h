@@ -22,11 +22,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ int wave_sum_int(int v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 // Inclusive prefix sum over the wave's lanes.
 __device__ __forceinline__ int wave_incl_scan_int(int v) {
   const int lane = static_cast<int>(threadIdx.x) & 63;
@@ -42,14 +37,6 @@ __device__ __forceinline__ int wave_excl_scan_int(int v, int *total) {
   const int incl = wave_incl_scan_int(v);
   *total = __shfl(incl, 63, 64);
   return incl - v;
-}
-
-// Sum over the 8 lanes of each group of 8 consecutive lanes.
-__device__ __forceinline__ double row8_sum(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
-  return v;
 }
 
 // Is the pair (oi, oj) of original indices excluded?  Window bits of oi for
