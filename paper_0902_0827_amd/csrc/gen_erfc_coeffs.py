@@ -19,12 +19,14 @@ written as a polynomial of degree DEG64 in
 which maps [0, inf) onto [-1, 1) and makes g smooth enough in s (it tends to zero
 linearly as s -> 1) that a Chebyshev interpolant of g(x(s)) at DEG64 + 1 nodes,
 computed in 40-digit arithmetic and converted to monomial coefficients, gives g to
-about 2e-16 relative by Horner's rule in double precision over all x >= 0.
+about 2e-16 relative by Horner's rule in double precision over all x >= 0.  A second
+table of degree DEG64_SHORT interpolates g on x <= XMAX64_SHORT only (beta R <= 4.2,
+the usual Ewald settings) to the same accuracy with six terms fewer.
 
 Run it to regenerate the constants printed into nb_pair_math.h:
 
     python gen_erfc_coeffs.py          # single precision (t * P(t))
-    python gen_erfc_coeffs.py --f64    # double precision (polynomial in s)
+    python gen_erfc_coeffs.py --f64    # double precision (polynomial in s), both tables
 """
 
 import mpmath as mp
@@ -35,6 +37,8 @@ DEG = 8
 XMAX = 6.0
 K64 = 3
 DEG64 = 24
+DEG64_SHORT = 18
+XMAX64_SHORT = 4.2
 
 
 def fit(p=P, deg=DEG, xmax=XMAX, iters=60):
@@ -82,6 +86,19 @@ def fit_f64(k=K64, deg=DEG64):
     return [float(v) for v in mono]
 
 
+def fit_f64_short(k=K64, deg=DEG64_SHORT, xmax=XMAX64_SHORT):
+    """Monomial coefficients (lowest first) of g(x(s)) interpolated at Chebyshev nodes of
+    s in [-1, s(xmax)] only: the range x <= xmax that a cutoff with beta R <= xmax uses."""
+    mp.mp.dps = 40
+    k = mp.mpf(k)
+    a, b = mp.mpf(-1), (mp.mpf(xmax) - k) / (mp.mpf(xmax) + k)
+    n = deg + 1
+    nodes = [(a + b) / 2 + (b - a) / 2 * mp.cos(mp.pi * (j + mp.mpf(1) / 2) / n) for j in range(n)]
+    vals = [g_exact(k * (1 + s) / (1 - s)) for s in nodes]
+    coef = mp.lu_solve(mp.matrix([[s ** i for i in range(n)] for s in nodes]), mp.matrix(vals))
+    return [float(coef[i]) for i in range(n)]
+
+
 def horner_f64(coef, x, k=K64):
     s = (x - k) / (x + k)
     acc = coef[-1]
@@ -107,6 +124,14 @@ if __name__ == "__main__":
               f"max relative error of g in double on [0, 30]: {check_f64(coef):.2e}")
         print("constexpr double kErfcxS[] = {")
         for v in coef:
+            print(f"    {v:.17e},")
+        print("};")
+        short = fit_f64_short()
+        print(f"// s = (x - {K64})/(x + {K64}), degree {DEG64_SHORT}, "
+              f"max relative error of g in double on [0, {XMAX64_SHORT}]: "
+              f"{check_f64(short, XMAX64_SHORT, 801):.2e}")
+        print("constexpr double kErfcxShort[] = {")
+        for v in short:
             print(f"    {v:.17e},")
         print("};")
     else:

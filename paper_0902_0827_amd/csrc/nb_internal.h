@@ -131,6 +131,7 @@ enum PairMode : int { kForces = 0, kEnergy = 1, kAdjoint = 2 };
 struct Consts {
   double rc2, beta, two_beta_sqrtpi, ke, sqrt_ke;
   float rc2f, betaf, two_beta_sqrtpif, mb2l2e, rc2_box;
+  int erfc_short;  // beta R within the short FP64 erfc table's range
 };
 
 struct Out {

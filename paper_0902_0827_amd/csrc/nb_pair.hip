@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_atom(Dev d, Consts c, Out o) {
         if (!(r2 < c.rc2) || j == i) return;
         if (pair_excluded(mask_i, far_i, oi, oj, sd.atom_begin, d.excl_far, o.excl_off, o.excl_idx)) return;
         const TypePair64 tp = row64[d.s_type[j]];
-        const PairF64 p = pair_f64(r2, tp.c6, tp.c12, qi64 * pj.w, c.beta, c.two_beta_sqrtpi);
+        const PairF64 p = pair_f64(r2, tp.c6, tp.c12, qi64 * pj.w, c.beta, c.two_beta_sqrtpi, c.erfc_short != 0);
         en += p.u_lj + p.u_c;
         if constexpr (MODE != kEnergy) {
           fx += p.f * dx;
@@ -323,6 +323,7 @@ Consts make_consts(const Plan &p) {
   c.two_beta_sqrtpif = static_cast<float>(c.two_beta_sqrtpi);
   c.mb2l2e = static_cast<float>(-p.beta * p.beta * 1.4426950408889634074);  // -beta^2 log2(e)
   c.rc2_box = static_cast<float>(c.rc2 * 1.0001);  // generous: the box filter may only keep extra atoms
+  c.erfc_short = p.beta * p.cutoff <= kErfcxShortMax ? 1 : 0;
   return c;
 }
 

@@ -521,7 +521,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
           TypePair64 tp;
           if constexpr (TABLDS) tp = TL[ti * T + tj];
           else tp = d.tab64[ti * T + tj];
-          const PairF64 p = pair_f64(r2d, tp.c6, tp.c12, qi64 * pj64.w, c.beta, c.two_beta_sqrtpi);
+          const PairF64 p = pair_f64(r2d, tp.c6, tp.c12, qi64 * pj64.w, c.beta, c.two_beta_sqrtpi, c.erfc_short != 0);
           en += p.u_lj + p.u_c;
           if constexpr (HALF) {
             hgx = p.f * dxd;

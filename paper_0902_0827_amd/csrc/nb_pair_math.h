@@ -111,12 +111,36 @@ __device__ __forceinline__ double fma_s(double a, double b, double c) {
   return r;
 }
 
-__device__ __forceinline__ double erfcx_f64(double x) {
+// The same g as a polynomial of degree 18 in s, interpolated on 0 <= x <= 4.2 only (to
+// 4e-16 relative there): enough for every pair when beta R <= 4.2.
+static __constant__ double kErfcxShort[19] = {
+    1.79001151181389956e-01,
+    -3.26233560043037218e-01,
+    2.45603801712330816e-01,
+    -1.50115936500776648e-01,
+    7.16658371979928960e-02,
+    -2.43924993186649779e-02,
+    4.26913633168420764e-03,
+    7.07746432994099325e-04,
+    -5.97061928621600265e-04,
+    4.52555777698059495e-05,
+    6.40573859040072902e-05,
+    -1.28618544324921400e-05,
+    -7.99671182594526170e-06,
+    2.04925522636487597e-06,
+    1.09284090032394909e-06,
+    -5.33848327689116094e-07,
+    -4.80395335088038175e-07,
+    -1.37166373609392244e-07,
+    -1.50800419617872139e-08};
+constexpr double kErfcxShortMax = 4.2;
+
+__device__ __forceinline__ double erfcx_f64(double x, bool short_range) {
   // The coefficients are read from constant memory through a pointer the compiler
   // cannot treat as loop-invariant, so that they arrive by scalar loads where the
   // chain needs them instead of occupying 48 vector registers across the pair loop.
   using ConstF64 = const __attribute__((address_space(4))) double;
-  ConstF64 *c = (ConstF64 *)(kErfcxS);  // generic -> constant address space
+  ConstF64 *c = (ConstF64 *)(short_range ? kErfcxShort : kErfcxS);  // generic -> constant address space
   asm volatile("" : "+s"(c));
   // 1/(x + 3) from the hardware reciprocal and two Newton steps (x + 3 >= 3)
   const double b = x + 3.0;
@@ -124,9 +148,16 @@ __device__ __forceinline__ double erfcx_f64(double x) {
   y = fma(fma(-b, y, 1.0), y, y);
   y = fma(fma(-b, y, 1.0), y, y);
   const double s = (x - 3.0) * y;
-  double p = c[24];
+  double p;
+  if (short_range) {  // wave-uniform: one choice per call
+    p = c[18];
 #pragma unroll
-  for (int k = 23; k >= 0; --k) p = fma_s(p, s, c[k]);
+    for (int k = 17; k >= 0; --k) p = fma_s(p, s, c[k]);
+  } else {
+    p = c[24];
+#pragma unroll
+    for (int k = 23; k >= 0; --k) p = fma_s(p, s, c[k]);
+  }
   return p;
 }
 
@@ -167,7 +198,7 @@ __device__ __forceinline__ double exp_neg_f64(double y) {
 // exp(-beta^2 r^2) by exp_neg_f64, and erfc from that exponential (which the force
 // needs anyway) times erfcx_f64.
 __device__ __forceinline__ PairF64 pair_f64(double r2, double c6, double c12, double qq, double beta,
-                                            double two_beta_sqrtpi) {
+                                            double two_beta_sqrtpi, bool short_erfc) {
   PairF64 o;
   // 1/r from the hardware reciprocal square root and two Newton steps (r2 > 0 here)
   double rinv = __builtin_amdgcn_rsq(r2);
@@ -181,7 +212,7 @@ __device__ __forceinline__ PairF64 pair_f64(double r2, double c6, double c12, do
   o.u_lj = a - b;
   o.dudsig_lj = 12.0 * a - 6.0 * b;
   const double e = exp_neg_f64(beta * beta * r2);  // exp(-(beta r)^2)
-  const double erfc_br = erfcx_f64(beta * r) * e;
+  const double erfc_br = erfcx_f64(beta * r, short_erfc) * e;
   o.erfc_over_r = erfc_br * rinv;
   o.u_c = qq * o.erfc_over_r;
   o.f = (o.dudsig_lj + qq * (o.erfc_over_r + two_beta_sqrtpi * e)) * rinv2;

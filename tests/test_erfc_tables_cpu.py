@@ -95,3 +95,20 @@ def test_exp_neg_reduction_and_taylor_table():
         ref = mp.exp(-mp.mpf(float(y)))
         worst = max(worst, abs(float((v - ref) / ref)))
     assert worst < 4e-16, worst
+
+
+def test_f64_short_erfcx_table_relative_error_below_4e_16_up_to_4_2():
+    """The table used when beta R <= 4.2."""
+    txt = _text()
+    init = txt[txt.index("kErfcxShort[19] = {"):]
+    coef = [float(v) for v in re.findall(r"-?\d\.\d+e[-+]\d+", init[:init.index("};")])]
+    assert len(coef) == 19
+    assert float(re.search(r"kErfcxShortMax = ([0-9.]+);", txt).group(1)) == 4.2
+    worst = 0.0
+    for x in np.concatenate([np.linspace(0.0, 4.2, 421), [3.06, 4.2 + 1e-9]]):
+        s = (x - 3.0) / (x + 3.0)
+        p = coef[18]
+        for c in reversed(coef[:18]):
+            p = p * s + c
+        worst = max(worst, abs(float((p - _g(x)) / _g(x))))
+    assert worst < 4.5e-16, worst

@@ -265,11 +265,11 @@ def _jittered_lattice(box, spacing, seed, cutoff, beta):
 
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
-@pytest.mark.parametrize("cutoff,beta", [(9.0, 0.0), (7.0, 0.34), (12.0, 0.25)])
+@pytest.mark.parametrize("cutoff,beta", [(9.0, 0.0), (7.0, 0.34), (12.0, 0.25), (9.0, 0.5)])
 def test_non_cubic_box_other_cutoffs_and_bare_coulomb(cutoff, beta, precision, kernel):
     """A 30 x 36 x 42 A box (a different fixed-point scale per axis and a different cell
-    grid per axis), cutoffs of 7 and 12 A, and beta = 0 (the truncated bare Coulomb
-    term, erfc = 1)."""
+    grid per axis), cutoffs of 7 and 12 A, beta = 0 (the truncated bare Coulomb term,
+    erfc = 1), and beta R = 4.5 (beyond the short FP64 erfc table)."""
     s = _jittered_lattice((30.0, 36.0, 42.0), 2.5, seed=21, cutoff=cutoff, beta=beta)
     _print_case("non_cubic", cutoff=cutoff, beta=beta, precision=precision, kernel=kernel, n=s.n)
     out = U.gpu_eval(s, precision, kernel=kernel, energy_call=True)
