@@ -289,6 +289,28 @@ def test_non_cubic_box_other_cutoffs_and_bare_coulomb(cutoff, beta, precision, k
     assert out["status"] == 0
 
 
+@pytest.mark.parametrize("kernel", [H.NB_KERNEL_CLUSTER, "cluster4_static", "half8", H.NB_KERNEL_ATOM])
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+def test_net_force_vanishes_and_translation_leaves_the_result(precision, kernel, chain):
+    """Newton's third law (the forces sum to zero up to rounding) and invariance under a
+    translation that is not a box multiple (every fixed-point coordinate changes)."""
+    out = U.gpu_eval(chain, precision, kernel=kernel)
+    f = out["force"].reshape(-1, 3)
+    f_rms = float(np.sqrt(np.mean(np.sum(f * f, axis=1))))
+    net = float(np.linalg.norm(f.sum(axis=0))) / (chain.n * f_rms)
+    print(f"  net force / (N F_rms) = {net:.3e}")
+    assert net <= (1e-14 if precision == H.NB_FP64 else 1e-7)
+    moved = S.System(**{**chain.__dict__})
+    moved.pos = np.mod(chain.pos + np.array([1.2345, -5.6789, 9.1011]), chain.box)
+    out2 = U.gpu_eval(moved, precision, kernel=kernel)
+    # the mixed path sees the FP32 rounding of the moved positions: compare with the oracle
+    ref = U.oracle_for(moved, precision)
+    tol = FP64_TOL if precision == H.NB_FP64 else MIXED_TOL
+    assert U.rel_rms(out2["force"], ref["force"]) <= tol
+    assert U.rel_rms(out2["force"], out["force"]) <= (1e-12 if precision == H.NB_FP64 else 1e-5)
+    assert out2["energy"][0] == pytest.approx(out["energy"][0], rel=1e-12 if precision == H.NB_FP64 else 1e-5)
+
+
 # --- batches -------------------------------------------------------------------------------
 
 @pytest.mark.parametrize("kernel", KERNELS)
