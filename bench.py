@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "nonbonded force evals/s @23k atoms, mixed vs FP64 at stated RMS force error"
 FP32_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak (dense)
+HBM_PEAK_GBPS = 8000.0    # MI355X published HBM3E bandwidth
 # Algorithmic FP32 work of one in-cutoff, non-excluded, unordered pair evaluated once
 # for force + energy + virial (FMA = 2 flops; rsqrt, reciprocal and exp2 not counted).
 FLOPS_PER_PAIR = 72
@@ -58,6 +59,39 @@ def time_steps(fn, steps, warmup, torch, H):
     per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]) * 1e-3
     return dict(sec=sec, pair_sec=pair_ms * 1e-3 / max(launches, 1), pair_launches=launches,
                 median=float(np.median(per)), p10=float(np.percentile(per, 10)), p90=float(np.percentile(per, 90)))
+
+
+# Algorithmic HBM bytes of nb_build_cells (mixed path, FP32 inputs): per atom read
+# position 12, charge 4, type 4, exclusion row offset 4, and write the sorted record
+# (fixed-point position and index 16, q sqrt(k_e) 4, type 4) and the exclusion window
+# (16 + far flag 4); 4 per exclusion-list entry read; 4 per cell start written.
+BUILD_BYTES_PER_ATOM = 12 + 4 + 4 + 4 + 16 + 4 + 4 + 16 + 4
+BUILD_BYTES_PER_EXCL = 4
+BUILD_BYTES_PER_CELL = 4
+
+
+def time_build(b, p, ws, steps, warmup, torch, H):
+    """Mean microseconds per nb_build_cells alone (HIP events around the loop)."""
+    for _ in range(warmup):
+        H.build_cells(b, p, ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        H.build_cells(b, p, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / steps
+
+
+def build_rate(b, p, ws, steps, torch, H):
+    """The build's algorithmic HBM bytes and achieved GB/s."""
+    us = time_build(b, p, ws, steps, 5, torch, H)
+    lay = H.workspace_layout(b, p)
+    n_excl = int(b.excl_index.numel())
+    nbytes = BUILD_BYTES_PER_ATOM * b.n_atoms + BUILD_BYTES_PER_EXCL * n_excl + BUILD_BYTES_PER_CELL * int(lay.n_cells)
+    return {"atoms": int(b.n_atoms), "cells": int(lay.n_cells), "build_us": us, "bytes": int(nbytes),
+            "achieved": nbytes / us * 1e-3, "frac": nbytes / us * 1e-3 / HBM_PEAK_GBPS}
 
 
 PAIR_SOURCES = ("nb_pair_cluster.hip", "nb_pair_math.h", "nb_pair_common.h", "nb_internal.h")
@@ -118,6 +152,7 @@ def run_batch(args, H, S, torch):
 
     t = time_steps(step, args.batch_steps, 5, torch, H)
     f = force.cpu().numpy()
+    build = build_rate(b, p, ws, args.batch_steps, torch, H)
     status = H.read_status(ws)
     log(f"[bench] batch: {t['sec'] * 1e3:.3f} ms/step, pair kernel {t['pair_sec'] * 1e6:.1f} us; params {chosen}")
     # sampled FP64 oracle rows (inputs rounded as the device saw them)
@@ -142,7 +177,7 @@ def run_batch(args, H, S, torch):
             "pair_kernel_us": t["pair_sec"] * 1e6, "atoms_per_s": b.n_atoms / t["sec"],
             "pairs_per_s_estimate": est_pairs / t["sec"], "pairs_in_cutoff_estimate": est_pairs,
             "rel_rms_force_sampled": float(np.sqrt(err_num / err_den)), "sampled_atoms": n_rows,
-            "params": chosen, "status_bits": status}
+            "params": chosen, "status_bits": status, "build": build}
 
 
 def main():
@@ -216,8 +251,9 @@ def main():
         steps = args.steps if prec == H.NB_MIXED else max(10, args.steps // 4)
         t = time_steps(step, steps, args.warmup, torch, H)
         torch.cuda.synchronize()
+        build = build_rate(b, p, ws, steps, torch, H) if prec == H.NB_MIXED else None
         results[prec_name] = dict(t, steps=steps, force=force.cpu().numpy(), energy=float(energy.cpu()[0]),
-                                  status=H.read_status(ws))
+                                  status=H.read_status(ws), build=build)
         log(f"[bench] {prec_name}: {t['sec'] * 1e3:.4f} ms/step (median {t['median'] * 1e3:.4f}), "
             f"pair kernel {t['pair_sec'] * 1e6:.1f} us over {t['pair_launches']} launches")
 
@@ -285,6 +321,12 @@ def main():
                      "launch_us": m["pair_sec"] * 1e6, "flops_per_pair": FLOPS_PER_PAIR},
         "cpu_baseline": cpu,
         "batch": batch,
+        # nb_build_cells alone: algorithmic HBM bytes (inputs read once, sorted records and
+        # exclusion windows written once) over its time, for this box and for the batch
+        "binning": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBPS,
+                    "bytes_per_atom": BUILD_BYTES_PER_ATOM, "bytes_per_exclusion_entry": BUILD_BYTES_PER_EXCL,
+                    "bytes_per_cell": BUILD_BYTES_PER_CELL, "box": m.get("build"),
+                    "batch": None if batch is None else batch.get("build")},
         "status_bits": [r["status"] for r in results.values()],
     }
     print(json.dumps(out), flush=True)
