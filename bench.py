@@ -252,8 +252,25 @@ def main():
         t = time_steps(step, steps, args.warmup, torch, H)
         torch.cuda.synchronize()
         build = build_rate(b, p, ws, steps, torch, H) if prec == H.NB_MIXED else None
+        # the adjoint (dE/dx, dE/dq, dE/dsigma_t, dE/deps_t with grad_energy = 1): build + backward
+        T = b.sigma.shape[0]
+        g_e = torch.ones(1, dtype=torch.float64, device="cuda")
+        g_x = torch.empty((s.n, 3), dtype=torch.float64, device="cuda")
+        g_q = torch.empty(s.n, dtype=torch.float64, device="cuda")
+        g_s = torch.empty(T, dtype=torch.float64, device="cuda")
+        g_p = torch.empty(T, dtype=torch.float64, device="cuda")
+
+        def adj_step():
+            H.build_cells(b, p, ws)
+            H.nonbonded_backward(b, p, ws, g_e, g_x, g_q, g_s, g_p)
+
+        adj_steps = max(10, steps // 4)
+        t_adj = time_steps(adj_step, adj_steps, args.warmup, torch, H)
+        adjoint = dict(sec=t_adj["sec"], pair_sec=t_adj["pair_sec"], steps=adj_steps, grad_pos=g_x.cpu().numpy(),
+                       grad_charge=g_q.cpu().numpy(), grad_sigma=g_s.cpu().numpy(), grad_eps=g_p.cpu().numpy())
+        log(f"[bench] {prec_name} adjoint: {t_adj['sec'] * 1e3:.4f} ms/step, pair kernel {t_adj['pair_sec'] * 1e6:.1f} us")
         results[prec_name] = dict(t, steps=steps, force=force.cpu().numpy(), energy=float(energy.cpu()[0]),
-                                  status=H.read_status(ws), build=build)
+                                  status=H.read_status(ws), build=build, adjoint=adjoint)
         log(f"[bench] {prec_name}: {t['sec'] * 1e3:.4f} ms/step (median {t['median'] * 1e3:.4f}), "
             f"pair kernel {t['pair_sec'] * 1e6:.1f} us over {t['pair_launches']} launches")
 
@@ -288,6 +305,14 @@ def main():
     f64 = results.get("fp64")
     err_m = rel_errors(m["force"], ref["mixed"]["force"])
     err_d = rel_errors(f64["force"], ref["fp64"]["force"]) if f64 else (None, None)
+
+    def adjoint_entry(res, r):
+        a = res["adjoint"]
+        rel = lambda x, y: float(np.linalg.norm(np.asarray(x) - y) / max(np.linalg.norm(y), 1e-300))
+        return {"value": 1.0 / a["sec"], "unit": "evals/s", "ms_per_step": a["sec"] * 1e3, "steps": a["steps"],
+                "pair_kernel_us": a["pair_sec"] * 1e6,
+                "rel_rms_grad_pos": rel(a["grad_pos"], -r["force"]), "rel_rms_grad_charge": rel(a["grad_charge"], r["phi"]),
+                "rel_grad_sigma": rel(a["grad_sigma"], r["dsigma"]), "rel_grad_eps": rel(a["grad_eps"], r["deps"])}
     achieved = pairs * FLOPS_PER_PAIR / m["pair_sec"] / 1e12
     default_kernel = args.kernel == "auto" and args.split == 0 and args.cluster_size == 0 and \
         args.cell_div == "0,0" and args.schedule == "auto" and args.wg_per_cu == 0
@@ -320,6 +345,9 @@ def main():
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
                      "launch_us": m["pair_sec"] * 1e6, "flops_per_pair": FLOPS_PER_PAIR},
         "cpu_baseline": cpu,
+        # nb_build_cells + nb_nonbonded_backward (dE/dx, dE/dq, dE/dsigma_t, dE/deps_t), errors
+        # against the oracle's gradients
+        "adjoint": {name: adjoint_entry(results[name], ref[name]) for name in results},
         "batch": batch,
         # nb_build_cells alone: algorithmic HBM bytes (inputs read once, sorted records and
         # exclusion windows written once) over its time, for this box and for the batch
