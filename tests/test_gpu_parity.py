@@ -5,6 +5,7 @@ precision pair terms: per-pair relative error ~1e-7, see the erfc fit and the
 fixed-point positions); binning and exclusion windows bit-exact.
 """
 
+import dataclasses
 import functools
 
 import numpy as np
@@ -466,6 +467,58 @@ def test_config5_mixed_against_sampled_oracle_and_fp64_gpu():
     fp64 = U.gpu_eval(s, H.NB_FP64)
     ref64 = U.oracle_for(s, H.NB_FP64, rows=rows)
     assert U.rel_rms(fp64["force"][rows], ref64["force"]) <= FP64_TOL
+
+
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+def test_config5_adjoint_identities_sampled_oracle_and_fp64_gpu(precision):
+    """The adjoint at full size (999,999 atoms, R = 12 A), where the oracle can only take
+    sampled rows.  Besides dE/dq on sampled rows and dE/dx = -F, three identities pin the
+    per-type and per-charge sums at any size.  E_LJ is homogeneous of degree one in the
+    eps_t (eps_ij = sqrt(eps_ti eps_tj)), so sum_t eps_t dE/deps_t = E_LJ; scaling every
+    sigma_t scales every sigma_ij, and s dE_LJ/ds = sum over pairs of (12 A - 6 B) = the
+    trace of the LJ virial; E_C is quadratic in the charges, so sum_i q_i dE/dq_i = 2 E_C.
+    E_C and the Coulomb virial come from the same call with every eps_t set to zero."""
+    s = U.cached_config(5).rounded(np.float32)  # one set of inputs for both paths
+    _print_case("cfg5-adjoint", n=s.n, precision=precision)
+    out = U.gpu_eval(s, precision, backward=True)
+    s_c = dataclasses.replace(s, eps=np.zeros_like(s.eps))
+    coul = U.gpu_eval(s_c, precision)
+    e, e_c = float(out["energy"][0]), float(coul["energy"][0])
+    tr_w = float(np.trace(out["virial"].reshape(3, 3)))
+    tr_wc = float(np.trace(coul["virial"].reshape(3, 3)))
+    q_sum = float(np.dot(s.charge, out["grad_charge"]))
+    eps_sum = float(np.dot(s.eps, out["grad_eps"]))
+    sig_sum = float(np.dot(s.sigma, out["grad_sigma"]))
+    print(f"  q.dE/dq={q_sum:.10e} 2E_C={2 * e_c:.10e}  eps.dE/deps={eps_sum:.10e} E_LJ={e - e_c:.10e}  "
+          f"sig.dE/dsig={sig_sum:.10e} trW_LJ={tr_w - tr_wc:.10e}")
+    if precision == H.NB_FP64:
+        assert q_sum == pytest.approx(2 * e_c, rel=1e-10)
+        assert eps_sum == pytest.approx(e - e_c, rel=1e-10)
+        assert sig_sum == pytest.approx(tr_w - tr_wc, rel=1e-10)
+    else:
+        # E_C and E_LJ are small differences of per-atom sums 100-1000 times larger, so
+        # per-pair errors of ~1e-7 are compared on the scale of those sums: sum |q_i phi_i|
+        # for the charges, and the per-type tolerance of the other adjoint tests (1e-4)
+        # for eps and sigma.
+        scale = float(np.abs(s.charge * out["grad_charge"]).sum())
+        print(f"  sum|q phi|={scale:.4e}")
+        assert abs(q_sum - 2 * e_c) <= MIXED_TOL * scale
+        assert eps_sum == pytest.approx(e - e_c, rel=10 * MIXED_TOL)
+        assert sig_sum == pytest.approx(tr_w - tr_wc, rel=10 * MIXED_TOL)
+    assert U.rel_rms(out["grad_pos"], -out["force"]) <= (1e-12 if precision == H.NB_FP64 else 1e-6)
+    rows = np.random.default_rng(55).choice(s.n, 96, replace=False)
+    ref = O.evaluate_system(s, rows=rows, ke=H.COULOMB_K)
+    assert U.rel_rms(out["grad_charge"][rows], ref["phi"]) <= (FP64_TOL if precision == H.NB_FP64 else MIXED_TOL)
+    assert U.rel_rms(out["grad_pos"][rows], -ref["force"]) <= (FP64_TOL if precision == H.NB_FP64 else MIXED_TOL)
+    if precision == H.NB_MIXED:  # against the FP64 GPU path on the same inputs
+        ref64 = U.gpu_eval(s, H.NB_FP64, backward=True)
+        for k in ("grad_pos", "grad_charge"):
+            err = U.rel_rms(out[k], ref64[k])
+            print(f"  {k}: mixed vs fp64 gpu rel_rms={err:.3e}")
+            assert err <= MIXED_TOL
+        lj = s.eps > 0
+        np.testing.assert_allclose(out["grad_sigma"][lj], ref64["grad_sigma"][lj], rtol=10 * MIXED_TOL)
+        np.testing.assert_allclose(out["grad_eps"][lj], ref64["grad_eps"][lj], rtol=10 * MIXED_TOL)
 
 
 def test_pair_kernels_refuse_a_workspace_built_for_another_kernel(chain):
