@@ -112,8 +112,7 @@ typedef struct {
   int32_t cell_div_z; /* cells per cutoff along z, 1..16 (0 = the kernel's default) */
   int32_t kernel;     /* NB_KERNEL_* */
   int32_t split;      /* cluster kernel: work items per cluster, each taking an equal share of
-                         its candidate j atoms, 1..8 (0 = 2 for batches of at most 6144
-                         clusters, else 1) */
+                         its candidate j atoms, 1..8 (0 = 1) */
   int32_t cluster_size; /* cluster kernel: atoms per i-cluster, 4 or 8 (0 = 8 mixed, 4 FP64) */
   int32_t schedule;   /* cluster kernel: NB_SCHED_* (0 = static) */
   int32_t wg_per_cu;  /* dynamic schedule: resident one-wave workgroups per compute unit, 1..32 (0 = 16) */

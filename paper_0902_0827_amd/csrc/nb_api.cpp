@@ -12,10 +12,6 @@
 
 namespace nb {
 
-// At most this many clusters (about 6 per SIMD of the MI355X) take two work items per
-// cluster by default.
-constexpr int64_t kSmallClusterCount = 6144;
-
 namespace {
 thread_local std::string g_last_error;
 
@@ -129,13 +125,12 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   p.n_cells = cells;
   p.n_blocks = blocks;
   p.n_clusters_max = clusters;
-  // Default items per cluster: the cluster kernels run one item per wave, and the
-  // MI355X holds about 3 to 5 such waves per SIMD (1024 SIMDs).  With few clusters
-  // every wave starts at once and the kernel ends with the busiest SIMD; two items per
-  // cluster give the hardware pieces half as large to hand out (measured on the
-  // 23.6k-atom box: pair kernel 70.0 -> 67.9 us mixed, 131 -> 127 us FP64; three
-  // items are no better).  Large batches already have many items per SIMD.
-  if (p.split == 0) p.split = (uses_clusters(p.kernel) && clusters <= kSmallClusterCount) ? 2 : 1;
+  // Default: one work item per cluster.  Two items per cluster hand the hardware pieces
+  // half as large, but each adds its own setup, row reductions and partial sums for
+  // k_finish to add: on the 23.6k-atom box (3,120 8-atom clusters, 3 waves per SIMD of
+  // the MI355X) one item per cluster gives the faster step on both paths (mixed
+  // 0.098 against 0.100 ms, FP64 0.161 against 0.163 ms).
+  if (p.split == 0) p.split = 1;
   p.n_columns = columns;
 
   Layout &l = p.lay;

@@ -45,6 +45,11 @@ constexpr int kRunPad = 4;           // sentinel entries after the last run
 // 128 VGPRs, no spills); left alone the compiler takes 134 and 3 waves fit.
 constexpr int kF64WavesPerEu = 4;
 constexpr int kFinishBlock = 256;
+// Exclusion window of one i atom in LDS, one byte per index difference: byte d is 1 when
+// j - i = d - 64 is excluded (d = 0..128; d = 64, the atom itself, is 1), and bytes
+// 129-131 are 0, so a difference outside the window reads byte 129.
+constexpr int kExBytes = 132;
+constexpr uint32_t kExClear = 2u * kWindow + 1u;
 
 __device__ __forceinline__ uint32_t uabs_diff(uint32_t a, uint32_t b) {
   const int32_t d = static_cast<int32_t>(a - b);
@@ -129,6 +134,7 @@ template <>
 struct WaveLds<false> {
   RingF32 ring[kRing];
   int2 runs[kMaxRuns + kRunPad];  // non-empty candidate runs: (first sorted atom, first candidate position)
+  uint32_t exw[8 * kExBytes / 4];  // exclusion window of each row's i atom, bytes
 };
 
 template <>
@@ -221,6 +227,18 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   const int T = d.T;
   StageT<F64> *const ST = reinterpret_cast<StageT<F64> *>(reinterpret_cast<char *>(tab_lds) +
                                                           (TABLDS ? tab_lds_bytes<F64>(T) : 0));
+  // Ring slots are read by every lane of a group, also those past the candidates it holds
+  // (their results are discarded): zeroed once, every slot holds a valid type index.
+  for (int k = lane; k < kRing; k += 64) {
+    if constexpr (F64) {
+      L.pos[k] = make_double4(0, 0, 0, 0);
+      L.meta[k] = make_int4(0, 0, 0, 0);
+    } else {
+      L.ring[k].fix = make_uint4(0u, 0u, 0u, 0u);
+      L.ring[k].qt = make_float2(0.f, 0.f);
+      L.ring[k].sidx = make_int2(0, 0);
+    }
+  }
   if constexpr (TABLDS) {
     for (int k = lane; k < T * T; k += 64) {
       if constexpr (F64) TL[k] = d.tab64[k];
@@ -305,6 +323,12 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     const int ia = ivalid ? i : first;
     const uint4 fi = d.s_fix[ia];
     const int oi = static_cast<int>(fi.w);
+    // Mixed path: the window byte of candidate oj is oj - oi_lo (unsigned, clamped) in row
+    // ii's window in LDS.  FP64 path: the mask stays in registers (LDS there is what limits
+    // the resident waves).
+    const uint32_t oi_lo = static_cast<uint32_t>(oi) - static_cast<uint32_t>(kWindow);
+    const uint8_t *ex_row = nullptr;
+    if constexpr (!F64) ex_row = reinterpret_cast<const uint8_t *>(L.exw) + ii * kExBytes;
     const uint4 mask_i = d.excl_mask[oi];
     const uint64_t mask_lo = (static_cast<uint64_t>(mask_i.y) << 32) | mask_i.x;
     const uint64_t mask_hi = (static_cast<uint64_t>(mask_i.w) << 32) | mask_i.z;
@@ -354,7 +378,20 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     // runs[r].y <= p < runs[r + 1].y, at sorted index runs[r].x + p - runs[r].y.
     const int ncol = xn * yn;
     int nrun = 0, total = 0;  // wave-uniform
-    wave_lds_sync();  // the previous item's reads of the runs are complete
+    wave_lds_sync();  // the previous item's reads of the runs and windows are complete
+    // Row ii's window as bytes, 4 per word: bits 0-63 of the mask are j - i = -64..-1,
+    // then j = i, then mask bits 64-127 (j - i = 1..64); word m holds bits 4m..4m+3 of
+    // that 132-bit string, each spread to the low bit of a byte.
+    for (int m = jj; !F64 && m < kExBytes / 4; m += J) {
+      const int w = m >> 3;
+      const uint32_t src = w == 0 ? mask_i.x
+                         : w == 1 ? mask_i.y
+                         : w == 2 ? (mask_i.z << 1) | 1u
+                         : w == 3 ? (mask_i.w << 1) | (mask_i.z >> 31)
+                                  : mask_i.w >> 31;
+      const uint32_t nib = (src >> ((m & 7) * 4)) & 15u;
+      if constexpr (!F64) L.exw[ii * (kExBytes / 4) + m] = (nib * 0x00204081u) & 0x01010101u;
+    }
     for (int k0 = 0; k0 < ncol; k0 += 64) {
       const int k = k0 + lane;
       int2 r0 = make_int2(0, 0), r1 = make_int2(0, 0);
@@ -473,10 +510,32 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         tj = __float_as_int(L.ring[slot].qt.y);
         if constexpr (HALF) sj = L.ring[slot].sidx.x;
       }
-      // Both ways: j is not i.  Once: candidates before the cluster in sorted order come
-      // from other columns and always count; from the cluster on (its own column) only
-      // those after i.
-      const bool other = HALF ? (sj < first || sj > i) : oi != oj;
+      // Exclusions (and j = i): bit (oj - oi) + 64 of row ii's window (bits 0-63 of the
+      // mask are oj - oi = -64..-1, bits 64-127 are 1..64); a difference outside the window
+      // is not excluded here.  Mixed path: one byte of the window in LDS, read ahead of the
+      // distance.  FP64 path: selected from the mask in registers.
+      uint32_t exb;
+      bool outside;
+      if constexpr (F64) {
+        const int delta = oj - oi;
+        outside = static_cast<uint32_t>(delta + kWindow) > 2u * kWindow;
+        const uint64_t wbits = delta < 0 ? mask_lo : mask_hi;
+        const int wb = delta < 0 ? delta + kWindow : delta - 1;
+        exb = (static_cast<uint32_t>(wbits >> (wb & 63)) & (outside ? 0u : 1u)) | (delta == 0 ? 1u : 0u);
+      } else {
+        const uint32_t dw = min(static_cast<uint32_t>(oj) - oi_lo, kExClear);
+        outside = dw == kExClear;
+        exb = ex_row[dw];
+      }
+      // type pair of (ti, tj), read with the window for every lane
+      TypePairT<F64> tp;
+      if constexpr (TABLDS) tp = TL[ti * T + tj];
+      else if constexpr (F64) tp = d.tab64[ti * T + tj];
+      else tp = d.tab32[ti * T + tj];
+      // Once (half shell): candidates before the cluster in sorted order come from other
+      // columns and always count; from the cluster on (its own column) only those after i.
+      // Both ways, j = i is the window's self bit.
+      const bool other = HALF ? (sj < first || sj > i) : true;
       bool hit;
       float r2f = 0.f, dxf = 0.f, dyf = 0.f, dzf = 0.f;
       double r2d = 0.0, dxd = 0.0, dyd = 0.0, dzd = 0.0;
@@ -491,7 +550,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         dyd -= bxy * rint(dyd * iby);
         dzd -= bxz * rint(dzd * ibz);
         r2d = dxd * dxd + dyd * dyd + dzd * dzd;
-        hit = ivalid && jv && r2d < c.rc2 && other;
+        hit = ivalid & jv & (r2d < c.rc2) & other;
       } else {
         const uint4 fj = L.ring[slot].fix;
         qj = L.ring[slot].qt.x;
@@ -499,29 +558,28 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         dyf = static_cast<float>(static_cast<int>(fi.y - fj.y));
         dzf = static_cast<float>(static_cast<int>(fi.z - fj.z));
         r2f = fmaf(s2z * dzf, dzf, fmaf(s2y * dyf, dyf, s2x * dxf * dxf));
-        hit = ivalid && jv && r2f < c.rc2f && other;
+        hit = ivalid & jv & (r2f < c.rc2f) & other;
       }
-      // Exclusions: window bit of oi for |oj - oi| <= 64 (bits 0-63: oj - oi = -64..-1,
-      // bits 64-127: 1..64), tested without branches; pairs farther apart only for atoms
-      // that carry the far flag.
-      const int delta = oj - oi;
-      const uint32_t inwin = static_cast<unsigned>(delta + kWindow) <= 2u * kWindow ? 1u : 0u;
-      const uint64_t wbits = delta < 0 ? mask_lo : mask_hi;
-      const int wb = delta < 0 ? delta + kWindow : delta - 1;
-      const uint32_t excluded = static_cast<uint32_t>(wbits >> (wb & 63)) & inwin;
-      hit = hit && (excluded & 1u) == 0u;
+      hit = hit & (exb == 0u);
+      // Pairs farther apart than the window only for atoms that carry the far flag.
       if (any_far) {  // wave-uniform: some atom of this cluster has an exclusion beyond the window
-        const bool far_check = hit && !inwin && far_i;
+        const bool far_check = hit && outside && far_i;
         if (far_check && far_excluded(oi, oj, atom_begin, d.excl_far, o.excl_off, o.excl_idx)) hit = false;
       }
       // the pair's force on i (f d_ij) and energy, for the half-shell j-side sums
       std::conditional_t<F64, double, float> hgx = 0, hgy = 0, hgz = 0, hu = 0;
-      if (hit) {
+      // Every lane evaluates its pair and a lane without one adds zeros (its terms, possibly
+      // not finite, are selected away), so the group runs without a branch.
+      {
         if constexpr (F64) {
-          TypePair64 tp;
-          if constexpr (TABLDS) tp = TL[ti * T + tj];
-          else tp = d.tab64[ti * T + tj];
-          const PairF64 p = pair_f64(r2d, tp.c6, tp.c12, qi64 * pj64.w, c.beta, c.two_beta_sqrtpi, c.erfc_short != 0);
+          PairF64 p = pair_f64(r2d, tp.c6, tp.c12, qi64 * pj64.w, c.beta, c.two_beta_sqrtpi, c.erfc_short != 0);
+          p.f = hit ? p.f : 0.0;
+          p.u_lj = hit ? p.u_lj : 0.0;
+          p.u_c = hit ? p.u_c : 0.0;
+          if constexpr (MODE == kAdjoint) {
+            p.erfc_over_r = hit ? p.erfc_over_r : 0.0;
+            p.dudsig_lj = hit ? p.dudsig_lj : 0.0;
+          }
           en += p.u_lj + p.u_c;
           if constexpr (HALF) {
             hgx = p.f * dxd;
@@ -546,10 +604,14 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
             beps += p.u_lj;
           }
         } else {
-          TypePair32 tp;
-          if constexpr (TABLDS) tp = TL[ti * T + tj];
-          else tp = d.tab32[ti * T + tj];
-          const PairF32 p = pair_f32(r2f, tp.c6, tp.c12, qi32 * qj, c.betaf, c.two_beta_sqrtpif, c.mb2l2e);
+          PairF32 p = pair_f32(r2f, tp.c6, tp.c12, qi32 * qj, c.betaf, c.two_beta_sqrtpif, c.mb2l2e);
+          p.f = hit ? p.f : 0.f;
+          p.u_lj = hit ? p.u_lj : 0.f;
+          p.u_c = hit ? p.u_c : 0.f;
+          if constexpr (MODE == kAdjoint) {
+            p.erfc_over_r = hit ? p.erfc_over_r : 0.f;
+            p.dudsig_lj = hit ? p.dudsig_lj : 0.f;
+          }
           sen += p.u_lj + p.u_c;
           if constexpr (HALF) hu = p.u_lj + p.u_c;
           if constexpr (MODE != kEnergy) {
