@@ -45,6 +45,7 @@ constexpr int kRunPad = 4;           // sentinel entries after the last run
 // 128 VGPRs, no spills); left alone the compiler takes 134 and 3 waves fit.
 constexpr int kF64WavesPerEu = 4;
 constexpr int kFinishBlock = 256;
+constexpr int kPairs2WavesPerCu = 16;  // 4 SIMDs x 4 resident waves of the two-group kernel
 // Exclusion window of one i atom in LDS, one byte per index difference: byte d is 1 when
 // j - i = d - 64 is excluded (d = 0..128; d = 64, the atom itself, is 1), and bytes
 // 129-131 are 0, so a difference outside the window reads byte 129.
@@ -94,10 +95,44 @@ __device__ __forceinline__ int shfl_rows_max(int v) {
   return v;
 }
 
-template <int J>
-__device__ __forceinline__ double row_sum(double v) {
-  for (int off = 1; off < J; off <<= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// One step of reduce_scatter below at lane offset OFF, N values still carried.
+template <int OFF, int N, int NV>
+__device__ __forceinline__ double reduce_scatter_step(double (&v)[NV], int lane) {
+  if constexpr (N > 1) {
+    constexpr int h = N / 2;
+    const bool up = (lane & OFF) != 0;
+#pragma unroll
+    for (int k = 0; k < h; ++k) {
+      const double keep = up ? v[h + k] : v[k];
+      const double give = up ? v[k] : v[h + k];
+      v[k] = keep + __shfl_xor(give, OFF, 64);
+    }
+    return reduce_scatter_step<OFF / 2, h, NV>(v, lane);
+  } else if constexpr (OFF > 0) {
+    v[0] += __shfl_xor(v[0], OFF, 64);
+    return reduce_scatter_step<OFF / 2, 1, NV>(v, lane);
+  } else {
+    return v[0];
+  }
+}
+
+// Sums of NV values over each aligned group of G lanes (NV and G powers of two, NV <= G),
+// each sum ending in its own lanes: lane l returns the group's sum of value
+// (l % G) / (G / NV).  The first log2(NV) butterfly steps halve the values a lane
+// carries (it keeps the half its lane bit selects and hands the other half to its
+// partner), the rest are plain butterfly steps: NV - 1 + log2(G / NV) shuffles instead
+// of NV log2(G).  The order of the additions is fixed, so the sums are deterministic.
+template <int G, int NV>
+__device__ __forceinline__ double reduce_scatter(const double (&in)[NV], int lane_in) {
+  static_assert((NV & (NV - 1)) == 0 && (G & (G - 1)) == 0 && NV <= G, "powers of two");
+  // The lane index is taken anew here, so that the compiler does not hoist the lane
+  // masks out of the enclosing loops and keep them in registers all along.
+  int lane = lane_in;
+  asm volatile("" : "+v"(lane));
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = in[k];
+  return reduce_scatter_step<G / 2, NV, NV>(v, lane);
 }
 
 // Index of the last column whose first cluster is <= k: a 64-way search, each lane
@@ -211,9 +246,17 @@ __device__ __forceinline__ int xcd_id() {
 // sums go there too at the end of the item, and the finishing pass copies the
 // accumulators out.  The pair work halves; the atomic order makes the last bits of
 // the result vary from run to run.
-template <bool F64, int MODE, bool TABLDS, int K, bool HALF>
+//
+// PAIRS2 (mixed path): the group loop takes two groups per pass, which needs more
+// registers (4 resident waves per SIMD instead of 5); the launcher uses it when every
+// item fits on the GPU at once at that occupancy.
+template <bool F64, int MODE, bool TABLDS, int K, bool HALF, bool PAIRS2>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? kF64WavesPerEu : 1, 8)))
 k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
+  // Products are fused into additions only within one expression (the explicit FMAs
+  // aside), so that the copies of the group loop, and the instantiations with one or two
+  // groups per pass, round every sum alike: the schedules give bitwise equal results.
+#pragma clang fp contract(on)
   constexpr int J = 64 / K;  // j atoms per group (lanes per row)
   extern __shared__ uint4 tab_lds[];  // [T * T] type pairs when TABLDS, then the stage when HALF
   __shared__ WaveLds<F64> L;
@@ -494,7 +537,12 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     };
 
     // Evaluate pair (row ii's atom, ring entry head + jj) for navail <= J entries.
-    auto process_group = [&](int navail) {
+    // FAR and VIR: the cluster may have far exclusions, the virial may be wanted (both
+    // then tested at run time).  The two-group loop has a copy for each combination, so
+    // that a pair of groups of the common case is one basic block.
+    auto process_group = [&](int navail, auto far_c, auto vir_c) {
+      constexpr bool FAR = decltype(far_c)::value;
+      constexpr bool VIR = decltype(vir_c)::value;
       // head is a multiple of J (only an item's last group is partial) and J divides
       // kRing, so the group's J slots are consecutive: a scalar base plus jj.
       const int slot = static_cast<int>(head & (kRing - 1)) + jj;
@@ -562,7 +610,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       }
       hit = hit & (exb == 0u);
       // Pairs farther apart than the window only for atoms that carry the far flag.
-      if (any_far) {  // wave-uniform: some atom of this cluster has an exclusion beyond the window
+      if (FAR && any_far) {  // wave-uniform: some atom of this cluster has an exclusion beyond the window
         const bool far_check = hit && outside && far_i;
         if (far_check && far_excluded(oi, oj, atom_begin, d.excl_far, o.excl_off, o.excl_idx)) hit = false;
       }
@@ -587,13 +635,13 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
             hgz = p.f * dzd;
             hu = p.u_lj + p.u_c;
           }
-          if constexpr (MODE != kEnergy) {
-            fx += p.f * dxd;
-            fy += p.f * dyd;
-            fz += p.f * dzd;
+          if constexpr (MODE != kEnergy) {  // explicit FMAs: the same rounding in every copy of the loop
+            fx = fma(p.f, dxd, fx);
+            fy = fma(p.f, dyd, fy);
+            fz = fma(p.f, dzd, fz);
           }
           if constexpr (MODE == kForces) {
-            if (o.want_virial) {
+            if (VIR && o.want_virial) {
               wxx += p.f * dxd * dxd; wxy += p.f * dxd * dyd; wxz += p.f * dxd * dzd;
               wyy += p.f * dyd * dyd; wyz += p.f * dyd * dzd; wzz += p.f * dzd * dzd;
             }
@@ -621,11 +669,13 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
               hgy = gy;
               hgz = gz;
             }
-            sfx += gx;
-            sfy += gy;
-            sfz += gz;
+            // explicit FMAs: the same rounding in every copy of the group loop, whether or
+            // not the products are also used for the virial
+            sfx = fmaf(p.f, dxf, sfx);
+            sfy = fmaf(p.f, dyf, sfy);
+            sfz = fmaf(p.f, dzf, sfz);
             if constexpr (MODE == kForces) {
-              if (o.want_virial) {
+              if (VIR && o.want_virial) {
                 swxx = fmaf(gx, dxf, swxx); swxy = fmaf(gx, dyf, swxy); swxz = fmaf(gx, dzf, swxz);
                 swyy = fmaf(gy, dyf, swyy); swyz = fmaf(gy, dzf, swyz); swzz = fmaf(gz, dzf, swzz);
               }
@@ -671,6 +721,35 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         }
       }
       head += static_cast<uint32_t>(navail);
+    };
+
+    // Every complete group in the ring; with PAIRS2 two at a time while there are two:
+    // the two copies form one basic block, so that their loads and latencies overlap.
+    // (The FP64 group would spill at twice its registers.)
+    auto drain_with = [&](auto far_c, auto vir_c) {
+      if constexpr (!F64 && PAIRS2) {
+        while (tail - head >= 2u * static_cast<uint32_t>(J)) {
+          process_group(J, far_c, vir_c);
+          process_group(J, far_c, vir_c);
+        }
+      }
+      while (tail - head >= static_cast<uint32_t>(J)) process_group(J, far_c, vir_c);
+    };
+    auto drain = [&]() {
+      if constexpr (F64 || !PAIRS2) {
+        drain_with(std::true_type{}, std::true_type{});
+      } else if constexpr (MODE == kForces) {
+        if (any_far) {
+          if (o.want_virial) drain_with(std::true_type{}, std::true_type{});
+          else drain_with(std::true_type{}, std::false_type{});
+        } else {
+          if (o.want_virial) drain_with(std::false_type{}, std::true_type{});
+          else drain_with(std::false_type{}, std::false_type{});
+        }
+      } else {
+        if (any_far) drain_with(std::true_type{}, std::false_type{});
+        else drain_with(std::false_type{}, std::false_type{});
+      }
     };
 
     // Walk this item's candidates 64 at a time; the next chunk's loads are issued
@@ -748,7 +827,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       }
       wave_lds_sync();
       tail += static_cast<uint32_t>(__popcll(mk));
-      while (tail - head >= static_cast<uint32_t>(J)) process_group(J);
+      drain();
 
       P = Pn;
       fj = fj_n;
@@ -758,7 +837,10 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       valid = valid_n;
       sj = sj_n;
     }
-    if (tail != head) process_group(static_cast<int>(tail - head));
+    if (tail != head) {
+      if (any_far) process_group(static_cast<int>(tail - head), std::true_type{}, std::true_type{});
+      else process_group(static_cast<int>(tail - head), std::false_type{}, std::true_type{});
+    }
     if (dynamic && !requested && !(closed & (1u << home))) {  // an item without candidates
       pending = request(home);
       have_pending = true;
@@ -793,43 +875,40 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       }
     }
 
-    // Per-atom sums of this item: rows reduced over their J lanes.  With one item
-    // per cluster they are final and go straight to the caller's arrays (original
-    // atom order); otherwise to this item's part, added up by k_finish.
-    fx = row_sum<J>(D(fx, sfx)) * scx;
-    fy = row_sum<J>(D(fy, sfy)) * scy;
-    fz = row_sum<J>(D(fz, sfz)) * scz;
-    const double w4 = MODE == kAdjoint ? row_sum<J>(D(phi, sphi)) * phi_scale : row_sum<J>(D(en, sen));
-    if constexpr (HALF) {
-      if (nst > 0) flush();
-      if (jj == 0 && ivalid) {
-        if constexpr (MODE == kForces) {
-          unsafeAtomicAdd(&d.jacc[i].x, fx);
-          unsafeAtomicAdd(&d.jacc[i].y, fy);
-          unsafeAtomicAdd(&d.jacc[i].z, fz);
-        } else if constexpr (MODE == kEnergy) {
-          if (o.atom_energy) unsafeAtomicAdd(&d.jacc[i].w, 0.5 * w4);
-        }
-      }
-    } else if (jj == 0 && ivalid) {
-      if (Q == 1) {
-        if constexpr (MODE == kForces) {
-          o.force[3 * static_cast<int64_t>(oi) + 0] = fx;
-          o.force[3 * static_cast<int64_t>(oi) + 1] = fy;
-          o.force[3 * static_cast<int64_t>(oi) + 2] = fz;
-        } else if constexpr (MODE == kEnergy) {
-          if (o.atom_energy) o.atom_energy[oi] = 0.5 * w4;
-        } else {
-          const double g = o.grad_energy[sys];
-          if (o.grad_pos) {
-            o.grad_pos[3 * static_cast<int64_t>(oi) + 0] = -g * fx;
-            o.grad_pos[3 * static_cast<int64_t>(oi) + 1] = -g * fy;
-            o.grad_pos[3 * static_cast<int64_t>(oi) + 2] = -g * fz;
+    // Per-atom sums of this item: the row's four sums (force x, y, z, then energy or
+    // phi) reduced over its J lanes, sum e ending in lanes jj = e J/4 .. (e + 1) J/4 - 1,
+    // whose first lane writes it.  With one item per cluster they are final and go
+    // straight to the caller's arrays (original atom order); otherwise to this item's
+    // part, added up by k_finish.
+    {
+      const double rowv[4] = {D(fx, sfx), D(fy, sfy), D(fz, sfz), MODE == kAdjoint ? D(phi, sphi) : D(en, sen)};
+      const int ent = jj / (J / 4);
+      const double sce = ent == 0 ? scx : ent == 1 ? scy : ent == 2 ? scz : (MODE == kAdjoint ? phi_scale : 1.0);
+      const double rv = reduce_scatter<J, 4>(rowv, lane) * sce;
+      const bool writer = ivalid && jj % (J / 4) == 0;
+      if constexpr (HALF) {
+        if (nst > 0) flush();
+        if (writer) {
+          if constexpr (MODE == kForces) {
+            if (ent < 3) unsafeAtomicAdd(&d.jacc[i].x + ent, rv);
+          } else if constexpr (MODE == kEnergy) {
+            if (ent == 3 && o.atom_energy) unsafeAtomicAdd(&d.jacc[i].w, 0.5 * rv);
           }
-          if (o.grad_charge) o.grad_charge[oi] = g * w4;
         }
-      } else {
-        d.part[static_cast<int64_t>(part) * d.N + i] = make_double4(fx, fy, fz, w4);
+      } else if (writer) {
+        if (Q == 1) {
+          if constexpr (MODE == kForces) {
+            if (ent < 3) o.force[3 * static_cast<int64_t>(oi) + ent] = rv;
+          } else if constexpr (MODE == kEnergy) {
+            if (ent == 3 && o.atom_energy) o.atom_energy[oi] = 0.5 * rv;
+          } else {
+            const double g = o.grad_energy[sys];
+            if (ent < 3 && o.grad_pos) o.grad_pos[3 * static_cast<int64_t>(oi) + ent] = -g * rv;
+            if (ent == 3 && o.grad_charge) o.grad_charge[oi] = g * rv;
+          }
+        } else {
+          (&d.part[static_cast<int64_t>(part) * d.N + i].x)[ent] = rv;
+        }
       }
     }
 
@@ -839,20 +918,18 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       if (o.want_part) {
         double mine = 0.0;
         if (MODE == kForces && o.want_virial) {
-          // the seven distinct entries summed together, one butterfly step at a time
-          // each pair counted twice by the full-shell form, once by the half-shell one
+          // the seven distinct entries (and a zero) reduced together over the wave, sum
+          // k ending in lanes 8k .. 8k + 7; each pair counted twice by the full-shell
+          // form, once by the half-shell one
           constexpr double hs = HALF ? 1.0 : 0.5;
-          double v[7] = {hs * D(en, sen), hs * scx * scx * D(wxx, swxx), hs * scx * scy * D(wxy, swxy),
-                         hs * scx * scz * D(wxz, swxz), hs * scy * scy * D(wyy, swyy),
-                         hs * scy * scz * D(wyz, swyz), hs * scz * scz * D(wzz, swzz)};
-#pragma unroll
-          for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-            for (int k = 0; k < 7; ++k) v[k] += __shfl_xor(v[k], off, 64);
-          }
+          const double v[8] = {hs * D(en, sen), hs * scx * scx * D(wxx, swxx), hs * scx * scy * D(wxy, swxy),
+                               hs * scx * scz * D(wxz, swxz), hs * scy * scy * D(wyy, swyy),
+                               hs * scy * scz * D(wyz, swyz), hs * scz * scz * D(wzz, swzz), 0.0};
+          const double r = reduce_scatter<64, 8>(v, lane);
           // entry order: energy, xx, xy, xz, yx, yy, yz, zx, zy, zz
-          mine = lane == 0 ? v[0] : lane == 1 ? v[1] : (lane == 2 || lane == 4) ? v[2]
-               : (lane == 3 || lane == 7) ? v[3] : lane == 5 ? v[4] : (lane == 6 || lane == 8) ? v[5] : v[6];
+          const int src = lane == 0 ? 0 : lane == 1 ? 1 : (lane == 2 || lane == 4) ? 2
+                        : (lane == 3 || lane == 7) ? 3 : lane == 5 ? 4 : (lane == 6 || lane == 8) ? 5 : 6;
+          mine = __shfl(r, 8 * src, 64);
           if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + m] = mine;
         } else {
           mine = wave_sum((HALF ? 1.0 : 0.5) * D(en, sen));
@@ -1062,14 +1139,22 @@ void launch_cluster_mode(int mode, bool half, int64_t wgs, int dyn, int wg_per_c
     g = std::max<int64_t>((g + kXcds - 1) / kXcds * kXcds, kXcds);  // a multiple of the XCD count
     hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(g)), block, lds, s, d, c, o, Q, dyn);
   };
+  // Two groups per pass (mixed path, full shell, static schedule) when the grid fits on
+  // the GPU at once at 4 waves per SIMD: then the fifth resident wave has nothing to do
+  // and the instruction-level parallelism of two groups is worth more (23.6k-atom box:
+  // 64.2 -> 61.0 us; 64-replica batch, 100,000 items: 1,083 against 1,117 us with it).
+  const bool pairs2 = !F64 && !half && !dyn && wgs <= static_cast<int64_t>(compute_units()) * kPairs2WavesPerCu;
   if (mode == kForces) {
-    if (half) go(k_pair_cluster<F64, kForces, TABLDS, K, true>, std::true_type{});
-    else go(k_pair_cluster<F64, kForces, TABLDS, K, false>, std::false_type{});
+    if (half) go(k_pair_cluster<F64, kForces, TABLDS, K, true, false>, std::true_type{});
+    else if (pairs2) go(k_pair_cluster<F64, kForces, TABLDS, K, false, !F64>, std::false_type{});
+    else go(k_pair_cluster<F64, kForces, TABLDS, K, false, false>, std::false_type{});
   } else if (mode == kEnergy) {
-    if (half) go(k_pair_cluster<F64, kEnergy, TABLDS, K, true>, std::true_type{});
-    else go(k_pair_cluster<F64, kEnergy, TABLDS, K, false>, std::false_type{});
+    if (half) go(k_pair_cluster<F64, kEnergy, TABLDS, K, true, false>, std::true_type{});
+    else if (pairs2) go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, !F64>, std::false_type{});
+    else go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, false>, std::false_type{});
   } else {
-    go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false>, std::false_type{});
+    if (pairs2) go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, !F64>, std::false_type{});
+    else go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, false>, std::false_type{});
   }
 }
 

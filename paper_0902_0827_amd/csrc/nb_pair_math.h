@@ -53,6 +53,9 @@ struct PairF32 {
 // mb2l2e = -beta^2 log2(e) are per-call constants.
 __device__ __forceinline__ PairF32 pair_f32(float r2, float c6, float c12, float qq, float beta,
                                             float two_beta_sqrtpi, float mb2l2e) {
+  // Products are fused into additions only within one expression, so that every kernel
+  // this is inlined into rounds the pair terms alike.
+#pragma clang fp contract(on)
   PairF32 o;
   const float rinv = __builtin_amdgcn_rsqf(r2);
   const float rinv2 = rinv * rinv;

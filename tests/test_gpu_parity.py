@@ -160,7 +160,9 @@ def test_split_and_cluster_size_give_the_same_forces(precision, K, chain):
     for o in outs:
         assert U.rel_rms(o["force"], ref["force"]) <= tol
         assert U.rel_rms(o["grad_charge"], ref["phi"]) <= tol
-        assert o["energy"][0] == pytest.approx(ref["energy_total"], rel=tol)
+        # mixed: on the scale of sum |E_i| (see test_forces_energy_virial_match_oracle)
+        scale = abs(ref["energy_total"]) if precision == H.NB_FP64 else np.abs(ref["energy"]).sum()
+        assert abs(o["energy"][0] - ref["energy_total"]) <= tol * scale
     for o in outs[1:]:  # splitting only reorders sums
         assert U.rel_rms(o["force"], outs[0]["force"]) <= (1e-13 if precision == H.NB_FP64 else 1e-6)
 
@@ -195,7 +197,13 @@ def test_forces_energy_virial_match_oracle(which, precision, kernel, chain):
     err = U.rel_rms(out["force"], ref["force"])
     print(f"  rel_rms={err:.3e} max_rel_atom={U.max_rel_atom(out['force'], ref['force']):.3e}")
     assert err <= tol
-    assert out["energy"][0] == pytest.approx(ref["energy_total"], rel=tol, abs=tol)
+    if precision == H.NB_FP64:
+        assert out["energy"][0] == pytest.approx(ref["energy_total"], rel=tol, abs=tol)
+    else:
+        # single-precision pair terms carry a relative error each, and the total is a small
+        # difference of per-atom energies (water: about 100 times larger): compared on
+        # the scale of sum |E_i|
+        assert abs(out["energy"][0] - ref["energy_total"]) <= tol * np.abs(ref["energy"]).sum()
     assert U.rel_rms(out["virial"][0], ref["virial"]) <= (1e-11 if precision == H.NB_FP64 else 1e-5)
     assert U.rel_rms(out["atom_energy"], ref["energy"]) <= (1e-11 if precision == H.NB_FP64 else 1e-5)
     # the energy call sums the same pairs in the same order; only the compiler's fusing of
