@@ -62,9 +62,10 @@ __device__ __forceinline__ uint32_t uabs_diff(uint32_t a, uint32_t b) {
 __device__ __forceinline__ float box_dist2(const uint4 &p, const uint4 &ctr, const uint4 &half, float s2x, float s2y,
                                            float s2z) {
   const uint32_t ax = uabs_diff(p.x, ctr.x), ay = uabs_diff(p.y, ctr.y), az = uabs_diff(p.z, ctr.z);
-  const float ex = static_cast<float>(ax > half.x ? ax - half.x : 0u);
-  const float ey = static_cast<float>(ay > half.y ? ay - half.y : 0u);
-  const float ez = static_cast<float>(az > half.z ? az - half.z : 0u);
+  // max(a - h, 0): one saturating subtraction each
+  const float ex = static_cast<float>(__builtin_elementwise_sub_sat(ax, half.x));
+  const float ey = static_cast<float>(__builtin_elementwise_sub_sat(ay, half.y));
+  const float ez = static_cast<float>(__builtin_elementwise_sub_sat(az, half.z));
   return fmaf(s2z * ez, ez, fmaf(s2y * ey, ey, s2x * ex * ex));
 }
 
@@ -184,9 +185,15 @@ struct WaveLds<true> {
 template <bool F64>
 using TypePairT = std::conditional_t<F64, TypePair64, TypePair32>;
 
-template <bool F64>
+// The entry as held in LDS: the FP64 path outside the adjoint needs only c6 and c12, and
+// half the bytes let one more wave per CU be resident (the LDS, not the registers,
+// limits that kernel).
+template <bool F64, int MODE>
+using TypePairLds = std::conditional_t<F64 && MODE != kAdjoint, double2, TypePairT<F64>>;
+
+template <bool F64, int MODE>
 constexpr size_t tab_lds_bytes(int T) {
-  return static_cast<size_t>(T) * static_cast<size_t>(T) * sizeof(TypePairT<F64>);
+  return static_cast<size_t>(T) * static_cast<size_t>(T) * sizeof(TypePairLds<F64, MODE>);
 }
 
 // Half-shell kernel: the candidates' shares of one item wait in LDS (after the type
@@ -202,9 +209,9 @@ using StageT = std::conditional_t<F64, StageF64, StageF32>;
 template <bool F64>
 constexpr int kStage = F64 ? 64 : 144;  // entries, multiples of 16
 
-template <bool F64, bool TABLDS, bool HALF>
+template <bool F64, int MODE, bool TABLDS, bool HALF>
 constexpr size_t dyn_lds_bytes(int T) {
-  return (TABLDS ? tab_lds_bytes<F64>(T) : 0) + (HALF ? kStage<F64> * sizeof(StageT<F64>) : 0);
+  return (TABLDS ? tab_lds_bytes<F64, MODE>(T) : 0) + (HALF ? kStage<F64> * sizeof(StageT<F64>) : 0);
 }
 
 // Orders this wave's LDS accesses (one wave's LDS operations execute in issue order;
@@ -260,7 +267,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   constexpr int J = 64 / K;  // j atoms per group (lanes per row)
   extern __shared__ uint4 tab_lds[];  // [T * T] type pairs when TABLDS, then the stage when HALF
   __shared__ WaveLds<F64> L;
-  TypePairT<F64> *const TL = reinterpret_cast<TypePairT<F64> *>(tab_lds);
+  TypePairLds<F64, MODE> *const TL = reinterpret_cast<TypePairLds<F64, MODE> *>(tab_lds);
   const int lane = static_cast<int>(threadIdx.x);
   if (!built_for(d.status, d.N, true, F64, HALF)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(d.status, NB_STATUS_NOT_BUILT);
@@ -269,7 +276,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   const int ii = lane / J, jj = lane % J;
   const int T = d.T;
   StageT<F64> *const ST = reinterpret_cast<StageT<F64> *>(reinterpret_cast<char *>(tab_lds) +
-                                                          (TABLDS ? tab_lds_bytes<F64>(T) : 0));
+                                                          (TABLDS ? tab_lds_bytes<F64, MODE>(T) : 0));
   // Ring slots are read by every lane of a group, also those past the candidates it holds
   // (their results are discarded): zeroed once, every slot holds a valid type index.
   for (int k = lane; k < kRing; k += 64) {
@@ -284,7 +291,8 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   }
   if constexpr (TABLDS) {
     for (int k = lane; k < T * T; k += 64) {
-      if constexpr (F64) TL[k] = d.tab64[k];
+      if constexpr (F64 && MODE != kAdjoint) TL[k] = make_double2(d.tab64[k].c6, d.tab64[k].c12);
+      else if constexpr (F64) TL[k] = d.tab64[k];
       else TL[k] = d.tab32[k];
     }
     wave_lds_sync();
@@ -577,7 +585,11 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       }
       // type pair of (ti, tj), read with the window for every lane
       TypePairT<F64> tp;
-      if constexpr (TABLDS) tp = TL[ti * T + tj];
+      if constexpr (TABLDS && F64 && MODE != kAdjoint) {
+        const double2 e = TL[ti * T + tj];
+        tp.c6 = e.x;
+        tp.c12 = e.y;
+      } else if constexpr (TABLDS) tp = TL[ti * T + tj];
       else if constexpr (F64) tp = d.tab64[ti * T + tj];
       else tp = d.tab32[ti * T + tj];
       // Once (half shell): candidates before the cluster in sorted order come from other
@@ -654,14 +666,14 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         } else {
           PairF32 p = pair_f32(r2f, tp.c6, tp.c12, qi32 * qj, c.betaf, c.two_beta_sqrtpif, c.mb2l2e);
           p.f = hit ? p.f : 0.f;
-          p.u_lj = hit ? p.u_lj : 0.f;
-          p.u_c = hit ? p.u_c : 0.f;
           if constexpr (MODE == kAdjoint) {
+            p.u_lj = hit ? p.u_lj : 0.f;
             p.erfc_over_r = hit ? p.erfc_over_r : 0.f;
             p.dudsig_lj = hit ? p.dudsig_lj : 0.f;
           }
-          sen += p.u_lj + p.u_c;
-          if constexpr (HALF) hu = p.u_lj + p.u_c;
+          const float pu = hit ? p.u_lj + p.u_c : 0.f;  // the pair's energy, one select
+          sen += pu;
+          if constexpr (HALF) hu = pu;
           if constexpr (MODE != kEnergy) {
             const float gx = p.f * dxf, gy = p.f * dyf, gz = p.f * dzf;
             if constexpr (HALF) {
@@ -1126,8 +1138,8 @@ template <bool F64, bool TABLDS, int K>
 void launch_cluster_mode(int mode, bool half, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s, const Dev &d,
                          const Consts &c, const Out &o, int Q) {
   const dim3 block(64);
-  auto go = [&](auto kern, auto half_tag) {
-    const size_t lds = dyn_lds_bytes<F64, TABLDS, decltype(half_tag)::value>(d.T);
+  auto go = [&](auto kern, auto mode_tag, auto half_tag) {
+    const size_t lds = dyn_lds_bytes<F64, decltype(mode_tag)::value, TABLDS, decltype(half_tag)::value>(d.T);
     int64_t g = wgs;
     if (dyn) {
       // persistent grid: what fits on the device at once (at most wg_per_cu per CU)
@@ -1145,16 +1157,16 @@ void launch_cluster_mode(int mode, bool half, int64_t wgs, int dyn, int wg_per_c
   // 64.2 -> 61.0 us; 64-replica batch, 100,000 items: 1,083 against 1,117 us with it).
   const bool pairs2 = !F64 && !half && !dyn && wgs <= static_cast<int64_t>(compute_units()) * kPairs2WavesPerCu;
   if (mode == kForces) {
-    if (half) go(k_pair_cluster<F64, kForces, TABLDS, K, true, false>, std::true_type{});
-    else if (pairs2) go(k_pair_cluster<F64, kForces, TABLDS, K, false, !F64>, std::false_type{});
-    else go(k_pair_cluster<F64, kForces, TABLDS, K, false, false>, std::false_type{});
+    if (half) go(k_pair_cluster<F64, kForces, TABLDS, K, true, false>, std::integral_constant<int, kForces>{}, std::true_type{});
+    else if (pairs2) go(k_pair_cluster<F64, kForces, TABLDS, K, false, !F64>, std::integral_constant<int, kForces>{}, std::false_type{});
+    else go(k_pair_cluster<F64, kForces, TABLDS, K, false, false>, std::integral_constant<int, kForces>{}, std::false_type{});
   } else if (mode == kEnergy) {
-    if (half) go(k_pair_cluster<F64, kEnergy, TABLDS, K, true, false>, std::true_type{});
-    else if (pairs2) go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, !F64>, std::false_type{});
-    else go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, false>, std::false_type{});
+    if (half) go(k_pair_cluster<F64, kEnergy, TABLDS, K, true, false>, std::integral_constant<int, kEnergy>{}, std::true_type{});
+    else if (pairs2) go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, !F64>, std::integral_constant<int, kEnergy>{}, std::false_type{});
+    else go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, false>, std::integral_constant<int, kEnergy>{}, std::false_type{});
   } else {
-    if (pairs2) go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, !F64>, std::false_type{});
-    else go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, false>, std::false_type{});
+    if (pairs2) go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, !F64>, std::integral_constant<int, kAdjoint>{}, std::false_type{});
+    else go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, false>, std::integral_constant<int, kAdjoint>{}, std::false_type{});
   }
 }
 
