@@ -185,11 +185,13 @@ struct WaveLds<true> {
 template <bool F64>
 using TypePairT = std::conditional_t<F64, TypePair64, TypePair32>;
 
-// The entry as held in LDS: the FP64 path outside the adjoint needs only c6 and c12, and
-// half the bytes let one more wave per CU be resident (the LDS, not the registers,
-// limits that kernel).
+// The entry as held in LDS: the FP64 path needs only c6 and c12 (and 1/sigma in the
+// adjoint), 16 or 24 bytes instead of 32, which lets one more wave per CU be resident
+// (the LDS, not the registers, limits that kernel).
+struct TypePairF64Adj { double c6, c12, inv_sig; };
 template <bool F64, int MODE>
-using TypePairLds = std::conditional_t<F64 && MODE != kAdjoint, double2, TypePairT<F64>>;
+using TypePairLds = std::conditional_t<!F64, TypePairT<F64>,
+                                       std::conditional_t<MODE == kAdjoint, TypePairF64Adj, double2>>;
 
 template <bool F64, int MODE>
 constexpr size_t tab_lds_bytes(int T) {
@@ -292,7 +294,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   if constexpr (TABLDS) {
     for (int k = lane; k < T * T; k += 64) {
       if constexpr (F64 && MODE != kAdjoint) TL[k] = make_double2(d.tab64[k].c6, d.tab64[k].c12);
-      else if constexpr (F64) TL[k] = d.tab64[k];
+      else if constexpr (F64) TL[k] = TypePairF64Adj{d.tab64[k].c6, d.tab64[k].c12, d.tab64[k].inv_sig};
       else TL[k] = d.tab32[k];
     }
     wave_lds_sync();
@@ -589,6 +591,11 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         const double2 e = TL[ti * T + tj];
         tp.c6 = e.x;
         tp.c12 = e.y;
+      } else if constexpr (TABLDS && F64) {
+        const TypePairF64Adj e = TL[ti * T + tj];
+        tp.c6 = e.c6;
+        tp.c12 = e.c12;
+        tp.inv_sig = e.inv_sig;
       } else if constexpr (TABLDS) tp = TL[ti * T + tj];
       else if constexpr (F64) tp = d.tab64[ti * T + tj];
       else tp = d.tab32[ti * T + tj];
