@@ -344,7 +344,8 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   bool have_pending = false;
 
   while (m >= 0) {
-    const int I = m / Q, part = m - (m / Q) * Q;
+    // (Q is uniform; with one item per cluster the divisions below are skipped)
+    const int I = Q == 1 ? m : m / Q, part = Q == 1 ? 0 : m - (m / Q) * Q;
 
     // The cluster: its column, system, and atoms.
     const int col = cluster_column(d.col_clu_start, static_cast<int>(d.n_columns), I);
@@ -502,8 +503,8 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     }
     if (lane < kRunPad) L.runs[nrun + lane] = make_int2(0, total);  // sentinels
     // This item's share of the candidates, [lo_c, hi_c).
-    const int lo_c = static_cast<int>((static_cast<int64_t>(total) * part) / Q);
-    const int hi_c = static_cast<int>((static_cast<int64_t>(total) * (part + 1)) / Q);
+    const int lo_c = Q == 1 ? 0 : static_cast<int>((static_cast<int64_t>(total) * part) / Q);
+    const int hi_c = Q == 1 ? total : static_cast<int>((static_cast<int64_t>(total) * (part + 1)) / Q);
     wave_lds_sync();  // the runs are visible to every lane
 
     // Per-lane sums for row ii's atom.  Mixed path: single precision over this item
