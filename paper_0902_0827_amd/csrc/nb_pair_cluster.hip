@@ -14,16 +14,19 @@
 //   2. pairs: whenever the ring holds J atoms, each lane evaluates the pair
 //      (i atom ii, j atom jj), so all 64 lanes work on candidates that passed the
 //      box test (on the 23.6k-atom box about 60% of them are inside R for K = 4,
-//      48% for K = 8, against ~25% for a plain cell stencil);
+//      48% for K = 8, against ~25% for a plain cell stencil); a lane without a pair
+//      adds zeros, so a group has no branch;
 //   3. each row of J lanes accumulates its i atom's sums in registers; rows are
 //      reduced with cross-lane shuffles at the end.
 //
-// A cluster's neighbour columns may be split over S waves (S = 1..4), which gives
-// the GPU S times more, shorter waves to interleave; each wave writes its part of
-// every atom's sums to its own slot, and k_finish adds the S parts in a fixed order,
-// converts to the caller's atom order and reduces energies, virials and per-type
-// sums.  Nothing is accumulated with atomics: results are deterministic.
-// Full shell (every pair is evaluated from both sides), as in the paper.
+// By default each cluster is one work item, and its wave writes the per-atom results
+// in the caller's atom order itself.  A cluster's candidates may instead be split
+// over Q work items (Q = 2..8): each writes its part of every atom's sums to its own
+// slot, and k_finish adds the Q parts in a fixed order and converts them to the
+// caller's atom order.  k_finish also reduces energies, virials and per-type sums.
+// Nothing is accumulated with atomics: results are deterministic.  Full shell (every
+// pair is evaluated from both sides), as in the paper; the half-shell variant is
+// described with the kernel.
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -42,7 +45,8 @@ constexpr int kTabLds = 16;          // type tables up to 16 x 16 are copied to 
 constexpr int kMaxRuns = 2 * 9 * 9;  // up to 9 x 9 neighbour columns, <= 2 z-runs each
 constexpr int kRunPad = 4;           // sentinel entries after the last run
 // FP64 pair kernels: registers are allocated for 4 resident waves per SIMD (at most
-// 128 VGPRs, no spills); left alone the compiler takes 134 and 3 waves fit.
+// 128 VGPRs; a few values outside the loops go to scratch); left alone the compiler
+// takes 134 and 3 waves fit.
 constexpr int kF64WavesPerEu = 4;
 constexpr int kFinishBlock = 256;
 constexpr int kPairs2WavesPerCu = 16;  // 4 SIMDs x 4 resident waves of the two-group kernel
@@ -969,9 +973,8 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   }
 }
 
-// Energy (and virial) of system b: sum of the wave slots [lo, hi), in a fixed order.
-// Loads are unconditional (indices clamped) so that a thread's loads are all in flight.
-// Sum of one partial component over the wave slots [lo, hi), in a fixed order.
+// Sum of one partial component (energy or a virial entry of a system) over the wave
+// slots [lo, hi), in a fixed order.
 // Loads are unconditional (indices clamped) so that a thread's loads are all in flight.
 __device__ inline double sum_component(const double *__restrict__ vals, int64_t lo, int64_t hi,
                                        double (*lds)[kPart]) {
