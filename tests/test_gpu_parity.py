@@ -172,7 +172,9 @@ def test_split_and_cluster_size_give_the_same_forces(precision, K, chain):
 def test_schedules_and_residency_give_bitwise_identical_results(precision, split, chain):
     """Every work item writes its own output slots, so neither the schedule (one item per
     wave, or persistent waves taking items from per-XCD counters) nor the number of
-    resident workgroups may change a single bit; repeated dynamic runs neither."""
+    resident workgroups may change a single bit; repeated dynamic runs neither.  On this
+    input the static schedule of the mixed path runs the two-groups-per-pass kernel and
+    the dynamic one the one-group kernel, so this also holds the two to the same bits."""
     runs = [U.gpu_eval(chain, precision, kernel=H.NB_KERNEL_CLUSTER, split=split, schedule=sch, wg_per_cu=w,
                        backward=True)
             for sch, w in [(H.NB_SCHED_STATIC, 0), (H.NB_SCHED_DYNAMIC, 1), (H.NB_SCHED_DYNAMIC, 4),
