@@ -167,3 +167,78 @@ int nbo_rows(int64_t n, const double *pos, const double *q, const int32_t *type,
   free(s_idx);
   return 0;
 }
+
+/*
+ * Ewald corrections around the real-space term (section 3: the electrostatics are
+ * PME, whose real-space part is the pair term above; the reciprocal part counts every
+ * pair, excluded ones included, and every charge with itself):
+ *
+ *   E_excl = - sum over excluded pairs {i, j} of k_e q_i q_j erf(beta r) / r
+ *            (union of both rows, any distance, minimum image; at r = 0 the limit
+ *            k_e q_i q_j 2 beta / sqrt(pi))
+ *   E_self = - k_e beta / sqrt(pi) sum_i q_i^2
+ *   F_i    = -dE_excl/dx_i = sum_j g_ij d_ij,
+ *   g_ij   = k_e q_i q_j [(2 beta / sqrt(pi)) exp(-beta^2 r^2) / r^2 - erf(beta r) / r^3]
+ *            (0 at r = 0)
+ *   virial = sum over excluded pairs d_ij (x) g_ij d_ij
+ *   energy[i] = (1/2) sum_j u_ij - k_e beta / sqrt(pi) q_i^2
+ *
+ * All rows; libm erf and exp.  Returns 0, or -1 / -2 / -4 on bad input.
+ */
+int nbo_ewald_corrections(int64_t n, const double *pos, const double *q,
+                          const int32_t *excl_off, const int32_t *excl_idx, const double *box,
+                          double beta, double ke, double *force, double *energy, double *virial,
+                          double *e_excl_out, double *e_self_out) {
+  if (n < 0 || beta < 0.0) return -1;
+  for (int a = 0; a < 3; ++a)
+    if (!(box[a] > 0.0)) return -2;
+  int64_t *s_off = NULL;
+  int32_t *s_idx = NULL;
+  if (sym_exclusions(n, excl_off, excl_idx, &s_off, &s_idx) != 0) return -4;
+  const double two_over_sqrt_pi = 2.0 / sqrt(acos(-1.0));
+  int64_t *stamp = calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+  double vir[9] = {0};
+  double e_excl = 0.0, e_self = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double f[3] = {0, 0, 0};
+    double ei = 0.0;
+    for (int64_t k = s_off[i]; k < s_off[i + 1]; ++k) {
+      const int64_t j = s_idx[k];
+      if (j == i || stamp[j] == i + 1) continue;  /* the atom itself, or a repeated entry */
+      stamp[j] = i + 1;
+      double d[3];
+      for (int a = 0; a < 3; ++a) {
+        double t = pos[3 * i + a] - pos[3 * j + a];
+        d[a] = t - box[a] * rint(t / box[a]);
+      }
+      const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      const double qq = ke * q[i] * q[j];
+      double u, g;
+      if (r2 > 0.0) {
+        const double r = sqrt(r2);
+        const double erf_br = erf(beta * r);
+        u = -qq * erf_br / r;
+        g = qq * (beta * two_over_sqrt_pi * exp(-beta * beta * r2) / r2 - erf_br / (r2 * r));
+      } else {
+        u = -qq * beta * two_over_sqrt_pi;
+        g = 0.0;
+      }
+      for (int a = 0; a < 3; ++a) f[a] += g * d[a];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) vir[3 * a + b] += 0.5 * d[a] * g * d[b];
+      ei += 0.5 * u;
+      e_excl += 0.5 * u;
+    }
+    const double si = -ke * beta * 0.5 * two_over_sqrt_pi * q[i] * q[i];
+    e_self += si;
+    if (force) for (int a = 0; a < 3; ++a) force[3 * i + a] = f[a];
+    if (energy) energy[i] = ei + si;
+  }
+  if (virial) for (int k = 0; k < 9; ++k) virial[k] = vir[k];
+  if (e_excl_out) *e_excl_out = e_excl;
+  if (e_self_out) *e_self_out = e_self;
+  free(stamp);
+  free(s_off);
+  free(s_idx);
+  return 0;
+}

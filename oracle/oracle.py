@@ -58,6 +58,9 @@ def _load():
         lib.nbo_rows.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int32, P, P, P, P, P,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_int64, P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
+        lib.nbo_ewald_corrections.restype = ctypes.c_int
+        lib.nbo_ewald_corrections.argtypes = [ctypes.c_int64, P, P, P, P, P, ctypes.c_double,
+                                              ctypes.c_double, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -124,3 +127,40 @@ def evaluate_system(system, rows=None, nthreads: int = 0, ke: float = COULOMB_K)
     return evaluate(system.pos, system.charge, system.type, system.sigma, system.eps,
                     system.excl_offset, system.excl_index, system.box, system.cutoff,
                     system.beta, ke=ke, rows=rows, nthreads=nthreads)
+
+
+def ewald_corrections(pos, charge, excl_offset, excl_index, box, beta, ke: float = COULOMB_K) -> dict:
+    """The excluded-pair and self corrections of the Ewald sum (``nbo_ewald_corrections``).
+
+    Inputs are promoted to float64; pass exactly the values the device computes with.
+    Returns force [N,3] (of the excluded-pair term), energy [N] (per-atom split: half of
+    each excluded pair's term plus the atom's self term), virial [3,3], e_excl, e_self and
+    energy_total = e_excl + e_self.
+    """
+    lib = _load()
+    pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
+    n = pos.shape[0]
+    q = np.ascontiguousarray(charge, np.float64)
+    eo = np.ascontiguousarray(excl_offset, np.int32)
+    ei = np.ascontiguousarray(excl_index, np.int32)
+    if ei.size == 0:
+        ei = np.zeros(1, np.int32)
+    bx = np.ascontiguousarray(box, np.float64).reshape(3)
+    force = np.zeros((n, 3))
+    energy = np.zeros(n)
+    vir = np.zeros(9)
+    e_excl = ctypes.c_double()
+    e_self = ctypes.c_double()
+    rc = lib.nbo_ewald_corrections(n, _ptr(pos), _ptr(q), _ptr(eo), _ptr(ei), _ptr(bx), float(beta),
+                                   float(ke), _ptr(force), _ptr(energy), _ptr(vir),
+                                   ctypes.byref(e_excl), ctypes.byref(e_self))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the input (code {rc})")
+    return dict(force=force, energy=energy, virial=vir.reshape(3, 3), e_excl=e_excl.value,
+                e_self=e_self.value, energy_total=e_excl.value + e_self.value)
+
+
+def ewald_corrections_system(system, ke: float = COULOMB_K) -> dict:
+    """``ewald_corrections`` on an object with the fields of ``systems.System``."""
+    return ewald_corrections(system.pos, system.charge, system.excl_offset, system.excl_index,
+                             system.box, system.beta, ke=ke)
