@@ -159,6 +159,24 @@ nb_status nb_nonbonded_backward(const nb_system *sys, const nb_params *params, v
                                 double *grad_charge, double *grad_sigma, double *grad_eps,
                                 hipStream_t stream);
 
+/* Ewald corrections that complete the real-space term of the forces above (section 3:
+ * the electrostatics are PME, whose reciprocal part counts every pair, excluded ones
+ * included, and every charge with itself):
+ *   excluded pairs: -k_e q_i q_j erf(beta r)/r for every pair {i, j} named in either
+ *     atom's exclusion row (each pair once, at any distance, minimum image; at r = 0 the
+ *     limit -k_e q_i q_j 2 beta/sqrt(pi));
+ *   self term: -k_e beta/sqrt(pi) sum_i q_i^2 per system.
+ * Writes (does not add to) force [device, N*3 doubles, caller's order: the forces of
+ * the excluded-pair term], energy [device, B doubles: both terms, or NULL] and virial
+ * [device, 9*B doubles: the excluded-pair term, row-major, or NULL].  FP64 arithmetic on
+ * the caller's positions and charges (either precision).  Requires nb_build_cells on
+ * this workspace with the same exclusion lists (it uses the exclusion windows of the
+ * build).  A far pair (|i - j| > 64) named in one row only is added to the other atom
+ * by an FP64 atomic, so such atoms' forces may vary in the last bits from run to run. */
+nb_status nb_ewald_corrections(const nb_system *sys, const nb_params *params, void *workspace,
+                               size_t workspace_bytes, double *force, double *energy, double *virial,
+                               hipStream_t stream);
+
 /* Synchronises `stream` and returns the NB_STATUS_* bits accumulated in the workspace. */
 nb_status nb_read_status(const void *workspace, hipStream_t stream, uint32_t *flags /*[host]*/);
 

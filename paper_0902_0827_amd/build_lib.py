@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnbhip.so")
 
-SOURCES = ["nb_api.cpp", "nb_build.hip", "nb_pair.hip", "nb_pair_cluster.hip"]
+SOURCES = ["nb_api.cpp", "nb_build.hip", "nb_pair.hip", "nb_pair_cluster.hip", "nb_ewald.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -305,6 +305,18 @@ nb_status nb_nonbonded_backward(const nb_system *sys, const nb_params *params, v
                     "nb_nonbonded_backward");
 }
 
+nb_status nb_ewald_corrections(const nb_system *sys, const nb_params *params, void *workspace,
+                               size_t workspace_bytes, double *force, double *energy, double *virial,
+                               hipStream_t stream) {
+  nb::Plan p;
+  nb_status st = nb::make_plan(sys, params, &p);
+  if (st != NB_OK) return st;
+  if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
+  if (!force) return fail(NB_ERR_ARG, "force must not be NULL");
+  return hip_status(nb::launch_ewald(p, nb::dev_view(p, workspace), sys, force, energy, virial, stream),
+                    "nb_ewald_corrections");
+}
+
 nb_status nb_read_status(const void *workspace, hipStream_t stream, uint32_t *flags) {
   if (!workspace || !flags) return fail(NB_ERR_ARG, "workspace and flags are required");
   hipError_t e = hipStreamSynchronize(stream);

@@ -169,6 +169,8 @@ inline void timer_after(hipStream_t s) {
 
 // Launchers (nb_build.hip / nb_pair.hip); each returns hipSuccess or the first error.
 hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hipStream_t s);
+hipError_t launch_ewald(const Plan &plan, const Dev &d, const nb_system *sys, double *force, double *energy,
+                        double *virial, hipStream_t s);
 hipError_t launch_forces(const Plan &plan, const Dev &d, const nb_system *sys, double *force,
                          double *energy, double *virial, hipStream_t s);
 hipError_t launch_energy(const Plan &plan, const Dev &d, const nb_system *sys, double *energy,

@@ -39,7 +39,7 @@ NB_MAX_TYPES = 64
 
 EXPORTED = ("nb_workspace_bytes", "nb_build_cells", "nb_nonbonded_forces", "nb_nonbonded_energy",
             "nb_nonbonded_backward", "nb_read_status", "nb_last_error", "nb_workspace_layout",
-            "nb_pair_timer_start", "nb_pair_timer_stop")
+            "nb_pair_timer_start", "nb_pair_timer_stop", "nb_ewald_corrections")
 
 
 class NbError(RuntimeError):
@@ -115,6 +115,7 @@ def load_library(path: str = LIB_PATH):
     lib.nb_nonbonded_forces.argtypes = [S, P, V, sz, V, V, V, V]
     lib.nb_nonbonded_energy.argtypes = [S, P, V, sz, V, V, V]
     lib.nb_nonbonded_backward.argtypes = [S, P, V, sz, V, V, V, V, V, V]
+    lib.nb_ewald_corrections.argtypes = [S, P, V, sz, V, V, V, V]
     lib.nb_read_status.argtypes = [V, V, ctypes.POINTER(ctypes.c_uint32)]
     lib.nb_workspace_layout.argtypes = [S, P, ctypes.POINTER(nb_layout)]
     lib.nb_pair_timer_start.argtypes = [ctypes.c_int32]
@@ -251,6 +252,13 @@ def nonbonded_forces(batch: DeviceBatch, params: nb_params, ws, force, energy=No
     lib = load_library()
     _check(lib.nb_nonbonded_forces(ctypes.byref(batch.struct()), ctypes.byref(params), _ptr(ws), ws.numel(),
                                    _ptr(force), _ptr(energy), _ptr(virial), _stream(stream)))
+
+
+def ewald_corrections(batch: DeviceBatch, params: nb_params, ws, force, energy=None, virial=None, stream=None):
+    """Excluded-pair and self corrections of the Ewald sum (nb_ewald_corrections)."""
+    lib = load_library()
+    _check(lib.nb_ewald_corrections(ctypes.byref(batch.struct()), ctypes.byref(params), _ptr(ws), ws.numel(),
+                                    _ptr(force), _ptr(energy), _ptr(virial), _stream(stream)))
 
 
 def nonbonded_energy(batch: DeviceBatch, params: nb_params, ws, energy, atom_energy=None, stream=None):

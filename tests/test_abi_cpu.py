@@ -136,6 +136,10 @@ def test_workspace_checks_happen_before_any_launch():
     assert lib.nb_nonbonded_backward(ctypes.byref(s), ctypes.byref(p), FAKE, need, None, None, None, None,
                                      None, None) == H.NB_ERR_ARG  # grad_energy is required
     assert lib.nb_nonbonded_energy(ctypes.byref(s), ctypes.byref(p), FAKE, need, None, None, None) == H.NB_ERR_ARG
+    assert lib.nb_ewald_corrections(ctypes.byref(s), ctypes.byref(p), FAKE, need, None, None, None, None) \
+        == H.NB_ERR_ARG  # force is required
+    assert lib.nb_ewald_corrections(ctypes.byref(s), ctypes.byref(p), FAKE, need - 1, FAKE, None, None, None) \
+        == H.NB_ERR_WORKSPACE
 
 
 def test_workload_generators_have_the_documented_shapes():

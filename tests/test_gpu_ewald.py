@@ -1,0 +1,120 @@
+"""GPU parity of the Ewald corrections (nb_ewald_corrections, through the C ABI) against
+the FP64 oracle: the excluded-pair erf term and the self term, per system, including
+far exclusions named in one row only and batches of several systems.
+
+Both precisions compute these in FP64 from the caller's arrays (float inputs are
+promoted), so the bar is 1e-13 relative RMS on forces and 1e-12 on energies and virials.
+"""
+
+import numpy as np
+import pytest
+
+import nbtest_util as U
+from oracle import oracle as O
+from paper_0902_0827_amd import nbhip as H
+from paper_0902_0827_amd import systems as S
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+FORCE_TOL = 1e-13
+SUM_TOL = 1e-12
+
+
+def _print_case(name, **kw):
+    print(f"[case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def with_far_one_sided(s):
+    """The system with three extra exclusions beyond the 64-index window, each named in
+    one row only (and one of them twice)."""
+    rows = [list(s.excl_index[s.excl_offset[i]:s.excl_offset[i + 1]]) for i in range(s.n)]
+    for a, b in [(2, 300), (5, 500), (17, 410), (17, 410)]:
+        rows[a].append(b)
+    off = np.zeros(s.n + 1, np.int32)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    t = S.System(**{**s.__dict__})
+    t.excl_offset, t.excl_index = off, np.array([j for r in rows for j in r], np.int32)
+    return t
+
+
+@pytest.fixture(scope="module")
+def chain_far():
+    return with_far_one_sided(U.small_chain())
+
+
+def energy_scale(ref):
+    """The total is the small difference of the excluded-pair and self sums (water: tens of
+    thousands each, a thousand apart), so its FP64 rounding is relative to their size."""
+    return abs(ref["e_excl"]) + abs(ref["e_self"])
+
+
+def gpu_ewald(systems, precision, kernel=H.NB_KERNEL_AUTO):
+    out = U.gpu_eval(systems, precision, kernel=kernel)  # builds the workspace (and runs the forces)
+    b, p, ws = out["batch"], out["params"], out["ws"]
+    force = torch.full((b.n_atoms, 3), 7.0, dtype=torch.float64, device="cuda")
+    energy = torch.full((b.n_systems,), 7.0, dtype=torch.float64, device="cuda")
+    vir = torch.full((b.n_systems, 3, 3), 7.0, dtype=torch.float64, device="cuda")
+    H.ewald_corrections(b, p, ws, force, energy, vir)
+    torch.cuda.synchronize()
+    return force.cpu().numpy(), energy.cpu().numpy(), vir.cpu().numpy(), H.read_status(ws)
+
+
+@pytest.mark.parametrize("kernel", [H.NB_KERNEL_AUTO, H.NB_KERNEL_ATOM])
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+@pytest.mark.parametrize("which", ["chain_far", "cfg1", "cfg2"])
+def test_corrections_match_oracle(which, precision, kernel, chain_far):
+    s = {"chain_far": lambda: chain_far, "cfg1": lambda: U.cached_config(1), "cfg2": lambda: U.cached_config(2)}[which]()
+    _print_case("ewald", which=which, precision=precision, kernel=kernel, n=s.n)
+    force, energy, vir, status = gpu_ewald(s, precision, kernel=kernel)
+    ref = O.ewald_corrections_system(U.rounded(s, precision), ke=H.COULOMB_K)
+    err = U.rel_rms(force, ref["force"])
+    print(f"  force rel_rms={err:.3e} energy={energy[0]:.12e} oracle={ref['energy_total']:.12e}")
+    assert err <= FORCE_TOL
+    assert abs(energy[0] - ref["energy_total"]) <= SUM_TOL * energy_scale(ref)
+    assert U.rel_rms(vir[0], ref["virial"]) <= SUM_TOL
+    assert (status & ~H.NB_STATUS_FAR_EXCLUSION) == 0  # the far pairs are reported, nothing else
+
+
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+def test_batch_of_systems(precision, chain_far):
+    systems = [chain_far, U.cached_config(1), S.water_box(500, 25.0, seed=9)]
+    _print_case("ewald-batch", precision=precision)
+    force, energy, vir, status = gpu_ewald(systems, precision)
+    a0 = 0
+    for b, s in enumerate(systems):
+        ref = O.ewald_corrections_system(U.rounded(s, precision), ke=H.COULOMB_K)
+        assert U.rel_rms(force[a0:a0 + s.n], ref["force"]) <= FORCE_TOL
+        assert abs(energy[b] - ref["energy_total"]) <= SUM_TOL * energy_scale(ref)
+        assert U.rel_rms(vir[b], ref["virial"]) <= SUM_TOL
+        a0 += s.n
+    assert (status & ~H.NB_STATUS_FAR_EXCLUSION) == 0
+
+
+def test_refuses_an_unbuilt_workspace(chain_far):
+    b = H.device_batch([chain_far], dtype=torch.float64)
+    p = H.make_params(chain_far.cutoff, chain_far.beta, H.NB_FP64)
+    ws = torch.zeros(H.workspace_bytes(b, p), dtype=torch.uint8, device="cuda")
+    force = torch.full((chain_far.n, 3), 7.0, dtype=torch.float64, device="cuda")
+    energy = torch.full((1,), 7.0, dtype=torch.float64, device="cuda")
+    H.ewald_corrections(b, p, ws, force, energy)
+    assert H.read_status(ws) & H.NB_STATUS_NOT_BUILT
+    assert float(force.abs().min()) == 7.0 and float(force.abs().max()) == 7.0 and float(energy[0]) == 7.0
+
+
+def test_repeatable_and_beta_zero(chain_far):
+    s = U.cached_config(2)  # no one-sided far pairs: bitwise the same each time
+    f1, e1, v1, _ = gpu_ewald(s, H.NB_MIXED)
+    f2, e2, v2, _ = gpu_ewald(s, H.NB_MIXED)
+    np.testing.assert_array_equal(f1, f2)
+    np.testing.assert_array_equal(e1, e2)
+    np.testing.assert_array_equal(v1, v2)
+    # with one-sided far pairs only their atomic additions may reorder
+    g1, _, _, _ = gpu_ewald(chain_far, H.NB_FP64)
+    g2, _, _, _ = gpu_ewald(chain_far, H.NB_FP64)
+    np.testing.assert_allclose(g1, g2, rtol=0, atol=1e-13 * np.abs(g1).max())
+    z = S.System(**{**chain_far.__dict__})
+    z.beta = 0.0
+    fz, ez, vz, st = gpu_ewald(z, H.NB_FP64)
+    assert np.all(fz == 0.0) and ez[0] == 0.0 and np.all(vz == 0.0) and (st & ~H.NB_STATUS_FAR_EXCLUSION) == 0
