@@ -94,6 +94,34 @@ def build_rate(b, p, ws, steps, torch, H):
             "achieved": nbytes / us * 1e-3, "frac": nbytes / us * 1e-3 / HBM_PEAK_GBPS}
 
 
+# Algorithmic HBM bytes of nb_ewald_corrections per atom: read position and charge (FP32
+# 16, FP64 32), the exclusion window 16 and far flag 4, write the FP64 force 24.  Partner
+# positions are other atoms' own reads; the per-block partials are a few bytes per 256 atoms.
+EWALD_BYTES_PER_ATOM = {"mixed": 16 + 16 + 4 + 24, "fp64": 32 + 16 + 4 + 24}
+
+
+def ewald_rate(b, p, ws, prec_name, steps, torch, H):
+    """nb_ewald_corrections on a built workspace: its outputs and mean microseconds per call
+    (all its launches, HIP events around the loop), with the algorithmic HBM rate."""
+    force = torch.empty((b.n_atoms, 3), dtype=torch.float64, device="cuda")
+    energy = torch.empty(b.n_systems, dtype=torch.float64, device="cuda")
+    vir = torch.empty((b.n_systems, 3, 3), dtype=torch.float64, device="cuda")
+    for _ in range(5):
+        H.ewald_corrections(b, p, ws, force, energy, vir)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        H.ewald_corrections(b, p, ws, force, energy, vir)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / steps
+    nbytes = EWALD_BYTES_PER_ATOM[prec_name] * b.n_atoms
+    return {"us_per_call": us, "bytes": int(nbytes), "achieved": nbytes / us * 1e-3,
+            "frac": nbytes / us * 1e-3 / HBM_PEAK_GBPS, "calls": steps,
+            "force": force.cpu().numpy(), "energy": energy.cpu().numpy(), "virial": vir.cpu().numpy()}
+
+
 PAIR_SOURCES = ("nb_pair_cluster.hip", "nb_pair_math.h", "nb_pair_common.h", "nb_internal.h")
 
 
@@ -153,6 +181,7 @@ def run_batch(args, H, S, torch):
     t = time_steps(step, args.batch_steps, 5, torch, H)
     f = force.cpu().numpy()
     build = build_rate(b, p, ws, args.batch_steps, torch, H)
+    ew = ewald_rate(b, p, ws, "mixed", args.batch_steps, torch, H)
     status = H.read_status(ws)
     log(f"[bench] batch: {t['sec'] * 1e3:.3f} ms/step, pair kernel {t['pair_sec'] * 1e6:.1f} us; params {chosen}")
     # sampled FP64 oracle rows (inputs rounded as the device saw them)
@@ -169,6 +198,20 @@ def run_batch(args, H, S, torch):
         pair_rows += r["pairs"]
         n_rows += len(rows)
         off += sys_b.n
+    # Ewald corrections of every replica against the oracle's
+    ew_num = ew_den = ew_e = 0.0
+    t0 = time.perf_counter()
+    off = 0
+    for k, sys_b in enumerate(systems):
+        r = O.ewald_corrections_system(sys_b.rounded(np.float32), ke=H.COULOMB_K)
+        ew_num += float(np.sum((ew["force"][off:off + sys_b.n] - r["force"]) ** 2))
+        ew_den += float(np.sum(r["force"] ** 2))
+        ew_e = max(ew_e, abs(float(ew["energy"][k]) - r["energy_total"]) / (abs(r["e_excl"]) + abs(r["e_self"])))
+        off += sys_b.n
+    ewald = {"us_per_call": ew["us_per_call"], "calls": ew["calls"], "bytes_per_call": ew["bytes"],
+             "achieved": ew["achieved"], "frac": ew["frac"], "rel_rms_force": float(np.sqrt(ew_num / ew_den)),
+             "max_energy_err_rel_to_terms": ew_e, "oracle_ms": (time.perf_counter() - t0) * 1e3}
+    log(f"[bench] batch Ewald corrections: {ew['us_per_call']:.2f} us per call")
     est_pairs = 0.5 * (pair_rows / n_rows) * b.n_atoms
     return {"workload": "64 replicas, N log-uniform in [3000, 30000] (807,400 atoms), water + chain, "
                         "0.95-1.05 g/cm^3, cutoff 9 A, Ewald beta 0.34/A, FP32 positions (seed 4)",
@@ -177,7 +220,7 @@ def run_batch(args, H, S, torch):
             "pair_kernel_us": t["pair_sec"] * 1e6, "atoms_per_s": b.n_atoms / t["sec"],
             "pairs_per_s_estimate": est_pairs / t["sec"], "pairs_in_cutoff_estimate": est_pairs,
             "rel_rms_force_sampled": float(np.sqrt(err_num / err_den)), "sampled_atoms": n_rows,
-            "params": chosen, "status_bits": status, "build": build}
+            "params": chosen, "status_bits": status, "build": build, "ewald": ewald}
 
 
 def main():
@@ -269,8 +312,10 @@ def main():
         adjoint = dict(sec=t_adj["sec"], pair_sec=t_adj["pair_sec"], steps=adj_steps, grad_pos=g_x.cpu().numpy(),
                        grad_charge=g_q.cpu().numpy(), grad_sigma=g_s.cpu().numpy(), grad_eps=g_p.cpu().numpy())
         log(f"[bench] {prec_name} adjoint: {t_adj['sec'] * 1e3:.4f} ms/step, pair kernel {t_adj['pair_sec'] * 1e6:.1f} us")
+        ewald = ewald_rate(b, p, ws, prec_name, steps, torch, H)
+        log(f"[bench] {prec_name} Ewald corrections: {ewald['us_per_call']:.2f} us per call")
         results[prec_name] = dict(t, steps=steps, force=force.cpu().numpy(), energy=float(energy.cpu()[0]),
-                                  status=H.read_status(ws), build=build, adjoint=adjoint)
+                                  status=H.read_status(ws), build=build, adjoint=adjoint, ewald=ewald)
         log(f"[bench] {prec_name}: {t['sec'] * 1e3:.4f} ms/step (median {t['median'] * 1e3:.4f}), "
             f"pair kernel {t['pair_sec'] * 1e6:.1f} us over {t['pair_launches']} launches")
 
@@ -281,11 +326,15 @@ def main():
     t_cpu = []
     reps = 0
     t_start = time.perf_counter()
+    ref_ew, t_ew = {}, []
     for prec_name, sys_in in (("mixed", s.rounded(np.float32)), ("fp64", s))[:len(paths)]:
         t0 = time.perf_counter()
         ref[prec_name] = O.evaluate_system(sys_in, ke=H.COULOMB_K)
         t_cpu.append(time.perf_counter() - t0)
         reps += 1
+        t0 = time.perf_counter()
+        ref_ew[prec_name] = O.ewald_corrections_system(sys_in, ke=H.COULOMB_K)
+        t_ew.append(time.perf_counter() - t0)
     if not args.no_cpu_baseline:
         # bounded sample: repeat full evaluations until ~10 s of wall time have been spent
         while time.perf_counter() - t_start < 10.0 and reps < 8:
@@ -313,6 +362,13 @@ def main():
                 "pair_kernel_us": a["pair_sec"] * 1e6,
                 "rel_rms_grad_pos": rel(a["grad_pos"], -r["force"]), "rel_rms_grad_charge": rel(a["grad_charge"], r["phi"]),
                 "rel_grad_sigma": rel(a["grad_sigma"], r["dsigma"]), "rel_grad_eps": rel(a["grad_eps"], r["deps"])}
+    def ewald_entry(ew, r):
+        return {"us_per_call": ew["us_per_call"], "calls": ew["calls"], "bytes_per_call": ew["bytes"],
+                "achieved": ew["achieved"], "frac": ew["frac"],
+                "rel_rms_force": rel_errors(ew["force"], r["force"])[0],
+                "energy_err_rel_to_terms": abs(float(ew["energy"][0]) - r["energy_total"]) /
+                                          (abs(r["e_excl"]) + abs(r["e_self"])),
+                "rel_virial": float(np.linalg.norm(ew["virial"][0] - r["virial"]) / np.linalg.norm(r["virial"]))}
     achieved = pairs * FLOPS_PER_PAIR / m["pair_sec"] / 1e12
     default_kernel = args.kernel == "auto" and args.split == 0 and args.cluster_size == 0 and \
         args.cell_div == "0,0" and args.schedule == "auto" and args.wg_per_cu == 0
@@ -355,6 +411,14 @@ def main():
                     "bytes_per_atom": BUILD_BYTES_PER_ATOM, "bytes_per_exclusion_entry": BUILD_BYTES_PER_EXCL,
                     "bytes_per_cell": BUILD_BYTES_PER_CELL, "box": m.get("build"),
                     "batch": None if batch is None else batch.get("build")},
+        # nb_ewald_corrections (excluded-pair erf and self terms) on the built workspace:
+        # algorithmic HBM bytes per call over its time (all launches), errors against the
+        # oracle's corrections, and the oracle's own time for them on one core
+        "ewald_corrections": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBPS,
+                              "bytes_per_atom": EWALD_BYTES_PER_ATOM,
+                              "box": {name: ewald_entry(results[name]["ewald"], ref_ew[name]) for name in results},
+                              "oracle_ms": float(np.median(t_ew)) * 1e3,
+                              "batch": None if batch is None else batch.get("ewald")},
         "status_bits": [r["status"] for r in results.values()],
     }
     print(json.dumps(out), flush=True)
