@@ -177,6 +177,30 @@ nb_status nb_ewald_corrections(const nb_system *sys, const nb_params *params, vo
                                size_t workspace_bytes, double *force, double *energy, double *virial,
                                hipStream_t stream);
 
+/* Reciprocal part of the Ewald sum by smooth particle-mesh Ewald (section 3: the
+ * long-range electrostatics are PME with fourth-order interpolation; the method of
+ * Essmann et al. 1995).  On a K1 x K2 x K3 grid (grid[3], host, each in [4, 1024], the
+ * same for every system of the batch) with cubic B-splines (order 4):
+ *   E_b = k_e/(2 pi V) sum_{m != 0} exp(-pi^2 m^2/beta^2)/m^2 B(m) |FFT(Q)(m)|^2
+ * where Q is the charge grid of system b, m = (n1/L1, n2/L2, n3/L3) and B the spline
+ * factor.  The m = 0 term is omitted (no neutralising-background term for a charged
+ * system).  Writes (does not add to) force [device, N*3 doubles, caller's order],
+ * energy [device, B doubles, or NULL] and virial [device, 9*B doubles,
+ * W_ab = -dE/d(strain_ab), row-major, or NULL].  FP64 arithmetic (either input
+ * precision); ewald_beta > 0 and coulomb_k come from params, which is validated as for
+ * the other calls.  `workspace` is its own buffer (not the nonbonded workspace) of
+ * nb_pme_workspace_bytes bytes, 256-byte aligned, owned by the caller; it needs no
+ * build.  The grid additions of the charge spreading are FP64 atomics, so results may
+ * vary in the last bits from run to run.  The FFTs use hipFFT plans made on the first
+ * call for a grid shape on a device and kept until the process ends (they hold the FFT
+ * library's own device buffers); calls for one grid shape from several host threads at
+ * once are serialised while they enqueue.  Returns NB_ERR_HIP if the FFT library
+ * refuses a plan or a transform. */
+nb_status nb_pme_workspace_bytes(const nb_system *sys, const int32_t grid[3] /*[host]*/, size_t *bytes /*[host]*/);
+nb_status nb_pme_reciprocal(const nb_system *sys, const nb_params *params, const int32_t grid[3] /*[host]*/,
+                            void *workspace, size_t workspace_bytes, double *force, double *energy,
+                            double *virial, hipStream_t stream);
+
 /* Synchronises `stream` and returns the NB_STATUS_* bits accumulated in the workspace. */
 nb_status nb_read_status(const void *workspace, hipStream_t stream, uint32_t *flags /*[host]*/);
 

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnbhip.so")
 
-SOURCES = ["nb_api.cpp", "nb_build.hip", "nb_pair.hip", "nb_pair_cluster.hip", "nb_ewald.hip"]
+SOURCES = ["nb_api.cpp", "nb_build.hip", "nb_pair.hip", "nb_pair_cluster.hip", "nb_ewald.hip", "nb_pme.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -34,11 +34,12 @@ FLAGS = [
     f"-I{INCLUDE}",
     f"-I{CSRC}",
 ]
+LIBS = ["-lhipfft"]
 
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, *FLAGS, *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+    cmd = [HIPCC, *FLAGS, *[os.path.join(CSRC, s) for s in SOURCES], *LIBS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

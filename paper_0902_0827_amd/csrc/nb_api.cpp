@@ -9,6 +9,7 @@
 #include <string>
 
 #include "nb_internal.h"
+#include "nb_pme.h"
 
 namespace nb {
 
@@ -315,6 +316,40 @@ nb_status nb_ewald_corrections(const nb_system *sys, const nb_params *params, vo
   if (!force) return fail(NB_ERR_ARG, "force must not be NULL");
   return hip_status(nb::launch_ewald(p, nb::dev_view(p, workspace), sys, force, energy, virial, stream),
                     "nb_ewald_corrections");
+}
+
+nb_status nb_pme_workspace_bytes(const nb_system *sys, const int32_t grid[3], size_t *bytes) {
+  if (!sys || !bytes) return fail(NB_ERR_ARG, "null system or output pointer");
+  if (sys->n_systems < 1) return fail(NB_ERR_ARG, "n_systems must be >= 1");
+  nb::PmeLayout lay;
+  const std::string why = nb::pme_layout(sys->n_systems, grid, &lay);
+  if (!why.empty()) return fail(NB_ERR_ARG, why);
+  *bytes = lay.total;
+  return NB_OK;
+}
+
+nb_status nb_pme_reciprocal(const nb_system *sys, const nb_params *params, const int32_t grid[3], void *workspace,
+                            size_t workspace_bytes, double *force, double *energy, double *virial,
+                            hipStream_t stream) {
+  nb::Plan p;
+  nb_status st = nb::make_plan(sys, params, &p);
+  if (st != NB_OK) return st;
+  if (!(params->ewald_beta > 0.0)) return fail(NB_ERR_ARG, "the reciprocal sum needs ewald_beta > 0");
+  nb::PmeLayout lay;
+  const std::string why = nb::pme_layout(sys->n_systems, grid, &lay);
+  if (!why.empty()) return fail(NB_ERR_ARG, why);
+  if (!workspace) return fail(NB_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(NB_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (workspace_bytes < lay.total)
+    return fail(NB_ERR_WORKSPACE,
+                "workspace too small: " + std::to_string(workspace_bytes) + " < " + std::to_string(lay.total));
+  if (!force) return fail(NB_ERR_ARG, "force must not be NULL");
+  std::string err;
+  const hipError_t e = nb::launch_pme(lay, sys, params->ewald_beta, params->coulomb_k, workspace, force, energy,
+                                      virial, stream, &err);
+  if (!err.empty()) return fail(NB_ERR_HIP, "nb_pme_reciprocal: " + err);
+  return hip_status(e, "nb_pme_reciprocal");
 }
 
 nb_status nb_read_status(const void *workspace, hipStream_t stream, uint32_t *flags) {

@@ -1,0 +1,371 @@
+// Reciprocal part of the Ewald sum by smooth particle-mesh Ewald (ACEMD paper, section 3:
+// the long-range electrostatics are PME with fourth-order interpolation; the method is
+// that of Essmann et al., J. Chem. Phys. 103, 8577 (1995)).  With u_a = K_a x_a / L_a
+// the scaled fractional coordinates and M_4 the cubic cardinal B-spline:
+//
+//   Q(k)   = sum_i q_i prod_a M_4(u_ai - k_a)           (periodic in k)
+//   E      = k_e/(2 pi V) sum_{m != 0} C(m) |FFT(Q)(m)|^2,
+//   C(m)   = exp(-pi^2 m^2/beta^2)/m^2 prod_a 9/(2 + cos(2 pi m_a/K_a))^2
+//   phi    = dE/dQ = k_e/(pi V) IFFT(C FFT(Q))          (unnormalised inverse)
+//   F_i    = -q_i sum_k phi(k) grad_i prod_a M_4(u_ai - k_a)
+//   W_ab   = sum_m E_m [delta_ab - 2 (1 + pi^2 m^2/beta^2) m_a m_b / m^2].
+//
+// The factor 9/(2 + cos t)^2 is |b(m)|^2 for order 4: the Euler exponential spline's
+// denominator 1/6 + (2/3) e^{it} + (1/6) e^{2it} has modulus (2 + cos t)/3.
+//
+// All arithmetic is FP64 (positions and charges of either precision are promoted).
+// Per system, in order on the caller's stream:
+//   k_pme_spread   one thread per atom, 64 FP64 atomic additions into the grid;
+//   D2Z FFT        (hipFFT, a plan per grid shape and device, made on first use);
+//   k_pme_convolve one thread per element of the half spectrum: C(m), the energy and
+//                  virial terms (per-block partials) and the product C FFT(Q);
+//   Z2D FFT        giving phi on the real grid;
+//   k_pme_gather   one thread per atom: its force from phi and the spline derivatives.
+// k_pme_reduce then sums each system's partials in a fixed order.  The grid additions
+// of the spread are the only ones whose order varies from run to run.
+#include <hipfft/hipfft.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "nb_internal.h"
+#include "nb_pair_common.h"
+#include "nb_pme.h"
+
+namespace nb {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kMinGrid = 4;     // the spline's four points must be distinct grid points
+constexpr int kMaxGrid = 1024;
+
+struct PmeSys {
+  double L[3];
+  int K[3];
+  int H;  // K3/2 + 1: the half spectrum's last dimension
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// The four grid points k = base - j (mod K), j = 0..3, of coordinate x, with M_4(u - k)
+// and dM_4/du at u - k = t + j, t = u - base in [0, 1).
+__device__ inline void spline4(double x, double L, int K, int idx[4], double w[4], double dw[4]) {
+  double f = x / L;
+  f -= floor(f);  // in [0, 1] for finite x
+  const double u = f * K;
+  int base = 0;
+  double t;
+  if (u >= 0.0 && u < K) {
+    base = static_cast<int>(floor(u));
+    t = u - base;
+  } else if (u == K) {  // f rounded up to 1: the point K is the point 0
+    t = 0.0;
+  } else {  // non-finite coordinate: indices stay in range, the results are NaN
+    t = u - u;
+  }
+  const double t2 = t * t, t3 = t2 * t, s = 1.0 - t;
+  w[0] = t3 * (1.0 / 6.0);
+  w[1] = (1.0 + 3.0 * t + 3.0 * t2 - 3.0 * t3) * (1.0 / 6.0);
+  w[2] = (4.0 - 6.0 * t2 + 3.0 * t3) * (1.0 / 6.0);
+  w[3] = s * s * s * (1.0 / 6.0);
+  dw[0] = 0.5 * t2;
+  dw[1] = 0.5 * (1.0 + 2.0 * t - 3.0 * t2);
+  dw[2] = 0.5 * (3.0 * t2 - 4.0 * t);
+  dw[3] = -0.5 * s * s;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) idx[j] = base - j < 0 ? base - j + K : base - j;
+}
+
+__global__ void __launch_bounds__(kBlock) k_pme_zero(double *__restrict__ g, int64_t n) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; e < n;
+       e += static_cast<int64_t>(gridDim.x) * kBlock)
+    g[e] = 0.0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_pme_spread(const T *__restrict__ pos, const T *__restrict__ charge, int n,
+                                                       PmeSys ps, double *__restrict__ grid) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int ix[4], iy[4], iz[4];
+  double wx[4], wy[4], wz[4], d[4];
+  spline4(static_cast<double>(pos[3 * i + 0]), ps.L[0], ps.K[0], ix, wx, d);
+  spline4(static_cast<double>(pos[3 * i + 1]), ps.L[1], ps.K[1], iy, wy, d);
+  spline4(static_cast<double>(pos[3 * i + 2]), ps.L[2], ps.K[2], iz, wz, d);
+  const double q = static_cast<double>(charge[i]);
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      const double qab = q * wx[a] * wy[b];
+      double *row = grid + (static_cast<int64_t>(ix[a]) * ps.K[1] + iy[b]) * ps.K[2];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) unsafeAtomicAdd(&row[iz[c]], qab * wz[c]);
+    }
+}
+
+// Signed reciprocal index of grid index i: i for i <= K/2, else i - K.
+__device__ inline int signed_index(int i, int K) { return 2 * i <= K ? i : i - K; }
+
+// 9 / (2 + cos(2 pi i / K))^2
+__device__ inline double bmod2(int i, int K) {
+  const double c = 2.0 + cospi(2.0 * static_cast<double>(i) / static_cast<double>(K));
+  return 9.0 / (c * c);
+}
+
+__global__ void __launch_bounds__(kBlock) k_pme_convolve(double2 *__restrict__ spec, PmeSys ps, int64_t n_spec,
+                                                         double beta, double ke, double *__restrict__ partials,
+                                                         int64_t n_part_blocks) {
+  __shared__ double red[kWaves][kPart];
+  const int64_t e = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
+  double v[kPart] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (e < n_spec) {
+    const int iz = static_cast<int>(e % ps.H);
+    const int64_t r = e / ps.H;
+    const int iy = static_cast<int>(r % ps.K[1]);
+    const int ix = static_cast<int>(r / ps.K[1]);
+    const double m[3] = {signed_index(ix, ps.K[0]) / ps.L[0], signed_index(iy, ps.K[1]) / ps.L[1],
+                         signed_index(iz, ps.K[2]) / ps.L[2]};
+    const double m2 = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+    double2 F = spec[e];
+    if (m2 > 0.0) {
+      const double V = ps.L[0] * ps.L[1] * ps.L[2];
+      const double a = kPi * kPi / (beta * beta);
+      const double C = exp(-a * m2) / m2 * bmod2(ix, ps.K[0]) * bmod2(iy, ps.K[1]) * bmod2(iz, ps.K[2]);
+      const double em = ke / (2.0 * kPi * V) * C * (F.x * F.x + F.y * F.y);
+      const double vf = 2.0 * (1.0 + a * m2) / m2;
+      // The half spectrum holds each element and its conjugate partner (K - i mod K per
+      // dimension) once, except in the planes iz = 0 and iz = K3/2, whose partners are
+      // elements of their own.  The partner has the same |F|^2 and m^2; its signed
+      // indices are -m except on a Nyquist index K/2, which stays +K/2.
+      const bool pair = !(iz == 0 || 2 * iz == ps.K[2]);
+      const int jx = ix == 0 ? 0 : ps.K[0] - ix, jy = iy == 0 ? 0 : ps.K[1] - iy;
+      const double mp[3] = {signed_index(jx, ps.K[0]) / ps.L[0], signed_index(jy, ps.K[1]) / ps.L[1],
+                            signed_index(ps.K[2] - iz, ps.K[2]) / ps.L[2]};
+      v[0] = pair ? 2.0 * em : em;
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const double d = p == q ? 1.0 : 0.0;
+          v[1 + 3 * p + q] = em * (d - vf * m[p] * m[q]) + (pair ? em * (d - vf * mp[p] * mp[q]) : 0.0);
+        }
+      const double sc = C * ke / (kPi * V);
+      F.x *= sc;
+      F.y *= sc;
+    } else {
+      F.x = 0.0;
+      F.y = 0.0;
+    }
+    spec[e] = F;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kPart; ++k) {
+    const double s = wave_sum(v[k]);
+    if (lane == 0) red[wave][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kPart) {
+    double s = 0.0;
+    for (int w = 0; w < kWaves; ++w) s += red[w][threadIdx.x];
+    partials[static_cast<int64_t>(threadIdx.x) * n_part_blocks + blockIdx.x] = s;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_pme_gather(const T *__restrict__ pos, const T *__restrict__ charge, int n,
+                                                       PmeSys ps, const double *__restrict__ phi,
+                                                       double *__restrict__ force) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int ix[4], iy[4], iz[4];
+  double wx[4], wy[4], wz[4], dx[4], dy[4], dz[4];
+  spline4(static_cast<double>(pos[3 * i + 0]), ps.L[0], ps.K[0], ix, wx, dx);
+  spline4(static_cast<double>(pos[3 * i + 1]), ps.L[1], ps.K[1], iy, wy, dy);
+  spline4(static_cast<double>(pos[3 * i + 2]), ps.L[2], ps.K[2], iz, wz, dz);
+  double gx = 0.0, gy = 0.0, gz = 0.0;  // sum_k phi(k) dQ(k)/du / q
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      const double *row = phi + (static_cast<int64_t>(ix[a]) * ps.K[1] + iy[b]) * ps.K[2];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double p = row[iz[c]];
+        gx += p * dx[a] * wy[b] * wz[c];
+        gy += p * wx[a] * dy[b] * wz[c];
+        gz += p * wx[a] * wy[b] * dz[c];
+      }
+    }
+  const double q = static_cast<double>(charge[i]);
+  force[3 * static_cast<int64_t>(i) + 0] = -q * gx * (ps.K[0] / ps.L[0]);
+  force[3 * static_cast<int64_t>(i) + 1] = -q * gy * (ps.K[1] / ps.L[1]);
+  force[3 * static_cast<int64_t>(i) + 2] = -q * gz * (ps.K[2] / ps.L[2]);
+}
+
+// Energy and virial of system blockIdx.x: its convolution partials in block order.
+__global__ void __launch_bounds__(kBlock) k_pme_reduce(const double *__restrict__ partials, int64_t n_part_blocks,
+                                                       double *energy, double *virial) {
+  __shared__ double red[kWaves][kPart];
+  const int b = blockIdx.x;
+  const double *pb = partials + static_cast<int64_t>(b) * kPart * n_part_blocks;
+  double acc[kPart];
+#pragma unroll
+  for (int k = 0; k < kPart; ++k) acc[k] = 0.0;
+  for (int64_t q = threadIdx.x; q < n_part_blocks; q += kBlock) {
+#pragma unroll
+    for (int k = 0; k < kPart; ++k) acc[k] += pb[static_cast<int64_t>(k) * n_part_blocks + q];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kPart; ++k) {
+    const double s = wave_sum(acc[k]);
+    if (lane == 0) red[wave][k] = s;
+  }
+  __syncthreads();
+  if (static_cast<int>(threadIdx.x) < kPart) {
+    double s = 0.0;
+    for (int w = 0; w < kWaves; ++w) s += red[w][threadIdx.x];
+    if (threadIdx.x == 0) {
+      if (energy) energy[b] = s;
+    } else if (virial) {
+      virial[9 * b + (threadIdx.x - 1)] = s;
+    }
+  }
+}
+
+// FFT plans, one forward (D2Z) and one inverse (Z2D) per grid shape and device, made on
+// first use and kept for the life of the process.  The mutex also covers setting a
+// plan's stream and enqueueing its transform.
+struct FftPlans {
+  hipfftHandle fwd = nullptr, inv = nullptr;
+};
+std::mutex g_fft_mu;
+std::map<std::tuple<int, int, int, int>, FftPlans> g_fft;
+
+const char *fft_error(hipfftResult r) {
+  switch (r) {
+    case HIPFFT_ALLOC_FAILED: return "FFT allocation failed";
+    case HIPFFT_INVALID_SIZE: return "FFT size refused";
+    case HIPFFT_EXEC_FAILED: return "FFT execution failed";
+    default: return "FFT library error";
+  }
+}
+
+}  // namespace
+
+std::string pme_layout(int B, const int32_t grid[3], PmeLayout *lay) {
+  if (!grid) return "grid is NULL";
+  for (int a = 0; a < 3; ++a)
+    if (grid[a] < kMinGrid || grid[a] > kMaxGrid) return "grid sizes must be in [4, 1024]";
+  PmeLayout l;
+  l.B = B;
+  for (int a = 0; a < 3; ++a) l.K[a] = grid[a];
+  l.grid = static_cast<int64_t>(grid[0]) * grid[1] * grid[2];
+  l.spec = static_cast<int64_t>(grid[0]) * grid[1] * (grid[2] / 2 + 1);
+  if (l.grid > (int64_t{1} << 28)) return "grid larger than 2^28 points";
+  l.conv_blocks = (l.spec + kBlock - 1) / kBlock;
+  size_t off = 0;
+  l.real = off;
+  off = align256(off + sizeof(double) * static_cast<size_t>(B) * l.grid);
+  l.cplx = off;
+  off = align256(off + 2 * sizeof(double) * static_cast<size_t>(B) * l.spec);
+  l.partials = off;
+  off = align256(off + sizeof(double) * static_cast<size_t>(B) * kPart * l.conv_blocks);
+  l.total = off;
+  *lay = l;
+  return "";
+}
+
+hipError_t launch_pme(const PmeLayout &lay, const nb_system *sys, double beta, double ke, void *ws, double *force,
+                      double *energy, double *virial, hipStream_t s, std::string *err) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  char *base = static_cast<char *>(ws);
+  double *real = reinterpret_cast<double *>(base + lay.real);
+  double2 *cplx = reinterpret_cast<double2 *>(base + lay.cplx);
+  double *partials = reinterpret_cast<double *>(base + lay.partials);
+  {
+    const int64_t n = lay.grid * lay.B;
+    const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL(k_pme_zero, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, real, n);
+  }
+  FftPlans plans;
+  {
+    std::lock_guard<std::mutex> lock(g_fft_mu);
+    auto key = std::make_tuple(dev, lay.K[0], lay.K[1], lay.K[2]);
+    auto it = g_fft.find(key);
+    if (it == g_fft.end()) {
+      FftPlans p;
+      hipfftResult r = hipfftPlan3d(&p.fwd, lay.K[0], lay.K[1], lay.K[2], HIPFFT_D2Z);
+      if (r != HIPFFT_SUCCESS) {
+        *err = std::string("hipfftPlan3d (D2Z): ") + fft_error(r);
+        return hipErrorUnknown;
+      }
+      r = hipfftPlan3d(&p.inv, lay.K[0], lay.K[1], lay.K[2], HIPFFT_Z2D);
+      if (r != HIPFFT_SUCCESS) {
+        hipfftDestroy(p.fwd);
+        *err = std::string("hipfftPlan3d (Z2D): ") + fft_error(r);
+        return hipErrorUnknown;
+      }
+      it = g_fft.emplace(key, p).first;
+    }
+    plans = it->second;
+  }
+  const bool f64 = sys->pos_is_f64 != 0;
+  for (int b = 0; b < lay.B; ++b) {
+    const int64_t a0 = sys->atom_offset[b], n = sys->atom_offset[b + 1] - a0;
+    PmeSys ps;
+    for (int a = 0; a < 3; ++a) {
+      ps.L[a] = sys->box[3 * b + a];
+      ps.K[a] = lay.K[a];
+    }
+    ps.H = lay.K[2] / 2 + 1;
+    double *g = real + b * lay.grid;
+    double2 *c = cplx + b * lay.spec;
+    const dim3 ga(static_cast<unsigned>((n + kBlock - 1) / kBlock)), blk(kBlock);
+    if (n > 0) {
+      if (f64)
+        hipLaunchKernelGGL(k_pme_spread<double>, ga, blk, 0, s, static_cast<const double *>(sys->pos) + 3 * a0,
+                           static_cast<const double *>(sys->charge) + a0, static_cast<int>(n), ps, g);
+      else
+        hipLaunchKernelGGL(k_pme_spread<float>, ga, blk, 0, s, static_cast<const float *>(sys->pos) + 3 * a0,
+                           static_cast<const float *>(sys->charge) + a0, static_cast<int>(n), ps, g);
+    }
+    {
+      std::lock_guard<std::mutex> lock(g_fft_mu);
+      hipfftResult r = hipfftSetStream(plans.fwd, s);
+      if (r == HIPFFT_SUCCESS) r = hipfftExecD2Z(plans.fwd, g, reinterpret_cast<hipfftDoubleComplex *>(c));
+      if (r != HIPFFT_SUCCESS) {
+        *err = std::string("hipfftExecD2Z: ") + fft_error(r);
+        return hipErrorUnknown;
+      }
+    }
+    hipLaunchKernelGGL(k_pme_convolve, dim3(static_cast<unsigned>(lay.conv_blocks)), blk, 0, s, c, ps, lay.spec, beta,
+                       ke, partials + b * kPart * lay.conv_blocks, lay.conv_blocks);
+    {
+      std::lock_guard<std::mutex> lock(g_fft_mu);
+      hipfftResult r = hipfftSetStream(plans.inv, s);
+      if (r == HIPFFT_SUCCESS) r = hipfftExecZ2D(plans.inv, reinterpret_cast<hipfftDoubleComplex *>(c), g);
+      if (r != HIPFFT_SUCCESS) {
+        *err = std::string("hipfftExecZ2D: ") + fft_error(r);
+        return hipErrorUnknown;
+      }
+    }
+    if (n > 0) {
+      if (f64)
+        hipLaunchKernelGGL(k_pme_gather<double>, ga, blk, 0, s, static_cast<const double *>(sys->pos) + 3 * a0,
+                           static_cast<const double *>(sys->charge) + a0, static_cast<int>(n), ps, g, force + 3 * a0);
+      else
+        hipLaunchKernelGGL(k_pme_gather<float>, ga, blk, 0, s, static_cast<const float *>(sys->pos) + 3 * a0,
+                           static_cast<const float *>(sys->charge) + a0, static_cast<int>(n), ps, g, force + 3 * a0);
+    }
+  }
+  if (energy || virial)
+    hipLaunchKernelGGL(k_pme_reduce, dim3(static_cast<unsigned>(lay.B)), dim3(kBlock), 0, s, partials,
+                       lay.conv_blocks, energy, virial);
+  return hipGetLastError();
+}
+
+}  // namespace nb

@@ -39,7 +39,8 @@ NB_MAX_TYPES = 64
 
 EXPORTED = ("nb_workspace_bytes", "nb_build_cells", "nb_nonbonded_forces", "nb_nonbonded_energy",
             "nb_nonbonded_backward", "nb_read_status", "nb_last_error", "nb_workspace_layout",
-            "nb_pair_timer_start", "nb_pair_timer_stop", "nb_ewald_corrections")
+            "nb_pair_timer_start", "nb_pair_timer_stop", "nb_ewald_corrections",
+            "nb_pme_workspace_bytes", "nb_pme_reciprocal")
 
 
 class NbError(RuntimeError):
@@ -116,6 +117,9 @@ def load_library(path: str = LIB_PATH):
     lib.nb_nonbonded_energy.argtypes = [S, P, V, sz, V, V, V]
     lib.nb_nonbonded_backward.argtypes = [S, P, V, sz, V, V, V, V, V, V]
     lib.nb_ewald_corrections.argtypes = [S, P, V, sz, V, V, V, V]
+    G = ctypes.POINTER(ctypes.c_int32)
+    lib.nb_pme_workspace_bytes.argtypes = [S, G, ctypes.POINTER(ctypes.c_size_t)]
+    lib.nb_pme_reciprocal.argtypes = [S, P, G, V, sz, V, V, V, V]
     lib.nb_read_status.argtypes = [V, V, ctypes.POINTER(ctypes.c_uint32)]
     lib.nb_workspace_layout.argtypes = [S, P, ctypes.POINTER(nb_layout)]
     lib.nb_pair_timer_start.argtypes = [ctypes.c_int32]
@@ -259,6 +263,35 @@ def ewald_corrections(batch: DeviceBatch, params: nb_params, ws, force, energy=N
     lib = load_library()
     _check(lib.nb_ewald_corrections(ctypes.byref(batch.struct()), ctypes.byref(params), _ptr(ws), ws.numel(),
                                     _ptr(force), _ptr(energy), _ptr(virial), _stream(stream)))
+
+
+def _grid(grid):
+    g = (ctypes.c_int32 * 3)(*[int(k) for k in grid])
+    return ctypes.cast(g, ctypes.POINTER(ctypes.c_int32)), g
+
+
+def pme_workspace_bytes(batch: DeviceBatch, grid) -> int:
+    lib = load_library()
+    n = ctypes.c_size_t()
+    gp, _keep = _grid(grid)
+    _check(lib.nb_pme_workspace_bytes(ctypes.byref(batch.struct()), gp, ctypes.byref(n)))
+    return int(n.value)
+
+
+def alloc_pme_workspace(batch: DeviceBatch, grid):
+    """A uint8 cuda tensor for nb_pme_reciprocal on this batch and grid."""
+    import torch
+    ws = torch.empty(max(pme_workspace_bytes(batch, grid), 1), dtype=torch.uint8, device=batch.pos.device)
+    assert ws.data_ptr() % 256 == 0
+    return ws
+
+
+def pme_reciprocal(batch: DeviceBatch, params: nb_params, grid, ws, force, energy=None, virial=None, stream=None):
+    """Reciprocal part of the Ewald sum by smooth PME on a K1 x K2 x K3 grid (nb_pme_reciprocal)."""
+    lib = load_library()
+    gp, _keep = _grid(grid)
+    _check(lib.nb_pme_reciprocal(ctypes.byref(batch.struct()), ctypes.byref(params), gp, _ptr(ws), ws.numel(),
+                                 _ptr(force), _ptr(energy), _ptr(virial), _stream(stream)))
 
 
 def nonbonded_energy(batch: DeviceBatch, params: nb_params, ws, energy, atom_energy=None, stream=None):

@@ -165,3 +165,33 @@ def test_pair_timer_argument_checks():
     ms, n = ctypes.c_double(), ctypes.c_int64()
     assert lib.nb_pair_timer_stop(ctypes.byref(ms), ctypes.byref(n)) == H.NB_ERR_ARG  # never started
     assert "not started" in H.last_error()
+
+
+def test_pme_workspace_and_argument_checks():
+    lib = H.load_library()
+    s = fake_system((648, 100))
+    p = H.make_params(9.0, 0.34)
+    G = ctypes.c_int32 * 3
+    n = ctypes.c_size_t()
+    P = lambda g: ctypes.cast(g, ctypes.POINTER(ctypes.c_int32))
+    # two systems, each a real grid, its half spectrum and its convolution partials (10 per 256 elements)
+    assert lib.nb_pme_workspace_bytes(ctypes.byref(s), P(G(32, 30, 27)), ctypes.byref(n)) == H.NB_OK
+    spec = 32 * 30 * (27 // 2 + 1)
+    up = lambda x: (x + 255) // 256 * 256
+    assert n.value == up(2 * 8 * 32 * 30 * 27) + up(2 * 16 * spec) + up(2 * 8 * 10 * ((spec + 255) // 256))
+    need = n.value
+    for bad in [(3, 32, 32), (32, 0, 32), (32, 32, 1025)]:
+        assert lib.nb_pme_workspace_bytes(ctypes.byref(s), P(G(*bad)), ctypes.byref(n)) == H.NB_ERR_ARG
+        assert "grid" in H.last_error()
+    g = P(G(32, 30, 27))
+    assert lib.nb_pme_reciprocal(ctypes.byref(s), ctypes.byref(p), g, FAKE, need - 1, FAKE, None, None, None) \
+        == H.NB_ERR_WORKSPACE
+    assert lib.nb_pme_reciprocal(ctypes.byref(s), ctypes.byref(p), g, FAKE + 8, need, FAKE, None, None, None) \
+        == H.NB_ERR_WORKSPACE
+    assert lib.nb_pme_reciprocal(ctypes.byref(s), ctypes.byref(p), g, FAKE, need, None, None, None, None) \
+        == H.NB_ERR_ARG  # force is required
+    assert lib.nb_pme_reciprocal(ctypes.byref(s), ctypes.byref(p), P(G(2, 30, 27)), FAKE, need, FAKE, None, None,
+                                 None) == H.NB_ERR_ARG
+    p0 = H.make_params(9.0, 0.0)
+    assert lib.nb_pme_reciprocal(ctypes.byref(s), ctypes.byref(p0), g, FAKE, need, FAKE, None, None, None) \
+        == H.NB_ERR_ARG and "beta" in H.last_error()

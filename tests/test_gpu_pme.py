@@ -1,0 +1,145 @@
+"""GPU parity of the reciprocal part of the Ewald sum (nb_pme_reciprocal, through the C
+ABI) against the FP64 SPME oracle on the same grid: odd and even grid sizes, non-cubic
+boxes, FP32 and FP64 inputs, batches of systems with different boxes, and the whole
+Ewald sum (real-space pair term + corrections + reciprocal part) against the Madelung
+constant of rock salt.
+
+Every step is FP64, so the bar is 1e-12 relative RMS on forces and 1e-12 relative on
+energies (1e-11 on virials); the FFTs and the atomic grid additions reorder roundings.
+"""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import nbtest_util as U
+from oracle import pme as PO
+from paper_0902_0827_amd import nbhip as H
+from paper_0902_0827_amd import systems as S
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+FORCE_TOL = 1e-12
+ENERGY_TOL = 1e-12
+VIRIAL_TOL = 1e-11
+MADELUNG_NACL = 1.747564594633
+
+
+def _print_case(name, **kw):
+    print(f"[case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def noncubic():
+    """500 waters with the box stretched to 20 x 22 x 24 A (positions wrap into it)."""
+    s = S.water_box(500, 20.0, seed=13)
+    return dataclasses.replace(s, box=np.array([20.0, 22.0, 24.0]))
+
+
+def rock_salt(cells=4, a=5.64):
+    fcc = np.array([[0, 0, 0], [0, .5, .5], [.5, 0, .5], [.5, .5, 0]])
+    pos, q = [], []
+    for o in np.ndindex(cells, cells, cells):
+        for b in fcc:
+            pos.append((np.array(o) + b) * a)
+            q.append(1.0)
+            pos.append(((np.array(o) + b + [0.5, 0, 0]) % cells) * a)
+            q.append(-1.0)
+    n = len(q)
+    return S.System(name="rock_salt", pos=np.array(pos), charge=np.array(q), type=np.zeros(n, np.int32),
+                    sigma=np.ones(1), eps=np.zeros(1), excl_offset=np.zeros(n + 1, np.int32),
+                    excl_index=np.zeros(0, np.int32), box=np.full(3, cells * a), cutoff=11.0, beta=0.45, seed=0)
+
+
+def gpu_pme(systems, precision, grid):
+    systems = systems if isinstance(systems, list) else [systems]
+    dt = torch.float64 if precision == H.NB_FP64 else torch.float32
+    b = H.device_batch(systems, dtype=dt)
+    s0 = systems[0]
+    p = H.make_params(s0.cutoff, s0.beta, precision)
+    ws = H.alloc_pme_workspace(b, grid)
+    force = torch.full((b.n_atoms, 3), 7.0, dtype=torch.float64, device="cuda")
+    energy = torch.full((b.n_systems,), 7.0, dtype=torch.float64, device="cuda")
+    vir = torch.full((b.n_systems, 3, 3), 7.0, dtype=torch.float64, device="cuda")
+    H.pme_reciprocal(b, p, grid, ws, force, energy, vir)
+    torch.cuda.synchronize()
+    return force.cpu().numpy(), energy.cpu().numpy(), vir.cpu().numpy()
+
+
+def check(force, energy, vir, ref):
+    err = U.rel_rms(force, ref["force"])
+    e_err = abs(energy - ref["energy"]) / abs(ref["energy"])
+    v_err = np.linalg.norm(vir - ref["virial"]) / np.linalg.norm(ref["virial"])
+    print(f"  force rel_rms={err:.3e} energy={energy:.12e} oracle={ref['energy']:.12e} virial={v_err:.3e}")
+    assert err <= FORCE_TOL
+    assert e_err <= ENERGY_TOL
+    assert v_err <= VIRIAL_TOL
+
+
+CASES = {
+    "noncubic_odd_grid": (noncubic, (20, 25, 27)),
+    "cfg1_even_grid": (lambda: U.cached_config(1), (20, 20, 20)),
+    "cfg1_grid_4": (lambda: U.cached_config(1), (4, 5, 6)),
+    "workload_64": (lambda: U.cached_config(2), (64, 64, 64)),
+}
+
+
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+@pytest.mark.parametrize("which", list(CASES))
+def test_reciprocal_matches_oracle(which, precision):
+    make, grid = CASES[which]
+    s = make()
+    _print_case("pme", which=which, precision=precision, n=s.n, grid=grid)
+    force, energy, vir = gpu_pme(s, precision, grid)
+    r = U.rounded(s, precision)
+    ref = PO.spme_reciprocal(r.pos, r.charge, r.box, r.beta, grid)
+    check(force, energy[0], vir[0], ref)
+
+
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+def test_batch_with_different_boxes(precision):
+    systems = [U.cached_config(1), noncubic(), S.water_box(300, 21.0, seed=17)]
+    grid = (24, 24, 30)
+    _print_case("pme-batch", precision=precision, grid=grid)
+    force, energy, vir = gpu_pme(systems, precision, grid)
+    a0 = 0
+    for b, s in enumerate(systems):
+        r = U.rounded(s, precision)
+        ref = PO.spme_reciprocal(r.pos, r.charge, r.box, r.beta, grid)
+        check(force[a0:a0 + s.n], energy[b], vir[b], ref)
+        a0 += s.n
+
+
+def test_repeatable_to_rounding():
+    s = U.cached_config(1)
+    f1, e1, v1 = gpu_pme(s, H.NB_FP64, (20, 20, 20))
+    f2, e2, v2 = gpu_pme(s, H.NB_FP64, (20, 20, 20))
+    np.testing.assert_allclose(f1, f2, rtol=0, atol=1e-13 * np.abs(f1).max())
+    assert abs(e1[0] - e2[0]) <= 1e-13 * abs(e1[0])
+
+
+def test_whole_ewald_sum_gives_the_madelung_constant():
+    """Real-space pair term (nb_nonbonded_forces) + self term (nb_ewald_corrections) +
+    reciprocal part (nb_pme_reciprocal) of a 512-ion rock-salt crystal, FP64 path."""
+    s = rock_salt()
+    _print_case("madelung", n=s.n)
+    out = U.gpu_eval(s, H.NB_FP64)  # build + real-space forces and energy
+    b, p, ws = out["batch"], out["params"], out["ws"]
+    assert out["status"] == 0
+    f_corr = torch.zeros((s.n, 3), dtype=torch.float64, device="cuda")
+    e_corr = torch.zeros(1, dtype=torch.float64, device="cuda")
+    H.ewald_corrections(b, p, ws, f_corr, e_corr)
+    pws = H.alloc_pme_workspace(b, (48, 48, 48))
+    f_rec = torch.zeros((s.n, 3), dtype=torch.float64, device="cuda")
+    e_rec = torch.zeros(1, dtype=torch.float64, device="cuda")
+    H.pme_reciprocal(b, p, (48, 48, 48), pws, f_rec, e_rec)
+    torch.cuda.synchronize()
+    e = float(out["energy"][0] + e_corr.cpu()[0] + e_rec.cpu()[0])
+    madelung = -e / (s.n / 2) * (5.64 / 2) / H.COULOMB_K
+    print(f"  Madelung constant {madelung:.13f}")
+    assert abs(madelung - MADELUNG_NACL) < 1e-9
+    # every ion of the perfect crystal is at a centre of symmetry: no net force
+    total = out["force"] + (f_corr + f_rec).cpu().numpy()
+    assert np.abs(total).max() < 1e-8
