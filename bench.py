@@ -122,6 +122,41 @@ def ewald_rate(b, p, ws, prec_name, steps, torch, H):
             "force": force.cpu().numpy(), "energy": energy.cpu().numpy(), "virial": vir.cpu().numpy()}
 
 
+# The reciprocal part (nb_pme_reciprocal) on the paper's 64^3 grid.  Algorithmic HBM bytes
+# per call: per atom position and charge read twice (spread, gather; FP32 16, FP64 32) and
+# the FP64 force written (24); per grid point the real grid cleared, spread and read by
+# the forward FFT (8 + 8), the half spectrum written, read and written by the convolution
+# and read by the inverse FFT (4 x 8), and the potential written and read by the gather
+# (8 + 8): 64 bytes.
+PME_GRID = (64, 64, 64)
+PME_BYTES_PER_ATOM = {"mixed": 2 * 16 + 24, "fp64": 2 * 32 + 24}
+PME_BYTES_PER_POINT = 64
+
+
+def pme_rate(b, p, prec_name, steps, torch, H, grid=PME_GRID):
+    """nb_pme_reciprocal: its outputs and mean microseconds per call (all launches, HIP
+    events around the loop), with the algorithmic HBM rate."""
+    ws = H.alloc_pme_workspace(b, grid)
+    force = torch.empty((b.n_atoms, 3), dtype=torch.float64, device="cuda")
+    energy = torch.empty(b.n_systems, dtype=torch.float64, device="cuda")
+    vir = torch.empty((b.n_systems, 3, 3), dtype=torch.float64, device="cuda")
+    for _ in range(5):
+        H.pme_reciprocal(b, p, grid, ws, force, energy, vir)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        H.pme_reciprocal(b, p, grid, ws, force, energy, vir)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / steps
+    points = int(np.prod(grid)) * b.n_systems
+    nbytes = PME_BYTES_PER_ATOM[prec_name] * b.n_atoms + PME_BYTES_PER_POINT * points
+    return {"us_per_call": us, "bytes": int(nbytes), "achieved": nbytes / us * 1e-3,
+            "frac": nbytes / us * 1e-3 / HBM_PEAK_GBPS, "calls": steps, "grid": list(grid),
+            "force": force.cpu().numpy(), "energy": energy.cpu().numpy(), "virial": vir.cpu().numpy()}
+
+
 PAIR_SOURCES = ("nb_pair_cluster.hip", "nb_pair_math.h", "nb_pair_common.h", "nb_internal.h")
 
 
@@ -314,8 +349,10 @@ def main():
         log(f"[bench] {prec_name} adjoint: {t_adj['sec'] * 1e3:.4f} ms/step, pair kernel {t_adj['pair_sec'] * 1e6:.1f} us")
         ewald = ewald_rate(b, p, ws, prec_name, steps, torch, H)
         log(f"[bench] {prec_name} Ewald corrections: {ewald['us_per_call']:.2f} us per call")
+        pme = pme_rate(b, p, prec_name, steps, torch, H)
+        log(f"[bench] {prec_name} PME reciprocal {PME_GRID}: {pme['us_per_call']:.2f} us per call")
         results[prec_name] = dict(t, steps=steps, force=force.cpu().numpy(), energy=float(energy.cpu()[0]),
-                                  status=H.read_status(ws), build=build, adjoint=adjoint, ewald=ewald)
+                                  status=H.read_status(ws), build=build, adjoint=adjoint, ewald=ewald, pme=pme)
         log(f"[bench] {prec_name}: {t['sec'] * 1e3:.4f} ms/step (median {t['median'] * 1e3:.4f}), "
             f"pair kernel {t['pair_sec'] * 1e6:.1f} us over {t['pair_launches']} launches")
 
@@ -326,7 +363,9 @@ def main():
     t_cpu = []
     reps = 0
     t_start = time.perf_counter()
+    from oracle import pme as PO
     ref_ew, t_ew = {}, []
+    ref_pme, t_pme = {}, []
     for prec_name, sys_in in (("mixed", s.rounded(np.float32)), ("fp64", s))[:len(paths)]:
         t0 = time.perf_counter()
         ref[prec_name] = O.evaluate_system(sys_in, ke=H.COULOMB_K)
@@ -335,6 +374,9 @@ def main():
         t0 = time.perf_counter()
         ref_ew[prec_name] = O.ewald_corrections_system(sys_in, ke=H.COULOMB_K)
         t_ew.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        ref_pme[prec_name] = PO.spme_reciprocal_system(sys_in, PME_GRID, ke=H.COULOMB_K)
+        t_pme.append(time.perf_counter() - t0)
     if not args.no_cpu_baseline:
         # bounded sample: repeat full evaluations until ~10 s of wall time have been spent
         while time.perf_counter() - t_start < 10.0 and reps < 8:
@@ -369,6 +411,12 @@ def main():
                 "energy_err_rel_to_terms": abs(float(ew["energy"][0]) - r["energy_total"]) /
                                           (abs(r["e_excl"]) + abs(r["e_self"])),
                 "rel_virial": float(np.linalg.norm(ew["virial"][0] - r["virial"]) / np.linalg.norm(r["virial"]))}
+    def pme_entry(pm, r):
+        return {"us_per_call": pm["us_per_call"], "calls": pm["calls"], "bytes_per_call": pm["bytes"],
+                "achieved": pm["achieved"], "frac": pm["frac"],
+                "rel_rms_force": rel_errors(pm["force"], r["force"])[0],
+                "energy_rel": abs(float(pm["energy"][0]) - r["energy"]) / abs(r["energy"]),
+                "rel_virial": float(np.linalg.norm(pm["virial"][0] - r["virial"]) / np.linalg.norm(r["virial"]))}
     achieved = pairs * FLOPS_PER_PAIR / m["pair_sec"] / 1e12
     default_kernel = args.kernel == "auto" and args.split == 0 and args.cluster_size == 0 and \
         args.cell_div == "0,0" and args.schedule == "auto" and args.wg_per_cu == 0
@@ -419,6 +467,14 @@ def main():
                               "box": {name: ewald_entry(results[name]["ewald"], ref_ew[name]) for name in results},
                               "oracle_ms": float(np.median(t_ew)) * 1e3,
                               "batch": None if batch is None else batch.get("ewald")},
+        # nb_pme_reciprocal (smooth PME, order 4) on the 64^3 grid: algorithmic HBM bytes
+        # per call over its time (all launches, FFTs included), errors against the SPME
+        # oracle on the same grid, and the oracle's own time (NumPy)
+        "pme_reciprocal": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBPS, "grid": list(PME_GRID),
+                           "order": 4, "bytes_per_atom": PME_BYTES_PER_ATOM,
+                           "bytes_per_grid_point": PME_BYTES_PER_POINT,
+                           "box": {name: pme_entry(results[name]["pme"], ref_pme[name]) for name in results},
+                           "oracle_ms": float(np.median(t_pme)) * 1e3},
         "status_bits": [r["status"] for r in results.values()],
     }
     print(json.dumps(out), flush=True)
