@@ -15,12 +15,12 @@
 //
 // All arithmetic is FP64 (positions and charges of either precision are promoted).
 // Per system, in order on the caller's stream:
-//   k_pme_spread   one thread per atom, 64 FP64 atomic additions into the grid;
+//   k_pme_spread   16 lanes per atom, 4 FP64 atomic additions into the grid each;
 //   D2Z FFT        (hipFFT, a plan per grid shape and device, made on first use);
 //   k_pme_convolve one thread per element of the half spectrum: C(m), the energy and
 //                  virial terms (per-block partials) and the product C FFT(Q);
 //   Z2D FFT        giving phi on the real grid;
-//   k_pme_gather   one thread per atom: its force from phi and the spline derivatives.
+//   k_pme_gather   16 lanes per atom: its force from phi and the spline derivatives.
 // k_pme_reduce then sums each system's partials in a fixed order.  The grid additions
 // of the spread are the only ones whose order varies from run to run.
 #include <hipfft/hipfft.h>
@@ -85,24 +85,26 @@ __global__ void __launch_bounds__(kBlock) k_pme_zero(double *__restrict__ g, int
     g[e] = 0.0;
 }
 
+// 16 lanes per atom, one per (x, y) row of its 4 x 4 x 4 footprint: each lane adds the
+// row's four z points.  Lane t of the grid takes atom t / 16 and row (t / 4 % 4, t % 4).
+constexpr int kLanesPerAtom = 16;
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_pme_spread(const T *__restrict__ pos, const T *__restrict__ charge, int n,
                                                        PmeSys ps, double *__restrict__ grid) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int64_t t = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
+  const int i = static_cast<int>(t / kLanesPerAtom);
   if (i >= n) return;
+  const int a = static_cast<int>(t >> 2) & 3, b = static_cast<int>(t) & 3;
   int ix[4], iy[4], iz[4];
   double wx[4], wy[4], wz[4], d[4];
   spline4(static_cast<double>(pos[3 * i + 0]), ps.L[0], ps.K[0], ix, wx, d);
   spline4(static_cast<double>(pos[3 * i + 1]), ps.L[1], ps.K[1], iy, wy, d);
   spline4(static_cast<double>(pos[3 * i + 2]), ps.L[2], ps.K[2], iz, wz, d);
-  const double q = static_cast<double>(charge[i]);
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) {
-      const double qab = q * wx[a] * wy[b];
-      double *row = grid + (static_cast<int64_t>(ix[a]) * ps.K[1] + iy[b]) * ps.K[2];
+  const double qab = static_cast<double>(charge[i]) * wx[a] * wy[b];
+  double *row = grid + (static_cast<int64_t>(ix[a]) * ps.K[1] + iy[b]) * ps.K[2];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) unsafeAtomicAdd(&row[iz[c]], qab * wz[c]);
-    }
+  for (int c = 0; c < 4; ++c) unsafeAtomicAdd(&row[iz[c]], qab * wz[c]);
 }
 
 // Signed reciprocal index of grid index i: i for i <= K/2, else i - K.
@@ -174,33 +176,42 @@ __global__ void __launch_bounds__(kBlock) k_pme_convolve(double2 *__restrict__ s
   }
 }
 
+// 16 lanes per atom as in the spread; the row sums meet by shuffles within the 16.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_pme_gather(const T *__restrict__ pos, const T *__restrict__ charge, int n,
                                                        PmeSys ps, const double *__restrict__ phi,
                                                        double *__restrict__ force) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+  const int64_t t = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
+  const int i_raw = static_cast<int>(t / kLanesPerAtom);
+  const bool valid = i_raw < n;
+  const int i = valid ? i_raw : n - 1;  // lanes past the end still join the shuffles
+  const int a = static_cast<int>(t >> 2) & 3, b = static_cast<int>(t) & 3;
   int ix[4], iy[4], iz[4];
   double wx[4], wy[4], wz[4], dx[4], dy[4], dz[4];
   spline4(static_cast<double>(pos[3 * i + 0]), ps.L[0], ps.K[0], ix, wx, dx);
   spline4(static_cast<double>(pos[3 * i + 1]), ps.L[1], ps.K[1], iy, wy, dy);
   spline4(static_cast<double>(pos[3 * i + 2]), ps.L[2], ps.K[2], iz, wz, dz);
-  double gx = 0.0, gy = 0.0, gz = 0.0;  // sum_k phi(k) dQ(k)/du / q
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) {
-      const double *row = phi + (static_cast<int64_t>(ix[a]) * ps.K[1] + iy[b]) * ps.K[2];
+  const double *row = phi + (static_cast<int64_t>(ix[a]) * ps.K[1] + iy[b]) * ps.K[2];
+  double sz = 0.0, sdz = 0.0;  // sum_c phi wz[c] and sum_c phi dz[c] along the row
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const double p = row[iz[c]];
-        gx += p * dx[a] * wy[b] * wz[c];
-        gy += p * wx[a] * dy[b] * wz[c];
-        gz += p * wx[a] * wy[b] * dz[c];
-      }
-    }
-  const double q = static_cast<double>(charge[i]);
-  force[3 * static_cast<int64_t>(i) + 0] = -q * gx * (ps.K[0] / ps.L[0]);
-  force[3 * static_cast<int64_t>(i) + 1] = -q * gy * (ps.K[1] / ps.L[1]);
-  force[3 * static_cast<int64_t>(i) + 2] = -q * gz * (ps.K[2] / ps.L[2]);
+  for (int c = 0; c < 4; ++c) {
+    const double p = row[iz[c]];
+    sz += p * wz[c];
+    sdz += p * dz[c];
+  }
+  double gx = dx[a] * wy[b] * sz, gy = wx[a] * dy[b] * sz, gz = wx[a] * wy[b] * sdz;
+#pragma unroll
+  for (int off = kLanesPerAtom / 2; off > 0; off >>= 1) {
+    gx += __shfl_xor(gx, off, kLanesPerAtom);
+    gy += __shfl_xor(gy, off, kLanesPerAtom);
+    gz += __shfl_xor(gz, off, kLanesPerAtom);
+  }
+  if (valid && (t & (kLanesPerAtom - 1)) == 0) {
+    const double q = static_cast<double>(charge[i]);
+    force[3 * static_cast<int64_t>(i) + 0] = -q * gx * (ps.K[0] / ps.L[0]);
+    force[3 * static_cast<int64_t>(i) + 1] = -q * gy * (ps.K[1] / ps.L[1]);
+    force[3 * static_cast<int64_t>(i) + 2] = -q * gz * (ps.K[2] / ps.L[2]);
+  }
 }
 
 // Energy and virial of system blockIdx.x: its convolution partials in block order.
@@ -286,11 +297,10 @@ hipError_t launch_pme(const PmeLayout &lay, const nb_system *sys, double beta, d
   double *real = reinterpret_cast<double *>(base + lay.real);
   double2 *cplx = reinterpret_cast<double2 *>(base + lay.cplx);
   double *partials = reinterpret_cast<double *>(base + lay.partials);
-  {
-    const int64_t n = lay.grid * lay.B;
-    const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 65536);
-    hipLaunchKernelGGL(k_pme_zero, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, real, n);
-  }
+  auto stride_blocks = [](int64_t n) {
+    return dim3(static_cast<unsigned>(std::min<int64_t>((n + kBlock - 1) / kBlock, 65536)));
+  };
+  hipLaunchKernelGGL(k_pme_zero, stride_blocks(lay.grid * lay.B), dim3(kBlock), 0, s, real, lay.grid * lay.B);
   FftPlans plans;
   {
     std::lock_guard<std::mutex> lock(g_fft_mu);
@@ -324,7 +334,7 @@ hipError_t launch_pme(const PmeLayout &lay, const nb_system *sys, double beta, d
     ps.H = lay.K[2] / 2 + 1;
     double *g = real + b * lay.grid;
     double2 *c = cplx + b * lay.spec;
-    const dim3 ga(static_cast<unsigned>((n + kBlock - 1) / kBlock)), blk(kBlock);
+    const dim3 ga(static_cast<unsigned>((n * kLanesPerAtom + kBlock - 1) / kBlock)), blk(kBlock);
     if (n > 0) {
       if (f64)
         hipLaunchKernelGGL(k_pme_spread<double>, ga, blk, 0, s, static_cast<const double *>(sys->pos) + 3 * a0,
