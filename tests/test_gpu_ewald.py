@@ -118,3 +118,30 @@ def test_repeatable_and_beta_zero(chain_far):
     z.beta = 0.0
     fz, ez, vz, st = gpu_ewald(z, H.NB_FP64)
     assert np.all(fz == 0.0) and ez[0] == 0.0 and np.all(vz == 0.0) and (st & ~H.NB_STATUS_FAR_EXCLUSION) == 0
+
+
+def _two_and_empty():
+    two = S.System(name="two", pos=np.array([[1.0, 1.0, 1.0], [2.0, 1.5, 1.2]]), charge=np.array([0.5, -0.7]),
+                   type=np.array([0, 0], np.int32), sigma=np.array([3.0]), eps=np.array([0.4]),
+                   excl_offset=np.array([0, 1, 1], np.int32), excl_index=np.array([1], np.int32),
+                   box=np.array([20.0, 21.0, 22.0]), cutoff=9.0, beta=0.3, seed=0)
+    empty = S.System(name="empty", pos=np.zeros((0, 3)), charge=np.zeros(0), type=np.zeros(0, np.int32),
+                     sigma=np.array([3.0]), eps=np.array([0.4]), excl_offset=np.zeros(1, np.int32),
+                     excl_index=np.zeros(0, np.int32), box=np.array([20.0, 20.0, 20.0]), cutoff=9.0,
+                     beta=0.3, seed=0)
+    return two, empty
+
+
+def test_tiny_and_empty_systems():
+    """A two-atom system with one exclusion (listed in one row), an empty system between
+    two copies of it: the empty one gets exactly zero energy and virial."""
+    two, empty = _two_and_empty()
+    _print_case("ewald-tiny-empty")
+    force, energy, vir, status = gpu_ewald([two, empty, two], H.NB_FP64)
+    ref = O.ewald_corrections_system(two, ke=H.COULOMB_K)
+    for sl, b in ((slice(0, 2), 0), (slice(2, 4), 2)):
+        np.testing.assert_allclose(force[sl], ref["force"], rtol=1e-13, atol=1e-13)
+        assert abs(energy[b] - ref["energy_total"]) <= SUM_TOL * energy_scale(ref)
+        np.testing.assert_allclose(vir[b], ref["virial"], rtol=1e-12, atol=1e-12 * np.abs(ref["virial"]).max())
+    assert energy[1] == 0.0 and not vir[1].any()
+    assert status == 0

@@ -143,3 +143,23 @@ def test_whole_ewald_sum_gives_the_madelung_constant():
     # every ion of the perfect crystal is at a centre of symmetry: no net force
     total = out["force"] + (f_corr + f_rec).cpu().numpy()
     assert np.abs(total).max() < 1e-8
+
+
+def test_tiny_and_empty_systems():
+    """Two charges, an empty system between two copies of them, on a 16^3 grid: the empty
+    system gets exactly zero energy and virial."""
+    two = S.System(name="two", pos=np.array([[1.0, 1.0, 1.0], [4.0, 1.0, 1.5]]), charge=np.array([0.5, -0.5]),
+                   type=np.array([0, 0], np.int32), sigma=np.array([3.0]), eps=np.array([0.4]),
+                   excl_offset=np.zeros(3, np.int32), excl_index=np.zeros(0, np.int32),
+                   box=np.array([20.0, 21.0, 22.0]), cutoff=9.0, beta=0.3, seed=0)
+    empty = S.System(name="empty", pos=np.zeros((0, 3)), charge=np.zeros(0), type=np.zeros(0, np.int32),
+                     sigma=np.array([3.0]), eps=np.array([0.4]), excl_offset=np.zeros(1, np.int32),
+                     excl_index=np.zeros(0, np.int32), box=np.array([20.0, 21.0, 22.0]), cutoff=9.0,
+                     beta=0.3, seed=0)
+    _print_case("pme-tiny-empty")
+    grid = (16, 16, 16)
+    force, energy, vir = gpu_pme([two, empty, two], H.NB_FP64, grid)
+    ref = PO.spme_reciprocal(two.pos, two.charge, two.box, two.beta, grid)
+    check(force[0:2], energy[0], vir[0], ref)
+    check(force[2:4], energy[2], vir[2], ref)
+    assert energy[1] == 0.0 and not vir[1].any()
