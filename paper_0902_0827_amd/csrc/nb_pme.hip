@@ -15,14 +15,17 @@
 //
 // All arithmetic is FP64 (positions and charges of either precision are promoted).
 // Per system, in order on the caller's stream:
-//   k_pme_spread   16 lanes per atom, 4 FP64 atomic additions into the grid each;
+//   k_pme_spread_planes  one workgroup per x-plane, the plane accumulated in LDS (planes
+//                  of up to 8192 points); else k_pme_zero and k_pme_spread, 16 lanes per
+//                  atom with 4 FP64 atomic additions into the grid each;
 //   D2Z FFT        (hipFFT, a plan per grid shape and device, made on first use);
 //   k_pme_convolve one thread per element of the half spectrum: C(m), the energy and
 //                  virial terms (per-block partials) and the product C FFT(Q);
 //   Z2D FFT        giving phi on the real grid;
 //   k_pme_gather   16 lanes per atom: its force from phi and the spline derivatives.
 // k_pme_reduce then sums each system's partials in a fixed order.  The grid additions
-// of the spread are the only ones whose order varies from run to run.
+// of the spread (LDS or global atomics) are the only ones whose order varies from run
+// to run.
 #include <hipfft/hipfft.h>
 
 #include <algorithm>
@@ -44,16 +47,16 @@ constexpr int kMaxGrid = 1024;
 
 struct PmeSys {
   double L[3];
+  double invL[3];
   int K[3];
   int H;  // K3/2 + 1: the half spectrum's last dimension
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-// The four grid points k = base - j (mod K), j = 0..3, of coordinate x, with M_4(u - k)
-// and dM_4/du at u - k = t + j, t = u - base in [0, 1).
-__device__ inline void spline4(double x, double L, int K, int idx[4], double w[4], double dw[4]) {
-  double f = x / L;
+// Grid cell of coordinate x: u = K (x/L mod 1), base = floor(u) in [0, K), t = u - base.
+__device__ inline void grid_cell(double x, double invL, int K, int *base_out, double *t_out) {
+  double f = x * invL;
   f -= floor(f);  // in [0, 1] for finite x
   const double u = f * K;
   int base = 0;
@@ -66,6 +69,16 @@ __device__ inline void spline4(double x, double L, int K, int idx[4], double w[4
   } else {  // non-finite coordinate: indices stay in range, the results are NaN
     t = u - u;
   }
+  *base_out = base;
+  *t_out = t;
+}
+
+// The four grid points k = base - j (mod K), j = 0..3, of coordinate x, with M_4(u - k)
+// and dM_4/du at u - k = t + j, t = u - base in [0, 1).
+__device__ inline void spline4(double x, double invL, int K, int idx[4], double w[4], double dw[4]) {
+  int base;
+  double t;
+  grid_cell(x, invL, K, &base, &t);
   const double t2 = t * t, t3 = t2 * t, s = 1.0 - t;
   w[0] = t3 * (1.0 / 6.0);
   w[1] = (1.0 + 3.0 * t + 3.0 * t2 - 3.0 * t3) * (1.0 / 6.0);
@@ -98,13 +111,56 @@ __global__ void __launch_bounds__(kBlock) k_pme_spread(const T *__restrict__ pos
   const int a = static_cast<int>(t >> 2) & 3, b = static_cast<int>(t) & 3;
   int ix[4], iy[4], iz[4];
   double wx[4], wy[4], wz[4], d[4];
-  spline4(static_cast<double>(pos[3 * i + 0]), ps.L[0], ps.K[0], ix, wx, d);
-  spline4(static_cast<double>(pos[3 * i + 1]), ps.L[1], ps.K[1], iy, wy, d);
-  spline4(static_cast<double>(pos[3 * i + 2]), ps.L[2], ps.K[2], iz, wz, d);
+  spline4(static_cast<double>(pos[3 * i + 0]), ps.invL[0], ps.K[0], ix, wx, d);
+  spline4(static_cast<double>(pos[3 * i + 1]), ps.invL[1], ps.K[1], iy, wy, d);
+  spline4(static_cast<double>(pos[3 * i + 2]), ps.invL[2], ps.K[2], iz, wz, d);
   const double qab = static_cast<double>(charge[i]) * wx[a] * wy[b];
   double *row = grid + (static_cast<int64_t>(ix[a]) * ps.K[1] + iy[b]) * ps.K[2];
 #pragma unroll
   for (int c = 0; c < 4; ++c) unsafeAtomicAdd(&row[iz[c]], qab * wz[c]);
+}
+
+// One workgroup per x-plane of the grid: it reads every atom, keeps those whose
+// footprint covers its plane (four planes per atom) and adds their 4 x 4 (y, z) points
+// with LDS atomics into the plane held in LDS, then stores the plane.  No global
+// atomics and no clearing pass.  Used when a plane fits in kPlaneMaxPoints doubles.
+constexpr int kPlaneBlock = 1024;
+constexpr int kPlaneMaxPoints = 8192;  // 64 KB of LDS
+
+template <typename T>
+__global__ void __launch_bounds__(kPlaneBlock) k_pme_spread_planes(const T *__restrict__ pos,
+                                                                   const T *__restrict__ charge, int n, PmeSys ps,
+                                                                   double *__restrict__ grid) {
+  extern __shared__ double plane[];
+  const int x = blockIdx.x;
+  const int P = ps.K[1] * ps.K[2];
+  for (int j = threadIdx.x; j < P; j += kPlaneBlock) plane[j] = 0.0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kPlaneBlock) {
+    int bx;
+    double tx;
+    grid_cell(static_cast<double>(pos[3 * i + 0]), ps.invL[0], ps.K[0], &bx, &tx);
+    int a = bx - x;  // the atom covers plane x as its point base - a (mod K), a in [0, 4)
+    if (a < 0) a += ps.K[0];
+    if (a >= 4) continue;
+    const double s = 1.0 - tx;
+    const double wa = a == 0 ? tx * tx * tx * (1.0 / 6.0)
+                    : a == 1 ? (1.0 + 3.0 * tx + 3.0 * tx * tx - 3.0 * tx * tx * tx) * (1.0 / 6.0)
+                    : a == 2 ? (4.0 - 6.0 * tx * tx + 3.0 * tx * tx * tx) * (1.0 / 6.0)
+                             : s * s * s * (1.0 / 6.0);
+    int iy[4], iz[4];
+    double wy[4], wz[4], d[4];
+    spline4(static_cast<double>(pos[3 * i + 1]), ps.invL[1], ps.K[1], iy, wy, d);
+    spline4(static_cast<double>(pos[3 * i + 2]), ps.invL[2], ps.K[2], iz, wz, d);
+    const double qa = static_cast<double>(charge[i]) * wa;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) unsafeAtomicAdd(&plane[iy[b] * ps.K[2] + iz[c]], qa * wy[b] * wz[c]);
+  }
+  __syncthreads();
+  double *out = grid + static_cast<int64_t>(x) * P;
+  for (int j = threadIdx.x; j < P; j += kPlaneBlock) out[j] = plane[j];
 }
 
 // Signed reciprocal index of grid index i: i for i <= K/2, else i - K.
@@ -188,9 +244,9 @@ __global__ void __launch_bounds__(kBlock) k_pme_gather(const T *__restrict__ pos
   const int a = static_cast<int>(t >> 2) & 3, b = static_cast<int>(t) & 3;
   int ix[4], iy[4], iz[4];
   double wx[4], wy[4], wz[4], dx[4], dy[4], dz[4];
-  spline4(static_cast<double>(pos[3 * i + 0]), ps.L[0], ps.K[0], ix, wx, dx);
-  spline4(static_cast<double>(pos[3 * i + 1]), ps.L[1], ps.K[1], iy, wy, dy);
-  spline4(static_cast<double>(pos[3 * i + 2]), ps.L[2], ps.K[2], iz, wz, dz);
+  spline4(static_cast<double>(pos[3 * i + 0]), ps.invL[0], ps.K[0], ix, wx, dx);
+  spline4(static_cast<double>(pos[3 * i + 1]), ps.invL[1], ps.K[1], iy, wy, dy);
+  spline4(static_cast<double>(pos[3 * i + 2]), ps.invL[2], ps.K[2], iz, wz, dz);
   const double *row = phi + (static_cast<int64_t>(ix[a]) * ps.K[1] + iy[b]) * ps.K[2];
   double sz = 0.0, sdz = 0.0;  // sum_c phi wz[c] and sum_c phi dz[c] along the row
 #pragma unroll
@@ -300,7 +356,10 @@ hipError_t launch_pme(const PmeLayout &lay, const nb_system *sys, double beta, d
   auto stride_blocks = [](int64_t n) {
     return dim3(static_cast<unsigned>(std::min<int64_t>((n + kBlock - 1) / kBlock, 65536)));
   };
-  hipLaunchKernelGGL(k_pme_zero, stride_blocks(lay.grid * lay.B), dim3(kBlock), 0, s, real, lay.grid * lay.B);
+  const int64_t plane_points = static_cast<int64_t>(lay.K[1]) * lay.K[2];
+  const bool planes = plane_points <= kPlaneMaxPoints;
+  if (!planes)
+    hipLaunchKernelGGL(k_pme_zero, stride_blocks(lay.grid * lay.B), dim3(kBlock), 0, s, real, lay.grid * lay.B);
   FftPlans plans;
   {
     std::lock_guard<std::mutex> lock(g_fft_mu);
@@ -329,13 +388,23 @@ hipError_t launch_pme(const PmeLayout &lay, const nb_system *sys, double beta, d
     PmeSys ps;
     for (int a = 0; a < 3; ++a) {
       ps.L[a] = sys->box[3 * b + a];
+      ps.invL[a] = 1.0 / ps.L[a];
       ps.K[a] = lay.K[a];
     }
     ps.H = lay.K[2] / 2 + 1;
     double *g = real + b * lay.grid;
     double2 *c = cplx + b * lay.spec;
     const dim3 ga(static_cast<unsigned>((n * kLanesPerAtom + kBlock - 1) / kBlock)), blk(kBlock);
-    if (n > 0) {
+    if (planes) {
+      const dim3 gp(static_cast<unsigned>(lay.K[0])), bp(kPlaneBlock);
+      const size_t lds = sizeof(double) * static_cast<size_t>(plane_points);
+      if (f64)
+        hipLaunchKernelGGL(k_pme_spread_planes<double>, gp, bp, lds, s, static_cast<const double *>(sys->pos) + 3 * a0,
+                           static_cast<const double *>(sys->charge) + a0, static_cast<int>(n), ps, g);
+      else
+        hipLaunchKernelGGL(k_pme_spread_planes<float>, gp, bp, lds, s, static_cast<const float *>(sys->pos) + 3 * a0,
+                           static_cast<const float *>(sys->charge) + a0, static_cast<int>(n), ps, g);
+    } else if (n > 0) {
       if (f64)
         hipLaunchKernelGGL(k_pme_spread<double>, ga, blk, 0, s, static_cast<const double *>(sys->pos) + 3 * a0,
                            static_cast<const double *>(sys->charge) + a0, static_cast<int>(n), ps, g);

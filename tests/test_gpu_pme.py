@@ -83,6 +83,8 @@ CASES = {
     "cfg1_even_grid": (lambda: U.cached_config(1), (20, 20, 20)),
     "cfg1_grid_4": (lambda: U.cached_config(1), (4, 5, 6)),
     "workload_64": (lambda: U.cached_config(2), (64, 64, 64)),
+    # y-z planes of more than 8192 points: the spread by global atomics instead of LDS planes
+    "cfg1_large_planes": (lambda: U.cached_config(1), (8, 96, 96)),
 }
 
 
