@@ -124,10 +124,10 @@ def ewald_rate(b, p, ws, prec_name, steps, torch, H):
 
 # The reciprocal part (nb_pme_reciprocal) on the paper's 64^3 grid.  Algorithmic HBM bytes
 # per call: per atom position and charge read twice (spread, gather; FP32 16, FP64 32) and
-# the FP64 force written (24); per grid point the real grid cleared, spread and read by
-# the forward FFT (8 + 8), the half spectrum written, read and written by the convolution
-# and read by the inverse FFT (4 x 8), and the potential written and read by the gather
-# (8 + 8): 64 bytes.
+# the FP64 force written (24); per grid point the charge grid written by the spread and
+# read by the forward FFT (8 + 8), the half spectrum written, read and written by the
+# convolution and read by the inverse FFT (4 x 8), and the potential written and read by
+# the gather (8 + 8): 64 bytes.
 PME_GRID = (64, 64, 64)
 PME_BYTES_PER_ATOM = {"mixed": 2 * 16 + 24, "fp64": 2 * 32 + 24}
 PME_BYTES_PER_POINT = 64
