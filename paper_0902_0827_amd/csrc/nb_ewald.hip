@@ -50,9 +50,10 @@ __device__ inline double3 min_image(double3 xi, double3 xj, const SysDesc &sd) {
 __device__ inline void excl_pair(double kqq, double r2, double beta, double *u, double *g) {
   if (r2 > 0.0) {
     const double r = sqrt(r2);
+    const double inv_r = 1.0 / r;  // the one division
     const double e = erf(beta * r);
-    *u = -kqq * e / r;
-    *g = kqq * (beta * kTwoOverSqrtPi * exp(-beta * beta * r2) / r2 - e / (r2 * r));
+    *u = -kqq * e * inv_r;
+    *g = kqq * inv_r * inv_r * (beta * kTwoOverSqrtPi * exp(-beta * beta * r2) - e * inv_r);
   } else {
     *u = -kqq * beta * kTwoOverSqrtPi;
     *g = 0.0;
