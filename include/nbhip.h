@@ -193,9 +193,11 @@ nb_status nb_ewald_corrections(const nb_system *sys, const nb_params *params, vo
  * build.  The grid additions of the charge spreading are FP64 atomics, so results may
  * vary in the last bits from run to run.  The FFTs use hipFFT plans made on the first
  * call for a grid shape on a device and kept until the process ends (they hold the FFT
- * library's own device buffers); calls for one grid shape from several host threads at
- * once are serialised while they enqueue.  Returns NB_ERR_HIP if the FFT library
- * refuses a plan or a transform. */
+ * library's own device buffers).  Calls for one grid shape on one device share these
+ * plans and their work buffers: enqueueing from several host threads is serialised, but
+ * calls on different streams must not run on the GPU at the same time (order them on
+ * one stream, or with events).  Returns NB_ERR_HIP if the FFT library refuses a plan or
+ * a transform. */
 nb_status nb_pme_workspace_bytes(const nb_system *sys, const int32_t grid[3] /*[host]*/, size_t *bytes /*[host]*/);
 nb_status nb_pme_reciprocal(const nb_system *sys, const nb_params *params, const int32_t grid[3] /*[host]*/,
                             void *workspace, size_t workspace_bytes, double *force, double *energy,

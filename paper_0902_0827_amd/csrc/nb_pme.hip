@@ -303,7 +303,8 @@ __global__ void __launch_bounds__(kBlock) k_pme_reduce(const double *__restrict_
 
 // FFT plans, one forward (D2Z) and one inverse (Z2D) per grid shape and device, made on
 // first use and kept for the life of the process.  The mutex also covers setting a
-// plan's stream and enqueueing its transform.
+// plan's stream and enqueueing its transform; transforms of one plan on different
+// streams would share its work buffer, so callers keep such calls ordered.
 struct FftPlans {
   hipfftHandle fwd = nullptr, inv = nullptr;
 };
