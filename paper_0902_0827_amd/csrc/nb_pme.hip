@@ -48,6 +48,8 @@ constexpr int kMaxGrid = 1024;
 struct PmeSys {
   double L[3];
   double invL[3];
+  double a;       // pi^2 / beta^2
+  double escale;  // k_e / (2 pi V)
   int K[3];
   int H;  // K3/2 + 1: the half spectrum's last dimension
 };
@@ -166,15 +168,14 @@ __global__ void __launch_bounds__(kPlaneBlock) k_pme_spread_planes(const T *__re
 // Signed reciprocal index of grid index i: i for i <= K/2, else i - K.
 __device__ inline int signed_index(int i, int K) { return 2 * i <= K ? i : i - K; }
 
-// 9 / (2 + cos(2 pi i / K))^2
-__device__ inline double bmod2(int i, int K) {
+// (2 + cos(2 pi i / K))^2 / 9: the reciprocal of the order-4 spline factor |b(m)|^2
+__device__ inline double inv_bmod2(int i, int K) {
   const double c = 2.0 + cospi(2.0 * static_cast<double>(i) / static_cast<double>(K));
-  return 9.0 / (c * c);
+  return c * c * (1.0 / 9.0);
 }
 
 __global__ void __launch_bounds__(kBlock) k_pme_convolve(double2 *__restrict__ spec, PmeSys ps, int64_t n_spec,
-                                                         double beta, double ke, double *__restrict__ partials,
-                                                         int64_t n_part_blocks) {
+                                                         double *__restrict__ partials, int64_t n_part_blocks) {
   __shared__ double red[kWaves][kPart];
   const int64_t e = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
   double v[kPart] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -183,24 +184,24 @@ __global__ void __launch_bounds__(kBlock) k_pme_convolve(double2 *__restrict__ s
     const int64_t r = e / ps.H;
     const int iy = static_cast<int>(r % ps.K[1]);
     const int ix = static_cast<int>(r / ps.K[1]);
-    const double m[3] = {signed_index(ix, ps.K[0]) / ps.L[0], signed_index(iy, ps.K[1]) / ps.L[1],
-                         signed_index(iz, ps.K[2]) / ps.L[2]};
+    const double m[3] = {signed_index(ix, ps.K[0]) * ps.invL[0], signed_index(iy, ps.K[1]) * ps.invL[1],
+                         signed_index(iz, ps.K[2]) * ps.invL[2]};
     const double m2 = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
     double2 F = spec[e];
     if (m2 > 0.0) {
-      const double V = ps.L[0] * ps.L[1] * ps.L[2];
-      const double a = kPi * kPi / (beta * beta);
-      const double C = exp(-a * m2) / m2 * bmod2(ix, ps.K[0]) * bmod2(iy, ps.K[1]) * bmod2(iz, ps.K[2]);
-      const double em = ke / (2.0 * kPi * V) * C * (F.x * F.x + F.y * F.y);
-      const double vf = 2.0 * (1.0 + a * m2) / m2;
+      const double inv_m2 = 1.0 / m2;
+      const double C =
+          exp(-ps.a * m2) * inv_m2 / (inv_bmod2(ix, ps.K[0]) * inv_bmod2(iy, ps.K[1]) * inv_bmod2(iz, ps.K[2]));
+      const double em = ps.escale * C * (F.x * F.x + F.y * F.y);
+      const double vf = 2.0 * (1.0 + ps.a * m2) * inv_m2;
       // The half spectrum holds each element and its conjugate partner (K - i mod K per
       // dimension) once, except in the planes iz = 0 and iz = K3/2, whose partners are
       // elements of their own.  The partner has the same |F|^2 and m^2; its signed
       // indices are -m except on a Nyquist index K/2, which stays +K/2.
       const bool pair = !(iz == 0 || 2 * iz == ps.K[2]);
       const int jx = ix == 0 ? 0 : ps.K[0] - ix, jy = iy == 0 ? 0 : ps.K[1] - iy;
-      const double mp[3] = {signed_index(jx, ps.K[0]) / ps.L[0], signed_index(jy, ps.K[1]) / ps.L[1],
-                            signed_index(ps.K[2] - iz, ps.K[2]) / ps.L[2]};
+      const double mp[3] = {signed_index(jx, ps.K[0]) * ps.invL[0], signed_index(jy, ps.K[1]) * ps.invL[1],
+                            signed_index(ps.K[2] - iz, ps.K[2]) * ps.invL[2]};
       v[0] = pair ? 2.0 * em : em;
 #pragma unroll
       for (int p = 0; p < 3; ++p)
@@ -209,7 +210,7 @@ __global__ void __launch_bounds__(kBlock) k_pme_convolve(double2 *__restrict__ s
           const double d = p == q ? 1.0 : 0.0;
           v[1 + 3 * p + q] = em * (d - vf * m[p] * m[q]) + (pair ? em * (d - vf * mp[p] * mp[q]) : 0.0);
         }
-      const double sc = C * ke / (kPi * V);
+      const double sc = 2.0 * ps.escale * C;  // k_e / (pi V) C
       F.x *= sc;
       F.y *= sc;
     } else {
@@ -393,6 +394,8 @@ hipError_t launch_pme(const PmeLayout &lay, const nb_system *sys, double beta, d
       ps.K[a] = lay.K[a];
     }
     ps.H = lay.K[2] / 2 + 1;
+    ps.a = kPi * kPi / (beta * beta);
+    ps.escale = ke / (2.0 * kPi * ps.L[0] * ps.L[1] * ps.L[2]);
     double *g = real + b * lay.grid;
     double2 *c = cplx + b * lay.spec;
     const dim3 ga(static_cast<unsigned>((n * kLanesPerAtom + kBlock - 1) / kBlock)), blk(kBlock);
@@ -422,8 +425,8 @@ hipError_t launch_pme(const PmeLayout &lay, const nb_system *sys, double beta, d
         return hipErrorUnknown;
       }
     }
-    hipLaunchKernelGGL(k_pme_convolve, dim3(static_cast<unsigned>(lay.conv_blocks)), blk, 0, s, c, ps, lay.spec, beta,
-                       ke, partials + b * kPart * lay.conv_blocks, lay.conv_blocks);
+    hipLaunchKernelGGL(k_pme_convolve, dim3(static_cast<unsigned>(lay.conv_blocks)), blk, 0, s, c, ps, lay.spec,
+                       partials + b * kPart * lay.conv_blocks, lay.conv_blocks);
     {
       std::lock_guard<std::mutex> lock(g_fft_mu);
       hipfftResult r = hipfftSetStream(plans.inv, s);
