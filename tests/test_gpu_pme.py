@@ -78,6 +78,15 @@ def check(force, energy, vir, ref):
     assert v_err <= VIRIAL_TOL
 
 
+def outside_box():
+    """The 648-atom box with atoms moved by whole box lengths, up to three either way."""
+    s = U.cached_config(1)
+    shift = np.zeros_like(s.pos)
+    shift[::2] = s.box * np.array([2, -3, 1])
+    shift[1::5] = -s.box * np.array([1, 1, 3])
+    return dataclasses.replace(s, pos=s.pos + shift)
+
+
 CASES = {
     "noncubic_odd_grid": (noncubic, (20, 25, 27)),
     "cfg1_even_grid": (lambda: U.cached_config(1), (20, 20, 20)),
@@ -85,6 +94,7 @@ CASES = {
     "workload_64": (lambda: U.cached_config(2), (64, 64, 64)),
     # y-z planes of more than 8192 points: the spread by global atomics instead of LDS planes
     "cfg1_large_planes": (lambda: U.cached_config(1), (8, 96, 96)),
+    "cfg1_outside_box": (outside_box, (20, 20, 20)),
 }
 
 
