@@ -44,6 +44,17 @@ def chain_far():
     return with_far_one_sided(U.small_chain())
 
 
+def outside_box():
+    """The 648-atom box with atoms moved by whole box lengths, up to three either way."""
+    s = U.cached_config(1)
+    shift = np.zeros_like(s.pos)
+    shift[::2] = s.box * np.array([2, -3, 1])
+    shift[1::5] = -s.box * np.array([1, 1, 3])
+    t = S.System(**{**s.__dict__})
+    t.pos = s.pos + shift
+    return t
+
+
 def energy_scale(ref):
     """The total is the small difference of the excluded-pair and self sums (water: tens of
     thousands each, a thousand apart), so its FP64 rounding is relative to their size."""
@@ -63,9 +74,10 @@ def gpu_ewald(systems, precision, kernel=H.NB_KERNEL_AUTO):
 
 @pytest.mark.parametrize("kernel", [H.NB_KERNEL_AUTO, H.NB_KERNEL_ATOM])
 @pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
-@pytest.mark.parametrize("which", ["chain_far", "cfg1", "cfg2"])
+@pytest.mark.parametrize("which", ["chain_far", "cfg1", "cfg2", "cfg1_outside_box"])
 def test_corrections_match_oracle(which, precision, kernel, chain_far):
-    s = {"chain_far": lambda: chain_far, "cfg1": lambda: U.cached_config(1), "cfg2": lambda: U.cached_config(2)}[which]()
+    s = {"chain_far": lambda: chain_far, "cfg1": lambda: U.cached_config(1), "cfg2": lambda: U.cached_config(2),
+         "cfg1_outside_box": outside_box}[which]()
     _print_case("ewald", which=which, precision=precision, kernel=kernel, n=s.n)
     force, energy, vir, status = gpu_ewald(s, precision, kernel=kernel)
     ref = O.ewald_corrections_system(U.rounded(s, precision), ke=H.COULOMB_K)
