@@ -14,14 +14,15 @@
 // denominator 1/6 + (2/3) e^{it} + (1/6) e^{2it} has modulus (2 + cos t)/3.
 //
 // All arithmetic is FP64 (positions and charges of either precision are promoted).
-// Per system, in order on the caller's stream:
+// In order on the caller's stream, each kernel launched per system:
 //   k_pme_spread_planes  one workgroup per x-plane, the plane accumulated in LDS (planes
 //                  of up to 8192 points); else k_pme_zero and k_pme_spread, 16 lanes per
 //                  atom with 4 FP64 atomic additions into the grid each;
-//   D2Z FFT        (hipFFT, a plan per grid shape and device, made on first use);
+//   D2Z FFT        (hipFFT, one batched call for all systems; a plan per grid shape,
+//                  batch size and device, made on first use);
 //   k_pme_convolve one thread per element of the half spectrum: C(m), the energy and
 //                  virial terms (per-block partials) and the product C FFT(Q);
-//   Z2D FFT        giving phi on the real grid;
+//   Z2D FFT        giving phi on the real grid (one batched call);
 //   k_pme_gather   16 lanes per atom: its force from phi and the spline derivatives.
 // k_pme_reduce then sums each system's partials in a fixed order.  The grid additions
 // of the spread (LDS or global atomics) are the only ones whose order varies from run
@@ -302,15 +303,16 @@ __global__ void __launch_bounds__(kBlock) k_pme_reduce(const double *__restrict_
   }
 }
 
-// FFT plans, one forward (D2Z) and one inverse (Z2D) per grid shape and device, made on
-// first use and kept for the life of the process.  The mutex also covers setting a
+// FFT plans, one forward (D2Z) and one inverse (Z2D) per grid shape, batch size and
+// device, each transforming the B systems' grids (contiguous, one after the other) in
+// one call; made on first use and kept for the life of the process.  The mutex also covers setting a
 // plan's stream and enqueueing its transform; transforms of one plan on different
 // streams would share its work buffer, so callers keep such calls ordered.
 struct FftPlans {
   hipfftHandle fwd = nullptr, inv = nullptr;
 };
 std::mutex g_fft_mu;
-std::map<std::tuple<int, int, int, int>, FftPlans> g_fft;
+std::map<std::tuple<int, int, int, int, int>, FftPlans> g_fft;
 
 const char *fft_error(hipfftResult r) {
   switch (r) {
@@ -365,19 +367,26 @@ hipError_t launch_pme(const PmeLayout &lay, const nb_system *sys, double beta, d
   FftPlans plans;
   {
     std::lock_guard<std::mutex> lock(g_fft_mu);
-    auto key = std::make_tuple(dev, lay.K[0], lay.K[1], lay.K[2]);
+    auto key = std::make_tuple(dev, lay.K[0], lay.K[1], lay.K[2], lay.B);
     auto it = g_fft.find(key);
     if (it == g_fft.end()) {
       FftPlans p;
-      hipfftResult r = hipfftPlan3d(&p.fwd, lay.K[0], lay.K[1], lay.K[2], HIPFFT_D2Z);
+      int dims[3] = {lay.K[0], lay.K[1], lay.K[2]};
+      // contiguous grids, unit stride: K1 K2 K3 reals and K1 K2 (K3/2+1) complex values
+      // per system, one system after the other
+      int real_embed[3] = {lay.K[0], lay.K[1], lay.K[2]};
+      int spec_embed[3] = {lay.K[0], lay.K[1], lay.K[2] / 2 + 1};
+      const int grid_dist = static_cast<int>(lay.grid), spec_dist = static_cast<int>(lay.spec);
+      hipfftResult r = hipfftPlanMany(&p.fwd, 3, dims, real_embed, 1, grid_dist, spec_embed, 1, spec_dist,
+                                      HIPFFT_D2Z, lay.B);
       if (r != HIPFFT_SUCCESS) {
-        *err = std::string("hipfftPlan3d (D2Z): ") + fft_error(r);
+        *err = std::string("hipfftPlanMany (D2Z): ") + fft_error(r);
         return hipErrorUnknown;
       }
-      r = hipfftPlan3d(&p.inv, lay.K[0], lay.K[1], lay.K[2], HIPFFT_Z2D);
+      r = hipfftPlanMany(&p.inv, 3, dims, spec_embed, 1, spec_dist, real_embed, 1, grid_dist, HIPFFT_Z2D, lay.B);
       if (r != HIPFFT_SUCCESS) {
         hipfftDestroy(p.fwd);
-        *err = std::string("hipfftPlan3d (Z2D): ") + fft_error(r);
+        *err = std::string("hipfftPlanMany (Z2D): ") + fft_error(r);
         return hipErrorUnknown;
       }
       it = g_fft.emplace(key, p).first;
@@ -385,7 +394,8 @@ hipError_t launch_pme(const PmeLayout &lay, const nb_system *sys, double beta, d
     plans = it->second;
   }
   const bool f64 = sys->pos_is_f64 != 0;
-  for (int b = 0; b < lay.B; ++b) {
+  // the parameters and grids of system b
+  auto system = [&](int b, int64_t *a0_out, int64_t *n_out, PmeSys *ps_out) {
     const int64_t a0 = sys->atom_offset[b], n = sys->atom_offset[b + 1] - a0;
     PmeSys ps;
     for (int a = 0; a < 3; ++a) {
@@ -396,9 +406,17 @@ hipError_t launch_pme(const PmeLayout &lay, const nb_system *sys, double beta, d
     ps.H = lay.K[2] / 2 + 1;
     ps.a = kPi * kPi / (beta * beta);
     ps.escale = ke / (2.0 * kPi * ps.L[0] * ps.L[1] * ps.L[2]);
+    *a0_out = a0;
+    *n_out = n;
+    *ps_out = ps;
+  };
+  const dim3 blk(kBlock);
+  for (int b = 0; b < lay.B; ++b) {  // charge grids
+    int64_t a0, n;
+    PmeSys ps;
+    system(b, &a0, &n, &ps);
     double *g = real + b * lay.grid;
-    double2 *c = cplx + b * lay.spec;
-    const dim3 ga(static_cast<unsigned>((n * kLanesPerAtom + kBlock - 1) / kBlock)), blk(kBlock);
+    const dim3 ga(static_cast<unsigned>((n * kLanesPerAtom + kBlock - 1) / kBlock));
     if (planes) {
       const dim3 gp(static_cast<unsigned>(lay.K[0])), bp(kPlaneBlock);
       const size_t lds = sizeof(double) * static_cast<size_t>(plane_points);
@@ -416,26 +434,39 @@ hipError_t launch_pme(const PmeLayout &lay, const nb_system *sys, double beta, d
         hipLaunchKernelGGL(k_pme_spread<float>, ga, blk, 0, s, static_cast<const float *>(sys->pos) + 3 * a0,
                            static_cast<const float *>(sys->charge) + a0, static_cast<int>(n), ps, g);
     }
-    {
-      std::lock_guard<std::mutex> lock(g_fft_mu);
-      hipfftResult r = hipfftSetStream(plans.fwd, s);
-      if (r == HIPFFT_SUCCESS) r = hipfftExecD2Z(plans.fwd, g, reinterpret_cast<hipfftDoubleComplex *>(c));
-      if (r != HIPFFT_SUCCESS) {
-        *err = std::string("hipfftExecD2Z: ") + fft_error(r);
-        return hipErrorUnknown;
-      }
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_fft_mu);
+    hipfftResult r = hipfftSetStream(plans.fwd, s);
+    if (r == HIPFFT_SUCCESS) r = hipfftExecD2Z(plans.fwd, real, reinterpret_cast<hipfftDoubleComplex *>(cplx));
+    if (r != HIPFFT_SUCCESS) {
+      *err = std::string("hipfftExecD2Z: ") + fft_error(r);
+      return hipErrorUnknown;
     }
+  }
+  for (int b = 0; b < lay.B; ++b) {  // convolution, energy and virial partials
+    int64_t a0, n;
+    PmeSys ps;
+    system(b, &a0, &n, &ps);
+    double2 *c = cplx + b * lay.spec;
     hipLaunchKernelGGL(k_pme_convolve, dim3(static_cast<unsigned>(lay.conv_blocks)), blk, 0, s, c, ps, lay.spec,
                        partials + b * kPart * lay.conv_blocks, lay.conv_blocks);
-    {
-      std::lock_guard<std::mutex> lock(g_fft_mu);
-      hipfftResult r = hipfftSetStream(plans.inv, s);
-      if (r == HIPFFT_SUCCESS) r = hipfftExecZ2D(plans.inv, reinterpret_cast<hipfftDoubleComplex *>(c), g);
-      if (r != HIPFFT_SUCCESS) {
-        *err = std::string("hipfftExecZ2D: ") + fft_error(r);
-        return hipErrorUnknown;
-      }
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_fft_mu);
+    hipfftResult r = hipfftSetStream(plans.inv, s);
+    if (r == HIPFFT_SUCCESS) r = hipfftExecZ2D(plans.inv, reinterpret_cast<hipfftDoubleComplex *>(cplx), real);
+    if (r != HIPFFT_SUCCESS) {
+      *err = std::string("hipfftExecZ2D: ") + fft_error(r);
+      return hipErrorUnknown;
     }
+  }
+  for (int b = 0; b < lay.B; ++b) {  // forces from the potential grids
+    int64_t a0, n;
+    PmeSys ps;
+    system(b, &a0, &n, &ps);
+    double *g = real + b * lay.grid;
+    const dim3 ga(static_cast<unsigned>((n * kLanesPerAtom + kBlock - 1) / kBlock));
     if (n > 0) {
       if (f64)
         hipLaunchKernelGGL(k_pme_gather<double>, ga, blk, 0, s, static_cast<const double *>(sys->pos) + 3 * a0,
