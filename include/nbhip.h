@@ -191,10 +191,11 @@ nb_status nb_ewald_corrections(const nb_system *sys, const nb_params *params, vo
  * the other calls.  `workspace` is its own buffer (not the nonbonded workspace) of
  * nb_pme_workspace_bytes bytes, 256-byte aligned, owned by the caller; it needs no
  * build.  The grid additions of the charge spreading are FP64 atomics, so results may
- * vary in the last bits from run to run.  The FFTs use hipFFT plans made on the first
- * call for a grid shape on a device and kept until the process ends (they hold the FFT
- * library's own device buffers).  Calls for one grid shape on one device share these
- * plans and their work buffers: enqueueing from several host threads is serialised, but
+ * vary in the last bits from run to run.  The FFTs use hipFFT plans (each transforming
+ * every system of the batch in one call) made on the first call for a grid shape and
+ * batch size on a device and kept until the process ends (they hold the FFT library's
+ * own device buffers).  Calls for one grid shape and batch size on one device share
+ * these plans and their work buffers: enqueueing from several host threads is serialised, but
  * calls on different streams must not run on the GPU at the same time (order them on
  * one stream, or with events).  Returns NB_ERR_HIP if the FFT library refuses a plan or
  * a transform. */
