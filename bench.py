@@ -158,7 +158,7 @@ def pme_rate(b, p, prec_name, steps, torch, H, grid=PME_GRID):
             "force": force.cpu().numpy(), "energy": energy.cpu().numpy(), "virial": vir.cpu().numpy()}
 
 
-PAIR_SOURCES = ("nb_pair_cluster.hip", "nb_pair_math.h", "nb_pair_common.h", "nb_internal.h")
+PAIR_SOURCES = ("nb_pair_cluster.h", "nb_pair_cluster_f32.hip", "nb_pair_math.h", "nb_pair_common.h", "nb_internal.h")
 
 
 def measured_traffic(profile):

@@ -16,9 +16,13 @@
  *
  * Conventions for every entry point:
  *   - Pointers marked [device] are HIP device pointers; [host] are host pointers.
- *   - The caller owns every buffer.  The library allocates no device memory and
- *     keeps no device state between calls; all of its scratch lives in the
- *     caller's workspace (size from nb_workspace_bytes).
+ *   - The caller owns every buffer.  The library allocates no device memory for
+ *     its kernels: all of their scratch lives in the caller's workspace (size from
+ *     nb_workspace_bytes or nb_pme_workspace_bytes).  The one device state kept
+ *     between calls is the FFT library's plans of the reciprocal part (their
+ *     read-only tables, made by nb_pme_workspace_bytes or nb_pme_reciprocal on first
+ *     use of a grid shape and batch size on a device, at most 32 per process, kept
+ *     until the process ends).
  *   - Every call only enqueues work on `stream` and returns; the only call that
  *     synchronises is nb_read_status.
  *   - Problems visible on the host are reported by the return code before any
@@ -46,7 +50,9 @@ typedef enum {
   NB_ERR_BOX = 2,        /* a box length <= 0 or not finite, or R >= min(L)/2 */
   NB_ERR_WORKSPACE = 3,  /* workspace NULL, misaligned or smaller than nb_workspace_bytes */
   NB_ERR_HIP = 4,        /* a HIP runtime call failed; see nb_last_error */
-  NB_ERR_CAPACITY = 5    /* a size exceeds what the 32-bit indexing of the library supports */
+  NB_ERR_CAPACITY = 5,   /* a size exceeds what the 32-bit indexing of the library supports */
+  NB_ERR_HOST = 6        /* a host-side failure (out of host memory, or an unexpected internal error):
+                            nothing was enqueued; see nb_last_error */
 } nb_status;
 
 /* Bits of the device status word (nb_read_status).  They accumulate from
@@ -108,7 +114,7 @@ typedef struct {
   double ewald_beta;  /* beta (1/A) >= 0; beta = 0 gives the bare truncated Coulomb term */
   double coulomb_k;   /* k_e (kJ mol^-1 A e^-2), 1389.35457644382 for CODATA 2018 */
   int32_t precision;  /* nb_precision */
-  int32_t cell_div_xy;/* cells per cutoff along x and y, 1..4 (0 = 2, the paper's R/2 bins) */
+  int32_t cell_div_xy;/* cells per cutoff along x and y, 1..3 (0 = 2, the paper's R/2 bins) */
   int32_t cell_div_z; /* cells per cutoff along z, 1..16 (0 = the kernel's default) */
   int32_t kernel;     /* NB_KERNEL_* */
   int32_t split;      /* cluster kernel: work items per cluster, each taking an equal share of
@@ -168,7 +174,8 @@ nb_status nb_nonbonded_backward(const nb_system *sys, const nb_params *params, v
  *   self term: -k_e beta/sqrt(pi) sum_i q_i^2 per system.
  * Writes (does not add to) force [device, N*3 doubles, caller's order: the forces of
  * the excluded-pair term], energy [device, B doubles: both terms, or NULL] and virial
- * [device, 9*B doubles: the excluded-pair term, row-major, or NULL].  FP64 arithmetic on
+ * [device, 9*B doubles: the excluded-pair term, row-major, or NULL]; force may be NULL only
+ * when the batch has no atoms (energies and virials are then zero).  FP64 arithmetic on
  * the caller's positions and charges (either precision).  Requires nb_build_cells on
  * this workspace with the same exclusion lists (it uses the exclusion windows of the
  * build).  A far pair (|i - j| > 64) named in one row only is added to the other atom
@@ -190,15 +197,16 @@ nb_status nb_ewald_corrections(const nb_system *sys, const nb_params *params, vo
  * precision); ewald_beta > 0 and coulomb_k come from params, which is validated as for
  * the other calls.  `workspace` is its own buffer (not the nonbonded workspace) of
  * nb_pme_workspace_bytes bytes, 256-byte aligned, owned by the caller; it needs no
- * build.  The grid additions of the charge spreading are FP64 atomics, so results may
- * vary in the last bits from run to run.  The FFTs use hipFFT plans (each transforming
- * every system of the batch in one call) made on the first call for a grid shape and
- * batch size on a device and kept until the process ends (they hold the FFT library's
- * own device buffers).  Calls for one grid shape and batch size on one device share
- * these plans and their work buffers: enqueueing from several host threads is serialised, but
- * calls on different streams must not run on the GPU at the same time (order them on
- * one stream, or with events).  Returns NB_ERR_HIP if the FFT library refuses a plan or
- * a transform. */
+ * build.  It holds the grids and the work area of the FFTs, so calls with different
+ * workspaces may run concurrently on different streams.  The LDS additions of the
+ * charge spreading are FP64 atomics, so results may vary in the last bits from run to
+ * run.  The FFTs use hipFFT plans (each transforming every system of the batch in one
+ * call) made on the first use of a grid shape and batch size on a device, by
+ * nb_pme_workspace_bytes (which therefore needs a current HIP device) or
+ * nb_pme_reciprocal, and kept until the process ends (only their read-only tables:
+ * they allocate no work buffers of their own); at most 32 such plans per process.
+ * Returns NB_ERR_HIP if the FFT library refuses a plan or a transform or the 32 are
+ * used up. */
 nb_status nb_pme_workspace_bytes(const nb_system *sys, const int32_t grid[3] /*[host]*/, size_t *bytes /*[host]*/);
 nb_status nb_pme_reciprocal(const nb_system *sys, const nb_params *params, const int32_t grid[3] /*[host]*/,
                             void *workspace, size_t workspace_bytes, double *force, double *energy,

@@ -2,12 +2,15 @@
 
     python -m paper_0902_0827_amd.build_lib
 
-Always recompiles.  Packed FP32 instructions are disabled (-packed-fp32-ops):
-hipcc's automatic v_pk_* FP32 forms are not used anywhere in this library.
+Always recompiles: every source to an object file in parallel (``_build/``, kept out
+of version control), then one link.  Packed FP32 instructions are disabled
+(-packed-fp32-ops): hipcc's automatic v_pk_* FP32 forms are not used anywhere in this
+library.
 """
 
 from __future__ import annotations
 
+import concurrent.futures as cf
 import os
 import subprocess
 import sys
@@ -17,17 +20,18 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnbhip.so")
+OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["nb_api.cpp", "nb_build.hip", "nb_pair.hip", "nb_pair_cluster.hip", "nb_ewald.hip", "nb_pme.hip"]
+SOURCES = ["nb_api.cpp", "nb_build.hip", "nb_pair.hip", "nb_pair_cluster_f32.hip", "nb_pair_cluster_f64.hip",
+           "nb_ewald.hip", "nb_pme.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-FLAGS = [
+CFLAGS = [
     f"--offload-arch={ARCH}",
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Wall",
     "-Wno-unused-result",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -37,15 +41,31 @@ FLAGS = [
 LIBS = ["-lhipfft"]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, *FLAGS, *[os.path.join(CSRC, s) for s in SOURCES], *LIBS, "-o", tmp]
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed to build libnbhip.so")
+        raise RuntimeError(f"hipcc failed on {src}")
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OBJDIR, exist_ok=True)
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    tmp = LIB + f".tmp{os.getpid()}"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, *LIBS, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed to link libnbhip.so")
     os.replace(tmp, LIB)
     return LIB
 

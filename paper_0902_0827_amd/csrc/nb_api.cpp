@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <string>
 
 #include "nb_internal.h"
@@ -47,7 +49,9 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   if (!(prm->ewald_beta >= 0.0) || !std::isfinite(prm->ewald_beta)) return fail(NB_ERR_ARG, "ewald_beta must be >= 0 and finite");
   if (!std::isfinite(prm->coulomb_k)) return fail(NB_ERR_ARG, "coulomb_k must be finite");
   if (prm->precision != NB_FP64 && prm->precision != NB_MIXED) return fail(NB_ERR_ARG, "unknown precision");
-  if (prm->cell_div_xy < 0 || prm->cell_div_xy > 4) return fail(NB_ERR_ARG, "cell_div_xy must be in [0, 4]");
+  // At most 3 cells per cutoff in x and y: the pair kernel's run table holds the runs of
+  // (2k+1)^2 <= 49 neighbour columns in one pass of its scan.
+  if (prm->cell_div_xy < 0 || prm->cell_div_xy > 3) return fail(NB_ERR_ARG, "cell_div_xy must be in [0, 3]");
   if (prm->cell_div_z < 0 || prm->cell_div_z > 16) return fail(NB_ERR_ARG, "cell_div_z must be in [0, 16]");
   if (prm->kernel < NB_KERNEL_AUTO || prm->kernel > NB_KERNEL_CLUSTER_HALF) return fail(NB_ERR_ARG, "unknown kernel variant");
   if (prm->split < 0 || prm->split > 8) return fail(NB_ERR_ARG, "split must be in [0, 8]");
@@ -227,188 +231,243 @@ nb_status hip_status(hipError_t e, const char *what) {
   return fail(NB_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Records a message without letting a second exception escape (the message itself may
+// fail to allocate, which leaves the previous one).
+nb_status fail_nothrow(nb_status code, const char *what, const char *why) noexcept {
+  try {
+    nb::set_error(std::string(what) + ": " + why);
+  } catch (...) {
+  }
+  return code;
+}
+
+// Runs the body of an entry point; no C++ exception crosses the C ABI.
+template <typename F>
+nb_status guarded(const char *what, F &&body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc &) {
+    return fail_nothrow(NB_ERR_HOST, what, "out of host memory");
+  } catch (const std::exception &e) {
+    return fail_nothrow(NB_ERR_HOST, what, e.what());
+  } catch (...) {
+    return fail_nothrow(NB_ERR_HOST, what, "unexpected exception");
+  }
+}
+
 }  // namespace
 
 extern "C" {
 
 nb_status nb_workspace_bytes(const nb_system *sys, const nb_params *params, size_t *bytes) {
-  if (!bytes) return fail(NB_ERR_ARG, "bytes is NULL");
-  nb::Plan p;
-  nb_status st = nb::make_plan(sys, params, &p);
-  if (st != NB_OK) return st;
-  *bytes = p.lay.total;
-  return NB_OK;
+  return guarded("nb_workspace_bytes", [&]() -> nb_status {
+    if (!bytes) return fail(NB_ERR_ARG, "bytes is NULL");
+    nb::Plan p;
+    nb_status st = nb::make_plan(sys, params, &p);
+    if (st != NB_OK) return st;
+    *bytes = p.lay.total;
+    return NB_OK;
+  });
 }
 
 nb_status nb_workspace_layout(const nb_system *sys, const nb_params *params, nb_layout *layout) {
-  if (!layout) return fail(NB_ERR_ARG, "layout is NULL");
-  nb::Plan p;
-  nb_status st = nb::make_plan(sys, params, &p);
-  if (st != NB_OK) return st;
-  layout->n_atoms = p.N;
-  layout->n_cells = p.n_cells;
-  for (int a = 0; a < 3; ++a) layout->dims[a] = p.desc[0].dims[a];
-  layout->off_cell_start = static_cast<int64_t>(p.lay.cell_start);
-  layout->off_sorted_fixed = static_cast<int64_t>(p.lay.s_fix);
-  layout->off_sorted_pos64 = static_cast<int64_t>(p.lay.s_pos64);
-  layout->off_excl_mask = static_cast<int64_t>(p.lay.excl_mask);
-  layout->off_status = static_cast<int64_t>(p.lay.status);
-  layout->n_columns = p.n_columns;
-  layout->n_clusters_max = p.n_clusters_max;
-  layout->off_col_clu_start = static_cast<int64_t>(p.lay.col_clu_start);
-  return NB_OK;
+  return guarded("nb_workspace_layout", [&]() -> nb_status {
+    if (!layout) return fail(NB_ERR_ARG, "layout is NULL");
+    nb::Plan p;
+    nb_status st = nb::make_plan(sys, params, &p);
+    if (st != NB_OK) return st;
+    layout->n_atoms = p.N;
+    layout->n_cells = p.n_cells;
+    for (int a = 0; a < 3; ++a) layout->dims[a] = p.desc[0].dims[a];
+    layout->off_cell_start = static_cast<int64_t>(p.lay.cell_start);
+    layout->off_sorted_fixed = static_cast<int64_t>(p.lay.s_fix);
+    layout->off_sorted_pos64 = static_cast<int64_t>(p.lay.s_pos64);
+    layout->off_excl_mask = static_cast<int64_t>(p.lay.excl_mask);
+    layout->off_status = static_cast<int64_t>(p.lay.status);
+    layout->n_columns = p.n_columns;
+    layout->n_clusters_max = p.n_clusters_max;
+    layout->off_col_clu_start = static_cast<int64_t>(p.lay.col_clu_start);
+    return NB_OK;
+  });
 }
 
 nb_status nb_build_cells(const nb_system *sys, const nb_params *params, void *workspace,
                          size_t workspace_bytes, hipStream_t stream) {
-  nb::Plan p;
-  nb_status st = nb::make_plan(sys, params, &p);
-  if (st != NB_OK) return st;
-  if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
-  return hip_status(nb::launch_build(p, nb::dev_view(p, workspace), sys, stream), "nb_build_cells");
+  return guarded("nb_build_cells", [&]() -> nb_status {
+    nb::Plan p;
+    nb_status st = nb::make_plan(sys, params, &p);
+    if (st != NB_OK) return st;
+    if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
+    return hip_status(nb::launch_build(p, nb::dev_view(p, workspace), sys, stream), "nb_build_cells");
+  });
 }
 
 nb_status nb_nonbonded_forces(const nb_system *sys, const nb_params *params, void *workspace,
                               size_t workspace_bytes, double *force, double *energy, double *virial,
                               hipStream_t stream) {
-  nb::Plan p;
-  nb_status st = nb::make_plan(sys, params, &p);
-  if (st != NB_OK) return st;
-  if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
-  if (!force && p.N > 0) return fail(NB_ERR_ARG, "force must not be NULL");
-  return hip_status(nb::launch_forces(p, nb::dev_view(p, workspace), sys, force, energy, virial, stream),
-                    "nb_nonbonded_forces");
+  return guarded("nb_nonbonded_forces", [&]() -> nb_status {
+    nb::Plan p;
+    nb_status st = nb::make_plan(sys, params, &p);
+    if (st != NB_OK) return st;
+    if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
+    if (!force && p.N > 0) return fail(NB_ERR_ARG, "force must not be NULL");
+    return hip_status(nb::launch_forces(p, nb::dev_view(p, workspace), sys, force, energy, virial, stream),
+                      "nb_nonbonded_forces");
+  });
 }
 
 nb_status nb_nonbonded_energy(const nb_system *sys, const nb_params *params, void *workspace,
                               size_t workspace_bytes, double *energy, double *atom_energy,
                               hipStream_t stream) {
-  nb::Plan p;
-  nb_status st = nb::make_plan(sys, params, &p);
-  if (st != NB_OK) return st;
-  if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
-  if (!energy) return fail(NB_ERR_ARG, "energy must not be NULL");
-  return hip_status(nb::launch_energy(p, nb::dev_view(p, workspace), sys, energy, atom_energy, stream),
-                    "nb_nonbonded_energy");
+  return guarded("nb_nonbonded_energy", [&]() -> nb_status {
+    nb::Plan p;
+    nb_status st = nb::make_plan(sys, params, &p);
+    if (st != NB_OK) return st;
+    if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
+    if (!energy) return fail(NB_ERR_ARG, "energy must not be NULL");
+    return hip_status(nb::launch_energy(p, nb::dev_view(p, workspace), sys, energy, atom_energy, stream),
+                      "nb_nonbonded_energy");
+  });
 }
 
 nb_status nb_nonbonded_backward(const nb_system *sys, const nb_params *params, void *workspace,
                                 size_t workspace_bytes, const double *grad_energy, double *grad_pos,
                                 double *grad_charge, double *grad_sigma, double *grad_eps,
                                 hipStream_t stream) {
-  nb::Plan p;
-  nb_status st = nb::make_plan(sys, params, &p);
-  if (st != NB_OK) return st;
-  if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
-  if (!grad_energy) return fail(NB_ERR_ARG, "grad_energy must not be NULL");
-  return hip_status(nb::launch_backward(p, nb::dev_view(p, workspace), sys, grad_energy, grad_pos,
-                                        grad_charge, grad_sigma, grad_eps, stream),
-                    "nb_nonbonded_backward");
+  return guarded("nb_nonbonded_backward", [&]() -> nb_status {
+    nb::Plan p;
+    nb_status st = nb::make_plan(sys, params, &p);
+    if (st != NB_OK) return st;
+    if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
+    if (!grad_energy) return fail(NB_ERR_ARG, "grad_energy must not be NULL");
+    return hip_status(nb::launch_backward(p, nb::dev_view(p, workspace), sys, grad_energy, grad_pos,
+                                          grad_charge, grad_sigma, grad_eps, stream),
+                      "nb_nonbonded_backward");
+  });
 }
 
 nb_status nb_ewald_corrections(const nb_system *sys, const nb_params *params, void *workspace,
                                size_t workspace_bytes, double *force, double *energy, double *virial,
                                hipStream_t stream) {
-  nb::Plan p;
-  nb_status st = nb::make_plan(sys, params, &p);
-  if (st != NB_OK) return st;
-  if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
-  if (!force) return fail(NB_ERR_ARG, "force must not be NULL");
-  return hip_status(nb::launch_ewald(p, nb::dev_view(p, workspace), sys, force, energy, virial, stream),
-                    "nb_ewald_corrections");
+  return guarded("nb_ewald_corrections", [&]() -> nb_status {
+    nb::Plan p;
+    nb_status st = nb::make_plan(sys, params, &p);
+    if (st != NB_OK) return st;
+    if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
+    if (!force && p.N > 0) return fail(NB_ERR_ARG, "force must not be NULL");
+    return hip_status(nb::launch_ewald(p, nb::dev_view(p, workspace), sys, force, energy, virial, stream),
+                      "nb_ewald_corrections");
+  });
 }
 
 nb_status nb_pme_workspace_bytes(const nb_system *sys, const int32_t grid[3], size_t *bytes) {
-  if (!sys || !bytes) return fail(NB_ERR_ARG, "null system or output pointer");
-  if (sys->n_systems < 1) return fail(NB_ERR_ARG, "n_systems must be >= 1");
-  nb::PmeLayout lay;
-  const std::string why = nb::pme_layout(sys->n_systems, grid, &lay);
-  if (!why.empty()) return fail(NB_ERR_ARG, why);
-  *bytes = lay.total;
-  return NB_OK;
+  return guarded("nb_pme_workspace_bytes", [&]() -> nb_status {
+    if (!sys || !bytes) return fail(NB_ERR_ARG, "null system or output pointer");
+    if (sys->n_systems < 1) return fail(NB_ERR_ARG, "n_systems must be >= 1");
+    nb::PmeLayout lay;
+    std::string why = nb::pme_layout(sys->n_systems, grid, &lay);
+    if (!why.empty()) return fail(NB_ERR_ARG, why);
+    why = nb::pme_attach_plans(&lay);
+    if (!why.empty()) return fail(NB_ERR_HIP, "nb_pme_workspace_bytes: " + why);
+    *bytes = lay.total;
+    return NB_OK;
+  });
 }
 
 nb_status nb_pme_reciprocal(const nb_system *sys, const nb_params *params, const int32_t grid[3], void *workspace,
                             size_t workspace_bytes, double *force, double *energy, double *virial,
                             hipStream_t stream) {
-  nb::Plan p;
-  nb_status st = nb::make_plan(sys, params, &p);
-  if (st != NB_OK) return st;
-  if (!(params->ewald_beta > 0.0)) return fail(NB_ERR_ARG, "the reciprocal sum needs ewald_beta > 0");
-  nb::PmeLayout lay;
-  const std::string why = nb::pme_layout(sys->n_systems, grid, &lay);
-  if (!why.empty()) return fail(NB_ERR_ARG, why);
-  if (!workspace) return fail(NB_ERR_WORKSPACE, "workspace is NULL");
-  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
-    return fail(NB_ERR_WORKSPACE, "workspace must be 256-byte aligned");
-  if (workspace_bytes < lay.total)
-    return fail(NB_ERR_WORKSPACE,
-                "workspace too small: " + std::to_string(workspace_bytes) + " < " + std::to_string(lay.total));
-  if (!force) return fail(NB_ERR_ARG, "force must not be NULL");
-  std::string err;
-  const hipError_t e = nb::launch_pme(lay, sys, params->ewald_beta, params->coulomb_k, workspace, force, energy,
-                                      virial, stream, &err);
-  if (!err.empty()) return fail(NB_ERR_HIP, "nb_pme_reciprocal: " + err);
-  return hip_status(e, "nb_pme_reciprocal");
+  return guarded("nb_pme_reciprocal", [&]() -> nb_status {
+    nb::Plan p;
+    nb_status st = nb::make_plan(sys, params, &p);
+    if (st != NB_OK) return st;
+    if (!(params->ewald_beta > 0.0)) return fail(NB_ERR_ARG, "the reciprocal sum needs ewald_beta > 0");
+    nb::PmeLayout lay;
+    std::string why = nb::pme_layout(sys->n_systems, grid, &lay);
+    if (!why.empty()) return fail(NB_ERR_ARG, why);
+    if (!force && p.N > 0) return fail(NB_ERR_ARG, "force must not be NULL");
+    if (!workspace) return fail(NB_ERR_WORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+      return fail(NB_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (workspace_bytes < lay.total)  // the grids alone do not fit
+      return fail(NB_ERR_WORKSPACE,
+                  "workspace too small: " + std::to_string(workspace_bytes) + " < " + std::to_string(lay.total));
+    why = nb::pme_attach_plans(&lay);
+    if (!why.empty()) return fail(NB_ERR_HIP, "nb_pme_reciprocal: " + why);
+    if (workspace_bytes < lay.total)
+      return fail(NB_ERR_WORKSPACE,
+                  "workspace too small: " + std::to_string(workspace_bytes) + " < " + std::to_string(lay.total));
+    std::string err;
+    const hipError_t e = nb::launch_pme(lay, sys, params->ewald_beta, params->coulomb_k, workspace, force, energy,
+                                        virial, stream, &err);
+    if (!err.empty()) return fail(NB_ERR_HIP, "nb_pme_reciprocal: " + err);
+    return hip_status(e, "nb_pme_reciprocal");
+  });
 }
 
 nb_status nb_read_status(const void *workspace, hipStream_t stream, uint32_t *flags) {
-  if (!workspace || !flags) return fail(NB_ERR_ARG, "workspace and flags are required");
-  hipError_t e = hipStreamSynchronize(stream);
-  if (e != hipSuccess) return hip_status(e, "nb_read_status: stream synchronise");
-  e = hipMemcpy(flags, workspace, sizeof(uint32_t), hipMemcpyDeviceToHost);
-  return hip_status(e, "nb_read_status: copy");
+  return guarded("nb_read_status", [&]() -> nb_status {
+    if (!workspace || !flags) return fail(NB_ERR_ARG, "workspace and flags are required");
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_status(e, "nb_read_status: stream synchronise");
+    e = hipMemcpy(flags, workspace, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    return hip_status(e, "nb_read_status: copy");
+  });
 }
 
 const char *nb_last_error(void) { return nb::g_last_error.c_str(); }
 
 nb_status nb_pair_timer_start(int32_t capacity) {
-  if (capacity < 1 || capacity > 65536) return fail(NB_ERR_ARG, "timer capacity must be in [1, 65536]");
-  nb::PairTimer &t = nb::g_pair_timer;
-  if (t.on) return fail(NB_ERR_ARG, "pair timer already started");
-  t.ev.clear();
-  t.used = 0;
-  for (int32_t k = 0; k < capacity; ++k) {
-    hipEvent_t a = nullptr, b = nullptr;
-    hipError_t e = hipEventCreate(&a);
-    if (e == hipSuccess) e = hipEventCreate(&b);
-    if (e != hipSuccess) {
-      if (a) (void)hipEventDestroy(a);
-      for (auto &pr : t.ev) {
-        (void)hipEventDestroy(pr.first);
-        (void)hipEventDestroy(pr.second);
+  return guarded("nb_pair_timer_start", [&]() -> nb_status {
+    if (capacity < 1 || capacity > 65536) return fail(NB_ERR_ARG, "timer capacity must be in [1, 65536]");
+    nb::PairTimer &t = nb::g_pair_timer;
+    if (t.on) return fail(NB_ERR_ARG, "pair timer already started");
+    t.ev.clear();
+    t.used = 0;
+    for (int32_t k = 0; k < capacity; ++k) {
+      hipEvent_t a = nullptr, b = nullptr;
+      hipError_t e = hipEventCreate(&a);
+      if (e == hipSuccess) e = hipEventCreate(&b);
+      if (e != hipSuccess) {
+        if (a) (void)hipEventDestroy(a);
+        for (auto &pr : t.ev) {
+          (void)hipEventDestroy(pr.first);
+          (void)hipEventDestroy(pr.second);
+        }
+        t.ev.clear();
+        return hip_status(e, "nb_pair_timer_start: event create");
       }
-      t.ev.clear();
-      return hip_status(e, "nb_pair_timer_start: event create");
+      t.ev.emplace_back(a, b);
     }
-    t.ev.emplace_back(a, b);
-  }
-  t.on = true;
-  return NB_OK;
+    t.on = true;
+    return NB_OK;
+  });
 }
 
 nb_status nb_pair_timer_stop(double *total_ms, int64_t *launches) {
-  if (!total_ms || !launches) return fail(NB_ERR_ARG, "total_ms and launches are required");
-  nb::PairTimer &t = nb::g_pair_timer;
-  if (!t.on) return fail(NB_ERR_ARG, "pair timer not started");
-  t.on = false;
-  double sum = 0.0;
-  hipError_t err = hipSuccess;
-  for (size_t k = 0; k < t.used && err == hipSuccess; ++k) {
-    err = hipEventSynchronize(t.ev[k].second);
-    float ms = 0.f;
-    if (err == hipSuccess) err = hipEventElapsedTime(&ms, t.ev[k].first, t.ev[k].second);
-    sum += ms;
-  }
-  for (auto &pr : t.ev) {
-    (void)hipEventDestroy(pr.first);
-    (void)hipEventDestroy(pr.second);
-  }
-  *total_ms = sum;
-  *launches = static_cast<int64_t>(t.used);
-  t.ev.clear();
-  t.used = 0;
-  return hip_status(err, "nb_pair_timer_stop");
+  return guarded("nb_pair_timer_stop", [&]() -> nb_status {
+    if (!total_ms || !launches) return fail(NB_ERR_ARG, "total_ms and launches are required");
+    nb::PairTimer &t = nb::g_pair_timer;
+    if (!t.on) return fail(NB_ERR_ARG, "pair timer not started");
+    t.on = false;
+    double sum = 0.0;
+    hipError_t err = hipSuccess;
+    for (size_t k = 0; k < t.used && err == hipSuccess; ++k) {
+      err = hipEventSynchronize(t.ev[k].second);
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, t.ev[k].first, t.ev[k].second);
+      sum += ms;
+    }
+    for (auto &pr : t.ev) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    *total_ms = sum;
+    *launches = static_cast<int64_t>(t.used);
+    t.ev.clear();
+    t.used = 0;
+    return hip_status(err, "nb_pair_timer_stop");
+  });
 }
 
 }  // extern "C"

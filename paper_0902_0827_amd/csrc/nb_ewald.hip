@@ -219,10 +219,12 @@ __global__ void __launch_bounds__(kEwaldReduceBlock) k_ewald_reduce(Dev d, doubl
 
 hipError_t launch_ewald(const Plan &p, const Dev &d, const nb_system *sys, double *force, double *energy,
                         double *virial, hipStream_t s) {
-  if (p.N == 0) return hipGetLastError();
   const dim3 grid(static_cast<unsigned>(p.n_blocks)), block(kBlock);
   const double ke = p.ke, beta = p.beta;
-  if (sys->pos_is_f64) {
+  // A batch without atoms launches no per-atom work, but its systems' energies and
+  // virials are still written (zeros: a system without blocks sums to nothing).
+  if (p.n_blocks == 0) {
+  } else if (sys->pos_is_f64) {
     const double *pos = static_cast<const double *>(sys->pos);
     const double *q = static_cast<const double *>(sys->charge);
     hipLaunchKernelGGL(k_ewald_atoms<double>, grid, block, 0, s, d, pos, q, sys->excl_offset, sys->excl_index, ke,

@@ -27,6 +27,8 @@
 // Nothing is accumulated with atomics: results are deterministic.  Full shell (every
 // pair is evaluated from both sides), as in the paper; the half-shell variant is
 // described with the kernel.
+#pragma once
+
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -1190,9 +1192,11 @@ void launch_cluster_k(int K, int mode, bool half, int64_t wgs, int dyn, int wg_p
 
 }  // namespace
 
-void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out &o, int mode, hipStream_t s,
-                         double *energy, double *virial, const double *eps, double *grad_sigma, double *grad_eps) {
-  const bool half = p.kernel == NB_KERNEL_CLUSTER_HALF && mode != kAdjoint;  // the adjoint stays full-shell
+// Pair-kernel launch for one precision; instantiated in nb_pair_cluster_f32.hip and
+// nb_pair_cluster_f64.hip so that the two compile in parallel.
+template <bool F64>
+void launch_cluster_pair_prec(const Plan &p, const Dev &d, const Consts &c, const Out &o, int mode, bool half,
+                              hipStream_t s) {
   if (p.N > 0 && p.n_clusters_max > 0) {
     const int64_t items = p.n_clusters_max * p.split;  // upper bound on the work items
     const int64_t wgs = items;  // one wave per workgroup
@@ -1200,33 +1204,10 @@ void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out
     const bool tab = p.T <= kTabLds;
     const int K = p.cluster_size;
     timer_before(s);
-    if (p.precision == NB_FP64) {
-      if (tab) launch_cluster_k<true, true>(K, mode, half, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
-      else launch_cluster_k<true, false>(K, mode, half, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
-    } else {
-      if (tab) launch_cluster_k<false, true>(K, mode, half, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
-      else launch_cluster_k<false, false>(K, mode, half, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
-    }
+    if (tab) launch_cluster_k<F64, true>(K, mode, half, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
+    else launch_cluster_k<F64, false>(K, mode, half, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
     timer_after(s);
   }
-  // With one item per cluster the full-shell kernel has written the per-atom outputs
-  // itself; the half-shell kernel's accumulators are always copied out here.
-  const int blocksA = static_cast<int>((p.N + kFinishBlock - 1) / kFinishBlock);
-  const int nA = half ? ((mode == kForces || o.atom_energy) ? blocksA : 0) : (p.split == 1 ? 0 : blocksA);
-  int nv = 0;
-  if (mode == kForces) nv = o.want_part ? (virial ? kPart : 1) : 0;
-  if (mode == kEnergy) nv = 1;
-  const int extra = mode == kAdjoint ? ((grad_sigma || grad_eps) ? 2 * p.T : 0) : 0;
-  const dim3 fg(static_cast<unsigned>(nA + kPart * p.B + extra));
-  if (mode == kForces)
-    hipLaunchKernelGGL(k_finish<kForces>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
-                       grad_sigma, grad_eps, half ? 1 : 0);
-  else if (mode == kEnergy)
-    hipLaunchKernelGGL(k_finish<kEnergy>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
-                       grad_sigma, grad_eps, half ? 1 : 0);
-  else
-    hipLaunchKernelGGL(k_finish<kAdjoint>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
-                       grad_sigma, grad_eps, 0);
 }
 
 }  // namespace nb

@@ -30,6 +30,7 @@
 #include <hipfft/hipfft.h>
 
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -54,6 +55,36 @@ struct PmeSys {
   int K[3];
   int H;  // K3/2 + 1: the half spectrum's last dimension
 };
+
+// Systems of one launch (at most kPmeChunk; a larger batch takes several launches per
+// step).  Only what differs between systems travels here; the rest of PmeSys is formed on
+// the device with the same IEEE operations as on the host (make_sys), so every system's
+// constants are the ones a launch per system would have used.
+constexpr int kPmeChunk = 32;
+struct PmeBatch {
+  int nsys;    // systems in this launch
+  int first;   // batch index of its first system (grid and partial offsets)
+  int K[3];
+  double a;    // pi^2 / beta^2
+  double ke;
+  double L[kPmeChunk][3];
+  int64_t a0[kPmeChunk];          // first atom of each system
+  int32_t n[kPmeChunk];           // atoms of each system
+  int32_t blk0[kPmeChunk + 1];    // first gather workgroup of each system (prefix sums)
+};
+
+__host__ __device__ inline PmeSys make_sys(const double L[3], const int K[3], double a, double ke) {
+  PmeSys ps;
+  for (int d = 0; d < 3; ++d) {
+    ps.L[d] = L[d];
+    ps.invL[d] = 1.0 / L[d];
+    ps.K[d] = K[d];
+  }
+  ps.H = K[2] / 2 + 1;
+  ps.a = a;
+  ps.escale = ke / (2.0 * kPi * L[0] * L[1] * L[2]);
+  return ps;
+}
 
 inline size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
@@ -131,11 +162,18 @@ constexpr int kPlaneBlock = 1024;
 constexpr int kPlaneMaxPoints = 8192;  // 64 KB of LDS
 
 template <typename T>
-__global__ void __launch_bounds__(kPlaneBlock) k_pme_spread_planes(const T *__restrict__ pos,
-                                                                   const T *__restrict__ charge, int n, PmeSys ps,
-                                                                   double *__restrict__ grid) {
+__global__ void __launch_bounds__(kPlaneBlock) k_pme_spread_planes(const T *__restrict__ pos_all,
+                                                                   const T *__restrict__ charge_all, PmeBatch pb,
+                                                                   int64_t grid_points, double *__restrict__ grids) {
   extern __shared__ double plane[];
-  const int x = blockIdx.x;
+  // workgroup (system b of the launch, plane x)
+  const int b = static_cast<int>(blockIdx.x) / pb.K[0];
+  const int x = static_cast<int>(blockIdx.x) - b * pb.K[0];
+  const PmeSys ps = make_sys(pb.L[b], pb.K, pb.a, pb.ke);
+  const T *__restrict__ pos = pos_all + 3 * pb.a0[b];
+  const T *__restrict__ charge = charge_all + pb.a0[b];
+  const int n = pb.n[b];
+  double *__restrict__ grid = grids + static_cast<int64_t>(pb.first + b) * grid_points;
   const int P = ps.K[1] * ps.K[2];
   for (int j = threadIdx.x; j < P; j += kPlaneBlock) plane[j] = 0.0;
   __syncthreads();
@@ -175,10 +213,16 @@ __device__ inline double inv_bmod2(int i, int K) {
   return c * c * (1.0 / 9.0);
 }
 
-__global__ void __launch_bounds__(kBlock) k_pme_convolve(double2 *__restrict__ spec, PmeSys ps, int64_t n_spec,
-                                                         double *__restrict__ partials, int64_t n_part_blocks) {
+__global__ void __launch_bounds__(kBlock) k_pme_convolve(double2 *__restrict__ specs, PmeBatch pb, int64_t n_spec,
+                                                         double *__restrict__ partials_all, int64_t n_part_blocks) {
   __shared__ double red[kWaves][kPart];
-  const int64_t e = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
+  // workgroup (system b of the launch, block blk of its half spectrum)
+  const int b = static_cast<int>(blockIdx.x / n_part_blocks);
+  const int64_t blk = blockIdx.x - static_cast<int64_t>(b) * n_part_blocks;
+  const PmeSys ps = make_sys(pb.L[b], pb.K, pb.a, pb.ke);
+  double2 *__restrict__ spec = specs + static_cast<int64_t>(pb.first + b) * n_spec;
+  double *__restrict__ partials = partials_all + static_cast<int64_t>(pb.first + b) * kPart * n_part_blocks;
+  const int64_t e = blk * kBlock + threadIdx.x;
   double v[kPart] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (e < n_spec) {
     const int iz = static_cast<int>(e % ps.H);
@@ -230,16 +274,26 @@ __global__ void __launch_bounds__(kBlock) k_pme_convolve(double2 *__restrict__ s
   if (threadIdx.x < kPart) {
     double s = 0.0;
     for (int w = 0; w < kWaves; ++w) s += red[w][threadIdx.x];
-    partials[static_cast<int64_t>(threadIdx.x) * n_part_blocks + blockIdx.x] = s;
+    partials[static_cast<int64_t>(threadIdx.x) * n_part_blocks + blk] = s;
   }
 }
 
 // 16 lanes per atom as in the spread; the row sums meet by shuffles within the 16.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_pme_gather(const T *__restrict__ pos, const T *__restrict__ charge, int n,
-                                                       PmeSys ps, const double *__restrict__ phi,
-                                                       double *__restrict__ force) {
-  const int64_t t = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
+__global__ void __launch_bounds__(kBlock) k_pme_gather(const T *__restrict__ pos_all, const T *__restrict__ charge_all,
+                                                       PmeBatch pb, int64_t grid_points,
+                                                       const double *__restrict__ phis,
+                                                       double *__restrict__ force_all) {
+  // system of this workgroup: the last one whose first workgroup is <= blockIdx.x
+  int sb = 0;
+  while (sb + 1 < pb.nsys && pb.blk0[sb + 1] <= static_cast<int>(blockIdx.x)) ++sb;
+  const PmeSys ps = make_sys(pb.L[sb], pb.K, pb.a, pb.ke);
+  const T *__restrict__ pos = pos_all + 3 * pb.a0[sb];
+  const T *__restrict__ charge = charge_all + pb.a0[sb];
+  const int n = pb.n[sb];
+  const double *__restrict__ phi = phis + static_cast<int64_t>(pb.first + sb) * grid_points;
+  double *__restrict__ force = force_all + 3 * pb.a0[sb];
+  const int64_t t = (static_cast<int64_t>(blockIdx.x) - pb.blk0[sb]) * kBlock + threadIdx.x;
   const int i_raw = static_cast<int>(t / kLanesPerAtom);
   const bool valid = i_raw < n;
   const int i = valid ? i_raw : n - 1;  // lanes past the end still join the shuffles
@@ -305,12 +359,16 @@ __global__ void __launch_bounds__(kBlock) k_pme_reduce(const double *__restrict_
 
 // FFT plans, one forward (D2Z) and one inverse (Z2D) per grid shape, batch size and
 // device, each transforming the B systems' grids (contiguous, one after the other) in
-// one call; made on first use and kept for the life of the process.  The mutex also covers setting a
-// plan's stream and enqueueing its transform; transforms of one plan on different
-// streams would share its work buffer, so callers keep such calls ordered.
+// one call; made on first use and kept for the life of the process (at most
+// kMaxFftPlans of them).  The plans do not allocate their work buffers: every call hands
+// them the work area of its own workspace, so calls on different streams with different
+// workspaces share nothing but the plans' read-only tables.  The mutex covers the cache
+// and, per call, setting a plan's stream and work area and enqueueing its transform.
 struct FftPlans {
   hipfftHandle fwd = nullptr, inv = nullptr;
+  size_t work = 0;  // bytes of work area either transform needs
 };
+constexpr size_t kMaxFftPlans = 32;
 std::mutex g_fft_mu;
 std::map<std::tuple<int, int, int, int, int>, FftPlans> g_fft;
 
@@ -321,6 +379,50 @@ const char *fft_error(hipfftResult r) {
     case HIPFFT_EXEC_FAILED: return "FFT execution failed";
     default: return "FFT library error";
   }
+}
+
+// The plans for this layout on the current device, made if needed.  Returns "" or the
+// reason they could not be made.  Caller holds g_fft_mu.
+std::string fft_plans_locked(int B, const int K[3], int64_t grid, int64_t spec, FftPlans *out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return "no current HIP device";
+  const auto key = std::make_tuple(dev, K[0], K[1], K[2], B);
+  auto it = g_fft.find(key);
+  if (it != g_fft.end()) {
+    *out = it->second;
+    return "";
+  }
+  if (g_fft.size() >= kMaxFftPlans)
+    return "more than 32 distinct (grid shape, batch size, device) FFT plans in this process";
+  FftPlans p;
+  int dims[3] = {K[0], K[1], K[2]};
+  // contiguous grids, unit stride: K1 K2 K3 reals and K1 K2 (K3/2+1) complex values per
+  // system, one system after the other
+  int real_embed[3] = {K[0], K[1], K[2]};
+  int spec_embed[3] = {K[0], K[1], K[2] / 2 + 1};
+  const int grid_dist = static_cast<int>(grid), spec_dist = static_cast<int>(spec);
+  size_t wf = 0, wi = 0;
+  hipfftResult r = hipfftCreate(&p.fwd);
+  if (r == HIPFFT_SUCCESS) r = hipfftSetAutoAllocation(p.fwd, 0);
+  if (r == HIPFFT_SUCCESS)
+    r = hipfftMakePlanMany(p.fwd, 3, dims, real_embed, 1, grid_dist, spec_embed, 1, spec_dist, HIPFFT_D2Z, B, &wf);
+  if (r != HIPFFT_SUCCESS) {
+    if (p.fwd) hipfftDestroy(p.fwd);
+    return std::string("hipfftMakePlanMany (D2Z): ") + fft_error(r);
+  }
+  r = hipfftCreate(&p.inv);
+  if (r == HIPFFT_SUCCESS) r = hipfftSetAutoAllocation(p.inv, 0);
+  if (r == HIPFFT_SUCCESS)
+    r = hipfftMakePlanMany(p.inv, 3, dims, spec_embed, 1, spec_dist, real_embed, 1, grid_dist, HIPFFT_Z2D, B, &wi);
+  if (r != HIPFFT_SUCCESS) {
+    hipfftDestroy(p.fwd);
+    if (p.inv) hipfftDestroy(p.inv);
+    return std::string("hipfftMakePlanMany (Z2D): ") + fft_error(r);
+  }
+  p.work = std::max(wf, wi);
+  g_fft.emplace(key, p);
+  *out = p;
+  return "";
 }
 
 }  // namespace
@@ -335,6 +437,7 @@ std::string pme_layout(int B, const int32_t grid[3], PmeLayout *lay) {
   l.grid = static_cast<int64_t>(grid[0]) * grid[1] * grid[2];
   l.spec = static_cast<int64_t>(grid[0]) * grid[1] * (grid[2] / 2 + 1);
   if (l.grid > (int64_t{1} << 28)) return "grid larger than 2^28 points";
+  if (static_cast<int64_t>(B) * l.grid > (int64_t{1} << 31)) return "batch grids larger than 2^31 points";
   l.conv_blocks = (l.spec + kBlock - 1) / kBlock;
   size_t off = 0;
   l.real = off;
@@ -343,138 +446,138 @@ std::string pme_layout(int B, const int32_t grid[3], PmeLayout *lay) {
   off = align256(off + 2 * sizeof(double) * static_cast<size_t>(B) * l.spec);
   l.partials = off;
   off = align256(off + sizeof(double) * static_cast<size_t>(B) * kPart * l.conv_blocks);
+  l.work = off;
   l.total = off;
   *lay = l;
   return "";
 }
 
+std::string pme_attach_plans(PmeLayout *lay) {
+  FftPlans plans;
+  {
+    std::lock_guard<std::mutex> lock(g_fft_mu);
+    const std::string why = fft_plans_locked(lay->B, lay->K, lay->grid, lay->spec, &plans);
+    if (!why.empty()) return why;
+  }
+  lay->work_bytes = plans.work;
+  lay->total = align256(lay->work + plans.work);
+  return "";
+}
+
 hipError_t launch_pme(const PmeLayout &lay, const nb_system *sys, double beta, double ke, void *ws, double *force,
                       double *energy, double *virial, hipStream_t s, std::string *err) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
   char *base = static_cast<char *>(ws);
   double *real = reinterpret_cast<double *>(base + lay.real);
   double2 *cplx = reinterpret_cast<double2 *>(base + lay.cplx);
   double *partials = reinterpret_cast<double *>(base + lay.partials);
+  void *work = lay.work_bytes ? static_cast<void *>(base + lay.work) : nullptr;
   auto stride_blocks = [](int64_t n) {
     return dim3(static_cast<unsigned>(std::min<int64_t>((n + kBlock - 1) / kBlock, 65536)));
   };
-  const int64_t plane_points = static_cast<int64_t>(lay.K[1]) * lay.K[2];
-  const bool planes = plane_points <= kPlaneMaxPoints;
-  if (!planes)
-    hipLaunchKernelGGL(k_pme_zero, stride_blocks(lay.grid * lay.B), dim3(kBlock), 0, s, real, lay.grid * lay.B);
   FftPlans plans;
   {
     std::lock_guard<std::mutex> lock(g_fft_mu);
-    auto key = std::make_tuple(dev, lay.K[0], lay.K[1], lay.K[2], lay.B);
-    auto it = g_fft.find(key);
-    if (it == g_fft.end()) {
-      FftPlans p;
-      int dims[3] = {lay.K[0], lay.K[1], lay.K[2]};
-      // contiguous grids, unit stride: K1 K2 K3 reals and K1 K2 (K3/2+1) complex values
-      // per system, one system after the other
-      int real_embed[3] = {lay.K[0], lay.K[1], lay.K[2]};
-      int spec_embed[3] = {lay.K[0], lay.K[1], lay.K[2] / 2 + 1};
-      const int grid_dist = static_cast<int>(lay.grid), spec_dist = static_cast<int>(lay.spec);
-      hipfftResult r = hipfftPlanMany(&p.fwd, 3, dims, real_embed, 1, grid_dist, spec_embed, 1, spec_dist,
-                                      HIPFFT_D2Z, lay.B);
-      if (r != HIPFFT_SUCCESS) {
-        *err = std::string("hipfftPlanMany (D2Z): ") + fft_error(r);
-        return hipErrorUnknown;
-      }
-      r = hipfftPlanMany(&p.inv, 3, dims, spec_embed, 1, spec_dist, real_embed, 1, grid_dist, HIPFFT_Z2D, lay.B);
-      if (r != HIPFFT_SUCCESS) {
-        hipfftDestroy(p.fwd);
-        *err = std::string("hipfftPlanMany (Z2D): ") + fft_error(r);
-        return hipErrorUnknown;
-      }
-      it = g_fft.emplace(key, p).first;
+    const std::string why = fft_plans_locked(lay.B, lay.K, lay.grid, lay.spec, &plans);
+    if (!why.empty()) {
+      *err = why;
+      return hipErrorUnknown;
     }
-    plans = it->second;
   }
+  if (plans.work > lay.work_bytes) {  // the workspace was sized for another device's plans
+    *err = "workspace sized for FFT plans of another device";
+    return hipErrorUnknown;
+  }
+  const int64_t plane_points = static_cast<int64_t>(lay.K[1]) * lay.K[2];
+  const bool planes = plane_points <= kPlaneMaxPoints;
   const bool f64 = sys->pos_is_f64 != 0;
-  // the parameters and grids of system b
-  auto system = [&](int b, int64_t *a0_out, int64_t *n_out, PmeSys *ps_out) {
-    const int64_t a0 = sys->atom_offset[b], n = sys->atom_offset[b + 1] - a0;
-    PmeSys ps;
-    for (int a = 0; a < 3; ++a) {
-      ps.L[a] = sys->box[3 * b + a];
-      ps.invL[a] = 1.0 / ps.L[a];
-      ps.K[a] = lay.K[a];
+  const double a = kPi * kPi / (beta * beta);
+  // the launch descriptor of systems [first, first + nsys)
+  auto chunk = [&](int first, int nsys) {
+    PmeBatch pb;
+    std::memset(&pb, 0, sizeof(pb));
+    pb.nsys = nsys;
+    pb.first = first;
+    for (int d = 0; d < 3; ++d) pb.K[d] = lay.K[d];
+    pb.a = a;
+    pb.ke = ke;
+    int32_t blocks = 0;
+    for (int k = 0; k < nsys; ++k) {
+      const int b = first + k;
+      for (int d = 0; d < 3; ++d) pb.L[k][d] = sys->box[3 * b + d];
+      pb.a0[k] = sys->atom_offset[b];
+      pb.n[k] = static_cast<int32_t>(sys->atom_offset[b + 1] - sys->atom_offset[b]);
+      pb.blk0[k] = blocks;
+      blocks += static_cast<int32_t>((static_cast<int64_t>(pb.n[k]) * kLanesPerAtom + kBlock - 1) / kBlock);
     }
-    ps.H = lay.K[2] / 2 + 1;
-    ps.a = kPi * kPi / (beta * beta);
-    ps.escale = ke / (2.0 * kPi * ps.L[0] * ps.L[1] * ps.L[2]);
-    *a0_out = a0;
-    *n_out = n;
-    *ps_out = ps;
+    pb.blk0[nsys] = blocks;
+    return pb;
   };
   const dim3 blk(kBlock);
-  for (int b = 0; b < lay.B; ++b) {  // charge grids
-    int64_t a0, n;
-    PmeSys ps;
-    system(b, &a0, &n, &ps);
-    double *g = real + b * lay.grid;
-    const dim3 ga(static_cast<unsigned>((n * kLanesPerAtom + kBlock - 1) / kBlock));
+  // charge grids
+  if (!planes)
+    hipLaunchKernelGGL(k_pme_zero, stride_blocks(lay.grid * lay.B), dim3(kBlock), 0, s, real, lay.grid * lay.B);
+  for (int first = 0; first < lay.B; first += kPmeChunk) {
+    const PmeBatch pb = chunk(first, std::min(kPmeChunk, lay.B - first));
     if (planes) {
-      const dim3 gp(static_cast<unsigned>(lay.K[0])), bp(kPlaneBlock);
+      const dim3 gp(static_cast<unsigned>(lay.K[0] * pb.nsys)), bp(kPlaneBlock);
       const size_t lds = sizeof(double) * static_cast<size_t>(plane_points);
       if (f64)
-        hipLaunchKernelGGL(k_pme_spread_planes<double>, gp, bp, lds, s, static_cast<const double *>(sys->pos) + 3 * a0,
-                           static_cast<const double *>(sys->charge) + a0, static_cast<int>(n), ps, g);
+        hipLaunchKernelGGL(k_pme_spread_planes<double>, gp, bp, lds, s, static_cast<const double *>(sys->pos),
+                           static_cast<const double *>(sys->charge), pb, lay.grid, real);
       else
-        hipLaunchKernelGGL(k_pme_spread_planes<float>, gp, bp, lds, s, static_cast<const float *>(sys->pos) + 3 * a0,
-                           static_cast<const float *>(sys->charge) + a0, static_cast<int>(n), ps, g);
-    } else if (n > 0) {
-      if (f64)
-        hipLaunchKernelGGL(k_pme_spread<double>, ga, blk, 0, s, static_cast<const double *>(sys->pos) + 3 * a0,
-                           static_cast<const double *>(sys->charge) + a0, static_cast<int>(n), ps, g);
-      else
-        hipLaunchKernelGGL(k_pme_spread<float>, ga, blk, 0, s, static_cast<const float *>(sys->pos) + 3 * a0,
-                           static_cast<const float *>(sys->charge) + a0, static_cast<int>(n), ps, g);
+        hipLaunchKernelGGL(k_pme_spread_planes<float>, gp, bp, lds, s, static_cast<const float *>(sys->pos),
+                           static_cast<const float *>(sys->charge), pb, lay.grid, real);
+    } else {
+      for (int k = 0; k < pb.nsys; ++k) {  // grids too large for a plane in LDS: per system
+        const int64_t n = pb.n[k];
+        if (n == 0) continue;
+        const PmeSys ps = make_sys(pb.L[k], pb.K, a, ke);
+        double *g = real + static_cast<int64_t>(first + k) * lay.grid;
+        const dim3 ga(static_cast<unsigned>((n * kLanesPerAtom + kBlock - 1) / kBlock));
+        if (f64)
+          hipLaunchKernelGGL(k_pme_spread<double>, ga, blk, 0, s, static_cast<const double *>(sys->pos) + 3 * pb.a0[k],
+                             static_cast<const double *>(sys->charge) + pb.a0[k], static_cast<int>(n), ps, g);
+        else
+          hipLaunchKernelGGL(k_pme_spread<float>, ga, blk, 0, s, static_cast<const float *>(sys->pos) + 3 * pb.a0[k],
+                             static_cast<const float *>(sys->charge) + pb.a0[k], static_cast<int>(n), ps, g);
+      }
     }
   }
   {
     std::lock_guard<std::mutex> lock(g_fft_mu);
     hipfftResult r = hipfftSetStream(plans.fwd, s);
+    if (r == HIPFFT_SUCCESS) r = hipfftSetWorkArea(plans.fwd, work);
     if (r == HIPFFT_SUCCESS) r = hipfftExecD2Z(plans.fwd, real, reinterpret_cast<hipfftDoubleComplex *>(cplx));
     if (r != HIPFFT_SUCCESS) {
       *err = std::string("hipfftExecD2Z: ") + fft_error(r);
       return hipErrorUnknown;
     }
   }
-  for (int b = 0; b < lay.B; ++b) {  // convolution, energy and virial partials
-    int64_t a0, n;
-    PmeSys ps;
-    system(b, &a0, &n, &ps);
-    double2 *c = cplx + b * lay.spec;
-    hipLaunchKernelGGL(k_pme_convolve, dim3(static_cast<unsigned>(lay.conv_blocks)), blk, 0, s, c, ps, lay.spec,
-                       partials + b * kPart * lay.conv_blocks, lay.conv_blocks);
+  for (int first = 0; first < lay.B; first += kPmeChunk) {  // convolution, energy and virial partials
+    const PmeBatch pb = chunk(first, std::min(kPmeChunk, lay.B - first));
+    hipLaunchKernelGGL(k_pme_convolve, dim3(static_cast<unsigned>(lay.conv_blocks * pb.nsys)), blk, 0, s, cplx, pb,
+                       lay.spec, partials, lay.conv_blocks);
   }
   {
     std::lock_guard<std::mutex> lock(g_fft_mu);
     hipfftResult r = hipfftSetStream(plans.inv, s);
+    if (r == HIPFFT_SUCCESS) r = hipfftSetWorkArea(plans.inv, work);
     if (r == HIPFFT_SUCCESS) r = hipfftExecZ2D(plans.inv, reinterpret_cast<hipfftDoubleComplex *>(cplx), real);
     if (r != HIPFFT_SUCCESS) {
       *err = std::string("hipfftExecZ2D: ") + fft_error(r);
       return hipErrorUnknown;
     }
   }
-  for (int b = 0; b < lay.B; ++b) {  // forces from the potential grids
-    int64_t a0, n;
-    PmeSys ps;
-    system(b, &a0, &n, &ps);
-    double *g = real + b * lay.grid;
-    const dim3 ga(static_cast<unsigned>((n * kLanesPerAtom + kBlock - 1) / kBlock));
-    if (n > 0) {
-      if (f64)
-        hipLaunchKernelGGL(k_pme_gather<double>, ga, blk, 0, s, static_cast<const double *>(sys->pos) + 3 * a0,
-                           static_cast<const double *>(sys->charge) + a0, static_cast<int>(n), ps, g, force + 3 * a0);
-      else
-        hipLaunchKernelGGL(k_pme_gather<float>, ga, blk, 0, s, static_cast<const float *>(sys->pos) + 3 * a0,
-                           static_cast<const float *>(sys->charge) + a0, static_cast<int>(n), ps, g, force + 3 * a0);
-    }
+  for (int first = 0; first < lay.B; first += kPmeChunk) {  // forces from the potential grids
+    const PmeBatch pb = chunk(first, std::min(kPmeChunk, lay.B - first));
+    if (pb.blk0[pb.nsys] == 0) continue;
+    const dim3 ga(static_cast<unsigned>(pb.blk0[pb.nsys]));
+    if (f64)
+      hipLaunchKernelGGL(k_pme_gather<double>, ga, blk, 0, s, static_cast<const double *>(sys->pos),
+                         static_cast<const double *>(sys->charge), pb, lay.grid, real, force);
+    else
+      hipLaunchKernelGGL(k_pme_gather<float>, ga, blk, 0, s, static_cast<const float *>(sys->pos),
+                         static_cast<const float *>(sys->charge), pb, lay.grid, real, force);
   }
   if (energy || virial)
     hipLaunchKernelGGL(k_pme_reduce, dim3(static_cast<unsigned>(lay.B)), dim3(kBlock), 0, s, partials,

@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libnbhip.so")
 # Coulomb constant k_e = e^2 N_A / (4 pi eps0), CODATA 2018, kJ mol^-1 A e^-2.
 COULOMB_K = 1389.35457644382
 
-NB_OK, NB_ERR_ARG, NB_ERR_BOX, NB_ERR_WORKSPACE, NB_ERR_HIP, NB_ERR_CAPACITY = range(6)
+NB_OK, NB_ERR_ARG, NB_ERR_BOX, NB_ERR_WORKSPACE, NB_ERR_HIP, NB_ERR_CAPACITY, NB_ERR_HOST = range(7)
 NB_FP64, NB_MIXED = 0, 1
 NB_SCHED_AUTO, NB_SCHED_STATIC, NB_SCHED_DYNAMIC = 0, 1, 2
 NB_KERNEL_AUTO, NB_KERNEL_ATOM, NB_KERNEL_CLUSTER, NB_KERNEL_CLUSTER_HALF = 0, 1, 2, 3

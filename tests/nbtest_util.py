@@ -30,6 +30,23 @@ def max_rel_atom(f, fref):
     return float((np.linalg.norm(f - fref, axis=1)[m] / nrm[m]).max())
 
 
+# Per-atom bound of every force comparison with the oracle, beside the relative RMS: the
+# largest |dF_i| / |F_i| over atoms whose force is above 1e-3 of the RMS force.
+FP64_MAX_REL = 1e-11
+MIXED_MAX_REL = 1e-4
+
+
+def assert_forces(f, fref, precision, rms_tol):
+    """Force parity element by element: relative RMS over all components within rms_tol,
+    and every atom (above 1e-3 of the RMS force) within the per-atom bound."""
+    err = rel_rms(f, fref)
+    mx = max_rel_atom(f, fref)
+    bound = FP64_MAX_REL if precision == H.NB_FP64 else MIXED_MAX_REL
+    assert err <= rms_tol, f"relative RMS {err:.3e} > {rms_tol:.1e}"
+    assert mx <= bound, f"max per-atom relative error {mx:.3e} > {bound:.1e}"
+    return err, mx
+
+
 def rounded(system, precision):
     """The values the device computes with: FP32 inputs for the mixed path."""
     return system.rounded(np.float32) if precision == H.NB_MIXED else system

@@ -95,6 +95,9 @@ def test_layout_reports_the_grid():
     (lambda s, p: setattr(p, "ewald_beta", -0.1), H.NB_ERR_ARG),
     (lambda s, p: setattr(p, "precision", 7), H.NB_ERR_ARG),
     (lambda s, p: setattr(p, "cell_div_xy", 9), H.NB_ERR_ARG),
+    # four cells per cutoff in x and y is refused: the pair kernel's run table is sized
+    # for (2k+1)^2 <= 49 neighbour columns
+    (lambda s, p: setattr(p, "cell_div_xy", 4), H.NB_ERR_ARG),
     (lambda s, p: setattr(p, "kernel", 99), H.NB_ERR_ARG),
     (lambda s, p: setattr(p, "kernel", H.NB_KERNEL_CLUSTER_HALF + 1), H.NB_ERR_ARG),
     (lambda s, p: setattr(p, "split", 9), H.NB_ERR_ARG),
@@ -168,30 +171,80 @@ def test_pair_timer_argument_checks():
 
 
 def test_pme_workspace_and_argument_checks():
+    """Grid and argument checks come before any HIP or FFT-library call.  The work area
+    of the FFT plans is part of the workspace; its size needs the plans, so a valid grid
+    asks the current device (NB_ERR_HIP here, without one)."""
     lib = H.load_library()
     s = fake_system((648, 100))
     p = H.make_params(9.0, 0.34)
     G = ctypes.c_int32 * 3
     n = ctypes.c_size_t()
     P = lambda g: ctypes.cast(g, ctypes.POINTER(ctypes.c_int32))
-    # two systems, each a real grid, its half spectrum and its convolution partials (10 per 256 elements)
-    assert lib.nb_pme_workspace_bytes(ctypes.byref(s), P(G(32, 30, 27)), ctypes.byref(n)) == H.NB_OK
-    spec = 32 * 30 * (27 // 2 + 1)
-    up = lambda x: (x + 255) // 256 * 256
-    assert n.value == up(2 * 8 * 32 * 30 * 27) + up(2 * 16 * spec) + up(2 * 8 * 10 * ((spec + 255) // 256))
-    need = n.value
     for bad in [(3, 32, 32), (32, 0, 32), (32, 32, 1025)]:
         assert lib.nb_pme_workspace_bytes(ctypes.byref(s), P(G(*bad)), ctypes.byref(n)) == H.NB_ERR_ARG
         assert "grid" in H.last_error()
+    code = lib.nb_pme_workspace_bytes(ctypes.byref(s), P(G(32, 30, 27)), ctypes.byref(n))
+    # two systems, each a real grid, its half spectrum and its convolution partials (10
+    # per 256 elements), then the FFT work area
+    spec = 32 * 30 * (27 // 2 + 1)
+    up = lambda x: (x + 255) // 256 * 256
+    grids = up(2 * 8 * 32 * 30 * 27) + up(2 * 16 * spec) + up(2 * 8 * 10 * ((spec + 255) // 256))
+    if code == H.NB_OK:
+        assert n.value >= grids
+    else:
+        assert code == H.NB_ERR_HIP and "nb_pme_workspace_bytes" in H.last_error()
     g = P(G(32, 30, 27))
-    assert lib.nb_pme_reciprocal(ctypes.byref(s), ctypes.byref(p), g, FAKE, need - 1, FAKE, None, None, None) \
+    # workspaces smaller than the grids alone are refused before the plans are made
+    assert lib.nb_pme_reciprocal(ctypes.byref(s), ctypes.byref(p), g, FAKE, grids - 1, FAKE, None, None, None) \
         == H.NB_ERR_WORKSPACE
-    assert lib.nb_pme_reciprocal(ctypes.byref(s), ctypes.byref(p), g, FAKE + 8, need, FAKE, None, None, None) \
+    assert lib.nb_pme_reciprocal(ctypes.byref(s), ctypes.byref(p), g, FAKE + 8, grids, FAKE, None, None, None) \
         == H.NB_ERR_WORKSPACE
-    assert lib.nb_pme_reciprocal(ctypes.byref(s), ctypes.byref(p), g, FAKE, need, None, None, None, None) \
+    assert lib.nb_pme_reciprocal(ctypes.byref(s), ctypes.byref(p), g, FAKE, grids, None, None, None, None) \
         == H.NB_ERR_ARG  # force is required
-    assert lib.nb_pme_reciprocal(ctypes.byref(s), ctypes.byref(p), P(G(2, 30, 27)), FAKE, need, FAKE, None, None,
+    assert lib.nb_pme_reciprocal(ctypes.byref(s), ctypes.byref(p), P(G(2, 30, 27)), FAKE, grids, FAKE, None, None,
                                  None) == H.NB_ERR_ARG
     p0 = H.make_params(9.0, 0.0)
-    assert lib.nb_pme_reciprocal(ctypes.byref(s), ctypes.byref(p0), g, FAKE, need, FAKE, None, None, None) \
+    assert lib.nb_pme_reciprocal(ctypes.byref(s), ctypes.byref(p0), g, FAKE, grids, FAKE, None, None, None) \
         == H.NB_ERR_ARG and "beta" in H.last_error()
+
+
+_CATCH_ALL_CHILD = r"""
+import ctypes, resource, sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from paper_0902_0827_amd import nbhip as H
+lib = H.load_library()
+B = 4_000_000  # the plan's per-system table (128 bytes each) needs 512 MB of host memory
+off = np.zeros(B + 1, np.int64)
+box = np.full(3 * B, 2.5)
+s = H.nb_system()
+s.n_systems = B
+s.atom_offset = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+s.box = box.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+s.lj_sigma = s.lj_eps = 0x7F0000000000
+s.n_types = 2
+p = H.make_params(1.0, 0.34, cell_div_xy=1, cell_div_z=1)  # 8 cells per system
+n = ctypes.c_size_t()
+ok = lib.nb_workspace_bytes(ctypes.byref(s), ctypes.byref(p), ctypes.byref(n))
+# cap the address space just above what the process maps now: the next large host
+# allocation inside the library fails with std::bad_alloc
+with open("/proc/self/statm") as f:
+    pages = int(f.read().split()[0])
+cap = pages * resource.getpagesize() + (64 << 20)
+resource.setrlimit(resource.RLIMIT_AS, (cap, cap))
+code = lib.nb_workspace_bytes(ctypes.byref(s), ctypes.byref(p), ctypes.byref(n))
+print(ok, code, H.last_error())
+"""
+
+
+def test_no_exception_crosses_the_abi():
+    """An allocation failure inside an entry point comes back as NB_ERR_HOST with a
+    message, not as a C++ exception through the C interface (which would abort)."""
+    import subprocess
+    import sys
+    res = subprocess.run([sys.executable, "-c", _CATCH_ALL_CHILD, ROOT], capture_output=True, text=True,
+                         timeout=300)
+    assert res.returncode == 0, res.stderr[-2000:]
+    ok, code, msg = res.stdout.strip().split(" ", 2)
+    assert int(ok) == H.NB_OK  # the same call succeeds without the cap
+    assert int(code) == H.NB_ERR_HOST and "out of host memory" in msg

@@ -157,3 +157,14 @@ def test_tiny_and_empty_systems():
         np.testing.assert_allclose(vir[b], ref["virial"], rtol=1e-12, atol=1e-12 * np.abs(ref["virial"]).max())
     assert energy[1] == 0.0 and not vir[1].any()
     assert status == 0
+
+
+def test_all_empty_batch_writes_zero_energies_and_virials():
+    """A batch whose systems hold no atoms launches no per-atom work, but every system's
+    energy and virial are still written (zeros), as for an empty system among others."""
+    _, empty = _two_and_empty()
+    _print_case("ewald-all-empty")
+    force, energy, vir, status = gpu_ewald([empty, empty], H.NB_MIXED)
+    assert force.shape == (0, 3)
+    assert not energy.any() and not vir.any()
+    assert status == 0

@@ -63,8 +63,9 @@ def test_binning_is_the_stable_counting_sort(divs, precision, chain):
 
 @pytest.mark.parametrize("divs", [(2, 2), (2, 8), (2, 16), (3, 12), pytest.param((4, 16), marks=pytest.mark.skip(
     reason="took a GPU memory fault under a cross-lane (DPP) variant of the wave scans that has since "
-           "been removed; the cause was not shown, so the case stays off the GPU this round (the "
-           "multi-workgroup scan is covered by (2, 16) and (3, 12) here and by the large tests)"))])
+           "been removed, without its cause shown; four cells per cutoff in x and y is now refused by "
+           "the library (NB_ERR_ARG, checked on the CPU), so the case does not run (the multi-workgroup "
+           "scan is covered by (2, 16) and (3, 12) here and by the million-atom tests)"))])
 def test_binning_at_full_size_config2(divs):
     """(2, 2) and (2, 8) scan in the scatter launch (cell counts fit in LDS); (2, 16),
     17,914 cells, and (3, 12), 28,519 cells, take the multi-workgroup scan: two tiles of
@@ -158,7 +159,7 @@ def test_split_and_cluster_size_give_the_same_forces(precision, K, chain):
     outs = [U.gpu_eval(chain, precision, kernel=H.NB_KERNEL_CLUSTER, split=k, cluster_size=K, backward=True)
             for k in (1, 2, 3, 4, 8)]
     for o in outs:
-        assert U.rel_rms(o["force"], ref["force"]) <= tol
+        U.assert_forces(o["force"], ref["force"], precision, tol)
         assert U.rel_rms(o["grad_charge"], ref["phi"]) <= tol
         # mixed: on the scale of sum |E_i| (see test_forces_energy_virial_match_oracle)
         scale = abs(ref["energy_total"]) if precision == H.NB_FP64 else np.abs(ref["energy"]).sum()
@@ -196,9 +197,9 @@ def test_forces_energy_virial_match_oracle(which, precision, kernel, chain):
     out = U.gpu_eval(s, precision, kernel=kernel, energy_call=True)
     ref = U.oracle_for(s, precision)
     tol = FP64_TOL if precision == H.NB_FP64 else MIXED_TOL
-    err = U.rel_rms(out["force"], ref["force"])
-    print(f"  rel_rms={err:.3e} max_rel_atom={U.max_rel_atom(out['force'], ref['force']):.3e}")
-    assert err <= tol
+    print(f"  rel_rms={U.rel_rms(out['force'], ref['force']):.3e} "
+          f"max_rel_atom={U.max_rel_atom(out['force'], ref['force']):.3e}")
+    U.assert_forces(out["force"], ref["force"], precision, tol)
     if precision == H.NB_FP64:
         assert out["energy"][0] == pytest.approx(ref["energy_total"], rel=tol, abs=tol)
     else:
@@ -231,9 +232,9 @@ def test_cell_grid_choice_does_not_change_the_result(kernel, chain):
     ref32 = U.oracle_for(chain, H.NB_MIXED)
     for divs in [(1, 1), (2, 2), (2, 8), (3, 3), (4, 16), (1, 12)]:
         out = U.gpu_eval(chain, H.NB_FP64, cell_div_xy=divs[0], cell_div_z=divs[1], kernel=kernel)
-        assert U.rel_rms(out["force"], ref["force"]) <= FP64_TOL, divs
+        U.assert_forces(out["force"], ref["force"], H.NB_FP64, FP64_TOL)
         out = U.gpu_eval(chain, H.NB_MIXED, cell_div_xy=divs[0], cell_div_z=divs[1], kernel=kernel)
-        assert U.rel_rms(out["force"], ref32["force"]) <= MIXED_TOL, divs
+        U.assert_forces(out["force"], ref32["force"], H.NB_MIXED, MIXED_TOL)
 
 
 def test_relabelled_atoms_give_permuted_forces(chain):
@@ -293,7 +294,7 @@ def test_non_cubic_box_other_cutoffs_and_bare_coulomb(cutoff, beta, precision, k
     e_err = abs(out["energy"][0] - ref["energy_total"]) / scale
     v_err = U.rel_rms(out["virial"][0], ref["virial"])
     print(f"  rel_rms={err:.3e} energy/sum|E_i|={e_err:.3e} virial={v_err:.3e}")
-    assert err <= tol
+    U.assert_forces(out["force"], ref["force"], precision, tol)
     assert e_err <= tol
     assert v_err <= (1e-11 if precision == H.NB_FP64 else 1e-5)
     assert U.rel_rms(out["atom_energy"], ref["energy"]) <= (1e-11 if precision == H.NB_FP64 else 1e-5)
@@ -317,7 +318,7 @@ def test_net_force_vanishes_and_translation_leaves_the_result(precision, kernel,
     # the mixed path sees the FP32 rounding of the moved positions: compare with the oracle
     ref = U.oracle_for(moved, precision)
     tol = FP64_TOL if precision == H.NB_FP64 else MIXED_TOL
-    assert U.rel_rms(out2["force"], ref["force"]) <= tol
+    U.assert_forces(out2["force"], ref["force"], precision, tol)
     assert U.rel_rms(out2["force"], out["force"]) <= (1e-12 if precision == H.NB_FP64 else 1e-5)
     assert out2["energy"][0] == pytest.approx(out["energy"][0], rel=1e-12 if precision == H.NB_FP64 else 1e-5)
 
@@ -367,7 +368,7 @@ def test_positions_outside_the_box_are_wrapped(precision, kernel, chain):
     moved.pos = chain.pos + shift
     out = U.gpu_eval(moved, precision, kernel=kernel)
     ref = U.oracle_for(moved, precision)
-    assert U.rel_rms(out["force"], ref["force"]) <= (1e-11 if precision == H.NB_FP64 else MIXED_TOL)
+    U.assert_forces(out["force"], ref["force"], precision, 1e-11 if precision == H.NB_FP64 else MIXED_TOL)
 
 
 def test_device_status_bits():
@@ -399,7 +400,7 @@ def test_backward_matches_oracle_gradients(precision, which, kernel, chain):
     out = U.gpu_eval(s, precision, kernel=kernel, backward=True, grad_energy=[g])
     ref = U.oracle_for(s, precision)
     tol = 1e-11 if precision == H.NB_FP64 else MIXED_TOL
-    assert U.rel_rms(out["grad_pos"], -g * ref["force"]) <= tol
+    U.assert_forces(out["grad_pos"], -g * ref["force"], precision, tol)
     assert U.rel_rms(out["grad_charge"], g * ref["phi"]) <= tol
     present = np.unique(s.type)
     lj = present[s.eps[present] > 0]
@@ -472,11 +473,11 @@ def test_config5_mixed_against_sampled_oracle_and_fp64_gpu():
     assert err <= MIXED_TOL
     rows = np.random.default_rng(5).choice(s.n, 96, replace=False)
     ref32 = U.oracle_for(s, H.NB_MIXED, rows=rows)
-    assert U.rel_rms(mixed["force"][rows], ref32["force"]) <= MIXED_TOL
-    assert U.rel_rms(fp64_same_in["force"][rows], ref32["force"]) <= FP64_TOL
+    U.assert_forces(mixed["force"][rows], ref32["force"], H.NB_MIXED, MIXED_TOL)
+    U.assert_forces(fp64_same_in["force"][rows], ref32["force"], H.NB_FP64, FP64_TOL)
     fp64 = U.gpu_eval(s, H.NB_FP64)
     ref64 = U.oracle_for(s, H.NB_FP64, rows=rows)
-    assert U.rel_rms(fp64["force"][rows], ref64["force"]) <= FP64_TOL
+    U.assert_forces(fp64["force"][rows], ref64["force"], H.NB_FP64, FP64_TOL)
 
 
 @pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
@@ -519,7 +520,7 @@ def test_config5_adjoint_identities_sampled_oracle_and_fp64_gpu(precision):
     rows = np.random.default_rng(55).choice(s.n, 96, replace=False)
     ref = O.evaluate_system(s, rows=rows, ke=H.COULOMB_K)
     assert U.rel_rms(out["grad_charge"][rows], ref["phi"]) <= (FP64_TOL if precision == H.NB_FP64 else MIXED_TOL)
-    assert U.rel_rms(out["grad_pos"][rows], -ref["force"]) <= (FP64_TOL if precision == H.NB_FP64 else MIXED_TOL)
+    U.assert_forces(out["grad_pos"][rows], -ref["force"], precision, FP64_TOL if precision == H.NB_FP64 else MIXED_TOL)
     if precision == H.NB_MIXED:  # against the FP64 GPU path on the same inputs
         ref64 = U.gpu_eval(s, H.NB_FP64, backward=True)
         for k in ("grad_pos", "grad_charge"):

@@ -175,3 +175,45 @@ def test_tiny_and_empty_systems():
     check(force[0:2], energy[0], vir[0], ref)
     check(force[2:4], energy[2], vir[2], ref)
     assert energy[1] == 0.0 and not vir[1].any()
+
+
+def test_more_systems_than_one_launch_takes():
+    """40 replicas (more than the 32 systems a launch of the spread, convolution and
+    gather carries): sampled replicas, the first and last of each launch, against the
+    oracle."""
+    systems = [S.water_box(60 + 3 * k, 13.0 + 0.1 * k, seed=100 + k) for k in range(40)]
+    grid = (16, 18, 20)
+    _print_case("pme-40-replicas", grid=grid)
+    force, energy, vir = gpu_pme(systems, H.NB_FP64, grid)
+    offs = np.concatenate([[0], np.cumsum([s.n for s in systems])])
+    for b in (0, 31, 32, 39):
+        s = systems[b]
+        ref = PO.spme_reciprocal(s.pos, s.charge, s.box, s.beta, grid)
+        check(force[offs[b]:offs[b + 1]], energy[b], vir[b], ref)
+
+
+def test_two_streams_with_two_workspaces():
+    """Two calls with the same grid shape and batch size (so the same FFT plans) on two
+    streams, each with its own workspace: each gives what it gives alone, because the FFT
+    work area lives in the caller's workspace."""
+    s1, s2 = U.cached_config(1), noncubic()
+    grid = (20, 20, 20)
+    _print_case("pme-two-streams", grid=grid)
+    alone = [gpu_pme(s, H.NB_FP64, grid) for s in (s1, s2)]
+    batches = [H.device_batch([s], dtype=torch.float64) for s in (s1, s2)]
+    params = [H.make_params(s.cutoff, s.beta, H.NB_FP64) for s in (s1, s2)]
+    wss = [H.alloc_pme_workspace(b, grid) for b in batches]
+    outs = [(torch.zeros((b.n_atoms, 3), dtype=torch.float64, device="cuda"),
+             torch.zeros(1, dtype=torch.float64, device="cuda"),
+             torch.zeros((1, 3, 3), dtype=torch.float64, device="cuda")) for b in batches]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for k in range(2):
+            with torch.cuda.stream(streams[k]):
+                H.pme_reciprocal(batches[k], params[k], grid, wss[k], *outs[k])
+    torch.cuda.synchronize()
+    for k in range(2):
+        f, e, v = (t.cpu().numpy() for t in outs[k])
+        np.testing.assert_allclose(f, alone[k][0], rtol=0, atol=1e-13 * np.abs(alone[k][0]).max())
+        assert abs(e[0] - alone[k][1][0]) <= 1e-13 * abs(alone[k][1][0])
