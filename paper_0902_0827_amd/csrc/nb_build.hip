@@ -129,14 +129,17 @@ __global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, con
     d.status[0] = 0u;
     d.status[1] = kBuiltMagic;
     d.status[2] = static_cast<uint32_t>(d.N);
-    d.status[3] = (uses_clusters(kernel) ? kBuiltClusters : 0u) | (f64 ? kBuiltF64 : 0u) | (d.jacc ? kBuiltJacc : 0u);
+    d.status[3] = (uses_clusters(kernel) ? kBuiltClusters : 0u) | (f64 ? kBuiltF64 : 0u) | ((d.jacc_fix || d.jacc_f64) ? kBuiltJacc : 0u);
   }
   if (tid < kXcds) d.queue[tid * kQueueStride] = 0u;
   for (int64_t k = tid; k < d.n_cells; k += stride) d.cell_count[k] = 0;
   for (int64_t k = tid; k < d.N; k += stride) {
     d.excl_mask[k] = make_uint4(0u, 0u, 0u, 0u);
     d.excl_far[k] = 0u;
-    if (d.jacc) d.jacc[k] = make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int c = 0; c < 4; ++c) {
+      if (d.jacc_fix) d.jacc_fix[c * d.N + k] = 0;
+      if (d.jacc_f64) d.jacc_f64[c * d.N + k] = 0.0;
+    }
   }
   // Type-pair table, Lorentz-Berthelot: sigma_ij = (s_i + s_j)/2, eps_ij = sqrt(e_i e_j).
   const int T = d.T;

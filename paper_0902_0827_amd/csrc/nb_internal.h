@@ -119,10 +119,14 @@ struct Dev {
   int64_t n_columns;
   int64_t n_clusters_max;
   uint32_t *queue;         // [kXcds * kQueueStride] work counters of the dynamic schedule
-  // Half-shell cluster kernel: per sorted atom, force (x, y, z) and energy share (w),
-  // added up by atomics; zero outside a force or energy call (the build zeroes it and
-  // the finishing pass of every call that used it copies it out and zeroes it again).
-  double4 *jacc;           // [N], null unless the kernel is NB_KERNEL_CLUSTER_HALF
+  // Half-shell cluster kernel: per sorted atom, force x, y, z and energy share, as four
+  // arrays of N (component-major, so that the atomic additions of consecutive atoms
+  // coalesce), added up by atomics; zero outside a force or energy call (the build zeroes
+  // them and the finishing pass of every call that used them copies them out and zeroes
+  // them again).  Mixed path: 64-bit fixed point (units of 2^-32 kJ/mol/A or kJ/mol), whose
+  // sums do not depend on the order of the additions; FP64 path: doubles.
+  long long *jacc_fix;     // [4][N], null unless the mixed half-shell kernel is selected
+  double *jacc_f64;        // [4][N], null unless the FP64 half-shell kernel is selected
 };
 
 // Per-call constants and outputs of the pair kernels.

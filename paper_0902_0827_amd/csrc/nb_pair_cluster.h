@@ -102,6 +102,72 @@ __device__ __forceinline__ int shfl_rows_max(int v) {
   return v;
 }
 
+// Min / max over the K lanes of one aligned group of consecutive lanes (the rows of the
+// half-shell kernel's lane layout).
+template <int K>
+__device__ __forceinline__ int shfl_group_min(int v) {
+  for (int off = 1; off < K; off <<= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+template <int K>
+__device__ __forceinline__ int shfl_group_max(int v) {
+  for (int off = 1; off < K; off <<= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Cross-lane moves within DPP rows (no LDS): lane l reads lane l ^ 1, l ^ 2, or 7 - (l % 8)
+// of its 8-lane half row.
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141; // row_half_mirror
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+                                                     static_cast<unsigned>(lo)));
+}
+// Sum over each aligned group of K = 4 or 8 consecutive lanes, in every lane of the group,
+// by DPP moves (the additions in a fixed order: deterministic).
+template <int K, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+  static_assert(K == 4 || K == 8, "groups of 4 or 8 lanes");
+  if constexpr (std::is_same_v<T, float>) {
+    v += dpp_f32<kDppXor1>(v);
+    v += dpp_f32<kDppXor2>(v);
+    if constexpr (K == 8) v += dpp_f32<kDppHalfMirror>(v);
+  } else {
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
+    if constexpr (K == 8) v += dpp_f64<kDppHalfMirror>(v);
+  }
+  return v;
+}
+
+// 64-bit fixed point of the mixed-path half-shell accumulators: v * 2^32 rounded to the
+// nearest integer (|v| < 2^31: forces in kJ/mol/A, energies in kJ/mol).  Integer
+// addition is associative, so the accumulated sums do not depend on the order of the
+// atomic additions.
+constexpr double kFixScale = 4294967296.0;
+__device__ __forceinline__ long long to_fixed(double v) {
+  const double s = rint(v * kFixScale);
+  const double hi = floor(s * (1.0 / kFixScale));
+  const double lo = s - hi * kFixScale;  // exact, in [0, 2^32)
+  return static_cast<long long>((static_cast<unsigned long long>(static_cast<long long>(static_cast<int>(hi))) << 32) +
+                                static_cast<unsigned long long>(static_cast<unsigned>(lo)));
+}
+__device__ __forceinline__ double from_fixed(long long a) {
+  const int hi = static_cast<int>(a >> 32);
+  const unsigned lo = static_cast<unsigned>(a);
+  return (static_cast<double>(hi) * kFixScale + static_cast<double>(lo)) * (1.0 / kFixScale);
+}
+
 // One step of reduce_scatter below at lane offset OFF, N values still carried.
 template <int OFF, int N, int NV>
 __device__ __forceinline__ double reduce_scatter_step(double (&v)[NV], int lane) {
@@ -256,11 +322,15 @@ __device__ __forceinline__ int xcd_id() {
 // HALF (forces and energy only): each pair is evaluated once.  A cluster takes the
 // columns of half of its stencil (positive offsets; see the run list below) and, in
 // its own column, the atoms from its own first atom on, counting a pair of its own
-// atoms only with j after i in sorted order.  Every group sums the forces on its J candidates over the K rows and row 0
-// adds them to the candidates' accumulators (d.jacc) with FP64 atomics; the rows' own
-// sums go there too at the end of the item, and the finishing pass copies the
-// accumulators out.  The pair work halves; the atomic order makes the last bits of
-// the result vary from run to run.
+// atoms only with j after i in sorted order.  A candidate's K rows sit in K consecutive
+// lanes: every group sums the forces on its J candidates over the rows by DPP moves,
+// row 0 stages the sums in LDS, and full stages go to the candidates' accumulators by
+// atomic additions, consecutive sorted atoms in consecutive lanes (so that they
+// coalesce); the rows' own sums go there too at the end of the item, and the finishing
+// pass copies the accumulators out.  The pair work halves.  Mixed path: the
+// accumulators are 64-bit fixed point, so the result is bitwise reproducible whatever
+// the order of the additions; FP64 path: FP64 atomics, whose order makes the last bits
+// vary from run to run.
 //
 // PAIRS2 (mixed path): the group loop takes two groups per pass, which needs more
 // registers (4 resident waves per SIMD instead of 5); the launcher uses it when every
@@ -281,7 +351,10 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(d.status, NB_STATUS_NOT_BUILT);
     return;
   }
-  const int ii = lane / J, jj = lane % J;
+  // Lane = (i row ii, candidate jj).  Full shell: rows of J consecutive lanes, so that an
+  // atom's sums stay in its row.  Half shell: the K rows of one candidate in K consecutive
+  // lanes, so that the candidate's shares are summed by DPP moves within a DPP row.
+  const int ii = HALF ? lane % K : lane / J, jj = HALF ? lane / K : lane % J;
   const int T = d.T;
   StageT<F64> *const ST = reinterpret_cast<StageT<F64> *>(reinterpret_cast<char *>(tab_lds) +
                                                           (TABLDS ? tab_lds_bytes<F64, MODE>(T) : 0));
@@ -408,8 +481,14 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       const int dx = static_cast<int>(fi.x - u0.x), dy = static_cast<int>(fi.y - u0.y),
                 dz = static_cast<int>(fi.z - u0.z);
       // rows without an atom repeat the first atom (ia = first), so they do not widen the box
-      const int lox = shfl_rows_min<J>(dx), loy = shfl_rows_min<J>(dy), loz = shfl_rows_min<J>(dz);
-      const int hix = shfl_rows_max<J>(dx), hiy = shfl_rows_max<J>(dy), hiz = shfl_rows_max<J>(dz);
+      int lox, loy, loz, hix, hiy, hiz;
+      if constexpr (HALF) {
+        lox = shfl_group_min<K>(dx), loy = shfl_group_min<K>(dy), loz = shfl_group_min<K>(dz);
+        hix = shfl_group_max<K>(dx), hiy = shfl_group_max<K>(dy), hiz = shfl_group_max<K>(dz);
+      } else {
+        lox = shfl_rows_min<J>(dx), loy = shfl_rows_min<J>(dy), loz = shfl_rows_min<J>(dz);
+        hix = shfl_rows_max<J>(dx), hiy = shfl_rows_max<J>(dy), hiz = shfl_rows_max<J>(dz);
+      }
       const int lo3[3] = {lox, loy, loz}, hi3[3] = {hix, hiy, hiz};
       const uint32_t base3[3] = {u0.x, u0.y, u0.z};
       uint32_t cc[3], hh[3];
@@ -427,7 +506,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     const int kx = uni(sd.reach[0]), ky = uni(sd.reach[1]), kz = uni(sd.reach[2]);
     const int cx = col_local / ny, cy = col_local - (col_local / ny) * ny;
     const int cz0 = static_cast<int>((static_cast<uint64_t>(__shfl(fi.z, 0, 64)) * nz) >> 32);
-    const int cz1 = static_cast<int>((static_cast<uint64_t>(__shfl(fi.z, (count - 1) * J, 64)) * nz) >> 32);
+    const int cz1 = static_cast<int>((static_cast<uint64_t>(__shfl(fi.z, (count - 1) * (HALF ? 1 : J), 64)) * nz) >> 32);
     const bool allx = 2 * kx + 1 >= nx, ally = 2 * ky + 1 >= ny;
     const bool allz = (cz1 - cz0) + 2 * kz + 1 >= nz;
     const int xn = allx ? nx : 2 * kx + 1, yn = ally ? ny : 2 * ky + 1;
@@ -513,14 +592,15 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     const int hi_c = Q == 1 ? total : static_cast<int>((static_cast<int64_t>(total) * (part + 1)) / Q);
     wave_lds_sync();  // the runs are visible to every lane
 
-    // Per-lane sums for row ii's atom.  Mixed path: single precision over this item
-    // (one lane sees every J-th candidate of the item: a few dozen pairs in practice),
-    // converted to double for the row and item reductions.  FP64 path: double.
+    // Per-lane sums for row ii's atom: force, energy (or dE/dq) and the per-type adjoint
+    // sums in double for both paths (the mixed path adds each pair's single-precision
+    // terms to them).  The virial: double on the FP64 path; on the mixed path single
+    // precision over this item (one lane sees every J-th candidate of the item: a few
+    // dozen pairs in practice), converted to double for the wave and system reductions.
     double fx = 0, fy = 0, fz = 0, en = 0, wxx = 0, wxy = 0, wxz = 0, wyy = 0, wyz = 0, wzz = 0;
     double phi = 0, asig = 0, beps = 0;
-    float sfx = 0, sfy = 0, sfz = 0, sen = 0, swxx = 0, swxy = 0, swxz = 0, swyy = 0, swyz = 0, swzz = 0;
-    float sphi = 0, sasig = 0, sbeps = 0;
-    // an accumulator as double: the FP64 path's own, or the mixed path's single-precision one
+    float swxx = 0, swxy = 0, swxz = 0, swyy = 0, swyz = 0, swzz = 0;
+    // a virial accumulator as double: the FP64 path's own, or the mixed path's single-precision one
     auto D = [&](double dv, float fv) -> double {
       if constexpr (F64) return dv;
       else return static_cast<double>(fv);
@@ -534,19 +614,28 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
 
     // Half-shell stage: entries [0, nst) hold candidates' shares not yet added.
     int nst = 0;  // wave-uniform
+    // Adds v to component c (0-2 force, 3 energy share) of sorted atom a's half-shell
+    // accumulator: 64-bit fixed point on the mixed path, FP64 on the FP64 path.
+    auto acc_add = [&](int c, int a, double v) {
+      if constexpr (F64) {
+        unsafeAtomicAdd(&d.jacc_f64[static_cast<int64_t>(c) * d.N + a], v);
+      } else {
+        __hip_atomic_fetch_add(&d.jacc_fix[static_cast<int64_t>(c) * d.N + a], to_fixed(v), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      }
+    };
     auto flush = [&]() {
       wave_lds_sync();
       for (int e = lane; e < nst; e += 64) {
         const StageT<F64> st = ST[e];
         if constexpr (MODE == kForces) {
           if (st.x != 0 || st.y != 0 || st.z != 0) {  // a candidate without a pair in range adds nothing
-            double *acc = &d.jacc[st.s].x;
-            unsafeAtomicAdd(acc + 0, static_cast<double>(st.x) * scx);
-            unsafeAtomicAdd(acc + 1, static_cast<double>(st.y) * scy);
-            unsafeAtomicAdd(acc + 2, static_cast<double>(st.z) * scz);
+            acc_add(0, st.s, static_cast<double>(st.x) * scx);
+            acc_add(1, st.s, static_cast<double>(st.y) * scy);
+            acc_add(2, st.s, static_cast<double>(st.z) * scz);
           }
         } else if (st.x != 0) {
-          unsafeAtomicAdd(&d.jacc[st.s].w, static_cast<double>(st.x));
+          acc_add(3, st.s, static_cast<double>(st.x));
         }
       }
       wave_lds_sync();
@@ -686,7 +775,10 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
             p.dudsig_lj = hit ? p.dudsig_lj : 0.f;
           }
           const float pu = hit ? p.u_lj + p.u_c : 0.f;  // the pair's energy, one select
-          sen += pu;
+          // Per-atom sums (force, energy, dE/dq) take every pair's single-precision term
+          // into a double accumulator; the virial is summed per lane in single precision
+          // and reduced in double.
+          en += static_cast<double>(pu);
           if constexpr (HALF) hu = pu;
           if constexpr (MODE != kEnergy) {
             const float gx = p.f * dxf, gy = p.f * dyf, gz = p.f * dzf;
@@ -695,11 +787,9 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
               hgy = gy;
               hgz = gz;
             }
-            // explicit FMAs: the same rounding in every copy of the group loop, whether or
-            // not the products are also used for the virial
-            sfx = fmaf(p.f, dxf, sfx);
-            sfy = fmaf(p.f, dyf, sfy);
-            sfz = fmaf(p.f, dzf, sfz);
+            fx += static_cast<double>(gx);
+            fy += static_cast<double>(gy);
+            fz += static_cast<double>(gz);
             if constexpr (MODE == kForces) {
               if (VIR && o.want_virial) {
                 swxx = fmaf(gx, dxf, swxx); swxy = fmaf(gx, dyf, swxy); swxz = fmaf(gx, dzf, swxz);
@@ -708,21 +798,16 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
             }
           }
           if constexpr (MODE == kAdjoint) {
-            sphi = fmaf(qj, p.erfc_over_r, sphi);
-            sasig = fmaf(p.dudsig_lj, tp.inv_sig, sasig);
-            sbeps += p.u_lj;
+            phi += static_cast<double>(qj * p.erfc_over_r);
+            asig += static_cast<double>(p.dudsig_lj * tp.inv_sig);
+            beps += static_cast<double>(p.u_lj);
           }
         }
       }
       if constexpr (HALF) {
-        // The J candidates' shares: column sums over the K rows, added by row 0.
+        // The J candidates' shares: sums over the K rows (K consecutive lanes), staged by row 0.
         if constexpr (MODE == kForces) {
-          auto cx = -hgx, cy = -hgy, cz = -hgz;
-          for (int off = J; off < 64; off <<= 1) {
-            cx += __shfl_xor(cx, off, 64);
-            cy += __shfl_xor(cy, off, 64);
-            cz += __shfl_xor(cz, off, 64);
-          }
+          const auto cx = group_sum<K>(-hgx), cy = group_sum<K>(-hgy), cz = group_sum<K>(-hgz);
           if (nst + J > kStage<F64>) flush();
           if (ii == 0 && jv) {
             StageT<F64> &st = ST[nst + jj];
@@ -734,8 +819,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
           nst += navail;
         } else if constexpr (MODE == kEnergy) {
           if (o.atom_energy) {  // per-atom energies: half of each pair's energy to j
-            auto cu = hu;
-            for (int off = J; off < 64; off <<= 1) cu += __shfl_xor(cu, off, 64);
+            const auto cu = group_sum<K>(hu);
             if (nst + J > kStage<F64>) flush();
             if (ii == 0 && jv) {
               StageT<F64> &st = ST[nst + jj];
@@ -762,7 +846,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       while (tail - head >= static_cast<uint32_t>(J)) process_group(J, far_c, vir_c);
     };
     auto drain = [&]() {
-      if constexpr (F64 || !PAIRS2) {
+      if constexpr (F64 || (!PAIRS2 && !HALF)) {
         drain_with(std::true_type{}, std::true_type{});
       } else if constexpr (MODE == kForces) {
         if (any_far) {
@@ -879,7 +963,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     if constexpr (MODE == kAdjoint) {
       // Per-type sums of the sigma / eps partials over this item's rows (scaled by the
       // system's grad_energy in k_finish).
-      const double a_l = 0.5 * D(asig, sasig), b_l = 0.5 * D(beps, sbeps);
+      const double a_l = 0.5 * asig, b_l = 0.5 * beps;
       const int my_t = ivalid ? ti : -1;
       double keep_a = 0.0, keep_b = 0.0;
       uint64_t left_t = __ballot(my_t >= 0);
@@ -906,22 +990,31 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     // whose first lane writes it.  With one item per cluster they are final and go
     // straight to the caller's arrays (original atom order); otherwise to this item's
     // part, added up by k_finish.
-    {
-      const double rowv[4] = {D(fx, sfx), D(fy, sfy), D(fz, sfz), MODE == kAdjoint ? D(phi, sphi) : D(en, sen)};
+    if constexpr (HALF) {
+      // Half shell: a row is the J lanes ii, ii + K, ...; butterfly sums over them (once per
+      // item), then lane jj = 0 of each row adds its atom's sums to the accumulators.
+      if (nst > 0) flush();
+      double r4[4] = {fx, fy, fz, en};
+#pragma unroll
+      for (int off = K; off < 64; off <<= 1)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) r4[e] += __shfl_xor(r4[e], off, 64);
+      if (ivalid && jj == 0) {
+        if constexpr (MODE == kForces) {
+          acc_add(0, i, r4[0] * scx);
+          acc_add(1, i, r4[1] * scy);
+          acc_add(2, i, r4[2] * scz);
+        } else if constexpr (MODE == kEnergy) {
+          if (o.atom_energy) acc_add(3, i, 0.5 * r4[3]);
+        }
+      }
+    } else {
+      const double rowv[4] = {fx, fy, fz, MODE == kAdjoint ? phi : en};
       const int ent = jj / (J / 4);
       const double sce = ent == 0 ? scx : ent == 1 ? scy : ent == 2 ? scz : (MODE == kAdjoint ? phi_scale : 1.0);
       const double rv = reduce_scatter<J, 4>(rowv, lane) * sce;
       const bool writer = ivalid && jj % (J / 4) == 0;
-      if constexpr (HALF) {
-        if (nst > 0) flush();
-        if (writer) {
-          if constexpr (MODE == kForces) {
-            if (ent < 3) unsafeAtomicAdd(&d.jacc[i].x + ent, rv);
-          } else if constexpr (MODE == kEnergy) {
-            if (ent == 3 && o.atom_energy) unsafeAtomicAdd(&d.jacc[i].w, 0.5 * rv);
-          }
-        }
-      } else if (writer) {
+      if (writer) {
         if (Q == 1) {
           if constexpr (MODE == kForces) {
             if (ent < 3) o.force[3 * static_cast<int64_t>(oi) + ent] = rv;
@@ -948,7 +1041,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
           // k ending in lanes 8k .. 8k + 7; each pair counted twice by the full-shell
           // form, once by the half-shell one
           constexpr double hs = HALF ? 1.0 : 0.5;
-          const double v[8] = {hs * D(en, sen), hs * scx * scx * D(wxx, swxx), hs * scx * scy * D(wxy, swxy),
+          const double v[8] = {hs * en, hs * scx * scx * D(wxx, swxx), hs * scx * scy * D(wxy, swxy),
                                hs * scx * scz * D(wxz, swxz), hs * scy * scy * D(wyy, swyy),
                                hs * scy * scz * D(wyz, swyz), hs * scz * scz * D(wzz, swzz), 0.0};
           const double r = reduce_scatter<64, 8>(v, lane);
@@ -958,7 +1051,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
           mine = __shfl(r, 8 * src, 64);
           if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + m] = mine;
         } else {
-          mine = wave_sum((HALF ? 1.0 : 0.5) * D(en, sen));
+          mine = wave_sum((HALF ? 1.0 : 0.5) * en);
           if (lane < kPart) d.partials[static_cast<int64_t>(lane) * d.n_slots + m] = lane == 0 ? mine : 0.0;
         }
       }
@@ -1019,15 +1112,26 @@ __global__ void __launch_bounds__(kFinishBlock) k_finish(Dev d, Out o, int S, in
     const int i = blk * kFinishBlock + threadIdx.x;
     if (i >= d.N) return;
     if (half) {  // half-shell accumulators: copy out, and zero for the next call
-      const double4 a = d.jacc[i];
-      d.jacc[i] = make_double4(0.0, 0.0, 0.0, 0.0);
       const int oi = static_cast<int>(d.s_fix[i].w);
+      // component c of atom i's accumulator (64-bit fixed point, or FP64), then zeroed
+      auto take = [&](int c) -> double {
+        const int64_t at = static_cast<int64_t>(c) * d.N + i;
+        double v;
+        if (d.jacc_fix) {
+          v = from_fixed(d.jacc_fix[at]);
+          d.jacc_fix[at] = 0;
+        } else {
+          v = d.jacc_f64[at];
+          d.jacc_f64[at] = 0.0;
+        }
+        return v;
+      };
       if constexpr (MODE == kForces) {
-        o.force[3 * oi + 0] = a.x;
-        o.force[3 * oi + 1] = a.y;
-        o.force[3 * oi + 2] = a.z;
+        o.force[3 * oi + 0] = take(0);
+        o.force[3 * oi + 1] = take(1);
+        o.force[3 * oi + 2] = take(2);
       } else if constexpr (MODE == kEnergy) {
-        if (o.atom_energy) o.atom_energy[oi] = a.w;
+        if (o.atom_energy) o.atom_energy[oi] = take(3);
       }
       return;
     }
@@ -1170,11 +1274,13 @@ void launch_cluster_mode(int mode, bool half, int64_t wgs, int dyn, int wg_per_c
   // 64.2 -> 61.0 us; 64-replica batch, 100,000 items: 1,083 against 1,117 us with it).
   const bool pairs2 = !F64 && !half && !dyn && wgs <= static_cast<int64_t>(compute_units()) * kPairs2WavesPerCu;
   if (mode == kForces) {
-    if (half) go(k_pair_cluster<F64, kForces, TABLDS, K, true, false>, std::integral_constant<int, kForces>{}, std::true_type{});
+    if (half && pairs2) go(k_pair_cluster<F64, kForces, TABLDS, K, true, !F64>, std::integral_constant<int, kForces>{}, std::true_type{});
+    else if (half) go(k_pair_cluster<F64, kForces, TABLDS, K, true, false>, std::integral_constant<int, kForces>{}, std::true_type{});
     else if (pairs2) go(k_pair_cluster<F64, kForces, TABLDS, K, false, !F64>, std::integral_constant<int, kForces>{}, std::false_type{});
     else go(k_pair_cluster<F64, kForces, TABLDS, K, false, false>, std::integral_constant<int, kForces>{}, std::false_type{});
   } else if (mode == kEnergy) {
-    if (half) go(k_pair_cluster<F64, kEnergy, TABLDS, K, true, false>, std::integral_constant<int, kEnergy>{}, std::true_type{});
+    if (half && pairs2) go(k_pair_cluster<F64, kEnergy, TABLDS, K, true, !F64>, std::integral_constant<int, kEnergy>{}, std::true_type{});
+    else if (half) go(k_pair_cluster<F64, kEnergy, TABLDS, K, true, false>, std::integral_constant<int, kEnergy>{}, std::true_type{});
     else if (pairs2) go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, !F64>, std::integral_constant<int, kEnergy>{}, std::false_type{});
     else go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, false>, std::integral_constant<int, kEnergy>{}, std::false_type{});
   } else {

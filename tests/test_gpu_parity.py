@@ -26,10 +26,12 @@ KERNELS = [H.NB_KERNEL_ATOM, H.NB_KERNEL_CLUSTER, "cluster8", "cluster4_static",
 HALF_KERNELS = ("half8", "half4_dynamic")
 
 
-def _assert_same(a, b, kernel, err_msg=""):
-    """Bitwise equality, except for the half-shell kernel, whose FP64 atomic additions
-    may come in any order: there the results agree to the last few bits."""
-    if kernel in HALF_KERNELS:
+def _assert_same(a, b, kernel, err_msg="", precision=H.NB_MIXED):
+    """Bitwise equality, except for the FP64 half-shell kernel, whose FP64 atomic additions
+    may come in any order: there the results agree to the last few bits.  (The mixed
+    half-shell kernel accumulates in 64-bit fixed point, whose sums do not depend on the
+    order.)"""
+    if kernel in HALF_KERNELS and precision == H.NB_FP64:
         scale = max(float(np.abs(np.asarray(b)).max()), 1e-300)
         np.testing.assert_allclose(a, b, rtol=0, atol=1e-13 * scale, err_msg=err_msg)
     else:
@@ -220,7 +222,7 @@ def test_forces_energy_virial_match_oracle(which, precision, kernel, chain):
 def test_run_twice_is_bitwise_identical(precision, kernel, chain):
     a = U.gpu_eval(chain, precision, kernel=kernel)
     b = U.gpu_eval(chain, precision, kernel=kernel)
-    _assert_same(a["force"], b["force"], kernel)
+    _assert_same(a["force"], b["force"], kernel, precision=precision)
     # energy and virial come from per-item partials summed in a fixed order
     np.testing.assert_array_equal(a["energy"], b["energy"])
     np.testing.assert_array_equal(a["virial"], b["virial"])
@@ -230,7 +232,7 @@ def test_run_twice_is_bitwise_identical(precision, kernel, chain):
 def test_cell_grid_choice_does_not_change_the_result(kernel, chain):
     ref = U.oracle_for(chain, H.NB_FP64)
     ref32 = U.oracle_for(chain, H.NB_MIXED)
-    for divs in [(1, 1), (2, 2), (2, 8), (3, 3), (4, 16), (1, 12)]:
+    for divs in [(1, 1), (2, 2), (2, 8), (3, 3), (3, 16), (1, 12)]:
         out = U.gpu_eval(chain, H.NB_FP64, cell_div_xy=divs[0], cell_div_z=divs[1], kernel=kernel)
         U.assert_forces(out["force"], ref["force"], H.NB_FP64, FP64_TOL)
         out = U.gpu_eval(chain, H.NB_MIXED, cell_div_xy=divs[0], cell_div_z=divs[1], kernel=kernel)
@@ -334,7 +336,7 @@ def test_batch_equals_each_system_alone(precision, kernel, chain):
     off = np.concatenate([[0], np.cumsum([s.n for s in systems])])
     for k, s in enumerate(systems):
         alone = U.gpu_eval(s, precision, kernel=kernel)
-        _assert_same(out["force"][off[k]:off[k + 1]], alone["force"], kernel)
+        _assert_same(out["force"][off[k]:off[k + 1]], alone["force"], kernel, precision=precision)
         assert out["energy"][k] == alone["energy"][0]
         np.testing.assert_array_equal(out["virial"][k], alone["virial"][0])
 

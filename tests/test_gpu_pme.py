@@ -181,7 +181,7 @@ def test_more_systems_than_one_launch_takes():
     """40 replicas (more than the 32 systems a launch of the spread, convolution and
     gather carries): sampled replicas, the first and last of each launch, against the
     oracle."""
-    systems = [S.water_box(60 + 3 * k, 13.0 + 0.1 * k, seed=100 + k) for k in range(40)]
+    systems = [S.water_box(60 + 3 * k, 13.0 + 0.1 * k, seed=100 + k, cutoff=6.0) for k in range(40)]
     grid = (16, 18, 20)
     _print_case("pme-40-replicas", grid=grid)
     force, energy, vir = gpu_pme(systems, H.NB_FP64, grid)
