@@ -212,6 +212,24 @@ nb_status nb_pme_reciprocal(const nb_system *sys, const nb_params *params, const
                             void *workspace, size_t workspace_bytes, double *force, double *energy,
                             double *virial, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): nb_build_cells followed by
+ * nb_nonbonded_forces, with the same arguments and results, but with the workspace
+ * taken from a scratch array of NB_NOALLOC_SCRATCH_BYTES (16 MiB) that the library holds
+ * in device memory on every GPU it runs on, from the loading of the library's code until
+ * the process ends.  The caller still passes the outputs.  No hipMalloc, hipFree or
+ * other allocating call is made.  Batches whose workspace (nb_workspace_bytes) exceeds
+ * NB_NOALLOC_SCRATCH_BYTES are refused with NB_ERR_CAPACITY before any work is enqueued
+ * (about 90,000 atoms at the densities of the configurations here).  The first call on a
+ * device looks up that device's copy of the array (hipGetSymbolAddress).  Every call on
+ * a GPU uses the same array, which keeps the last call's contents (the build rewrites
+ * everything the pair kernel reads): calls that overlap on one GPU, on different streams
+ * or from different threads, race and must be ordered by the caller.  The device status
+ * word of the build cannot be read back (no workspace pointer is handed out). */
+#define NB_NOALLOC_SCRATCH_BYTES (16u << 20)
+nb_status nb_nonbonded_forces_noalloc(const nb_system *sys, const nb_params *params, double *force,
+                                      double *energy, double *virial, hipStream_t stream);
+
 /* Synchronises `stream` and returns the NB_STATUS_* bits accumulated in the workspace. */
 nb_status nb_read_status(const void *workspace, hipStream_t stream, uint32_t *flags /*[host]*/);
 

@@ -412,6 +412,20 @@ nb_status nb_pme_reciprocal(const nb_system *sys, const nb_params *params, const
   });
 }
 
+nb_status nb_nonbonded_forces_noalloc(const nb_system *sys, const nb_params *params, double *force,
+                                      double *energy, double *virial, hipStream_t stream) {
+  return guarded("nb_nonbonded_forces_noalloc", [&]() -> nb_status {
+    nb::Plan p;
+    nb_status st = nb::make_plan(sys, params, &p);
+    if (st != NB_OK) return st;
+    if (!force && p.N > 0) return fail(NB_ERR_ARG, "force must not be NULL");
+    std::string why;
+    st = nb::noalloc_forces(p, sys, force, energy, virial, stream, &why);
+    if (st != NB_OK) return fail(st, "nb_nonbonded_forces_noalloc: " + why);
+    return NB_OK;
+  });
+}
+
 nb_status nb_read_status(const void *workspace, hipStream_t stream, uint32_t *flags) {
   return guarded("nb_read_status", [&]() -> nb_status {
     if (!workspace || !flags) return fail(NB_ERR_ARG, "workspace and flags are required");

@@ -182,6 +182,10 @@ hipError_t launch_energy(const Plan &plan, const Dev &d, const nb_system *sys, d
 hipError_t launch_backward(const Plan &plan, const Dev &d, const nb_system *sys,
                            const double *grad_energy, double *grad_pos, double *grad_charge,
                            double *grad_sigma, double *grad_eps, hipStream_t s);
+// Build and forces on the library's own scratch array (nb_noalloc.hip); `why` receives
+// the message of a non-OK return.
+nb_status noalloc_forces(const Plan &p, const nb_system *sys, double *force, double *energy, double *virial,
+                         hipStream_t stream, std::string *why);
 // Cluster pair kernel and its finishing pass (nb_pair_cluster.hip).
 void launch_cluster_pair(const Plan &plan, const Dev &d, const Consts &c, const Out &o, int mode, hipStream_t s,
                          double *energy, double *virial, const double *eps, double *grad_sigma, double *grad_eps);

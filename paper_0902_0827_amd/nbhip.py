@@ -40,7 +40,7 @@ NB_MAX_TYPES = 64
 EXPORTED = ("nb_workspace_bytes", "nb_build_cells", "nb_nonbonded_forces", "nb_nonbonded_energy",
             "nb_nonbonded_backward", "nb_read_status", "nb_last_error", "nb_workspace_layout",
             "nb_pair_timer_start", "nb_pair_timer_stop", "nb_ewald_corrections",
-            "nb_pme_workspace_bytes", "nb_pme_reciprocal")
+            "nb_pme_workspace_bytes", "nb_pme_reciprocal", "nb_nonbonded_forces_noalloc")
 
 
 class NbError(RuntimeError):
@@ -117,6 +117,7 @@ def load_library(path: str = LIB_PATH):
     lib.nb_nonbonded_energy.argtypes = [S, P, V, sz, V, V, V]
     lib.nb_nonbonded_backward.argtypes = [S, P, V, sz, V, V, V, V, V, V]
     lib.nb_ewald_corrections.argtypes = [S, P, V, sz, V, V, V, V]
+    lib.nb_nonbonded_forces_noalloc.argtypes = [S, P, V, V, V, V]
     G = ctypes.POINTER(ctypes.c_int32)
     lib.nb_pme_workspace_bytes.argtypes = [S, G, ctypes.POINTER(ctypes.c_size_t)]
     lib.nb_pme_reciprocal.argtypes = [S, P, G, V, sz, V, V, V, V]
@@ -256,6 +257,13 @@ def nonbonded_forces(batch: DeviceBatch, params: nb_params, ws, force, energy=No
     lib = load_library()
     _check(lib.nb_nonbonded_forces(ctypes.byref(batch.struct()), ctypes.byref(params), _ptr(ws), ws.numel(),
                                    _ptr(force), _ptr(energy), _ptr(virial), _stream(stream)))
+
+
+def nonbonded_forces_noalloc(batch: DeviceBatch, params: nb_params, force, energy=None, virial=None, stream=None):
+    """Build + forces on the library's own scratch array (nb_nonbonded_forces_noalloc)."""
+    lib = load_library()
+    _check(lib.nb_nonbonded_forces_noalloc(ctypes.byref(batch.struct()), ctypes.byref(params), _ptr(force),
+                                           _ptr(energy), _ptr(virial), _stream(stream)))
 
 
 def ewald_corrections(batch: DeviceBatch, params: nb_params, ws, force, energy=None, virial=None, stream=None):

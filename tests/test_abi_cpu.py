@@ -248,3 +248,15 @@ def test_no_exception_crosses_the_abi():
     ok, code, msg = res.stdout.strip().split(" ", 2)
     assert int(ok) == H.NB_OK  # the same call succeeds without the cap
     assert int(code) == H.NB_ERR_HOST and "out of host memory" in msg
+
+
+def test_noalloc_entry_point_refuses_batches_beyond_its_scratch():
+    """The allocation-free entry point checks the batch's workspace against its fixed
+    scratch size before any HIP call."""
+    lib = H.load_library()
+    s = fake_system((300_000, 300_000), L=150.0)
+    p = H.make_params(9.0, 0.34)
+    code = lib.nb_nonbonded_forces_noalloc(ctypes.byref(s), ctypes.byref(p), FAKE, None, None, None)
+    assert code == H.NB_ERR_CAPACITY and "allocation-free" in H.last_error()
+    assert lib.nb_nonbonded_forces_noalloc(ctypes.byref(s), ctypes.byref(p), None, None, None, None) \
+        == H.NB_ERR_ARG  # force is required
