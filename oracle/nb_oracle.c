@@ -21,6 +21,15 @@
  *   f_ij = 24 eps_ij [2 (sigma_ij/r)^12 - (sigma_ij/r)^6] / r^2
  *        + k_e q_i q_j [erfc(beta r) / r^3 + (2 beta / sqrt(pi)) exp(-beta^2 r^2) / r^2]
  *
+ * Force-field options (ACEMD paper, section 3, CHARMM/AMBER support; section 5, the
+ * benchmark's cutoff "switched at 7.5 A"):
+ *   - scaled 1-4 pairs: a pair listed in either atom's 1-4 row (and not excluded) has its
+ *     Lennard-Jones term multiplied by s14_lj and its real-space Coulomb term by s14_c;
+ *   - Lennard-Jones switching from r_on to R (sw_on = r_on > 0): u_LJ is multiplied by
+ *     S(r) = (1 - x)^2 (1 + 2x), x = (r^2 - r_on^2)/(R^2 - r_on^2) clamped to [0, 1]
+ *     (the CHARMM energy switch of Brooks et al., J. Comput. Chem. 4, 187 (1983)); the
+ *     force is -d(S u_LJ)/dr; the Coulomb term is not switched.
+ *
  * The evaluation is "row" based and deliberately plain: for every requested atom
  * i it loops over all N atoms j (an O(N) row, O(N^2) overall), so forces on a
  * subset of atoms (the sampled mode used for million-atom boxes) come from the
@@ -75,15 +84,31 @@ static int sym_exclusions(int64_t n, const int32_t *off, const int32_t *idx,
   return 0;
 }
 
-int nbo_rows(int64_t n, const double *pos, const double *q, const int32_t *type,
-             int32_t ntypes, const double *sigma, const double *eps,
-             const int32_t *excl_off, const int32_t *excl_idx, const double *box,
-             double cutoff, double beta, double ke,
-             int64_t n_rows, const int64_t *rows,
-             double *force, double *energy, double *phi, double *a_sig, double *b_eps,
-             double *virial, double *e_lj_out, double *e_c_out, int64_t *pair_count_out,
-             int nthreads) {
+/* CHARMM switch S(r) and dS/d(r^2) at squared distance r2 (r_on^2 = s_on, R^2 = rc2). */
+static void lj_switch(double r2, double s_on, double rc2, double *S, double *dS_dr2) {
+  double x = (r2 - s_on) / (rc2 - s_on);
+  if (x <= 0.0) {
+    *S = 1.0;
+    *dS_dr2 = 0.0;
+    return;
+  }
+  if (x > 1.0) x = 1.0;
+  *S = (1.0 - x) * (1.0 - x) * (1.0 + 2.0 * x);
+  *dS_dr2 = -6.0 * x * (1.0 - x) / (rc2 - s_on);
+}
+
+int nbo_rows_ff(int64_t n, const double *pos, const double *q, const int32_t *type,
+                int32_t ntypes, const double *sigma, const double *eps,
+                const int32_t *excl_off, const int32_t *excl_idx, const double *box,
+                double cutoff, double beta, double ke,
+                const int32_t *p14_off, const int32_t *p14_idx, double s14_lj, double s14_c,
+                double sw_on,
+                int64_t n_rows, const int64_t *rows,
+                double *force, double *energy, double *phi, double *a_sig, double *b_eps,
+                double *virial, double *e_lj_out, double *e_c_out, int64_t *pair_count_out,
+                int nthreads) {
   if (n < 0 || ntypes <= 0 || cutoff <= 0.0 || beta < 0.0) return -1;
+  if (sw_on < 0.0 || sw_on >= cutoff) return -1;
   for (int a = 0; a < 3; ++a)
     if (!(box[a] > 0.0) || !(cutoff < 0.5 * box[a])) return -2;
   for (int64_t i = 0; i < n; ++i)
@@ -91,6 +116,14 @@ int nbo_rows(int64_t n, const double *pos, const double *q, const int32_t *type,
   int64_t *s_off = NULL;
   int32_t *s_idx = NULL;
   if (sym_exclusions(n, excl_off, excl_idx, &s_off, &s_idx) != 0) return -4;
+  int64_t *p_off = NULL;
+  int32_t *p_idx = NULL;
+  if (p14_off && sym_exclusions(n, p14_off, p14_idx, &p_off, &p_idx) != 0) {
+    free(s_off);
+    free(s_idx);
+    return -4;
+  }
+  const double s_on = sw_on * sw_on;
   const int64_t m = rows ? n_rows : n;
   const double rc2 = cutoff * cutoff;
   const double two_over_sqrt_pi = 2.0 / sqrt(acos(-1.0));
@@ -105,12 +138,16 @@ int nbo_rows(int64_t n, const double *pos, const double *q, const int32_t *type,
 
 #pragma omp parallel reduction(+ : e_lj, e_c, pairs) reduction(+ : vir[:9])
   {
-    /* stamp[j] == row + 1 marks j as excluded from the current row. */
+    /* stamp[j] == row + 1 marks j as excluded from the current row; stamp14[j] == row + 1
+       marks j as a scaled 1-4 partner of it. */
     int64_t *stamp = calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    int64_t *stamp14 = calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
 #pragma omp for schedule(dynamic, 16)
     for (int64_t r = 0; r < m; ++r) {
       const int64_t i = rows ? rows[r] : r;
       for (int64_t k = s_off[i]; k < s_off[i + 1]; ++k) stamp[s_idx[k]] = i + 1;
+      if (p_off)
+        for (int64_t k = p_off[i]; k < p_off[i + 1]; ++k) stamp14[p_idx[k]] = i + 1;
       double f[3] = {0, 0, 0};
       double ei = 0.0, ph = 0.0, as = 0.0, be = 0.0;
       for (int64_t j = 0; j < n; ++j) {
@@ -123,20 +160,27 @@ int nbo_rows(int64_t n, const double *pos, const double *q, const int32_t *type,
         const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         if (!(r2 < rc2)) continue;
         const double r = sqrt(r2);
+        /* scale factors of a 1-4 pair, and the switch of the LJ term */
+        const int scaled = p_off && stamp14[j] == i + 1;
+        const double w_lj = scaled ? s14_lj : 1.0, w_c = scaled ? s14_c : 1.0;
+        double S = 1.0, dS_dr2 = 0.0;
+        if (sw_on > 0.0) lj_switch(r2, s_on, rc2, &S, &dS_dr2);
         /* Lennard-Jones 12-6 with Lorentz-Berthelot combination. */
         const double sij = 0.5 * (sigma[type[i]] + sigma[type[j]]);
         const double eij = sqrt(eps[type[i]] * eps[type[j]]);
         const double s2 = (sij * sij) / r2;
         const double s6 = s2 * s2 * s2;
         const double s12 = s6 * s6;
-        const double u_lj = 4.0 * eij * (s12 - s6);
-        const double f_lj = 24.0 * eij * (2.0 * s12 - s6) / r2;
-        /* d u_lj / d sigma_ij = (4 eps / sigma)(12 s^12 - 6 s^6); zero if sigma_ij = 0. */
-        const double du_dsig = sij > 0.0 ? 4.0 * eij * (12.0 * s12 - 6.0 * s6) / sij : 0.0;
+        const double u_lj0 = 4.0 * eij * (s12 - s6);
+        /* u = w S u0: F = -du/dr d/r = w [S f0 - 2 u0 dS/d(r^2)] d */
+        const double u_lj = w_lj * S * u_lj0;
+        const double f_lj = w_lj * (S * 24.0 * eij * (2.0 * s12 - s6) / r2 - 2.0 * u_lj0 * dS_dr2);
+        /* d u_lj / d sigma_ij = w S (4 eps / sigma)(12 s^12 - 6 s^6); zero if sigma_ij = 0. */
+        const double du_dsig = sij > 0.0 ? w_lj * S * 4.0 * eij * (12.0 * s12 - 6.0 * s6) / sij : 0.0;
         /* Ewald real-space Coulomb. */
         const double erfc_br = erfc(beta * r);
-        const double u_c = ke * q[i] * q[j] * erfc_br / r;
-        const double f_c = ke * q[i] * q[j] *
+        const double u_c = w_c * ke * q[i] * q[j] * erfc_br / r;
+        const double f_c = w_c * ke * q[i] * q[j] *
                            (erfc_br / (r2 * r) + beta * two_over_sqrt_pi * exp(-beta * beta * r2) / r2);
         const double fs = f_lj + f_c;
         for (int a = 0; a < 3; ++a) f[a] += fs * d[a];
@@ -145,7 +189,7 @@ int nbo_rows(int64_t n, const double *pos, const double *q, const int32_t *type,
         ei += 0.5 * (u_lj + u_c);
         e_lj += 0.5 * u_lj;
         e_c += 0.5 * u_c;
-        ph += ke * q[j] * erfc_br / r;
+        ph += w_c * ke * q[j] * erfc_br / r;
         as += 0.5 * du_dsig;
         be += 0.5 * u_lj;
         pairs += 1;
@@ -157,6 +201,7 @@ int nbo_rows(int64_t n, const double *pos, const double *q, const int32_t *type,
       if (b_eps) b_eps[r] = be;
     }
     free(stamp);
+    free(stamp14);
   }
   if (virial) for (int k = 0; k < 9; ++k) virial[k] = vir[k];
   if (e_lj_out) *e_lj_out = e_lj;
@@ -165,7 +210,23 @@ int nbo_rows(int64_t n, const double *pos, const double *q, const int32_t *type,
   if (pair_count_out) *pair_count_out = rows ? pairs : pairs / 2;
   free(s_off);
   free(s_idx);
+  free(p_off);
+  free(p_idx);
   return 0;
+}
+
+/* The plain interaction: no 1-4 list, no switch. */
+int nbo_rows(int64_t n, const double *pos, const double *q, const int32_t *type,
+             int32_t ntypes, const double *sigma, const double *eps,
+             const int32_t *excl_off, const int32_t *excl_idx, const double *box,
+             double cutoff, double beta, double ke,
+             int64_t n_rows, const int64_t *rows,
+             double *force, double *energy, double *phi, double *a_sig, double *b_eps,
+             double *virial, double *e_lj_out, double *e_c_out, int64_t *pair_count_out,
+             int nthreads) {
+  return nbo_rows_ff(n, pos, q, type, ntypes, sigma, eps, excl_off, excl_idx, box, cutoff, beta, ke,
+                     NULL, NULL, 1.0, 1.0, 0.0, n_rows, rows, force, energy, phi, a_sig, b_eps, virial,
+                     e_lj_out, e_c_out, pair_count_out, nthreads);
 }
 
 /*
@@ -174,6 +235,7 @@ int nbo_rows(int64_t n, const double *pos, const double *q, const int32_t *type,
  * pair, excluded ones included, and every charge with itself):
  *
  *   E_excl = - sum over excluded pairs {i, j} of k_e q_i q_j erf(beta r) / r
+ *            - (1 - s14_c) sum over scaled 1-4 pairs (not excluded) of the same term
  *            (union of both rows, any distance, minimum image; at r = 0 the limit
  *            k_e q_i q_j 2 beta / sqrt(pi))
  *   E_self = - k_e beta / sqrt(pi) sum_i q_i^2
@@ -185,16 +247,22 @@ int nbo_rows(int64_t n, const double *pos, const double *q, const int32_t *type,
  *
  * All rows; libm erf and exp.  Returns 0, or -1 / -2 / -4 on bad input.
  */
-int nbo_ewald_corrections(int64_t n, const double *pos, const double *q,
-                          const int32_t *excl_off, const int32_t *excl_idx, const double *box,
-                          double beta, double ke, double *force, double *energy, double *virial,
-                          double *e_excl_out, double *e_self_out) {
+int nbo_ewald_corrections_ff(int64_t n, const double *pos, const double *q,
+                             const int32_t *excl_off, const int32_t *excl_idx,
+                             const int32_t *p14_off, const int32_t *p14_idx, double s14_c,
+                             const double *box, double beta, double ke, double *force, double *energy,
+                             double *virial, double *e_excl_out, double *e_self_out) {
   if (n < 0 || beta < 0.0) return -1;
   for (int a = 0; a < 3; ++a)
     if (!(box[a] > 0.0)) return -2;
-  int64_t *s_off = NULL;
-  int32_t *s_idx = NULL;
+  int64_t *s_off = NULL, *p_off = NULL;
+  int32_t *s_idx = NULL, *p_idx = NULL;
   if (sym_exclusions(n, excl_off, excl_idx, &s_off, &s_idx) != 0) return -4;
+  if (p14_off && sym_exclusions(n, p14_off, p14_idx, &p_off, &p_idx) != 0) {
+    free(s_off);
+    free(s_idx);
+    return -4;
+  }
   const double two_over_sqrt_pi = 2.0 / sqrt(acos(-1.0));
   int64_t *stamp = calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
   double vir[9] = {0};
@@ -202,32 +270,41 @@ int nbo_ewald_corrections(int64_t n, const double *pos, const double *q,
   for (int64_t i = 0; i < n; ++i) {
     double f[3] = {0, 0, 0};
     double ei = 0.0;
-    for (int64_t k = s_off[i]; k < s_off[i + 1]; ++k) {
-      const int64_t j = s_idx[k];
-      if (j == i || stamp[j] == i + 1) continue;  /* the atom itself, or a repeated entry */
-      stamp[j] = i + 1;
-      double d[3];
-      for (int a = 0; a < 3; ++a) {
-        double t = pos[3 * i + a] - pos[3 * j + a];
-        d[a] = t - box[a] * rint(t / box[a]);
+    /* pass 0: excluded partners (weight 1); pass 1: scaled 1-4 partners that are not also
+       excluded (weight 1 - s14_c: the reciprocal part counts them in full, the real-space
+       part with s14_c) */
+    for (int pass = 0; pass < 2; ++pass) {
+      const int64_t *o = pass == 0 ? s_off : p_off;
+      const int32_t *x = pass == 0 ? s_idx : p_idx;
+      const double w = pass == 0 ? 1.0 : 1.0 - s14_c;
+      if (!o) continue;
+      for (int64_t k = o[i]; k < o[i + 1]; ++k) {
+        const int64_t j = x[k];
+        if (j == i || stamp[j] == i + 1) continue;  /* the atom itself, or a repeated entry */
+        stamp[j] = i + 1;
+        double d[3];
+        for (int a = 0; a < 3; ++a) {
+          double t = pos[3 * i + a] - pos[3 * j + a];
+          d[a] = t - box[a] * rint(t / box[a]);
+        }
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        const double qq = w * ke * q[i] * q[j];
+        double u, g;
+        if (r2 > 0.0) {
+          const double r = sqrt(r2);
+          const double erf_br = erf(beta * r);
+          u = -qq * erf_br / r;
+          g = qq * (beta * two_over_sqrt_pi * exp(-beta * beta * r2) / r2 - erf_br / (r2 * r));
+        } else {
+          u = -qq * beta * two_over_sqrt_pi;
+          g = 0.0;
+        }
+        for (int a = 0; a < 3; ++a) f[a] += g * d[a];
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) vir[3 * a + b] += 0.5 * d[a] * g * d[b];
+        ei += 0.5 * u;
+        e_excl += 0.5 * u;
       }
-      const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-      const double qq = ke * q[i] * q[j];
-      double u, g;
-      if (r2 > 0.0) {
-        const double r = sqrt(r2);
-        const double erf_br = erf(beta * r);
-        u = -qq * erf_br / r;
-        g = qq * (beta * two_over_sqrt_pi * exp(-beta * beta * r2) / r2 - erf_br / (r2 * r));
-      } else {
-        u = -qq * beta * two_over_sqrt_pi;
-        g = 0.0;
-      }
-      for (int a = 0; a < 3; ++a) f[a] += g * d[a];
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) vir[3 * a + b] += 0.5 * d[a] * g * d[b];
-      ei += 0.5 * u;
-      e_excl += 0.5 * u;
     }
     const double si = -ke * beta * 0.5 * two_over_sqrt_pi * q[i] * q[i];
     e_self += si;
@@ -240,5 +317,15 @@ int nbo_ewald_corrections(int64_t n, const double *pos, const double *q,
   free(stamp);
   free(s_off);
   free(s_idx);
+  free(p_off);
+  free(p_idx);
   return 0;
+}
+
+int nbo_ewald_corrections(int64_t n, const double *pos, const double *q,
+                          const int32_t *excl_off, const int32_t *excl_idx, const double *box,
+                          double beta, double ke, double *force, double *energy, double *virial,
+                          double *e_excl_out, double *e_self_out) {
+  return nbo_ewald_corrections_ff(n, pos, q, excl_off, excl_idx, NULL, NULL, 1.0, box, beta, ke, force,
+                                  energy, virial, e_excl_out, e_self_out);
 }

@@ -61,6 +61,13 @@ def _load():
         lib.nbo_ewald_corrections.restype = ctypes.c_int
         lib.nbo_ewald_corrections.argtypes = [ctypes.c_int64, P, P, P, P, P, ctypes.c_double,
                                               ctypes.c_double, P, P, P, P, P]
+        D = ctypes.c_double
+        lib.nbo_rows_ff.restype = ctypes.c_int
+        lib.nbo_rows_ff.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int32, P, P, P, P, P, D, D, D,
+                                    P, P, D, D, D,
+                                    ctypes.c_int64, P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
+        lib.nbo_ewald_corrections_ff.restype = ctypes.c_int
+        lib.nbo_ewald_corrections_ff.argtypes = [ctypes.c_int64, P, P, P, P, P, P, D, P, D, D, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -69,14 +76,27 @@ def _ptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
+def _csr(off, idx):
+    """Contiguous int32 CSR arrays (a placeholder entry for an empty index list)."""
+    o = np.ascontiguousarray(off, np.int32)
+    i = np.ascontiguousarray(idx, np.int32)
+    return o, (i if i.size else np.zeros(1, np.int32))
+
+
 def evaluate(pos, charge, types, sigma, eps, excl_offset, excl_index, box, cutoff, beta,
-             ke: float = COULOMB_K, rows: Optional[np.ndarray] = None, nthreads: int = 0) -> dict:
+             ke: float = COULOMB_K, rows: Optional[np.ndarray] = None, nthreads: int = 0,
+             pair14_offset=None, pair14_index=None, scale14_lj: float = 1.0, scale14_coul: float = 1.0,
+             lj_switch_on: float = 0.0) -> dict:
     """Evaluate the brute-force sums for every atom (rows=None) or for the atoms in ``rows``.
 
     Inputs are promoted to float64; pass exactly the values the device computes with.
     Returns per-row arrays (force [m,3], energy [m], phi [m], a_sig [m], b_eps [m]) and
     totals over the evaluated rows (virial [3,3], e_lj, e_c, energy_total, pairs).  With
     rows=None also the per-type gradients dsigma [T] and deps [T].
+
+    Force-field options: pairs in the 1-4 lists (CSR, union of both rows, not excluded)
+    have their LJ term scaled by scale14_lj and their Coulomb term by scale14_coul; with
+    lj_switch_on = r_on > 0 the LJ term is switched off between r_on and the cutoff.
     """
     lib = _load()
     pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
@@ -101,11 +121,13 @@ def evaluate(pos, charge, types, sigma, eps, excl_offset, excl_index, box, cutof
     e_lj = ctypes.c_double()
     e_c = ctypes.c_double()
     npairs = ctypes.c_int64()
-    rc = lib.nbo_rows(n, _ptr(pos), _ptr(q), _ptr(t), int(sig.shape[0]), _ptr(sig), _ptr(ep),
-                      _ptr(eo), _ptr(ei), _ptr(bx), float(cutoff), float(beta), float(ke),
-                      m, _ptr(r), _ptr(force), _ptr(energy), _ptr(phi), _ptr(a_sig), _ptr(b_eps),
-                      _ptr(vir), ctypes.byref(e_lj), ctypes.byref(e_c), ctypes.byref(npairs),
-                      int(nthreads))
+    po, pi = _csr(pair14_offset, pair14_index) if pair14_offset is not None else (None, None)
+    rc = lib.nbo_rows_ff(n, _ptr(pos), _ptr(q), _ptr(t), int(sig.shape[0]), _ptr(sig), _ptr(ep),
+                         _ptr(eo), _ptr(ei), _ptr(bx), float(cutoff), float(beta), float(ke),
+                         _ptr(po), _ptr(pi), float(scale14_lj), float(scale14_coul), float(lj_switch_on),
+                         m, _ptr(r), _ptr(force), _ptr(energy), _ptr(phi), _ptr(a_sig), _ptr(b_eps),
+                         _ptr(vir), ctypes.byref(e_lj), ctypes.byref(e_c), ctypes.byref(npairs),
+                         int(nthreads))
     if rc != 0:
         raise ValueError(f"oracle rejected the input (code {rc})")
     out = dict(force=force, energy=energy, phi=phi, a_sig=a_sig, b_eps=b_eps,
@@ -122,20 +144,25 @@ def evaluate(pos, charge, types, sigma, eps, excl_offset, excl_index, box, cutof
     return out
 
 
-def evaluate_system(system, rows=None, nthreads: int = 0, ke: float = COULOMB_K) -> dict:
-    """``evaluate`` on an object with the fields of ``systems.System``."""
+def evaluate_system(system, rows=None, nthreads: int = 0, ke: float = COULOMB_K, **ff) -> dict:
+    """``evaluate`` on an object with the fields of ``systems.System`` (its 1-4 lists, when
+    it has them, and the force-field options given as keyword arguments)."""
+    if getattr(system, "pair14_offset", None) is not None and "pair14_offset" not in ff:
+        ff = dict(ff, pair14_offset=system.pair14_offset, pair14_index=system.pair14_index)
     return evaluate(system.pos, system.charge, system.type, system.sigma, system.eps,
                     system.excl_offset, system.excl_index, system.box, system.cutoff,
-                    system.beta, ke=ke, rows=rows, nthreads=nthreads)
+                    system.beta, ke=ke, rows=rows, nthreads=nthreads, **ff)
 
 
-def ewald_corrections(pos, charge, excl_offset, excl_index, box, beta, ke: float = COULOMB_K) -> dict:
-    """The excluded-pair and self corrections of the Ewald sum (``nbo_ewald_corrections``).
+def ewald_corrections(pos, charge, excl_offset, excl_index, box, beta, ke: float = COULOMB_K,
+                      pair14_offset=None, pair14_index=None, scale14_coul: float = 1.0) -> dict:
+    """The excluded-pair and self corrections of the Ewald sum (``nbo_ewald_corrections_ff``).
 
     Inputs are promoted to float64; pass exactly the values the device computes with.
     Returns force [N,3] (of the excluded-pair term), energy [N] (per-atom split: half of
     each excluded pair's term plus the atom's self term), virial [3,3], e_excl, e_self and
-    energy_total = e_excl + e_self.
+    energy_total = e_excl + e_self.  Scaled 1-4 pairs (not excluded) add the excluded-pair
+    term times (1 - scale14_coul).
     """
     lib = _load()
     pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
@@ -151,16 +178,20 @@ def ewald_corrections(pos, charge, excl_offset, excl_index, box, beta, ke: float
     vir = np.zeros(9)
     e_excl = ctypes.c_double()
     e_self = ctypes.c_double()
-    rc = lib.nbo_ewald_corrections(n, _ptr(pos), _ptr(q), _ptr(eo), _ptr(ei), _ptr(bx), float(beta),
-                                   float(ke), _ptr(force), _ptr(energy), _ptr(vir),
-                                   ctypes.byref(e_excl), ctypes.byref(e_self))
+    po, pi = _csr(pair14_offset, pair14_index) if pair14_offset is not None else (None, None)
+    rc = lib.nbo_ewald_corrections_ff(n, _ptr(pos), _ptr(q), _ptr(eo), _ptr(ei), _ptr(po), _ptr(pi),
+                                      float(scale14_coul), _ptr(bx), float(beta), float(ke), _ptr(force),
+                                      _ptr(energy), _ptr(vir), ctypes.byref(e_excl), ctypes.byref(e_self))
     if rc != 0:
         raise ValueError(f"oracle rejected the input (code {rc})")
     return dict(force=force, energy=energy, virial=vir.reshape(3, 3), e_excl=e_excl.value,
                 e_self=e_self.value, energy_total=e_excl.value + e_self.value)
 
 
-def ewald_corrections_system(system, ke: float = COULOMB_K) -> dict:
-    """``ewald_corrections`` on an object with the fields of ``systems.System``."""
+def ewald_corrections_system(system, ke: float = COULOMB_K, **ff) -> dict:
+    """``ewald_corrections`` on an object with the fields of ``systems.System`` (its 1-4
+    lists, when it has them; scale14_coul as a keyword argument)."""
+    if getattr(system, "pair14_offset", None) is not None and "pair14_offset" not in ff:
+        ff = dict(ff, pair14_offset=system.pair14_offset, pair14_index=system.pair14_index)
     return ewald_corrections(system.pos, system.charge, system.excl_offset, system.excl_index,
-                             system.box, system.beta, ke=ke)
+                             system.box, system.beta, ke=ke, **ff)

@@ -70,6 +70,10 @@ class System:
     beta: float
     seed: int
     n_solute: int = 0
+    # Scaled 1-4 pairs (CSR rows like the exclusions), or None: the solute chain's i, i+3
+    # pairs (with_chain_14).  Water has none.
+    pair14_offset: Optional[np.ndarray] = None
+    pair14_index: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:
@@ -352,6 +356,21 @@ def water_box(n_waters: int, L: float, seed: int, cutoff: float = 9.0, beta: flo
                          name=f"water{n_waters}")
 
 
+def with_chain_14(s: System) -> System:
+    """Copy of a system whose solute chain (the first n_solute atoms, bonded in order) lists
+    its 1-4 pairs (i, i + 3), in both rows, as scaled pairs."""
+    rows = [[] for _ in range(s.n)]
+    for i in range(max(s.n_solute - 3, 0)):
+        rows[i].append(i + 3)
+        rows[i + 3].append(i)
+    off = np.zeros(s.n + 1, np.int32)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    t = dataclasses.replace(s)
+    t.pair14_offset = off
+    t.pair14_index = np.array([j for r in rows for j in sorted(r)], np.int32)
+    return t
+
+
 def concat_systems(systems: List[System]):
     """Pack systems back to back (batch layout): returns a dict of concatenated arrays.
 
@@ -366,8 +385,21 @@ def concat_systems(systems: List[System]):
     for s in systems:
         excl_off.append(s.excl_offset[1:].astype(np.int64) + base)
         base += int(s.excl_offset[-1])
+    p14_off, p14_idx = None, None
+    if any(s.pair14_offset is not None for s in systems):
+        p14_off = [np.zeros(1, np.int64)]
+        base = 0
+        for s in systems:
+            o = s.pair14_offset if s.pair14_offset is not None else np.zeros(s.n + 1, np.int32)
+            p14_off.append(o[1:].astype(np.int64) + base)
+            base += int(o[-1])
+        p14_off = np.concatenate(p14_off).astype(np.int32)
+        p14_idx = np.concatenate([s.pair14_index for s in systems if s.pair14_index is not None]
+                                 + [np.zeros(0, np.int32)]).astype(np.int32)
     return dict(
         atom_offset=offs,
+        pair14_offset=p14_off,
+        pair14_index=p14_idx,
         pos=np.concatenate([s.pos for s in systems]),
         charge=np.concatenate([s.charge for s in systems]),
         type=np.concatenate([s.type for s in systems]),
