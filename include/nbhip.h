@@ -10,7 +10,9 @@
  *   u_ij = 4 eps_ij [(sigma_ij/r)^12 - (sigma_ij/r)^6] + k_e q_i q_j erfc(beta r)/r,
  *   sigma_ij = (sigma_ti + sigma_tj)/2,  eps_ij = sqrt(eps_ti eps_tj),
  *
- * with the cutoff test r < R strict and no shift or switch.  Atoms are first
+ * with the cutoff test r < R strict, and optionally a switch of the Lennard-Jones term
+ * and scaled 1-4 pairs (nb_params.lj_switch_on, nb_system.pair14_*).  The kernel variant
+ * NB_KERNEL_ATOM supports neither option.  Atoms are first
  * binned into a cell list (section 3: one thread per atom computes its cell;
  * cells a fraction of R wide), then a pair kernel visits the neighbouring cells.
  *
@@ -63,6 +65,7 @@ typedef enum {
 #define NB_STATUS_FAR_EXCLUSION 0x8u  /* informational: some exclusion is more than 64 atoms apart in index */
 #define NB_STATUS_NOT_BUILT 0x10u     /* the workspace was not built by nb_build_cells for this system size and
                                          kernel variant: the pair kernels wrote nothing */
+#define NB_STATUS_FAR_PAIR14 0x20u    /* a 1-4 pair more than 64 atoms apart in index: left unscaled */
 
 typedef enum {
   NB_FP64 = 0,  /* double-precision pair arithmetic from double positions */
@@ -91,6 +94,14 @@ typedef struct {
                                  A pair listed in either atom's row is excluded both ways (section 3
                                  stores bonded exclusions as per-atom bitmaps over index distance
                                  |i-j| <= 64; larger distances take a slower path). */
+  const int32_t *pair14_offset; /* [device] N+1 CSR row offsets of the scaled 1-4 pairs, or NULL for none */
+  const int32_t *pair14_index;  /* [device] 1-4 partners of each atom, local indices.  A pair listed in
+                                 either row (and not excluded) has its Lennard-Jones term scaled by
+                                 nb_params.scale14_lj and its real-space Coulomb term by scale14_coul
+                                 (section 3: CHARMM/AMBER 1-4 pairs, stored in bitmaps beside the
+                                 exclusions).  Only |i-j| <= 64 is supported, as in the paper's
+                                 bitmaps: a farther 1-4 pair sets NB_STATUS_FAR_PAIR14 and
+                                 interacts unscaled. */
 } nb_system;
 
 #define NB_MAX_TYPES 64
@@ -122,6 +133,15 @@ typedef struct {
   int32_t cluster_size; /* cluster kernel: atoms per i-cluster, 4 or 8 (0 = 8 mixed, 4 FP64) */
   int32_t schedule;   /* cluster kernel: NB_SCHED_* (0 = static) */
   int32_t wg_per_cu;  /* dynamic schedule: resident one-wave workgroups per compute unit, 1..32 (0 = 16) */
+  double lj_switch_on;/* r_on (A), 0 <= r_on < R; 0 = no switch.  Otherwise the Lennard-Jones term is
+                         multiplied by S = (1-x)^2 (1+2x), x = (r^2 - r_on^2)/(R^2 - r_on^2) in [0, 1]
+                         (the CHARMM energy switch; section 5's benchmark switches at 7.5 A for
+                         R = 9 A), and the force is -d(S u_LJ)/dr; the Coulomb term is not switched */
+  double scale14_lj;  /* factor of the Lennard-Jones term of 1-4 pairs (AMBER: 0.5) */
+  double scale14_coul;/* factor of the real-space Coulomb term of 1-4 pairs (AMBER: 1/1.2);
+                         nb_ewald_corrections adds -(1 - scale14_coul) k_e q_i q_j erf(beta r)/r
+                         for them, so that with the reciprocal part the whole Coulomb interaction
+                         of a 1-4 pair is scale14_coul k_e q_i q_j / r */
 } nb_params;
 
 /* Bytes of device workspace needed for this batch and these parameters.

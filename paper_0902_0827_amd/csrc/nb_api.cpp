@@ -59,6 +59,12 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   if (prm->wg_per_cu < 0 || prm->wg_per_cu > 32) return fail(NB_ERR_ARG, "wg_per_cu must be in [0, 32]");
   if (prm->cluster_size != 0 && prm->cluster_size != 4 && prm->cluster_size != 8)
     return fail(NB_ERR_ARG, "cluster_size must be 0, 4 or 8");
+  if (!(prm->lj_switch_on >= 0.0) || !(prm->lj_switch_on < prm->cutoff))
+    return fail(NB_ERR_ARG, "lj_switch_on must be in [0, cutoff)");
+  if (!std::isfinite(prm->scale14_lj) || !std::isfinite(prm->scale14_coul))
+    return fail(NB_ERR_ARG, "scale14_lj and scale14_coul must be finite");
+  if ((sys->pair14_offset == nullptr) != (sys->pair14_index == nullptr))
+    return fail(NB_ERR_ARG, "pair14_offset and pair14_index must both be given or both be NULL");
 
   const int B = sys->n_systems;
   if (sys->atom_offset[0] != 0) return fail(NB_ERR_ARG, "atom_offset[0] must be 0");
@@ -93,6 +99,13 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   p.cutoff = prm->cutoff;
   p.beta = prm->ewald_beta;
   p.ke = prm->coulomb_k;
+  p.switch_on = prm->lj_switch_on;
+  p.has14 = sys->pair14_offset != nullptr;
+  p.s14_lj = p.has14 ? prm->scale14_lj : 1.0;
+  p.s14_c = p.has14 ? prm->scale14_coul : 1.0;
+  p.ff = p.has14 || p.switch_on > 0.0;
+  if (p.ff && p.kernel == NB_KERNEL_ATOM)
+    return fail(NB_ERR_ARG, "the per-atom kernel supports neither the LJ switch nor 1-4 pairs");
   p.desc.resize(B);
   int64_t cells = 0, blocks = 0, clusters = 0, columns = 0;
   for (int b = 0; b < B; ++b) {
@@ -173,6 +186,7 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   l.part = take(32 * static_cast<size_t>(N) * static_cast<size_t>(p.split));
   l.queue = take(4 * static_cast<size_t>(kXcds * kQueueStride));
   l.jacc = p.kernel == NB_KERNEL_CLUSTER_HALF ? take(32 * static_cast<size_t>(N)) : 0;
+  l.p14_mask = p.has14 ? take(16 * static_cast<size_t>(N)) : 0;
   l.total = o;
   *plan = std::move(p);
   return NB_OK;
@@ -213,6 +227,7 @@ Dev dev_view(const Plan &p, void *ws) {
   d.n_columns = p.n_columns;
   d.n_clusters_max = p.n_clusters_max;
   d.queue = reinterpret_cast<uint32_t *>(base + l.queue);
+  d.p14_mask = p.has14 ? reinterpret_cast<uint4 *>(base + l.p14_mask) : nullptr;
   const bool half = p.kernel == NB_KERNEL_CLUSTER_HALF;
   d.jacc_fix = half && p.precision == NB_MIXED ? reinterpret_cast<long long *>(base + l.jacc) : nullptr;
   d.jacc_f64 = half && p.precision == NB_FP64 ? reinterpret_cast<double *>(base + l.jacc) : nullptr;

@@ -135,6 +135,7 @@ __global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, con
   for (int64_t k = tid; k < d.n_cells; k += stride) d.cell_count[k] = 0;
   for (int64_t k = tid; k < d.N; k += stride) {
     d.excl_mask[k] = make_uint4(0u, 0u, 0u, 0u);
+    if (d.p14_mask) d.p14_mask[k] = make_uint4(0u, 0u, 0u, 0u);
     d.excl_far[k] = 0u;
     for (int c = 0; c < 4; ++c) {
       if (d.jacc_fix) d.jacc_fix[c * d.N + k] = 0;
@@ -165,16 +166,68 @@ __global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, con
 
 __device__ inline void set_status(const Dev &d, uint32_t bit) { atomicOr(d.status, bit); }
 
-__device__ inline void window_set(const Dev &d, int atom, int delta) {
+__device__ inline void window_set(uint4 *masks, int atom, int delta) {
   // delta in [-64, -1] -> bit delta + 64; delta in [1, 64] -> bit delta + 63.
   const int bit = delta < 0 ? delta + kWindow : delta + kWindow - 1;
-  unsigned int *w = reinterpret_cast<unsigned int *>(&d.excl_mask[atom]);
+  unsigned int *w = reinterpret_cast<unsigned int *>(&masks[atom]);
   atomicOr(&w[bit >> 5], 1u << (bit & 31));
+}
+
+// Folds atom i's row of a pair list (exclusions or scaled 1-4 pairs) into the 128-bit index
+// windows `masks` (section 3: bitmaps over |i - j| <= 64).  A pair listed in either row
+// counts both ways: the bits of this atom's own row are gathered in registers and added
+// with one atomicOr per window word that has any; the partner's bit for this atom is set
+// here only when the partner's row does not list this atom (else the partner sets it from
+// its own row).  Lists usually name each pair from both sides, so this replaces four
+// device-scope atomics per listed pair by about one per atom.  Pairs farther apart than the
+// window call far(j); a bad row or index sets NB_STATUS_BAD_EXCLUSION.
+template <typename Far>
+__device__ inline void fold_row(const Dev &d, uint4 *masks, const int32_t *__restrict__ off,
+                                const int32_t *__restrict__ idx, int i, const SysDesc &sd, Far far) {
+  const int lo = off[i], hi = off[i + 1];
+  if (hi < lo) {
+    set_status(d, NB_STATUS_BAD_EXCLUSION);
+    return;
+  }
+  const int n_sys = sd.atom_end - sd.atom_begin;
+  const int il = i - sd.atom_begin;
+  uint32_t own0 = 0u, own1 = 0u, own2 = 0u, own3 = 0u;
+  for (int k = lo; k < hi; ++k) {
+    const int jl = idx[k];
+    if (jl < 0 || jl >= n_sys) {
+      set_status(d, NB_STATUS_BAD_EXCLUSION);
+      continue;
+    }
+    const int j = sd.atom_begin + jl;
+    const int delta = j - i;
+    if (delta == 0) continue;
+    if (delta >= -kWindow && delta <= kWindow) {
+      const int bit = delta < 0 ? delta + kWindow : delta + kWindow - 1;
+      const uint32_t m = 1u << (bit & 31);
+      const int ws = bit >> 5;
+      own0 |= ws == 0 ? m : 0u;
+      own1 |= ws == 1 ? m : 0u;
+      own2 |= ws == 2 ? m : 0u;
+      own3 |= ws == 3 ? m : 0u;
+      const int jlo = off[j], jhi = off[j + 1];
+      bool listed = false;
+      for (int q = jlo; q < jhi && !listed; ++q) listed = idx[q] == il;
+      if (!listed) window_set(masks, j, -delta);
+    } else {
+      far(j);
+    }
+  }
+  unsigned int *w = reinterpret_cast<unsigned int *>(&masks[i]);
+  if (own0) atomicOr(&w[0], own0);
+  if (own1) atomicOr(&w[1], own1);
+  if (own2) atomicOr(&w[2], own2);
+  if (own3) atomicOr(&w[3], own3);
 }
 
 template <typename Real>
 __global__ void k_bin(Dev d, const Real *__restrict__ pos, const int32_t *__restrict__ type,
-                      const int32_t *__restrict__ excl_off, const int32_t *__restrict__ excl_idx) {
+                      const int32_t *__restrict__ excl_off, const int32_t *__restrict__ excl_idx,
+                      const int32_t *__restrict__ p14_off, const int32_t *__restrict__ p14_idx) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.N) return;
   const int b = find_system(d.desc, d.B, i);
@@ -203,52 +256,16 @@ __global__ void k_bin(Dev d, const Real *__restrict__ pos, const int32_t *__rest
   const int t = type[i];
   if (t < 0 || t >= d.T) set_status(d, NB_STATUS_BAD_TYPE);
 
-  // Exclusions: a pair listed in either row excludes both ways (section 3: bitmaps over
-  // |i - j| <= 64).  The bits of this atom's own row are gathered in registers and added
-  // with one atomicOr per window word that has any; the partner's bit for this atom is
-  // set here only when the partner's row does not list this atom (else the partner sets
-  // it from its own row).  Exclusion lists usually name each pair from both sides, so
-  // this replaces four device-scope atomics per listed pair by about one per atom.
-  const int lo = excl_off[i], hi = excl_off[i + 1];
-  if (hi < lo) {
-    set_status(d, NB_STATUS_BAD_EXCLUSION);
-    return;
-  }
-  const int n_sys = sd.atom_end - sd.atom_begin;
-  const int il = i - sd.atom_begin;
-  uint32_t own0 = 0u, own1 = 0u, own2 = 0u, own3 = 0u;
-  for (int k = lo; k < hi; ++k) {
-    const int jl = excl_idx[k];
-    if (jl < 0 || jl >= n_sys) {
-      set_status(d, NB_STATUS_BAD_EXCLUSION);
-      continue;
-    }
-    const int j = sd.atom_begin + jl;
-    const int delta = j - i;
-    if (delta == 0) continue;
-    if (delta >= -kWindow && delta <= kWindow) {
-      const int bit = delta < 0 ? delta + kWindow : delta + kWindow - 1;
-      const uint32_t m = 1u << (bit & 31);
-      const int ws = bit >> 5;
-      own0 |= ws == 0 ? m : 0u;
-      own1 |= ws == 1 ? m : 0u;
-      own2 |= ws == 2 ? m : 0u;
-      own3 |= ws == 3 ? m : 0u;
-      const int jlo = excl_off[j], jhi = excl_off[j + 1];
-      bool listed = false;
-      for (int q = jlo; q < jhi && !listed; ++q) listed = excl_idx[q] == il;
-      if (!listed) window_set(d, j, -delta);
-    } else {
-      atomicOr(&d.excl_far[i], 1u);
-      atomicOr(&d.excl_far[j], 1u);
-      set_status(d, NB_STATUS_FAR_EXCLUSION);
-    }
-  }
-  unsigned int *w = reinterpret_cast<unsigned int *>(&d.excl_mask[i]);
-  if (own0) atomicOr(&w[0], own0);
-  if (own1) atomicOr(&w[1], own1);
-  if (own2) atomicOr(&w[2], own2);
-  if (own3) atomicOr(&w[3], own3);
+  // Exclusions: a pair listed in either row excludes both ways; beyond the window the
+  // atoms carry the far flag and the pair kernels search their rows.
+  fold_row(d, d.excl_mask, excl_off, excl_idx, i, sd, [&](int j) {
+    atomicOr(&d.excl_far[i], 1u);
+    atomicOr(&d.excl_far[j], 1u);
+    set_status(d, NB_STATUS_FAR_EXCLUSION);
+  });
+  // Scaled 1-4 pairs: the paper's bitmaps hold them within the window only; a farther one
+  // is reported and left unscaled.
+  if (d.p14_mask) fold_row(d, d.p14_mask, p14_off, p14_idx, i, sd, [&](int) { set_status(d, NB_STATUS_FAR_PAIR14); });
 }
 
 // Exclusive scan of count(0 .. n-1) into store(k, prefix) for k < n and store(n, total),
@@ -580,10 +597,10 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
   const unsigned g = grid_for(plan.N, kBlock);
   if (sys->pos_is_f64)
     hipLaunchKernelGGL(k_bin<double>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const double *>(sys->pos),
-                       sys->type, sys->excl_offset, sys->excl_index);
+                       sys->type, sys->excl_offset, sys->excl_index, sys->pair14_offset, sys->pair14_index);
   else
     hipLaunchKernelGGL(k_bin<float>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const float *>(sys->pos),
-                       sys->type, sys->excl_offset, sys->excl_index);
+                       sys->type, sys->excl_offset, sys->excl_index, sys->pair14_offset, sys->pair14_index);
   if (plan.n_cells + 1 <= kFuseCells) {
     const unsigned gs = grid_for(plan.N, kScanBlock);
     hipLaunchKernelGGL(k_scan_scatter, dim3(gs), dim3(kScanBlock), 4 * static_cast<size_t>(plan.n_cells + 1), s, d,

@@ -6,7 +6,11 @@
 //   for every excluded pair {i, j} (the union of both atoms' exclusion rows, at any
 //   distance, minimum image):   u_ij = -k_e q_i q_j erf(beta r) / r
 //                               (at r = 0 its limit -k_e q_i q_j 2 beta / sqrt(pi))
-//   for every atom:             -k_e beta / sqrt(pi) q_i^2.
+//   for every atom:             -k_e beta / sqrt(pi) q_i^2
+//   for every scaled 1-4 pair {i, j} that is not excluded (the union of both 1-4 rows,
+//   within the 64-index window): (1 - s14_coul) u_ij, so that with the pair kernels'
+//   s14_coul erfc term and the reciprocal part the whole Coulomb interaction of the pair
+//   is s14_coul k_e q_i q_j / r.
 //
 // The force on i from pair {i, j} is g_ij d_ij with
 //   g_ij = k_e q_i q_j [(2 beta / sqrt(pi)) exp(-beta^2 r^2) / r^2 - erf(beta r) / r^3].
@@ -79,7 +83,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ewald_atoms(Dev d, const T *__restrict__ pos, const T *__restrict__ charge,
                                                         const int32_t *__restrict__ excl_off,
                                                         const int32_t *__restrict__ excl_idx, double ke, double beta,
-                                                        double *force) {
+                                                        double w14, double *force) {
   __shared__ double red[kWaves][kPart];
   const int blk = blockIdx.x;
   if (!built_for(d.status, d.N, false, false)) {
@@ -94,11 +98,12 @@ __global__ void __launch_bounds__(kBlock) k_ewald_atoms(Dev d, const T *__restri
     const double3 xi = load3(pos, i);
     const double qi = static_cast<double>(charge[i]);
     double3 f = make_double3(0, 0, 0);
-    auto add = [&](int j, double w) {  // pair {i, j}; w = this side's share of energy and virial
+    // pair {i, j} with weight wp; w = this side's share of energy and virial
+    auto add = [&](int j, double w, double wp) {
       const double3 dd = min_image(xi, load3(pos, j), sd);
       const double r2 = dd.x * dd.x + dd.y * dd.y + dd.z * dd.z;
       double u, g;
-      excl_pair(ke * qi * static_cast<double>(charge[j]), r2, beta, &u, &g);
+      excl_pair(wp * ke * qi * static_cast<double>(charge[j]), r2, beta, &u, &g);
       f.x += g * dd.x;
       f.y += g * dd.y;
       f.z += g * dd.z;
@@ -115,7 +120,20 @@ __global__ void __launch_bounds__(kBlock) k_ewald_atoms(Dev d, const T *__restri
       while (bits) {
         const int bit = 32 * wd + __ffs(static_cast<int>(bits)) - 1;
         bits &= bits - 1u;
-        add(bit < kWindow ? i + bit - kWindow : i + bit - kWindow + 1, 0.5);
+        add(bit < kWindow ? i + bit - kWindow : i + bit - kWindow + 1, 0.5, 1.0);
+      }
+    }
+    // scaled 1-4 partners that are not excluded, weight 1 - s14_coul
+    if (d.p14_mask && w14 != 0.0) {
+      const uint4 m14 = d.p14_mask[i];
+      const uint32_t w14s[4] = {m14.x & ~m.x, m14.y & ~m.y, m14.z & ~m.z, m14.w & ~m.w};
+      for (int wd = 0; wd < 4; ++wd) {
+        uint32_t bits = w14s[wd];
+        while (bits) {
+          const int bit = 32 * wd + __ffs(static_cast<int>(bits)) - 1;
+          bits &= bits - 1u;
+          add(bit < kWindow ? i + bit - kWindow : i + bit - kWindow + 1, 0.5, w14);
+        }
       }
     }
     // far entries of the atom's own row
@@ -128,7 +146,7 @@ __global__ void __launch_bounds__(kBlock) k_ewald_atoms(Dev d, const T *__restri
         if (jl < 0 || jl >= nb) continue;                     // not an atom of the system (the build flags it)
         if (repeated(excl_off, excl_idx, i, k)) continue;
         const int j = sd.atom_begin + jl;
-        add(j, row_lists(excl_off, excl_idx, j, il) ? 0.5 : 1.0);
+        add(j, row_lists(excl_off, excl_idx, j, il) ? 0.5 : 1.0, 1.0);
       }
     }
     v[0] -= ke * beta * 0.5 * kTwoOverSqrtPi * qi * qi;  // self term
@@ -228,14 +246,14 @@ hipError_t launch_ewald(const Plan &p, const Dev &d, const nb_system *sys, doubl
     const double *pos = static_cast<const double *>(sys->pos);
     const double *q = static_cast<const double *>(sys->charge);
     hipLaunchKernelGGL(k_ewald_atoms<double>, grid, block, 0, s, d, pos, q, sys->excl_offset, sys->excl_index, ke,
-                       beta, force);
+                       beta, 1.0 - p.s14_c, force);
     hipLaunchKernelGGL(k_ewald_far<double>, grid, block, 0, s, d, pos, q, sys->excl_offset, sys->excl_index, ke,
                        beta, force);
   } else {
     const float *pos = static_cast<const float *>(sys->pos);
     const float *q = static_cast<const float *>(sys->charge);
     hipLaunchKernelGGL(k_ewald_atoms<float>, grid, block, 0, s, d, pos, q, sys->excl_offset, sys->excl_index, ke,
-                       beta, force);
+                       beta, 1.0 - p.s14_c, force);
     hipLaunchKernelGGL(k_ewald_far<float>, grid, block, 0, s, d, pos, q, sys->excl_offset, sys->excl_index, ke,
                        beta, force);
   }

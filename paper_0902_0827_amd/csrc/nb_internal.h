@@ -66,7 +66,7 @@ struct alignas(16) TypePair32 { float c6, c12, inv_sig, pad; };
 struct Layout {
   size_t status, desc, tab64, tab32, cell_count, cell_start, atom_cell, atom_slot, atom_fix, tmp, s_range, scan_tiles;
   size_t s_fix, s_pos64, s_q32, s_type, excl_mask, excl_far, partials, adj_partials;
-  size_t col_clu_start, part, queue, jacc;
+  size_t col_clu_start, part, queue, jacc, p14_mask;
   size_t total;
 };
 
@@ -83,6 +83,10 @@ struct Plan {
   int schedule = 2;      // NB_SCHED_STATIC or NB_SCHED_DYNAMIC (cluster kernel)
   int wg_per_cu = 16;    // resident one-wave workgroups per compute unit (dynamic schedule)
   double cutoff = 0, beta = 0, ke = 0;
+  // Force-field options: LJ switch from r_on (0 = none), scaled 1-4 pairs (has14: the
+  // system carries 1-4 lists); ff when either is in use (the pair kernels' FF variants).
+  double switch_on = 0, s14_lj = 1, s14_c = 1;
+  bool has14 = false, ff = false;
   int64_t n_cells = 0, n_blocks = 0, n_clusters_max = 0, n_columns = 0;
   std::vector<SysDesc> desc;
   Layout lay{};
@@ -107,6 +111,7 @@ struct Dev {
   float *s_q32;      // sorted: charge * sqrt(k_e) in float
   int32_t *s_type;   // sorted: type (clamped into range)
   uint4 *excl_mask;  // original order: 128-bit exclusion window
+  uint4 *p14_mask;   // original order: 128-bit window of the scaled 1-4 partners (null without 1-4 lists)
   uint32_t *excl_far;// original order: nonzero if the atom has an exclusion beyond the window
   double *partials;      // [kPart][n_slots]: per-block (or per-wave) energy and virial sums
   double *adj_partials;  // [2 T][n_slots]: per-block (or per-wave) sigma / eps sums by type
@@ -136,6 +141,10 @@ struct Consts {
   double rc2, beta, two_beta_sqrtpi, ke, sqrt_ke;
   float rc2f, betaf, two_beta_sqrtpif, mb2l2e, rc2_box;
   int erfc_short;  // beta R within the short FP64 erfc table's range
+  // FF variants: 1-4 scale factors and the LJ switch as x = (r^2 - sw_on2) sw_inv, S = 1 for
+  // x <= 0 (no switch: sw_on2 = R^2 and sw_inv = 0, so S = 1 for every pair)
+  double s14_lj, s14_c, sw_on2, sw_inv;
+  float s14_ljf, s14_cf, sw_on2f, sw_invf;
 };
 
 struct Out {

@@ -324,6 +324,19 @@ Consts make_consts(const Plan &p) {
   c.mb2l2e = static_cast<float>(-p.beta * p.beta * 1.4426950408889634074);  // -beta^2 log2(e)
   c.rc2_box = static_cast<float>(c.rc2 * 1.0001);  // generous: the box filter may only keep extra atoms
   c.erfc_short = p.beta * p.cutoff <= kErfcxShortMax ? 1 : 0;
+  c.s14_lj = p.s14_lj;
+  c.s14_c = p.s14_c;
+  if (p.switch_on > 0.0) {
+    c.sw_on2 = p.switch_on * p.switch_on;
+    c.sw_inv = 1.0 / (c.rc2 - c.sw_on2);
+  } else {
+    c.sw_on2 = c.rc2;
+    c.sw_inv = 0.0;
+  }
+  c.s14_ljf = static_cast<float>(c.s14_lj);
+  c.s14_cf = static_cast<float>(c.s14_c);
+  c.sw_on2f = static_cast<float>(c.sw_on2);
+  c.sw_invf = static_cast<float>(c.sw_inv);
   return c;
 }
 

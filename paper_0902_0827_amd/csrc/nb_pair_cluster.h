@@ -227,7 +227,7 @@ __device__ __forceinline__ int cluster_column(const int32_t *__restrict__ col_cl
   return lo;
 }
 
-template <bool F64>
+template <bool F64, bool FF>
 struct WaveLds;
 
 // One staged j atom of the mixed-precision kernel (one 32-byte slot, so that a group
@@ -238,18 +238,28 @@ struct alignas(16) RingF32 {
   int2 sidx;   // sorted index (half-shell kernel), unused
 };
 
-template <>
-struct WaveLds<false> {
+// Row windows of the i atoms: byte d of row ii describes j - i = d - 64: bit 0 excluded,
+// bit 1 a scaled 1-4 pair (FF variants).
+template <bool FF>
+struct WaveLds<false, FF> {
   RingF32 ring[kRing];
   int2 runs[kMaxRuns + kRunPad];  // non-empty candidate runs: (first sorted atom, first candidate position)
   uint32_t exw[8 * kExBytes / 4];  // exclusion window of each row's i atom, bytes
 };
 
 template <>
-struct WaveLds<true> {
+struct WaveLds<true, false> {
   double4 pos[kRing];  // x, y, z, q
   int4 meta[kRing];    // original index, type, sorted index (half-shell kernel), unused
   int2 runs[kMaxRuns + kRunPad];  // non-empty candidate runs: (first sorted atom, first candidate position)
+};
+
+template <>
+struct WaveLds<true, true> {  // the FP64 FF variants read their windows from LDS as well
+  double4 pos[kRing];
+  int4 meta[kRing];
+  int2 runs[kMaxRuns + kRunPad];
+  uint32_t exw[8 * kExBytes / 4];
 };
 
 // Type-pair table entry of each precision; the table is copied into dynamic LDS sized
@@ -335,7 +345,7 @@ __device__ __forceinline__ int xcd_id() {
 // PAIRS2 (mixed path): the group loop takes two groups per pass, which needs more
 // registers (4 resident waves per SIMD instead of 5); the launcher uses it when every
 // item fits on the GPU at once at that occupancy.
-template <bool F64, int MODE, bool TABLDS, int K, bool HALF, bool PAIRS2>
+template <bool F64, int MODE, bool TABLDS, int K, bool HALF, bool PAIRS2, bool FF>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? kF64WavesPerEu : 1, 8)))
 k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   // Products are fused into additions only within one expression (the explicit FMAs
@@ -344,7 +354,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
 #pragma clang fp contract(on)
   constexpr int J = 64 / K;  // j atoms per group (lanes per row)
   extern __shared__ uint4 tab_lds[];  // [T * T] type pairs when TABLDS, then the stage when HALF
-  __shared__ WaveLds<F64> L;
+  __shared__ WaveLds<F64, FF> L;
   TypePairLds<F64, MODE> *const TL = reinterpret_cast<TypePairLds<F64, MODE> *>(tab_lds);
   const int lane = static_cast<int>(threadIdx.x);
   if (!built_for(d.status, d.N, true, F64, HALF)) {
@@ -461,8 +471,12 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     // the resident waves).
     const uint32_t oi_lo = static_cast<uint32_t>(oi) - static_cast<uint32_t>(kWindow);
     const uint8_t *ex_row = nullptr;
-    if constexpr (!F64) ex_row = reinterpret_cast<const uint8_t *>(L.exw) + ii * kExBytes;
+    if constexpr (!F64 || FF) ex_row = reinterpret_cast<const uint8_t *>(L.exw) + ii * kExBytes;
     const uint4 mask_i = d.excl_mask[oi];
+    uint4 mask14_i = make_uint4(0u, 0u, 0u, 0u);
+    if constexpr (FF) {
+      if (d.p14_mask) mask14_i = d.p14_mask[oi];
+    }
     const uint64_t mask_lo = (static_cast<uint64_t>(mask_i.y) << 32) | mask_i.x;
     const uint64_t mask_hi = (static_cast<uint64_t>(mask_i.w) << 32) | mask_i.z;
     const bool far_i = d.excl_far[oi] != 0u;
@@ -521,15 +535,21 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     // Row ii's window as bytes, 4 per word: bits 0-63 of the mask are j - i = -64..-1,
     // then j = i, then mask bits 64-127 (j - i = 1..64); word m holds bits 4m..4m+3 of
     // that 132-bit string, each spread to the low bit of a byte.
-    for (int m = jj; !F64 && m < kExBytes / 4; m += J) {
+    // FF variants: bit 1 of each byte from the 1-4 window, whose self position is 0.
+    for (int m = jj; (!F64 || FF) && m < kExBytes / 4; m += J) {
       const int w = m >> 3;
-      const uint32_t src = w == 0 ? mask_i.x
-                         : w == 1 ? mask_i.y
-                         : w == 2 ? (mask_i.z << 1) | 1u
-                         : w == 3 ? (mask_i.w << 1) | (mask_i.z >> 31)
-                                  : mask_i.w >> 31;
-      const uint32_t nib = (src >> ((m & 7) * 4)) & 15u;
-      if constexpr (!F64) L.exw[ii * (kExBytes / 4) + m] = (nib * 0x00204081u) & 0x01010101u;
+      auto spread = [&](const uint4 &mk, uint32_t self) -> uint32_t {
+        const uint32_t src = w == 0 ? mk.x
+                           : w == 1 ? mk.y
+                           : w == 2 ? (mk.z << 1) | self
+                           : w == 3 ? (mk.w << 1) | (mk.z >> 31)
+                                    : mk.w >> 31;
+        const uint32_t nib = (src >> ((m & 7) * 4)) & 15u;
+        return (nib * 0x00204081u) & 0x01010101u;
+      };
+      uint32_t word = spread(mask_i, 1u);
+      if constexpr (FF) word |= spread(mask14_i, 0u) << 1;
+      if constexpr (!F64 || FF) L.exw[ii * (kExBytes / 4) + m] = word;
     }
     for (int k0 = 0; k0 < ncol; k0 += 64) {
       const int k = k0 + lane;
@@ -670,7 +690,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       // distance.  FP64 path: selected from the mask in registers.
       uint32_t exb;
       bool outside;
-      if constexpr (F64) {
+      if constexpr (F64 && !FF) {
         const int delta = oj - oi;
         outside = static_cast<uint32_t>(delta + kWindow) > 2u * kWindow;
         const uint64_t wbits = delta < 0 ? mask_lo : mask_hi;
@@ -723,7 +743,22 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         r2f = fmaf(s2z * dzf, dzf, fmaf(s2y * dyf, dyf, s2x * dxf * dxf));
         hit = ivalid & jv & (r2f < c.rc2f) & other;
       }
-      hit = hit & (exb == 0u);
+      // FF variants: bit 0 of the window byte excludes, bit 1 marks a scaled 1-4 pair
+      float wljf = 1.f, wcf = 1.f;
+      double wljd = 1.0, wcd = 1.0;
+      if constexpr (FF) {
+        hit = hit & ((exb & 1u) == 0u);
+        const bool scaled = (exb & 2u) != 0u;
+        if constexpr (F64) {
+          wljd = scaled ? c.s14_lj : 1.0;
+          wcd = scaled ? c.s14_c : 1.0;
+        } else {
+          wljf = scaled ? c.s14_ljf : 1.f;
+          wcf = scaled ? c.s14_cf : 1.f;
+        }
+      } else {
+        hit = hit & (exb == 0u);
+      }
       // Pairs farther apart than the window only for atoms that carry the far flag.
       if (FAR && any_far) {  // wave-uniform: some atom of this cluster has an exclusion beyond the window
         const bool far_check = hit && outside && far_i;
@@ -735,7 +770,9 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       // not finite, are selected away), so the group runs without a branch.
       {
         if constexpr (F64) {
-          PairF64 p = pair_f64(r2d, tp.c6, tp.c12, qi64 * pj64.w, c.beta, c.two_beta_sqrtpi, c.erfc_short != 0);
+          PairF64 p = FF ? pair_f64_ff(r2d, tp.c6, tp.c12, qi64 * pj64.w * wcd, wljd, c.beta, c.two_beta_sqrtpi,
+                                       c.erfc_short != 0, c.sw_on2, c.sw_inv)
+                         : pair_f64(r2d, tp.c6, tp.c12, qi64 * pj64.w, c.beta, c.two_beta_sqrtpi, c.erfc_short != 0);
           p.f = hit ? p.f : 0.0;
           p.u_lj = hit ? p.u_lj : 0.0;
           p.u_c = hit ? p.u_c : 0.0;
@@ -762,12 +799,14 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
             }
           }
           if constexpr (MODE == kAdjoint) {
-            phi += pj64.w * p.erfc_over_r;
+            phi += (FF ? pj64.w * wcd : pj64.w) * p.erfc_over_r;
             asig += p.dudsig_lj * tp.inv_sig;
             beps += p.u_lj;
           }
         } else {
-          PairF32 p = pair_f32(r2f, tp.c6, tp.c12, qi32 * qj, c.betaf, c.two_beta_sqrtpif, c.mb2l2e);
+          PairF32 p = FF ? pair_f32_ff(r2f, tp.c6, tp.c12, qi32 * qj * wcf, wljf, c.betaf, c.two_beta_sqrtpif,
+                                       c.mb2l2e, c.sw_on2f, c.sw_invf)
+                         : pair_f32(r2f, tp.c6, tp.c12, qi32 * qj, c.betaf, c.two_beta_sqrtpif, c.mb2l2e);
           p.f = hit ? p.f : 0.f;
           if constexpr (MODE == kAdjoint) {
             p.u_lj = hit ? p.u_lj : 0.f;
@@ -798,7 +837,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
             }
           }
           if constexpr (MODE == kAdjoint) {
-            phi += static_cast<double>(qj * p.erfc_over_r);
+            phi += static_cast<double>((FF ? qj * wcf : qj) * p.erfc_over_r);
             asig += static_cast<double>(p.dudsig_lj * tp.inv_sig);
             beps += static_cast<double>(p.u_lj);
           }
@@ -1252,8 +1291,8 @@ int resident_workgroups(const void *kern, size_t lds_bytes, Query query) {
 }
 
 template <bool F64, bool TABLDS, int K>
-void launch_cluster_mode(int mode, bool half, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s, const Dev &d,
-                         const Consts &c, const Out &o, int Q) {
+void launch_cluster_mode(int mode, bool half, bool ff, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s,
+                         const Dev &d, const Consts &c, const Out &o, int Q) {
   const dim3 block(64);
   auto go = [&](auto kern, auto mode_tag, auto half_tag) {
     const size_t lds = dyn_lds_bytes<F64, decltype(mode_tag)::value, TABLDS, decltype(half_tag)::value>(d.T);
@@ -1273,27 +1312,33 @@ void launch_cluster_mode(int mode, bool half, int64_t wgs, int dyn, int wg_per_c
   // and the instruction-level parallelism of two groups is worth more (23.6k-atom box:
   // 64.2 -> 61.0 us; 64-replica batch, 100,000 items: 1,083 against 1,117 us with it).
   const bool pairs2 = !F64 && !half && !dyn && wgs <= static_cast<int64_t>(compute_units()) * kPairs2WavesPerCu;
-  if (mode == kForces) {
-    if (half && pairs2) go(k_pair_cluster<F64, kForces, TABLDS, K, true, !F64>, std::integral_constant<int, kForces>{}, std::true_type{});
-    else if (half) go(k_pair_cluster<F64, kForces, TABLDS, K, true, false>, std::integral_constant<int, kForces>{}, std::true_type{});
-    else if (pairs2) go(k_pair_cluster<F64, kForces, TABLDS, K, false, !F64>, std::integral_constant<int, kForces>{}, std::false_type{});
-    else go(k_pair_cluster<F64, kForces, TABLDS, K, false, false>, std::integral_constant<int, kForces>{}, std::false_type{});
-  } else if (mode == kEnergy) {
-    if (half && pairs2) go(k_pair_cluster<F64, kEnergy, TABLDS, K, true, !F64>, std::integral_constant<int, kEnergy>{}, std::true_type{});
-    else if (half) go(k_pair_cluster<F64, kEnergy, TABLDS, K, true, false>, std::integral_constant<int, kEnergy>{}, std::true_type{});
-    else if (pairs2) go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, !F64>, std::integral_constant<int, kEnergy>{}, std::false_type{});
-    else go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, false>, std::integral_constant<int, kEnergy>{}, std::false_type{});
-  } else {
-    if (pairs2) go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, !F64>, std::integral_constant<int, kAdjoint>{}, std::false_type{});
-    else go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, false>, std::integral_constant<int, kAdjoint>{}, std::false_type{});
-  }
+  auto dispatch = [&](auto ff_c) {
+    constexpr bool FF = decltype(ff_c)::value;
+    using M0 = std::integral_constant<int, kForces>;
+    using M1 = std::integral_constant<int, kEnergy>;
+    using M2 = std::integral_constant<int, kAdjoint>;
+    if (mode == kForces) {
+      if (half) go(k_pair_cluster<F64, kForces, TABLDS, K, true, false, FF>, M0{}, std::true_type{});
+      else if (pairs2) go(k_pair_cluster<F64, kForces, TABLDS, K, false, !F64, FF>, M0{}, std::false_type{});
+      else go(k_pair_cluster<F64, kForces, TABLDS, K, false, false, FF>, M0{}, std::false_type{});
+    } else if (mode == kEnergy) {
+      if (half) go(k_pair_cluster<F64, kEnergy, TABLDS, K, true, false, FF>, M1{}, std::true_type{});
+      else if (pairs2) go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, !F64, FF>, M1{}, std::false_type{});
+      else go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, false, FF>, M1{}, std::false_type{});
+    } else {
+      if (pairs2) go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, !F64, FF>, M2{}, std::false_type{});
+      else go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, false, FF>, M2{}, std::false_type{});
+    }
+  };
+  if (ff) dispatch(std::true_type{});
+  else dispatch(std::false_type{});
 }
 
 template <bool F64, bool TABLDS>
-void launch_cluster_k(int K, int mode, bool half, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s, const Dev &d,
-                      const Consts &c, const Out &o, int Q) {
-  if (K == 8) launch_cluster_mode<F64, TABLDS, 8>(mode, half, wgs, dyn, wg_per_cu, s, d, c, o, Q);
-  else launch_cluster_mode<F64, TABLDS, 4>(mode, half, wgs, dyn, wg_per_cu, s, d, c, o, Q);
+void launch_cluster_k(int K, int mode, bool half, bool ff, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s,
+                      const Dev &d, const Consts &c, const Out &o, int Q) {
+  if (K == 8) launch_cluster_mode<F64, TABLDS, 8>(mode, half, ff, wgs, dyn, wg_per_cu, s, d, c, o, Q);
+  else launch_cluster_mode<F64, TABLDS, 4>(mode, half, ff, wgs, dyn, wg_per_cu, s, d, c, o, Q);
 }
 
 }  // namespace
@@ -1310,8 +1355,8 @@ void launch_cluster_pair_prec(const Plan &p, const Dev &d, const Consts &c, cons
     const bool tab = p.T <= kTabLds;
     const int K = p.cluster_size;
     timer_before(s);
-    if (tab) launch_cluster_k<F64, true>(K, mode, half, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
-    else launch_cluster_k<F64, false>(K, mode, half, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
+    if (tab) launch_cluster_k<F64, true>(K, mode, half, p.ff, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
+    else launch_cluster_k<F64, false>(K, mode, half, p.ff, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
     timer_after(s);
   }
 }

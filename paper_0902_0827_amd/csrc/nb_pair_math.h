@@ -73,6 +73,41 @@ __device__ __forceinline__ PairF32 pair_f32(float r2, float c6, float c12, float
   return o;
 }
 
+// The same pair terms with the force-field options: the Lennard-Jones term weighted by
+// w_lj (the 1-4 scale, else 1) and by the switch S(x) = (1 - x)^2 (1 + 2x),
+// x = max((r^2 - sw_on2) sw_inv, 0) (the caller folds the 1-4 Coulomb scale into qq).
+// With u0 and d0 = 12 a - 6 b the unswitched energy and its -r du/dr:
+//   u_lj      = w S u0
+//   dudsig_lj = w S d0                    (the sigma derivative at fixed r, for the adjoint)
+//   f         = [w (S d0 + 12 x (1 - x) r^2 sw_inv u0) + qq (...)] / r^2
+// the middle term being -2 r^2 u0 dS/d(r^2).  No switch: sw_inv = 0, so x = 0 and S = 1.
+__device__ __forceinline__ PairF32 pair_f32_ff(float r2, float c6, float c12, float qq, float w_lj, float beta,
+                                               float two_beta_sqrtpi, float mb2l2e, float sw_on2, float sw_inv) {
+#pragma clang fp contract(on)
+  PairF32 o;
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  const float rinv2 = rinv * rinv;
+  const float rinv6 = rinv2 * rinv2 * rinv2;
+  const float a = c12 * rinv6 * rinv6;
+  const float b = c6 * rinv6;
+  const float u0 = a - b;
+  const float d0 = fmaf(12.0f, a, -6.0f * b);
+  const float x = fmaxf((r2 - sw_on2) * sw_inv, 0.0f);
+  const float omx = 1.0f - x;
+  const float ws = w_lj * (omx * omx * fmaf(2.0f, x, 1.0f));
+  o.u_lj = ws * u0;
+  o.dudsig_lj = ws * d0;
+  const float dsw = w_lj * (12.0f * x * omx) * (r2 * sw_inv);
+  const float d_force = fmaf(dsw, u0, o.dudsig_lj);
+  const float r = r2 * rinv;
+  const float e = __builtin_amdgcn_exp2f(r2 * mb2l2e);  // exp(-beta^2 r^2)
+  const float erfc_br = erfcx_f32(beta * r) * e;
+  o.erfc_over_r = erfc_br * rinv;
+  o.u_c = qq * o.erfc_over_r;
+  o.f = fmaf(qq, fmaf(two_beta_sqrtpi, e, o.erfc_over_r), d_force) * rinv2;
+  return o;
+}
+
 // erfc(x) = exp(-x^2) * g(x) in double precision, with g a polynomial of degree 24 in
 // s = (x - 3)/(x + 3), which maps x in [0, inf) onto [-1, 1): a Chebyshev interpolant
 // of g converted to monomial form (gen_erfc_coeffs.py --f64).  Relative error of g
@@ -219,6 +254,35 @@ __device__ __forceinline__ PairF64 pair_f64(double r2, double c6, double c12, do
   o.erfc_over_r = erfc_br * rinv;
   o.u_c = qq * o.erfc_over_r;
   o.f = (o.dudsig_lj + qq * (o.erfc_over_r + two_beta_sqrtpi * e)) * rinv2;
+  return o;
+}
+
+// The double-precision pair terms with the force-field options (as pair_f32_ff).
+__device__ __forceinline__ PairF64 pair_f64_ff(double r2, double c6, double c12, double qq, double w_lj, double beta,
+                                               double two_beta_sqrtpi, bool short_erfc, double sw_on2,
+                                               double sw_inv) {
+  PairF64 o;
+  double rinv = __builtin_amdgcn_rsq(r2);
+  rinv = rinv * fma(-0.5 * r2, rinv * rinv, 1.5);
+  rinv = rinv * fma(-0.5 * r2, rinv * rinv, 1.5);
+  const double r = r2 * rinv;
+  const double rinv2 = rinv * rinv;
+  const double rinv6 = rinv2 * rinv2 * rinv2;
+  const double a = c12 * rinv6 * rinv6;
+  const double b = c6 * rinv6;
+  const double u0 = a - b;
+  const double d0 = 12.0 * a - 6.0 * b;
+  const double x = fmax((r2 - sw_on2) * sw_inv, 0.0);
+  const double omx = 1.0 - x;
+  const double ws = w_lj * (omx * omx * (1.0 + 2.0 * x));
+  o.u_lj = ws * u0;
+  o.dudsig_lj = ws * d0;
+  const double d_force = o.dudsig_lj + w_lj * (12.0 * x * omx) * (r2 * sw_inv) * u0;
+  const double e = exp_neg_f64(beta * beta * r2);  // exp(-(beta r)^2)
+  const double erfc_br = erfcx_f64(beta * r, short_erfc) * e;
+  o.erfc_over_r = erfc_br * rinv;
+  o.u_c = qq * o.erfc_over_r;
+  o.f = (d_force + qq * (o.erfc_over_r + two_beta_sqrtpi * e)) * rinv2;
   return o;
 }
 

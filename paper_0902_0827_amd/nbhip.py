@@ -35,6 +35,7 @@ NB_STATUS_BAD_TYPE = 0x2
 NB_STATUS_BAD_EXCLUSION = 0x4
 NB_STATUS_FAR_EXCLUSION = 0x8
 NB_STATUS_NOT_BUILT = 0x10
+NB_STATUS_FAR_PAIR14 = 0x20
 NB_MAX_TYPES = 64
 
 EXPORTED = ("nb_workspace_bytes", "nb_build_cells", "nb_nonbonded_forces", "nb_nonbonded_energy",
@@ -63,6 +64,8 @@ class nb_system(ctypes.Structure):
         ("n_types", ctypes.c_int32),
         ("excl_offset", ctypes.c_void_p),
         ("excl_index", ctypes.c_void_p),
+        ("pair14_offset", ctypes.c_void_p),
+        ("pair14_index", ctypes.c_void_p),
     ]
 
 
@@ -79,6 +82,9 @@ class nb_params(ctypes.Structure):
         ("cluster_size", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
         ("wg_per_cu", ctypes.c_int32),
+        ("lj_switch_on", ctypes.c_double),
+        ("scale14_lj", ctypes.c_double),
+        ("scale14_coul", ctypes.c_double),
     ]
 
 
@@ -152,9 +158,11 @@ def _stream(stream=None) -> int:
 
 def make_params(cutoff: float, beta: float, precision: int = NB_MIXED, coulomb_k: float = COULOMB_K,
                 cell_div_xy: int = 0, cell_div_z: int = 0, kernel: int = NB_KERNEL_AUTO, split: int = 0,
-                cluster_size: int = 0, schedule: int = 0, wg_per_cu: int = 0) -> nb_params:
+                cluster_size: int = 0, schedule: int = 0, wg_per_cu: int = 0, lj_switch_on: float = 0.0,
+                scale14_lj: float = 1.0, scale14_coul: float = 1.0) -> nb_params:
     return nb_params(float(cutoff), float(beta), float(coulomb_k), int(precision), int(cell_div_xy),
-                     int(cell_div_z), int(kernel), int(split), int(cluster_size), int(schedule), int(wg_per_cu))
+                     int(cell_div_z), int(kernel), int(split), int(cluster_size), int(schedule), int(wg_per_cu),
+                     float(lj_switch_on), float(scale14_lj), float(scale14_coul))
 
 
 @dataclass
@@ -170,6 +178,8 @@ class DeviceBatch:
     excl_index: "object"   # [n_excl] int32 (at least one element)
     atom_offset: np.ndarray
     box: np.ndarray        # [B,3] float64
+    pair14_offset: "object" = None  # [N+1] int32, or None
+    pair14_index: "object" = None   # [n_14] int32 (at least one element), or None
     _struct: nb_system = field(default=None, repr=False)
 
     @property
@@ -198,6 +208,8 @@ class DeviceBatch:
         s.n_types = int(self.sigma.shape[0])
         s.excl_offset = _ptr(self.excl_offset)
         s.excl_index = _ptr(self.excl_index)
+        s.pair14_offset = _ptr(self.pair14_offset)
+        s.pair14_index = _ptr(self.pair14_index)
         self._struct = s
         return s
 
@@ -220,6 +232,11 @@ def device_batch(systems: Sequence, dtype=None, device: str = "cuda") -> DeviceB
         excl_index=torch.tensor(ei, dtype=torch.int32, device=device),
         atom_offset=cat["atom_offset"].astype(np.int64),
         box=cat["box"].astype(np.float64),
+        pair14_offset=None if cat["pair14_offset"] is None else
+        torch.tensor(cat["pair14_offset"], dtype=torch.int32, device=device),
+        pair14_index=None if cat["pair14_offset"] is None else
+        torch.tensor(cat["pair14_index"] if cat["pair14_index"].size else np.zeros(1, np.int32),
+                     dtype=torch.int32, device=device),
     )
 
 

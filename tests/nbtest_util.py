@@ -61,12 +61,14 @@ def small_chain():
     return S.solvated_chain(18.6, 30, 190, seed=11, cutoff=9.0, beta=0.34, name="small")
 
 
-def oracle_for(system, precision, rows=None):
-    return O.evaluate_system(rounded(system, precision), rows=rows, ke=H.COULOMB_K)
+def oracle_for(system, precision, rows=None, **ff):
+    """The oracle on the values the device computes with; ff: lj_switch_on, scale14_lj,
+    scale14_coul (the system's own 1-4 lists are used when it has them)."""
+    return O.evaluate_system(rounded(system, precision), rows=rows, ke=H.COULOMB_K, **ff)
 
 
 def gpu_eval(systems, precision, cell_div_xy=0, cell_div_z=0, kernel=H.NB_KERNEL_AUTO, energy_call=False,
-             backward=False, grad_energy=None, split=0, cluster_size=0, schedule=0, wg_per_cu=0):
+             backward=False, grad_energy=None, split=0, cluster_size=0, schedule=0, wg_per_cu=0, **ff):
     """Runs build_cells + forces (and optionally energy / backward) through the C ABI.
     kernel "cluster8" is the cluster kernel with 8-atom clusters, "cluster4_static" the
     cluster kernel with 4-atom clusters, two items per cluster and one item per wave;
@@ -86,7 +88,7 @@ def gpu_eval(systems, precision, cell_div_xy=0, cell_div_z=0, kernel=H.NB_KERNEL
     b = H.device_batch(systems, dtype=dt)
     p = H.make_params(systems[0].cutoff, systems[0].beta, precision, cell_div_xy=cell_div_xy,
                       cell_div_z=cell_div_z, kernel=kernel, split=split, cluster_size=cluster_size,
-                      schedule=schedule, wg_per_cu=wg_per_cu)
+                      schedule=schedule, wg_per_cu=wg_per_cu, **ff)
     force, energy, vir, ws = H.evaluate(b, p)
     out = dict(force=force.cpu().numpy(), energy=energy.cpu().numpy(), virial=vir.cpu().numpy(),
                batch=b, params=p, ws=ws)

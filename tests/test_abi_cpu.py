@@ -260,3 +260,24 @@ def test_noalloc_entry_point_refuses_batches_beyond_its_scratch():
     assert code == H.NB_ERR_CAPACITY and "allocation-free" in H.last_error()
     assert lib.nb_nonbonded_forces_noalloc(ctypes.byref(s), ctypes.byref(p), None, None, None, None) \
         == H.NB_ERR_ARG  # force is required
+
+
+def test_force_field_options_are_validated_on_the_host():
+    lib = H.load_library()
+    n = ctypes.c_size_t()
+    s = fake_system((648,))
+    ok = lambda p: lib.nb_workspace_bytes(ctypes.byref(s), ctypes.byref(p), ctypes.byref(n))
+    assert ok(H.make_params(9.0, 0.34, lj_switch_on=7.5)) == H.NB_OK
+    assert ok(H.make_params(9.0, 0.34, lj_switch_on=9.0)) == H.NB_ERR_ARG  # r_on must be below R
+    assert ok(H.make_params(9.0, 0.34, lj_switch_on=-1.0)) == H.NB_ERR_ARG
+    assert ok(H.make_params(9.0, 0.34, scale14_lj=float("nan"))) == H.NB_ERR_ARG
+    # the per-atom kernel supports neither option
+    assert ok(H.make_params(9.0, 0.34, kernel=H.NB_KERNEL_ATOM, lj_switch_on=7.5)) == H.NB_ERR_ARG
+    assert "per-atom" in H.last_error()
+    base = ws_bytes(s, H.make_params(9.0, 0.34))[1]
+    s.pair14_offset = FAKE
+    assert ok(H.make_params(9.0, 0.34)) == H.NB_ERR_ARG  # offsets without indices
+    s.pair14_index = FAKE
+    assert ok(H.make_params(9.0, 0.34)) == H.NB_OK
+    assert n.value >= base + 16 * 648  # one 128-bit 1-4 window per atom
+    assert ok(H.make_params(9.0, 0.34, kernel=H.NB_KERNEL_ATOM)) == H.NB_ERR_ARG
