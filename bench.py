@@ -351,6 +351,30 @@ def run_large(args, H, S, torch):
             "binning": m["build"], "sampled_atoms": len(rows), "oracle_ms_sampled": oracle_ms}
 
 
+def run_tables(args, H, s, torch):
+    """The paper's tabulated variant on the 23.6k box (mixed path): linear tables of 4096
+    intervals and cubic Hermite tables of 1024, step and pair-kernel time beside the
+    direct evaluation's; forces returned for the error columns."""
+    out = {}
+    for name, table in (("linear_4096", 1), ("cubic_1024", 2)):
+        b = H.device_batch([s], dtype=torch.float32)
+        p = H.make_params(s.cutoff, s.beta, H.NB_MIXED, table=table)
+        ws = H.alloc_workspace(b, p)
+        force = torch.empty((s.n, 3), dtype=torch.float64, device="cuda")
+        energy = torch.empty(1, dtype=torch.float64, device="cuda")
+        vir = torch.empty((1, 3, 3), dtype=torch.float64, device="cuda")
+
+        def step():
+            H.build_cells(b, p, ws)
+            H.nonbonded_forces(b, p, ws, force, energy, vir)
+
+        t = time_steps(step, args.steps, args.warmup, torch, H)
+        log(f"[bench] table {name}: {t['sec'] * 1e3:.4f} ms/step, pair kernel {t['pair_sec'] * 1e6:.1f} us")
+        out[name] = {"ms_per_step": t["sec"] * 1e3, "pair_kernel_us": t["pair_sec"] * 1e6,
+                     "force": force.cpu().numpy(), "energy": float(energy.cpu()[0])}
+    return out
+
+
 def cpu_info():
     """Host CPU model (lscpu) and the threads the oracle may use."""
     import subprocess
@@ -384,6 +408,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-replica batch measurement")
     ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--no-large", action="store_true", help="skip the million-atom water box")
+    ap.add_argument("--no-tables", action="store_true", help="skip the tabulated variant")
     ap.add_argument("--large-steps", type=int, default=20)
     ap.add_argument("--large-rows", type=int, default=256, help="oracle rows sampled on the million-atom box")
     ap.add_argument("--tune-budget", type=float, default=45.0,
@@ -507,6 +532,7 @@ def main():
 
     batch = None if args.no_batch else run_batch(args, H, S, torch)
     large = None if args.no_large else run_large(args, H, S, torch)
+    tables = None if args.no_tables else run_tables(args, H, s, torch)
 
     pairs = ref["mixed"]["pairs"]
     m = results["mixed"]
@@ -576,6 +602,14 @@ def main():
         # the million-atom box: mixed forward and adjoint, FP64 path, binning at this size,
         # errors on sampled oracle rows and against the FP64 GPU path
         "large": large,
+        # the paper's tabulated variant (radial tables, linear n = 4096 and cubic n = 1024)
+        # against the direct evaluation on the same box: time and force error
+        "tables": None if tables is None else {
+            name: {"ms_per_step": t["ms_per_step"], "pair_kernel_us": t["pair_kernel_us"],
+                   "rel_rms_force": rel_errors(t["force"], ref["mixed"]["force"])[0],
+                   "max_rel_force": rel_errors(t["force"], ref["mixed"]["force"])[1],
+                   "energy_rel": abs(t["energy"] - ref["mixed"]["energy_total"]) / abs(ref["mixed"]["energy_total"])}
+            for name, t in tables.items()},
         # nb_build_cells alone: algorithmic HBM bytes (inputs read once, sorted records and
         # exclusion windows written once) over its time, for this box and for the batch
         "binning": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBPS,

@@ -142,6 +142,14 @@ typedef struct {
                          nb_ewald_corrections adds -(1 - scale14_coul) k_e q_i q_j erf(beta r)/r
                          for them, so that with the reciprocal part the whole Coulomb interaction
                          of a 1-4 pair is scale14_coul k_e q_i q_j / r */
+  int32_t table;      /* mixed path, forces and energies: 0 = direct evaluation; 1 = the paper's
+                         tabulated variant (section 3, texture tables): r^-12, r^-6, erfc(beta r)/r
+                         and the Coulomb force factor linearly interpolated from tables uniform in r
+                         over [0, R], built by nb_build_cells; 2 = the same with cubic Hermite
+                         interpolation.  Not combined with the switch or 1-4 pairs; the adjoint
+                         always evaluates directly; the FP64 path ignores it */
+  int32_t table_size; /* intervals of the tables, 16..65536 (0 = 4096 linear, the paper's n;
+                         1024 cubic) */
 } nb_params;
 
 /* Bytes of device workspace needed for this batch and these parameters.

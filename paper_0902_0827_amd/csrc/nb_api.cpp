@@ -65,6 +65,9 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
     return fail(NB_ERR_ARG, "scale14_lj and scale14_coul must be finite");
   if ((sys->pair14_offset == nullptr) != (sys->pair14_index == nullptr))
     return fail(NB_ERR_ARG, "pair14_offset and pair14_index must both be given or both be NULL");
+  if (prm->table < 0 || prm->table > 2) return fail(NB_ERR_ARG, "table must be 0, 1 or 2");
+  if (prm->table_size != 0 && (prm->table_size < 16 || prm->table_size > 65536))
+    return fail(NB_ERR_ARG, "table_size must be 0 or in [16, 65536]");
 
   const int B = sys->n_systems;
   if (sys->atom_offset[0] != 0) return fail(NB_ERR_ARG, "atom_offset[0] must be 0");
@@ -106,6 +109,11 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   p.ff = p.has14 || p.switch_on > 0.0;
   if (p.ff && p.kernel == NB_KERNEL_ATOM)
     return fail(NB_ERR_ARG, "the per-atom kernel supports neither the LJ switch nor 1-4 pairs");
+  // the tabulated variant: mixed path, cluster kernels, plain interaction only
+  p.table = p.precision == NB_MIXED ? prm->table : 0;
+  if (p.table != 0 && (p.ff || p.kernel == NB_KERNEL_ATOM))
+    return fail(NB_ERR_ARG, "the tables are not combined with the switch, 1-4 pairs or the per-atom kernel");
+  p.table_n = p.table == 0 ? 0 : (prm->table_size ? prm->table_size : (p.table == 1 ? 4096 : 1024));
   p.desc.resize(B);
   int64_t cells = 0, blocks = 0, clusters = 0, columns = 0;
   for (int b = 0; b < B; ++b) {
@@ -187,6 +195,7 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   l.queue = take(4 * static_cast<size_t>(kXcds * kQueueStride));
   l.jacc = p.kernel == NB_KERNEL_CLUSTER_HALF ? take(32 * static_cast<size_t>(N)) : 0;
   l.p14_mask = p.has14 ? take(16 * static_cast<size_t>(N)) : 0;
+  l.rtab = p.table ? take(16 * static_cast<size_t>(p.table_n + 1) * static_cast<size_t>(p.table)) : 0;
   l.total = o;
   *plan = std::move(p);
   return NB_OK;
@@ -228,6 +237,7 @@ Dev dev_view(const Plan &p, void *ws) {
   d.n_clusters_max = p.n_clusters_max;
   d.queue = reinterpret_cast<uint32_t *>(base + l.queue);
   d.p14_mask = p.has14 ? reinterpret_cast<uint4 *>(base + l.p14_mask) : nullptr;
+  d.rtab = p.table ? reinterpret_cast<float4 *>(base + l.rtab) : nullptr;
   const bool half = p.kernel == NB_KERNEL_CLUSTER_HALF;
   d.jacc_fix = half && p.precision == NB_MIXED ? reinterpret_cast<long long *>(base + l.jacc) : nullptr;
   d.jacc_f64 = half && p.precision == NB_FP64 ? reinterpret_cast<double *>(base + l.jacc) : nullptr;

@@ -27,6 +27,7 @@
 // measured slower on MI355X (a device-wide barrier across the 8 XCDs costs more
 // than a kernel boundary).
 #include "nb_internal.h"
+#include "nb_pair_math.h"
 
 namespace nb {
 
@@ -120,8 +121,40 @@ __global__ void k_put_desc(Dev d, DescChunk c) {
   if (k < c.count) d.desc[c.first + k] = unpack_desc(c.d[k]);
 }
 
+// Radial tables of the tabulated variant (kind 1 linear, 2 cubic Hermite), n intervals of
+// width h over [0, R]: node k holds, at r = k h (node 0 repeats node 1), r^-12, r^-6,
+// EC = erfc(beta r)/r and FC = [erfc(beta r)/r + (2 beta/sqrt(pi)) exp(-beta^2 r^2)]/r^2,
+// computed in FP64 and rounded to float; cubic tables add h times the r-derivatives:
+//   -12 r^-13, -6 r^-7, -r FC, and -3 g/r^3 - 2 beta^2 (2 beta/sqrt(pi)) exp(-beta^2 r^2)/r
+// with g = r^2 FC.
+struct TableArgs {
+  int kind, n, short_erfc;
+  double h, beta, two_beta_sqrtpi;
+};
+
+__device__ inline void table_node(const Dev &d, const TableArgs &ta, int k) {
+  const double r = (k == 0 ? 1 : k) * ta.h;
+  const double r2 = r * r, rinv = 1.0 / r, rinv2 = rinv * rinv;
+  const double r6 = rinv2 * rinv2 * rinv2;
+  const double e = exp_neg_f64(ta.beta * ta.beta * r2);
+  const double ec = erfcx_f64(ta.beta * r, ta.short_erfc != 0) * e * rinv;
+  const double g = ec + ta.two_beta_sqrtpi * e;
+  const double fc = g * rinv2;
+  const float4 v = make_float4(static_cast<float>(r6 * r6), static_cast<float>(r6), static_cast<float>(ec),
+                               static_cast<float>(fc));
+  if (ta.kind == 1) {
+    d.rtab[k] = v;
+  } else {
+    const double dfc = -3.0 * g * rinv2 * rinv - 2.0 * ta.beta * ta.beta * ta.two_beta_sqrtpi * e * rinv;
+    d.rtab[2 * k] = v;
+    d.rtab[2 * k + 1] = make_float4(static_cast<float>(-12.0 * r6 * r6 * rinv * ta.h),
+                                    static_cast<float>(-6.0 * r6 * rinv * ta.h), static_cast<float>(-r * fc * ta.h),
+                                    static_cast<float>(dfc * ta.h));
+  }
+}
+
 __global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, const double *__restrict__ eps,
-                       int kernel, int f64) {
+                       int kernel, int f64, TableArgs ta) {
   const int64_t tid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   if (tid < c.count) d.desc[c.first + tid] = unpack_desc(c.d[tid]);
@@ -142,6 +175,8 @@ __global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, con
       if (d.jacc_f64) d.jacc_f64[c * d.N + k] = 0.0;
     }
   }
+  if (ta.kind != 0)
+    for (int64_t k = tid; k <= ta.n; k += stride) table_node(d, ta, static_cast<int>(k));
   // Type-pair table, Lorentz-Berthelot: sigma_ij = (s_i + s_j)/2, eps_ij = sqrt(e_i e_j).
   const int T = d.T;
   for (int64_t k = tid; k < static_cast<int64_t>(T) * T; k += stride) {
@@ -581,7 +616,17 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
   unsigned g_init = grid_for(init_work, kBlock);
   if (g_init > 4096) g_init = 4096;
   const int f64 = plan.precision == NB_FP64 ? 1 : 0;
-  hipLaunchKernelGGL(k_init, dim3(g_init), dim3(kBlock), 0, s, d, first, sys->lj_sigma, sys->lj_eps, plan.kernel, f64);
+  TableArgs ta{};
+  ta.kind = plan.table;
+  ta.n = plan.table_n;
+  if (plan.table) {
+    ta.h = plan.cutoff / plan.table_n;
+    ta.beta = plan.beta;
+    ta.two_beta_sqrtpi = 2.0 * plan.beta / 1.7724538509055160273;
+    ta.short_erfc = plan.beta * plan.cutoff <= kErfcxShortMax ? 1 : 0;
+  }
+  hipLaunchKernelGGL(k_init, dim3(g_init), dim3(kBlock), 0, s, d, first, sys->lj_sigma, sys->lj_eps, plan.kernel, f64,
+                     ta);
   for (int b0 = kDescChunk; b0 < plan.B; b0 += kDescChunk) {
     DescChunk c{};
     c.first = b0;

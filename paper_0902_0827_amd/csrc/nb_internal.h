@@ -66,7 +66,7 @@ struct alignas(16) TypePair32 { float c6, c12, inv_sig, pad; };
 struct Layout {
   size_t status, desc, tab64, tab32, cell_count, cell_start, atom_cell, atom_slot, atom_fix, tmp, s_range, scan_tiles;
   size_t s_fix, s_pos64, s_q32, s_type, excl_mask, excl_far, partials, adj_partials;
-  size_t col_clu_start, part, queue, jacc, p14_mask;
+  size_t col_clu_start, part, queue, jacc, p14_mask, rtab;
   size_t total;
 };
 
@@ -87,6 +87,8 @@ struct Plan {
   // system carries 1-4 lists); ff when either is in use (the pair kernels' FF variants).
   double switch_on = 0, s14_lj = 1, s14_c = 1;
   bool has14 = false, ff = false;
+  // Tabulated variant: 0 direct, 1 linear, 2 cubic Hermite radial tables of table_n intervals.
+  int table = 0, table_n = 0;
   int64_t n_cells = 0, n_blocks = 0, n_clusters_max = 0, n_columns = 0;
   std::vector<SysDesc> desc;
   Layout lay{};
@@ -112,6 +114,7 @@ struct Dev {
   int32_t *s_type;   // sorted: type (clamped into range)
   uint4 *excl_mask;  // original order: 128-bit exclusion window
   uint4 *p14_mask;   // original order: 128-bit window of the scaled 1-4 partners (null without 1-4 lists)
+  float4 *rtab;      // radial tables of the tabulated variant (null for direct evaluation)
   uint32_t *excl_far;// original order: nonzero if the atom has an exclusion beyond the window
   double *partials;      // [kPart][n_slots]: per-block (or per-wave) energy and virial sums
   double *adj_partials;  // [2 T][n_slots]: per-block (or per-wave) sigma / eps sums by type
@@ -145,6 +148,8 @@ struct Consts {
   // x <= 0 (no switch: sw_on2 = R^2 and sw_inv = 0, so S = 1 for every pair)
   double s14_lj, s14_c, sw_on2, sw_inv;
   float s14_ljf, s14_cf, sw_on2f, sw_invf;
+  // tabulated variant: 1/h of the radial tables and the last interval's index n - 1
+  float tab_inv_h, tab_last;
 };
 
 struct Out {

@@ -337,6 +337,8 @@ Consts make_consts(const Plan &p) {
   c.s14_cf = static_cast<float>(c.s14_c);
   c.sw_on2f = static_cast<float>(c.sw_on2);
   c.sw_invf = static_cast<float>(c.sw_inv);
+  c.tab_inv_h = p.table ? static_cast<float>(p.table_n / p.cutoff) : 0.f;
+  c.tab_last = p.table ? static_cast<float>(p.table_n - 1) : 0.f;
   return c;
 }
 

@@ -345,7 +345,13 @@ __device__ __forceinline__ int xcd_id() {
 // PAIRS2 (mixed path): the group loop takes two groups per pass, which needs more
 // registers (4 resident waves per SIMD instead of 5); the launcher uses it when every
 // item fits on the GPU at once at that occupancy.
-template <bool F64, int MODE, bool TABLDS, int K, bool HALF, bool PAIRS2, bool FF>
+// Variants of the pair evaluation (template parameter VAR).
+constexpr int kVarPlain = 0;  // direct evaluation
+constexpr int kVarFF = 1;     // direct, with the LJ switch and scaled 1-4 pairs
+constexpr int kVarLin = 2;    // radial terms linearly interpolated from tables (mixed forces / energy)
+constexpr int kVarCub = 3;    // radial terms from cubic Hermite tables (mixed forces / energy)
+
+template <bool F64, int MODE, bool TABLDS, int K, bool HALF, bool PAIRS2, int VAR>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? kF64WavesPerEu : 1, 8)))
 k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   // Products are fused into additions only within one expression (the explicit FMAs
@@ -354,6 +360,9 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
 #pragma clang fp contract(on)
   constexpr int J = 64 / K;  // j atoms per group (lanes per row)
   extern __shared__ uint4 tab_lds[];  // [T * T] type pairs when TABLDS, then the stage when HALF
+  constexpr bool FF = VAR == kVarFF;
+  constexpr int TAB = VAR == kVarLin ? 1 : VAR == kVarCub ? 2 : 0;
+  static_assert(TAB == 0 || (!F64 && MODE != kAdjoint), "tables: mixed forces and energies only");
   __shared__ WaveLds<F64, FF> L;
   TypePairLds<F64, MODE> *const TL = reinterpret_cast<TypePairLds<F64, MODE> *>(tab_lds);
   const int lane = static_cast<int>(threadIdx.x);
@@ -804,9 +813,14 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
             beps += p.u_lj;
           }
         } else {
-          PairF32 p = FF ? pair_f32_ff(r2f, tp.c6, tp.c12, qi32 * qj * wcf, wljf, c.betaf, c.two_beta_sqrtpif,
-                                       c.mb2l2e, c.sw_on2f, c.sw_invf)
-                         : pair_f32(r2f, tp.c6, tp.c12, qi32 * qj, c.betaf, c.two_beta_sqrtpif, c.mb2l2e);
+          PairF32 p;
+          if constexpr (TAB != 0)
+            p = pair_f32_tab<TAB>(r2f, tp.c6, tp.c12, qi32 * qj, d.rtab, c.tab_inv_h, c.tab_last);
+          else if constexpr (FF)
+            p = pair_f32_ff(r2f, tp.c6, tp.c12, qi32 * qj * wcf, wljf, c.betaf, c.two_beta_sqrtpif, c.mb2l2e,
+                            c.sw_on2f, c.sw_invf);
+          else
+            p = pair_f32(r2f, tp.c6, tp.c12, qi32 * qj, c.betaf, c.two_beta_sqrtpif, c.mb2l2e);
           p.f = hit ? p.f : 0.f;
           if constexpr (MODE == kAdjoint) {
             p.u_lj = hit ? p.u_lj : 0.f;
@@ -1291,7 +1305,7 @@ int resident_workgroups(const void *kern, size_t lds_bytes, Query query) {
 }
 
 template <bool F64, bool TABLDS, int K>
-void launch_cluster_mode(int mode, bool half, bool ff, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s,
+void launch_cluster_mode(int mode, bool half, int var, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s,
                          const Dev &d, const Consts &c, const Out &o, int Q) {
   const dim3 block(64);
   auto go = [&](auto kern, auto mode_tag, auto half_tag) {
@@ -1312,33 +1326,40 @@ void launch_cluster_mode(int mode, bool half, bool ff, int64_t wgs, int dyn, int
   // and the instruction-level parallelism of two groups is worth more (23.6k-atom box:
   // 64.2 -> 61.0 us; 64-replica batch, 100,000 items: 1,083 against 1,117 us with it).
   const bool pairs2 = !F64 && !half && !dyn && wgs <= static_cast<int64_t>(compute_units()) * kPairs2WavesPerCu;
-  auto dispatch = [&](auto ff_c) {
-    constexpr bool FF = decltype(ff_c)::value;
+  auto dispatch = [&](auto var_c) {
+    constexpr int VAR = decltype(var_c)::value;
     using M0 = std::integral_constant<int, kForces>;
     using M1 = std::integral_constant<int, kEnergy>;
     using M2 = std::integral_constant<int, kAdjoint>;
     if (mode == kForces) {
-      if (half) go(k_pair_cluster<F64, kForces, TABLDS, K, true, false, FF>, M0{}, std::true_type{});
-      else if (pairs2) go(k_pair_cluster<F64, kForces, TABLDS, K, false, !F64, FF>, M0{}, std::false_type{});
-      else go(k_pair_cluster<F64, kForces, TABLDS, K, false, false, FF>, M0{}, std::false_type{});
+      if (half) go(k_pair_cluster<F64, kForces, TABLDS, K, true, false, VAR>, M0{}, std::true_type{});
+      else if (pairs2) go(k_pair_cluster<F64, kForces, TABLDS, K, false, !F64, VAR>, M0{}, std::false_type{});
+      else go(k_pair_cluster<F64, kForces, TABLDS, K, false, false, VAR>, M0{}, std::false_type{});
     } else if (mode == kEnergy) {
-      if (half) go(k_pair_cluster<F64, kEnergy, TABLDS, K, true, false, FF>, M1{}, std::true_type{});
-      else if (pairs2) go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, !F64, FF>, M1{}, std::false_type{});
-      else go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, false, FF>, M1{}, std::false_type{});
+      if (half) go(k_pair_cluster<F64, kEnergy, TABLDS, K, true, false, VAR>, M1{}, std::true_type{});
+      else if (pairs2) go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, !F64, VAR>, M1{}, std::false_type{});
+      else go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, false, VAR>, M1{}, std::false_type{});
     } else {
-      if (pairs2) go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, !F64, FF>, M2{}, std::false_type{});
-      else go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, false, FF>, M2{}, std::false_type{});
+      constexpr int VA = VAR == kVarFF ? kVarFF : kVarPlain;  // the adjoint evaluates directly
+      if (pairs2) go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, !F64, VA>, M2{}, std::false_type{});
+      else go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, false, VA>, M2{}, std::false_type{});
     }
   };
-  if (ff) dispatch(std::true_type{});
-  else dispatch(std::false_type{});
+  if (var == kVarFF) dispatch(std::integral_constant<int, kVarFF>{});
+  else if constexpr (!F64) {
+    if (var == kVarLin) dispatch(std::integral_constant<int, kVarLin>{});
+    else if (var == kVarCub) dispatch(std::integral_constant<int, kVarCub>{});
+    else dispatch(std::integral_constant<int, kVarPlain>{});
+  } else {
+    dispatch(std::integral_constant<int, kVarPlain>{});
+  }
 }
 
 template <bool F64, bool TABLDS>
-void launch_cluster_k(int K, int mode, bool half, bool ff, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s,
+void launch_cluster_k(int K, int mode, bool half, int var, int64_t wgs, int dyn, int wg_per_cu, hipStream_t s,
                       const Dev &d, const Consts &c, const Out &o, int Q) {
-  if (K == 8) launch_cluster_mode<F64, TABLDS, 8>(mode, half, ff, wgs, dyn, wg_per_cu, s, d, c, o, Q);
-  else launch_cluster_mode<F64, TABLDS, 4>(mode, half, ff, wgs, dyn, wg_per_cu, s, d, c, o, Q);
+  if (K == 8) launch_cluster_mode<F64, TABLDS, 8>(mode, half, var, wgs, dyn, wg_per_cu, s, d, c, o, Q);
+  else launch_cluster_mode<F64, TABLDS, 4>(mode, half, var, wgs, dyn, wg_per_cu, s, d, c, o, Q);
 }
 
 }  // namespace
@@ -1355,8 +1376,9 @@ void launch_cluster_pair_prec(const Plan &p, const Dev &d, const Consts &c, cons
     const bool tab = p.T <= kTabLds;
     const int K = p.cluster_size;
     timer_before(s);
-    if (tab) launch_cluster_k<F64, true>(K, mode, half, p.ff, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
-    else launch_cluster_k<F64, false>(K, mode, half, p.ff, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
+    const int var = p.ff ? kVarFF : p.table == 1 ? kVarLin : p.table == 2 ? kVarCub : kVarPlain;
+    if (tab) launch_cluster_k<F64, true>(K, mode, half, var, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
+    else launch_cluster_k<F64, false>(K, mode, half, var, wgs, dyn, p.wg_per_cu, s, d, c, o, p.split);
     timer_after(s);
   }
 }

@@ -108,6 +108,50 @@ __device__ __forceinline__ PairF32 pair_f32_ff(float r2, float c6, float c12, fl
   return o;
 }
 
+// Tabulated variant (section 3: the paper reads the radial parts of the electrostatic
+// and van der Waals terms from linearly interpolated texture tables).  Node k of a table
+// uniform in r (r = k h, h = R/n, nodes 0..n) holds
+//   E12 = r^-12,  E6 = r^-6,  EC = erfc(beta r)/r,  FC = [erfc(beta r)/r + (2 beta/sqrt(pi)) exp(-beta^2 r^2)]/r^2
+// (node 0 repeats node 1: no pair is that close).  TAB = 1: one float4 per node, linear
+// interpolation; TAB = 2: per node the values and h times their r-derivatives (two float4),
+// cubic Hermite interpolation.  Then u_LJ = c12 E12 - c6 E6, u_C = qq EC and
+// f = (12 c12 E12 - 6 c6 E6)/r^2 + qq FC.
+template <int TAB>
+__device__ __forceinline__ PairF32 pair_f32_tab(float r2, float c6, float c12, float qq,
+                                                const float4 *__restrict__ tab, float inv_h, float last) {
+#pragma clang fp contract(on)
+  PairF32 o;
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  const float rinv2 = rinv * rinv;
+  // lanes without a pair may hold any distance (or NaN at r = 0): the node index is
+  // clamped to the table (fminf returns `last` for NaN) and their terms are discarded
+  const float t = fminf(r2 * rinv * inv_h, last);
+  const int k = static_cast<int>(t);
+  const float u = t - static_cast<float>(k);
+  float4 e;
+  if constexpr (TAB == 1) {
+    const float4 a = tab[k], b = tab[k + 1];
+    e = make_float4(fmaf(u, b.x - a.x, a.x), fmaf(u, b.y - a.y, a.y), fmaf(u, b.z - a.z, a.z),
+                    fmaf(u, b.w - a.w, a.w));
+  } else {
+    const float4 a = tab[2 * k], da = tab[2 * k + 1], b = tab[2 * k + 2], db = tab[2 * k + 3];
+    const float omu = 1.0f - u;
+    const float h00 = fmaf(2.0f, u, 1.0f) * omu * omu, h10 = u * omu * omu;
+    const float h01 = u * u * fmaf(-2.0f, u, 3.0f), h11 = -u * u * omu;
+    e = make_float4(fmaf(h00, a.x, fmaf(h10, da.x, fmaf(h01, b.x, h11 * db.x))),
+                    fmaf(h00, a.y, fmaf(h10, da.y, fmaf(h01, b.y, h11 * db.y))),
+                    fmaf(h00, a.z, fmaf(h10, da.z, fmaf(h01, b.z, h11 * db.z))),
+                    fmaf(h00, a.w, fmaf(h10, da.w, fmaf(h01, b.w, h11 * db.w))));
+  }
+  const float a12 = c12 * e.x, b6 = c6 * e.y;
+  o.u_lj = a12 - b6;
+  o.dudsig_lj = fmaf(12.0f, a12, -6.0f * b6);
+  o.erfc_over_r = e.z;
+  o.u_c = qq * e.z;
+  o.f = fmaf(o.dudsig_lj, rinv2, qq * e.w);
+  return o;
+}
+
 // erfc(x) = exp(-x^2) * g(x) in double precision, with g a polynomial of degree 24 in
 // s = (x - 3)/(x + 3), which maps x in [0, inf) onto [-1, 1): a Chebyshev interpolant
 // of g converted to monomial form (gen_erfc_coeffs.py --f64).  Relative error of g

@@ -85,6 +85,8 @@ class nb_params(ctypes.Structure):
         ("lj_switch_on", ctypes.c_double),
         ("scale14_lj", ctypes.c_double),
         ("scale14_coul", ctypes.c_double),
+        ("table", ctypes.c_int32),
+        ("table_size", ctypes.c_int32),
     ]
 
 
@@ -159,10 +161,11 @@ def _stream(stream=None) -> int:
 def make_params(cutoff: float, beta: float, precision: int = NB_MIXED, coulomb_k: float = COULOMB_K,
                 cell_div_xy: int = 0, cell_div_z: int = 0, kernel: int = NB_KERNEL_AUTO, split: int = 0,
                 cluster_size: int = 0, schedule: int = 0, wg_per_cu: int = 0, lj_switch_on: float = 0.0,
-                scale14_lj: float = 1.0, scale14_coul: float = 1.0) -> nb_params:
+                scale14_lj: float = 1.0, scale14_coul: float = 1.0, table: int = 0,
+                table_size: int = 0) -> nb_params:
     return nb_params(float(cutoff), float(beta), float(coulomb_k), int(precision), int(cell_div_xy),
                      int(cell_div_z), int(kernel), int(split), int(cluster_size), int(schedule), int(wg_per_cu),
-                     float(lj_switch_on), float(scale14_lj), float(scale14_coul))
+                     float(lj_switch_on), float(scale14_lj), float(scale14_coul), int(table), int(table_size))
 
 
 @dataclass
