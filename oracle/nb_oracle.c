@@ -30,6 +30,15 @@
  *     (the CHARMM energy switch of Brooks et al., J. Comput. Chem. 4, 187 (1983)); the
  *     force is -d(S u_LJ)/dr; the Coulomb term is not switched.
  *
+ * Force vector-Jacobian product (force matching): with a vector v_i per atom and
+ * L = sum_i v_i . F_i = sum over ordered pairs of f_ij w_ij, w_ij = v_i . d_ij, the
+ * derivatives of L with respect to the parameters are, per row i (full sums over j),
+ *   dq2[i] = sum_j k_e w_c q_j gC_ij (v_i - v_j) . d_ij        (= dL/dq_i)
+ *   a2[i]  = sum_j (1/2) df_ij/dsigma_ij (v_i - v_j) . d_ij    (sum over t_i = t: dL/dsigma_t)
+ *   b2[i]  = sum_j (1/2) fLJ_ij (v_i - v_j) . d_ij             (sum over t_i = t, / eps_t: dL/deps_t)
+ * with gC the Coulomb force factor per unit k_e q_i q_j and fLJ the LJ force factor (f =
+ * fLJ + fC, F_i = sum_j f_ij d_ij).
+ *
  * The evaluation is "row" based and deliberately plain: for every requested atom
  * i it loops over all N atoms j (an O(N) row, O(N^2) overall), so forces on a
  * subset of atoms (the sampled mode used for million-atom boxes) come from the
@@ -97,16 +106,17 @@ static void lj_switch(double r2, double s_on, double rc2, double *S, double *dS_
   *dS_dr2 = -6.0 * x * (1.0 - x) / (rc2 - s_on);
 }
 
-int nbo_rows_ff(int64_t n, const double *pos, const double *q, const int32_t *type,
-                int32_t ntypes, const double *sigma, const double *eps,
-                const int32_t *excl_off, const int32_t *excl_idx, const double *box,
-                double cutoff, double beta, double ke,
-                const int32_t *p14_off, const int32_t *p14_idx, double s14_lj, double s14_c,
-                double sw_on,
-                int64_t n_rows, const int64_t *rows,
-                double *force, double *energy, double *phi, double *a_sig, double *b_eps,
-                double *virial, double *e_lj_out, double *e_c_out, int64_t *pair_count_out,
-                int nthreads) {
+int nbo_rows_vjp(int64_t n, const double *pos, const double *q, const int32_t *type,
+                 int32_t ntypes, const double *sigma, const double *eps,
+                 const int32_t *excl_off, const int32_t *excl_idx, const double *box,
+                 double cutoff, double beta, double ke,
+                 const int32_t *p14_off, const int32_t *p14_idx, double s14_lj, double s14_c,
+                 double sw_on, const double *vv,
+                 int64_t n_rows, const int64_t *rows,
+                 double *force, double *energy, double *phi, double *a_sig, double *b_eps,
+                 double *dq2, double *a2, double *b2,
+                 double *virial, double *e_lj_out, double *e_c_out, int64_t *pair_count_out,
+                 int nthreads) {
   if (n < 0 || ntypes <= 0 || cutoff <= 0.0 || beta < 0.0) return -1;
   if (sw_on < 0.0 || sw_on >= cutoff) return -1;
   for (int a = 0; a < 3; ++a)
@@ -149,7 +159,7 @@ int nbo_rows_ff(int64_t n, const double *pos, const double *q, const int32_t *ty
       if (p_off)
         for (int64_t k = p_off[i]; k < p_off[i + 1]; ++k) stamp14[p_idx[k]] = i + 1;
       double f[3] = {0, 0, 0};
-      double ei = 0.0, ph = 0.0, as = 0.0, be = 0.0;
+      double ei = 0.0, ph = 0.0, as = 0.0, be = 0.0, cq2 = 0.0, ca2 = 0.0, cb2 = 0.0;
       for (int64_t j = 0; j < n; ++j) {
         if (j == i || stamp[j] == i + 1) continue;
         double d[3];
@@ -183,6 +193,21 @@ int nbo_rows_ff(int64_t n, const double *pos, const double *q, const int32_t *ty
         const double f_c = w_c * ke * q[i] * q[j] *
                            (erfc_br / (r2 * r) + beta * two_over_sqrt_pi * exp(-beta * beta * r2) / r2);
         const double fs = f_lj + f_c;
+        if (vv) {
+          /* (v_i - v_j) . d_ij, and the parameter derivatives of this pair's force factor:
+             f_LJ = w [S dd0/r^2 - 2 u0 dS/d(r^2)] with dd0 = 24 eps (2 s^12 - s^6); both
+             terms scale as eps_ij, and d/dsigma_ij of dd0 is 24 eps (24 s^12 - 6 s^6)/sigma
+             (of u0: dd0 / sigma) */
+          double wv = 0.0;
+          for (int a = 0; a < 3; ++a) wv += (vv[3 * i + a] - vv[3 * j + a]) * d[a];
+          const double dd0_ds = sij > 0.0 ? 24.0 * eij * (24.0 * s12 - 6.0 * s6) / sij : 0.0;
+          const double du0_ds = sij > 0.0 ? 4.0 * eij * (12.0 * s12 - 6.0 * s6) / sij : 0.0;
+          const double dflj_ds = w_lj * (S * dd0_ds / r2 - 2.0 * du0_ds * dS_dr2);
+          const double gc = w_c * (erfc_br / (r2 * r) + beta * two_over_sqrt_pi * exp(-beta * beta * r2) / r2);
+          cq2 += ke * q[j] * gc * wv;
+          ca2 += 0.5 * dflj_ds * wv;
+          cb2 += 0.5 * f_lj * wv;
+        }
         for (int a = 0; a < 3; ++a) f[a] += fs * d[a];
         for (int a = 0; a < 3; ++a)
           for (int b = 0; b < 3; ++b) vir[3 * a + b] += 0.5 * d[a] * fs * d[b];
@@ -199,6 +224,9 @@ int nbo_rows_ff(int64_t n, const double *pos, const double *q, const int32_t *ty
       if (phi) phi[r] = ph;
       if (a_sig) a_sig[r] = as;
       if (b_eps) b_eps[r] = be;
+      if (dq2) dq2[r] = cq2;
+      if (a2) a2[r] = ca2;
+      if (b2) b2[r] = cb2;
     }
     free(stamp);
     free(stamp14);
@@ -213,6 +241,21 @@ int nbo_rows_ff(int64_t n, const double *pos, const double *q, const int32_t *ty
   free(p_off);
   free(p_idx);
   return 0;
+}
+
+int nbo_rows_ff(int64_t n, const double *pos, const double *q, const int32_t *type,
+                int32_t ntypes, const double *sigma, const double *eps,
+                const int32_t *excl_off, const int32_t *excl_idx, const double *box,
+                double cutoff, double beta, double ke,
+                const int32_t *p14_off, const int32_t *p14_idx, double s14_lj, double s14_c,
+                double sw_on,
+                int64_t n_rows, const int64_t *rows,
+                double *force, double *energy, double *phi, double *a_sig, double *b_eps,
+                double *virial, double *e_lj_out, double *e_c_out, int64_t *pair_count_out,
+                int nthreads) {
+  return nbo_rows_vjp(n, pos, q, type, ntypes, sigma, eps, excl_off, excl_idx, box, cutoff, beta, ke, p14_off,
+                      p14_idx, s14_lj, s14_c, sw_on, NULL, n_rows, rows, force, energy, phi, a_sig, b_eps, NULL,
+                      NULL, NULL, virial, e_lj_out, e_c_out, pair_count_out, nthreads);
 }
 
 /* The plain interaction: no 1-4 list, no switch. */

@@ -62,6 +62,10 @@ def _load():
         lib.nbo_ewald_corrections.argtypes = [ctypes.c_int64, P, P, P, P, P, ctypes.c_double,
                                               ctypes.c_double, P, P, P, P, P]
         D = ctypes.c_double
+        lib.nbo_rows_vjp.restype = ctypes.c_int
+        lib.nbo_rows_vjp.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int32, P, P, P, P, P, D, D, D,
+                                     P, P, D, D, D, P,
+                                     ctypes.c_int64, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
         lib.nbo_rows_ff.restype = ctypes.c_int
         lib.nbo_rows_ff.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int32, P, P, P, P, P, D, D, D,
                                     P, P, D, D, D,
@@ -86,7 +90,7 @@ def _csr(off, idx):
 def evaluate(pos, charge, types, sigma, eps, excl_offset, excl_index, box, cutoff, beta,
              ke: float = COULOMB_K, rows: Optional[np.ndarray] = None, nthreads: int = 0,
              pair14_offset=None, pair14_index=None, scale14_lj: float = 1.0, scale14_coul: float = 1.0,
-             lj_switch_on: float = 0.0) -> dict:
+             lj_switch_on: float = 0.0, vjp=None) -> dict:
     """Evaluate the brute-force sums for every atom (rows=None) or for the atoms in ``rows``.
 
     Inputs are promoted to float64; pass exactly the values the device computes with.
@@ -97,6 +101,10 @@ def evaluate(pos, charge, types, sigma, eps, excl_offset, excl_index, box, cutof
     Force-field options: pairs in the 1-4 lists (CSR, union of both rows, not excluded)
     have their LJ term scaled by scale14_lj and their Coulomb term by scale14_coul; with
     lj_switch_on = r_on > 0 the LJ term is switched off between r_on and the cutoff.
+
+    vjp: a vector v [N,3]; then also the derivatives of L = sum_i v_i . F_i with respect to
+    the parameters (force matching): vjp_charge [m] per row, and with rows=None
+    vjp_sigma [T] and vjp_eps [T] (0 for eps_t = 0).
     """
     lib = _load()
     pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
@@ -122,12 +130,17 @@ def evaluate(pos, charge, types, sigma, eps, excl_offset, excl_index, box, cutof
     e_c = ctypes.c_double()
     npairs = ctypes.c_int64()
     po, pi = _csr(pair14_offset, pair14_index) if pair14_offset is not None else (None, None)
-    rc = lib.nbo_rows_ff(n, _ptr(pos), _ptr(q), _ptr(t), int(sig.shape[0]), _ptr(sig), _ptr(ep),
-                         _ptr(eo), _ptr(ei), _ptr(bx), float(cutoff), float(beta), float(ke),
-                         _ptr(po), _ptr(pi), float(scale14_lj), float(scale14_coul), float(lj_switch_on),
-                         m, _ptr(r), _ptr(force), _ptr(energy), _ptr(phi), _ptr(a_sig), _ptr(b_eps),
-                         _ptr(vir), ctypes.byref(e_lj), ctypes.byref(e_c), ctypes.byref(npairs),
-                         int(nthreads))
+    vv = None if vjp is None else np.ascontiguousarray(vjp, np.float64).reshape(n, 3)
+    dq2 = np.zeros(m) if vv is not None else None
+    a2 = np.zeros(m) if vv is not None else None
+    b2 = np.zeros(m) if vv is not None else None
+    rc = lib.nbo_rows_vjp(n, _ptr(pos), _ptr(q), _ptr(t), int(sig.shape[0]), _ptr(sig), _ptr(ep),
+                          _ptr(eo), _ptr(ei), _ptr(bx), float(cutoff), float(beta), float(ke),
+                          _ptr(po), _ptr(pi), float(scale14_lj), float(scale14_coul), float(lj_switch_on),
+                          _ptr(vv), m, _ptr(r), _ptr(force), _ptr(energy), _ptr(phi), _ptr(a_sig), _ptr(b_eps),
+                          _ptr(dq2), _ptr(a2), _ptr(b2),
+                          _ptr(vir), ctypes.byref(e_lj), ctypes.byref(e_c), ctypes.byref(npairs),
+                          int(nthreads))
     if rc != 0:
         raise ValueError(f"oracle rejected the input (code {rc})")
     out = dict(force=force, energy=energy, phi=phi, a_sig=a_sig, b_eps=b_eps,
@@ -141,6 +154,15 @@ def evaluate(pos, charge, types, sigma, eps, excl_offset, excl_index, box, cutof
         np.add.at(bsum, t, b_eps)
         deps = np.where(ep > 0, bsum / np.where(ep > 0, ep, 1.0), 0.0)
         out.update(dsigma=dsig, deps=deps)
+    if vv is not None:
+        out["vjp_charge"] = dq2
+        if r is None:
+            T = sig.shape[0]
+            vs = np.zeros(T)
+            vb = np.zeros(T)
+            np.add.at(vs, t, a2)
+            np.add.at(vb, t, b2)
+            out.update(vjp_sigma=vs, vjp_eps=np.where(ep > 0, vb / np.where(ep > 0, ep, 1.0), 0.0))
     return out
 
 
