@@ -193,6 +193,20 @@ nb_status nb_nonbonded_backward(const nb_system *sys, const nb_params *params, v
                                 double *grad_charge, double *grad_sigma, double *grad_eps,
                                 hipStream_t stream);
 
+/* Vector-Jacobian product of the forces (the double backward of force matching): with
+ * v [device, N*3 doubles, caller's order] and L = sum_b sum_{i in b} v_i . F_i,
+ *   grad_charge[i] = dL/dq_i       [device, N doubles or NULL]
+ *   grad_sigma[t]  = dL/dsigma_t   [device, n_types or NULL]
+ *   grad_eps[t]    = dL/deps_t     [device, n_types or NULL; 0 where eps_t = 0]
+ * for the same interaction as nb_nonbonded_forces (switch and 1-4 scaling included;
+ * direct evaluation whatever nb_params.table says).  Per pair this is the parameter
+ * derivative of the force factor times (v_i - v_j) . d_ij, summed in double precision.
+ * Requires nb_build_cells on this workspace and a cluster kernel (NB_KERNEL_ATOM is
+ * refused).  Outputs are overwritten. */
+nb_status nb_nonbonded_force_vjp(const nb_system *sys, const nb_params *params, void *workspace,
+                                 size_t workspace_bytes, const double *v, double *grad_charge,
+                                 double *grad_sigma, double *grad_eps, hipStream_t stream);
+
 /* Ewald corrections that complete the real-space term of the forces above (section 3:
  * the electrostatics are PME, whose reciprocal part counts every pair, excluded ones
  * included, and every charge with itself):

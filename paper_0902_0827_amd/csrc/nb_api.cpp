@@ -196,6 +196,7 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   l.jacc = p.kernel == NB_KERNEL_CLUSTER_HALF ? take(32 * static_cast<size_t>(N)) : 0;
   l.p14_mask = p.has14 ? take(16 * static_cast<size_t>(N)) : 0;
   l.rtab = p.table ? take(16 * static_cast<size_t>(p.table_n + 1) * static_cast<size_t>(p.table)) : 0;
+  l.vsort = take(32 * static_cast<size_t>(N));
   l.total = o;
   *plan = std::move(p);
   return NB_OK;
@@ -238,6 +239,7 @@ Dev dev_view(const Plan &p, void *ws) {
   d.queue = reinterpret_cast<uint32_t *>(base + l.queue);
   d.p14_mask = p.has14 ? reinterpret_cast<uint4 *>(base + l.p14_mask) : nullptr;
   d.rtab = p.table ? reinterpret_cast<float4 *>(base + l.rtab) : nullptr;
+  d.vsort = reinterpret_cast<double4 *>(base + l.vsort);
   const bool half = p.kernel == NB_KERNEL_CLUSTER_HALF;
   d.jacc_fix = half && p.precision == NB_MIXED ? reinterpret_cast<long long *>(base + l.jacc) : nullptr;
   d.jacc_f64 = half && p.precision == NB_FP64 ? reinterpret_cast<double *>(base + l.jacc) : nullptr;
@@ -375,6 +377,22 @@ nb_status nb_nonbonded_backward(const nb_system *sys, const nb_params *params, v
     return hip_status(nb::launch_backward(p, nb::dev_view(p, workspace), sys, grad_energy, grad_pos,
                                           grad_charge, grad_sigma, grad_eps, stream),
                       "nb_nonbonded_backward");
+  });
+}
+
+nb_status nb_nonbonded_force_vjp(const nb_system *sys, const nb_params *params, void *workspace,
+                                 size_t workspace_bytes, const double *v, double *grad_charge,
+                                 double *grad_sigma, double *grad_eps, hipStream_t stream) {
+  return guarded("nb_nonbonded_force_vjp", [&]() -> nb_status {
+    nb::Plan p;
+    nb_status st = nb::make_plan(sys, params, &p);
+    if (st != NB_OK) return st;
+    if ((st = check_ws(p, workspace, workspace_bytes)) != NB_OK) return st;
+    if (!v && p.N > 0) return fail(NB_ERR_ARG, "v must not be NULL");
+    if (!nb::uses_clusters(p.kernel)) return fail(NB_ERR_ARG, "the force VJP needs a cluster kernel");
+    return hip_status(nb::launch_force_vjp(p, nb::dev_view(p, workspace), sys, v, grad_charge, grad_sigma,
+                                           grad_eps, stream),
+                      "nb_nonbonded_force_vjp");
   });
 }
 

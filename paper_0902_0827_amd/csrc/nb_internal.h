@@ -66,7 +66,7 @@ struct alignas(16) TypePair32 { float c6, c12, inv_sig, pad; };
 struct Layout {
   size_t status, desc, tab64, tab32, cell_count, cell_start, atom_cell, atom_slot, atom_fix, tmp, s_range, scan_tiles;
   size_t s_fix, s_pos64, s_q32, s_type, excl_mask, excl_far, partials, adj_partials;
-  size_t col_clu_start, part, queue, jacc, p14_mask, rtab;
+  size_t col_clu_start, part, queue, jacc, p14_mask, rtab, vsort;
   size_t total;
 };
 
@@ -115,6 +115,7 @@ struct Dev {
   uint4 *excl_mask;  // original order: 128-bit exclusion window
   uint4 *p14_mask;   // original order: 128-bit window of the scaled 1-4 partners (null without 1-4 lists)
   float4 *rtab;      // radial tables of the tabulated variant (null for direct evaluation)
+  double4 *vsort;    // force VJP: the caller's vector v in sorted order (mixed path: times L/2^32)
   uint32_t *excl_far;// original order: nonzero if the atom has an exclusion beyond the window
   double *partials;      // [kPart][n_slots]: per-block (or per-wave) energy and virial sums
   double *adj_partials;  // [2 T][n_slots]: per-block (or per-wave) sigma / eps sums by type
@@ -138,7 +139,9 @@ struct Dev {
 };
 
 // Per-call constants and outputs of the pair kernels.
-enum PairMode : int { kForces = 0, kEnergy = 1, kAdjoint = 2 };
+// kVJP: the vector-Jacobian product of the forces with respect to charges, sigma_t and
+// eps_t (the force-matching gradient).
+enum PairMode : int { kForces = 0, kEnergy = 1, kAdjoint = 2, kVJP = 3 };
 
 struct Consts {
   double rc2, beta, two_beta_sqrtpi, ke, sqrt_ke;
@@ -158,6 +161,7 @@ struct Out {
   double *grad_pos;
   double *grad_charge;
   const double *grad_energy;
+  const double *vjp_v;    // force VJP: v [N*3], caller's order
   const int32_t *excl_off;
   const int32_t *excl_idx;
   int want_part;    // write energy (and, for forces, virial) partials
@@ -196,6 +200,8 @@ hipError_t launch_energy(const Plan &plan, const Dev &d, const nb_system *sys, d
 hipError_t launch_backward(const Plan &plan, const Dev &d, const nb_system *sys,
                            const double *grad_energy, double *grad_pos, double *grad_charge,
                            double *grad_sigma, double *grad_eps, hipStream_t s);
+hipError_t launch_force_vjp(const Plan &plan, const Dev &d, const nb_system *sys, const double *v,
+                            double *grad_charge, double *grad_sigma, double *grad_eps, hipStream_t s);
 // Build and forces on the library's own scratch array (nb_noalloc.hip); `why` receives
 // the message of a non-OK return.
 nb_status noalloc_forces(const Plan &p, const nb_system *sys, double *force, double *energy, double *virial,

@@ -361,7 +361,32 @@ void launch_pair(const Plan &p, const Dev &d, const Out &o, hipStream_t s) {
   timer_after(s);
 }
 
+// The force VJP's vector in sorted order: vsort[s] = v[o] for the atom o at sorted
+// position s; on the mixed path each component times the system's fixed-point unit L/2^32,
+// so that its product with a fixed-point displacement is in Angstrom.
+__global__ void __launch_bounds__(kBlock) k_vjp_prep(Dev d, const double *__restrict__ v, int f64) {
+  const int64_t s = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x;
+  if (s >= d.N || !built_for(d.status, d.N, false, false)) return;
+  const int o = static_cast<int>(d.s_fix[s].w);
+  const SysDesc &sd = d.desc[d.atom_fix[o].w];
+  const double sx = f64 ? 1.0 : sd.scale[0], sy = f64 ? 1.0 : sd.scale[1], sz = f64 ? 1.0 : sd.scale[2];
+  d.vsort[s] = make_double4(v[3 * static_cast<int64_t>(o)] * sx, v[3 * static_cast<int64_t>(o) + 1] * sy,
+                            v[3 * static_cast<int64_t>(o) + 2] * sz, 0.0);
+}
+
 }  // namespace
+
+hipError_t launch_force_vjp(const Plan &p, const Dev &d, const nb_system *sys, const double *v,
+                            double *grad_charge, double *grad_sigma, double *grad_eps, hipStream_t s) {
+  Out o = base_out(sys);
+  o.grad_charge = grad_charge;
+  o.vjp_v = v;
+  if (p.N > 0)
+    hipLaunchKernelGGL(k_vjp_prep, dim3(static_cast<unsigned>((p.N + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d, v,
+                       p.precision == NB_FP64 ? 1 : 0);
+  launch_cluster_pair(p, d, make_consts(p), o, kVJP, s, nullptr, nullptr, sys->lj_eps, grad_sigma, grad_eps);
+  return hipGetLastError();
+}
 
 hipError_t launch_forces(const Plan &p, const Dev &d, const nb_system *sys, double *force, double *energy,
                          double *virial, hipStream_t s) {

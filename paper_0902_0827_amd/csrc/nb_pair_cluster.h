@@ -273,7 +273,7 @@ using TypePairT = std::conditional_t<F64, TypePair64, TypePair32>;
 struct TypePairF64Adj { double c6, c12, inv_sig; };
 template <bool F64, int MODE>
 using TypePairLds = std::conditional_t<!F64, TypePairT<F64>,
-                                       std::conditional_t<MODE == kAdjoint, TypePairF64Adj, double2>>;
+                                       std::conditional_t<MODE == kAdjoint || MODE == kVJP, TypePairF64Adj, double2>>;
 
 template <bool F64, int MODE>
 constexpr size_t tab_lds_bytes(int T) {
@@ -362,6 +362,11 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   extern __shared__ uint4 tab_lds[];  // [T * T] type pairs when TABLDS, then the stage when HALF
   constexpr bool FF = VAR == kVarFF;
   constexpr int TAB = VAR == kVarLin ? 1 : VAR == kVarCub ? 2 : 0;
+  // the adjoint and the force VJP share the per-atom dE/dq-like row sum and the per-type sums
+  constexpr bool ADJ = MODE == kAdjoint || MODE == kVJP;
+  static_assert(!(HALF && ADJ), "the adjoint and the force VJP are full-shell");
+  // force VJP: each staged candidate's v_j (sorted copy), beside the ring
+  __shared__ std::conditional_t<MODE == kVJP, std::conditional_t<F64, double4, float4>, int> VJ[MODE == kVJP ? kRing : 1];
   static_assert(TAB == 0 || (!F64 && MODE != kAdjoint), "tables: mixed forces and energies only");
   __shared__ WaveLds<F64, FF> L;
   TypePairLds<F64, MODE> *const TL = reinterpret_cast<TypePairLds<F64, MODE> *>(tab_lds);
@@ -391,7 +396,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   }
   if constexpr (TABLDS) {
     for (int k = lane; k < T * T; k += 64) {
-      if constexpr (F64 && MODE != kAdjoint) TL[k] = make_double2(d.tab64[k].c6, d.tab64[k].c12);
+      if constexpr (F64 && !ADJ) TL[k] = make_double2(d.tab64[k].c6, d.tab64[k].c12);
       else if constexpr (F64) TL[k] = TypePairF64Adj{d.tab64[k].c6, d.tab64[k].c12, d.tab64[k].inv_sig};
       else TL[k] = d.tab32[k];
     }
@@ -496,6 +501,13 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     if constexpr (F64) pi64 = d.s_pos64[ia];
     else qi32 = d.s_q32[ia];
     const double qi64 = F64 ? pi64.w * c.ke : 0.0;
+    // force VJP: the row atom's v (sorted copy; mixed path in fixed-point units)
+    double4 vi64 = make_double4(0, 0, 0, 0);
+    float4 vi32 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (MODE == kVJP) {
+      vi64 = d.vsort[ia];
+      vi32 = make_float4(static_cast<float>(vi64.x), static_cast<float>(vi64.y), static_cast<float>(vi64.z), 0.f);
+    }
 
     // Bounding box of the cluster, relative to its first atom (minimum image).
     uint4 ctr, half;
@@ -712,7 +724,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       }
       // type pair of (ti, tj), read with the window for every lane
       TypePairT<F64> tp;
-      if constexpr (TABLDS && F64 && MODE != kAdjoint) {
+      if constexpr (TABLDS && F64 && !ADJ) {
         const double2 e = TL[ti * T + tj];
         tp.c6 = e.x;
         tp.c12 = e.y;
@@ -777,7 +789,28 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       std::conditional_t<F64, double, float> hgx = 0, hgy = 0, hgz = 0, hu = 0;
       // Every lane evaluates its pair and a lane without one adds zeros (its terms, possibly
       // not finite, are selected away), so the group runs without a branch.
-      {
+      if constexpr (MODE == kVJP) {
+        // force VJP: (v_i - v_j) . d_ij times the parameter derivatives of the force factor
+        if constexpr (F64) {
+          const double4 vjv = VJ[slot];
+          const double wv = (vi64.x - vjv.x) * dxd + (vi64.y - vjv.y) * dyd + (vi64.z - vjv.z) * dzd;
+          const PairVjpF64 p = pair_vjp_f64(r2d, tp.c6, tp.c12, wljd, wcd, c.beta, c.two_beta_sqrtpi,
+                                            c.erfc_short != 0, c.sw_on2, c.sw_inv);
+          const double tq = pj64.w * p.gc * wv, ts = p.dflj * tp.inv_sig * wv, te = p.flj * wv;
+          phi += hit ? tq : 0.0;
+          asig += hit ? ts : 0.0;
+          beps += hit ? te : 0.0;
+        } else {
+          const float4 vjv = VJ[slot];
+          const float wv = fmaf(vi32.z - vjv.z, dzf, fmaf(vi32.y - vjv.y, dyf, (vi32.x - vjv.x) * dxf));
+          const PairVjpF32 p = pair_vjp_f32(r2f, tp.c6, tp.c12, wljf, wcf, c.betaf, c.two_beta_sqrtpif, c.mb2l2e,
+                                            c.sw_on2f, c.sw_invf);
+          const float tq = qj * p.gc * wv, ts = p.dflj * tp.inv_sig * wv, te = p.flj * wv;
+          phi += static_cast<double>(hit ? tq : 0.f);
+          asig += static_cast<double>(hit ? ts : 0.f);
+          beps += static_cast<double>(hit ? te : 0.f);
+        }
+      } else {
         if constexpr (F64) {
           PairF64 p = FF ? pair_f64_ff(r2d, tp.c6, tp.c12, qi64 * pj64.w * wcd, wljd, c.beta, c.two_beta_sqrtpi,
                                        c.erfc_short != 0, c.sw_on2, c.sw_inv)
@@ -922,7 +955,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     // run0 .. run0 + 3 are read at once (wave-uniform addresses) and each lane picks
     // its run by comparisons; the rare lane beyond them walks on.  The next chunk
     // starts in the run of this chunk's last lane or a later one.
-    auto load = [&](int P, uint4 &f, int &t, float &q, double4 &p, bool &v, int &sidx) {
+    auto load = [&](int P, uint4 &f, int &t, float &q, double4 &p, bool &v, int &sidx, double4 &vv) {
       while (L.runs[run0 + 1].y <= P) ++run0;
       const int2 ra = L.runs[run0], rb = L.runs[run0 + 1], rc = L.runs[run0 + 2], rd = L.runs[run0 + 3];
       const int pos = P + lane;
@@ -942,6 +975,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       t = d.s_type[aa];
       if constexpr (F64) p = d.s_pos64[aa];
       else q = d.s_q32[aa];
+      if constexpr (MODE == kVJP) vv = d.vsort[aa];
     };
     uint4 fj = make_uint4(0u, 0u, 0u, 0u);
     int tj = 0;
@@ -949,9 +983,10 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     double4 pj64 = make_double4(0, 0, 0, 0);
     bool valid = false;
     int sj = 0;
+    double4 vj = make_double4(0, 0, 0, 0);  // force VJP: the candidate's v (sorted copy)
     wait_vm_loads();  // the cluster's own data has arrived before the pair loop starts
     int P = lo_c;
-    if (P < hi_c) load(P, fj, tj, qj, pj64, valid, sj);
+    if (P < hi_c) load(P, fj, tj, qj, pj64, valid, sj, vj);
     bool requested = false;
     while (P < hi_c) {
       const int Pn = P + 64;
@@ -961,8 +996,9 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       double4 pj64_n = pj64;
       bool valid_n = false;
       int sj_n = sj;
+      double4 vj_n = vj;
       if (Pn < hi_c) {
-        load(Pn, fj_n, tj_n, qj_n, pj64_n, valid_n, sj_n);
+        load(Pn, fj_n, tj_n, qj_n, pj64_n, valid_n, sj_n, vj_n);
       } else if (dynamic && !(closed & (1u << home))) {
         // the next item, requested after this item's last loads (vector-memory waits
         // complete in issue order, so an earlier request would hold up the chunks)
@@ -987,6 +1023,10 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
           L.ring[slot].qt = make_float2(qj, __int_as_float(tj));
           if constexpr (HALF) L.ring[slot].sidx = make_int2(sj, 0);
         }
+        if constexpr (MODE == kVJP) {
+          if constexpr (F64) VJ[slot] = vj;
+          else VJ[slot] = make_float4(static_cast<float>(vj.x), static_cast<float>(vj.y), static_cast<float>(vj.z), 0.f);
+        }
       }
       wave_lds_sync();
       tail += static_cast<uint32_t>(__popcll(mk));
@@ -999,6 +1039,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       pj64 = pj64_n;
       valid = valid_n;
       sj = sj_n;
+      vj = vj_n;
     }
     if (tail != head) {
       if (any_far) process_group(static_cast<int>(tail - head), std::true_type{}, std::true_type{});
@@ -1013,9 +1054,9 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     // few of them are live in double at a time.
     const double phi_scale = F64 ? c.ke : c.sqrt_ke;
 
-    if constexpr (MODE == kAdjoint) {
+    if constexpr (ADJ) {
       // Per-type sums of the sigma / eps partials over this item's rows (scaled by the
-      // system's grad_energy in k_finish).
+      // system's grad_energy in k_finish for the adjoint).
       const double a_l = 0.5 * asig, b_l = 0.5 * beps;
       const int my_t = ivalid ? ti : -1;
       double keep_a = 0.0, keep_b = 0.0;
@@ -1062,9 +1103,9 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         }
       }
     } else {
-      const double rowv[4] = {fx, fy, fz, MODE == kAdjoint ? phi : en};
+      const double rowv[4] = {fx, fy, fz, ADJ ? phi : en};
       const int ent = jj / (J / 4);
-      const double sce = ent == 0 ? scx : ent == 1 ? scy : ent == 2 ? scz : (MODE == kAdjoint ? phi_scale : 1.0);
+      const double sce = ent == 0 ? scx : ent == 1 ? scy : ent == 2 ? scz : (ADJ ? phi_scale : 1.0);
       const double rv = reduce_scatter<J, 4>(rowv, lane) * sce;
       const bool writer = ivalid && jj % (J / 4) == 0;
       if (writer) {
@@ -1073,6 +1114,8 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
             if (ent < 3) o.force[3 * static_cast<int64_t>(oi) + ent] = rv;
           } else if constexpr (MODE == kEnergy) {
             if (ent == 3 && o.atom_energy) o.atom_energy[oi] = 0.5 * rv;
+          } else if constexpr (MODE == kVJP) {
+            if (ent == 3 && o.grad_charge) o.grad_charge[oi] = rv;
           } else {
             const double g = o.grad_energy[sys];
             if (ent < 3 && o.grad_pos) o.grad_pos[3 * static_cast<int64_t>(oi) + ent] = -g * rv;
@@ -1203,6 +1246,8 @@ __global__ void __launch_bounds__(kFinishBlock) k_finish(Dev d, Out o, int S, in
       o.force[3 * oi + 2] = s.z;
     } else if constexpr (MODE == kEnergy) {
       if (o.atom_energy) o.atom_energy[oi] = 0.5 * s.w;
+    } else if constexpr (MODE == kVJP) {
+      if (o.grad_charge) o.grad_charge[oi] = s.w;
     } else {
       int lo = 0, hi = d.B - 1;
       while (lo < hi) {
@@ -1221,7 +1266,7 @@ __global__ void __launch_bounds__(kFinishBlock) k_finish(Dev d, Out o, int S, in
   }
   if (blk < nA + kPart * d.B) {
     const int b = (blk - nA) / kPart, k = (blk - nA) % kPart;
-    if (MODE == kAdjoint || k >= nv) return;
+    if (MODE == kAdjoint || MODE == kVJP || k >= nv) return;
     const SysDesc &sd = d.desc[b];
     const int64_t lo = static_cast<int64_t>(d.col_clu_start[sd.col_begin]) * S;
     const int64_t hi = static_cast<int64_t>(d.col_clu_start[sd.col_begin + sd.dims[0] * sd.dims[1]]) * S;
@@ -1235,9 +1280,9 @@ __global__ void __launch_bounds__(kFinishBlock) k_finish(Dev d, Out o, int S, in
     }
     return;
   }
-  if constexpr (MODE == kAdjoint) {
-    // One (sigma or eps, type) entry: sum over every wave slot of every system,
-    // each scaled by its system's grad_energy.
+  if constexpr (MODE == kAdjoint || MODE == kVJP) {
+    // One (sigma or eps, type) entry: sum over every wave slot of every system, each
+    // scaled by its system's grad_energy for the adjoint (the force VJP has no such weight).
     const int T = d.T;
     const int t = blk - nA - kPart * d.B;
     if (t >= 2 * T) return;
@@ -1257,7 +1302,7 @@ __global__ void __launch_bounds__(kFinishBlock) k_finish(Dev d, Out o, int S, in
 #pragma unroll
         for (int u = 0; u < 4; ++u) s += q0 + u * kFinishBlock < hi ? v[u] : 0.0;
       }
-      acc += o.grad_energy[b] * s;
+      acc += MODE == kVJP ? s : o.grad_energy[b] * s;
     }
     acc = wave_sum(acc);
     if (lane == 0) lds[wave][0] = acc;
@@ -1331,6 +1376,7 @@ void launch_cluster_mode(int mode, bool half, int var, int64_t wgs, int dyn, int
     using M0 = std::integral_constant<int, kForces>;
     using M1 = std::integral_constant<int, kEnergy>;
     using M2 = std::integral_constant<int, kAdjoint>;
+    using M3 = std::integral_constant<int, kVJP>;
     if (mode == kForces) {
       if (half) go(k_pair_cluster<F64, kForces, TABLDS, K, true, false, VAR>, M0{}, std::true_type{});
       else if (pairs2) go(k_pair_cluster<F64, kForces, TABLDS, K, false, !F64, VAR>, M0{}, std::false_type{});
@@ -1340,9 +1386,15 @@ void launch_cluster_mode(int mode, bool half, int var, int64_t wgs, int dyn, int
       else if (pairs2) go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, !F64, VAR>, M1{}, std::false_type{});
       else go(k_pair_cluster<F64, kEnergy, TABLDS, K, false, false, VAR>, M1{}, std::false_type{});
     } else {
-      constexpr int VA = VAR == kVarFF ? kVarFF : kVarPlain;  // the adjoint evaluates directly
-      if (pairs2) go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, !F64, VA>, M2{}, std::false_type{});
-      else go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, false, VA>, M2{}, std::false_type{});
+      // the adjoint and the force VJP evaluate directly (never from tables), full shell
+      constexpr int VA = VAR == kVarFF ? kVarFF : kVarPlain;
+      if (mode == kAdjoint) {
+        if (pairs2) go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, !F64, VA>, M2{}, std::false_type{});
+        else go(k_pair_cluster<F64, kAdjoint, TABLDS, K, false, false, VA>, M2{}, std::false_type{});
+      } else {
+        if (pairs2) go(k_pair_cluster<F64, kVJP, TABLDS, K, false, !F64, VA>, M3{}, std::false_type{});
+        else go(k_pair_cluster<F64, kVJP, TABLDS, K, false, false, VA>, M3{}, std::false_type{});
+      }
     }
   };
   if (var == kVarFF) dispatch(std::integral_constant<int, kVarFF>{});

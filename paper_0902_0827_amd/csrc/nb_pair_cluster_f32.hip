@@ -9,7 +9,8 @@ void launch_cluster_pair_f64(const Plan &p, const Dev &d, const Consts &c, const
 
 void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out &o, int mode, hipStream_t s,
                          double *energy, double *virial, const double *eps, double *grad_sigma, double *grad_eps) {
-  const bool half = p.kernel == NB_KERNEL_CLUSTER_HALF && mode != kAdjoint;  // the adjoint stays full-shell
+  // the adjoint and the force VJP stay full-shell
+  const bool half = p.kernel == NB_KERNEL_CLUSTER_HALF && mode != kAdjoint && mode != kVJP;
   if (p.precision == NB_FP64) launch_cluster_pair_f64(p, d, c, o, mode, half, s);
   else launch_cluster_pair_prec<false>(p, d, c, o, mode, half, s);
   // With one item per cluster the full-shell kernel has written the per-atom outputs
@@ -19,7 +20,7 @@ void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out
   int nv = 0;
   if (mode == kForces) nv = o.want_part ? (virial ? kPart : 1) : 0;
   if (mode == kEnergy) nv = 1;
-  const int extra = mode == kAdjoint ? ((grad_sigma || grad_eps) ? 2 * p.T : 0) : 0;
+  const int extra = (mode == kAdjoint || mode == kVJP) ? ((grad_sigma || grad_eps) ? 2 * p.T : 0) : 0;
   const dim3 fg(static_cast<unsigned>(nA + kPart * p.B + extra));
   if (mode == kForces)
     hipLaunchKernelGGL(k_finish<kForces>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
@@ -27,6 +28,9 @@ void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out
   else if (mode == kEnergy)
     hipLaunchKernelGGL(k_finish<kEnergy>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
                        grad_sigma, grad_eps, half ? 1 : 0);
+  else if (mode == kVJP)
+    hipLaunchKernelGGL(k_finish<kVJP>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
+                       grad_sigma, grad_eps, 0);
   else
     hipLaunchKernelGGL(k_finish<kAdjoint>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
                        grad_sigma, grad_eps, 0);

@@ -108,6 +108,39 @@ __device__ __forceinline__ PairF32 pair_f32_ff(float r2, float c6, float c12, fl
   return o;
 }
 
+// Parameter derivatives of the force factor, for the force VJP: the LJ force factor
+// f_LJ = w [S d0 + 12 x (1 - x) r^2 sw_inv u0] / r^2 (as pair_f32_ff; S = 1 without a
+// switch), sigma_ij df_LJ/dsigma_ij = w [S dd + 12 x (1 - x) r^2 sw_inv d0] / r^2 with
+// dd = 144 a - 36 b (sigma d/dsigma takes u0 to d0 and d0 to dd), and the Coulomb force
+// factor per unit qq, w_c [erfc(beta r)/r + (2 beta/sqrt(pi)) exp(-beta^2 r^2)] / r^2.
+struct PairVjpF32 { float flj, dflj, gc; };
+struct PairVjpF64 { double flj, dflj, gc; };
+
+__device__ __forceinline__ PairVjpF32 pair_vjp_f32(float r2, float c6, float c12, float w_lj, float w_c, float beta,
+                                                   float two_beta_sqrtpi, float mb2l2e, float sw_on2, float sw_inv) {
+#pragma clang fp contract(on)
+  PairVjpF32 o;
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  const float rinv2 = rinv * rinv;
+  const float rinv6 = rinv2 * rinv2 * rinv2;
+  const float a = c12 * rinv6 * rinv6;
+  const float b = c6 * rinv6;
+  const float u0 = a - b;
+  const float d0 = fmaf(12.0f, a, -6.0f * b);
+  const float dd = fmaf(144.0f, a, -36.0f * b);
+  const float x = fmaxf((r2 - sw_on2) * sw_inv, 0.0f);
+  const float omx = 1.0f - x;
+  const float sw = omx * omx * fmaf(2.0f, x, 1.0f);
+  const float qs = (12.0f * x * omx) * (r2 * sw_inv);
+  o.flj = w_lj * fmaf(qs, u0, sw * d0) * rinv2;
+  o.dflj = w_lj * fmaf(qs, d0, sw * dd) * rinv2;
+  const float r = r2 * rinv;
+  const float e = __builtin_amdgcn_exp2f(r2 * mb2l2e);
+  const float eor = erfcx_f32(beta * r) * e * rinv;
+  o.gc = w_c * fmaf(two_beta_sqrtpi, e, eor) * rinv2;
+  return o;
+}
+
 // Tabulated variant (section 3: the paper reads the radial parts of the electrostatic
 // and van der Waals terms from linearly interpolated texture tables).  Node k of a table
 // uniform in r (r = k h, h = R/n, nodes 0..n) holds
@@ -298,6 +331,34 @@ __device__ __forceinline__ PairF64 pair_f64(double r2, double c6, double c12, do
   o.erfc_over_r = erfc_br * rinv;
   o.u_c = qq * o.erfc_over_r;
   o.f = (o.dudsig_lj + qq * (o.erfc_over_r + two_beta_sqrtpi * e)) * rinv2;
+  return o;
+}
+
+// Parameter derivatives of the force factor in double precision (as pair_vjp_f32).
+__device__ __forceinline__ PairVjpF64 pair_vjp_f64(double r2, double c6, double c12, double w_lj, double w_c,
+                                                   double beta, double two_beta_sqrtpi, bool short_erfc, double sw_on2,
+                                                   double sw_inv) {
+  PairVjpF64 o;
+  double rinv = __builtin_amdgcn_rsq(r2);
+  rinv = rinv * fma(-0.5 * r2, rinv * rinv, 1.5);
+  rinv = rinv * fma(-0.5 * r2, rinv * rinv, 1.5);
+  const double r = r2 * rinv;
+  const double rinv2 = rinv * rinv;
+  const double rinv6 = rinv2 * rinv2 * rinv2;
+  const double a = c12 * rinv6 * rinv6;
+  const double b = c6 * rinv6;
+  const double u0 = a - b;
+  const double d0 = 12.0 * a - 6.0 * b;
+  const double dd = 144.0 * a - 36.0 * b;
+  const double x = fmax((r2 - sw_on2) * sw_inv, 0.0);
+  const double omx = 1.0 - x;
+  const double sw = omx * omx * (1.0 + 2.0 * x);
+  const double qs = (12.0 * x * omx) * (r2 * sw_inv);
+  o.flj = w_lj * (sw * d0 + qs * u0) * rinv2;
+  o.dflj = w_lj * (sw * dd + qs * d0) * rinv2;
+  const double e = exp_neg_f64(beta * beta * r2);
+  const double eor = erfcx_f64(beta * r, short_erfc) * e * rinv;
+  o.gc = w_c * (eor + two_beta_sqrtpi * e) * rinv2;
   return o;
 }
 

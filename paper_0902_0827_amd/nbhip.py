@@ -41,7 +41,8 @@ NB_MAX_TYPES = 64
 EXPORTED = ("nb_workspace_bytes", "nb_build_cells", "nb_nonbonded_forces", "nb_nonbonded_energy",
             "nb_nonbonded_backward", "nb_read_status", "nb_last_error", "nb_workspace_layout",
             "nb_pair_timer_start", "nb_pair_timer_stop", "nb_ewald_corrections",
-            "nb_pme_workspace_bytes", "nb_pme_reciprocal", "nb_nonbonded_forces_noalloc")
+            "nb_pme_workspace_bytes", "nb_pme_reciprocal", "nb_nonbonded_forces_noalloc",
+            "nb_nonbonded_force_vjp")
 
 
 class NbError(RuntimeError):
@@ -124,6 +125,7 @@ def load_library(path: str = LIB_PATH):
     lib.nb_nonbonded_forces.argtypes = [S, P, V, sz, V, V, V, V]
     lib.nb_nonbonded_energy.argtypes = [S, P, V, sz, V, V, V]
     lib.nb_nonbonded_backward.argtypes = [S, P, V, sz, V, V, V, V, V, V]
+    lib.nb_nonbonded_force_vjp.argtypes = [S, P, V, sz, V, V, V, V, V]
     lib.nb_ewald_corrections.argtypes = [S, P, V, sz, V, V, V, V]
     lib.nb_nonbonded_forces_noalloc.argtypes = [S, P, V, V, V, V]
     G = ctypes.POINTER(ctypes.c_int32)
@@ -336,6 +338,15 @@ def nonbonded_backward(batch: DeviceBatch, params: nb_params, ws, grad_energy, g
                                      _ptr(grad_eps), _stream(stream)))
 
 
+def nonbonded_force_vjp(batch: DeviceBatch, params: nb_params, ws, v, grad_charge=None, grad_sigma=None,
+                        grad_eps=None, stream=None):
+    """dL/dq [N], dL/dsigma [T], dL/deps [T] of L = sum_i v_i . F_i (any output may be None)."""
+    lib = load_library()
+    _check(lib.nb_nonbonded_force_vjp(ctypes.byref(batch.struct()), ctypes.byref(params), _ptr(ws), ws.numel(),
+                                      _ptr(v), _ptr(grad_charge), _ptr(grad_sigma), _ptr(grad_eps),
+                                      _stream(stream)))
+
+
 def read_status(ws, stream=None) -> int:
     lib = load_library()
     flags = ctypes.c_uint32()
@@ -372,6 +383,16 @@ def evaluate(batch: DeviceBatch, params: nb_params, ws=None, virial: bool = True
     return force, energy, vir, ws
 
 
+def _rebatch(batch: DeviceBatch, pos, charge, sigma, eps) -> DeviceBatch:
+    import torch
+    return DeviceBatch(pos=pos.detach().contiguous(), charge=charge.detach().contiguous(), type=batch.type,
+                       sigma=sigma.detach().to(torch.float64).contiguous(),
+                       eps=eps.detach().to(torch.float64).contiguous(),
+                       excl_offset=batch.excl_offset, excl_index=batch.excl_index,
+                       atom_offset=batch.atom_offset, box=batch.box,
+                       pair14_offset=batch.pair14_offset, pair14_index=batch.pair14_index)
+
+
 def _autograd():
     import torch
 
@@ -384,11 +405,7 @@ def _autograd():
 
         @staticmethod
         def forward(ctx, pos, charge, sigma, eps, batch: DeviceBatch, params: nb_params):
-            b = DeviceBatch(pos=pos.detach().contiguous(), charge=charge.detach().contiguous(), type=batch.type,
-                            sigma=sigma.detach().to(torch.float64).contiguous(),
-                            eps=eps.detach().to(torch.float64).contiguous(),
-                            excl_offset=batch.excl_offset, excl_index=batch.excl_index,
-                            atom_offset=batch.atom_offset, box=batch.box)
+            b = _rebatch(batch, pos, charge, sigma, eps)
             ws = alloc_workspace(b, params)
             build_cells(b, params, ws)
             energy = torch.empty(b.n_systems, dtype=torch.float64, device=pos.device)
@@ -412,24 +429,65 @@ def _autograd():
             return (None if gp is None else gp.to(pd), None if gq is None else gq.to(qd),
                     None if gs is None else gs.to(sd), None if ge is None else ge.to(ed), None, None)
 
-    return NonbondedEnergy
+    class NonbondedForces(torch.autograd.Function):
+        """F(pos, charge, sigma, eps) [N,3] float64, differentiable in charge, sigma and eps
+        through the force VJP (force matching).  The position derivative (a Hessian-vector
+        product) is not provided: asking for it raises."""
+
+        @staticmethod
+        def forward(ctx, pos, charge, sigma, eps, batch: DeviceBatch, params: nb_params):
+            b = _rebatch(batch, pos, charge, sigma, eps)
+            ws = alloc_workspace(b, params)
+            build_cells(b, params, ws)
+            force = torch.empty((b.n_atoms, 3), dtype=torch.float64, device=pos.device)
+            nonbonded_forces(b, params, ws, force)
+            ctx.batch, ctx.params, ctx.ws = b, params, ws
+            ctx.dtypes = (charge.dtype, sigma.dtype, eps.dtype)
+            return force
+
+        @staticmethod
+        def backward(ctx, grad_force):
+            if ctx.needs_input_grad[0]:
+                raise NotImplementedError("NonbondedForces: no derivative with respect to positions")
+            b, params, ws = ctx.batch, ctx.params, ctx.ws
+            dev = b.pos.device
+            v = grad_force.detach().to(torch.float64).contiguous()
+            need = ctx.needs_input_grad
+            gq = torch.empty(b.n_atoms, dtype=torch.float64, device=dev) if need[1] else None
+            gs = torch.empty(b.sigma.shape[0], dtype=torch.float64, device=dev) if need[2] else None
+            ge = torch.empty(b.sigma.shape[0], dtype=torch.float64, device=dev) if need[3] else None
+            nonbonded_force_vjp(b, params, ws, v, gq, gs, ge)
+            qd, sd, ed = ctx.dtypes
+            return (None, None if gq is None else gq.to(qd), None if gs is None else gs.to(sd),
+                    None if ge is None else ge.to(ed), None, None)
+
+    return NonbondedEnergy, NonbondedForces
 
 
 _NE = None
+_NF = None
+
+
+def _functions():
+    global _NE, _NF
+    if _NE is None:
+        _NE, _NF = _autograd()
+    return _NE, _NF
 
 
 def nonbonded_energy_autograd(pos, charge, sigma, eps, batch: DeviceBatch, params: nb_params):
     """Differentiable energies [B] (see NonbondedEnergy)."""
-    global _NE
-    if _NE is None:
-        _NE = _autograd()
-    return _NE.apply(pos, charge, sigma, eps, batch, params)
+    return _functions()[0].apply(pos, charge, sigma, eps, batch, params)
+
+
+def nonbonded_forces_autograd(pos, charge, sigma, eps, batch: DeviceBatch, params: nb_params):
+    """Forces [N,3] differentiable in charge, sigma and eps (see NonbondedForces)."""
+    return _functions()[1].apply(pos, charge, sigma, eps, batch, params)
 
 
 def __getattr__(name):
     if name == "NonbondedEnergy":
-        global _NE
-        if _NE is None:
-            _NE = _autograd()
-        return _NE
+        return _functions()[0]
+    if name == "NonbondedForces":
+        return _functions()[1]
     raise AttributeError(name)

@@ -281,3 +281,22 @@ def test_force_field_options_are_validated_on_the_host():
     assert ok(H.make_params(9.0, 0.34)) == H.NB_OK
     assert n.value >= base + 16 * 648  # one 128-bit 1-4 window per atom
     assert ok(H.make_params(9.0, 0.34, kernel=H.NB_KERNEL_ATOM)) == H.NB_ERR_ARG
+
+
+def test_force_vjp_host_checks():
+    """The force VJP needs v and a cluster kernel; both are checked before any launch."""
+    lib = H.load_library()
+    s = fake_system((648,))
+    p = H.make_params(9.0, 0.34)
+    code, need = ws_bytes(s, p)
+    assert code == H.NB_OK
+    assert lib.nb_nonbonded_force_vjp(ctypes.byref(s), ctypes.byref(p), FAKE, need, None, None, None, None,
+                                      None) == H.NB_ERR_ARG  # v is required
+    assert lib.nb_nonbonded_force_vjp(ctypes.byref(s), ctypes.byref(p), FAKE, need - 1, FAKE, None, None, None,
+                                      None) == H.NB_ERR_WORKSPACE
+    pa = H.make_params(9.0, 0.34, kernel=H.NB_KERNEL_ATOM)
+    code, need_a = ws_bytes(s, pa)
+    assert code == H.NB_OK
+    assert lib.nb_nonbonded_force_vjp(ctypes.byref(s), ctypes.byref(pa), FAKE, need_a, FAKE, None, None, None,
+                                      None) == H.NB_ERR_ARG
+    assert "cluster kernel" in H.last_error()
