@@ -66,6 +66,9 @@ typedef enum {
 #define NB_STATUS_NOT_BUILT 0x10u     /* the workspace was not built by nb_build_cells for this system size and
                                          kernel variant: the pair kernels wrote nothing */
 #define NB_STATUS_FAR_PAIR14 0x20u    /* a 1-4 pair more than 64 atoms apart in index: left unscaled */
+#define NB_STATUS_BAD_TOPOLOGY 0x40u  /* MD calls: a water or a bonded term names atoms outside the batch or
+                                         in two systems (the term is skipped; such a water's atoms move
+                                         as free atoms) */
 
 typedef enum {
   NB_FP64 = 0,  /* double-precision pair arithmetic from double positions */
@@ -271,6 +274,81 @@ nb_status nb_pme_reciprocal(const nb_system *sys, const nb_params *params, const
 #define NB_NOALLOC_SCRATCH_BYTES (16u << 20)
 nb_status nb_nonbonded_forces_noalloc(const nb_system *sys, const nb_params *params, double *force,
                                       double *energy, double *virial, hipStream_t stream);
+
+/* ---- Molecular dynamics around the force evaluation ----
+ *
+ * Section 3 describes production runs in the NVT ensemble: bonded and nonbonded forces,
+ * velocity-Verlet integration under a Langevin thermostat, PME electrostatics and
+ * constrained bonds to hydrogen, with the speed in ns/day at a 4 fs step reported in
+ * Table 5.  The calls below run that loop for every system of a batch on the GPU.
+ *
+ * Forces: the short-range term of nb_nonbonded_forces (with every nb_params option and
+ * kernel variant), with a PME grid also the Ewald corrections (nb_ewald_corrections) and
+ * the reciprocal part (nb_pme_reciprocal), plus harmonic bonds E = k (r - r0)^2 and angles
+ * E = k (theta - theta0)^2 (minimum image; their forces are added by FP64 atomics, so they
+ * may vary in the last bits from run to run).
+ *
+ * Step (the paper names no splitting; this is Bussi and Parrinello's Langevin velocity
+ * Verlet, Phys. Rev. E 75, 056707 (2007)), with c = exp(-gamma dt/2):
+ *   v <- c v + sqrt((1 - c^2) kT/m) xi;  v <- v + (dt/2) F/m;  x <- x + dt v, constrained,
+ *   and v <- (constrained displacement)/dt;  F <- F(x);  v <- v + (dt/2) F/m;
+ *   v <- c v + sqrt((1 - c^2) kT/m) xi';  v constrained.
+ * Constraints: rigid 3-site waters (the exact solutions of the SHAKE position and RATTLE
+ * velocity equations of each molecule).  Noise: Philox4x32-10 with counter (atom index in
+ * the batch, step mod 2^32, step div 2^32, 0 for xi or 1 for xi') and key (seed mod 2^32,
+ * seed div 2^32); uniforms (u + 1/2)/2^32; Box-Muller normals x, y from words 0, 1 and z
+ * from words 2, 3.  gamma = 0 draws no noise (velocity Verlet with constraints).
+ * Units: Angstrom, ps, g/mol, kJ/mol, K (F/m = 100 A/ps^2 per (kJ/mol/A)/(g/mol)).
+ * The state is double precision: sys->pos_is_f64 must be 1 (charges double too).
+ */
+typedef struct {
+  const double *mass;           /* [device] N masses (g/mol), > 0 */
+  int64_t n_waters;             /* rigid 3-site waters */
+  const int32_t *water_o;       /* [device] n_waters indices (in the batch) of their O atoms; the H atoms are
+                                   O + 1 and O + 2, in the same system; no atom in two waters */
+  double water_r_oh, water_r_hh;/* the held O-H and H-H distances (A); r_hh < 2 r_oh */
+  int64_t n_bonds;
+  const int32_t *bond_atoms;    /* [device] 2 n_bonds atom indices (in the batch) */
+  const double *bond_k;         /* [device] n_bonds, kJ/mol/A^2 */
+  const double *bond_r0;        /* [device] n_bonds, A */
+  int64_t n_angles;
+  const int32_t *angle_atoms;   /* [device] 3 n_angles atom indices i, j, k: the angle at j */
+  const double *angle_k;        /* [device] n_angles, kJ/mol/rad^2 */
+  const double *angle_theta0;   /* [device] n_angles, rad */
+} nb_md_topology;
+
+typedef struct {
+  double dt;            /* time step (ps), > 0 */
+  double temperature;   /* K, >= 0 */
+  double gamma;         /* Langevin friction (1/ps), >= 0; 0: no thermostat */
+  uint64_t seed;        /* key of the thermostat noise */
+  int32_t pme_grid[3];  /* [host] reciprocal-part grid (as nb_pme_reciprocal; needs ewald_beta > 0);
+                           {0, 0, 0}: no reciprocal part and no Ewald corrections */
+  int32_t reserved;     /* 0 */
+} nb_md_params;
+
+/* Workspace of the MD calls (it holds a nonbonded workspace, a reciprocal-part workspace
+ * and the force parts); with a PME grid it needs a current HIP device (FFT plans). */
+nb_status nb_md_workspace_bytes(const nb_system *sys, const nb_params *params, const nb_md_params *md,
+                                size_t *bytes /*[host]*/);
+
+/* Total force at sys->pos [device, N*3 doubles, written] and, if energy is not NULL, the
+ * energies per system [device, 4*B doubles: short-range, Ewald corrections, reciprocal,
+ * bonded].  The MD workspace (256-byte aligned, nb_md_workspace_bytes) is the caller's. */
+nb_status nb_md_forces(const nb_system *sys, const nb_params *params, const nb_md_topology *topo /*[host]*/,
+                       const nb_md_params *md /*[host]*/, void *workspace, size_t workspace_bytes, double *force,
+                       double *energy, hipStream_t stream);
+
+/* n_steps >= 0 steps of the integrator, numbered first_step .. first_step + n_steps - 1
+ * (the noise counters), from the positions pos (== sys->pos) and velocities vel [device,
+ * N*3 doubles each, updated in place].  The forces at the starting positions are computed
+ * first, so consecutive calls continue one trajectory.  If energy is not NULL, the final
+ * state's energies per system [device, 5*B doubles: short-range, Ewald corrections,
+ * reciprocal, bonded, kinetic].  Velocities need not satisfy the constraints on entry; on
+ * return they do. */
+nb_status nb_md_run(const nb_system *sys, const nb_params *params, const nb_md_topology *topo /*[host]*/,
+                    const nb_md_params *md /*[host]*/, void *workspace, size_t workspace_bytes, double *pos,
+                    double *vel, int64_t first_step, int64_t n_steps, double *energy, hipStream_t stream);
 
 /* Synchronises `stream` and returns the NB_STATUS_* bits accumulated in the workspace. */
 nb_status nb_read_status(const void *workspace, hipStream_t stream, uint32_t *flags /*[host]*/);

@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "libnbhip.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["nb_api.cpp", "nb_build.hip", "nb_pair.hip", "nb_pair_cluster_f32.hip", "nb_pair_cluster_f64.hip",
-           "nb_ewald.hip", "nb_pme.hip", "nb_noalloc.hip"]
+           "nb_ewald.hip", "nb_pme.hip", "nb_noalloc.hip", "nb_md.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -11,6 +11,7 @@
 #include <string>
 
 #include "nb_internal.h"
+#include "nb_md.h"
 #include "nb_pme.h"
 
 namespace nb {
@@ -466,6 +467,70 @@ nb_status nb_nonbonded_forces_noalloc(const nb_system *sys, const nb_params *par
     st = nb::noalloc_forces(p, sys, force, energy, virial, stream, &why);
     if (st != NB_OK) return fail(st, "nb_nonbonded_forces_noalloc: " + why);
     return NB_OK;
+  });
+}
+
+nb_status nb_md_workspace_bytes(const nb_system *sys, const nb_params *params, const nb_md_params *md,
+                                size_t *bytes) {
+  return guarded("nb_md_workspace_bytes", [&]() -> nb_status {
+    if (!bytes) return fail(NB_ERR_ARG, "bytes is NULL");
+    nb::MdPlan mp;
+    std::string why;
+    const nb_status st = nb::md_plan(sys, params, md, &mp, &why);
+    if (st != NB_OK) return why.empty() ? st : fail(st, "nb_md_workspace_bytes: " + why);
+    *bytes = mp.ml.total;
+    return NB_OK;
+  });
+}
+
+namespace {
+// Plan, workspace and topology checks shared by the two MD calls.
+nb_status md_prepare(const char *what, const nb_system *sys, const nb_params *params, const nb_md_topology *topo,
+                     const nb_md_params *md, void *workspace, size_t workspace_bytes, nb::MdPlan *mp) {
+  std::string why;
+  nb_status st = nb::md_plan(sys, params, md, mp, &why);
+  if (st != NB_OK) return why.empty() ? st : fail(st, std::string(what) + ": " + why);
+  if (!workspace) return fail(NB_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(NB_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (workspace_bytes < mp->ml.total)
+    return fail(NB_ERR_WORKSPACE, "workspace too small: " + std::to_string(workspace_bytes) + " < " +
+                                      std::to_string(mp->ml.total));
+  why = nb::md_check_topology(*mp, topo);
+  if (!why.empty()) return fail(NB_ERR_ARG, std::string(what) + ": " + why);
+  if (mp->p.N > 0 && !sys->pos) return fail(NB_ERR_ARG, "pos is NULL");
+  return NB_OK;
+}
+}  // namespace
+
+nb_status nb_md_forces(const nb_system *sys, const nb_params *params, const nb_md_topology *topo,
+                       const nb_md_params *md, void *workspace, size_t workspace_bytes, double *force,
+                       double *energy, hipStream_t stream) {
+  return guarded("nb_md_forces", [&]() -> nb_status {
+    nb::MdPlan mp;
+    nb_status st = md_prepare("nb_md_forces", sys, params, topo, md, workspace, workspace_bytes, &mp);
+    if (st != NB_OK) return st;
+    if (!force && mp.p.N > 0) return fail(NB_ERR_ARG, "force must not be NULL");
+    std::string err;
+    const hipError_t e = nb::md_forces(mp, sys, topo, md, workspace, force, energy, stream, &err);
+    if (!err.empty()) return fail(NB_ERR_HIP, "nb_md_forces: " + err);
+    return hip_status(e, "nb_md_forces");
+  });
+}
+
+nb_status nb_md_run(const nb_system *sys, const nb_params *params, const nb_md_topology *topo,
+                    const nb_md_params *md, void *workspace, size_t workspace_bytes, double *pos, double *vel,
+                    int64_t first_step, int64_t n_steps, double *energy, hipStream_t stream) {
+  return guarded("nb_md_run", [&]() -> nb_status {
+    nb::MdPlan mp;
+    nb_status st = md_prepare("nb_md_run", sys, params, topo, md, workspace, workspace_bytes, &mp);
+    if (st != NB_OK) return st;
+    if (n_steps < 0 || first_step < 0) return fail(NB_ERR_ARG, "first_step and n_steps must be >= 0");
+    if (mp.p.N > 0 && (!vel || pos != sys->pos)) return fail(NB_ERR_ARG, "pos must be sys->pos and vel non-NULL");
+    std::string err;
+    const hipError_t e = nb::md_run(mp, sys, topo, md, workspace, vel, first_step, n_steps, energy, stream, &err);
+    if (!err.empty()) return fail(NB_ERR_HIP, "nb_md_run: " + err);
+    return hip_status(e, "nb_md_run");
   });
 }
 

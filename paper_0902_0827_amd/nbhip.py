@@ -36,13 +36,14 @@ NB_STATUS_BAD_EXCLUSION = 0x4
 NB_STATUS_FAR_EXCLUSION = 0x8
 NB_STATUS_NOT_BUILT = 0x10
 NB_STATUS_FAR_PAIR14 = 0x20
+NB_STATUS_BAD_TOPOLOGY = 0x40
 NB_MAX_TYPES = 64
 
 EXPORTED = ("nb_workspace_bytes", "nb_build_cells", "nb_nonbonded_forces", "nb_nonbonded_energy",
             "nb_nonbonded_backward", "nb_read_status", "nb_last_error", "nb_workspace_layout",
             "nb_pair_timer_start", "nb_pair_timer_stop", "nb_ewald_corrections",
             "nb_pme_workspace_bytes", "nb_pme_reciprocal", "nb_nonbonded_forces_noalloc",
-            "nb_nonbonded_force_vjp")
+            "nb_nonbonded_force_vjp", "nb_md_workspace_bytes", "nb_md_forces", "nb_md_run")
 
 
 class NbError(RuntimeError):
@@ -91,6 +92,35 @@ class nb_params(ctypes.Structure):
     ]
 
 
+class nb_md_topology(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_void_p),
+        ("n_waters", ctypes.c_int64),
+        ("water_o", ctypes.c_void_p),
+        ("water_r_oh", ctypes.c_double),
+        ("water_r_hh", ctypes.c_double),
+        ("n_bonds", ctypes.c_int64),
+        ("bond_atoms", ctypes.c_void_p),
+        ("bond_k", ctypes.c_void_p),
+        ("bond_r0", ctypes.c_void_p),
+        ("n_angles", ctypes.c_int64),
+        ("angle_atoms", ctypes.c_void_p),
+        ("angle_k", ctypes.c_void_p),
+        ("angle_theta0", ctypes.c_void_p),
+    ]
+
+
+class nb_md_params(ctypes.Structure):
+    _fields_ = [
+        ("dt", ctypes.c_double),
+        ("temperature", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("pme_grid", ctypes.c_int32 * 3),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
 class nb_layout(ctypes.Structure):
     _fields_ = [
         ("n_atoms", ctypes.c_int64),
@@ -126,6 +156,10 @@ def load_library(path: str = LIB_PATH):
     lib.nb_nonbonded_energy.argtypes = [S, P, V, sz, V, V, V]
     lib.nb_nonbonded_backward.argtypes = [S, P, V, sz, V, V, V, V, V, V]
     lib.nb_nonbonded_force_vjp.argtypes = [S, P, V, sz, V, V, V, V, V]
+    MT, MP = ctypes.POINTER(nb_md_topology), ctypes.POINTER(nb_md_params)
+    lib.nb_md_workspace_bytes.argtypes = [S, P, MP, ctypes.POINTER(sz)]
+    lib.nb_md_forces.argtypes = [S, P, MT, MP, V, sz, V, V, V]
+    lib.nb_md_run.argtypes = [S, P, MT, MP, V, sz, V, V, ctypes.c_int64, ctypes.c_int64, V, V]
     lib.nb_ewald_corrections.argtypes = [S, P, V, sz, V, V, V, V]
     lib.nb_nonbonded_forces_noalloc.argtypes = [S, P, V, V, V, V]
     G = ctypes.POINTER(ctypes.c_int32)
@@ -345,6 +379,90 @@ def nonbonded_force_vjp(batch: DeviceBatch, params: nb_params, ws, v, grad_charg
     _check(lib.nb_nonbonded_force_vjp(ctypes.byref(batch.struct()), ctypes.byref(params), _ptr(ws), ws.numel(),
                                       _ptr(v), _ptr(grad_charge), _ptr(grad_sigma), _ptr(grad_eps),
                                       _stream(stream)))
+
+
+# --- molecular dynamics --------------------------------------------------------------------
+
+@dataclass
+class DeviceTopology:
+    """Device tensors of an MD topology (systems.md_topology / concat_topologies layout)."""
+
+    mass: "object"
+    water_o: "object"
+    r_oh: float
+    r_hh: float
+    bonds: "object"
+    bond_k: "object"
+    bond_r0: "object"
+    angles: "object"
+    angle_k: "object"
+    angle_theta0: "object"
+
+    def struct(self) -> nb_md_topology:
+        t = nb_md_topology()
+        t.mass = _ptr(self.mass)
+        t.n_waters = int(self.water_o.numel())
+        t.water_o = _ptr(self.water_o) if t.n_waters else None
+        t.water_r_oh, t.water_r_hh = float(self.r_oh), float(self.r_hh)
+        t.n_bonds = int(self.bonds.shape[0])
+        t.bond_atoms = _ptr(self.bonds) if t.n_bonds else None
+        t.bond_k = _ptr(self.bond_k) if t.n_bonds else None
+        t.bond_r0 = _ptr(self.bond_r0) if t.n_bonds else None
+        t.n_angles = int(self.angles.shape[0])
+        t.angle_atoms = _ptr(self.angles) if t.n_angles else None
+        t.angle_k = _ptr(self.angle_k) if t.n_angles else None
+        t.angle_theta0 = _ptr(self.angle_theta0) if t.n_angles else None
+        return t
+
+
+def device_topology(topo: dict, device: str = "cuda") -> DeviceTopology:
+    import torch
+    f64 = lambda a: torch.tensor(np.asarray(a, np.float64), dtype=torch.float64, device=device)
+    i32 = lambda a: torch.tensor(np.asarray(a, np.int32), dtype=torch.int32, device=device)
+    return DeviceTopology(mass=f64(topo["mass"]), water_o=i32(topo["water_o"]), r_oh=topo["r_oh"],
+                          r_hh=topo["r_hh"], bonds=i32(topo["bonds"]).reshape(-1, 2), bond_k=f64(topo["bond_k"]),
+                          bond_r0=f64(topo["bond_r0"]), angles=i32(topo["angles"]).reshape(-1, 3),
+                          angle_k=f64(topo["angle_k"]), angle_theta0=f64(topo["angle_theta0"]))
+
+
+def make_md_params(dt: float, temperature: float = 300.0, gamma: float = 1.0, seed: int = 1,
+                   pme_grid=(0, 0, 0)) -> nb_md_params:
+    m = nb_md_params()
+    m.dt, m.temperature, m.gamma, m.seed = float(dt), float(temperature), float(gamma), int(seed)
+    for a in range(3):
+        m.pme_grid[a] = int(pme_grid[a])
+    m.reserved = 0
+    return m
+
+
+def md_workspace_bytes(batch: DeviceBatch, params: nb_params, md: nb_md_params) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().nb_md_workspace_bytes(ctypes.byref(batch.struct()), ctypes.byref(params),
+                                                ctypes.byref(md), ctypes.byref(n)))
+    return int(n.value)
+
+
+def alloc_md_workspace(batch: DeviceBatch, params: nb_params, md: nb_md_params):
+    import torch
+    ws = torch.empty(max(md_workspace_bytes(batch, params, md), 1), dtype=torch.uint8, device=batch.pos.device)
+    assert ws.data_ptr() % 256 == 0
+    return ws
+
+
+def md_forces(batch: DeviceBatch, params: nb_params, topo: DeviceTopology, md: nb_md_params, ws, force,
+              energy=None, stream=None):
+    _check(load_library().nb_md_forces(ctypes.byref(batch.struct()), ctypes.byref(params),
+                                       ctypes.byref(topo.struct()), ctypes.byref(md), _ptr(ws), ws.numel(),
+                                       _ptr(force), _ptr(energy), _stream(stream)))
+
+
+def md_run(batch: DeviceBatch, params: nb_params, topo: DeviceTopology, md: nb_md_params, ws, vel,
+           first_step: int, n_steps: int, energy=None, stream=None):
+    """n_steps integrator steps in place on batch.pos (float64) and vel."""
+    _check(load_library().nb_md_run(ctypes.byref(batch.struct()), ctypes.byref(params),
+                                    ctypes.byref(topo.struct()), ctypes.byref(md), _ptr(ws), ws.numel(),
+                                    _ptr(batch.pos), _ptr(vel), int(first_step), int(n_steps), _ptr(energy),
+                                    _stream(stream)))
 
 
 def read_status(ws, stream=None) -> int:

@@ -371,6 +371,49 @@ def with_chain_14(s: System) -> System:
     return t
 
 
+# Stand-in bonded force field of the bead chain for the MD loop (the chain recipe names
+# none): harmonic bonds at the chain's bond length and harmonic angles.
+MASS_O = 15.999
+MASS_H = 1.008
+CHAIN_BOND_K = 300.0                     # kJ/mol/A^2
+CHAIN_ANGLE_K = 50.0                     # kJ/mol/rad^2
+CHAIN_ANGLE_THETA0 = math.radians(109.5)
+
+
+def water_hh() -> float:
+    """H-H distance of the rigid water geometry."""
+    return 2.0 * OH_BOND * math.sin(math.radians(HOH_ANGLE_DEG) / 2)
+
+
+def md_topology(system: System) -> dict:
+    """Masses, rigid waters (O indices) and the chain's bonds and angles of one system,
+    with atom indices local to it."""
+    n, n_s = system.n, system.n_solute
+    n_w = (n - n_s) // 3
+    mass = np.full(n, MASS_BEAD)
+    mass[n_s:] = np.tile([MASS_O, MASS_H, MASS_H], n_w)
+    i = np.arange(max(n_s - 1, 0))
+    bonds = np.stack([i, i + 1], 1).astype(np.int32).reshape(-1, 2)
+    j = np.arange(max(n_s - 2, 0))
+    angles = np.stack([j, j + 1, j + 2], 1).astype(np.int32).reshape(-1, 3)
+    return dict(mass=mass, water_o=(n_s + 3 * np.arange(n_w)).astype(np.int32), r_oh=OH_BOND, r_hh=water_hh(),
+                bonds=bonds, bond_k=np.full(len(bonds), CHAIN_BOND_K), bond_r0=np.full(len(bonds), BOND),
+                angles=angles, angle_k=np.full(len(angles), CHAIN_ANGLE_K),
+                angle_theta0=np.full(len(angles), CHAIN_ANGLE_THETA0))
+
+
+def concat_topologies(topos: List[dict], sizes) -> dict:
+    """Batch layout of per-system md_topology dicts: atom indices shifted by each system's
+    offset."""
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    cat = lambda key, shift: np.concatenate([t[key] + (offs[k] if shift else 0) for k, t in enumerate(topos)])
+    return dict(mass=cat("mass", False), water_o=cat("water_o", True).astype(np.int32),
+                r_oh=topos[0]["r_oh"], r_hh=topos[0]["r_hh"],
+                bonds=cat("bonds", True).astype(np.int32).reshape(-1, 2), bond_k=cat("bond_k", False),
+                bond_r0=cat("bond_r0", False), angles=cat("angles", True).astype(np.int32).reshape(-1, 3),
+                angle_k=cat("angle_k", False), angle_theta0=cat("angle_theta0", False))
+
+
 def concat_systems(systems: List[System]):
     """Pack systems back to back (batch layout): returns a dict of concatenated arrays.
 

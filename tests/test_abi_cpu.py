@@ -300,3 +300,70 @@ def test_force_vjp_host_checks():
     assert lib.nb_nonbonded_force_vjp(ctypes.byref(s), ctypes.byref(pa), FAKE, need_a, FAKE, None, None, None,
                                       None) == H.NB_ERR_ARG
     assert "cluster kernel" in H.last_error()
+
+
+def _md_topo(n_waters=216):
+    t = H.nb_md_topology()
+    t.mass = FAKE
+    t.n_waters = n_waters
+    t.water_o = FAKE
+    t.water_r_oh, t.water_r_hh = 0.9572, 1.5139
+    t.n_bonds = t.n_angles = 0
+    return t
+
+
+def test_md_calls_validate_on_the_host():
+    """MD workspace size and argument checks (no GPU: no PME grid, fake device pointers)."""
+    lib = H.load_library()
+    s = fake_system((648,))
+    p = H.make_params(9.0, 0.34)
+    md = H.make_md_params(0.004, 300.0, 1.0, 7)
+    n = ctypes.c_size_t()
+    call = lambda: lib.nb_md_workspace_bytes(ctypes.byref(s), ctypes.byref(p), ctypes.byref(md), ctypes.byref(n))
+    assert call() == H.NB_ERR_ARG and "pos_is_f64" in H.last_error()  # the MD state is FP64
+    s.pos_is_f64 = 1
+    assert call() == H.NB_OK
+    nb = ws_bytes(s, p)[1]
+    assert n.value >= nb + 2 * 3 * 8 * 648 + 648  # short-range and bonded forces, roles
+    need = n.value
+    md.dt = 0.0
+    assert call() == H.NB_ERR_ARG
+    md.dt = 0.004
+    md.gamma = -1.0
+    assert call() == H.NB_ERR_ARG
+    md.gamma = 1.0
+    md.pme_grid[0] = 2  # a grid below 4 points
+    md.pme_grid[1] = md.pme_grid[2] = 32
+    assert call() == H.NB_ERR_ARG
+    md.pme_grid[0] = md.pme_grid[1] = md.pme_grid[2] = 0
+    topo = _md_topo()
+    run = lambda t, ws, size, pos, vel, n_steps: lib.nb_md_run(
+        ctypes.byref(s), ctypes.byref(p), t, ctypes.byref(md), ws, size, pos, vel, 0, n_steps, None, None)
+    assert run(None, FAKE, need, FAKE, FAKE, 1) == H.NB_ERR_ARG                    # no topology
+    assert run(ctypes.byref(topo), FAKE, need - 1, FAKE, FAKE, 1) == H.NB_ERR_WORKSPACE
+    assert run(ctypes.byref(topo), FAKE, need, FAKE + 8, FAKE, 1) == H.NB_ERR_ARG  # pos is not sys->pos
+    assert run(ctypes.byref(topo), FAKE, need, FAKE, None, 1) == H.NB_ERR_ARG      # no velocities
+    assert run(ctypes.byref(topo), FAKE, need, FAKE, FAKE, -1) == H.NB_ERR_ARG
+    bad = _md_topo()
+    bad.water_r_hh = 2.0  # not a triangle with r_oh = 0.9572
+    assert run(ctypes.byref(bad), FAKE, need, FAKE, FAKE, 1) == H.NB_ERR_ARG
+    bad = _md_topo(217)   # more waters than 648 atoms hold
+    assert run(ctypes.byref(bad), FAKE, need, FAKE, FAKE, 1) == H.NB_ERR_ARG
+    bad = _md_topo()
+    bad.n_bonds = 3       # bonds without arrays
+    assert run(ctypes.byref(bad), FAKE, need, FAKE, FAKE, 1) == H.NB_ERR_ARG
+    assert lib.nb_md_forces(ctypes.byref(s), ctypes.byref(p), ctypes.byref(topo), ctypes.byref(md), FAKE, need,
+                            None, None, None) == H.NB_ERR_ARG  # force is required
+
+
+def test_md_topology_generator():
+    s = S.config2()
+    t = S.md_topology(s)
+    assert t["water_o"].size == (s.n - s.n_solute) // 3 == 7200
+    assert len(t["bonds"]) == s.n_solute - 1 and len(t["angles"]) == s.n_solute - 2
+    # the generator's waters hold the rigid geometry the constraints keep
+    o = t["water_o"]
+    d = lambda a, b: np.linalg.norm(S._minimage(s.pos[a] - s.pos[b], s.box), axis=1)
+    assert np.allclose(d(o, o + 1), t["r_oh"], atol=1e-12) and np.allclose(d(o + 1, o + 2), t["r_hh"], atol=1e-12)
+    cat = S.concat_topologies([t, t], [s.n, s.n])
+    assert cat["water_o"][7200] == s.n + o[0] and cat["bonds"][len(t["bonds"])][0] == s.n
