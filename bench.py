@@ -129,6 +129,8 @@ def ewald_rate(b, p, ws, prec_name, steps, torch, H):
 # convolution and read by the inverse FFT (4 x 8), and the potential written and read by
 # the gather (8 + 8): 64 bytes.
 PME_GRID = (64, 64, 64)
+MD_DT_PS = 0.004            # the paper's production time step (Table 5)
+KB_KJ_MOL_K = 8.314462618e-3  # molar gas constant (temperature read-out of the MD leg)
 PME_BATCH_GRID = (48, 48, 48)  # one grid for every replica of the batch (boxes of 32-68 A)
 PME_BYTES_PER_ATOM = {"mixed": 2 * 16 + 24, "fp64": 2 * 32 + 24}
 PME_BYTES_PER_POINT = 64
@@ -375,6 +377,47 @@ def run_tables(args, H, s, torch):
     return out
 
 
+def run_md(args, H, S, torch, s):
+    """The MD loop at the paper's production setting (section 3, Table 5: 4 fs step,
+    Langevin thermostat, rigid waters, PME every step, R = 9 A with the LJ switch from
+    7.5 A) on the 23.6k-atom chain-in-water box: ms per step and ns/day, mixed path and
+    FP64 path, after an untimed start from rest (the paper's DHFR benchmark has 23,558
+    atoms; Table 5 gives 19.7 ns/day for it on one GTX 280, another machine's figure)."""
+    out = {}
+    for name, prec, n_steps in (("mixed", H.NB_MIXED, args.md_steps), ("fp64", H.NB_FP64, max(20, args.md_steps // 5))):
+        b = H.device_batch([s], dtype=torch.float64)
+        p = H.make_params(s.cutoff, s.beta, prec, lj_switch_on=7.5)
+        md = H.make_md_params(MD_DT_PS, 300.0, 1.0, seed=2009, pme_grid=PME_GRID)
+        topo = S.md_topology(s)
+        t = H.device_topology(topo)
+        ws = H.alloc_md_workspace(b, p, md)
+        vel = torch.zeros((s.n, 3), dtype=torch.float64, device="cuda")
+        energy = torch.empty(5, dtype=torch.float64, device="cuda")
+        # untimed start from rest: the lattice start's excess potential energy is taken out
+        # by a stronger friction (10/ps) before the timed run at 1/ps
+        warm = H.make_md_params(MD_DT_PS, 300.0, 10.0, seed=2009, pme_grid=PME_GRID)
+        H.md_run(b, p, t, warm, ws, vel, 0, args.md_warmup, energy)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H.md_run(b, p, t, md, ws, vel, args.md_warmup, n_steps, energy)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / n_steps
+        e = energy.cpu().numpy()
+        dof = 3 * s.n - 3 * topo["water_o"].size
+        temp = 2 * e[4] / (dof * KB_KJ_MOL_K)
+        ns_day = MD_DT_PS * 1e-3 * 86400.0 / sec
+        log(f"[bench] MD {name}: {sec * 1e3:.4f} ms/step, {ns_day:.1f} ns/day at {MD_DT_PS * 1e3:.0f} fs, "
+            f"T = {temp:.1f} K after {args.md_warmup + n_steps} steps")
+        out[name] = {"ms_per_step": sec * 1e3, "ns_per_day": ns_day, "steps": n_steps, "warmup_steps": args.md_warmup,
+                     "temperature_K": temp, "energy_kJ_mol": {"short_range": e[0], "ewald_corrections": e[1],
+                                                              "reciprocal": e[2], "bonded": e[3], "kinetic": e[4]},
+                     "status": H.read_status(ws)}
+    out["setting"] = {"dt_fs": MD_DT_PS * 1e3, "thermostat": "Langevin, gamma 1/ps, 300 K", "pme_grid": list(PME_GRID),
+                      "lj_switch": [7.5, 9.0], "constraints": "rigid waters",
+                      "bonded": "chain harmonic bonds and angles"}
+    return out
+
+
 def cpu_info():
     """Host CPU model (lscpu) and the threads the oracle may use."""
     import subprocess
@@ -410,6 +453,9 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the million-atom water box")
     ap.add_argument("--no-tables", action="store_true", help="skip the tabulated variant")
     ap.add_argument("--large-steps", type=int, default=20)
+    ap.add_argument("--no-md", action="store_true", help="skip the MD loop (ns/day)")
+    ap.add_argument("--md-steps", type=int, default=500)
+    ap.add_argument("--md-warmup", type=int, default=250)
     ap.add_argument("--large-rows", type=int, default=256, help="oracle rows sampled on the million-atom box")
     ap.add_argument("--tune-budget", type=float, default=45.0,
                     help="seconds the autotuner may spend on the batch (0: library defaults)")
@@ -533,6 +579,7 @@ def main():
     batch = None if args.no_batch else run_batch(args, H, S, torch)
     large = None if args.no_large else run_large(args, H, S, torch)
     tables = None if args.no_tables else run_tables(args, H, s, torch)
+    md = None if args.no_md else run_md(args, H, S, torch, s)
 
     pairs = ref["mixed"]["pairs"]
     m = results["mixed"]
@@ -634,6 +681,9 @@ def main():
                            "box": {name: pme_entry(results[name]["pme"], ref_pme[name]) for name in results},
                            "oracle_ms": float(np.median(t_pme)) * 1e3,
                            "batch": None if batch is None else batch.get("pme")},
+        # the MD loop around the forces (velocity Verlet + Langevin, rigid waters, PME every
+        # step) at a 4 fs step: ms per step and ns/day
+        "md": md,
         "status_bits": [r["status"] for r in results.values()],
     }
     print(json.dumps(out), flush=True)
