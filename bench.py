@@ -387,7 +387,9 @@ def run_md(args, H, S, torch, s):
     for name, prec, n_steps in (("mixed", H.NB_MIXED, args.md_steps), ("fp64", H.NB_FP64, max(20, args.md_steps // 5))):
         b = H.device_batch([s], dtype=torch.float64)
         p = H.make_params(s.cutoff, s.beta, prec, lj_switch_on=7.5)
-        md = H.make_md_params(MD_DT_PS, 300.0, 1.0, seed=2009, pme_grid=PME_GRID)
+        # the reciprocal part on a second stream, beside the short-range work
+        aux = torch.cuda.Stream()
+        md = H.make_md_params(MD_DT_PS, 300.0, 1.0, seed=2009, pme_grid=PME_GRID, aux_stream=aux)
         topo = S.md_topology(s)
         t = H.device_topology(topo)
         ws = H.alloc_md_workspace(b, p, md)
@@ -395,7 +397,7 @@ def run_md(args, H, S, torch, s):
         energy = torch.empty(5, dtype=torch.float64, device="cuda")
         # untimed start from rest: the lattice start's excess potential energy is taken out
         # by a stronger friction (10/ps) before the timed run at 1/ps
-        warm = H.make_md_params(MD_DT_PS, 300.0, 10.0, seed=2009, pme_grid=PME_GRID)
+        warm = H.make_md_params(MD_DT_PS, 300.0, 10.0, seed=2009, pme_grid=PME_GRID, aux_stream=aux)
         H.md_run(b, p, t, warm, ws, vel, 0, args.md_warmup, energy)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -325,6 +325,10 @@ typedef struct {
   int32_t pme_grid[3];  /* [host] reciprocal-part grid (as nb_pme_reciprocal; needs ewald_beta > 0);
                            {0, 0, 0}: no reciprocal part and no Ewald corrections */
   int32_t reserved;     /* 0 */
+  hipStream_t aux_stream; /* NULL, or a second stream (default priority) on which the reciprocal part
+                           runs concurrently with the short-range term: every call then orders it
+                           against `stream` with HIP events of its own, so the caller only needs
+                           both streams to be usable on the current device */
 } nb_md_params;
 
 /* Workspace of the MD calls (it holds a nonbonded workspace, a reciprocal-part workspace

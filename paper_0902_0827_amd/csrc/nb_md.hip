@@ -14,7 +14,7 @@
 //
 // Rigid 3-site waters are the constrained molecules.  Their positions: the constrained
 // displacement of each atom is a sum of the pre-move bond vectors times multipliers,
-// which one thread per water finds by Newton's method on the three length equations
+// which the water's three lanes find by Newton's method on the three length equations
 // (a 3 x 3 solve per iteration; quadratic convergence from zero takes 3-5 iterations at
 // MD displacements).  Their velocities: the three multipliers that remove the relative
 // velocity along each bond solve one 3 x 3 linear system.  Both are the solutions of the
@@ -44,6 +44,7 @@ constexpr double kAccel = 100.0;          // (kJ/mol/A)/(g/mol) in A/ps^2
 constexpr double kBoltzmann = 8.314462618e-3;  // molar gas constant, kJ/mol/K
 constexpr double kKineticUnit = 0.01;     // g/mol A^2/ps^2 in kJ/mol
 constexpr int kNewtonMax = 12;
+constexpr int kWatersPerWave = 21;  // three lanes each
 constexpr int kMdBlock = 256;
 constexpr uint32_t kMdStatusBad = NB_STATUS_BAD_TOPOLOGY;
 
@@ -64,6 +65,8 @@ struct MdArgs {
   uint32_t key0, key1;
   int64_t step_end, step_start;  // the step a kEnd half finishes, the step a kStart half begins
   int thermostat;                // 0: gamma = 0, no noise is drawn
+  const int32_t *water_o;
+  int64_t n_waters;
 };
 
 __device__ inline int system_of(const SysDesc *desc, int B, int64_t atom) {
@@ -128,14 +131,11 @@ struct WaterCoupling {
   }
 };
 
-// Adds w_a sum_p m_p sigma_pa s_p to the three atoms' vectors y.
-__device__ inline void apply_multipliers(double (&y)[3][3], const double (&w)[3], const double (&m)[3],
-                                         const double (&s)[3][3]) {
-  for (int c = 0; c < 3; ++c) {
-    y[0][c] += w[0] * (m[0] * s[0][c] + m[1] * s[1][c]);
-    y[1][c] += w[1] * (-m[0] * s[0][c] + m[2] * s[2][c]);
-    y[2][c] += w[2] * (-m[1] * s[1][c] - m[2] * s[2][c]);
-  }
+// The move of atom a: w_a sum_p m_p sigma_pa s_p (component c).
+__device__ inline double multiplier_move(int a, double wa, const double (&m)[3], const double (&s)[3][3], int c) {
+  return a == 0 ? wa * (m[0] * s[0][c] + m[1] * s[1][c])
+       : a == 1 ? wa * (-m[0] * s[0][c] + m[2] * s[2][c])
+                : wa * (-m[1] * s[1][c] - m[2] * s[2][c]);
 }
 
 __device__ inline void bond_vectors(const double (&y)[3][3], double (&s)[3][3]) {
@@ -146,133 +146,166 @@ __device__ inline void bond_vectors(const double (&y)[3][3], double (&s)[3][3]) 
   }
 }
 
-// One unit: a free atom (NA = 1) or a rigid water (NA = 3, atoms i, i + 1, i + 2).
-template <int PH, int NA>
-__device__ inline void integrate_unit(const MdArgs &k, int64_t i, int b) {
-  double x[NA][3], v[NA][3], f[NA][3], w[NA];
-  for (int a = 0; a < NA; ++a) {
-    const int64_t at = i + a;
-    w[a] = 1.0 / k.mass[at];
+// v <- c v + sqrt(noise_var / m) xi for one atom.
+__device__ inline void thermostat(const MdArgs &k, double (&v)[3], double w, int64_t atom, int64_t step,
+                                  uint32_t half) {
+  const double3 z = normals(k, atom, step, half);
+  const double sd = sqrt(k.noise_var * w);
+  v[0] = k.c * v[0] + sd * z.x;
+  v[1] = k.c * v[1] + sd * z.y;
+  v[2] = k.c * v[2] + sd * z.z;
+}
+
+// Reads atom `at`'s position, velocity, summed force and inverse mass; zeroes its bonded
+// force for the next evaluation.
+__device__ inline void load_atom(const MdArgs &k, int64_t at, double (&x)[3], double (&v)[3], double (&f)[3],
+                                 double &w) {
+  w = 1.0 / k.mass[at];
+  for (int c = 0; c < 3; ++c) {
+    const int64_t e = 3 * at + c;
+    x[c] = k.pos[e];
+    v[c] = k.vel[e];
+    double fs = k.f_nb[e] + k.f_bond[e];
+    if (k.f_corr) fs += k.f_corr[e] + k.f_rec[e];
+    f[c] = fs;
+    k.f_bond[e] = 0.0;
+  }
+}
+
+// A free atom (one thread).
+template <int PH>
+__device__ inline void integrate_free(const MdArgs &k, int64_t i) {
+  double x[3], v[3], f[3], w;
+  load_atom(k, i, x, v, f, w);
+  const double hdt = 0.5 * k.dt * kAccel;
+  if constexpr ((PH & kEnd) != 0) {
+    for (int c = 0; c < 3; ++c) v[c] += hdt * f[c] * w;
+    if (k.thermostat) thermostat(k, v, w, i, k.step_end, 1u);
+  }
+  if constexpr ((PH & kStart) != 0) {
+    if (k.thermostat) thermostat(k, v, w, i, k.step_start, 0u);
     for (int c = 0; c < 3; ++c) {
-      const int64_t e = 3 * at + c;
-      x[a][c] = k.pos[e];
-      v[a][c] = k.vel[e];
-      double fs = k.f_nb[e] + k.f_bond[e];
-      if (k.f_corr) fs += k.f_corr[e] + k.f_rec[e];
-      f[a][c] = fs;
-      k.f_bond[e] = 0.0;  // the next bonded evaluation adds into zeros
+      v[c] += hdt * f[c] * w;
+      x[c] += k.dt * v[c];
+      k.pos[3 * i + c] = x[c];
     }
   }
-  const SysDesc &sd = k.desc[b];
-  // water: coordinates relative to the O atom's (minimum image within the molecule)
-  double y[NA][3];
-  for (int a = 0; a < NA; ++a)
-    for (int c = 0; c < 3; ++c) y[a][c] = a == 0 ? 0.0 : minimage(x[a][c] - x[0][c], sd.box[c], sd.inv_box[c]);
+  for (int c = 0; c < 3; ++c) k.vel[3 * i + c] = v[c];
+}
+
+// A rigid water: three consecutive lanes (base, base + 1, base + 2 of one wave), lane a
+// holding atom O + a.  Each lane draws its own atom's noise; the molecule's multipliers
+// are solved by all three lanes alike from the values shuffled between them, and each
+// lane moves its own atom.  Lanes with valid = false only take part in the shuffles.
+template <int PH>
+__device__ inline void integrate_water(const MdArgs &k, int64_t o, int a, int base, bool valid) {
+  double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, f[3] = {0, 0, 0}, w = 1.0;
+  int b = 0;
+  if (valid) {
+    load_atom(k, o + a, x, v, f, w);
+    b = system_of(k.desc, k.B, o);
+  }
+  const double L[3] = {k.desc[b].box[0], k.desc[b].box[1], k.desc[b].box[2]};
+  const double iL[3] = {k.desc[b].inv_box[0], k.desc[b].inv_box[1], k.desc[b].inv_box[2]};
+  // own position relative to the O atom (minimum image within the molecule); every shuffle
+  // runs on all lanes (a lane that skips one leaves its value unreadable to the others)
+  double y[3];
+  for (int c = 0; c < 3; ++c) {
+    const double xo = __shfl(x[c], base, 64);
+    y[c] = a == 0 ? 0.0 : minimage(x[c] - xo, L[c], iL[c]);
+  }
+  double W[3], Y[3][3];
+  for (int q = 0; q < 3; ++q) {
+    W[q] = __shfl(w, base + q, 64);
+    for (int c = 0; c < 3; ++c) Y[q][c] = __shfl(y[c], base + q, 64);
+  }
+  const WaterCoupling cp(W);
+  double s[3][3];
+  bond_vectors(Y, s);  // the bond vectors at the current positions
   const double hdt = 0.5 * k.dt * kAccel;
 
   if constexpr ((PH & kEnd) != 0) {
-    for (int a = 0; a < NA; ++a)
-      for (int c = 0; c < 3; ++c) v[a][c] += hdt * f[a][c] * w[a];
-    if (k.thermostat) {
-      for (int a = 0; a < NA; ++a) {
-        const double3 z = normals(k, i + a, k.step_end, 1u);
-        const double sd_a = sqrt(k.noise_var * w[a]);
-        v[a][0] = k.c * v[a][0] + sd_a * z.x;
-        v[a][1] = k.c * v[a][1] + sd_a * z.y;
-        v[a][2] = k.c * v[a][2] + sd_a * z.z;
-      }
+    for (int c = 0; c < 3; ++c) v[c] += hdt * f[c] * w;
+    if (k.thermostat && valid) thermostat(k, v, w, o + a, k.step_end, 1u);
+    // velocity constraints: (v_i - v_j) . s_q = 0 for the three bonds
+    double V[3][3];
+    for (int q = 0; q < 3; ++q)
+      for (int c = 0; c < 3; ++c) V[q][c] = __shfl(v[c], base + q, 64);
+    const int P0[3] = {0, 0, 1}, P1[3] = {1, 2, 2};
+    double A[3][3], r[3], mu[3];
+    for (int q = 0; q < 3; ++q) {
+      double dv[3];
+      for (int c = 0; c < 3; ++c) dv[c] = V[P0[q]][c] - V[P1[q]][c];
+      r[q] = -dot3(dv, s[q]);
+      for (int p = 0; p < 3; ++p) A[q][p] = cp.C[q][p] * dot3(s[p], s[q]);
     }
-    if constexpr (NA == 3) {
-      // velocity constraints: (v_i - v_j) . s_q = 0 for the three bonds
-      const double (&ww)[3] = reinterpret_cast<const double (&)[3]>(w);
-      const WaterCoupling cp(ww);
-      double s[3][3];
-      bond_vectors(reinterpret_cast<const double (&)[3][3]>(y), s);
-      const int P0[3] = {0, 0, 1}, P1[3] = {1, 2, 2};
-      double A[3][3], r[3], mu[3];
-      for (int q = 0; q < 3; ++q) {
-        double dv[3];
-        for (int c = 0; c < 3; ++c) dv[c] = v[P0[q]][c] - v[P1[q]][c];
-        r[q] = -dot3(dv, s[q]);
-        for (int p = 0; p < 3; ++p) A[q][p] = cp.C[q][p] * dot3(s[p], s[q]);
-      }
-      solve3(A, r, mu);
-      apply_multipliers(reinterpret_cast<double (&)[3][3]>(v), ww, mu, s);
-    }
+    solve3(A, r, mu);
+    for (int c = 0; c < 3; ++c) v[c] += multiplier_move(a, w, mu, s, c);
   }
 
   if constexpr ((PH & kStart) != 0) {
-    if (k.thermostat) {
-      for (int a = 0; a < NA; ++a) {
-        const double3 z = normals(k, i + a, k.step_start, 0u);
-        const double sd_a = sqrt(k.noise_var * w[a]);
-        v[a][0] = k.c * v[a][0] + sd_a * z.x;
-        v[a][1] = k.c * v[a][1] + sd_a * z.y;
-        v[a][2] = k.c * v[a][2] + sd_a * z.z;
-      }
-    }
-    for (int a = 0; a < NA; ++a)
-      for (int c = 0; c < 3; ++c) v[a][c] += hdt * f[a][c] * w[a];
-    if constexpr (NA == 1) {
-      for (int c = 0; c < 3; ++c) x[0][c] += k.dt * v[0][c];
-    } else {
-      // positions: yc = y + dt v + w_a sum_p m_p sigma_pa s_p with the three lengths held
-      const double (&ww)[3] = reinterpret_cast<const double (&)[3]>(w);
-      const WaterCoupling cp(ww);
-      double s[3][3];
-      bond_vectors(reinterpret_cast<const double (&)[3][3]>(y), s);
-      const double d2[3] = {k.r_oh2, k.r_oh2, k.r_hh2};
-      double yu[3][3];
-      for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 3; ++c) yu[a][c] = y[a][c] + k.dt * v[a][c];
-      double m[3] = {0.0, 0.0, 0.0};
+    if (k.thermostat && valid) thermostat(k, v, w, o + a, k.step_start, 0u);
+    for (int c = 0; c < 3; ++c) v[c] += hdt * f[c] * w;
+    // positions: yc = y + dt v + w_a sum_p m_p sigma_pa s_p with the three lengths held
+    double YU[3][3];
+    for (int q = 0; q < 3; ++q)
+      for (int c = 0; c < 3; ++c) YU[q][c] = __shfl(y[c] + k.dt * v[c], base + q, 64);
+    const double d2[3] = {k.r_oh2, k.r_oh2, k.r_hh2};
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int it = 0; it < kNewtonMax; ++it) {
       double yc[3][3];
-      for (int it = 0; it < kNewtonMax; ++it) {
-        for (int a = 0; a < 3; ++a)
-          for (int c = 0; c < 3; ++c) yc[a][c] = yu[a][c];
-        apply_multipliers(yc, ww, m, s);
-        double u[3][3];
-        bond_vectors(yc, u);
-        double g[3], J[3][3], dm[3];
-        double worst = 0.0;
-        for (int q = 0; q < 3; ++q) {
-          g[q] = -(dot3(u[q], u[q]) - d2[q]);
-          worst = fmax(worst, fabs(g[q]) / d2[q]);
-          for (int p = 0; p < 3; ++p) J[q][p] = 2.0 * cp.C[q][p] * dot3(u[q], s[p]);
-        }
-        if (worst < 2e-15) break;
-        solve3(J, g, dm);
-        m[0] += dm[0];
-        m[1] += dm[1];
-        m[2] += dm[2];
+      for (int q = 0; q < 3; ++q)
+        for (int c = 0; c < 3; ++c) yc[q][c] = YU[q][c] + multiplier_move(q, W[q], m, s, c);
+      double u[3][3];
+      bond_vectors(yc, u);
+      double g[3], J[3][3], dm[3];
+      double worst = 0.0;
+      for (int q = 0; q < 3; ++q) {
+        g[q] = -(dot3(u[q], u[q]) - d2[q]);
+        worst = fmax(worst, fabs(g[q]) / d2[q]);
+        for (int p = 0; p < 3; ++p) J[q][p] = 2.0 * cp.C[q][p] * dot3(u[q], s[p]);
       }
-      for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 3; ++c) yc[a][c] = yu[a][c];
-      apply_multipliers(yc, ww, m, s);
-      const double inv_dt = 1.0 / k.dt;
-      for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 3; ++c) {
-          const double dx = yc[a][c] - y[a][c];
-          x[a][c] += dx;
-          v[a][c] = dx * inv_dt;
-        }
+      if (!(worst >= 2e-15)) break;  // converged (or not a number: nothing more to gain)
+      solve3(J, g, dm);
+      m[0] += dm[0];
+      m[1] += dm[1];
+      m[2] += dm[2];
     }
-    for (int a = 0; a < NA; ++a)
-      for (int c = 0; c < 3; ++c) k.pos[3 * (i + a) + c] = x[a][c];
+    const double inv_dt = 1.0 / k.dt;
+    for (int c = 0; c < 3; ++c) {
+      const double dx = YU[a][c] + multiplier_move(a, w, m, s, c) - y[c];
+      x[c] += dx;
+      v[c] = dx * inv_dt;
+    }
+    if (valid)
+      for (int c = 0; c < 3; ++c) k.pos[3 * (o + a) + c] = x[c];
   }
-  for (int a = 0; a < NA; ++a)
-    for (int c = 0; c < 3; ++c) k.vel[3 * (i + a) + c] = v[a][c];
+  if (valid)
+    for (int c = 0; c < 3; ++c) k.vel[3 * (o + a) + c] = v[c];
 }
 
+// Blocks [0, water_blocks) take the waters, 21 per wave (lanes 3u, 3u + 1, 3u + 2 for
+// water u; lane 63 idle); the other blocks take the free atoms, one thread per atom.
 template <int PH>
-__global__ void __launch_bounds__(kMdBlock) k_md_integrate(MdArgs k) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * kMdBlock + threadIdx.x;
-  if (i >= k.N) return;
-  const uint8_t r = k.role[i];
-  if (r == 2) return;  // a water H: its O's thread moves it
-  const int b = system_of(k.desc, k.B, i);
-  if (r == 1) integrate_unit<PH, 3>(k, i, b);
-  else integrate_unit<PH, 1>(k, i, b);
+__global__ void __launch_bounds__(kMdBlock) k_md_integrate(MdArgs k, unsigned water_blocks) {
+  if (blockIdx.x < water_blocks) {
+    const int lane = static_cast<int>(threadIdx.x) & 63;
+    const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kMdBlock + threadIdx.x) >> 6;
+    const int grp = lane / 3, a = lane - 3 * grp;
+    const int64_t w = wave * kWatersPerWave + grp;
+    bool valid = grp < kWatersPerWave && w < k.n_waters;
+    int64_t o = 0;
+    if (valid) {
+      o = k.water_o[w];
+      valid = o >= 0 && o + 2 < k.N && k.role[o] == 1;  // the waters k_md_roles accepted
+      if (!valid) o = 0;
+    }
+    integrate_water<PH>(k, o, a, 3 * grp, valid);
+    return;
+  }
+  const int64_t i = static_cast<int64_t>(blockIdx.x - water_blocks) * kMdBlock + threadIdx.x;
+  if (i >= k.N || k.role[i] != 0) return;  // water atoms are the water lanes' own
+  integrate_free<PH>(k, i);
 }
 
 // Clears the roles, the bonded forces, the energy accumulators and the MD status.
@@ -464,19 +497,49 @@ void setup(const MdPlan &mp, const Views &v, const nb_md_topology *topo, hipStre
                        topo->n_waters, v.d.desc, mp.p.B, N, v.md_status);
 }
 
+// The second stream of the reciprocal part and the two events that order it against
+// the main stream (fork after the positions are written, join before they are read
+// again).  Events are made per call and released when the call returns (HIP keeps them
+// until the work they mark completes).
+struct Aux {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  ~Aux() {
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+  }
+  hipError_t open(hipStream_t aux, hipStream_t main, bool pme) {
+    if (!aux || aux == main || !pme) return hipSuccess;
+    hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    if (e == hipSuccess) s = aux;
+    return e;
+  }
+};
+
 // Every force part at the system's positions; energies into the accumulators when asked.
+// With an auxiliary stream the reciprocal part runs there, beside the short-range work.
 hipError_t forces(const MdPlan &mp, const Views &v, const nb_system *sys, const nb_md_topology *topo, bool want_e,
-                  hipStream_t s, std::string *err) {
+                  hipStream_t s, const Aux &aux, std::string *err) {
   const int B = mp.p.B;
   double *e_nb = want_e ? v.energy : nullptr;
   double *e_corr = want_e ? v.energy + B : nullptr;
   double *e_rec = want_e ? v.energy + 2 * B : nullptr;
   double *e_bond = want_e ? v.energy + 3 * B : nullptr;
-  hipError_t e = launch_build(mp.p, v.d, sys, s);
+  hipError_t e = hipSuccess;
+  if (mp.ml.pme && aux.s) {
+    e = hipEventRecord(aux.fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(aux.s, aux.fork, 0);
+    if (e == hipSuccess)
+      e = launch_pme(mp.pl, sys, mp.p.beta, mp.p.ke, v.pme_ws, v.f_rec, e_rec, nullptr, aux.s, err);
+    if (e == hipSuccess) e = hipEventRecord(aux.join, aux.s);
+  }
+  if (e == hipSuccess) e = launch_build(mp.p, v.d, sys, s);
   if (e == hipSuccess) e = launch_forces(mp.p, v.d, sys, v.f_nb, e_nb, nullptr, s);
   if (e == hipSuccess && mp.ml.pme) {
     e = launch_ewald(mp.p, v.d, sys, v.f_corr, e_corr, nullptr, s);
-    if (e == hipSuccess) e = launch_pme(mp.pl, sys, mp.p.beta, mp.p.ke, v.pme_ws, v.f_rec, e_rec, nullptr, s, err);
+    if (e == hipSuccess && !aux.s)
+      e = launch_pme(mp.pl, sys, mp.p.beta, mp.p.ke, v.pme_ws, v.f_rec, e_rec, nullptr, s, err);
   }
   const int64_t nt = topo->n_bonds + topo->n_angles;
   if (e == hipSuccess && nt > 0) {
@@ -499,6 +562,7 @@ hipError_t forces(const MdPlan &mp, const Views &v, const nb_system *sys, const 
     hipLaunchKernelGGL(k_md_bonded, dim3(blocks_for(nt)), dim3(kMdBlock), 0, s, a);
     e = hipGetLastError();
   }
+  if (e == hipSuccess && mp.ml.pme && aux.s) e = hipStreamWaitEvent(s, aux.join, 0);
   return e;
 }
 
@@ -590,10 +654,12 @@ std::string md_check_topology(const MdPlan &mp, const nb_md_topology *t) {
 
 hipError_t md_forces(const MdPlan &mp, const nb_system *sys, const nb_md_topology *topo, const nb_md_params *md,
                      void *ws, double *force, double *energy, hipStream_t s, std::string *err) {
-  (void)md;
   const Views v = views(mp, ws);
+  Aux aux;
+  hipError_t e = aux.open(md->aux_stream, s, mp.ml.pme);
+  if (e != hipSuccess) return e;
   setup(mp, v, topo, s);
-  hipError_t e = forces(mp, v, sys, topo, energy != nullptr, s, err);
+  e = forces(mp, v, sys, topo, energy != nullptr, s, aux, err);
   if (e != hipSuccess) return e;
   const int64_t n3 = 3 * mp.p.N;
   if (n3 > 0)
@@ -609,8 +675,11 @@ hipError_t md_run(const MdPlan &mp, const nb_system *sys, const nb_md_topology *
                   void *ws, double *vel, int64_t first_step, int64_t n_steps, double *energy, hipStream_t s,
                   std::string *err) {
   const Views v = views(mp, ws);
+  Aux aux;
+  hipError_t e = aux.open(md->aux_stream, s, mp.ml.pme);
+  if (e != hipSuccess) return e;
   setup(mp, v, topo, s);
-  hipError_t e = forces(mp, v, sys, topo, energy != nullptr && n_steps == 0, s, err);
+  e = forces(mp, v, sys, topo, energy != nullptr && n_steps == 0, s, aux, err);
   MdArgs k;
   k.pos = static_cast<double *>(const_cast<void *>(sys->pos));
   k.vel = vel;
@@ -631,23 +700,28 @@ hipError_t md_run(const MdPlan &mp, const nb_system *sys, const nb_md_topology *
   k.key0 = static_cast<uint32_t>(md->seed);
   k.key1 = static_cast<uint32_t>(md->seed >> 32);
   k.thermostat = md->gamma > 0.0 ? 1 : 0;
-  const dim3 g(blocks_for(mp.p.N)), blk(kMdBlock);
+  k.water_o = topo->water_o;
+  k.n_waters = topo->n_waters;
+  constexpr int64_t kWatersPerBlock = kWatersPerWave * (kMdBlock / 64);
+  const unsigned wb = static_cast<unsigned>((topo->n_waters + kWatersPerBlock - 1) / kWatersPerBlock);
+  const dim3 g(wb + blocks_for(mp.p.N)), blk(kMdBlock);
   for (int64_t st = 0; st < n_steps && e == hipSuccess && mp.p.N > 0; ++st) {
     k.step_start = first_step + st;
     k.step_end = first_step + st - 1;
-    if (st == 0) hipLaunchKernelGGL(k_md_integrate<kStart>, g, blk, 0, s, k);
-    else hipLaunchKernelGGL(k_md_integrate<kEndStart>, g, blk, 0, s, k);
+    if (st == 0) hipLaunchKernelGGL(k_md_integrate<kStart>, g, blk, 0, s, k, wb);
+    else hipLaunchKernelGGL(k_md_integrate<kEndStart>, g, blk, 0, s, k, wb);
     e = hipGetLastError();
-    if (e == hipSuccess) e = forces(mp, v, sys, topo, energy != nullptr && st == n_steps - 1, s, err);
+    if (e == hipSuccess) e = forces(mp, v, sys, topo, energy != nullptr && st == n_steps - 1, s, aux, err);
   }
   if (e != hipSuccess) return e;
   if (n_steps > 0 && mp.p.N > 0) {
     k.step_end = first_step + n_steps - 1;
-    hipLaunchKernelGGL(k_md_integrate<kEnd>, g, blk, 0, s, k);
+    hipLaunchKernelGGL(k_md_integrate<kEnd>, g, blk, 0, s, k, wb);
   }
   if (energy) {
     if (mp.p.N > 0)
-      hipLaunchKernelGGL(k_md_kinetic, g, blk, 0, s, vel, topo->mass, v.d.desc, mp.p.B, mp.p.N, v.energy + 4 * mp.p.B);
+      hipLaunchKernelGGL(k_md_kinetic, dim3(blocks_for(mp.p.N)), blk, 0, s, vel, topo->mass, v.d.desc, mp.p.B, mp.p.N,
+                         v.energy + 4 * mp.p.B);
     hipLaunchKernelGGL(k_md_pack, dim3(blocks_for(5 * mp.p.B)), dim3(kMdBlock), 0, s, energy, v.energy, mp.p.B, 5);
   }
   hipLaunchKernelGGL(k_md_status, dim3(1), dim3(64), 0, s, v.d.status, v.md_status);

@@ -118,6 +118,7 @@ class nb_md_params(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("pme_grid", ctypes.c_int32 * 3),
         ("reserved", ctypes.c_int32),
+        ("aux_stream", ctypes.c_void_p),
     ]
 
 
@@ -426,12 +427,15 @@ def device_topology(topo: dict, device: str = "cuda") -> DeviceTopology:
 
 
 def make_md_params(dt: float, temperature: float = 300.0, gamma: float = 1.0, seed: int = 1,
-                   pme_grid=(0, 0, 0)) -> nb_md_params:
+                   pme_grid=(0, 0, 0), aux_stream=None) -> nb_md_params:
+    """aux_stream: None, or a torch.cuda.Stream for the reciprocal part (run concurrently)."""
     m = nb_md_params()
     m.dt, m.temperature, m.gamma, m.seed = float(dt), float(temperature), float(gamma), int(seed)
     for a in range(3):
         m.pme_grid[a] = int(pme_grid[a])
     m.reserved = 0
+    m.aux_stream = None if aux_stream is None else int(aux_stream.cuda_stream)
+    m._aux = aux_stream  # keeps the stream alive as long as the params
     return m
 
 

@@ -74,13 +74,16 @@ def test_md_forces_match_oracle(precision, ff):
     assert got[3] == pytest.approx(e["bonded"], rel=1e-11)
 
 
+@pytest.mark.parametrize("aux", [False, True])
 @pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
-def test_md_steps_match_oracle(precision):
+def test_md_steps_match_oracle(precision, aux):
     """One step, then four more in a second call (the trajectory continues), against the
-    oracle's steps with the same noise: PME, switch, thermostat, waters and the chain."""
+    oracle's steps with the same noise: PME (on the caller's stream, or on a second stream
+    beside the short-range work), switch, thermostat, waters and the chain."""
     s = U.small_chain()
-    _print_case("md_steps", precision=precision, n=s.n)
-    md = H.make_md_params(0.002, 300.0, 5.0, seed=0x1234_5678_9ABC, pme_grid=GRID_SMALL)
+    _print_case("md_steps", precision=precision, aux=aux, n=s.n)
+    md = H.make_md_params(0.002, 300.0, 5.0, seed=0x1234_5678_9ABC, pme_grid=GRID_SMALL,
+                          aux_stream=torch.cuda.Stream() if aux else None)
     b, p, t, ws, topo = _setup(s, precision, md, **FF)
     rng = np.random.default_rng(21)
     v0 = rng.standard_normal((s.n, 3)) * 4.0
@@ -114,7 +117,7 @@ def test_md_thermostat_and_rigid_water_at_4fs():
     stay rigid and nothing is flagged."""
     s = U.cached_config(2)
     _print_case("md_cfg2_4fs", n=s.n)
-    md = H.make_md_params(0.004, 300.0, 5.0, seed=99, pme_grid=GRID_CFG2)
+    md = H.make_md_params(0.004, 300.0, 5.0, seed=99, pme_grid=GRID_CFG2, aux_stream=torch.cuda.Stream())
     b, p, t, ws, topo = _setup(s, H.NB_MIXED, md, **FF)
     vel = torch.zeros((s.n, 3), dtype=torch.float64, device="cuda")
     energy = torch.empty(5, dtype=torch.float64, device="cuda")
