@@ -31,7 +31,7 @@ HBM_PEAK_GBPS = 8000.0    # MI355X published HBM3E bandwidth
 # for force + energy + virial (FMA = 2 flops; rsqrt, reciprocal and exp2 not counted).
 FLOPS_PER_PAIR = 72
 # Counter summary (FETCH_SIZE / WRITE_SIZE, calibrated) of the default mixed pair kernel.
-PAIR_PROFILE = "pair_cluster8_23k_mixed_pmc.md"
+PAIR_PROFILE = "pair_half8_23k_mixed_pmc.md"
 
 
 def log(msg):
