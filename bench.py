@@ -163,6 +163,19 @@ def pme_rate(b, p, prec_name, steps, torch, H, grid=PME_GRID):
 PAIR_SOURCES = ("nb_pair_cluster.h", "nb_pair_cluster_f32.hip", "nb_pair_math.h", "nb_pair_common.h", "nb_internal.h")
 
 
+def pair_source_hash():
+    """First 16 hex digits of the SHA-256 of the pair-kernel sources with their comments
+    and blank space removed: changes with the code, not with its comments."""
+    h = hashlib.sha256()
+    for f in PAIR_SOURCES:
+        with open(os.path.join(ROOT, "paper_0902_0827_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].strip()
+                if code:
+                    h.update(code.encode() + b"\n")
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(profile):
     """HBM bytes per pair-kernel launch from a committed counter summary, or None when
     the pair-kernel sources have changed since those counters were taken."""
@@ -171,11 +184,7 @@ def measured_traffic(profile):
         return None
     kv = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line and
               line.split(": ", 1)[0] in ("source_sha256_16", "fetch_bytes_per_launch", "write_bytes_per_launch"))
-    h = hashlib.sha256()
-    for f in PAIR_SOURCES:
-        with open(os.path.join(ROOT, "paper_0902_0827_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    if kv.get("source_sha256_16") != h.hexdigest()[:16]:
+    if kv.get("source_sha256_16") != pair_source_hash():
         return None
     return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
 

@@ -19,14 +19,16 @@
 //   3. each row of J lanes accumulates its i atom's sums in registers; rows are
 //      reduced with cross-lane shuffles at the end.
 //
-// By default each cluster is one work item, and its wave writes the per-atom results
-// in the caller's atom order itself.  A cluster's candidates may instead be split
-// over Q work items (Q = 2..8): each writes its part of every atom's sums to its own
-// slot, and k_finish adds the Q parts in a fixed order and converts them to the
-// caller's atom order.  k_finish also reduces energies, virials and per-type sums.
-// Nothing is accumulated with atomics: results are deterministic.  Full shell (every
-// pair is evaluated from both sides), as in the paper; the half-shell variant is
-// described with the kernel.
+// Full shell (every pair evaluated from both sides, as in the paper): by default each
+// cluster is one work item, and its wave writes the per-atom results in the caller's
+// atom order itself.  A cluster's candidates may instead be split over Q work items
+// (Q = 2..8): each writes its part of every atom's sums to its own slot, and k_finish
+// adds the Q parts in a fixed order and converts them to the caller's atom order.
+// k_finish also reduces energies, virials and per-type sums.  Nothing is accumulated
+// with atomics: results are deterministic.  The half-shell form (each pair once; the
+// mixed path's default for forces and energies) is described with the kernel: its
+// candidates' shares go to per-atom accumulators by atomics, in 64-bit fixed point on
+// the mixed path so that the sums stay deterministic.
 #pragma once
 
 #include <map>
