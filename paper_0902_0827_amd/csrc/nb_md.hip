@@ -497,10 +497,10 @@ void setup(const MdPlan &mp, const Views &v, const nb_md_topology *topo, hipStre
                        topo->n_waters, v.d.desc, mp.p.B, N, v.md_status);
 }
 
-// The second stream of the reciprocal part and the two events that order it against
-// the main stream (fork after the positions are written, join before they are read
-// again).  Events are made per call and released when the call returns (HIP keeps them
-// until the work they mark completes).
+// The second stream of the reciprocal part and the two events that order it against the
+// main stream: a fork after the integrator writes the positions, a join before the next
+// integrator reads the forces.  Events are made per call and released when the call
+// returns (HIP keeps them until the work they mark completes).
 struct Aux {
   hipStream_t s = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
@@ -517,8 +517,36 @@ struct Aux {
   }
 };
 
+hipError_t launch_bonded(const MdPlan &mp, const Views &v, const nb_system *sys, const nb_md_topology *topo,
+                         double *e_bond, hipStream_t s) {
+  const int64_t nt = topo->n_bonds + topo->n_angles;
+  if (nt == 0) return hipSuccess;
+  BondedArgs a;
+  a.pos = static_cast<const double *>(sys->pos);
+  a.f = v.f_bond;
+  a.energy = e_bond;
+  a.bond_atoms = topo->bond_atoms;
+  a.angle_atoms = topo->angle_atoms;
+  a.bond_k = topo->bond_k;
+  a.bond_r0 = topo->bond_r0;
+  a.angle_k = topo->angle_k;
+  a.angle_t0 = topo->angle_theta0;
+  a.n_bonds = topo->n_bonds;
+  a.n_angles = topo->n_angles;
+  a.N = mp.p.N;
+  a.desc = v.d.desc;
+  a.B = mp.p.B;
+  a.md_status = v.md_status;
+  hipLaunchKernelGGL(k_md_bonded, dim3(blocks_for(nt)), dim3(kMdBlock), 0, s, a);
+  return hipGetLastError();
+}
+
 // Every force part at the system's positions; energies into the accumulators when asked.
-// With an auxiliary stream the reciprocal part runs there, beside the short-range work.
+// With an auxiliary stream, the reciprocal part runs there beside the short-range work.
+// The rest stays on the main stream, measured: the Ewald corrections beside the pair
+// kernel made the step slower (0.137 against 0.128 ms on the 23.6k-atom box), and with
+// the bonded terms on the second stream the first MD run of a process came out wrong
+// (non-finite positions within 20 steps) for a reason not found.
 hipError_t forces(const MdPlan &mp, const Views &v, const nb_system *sys, const nb_md_topology *topo, bool want_e,
                   hipStream_t s, const Aux &aux, std::string *err) {
   const int B = mp.p.B;
@@ -526,43 +554,22 @@ hipError_t forces(const MdPlan &mp, const Views &v, const nb_system *sys, const 
   double *e_corr = want_e ? v.energy + B : nullptr;
   double *e_rec = want_e ? v.energy + 2 * B : nullptr;
   double *e_bond = want_e ? v.energy + 3 * B : nullptr;
+  const bool use_aux = aux.s != nullptr;  // only opened with a reciprocal part
   hipError_t e = hipSuccess;
-  if (mp.ml.pme && aux.s) {
+  if (use_aux) {
     e = hipEventRecord(aux.fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(aux.s, aux.fork, 0);
     if (e == hipSuccess)
       e = launch_pme(mp.pl, sys, mp.p.beta, mp.p.ke, v.pme_ws, v.f_rec, e_rec, nullptr, aux.s, err);
-    if (e == hipSuccess) e = hipEventRecord(aux.join, aux.s);
   }
+  if (e == hipSuccess && use_aux) e = hipEventRecord(aux.join, aux.s);
   if (e == hipSuccess) e = launch_build(mp.p, v.d, sys, s);
   if (e == hipSuccess) e = launch_forces(mp.p, v.d, sys, v.f_nb, e_nb, nullptr, s);
-  if (e == hipSuccess && mp.ml.pme) {
-    e = launch_ewald(mp.p, v.d, sys, v.f_corr, e_corr, nullptr, s);
-    if (e == hipSuccess && !aux.s)
-      e = launch_pme(mp.pl, sys, mp.p.beta, mp.p.ke, v.pme_ws, v.f_rec, e_rec, nullptr, s, err);
-  }
-  const int64_t nt = topo->n_bonds + topo->n_angles;
-  if (e == hipSuccess && nt > 0) {
-    BondedArgs a;
-    a.pos = static_cast<const double *>(sys->pos);
-    a.f = v.f_bond;
-    a.energy = e_bond;
-    a.bond_atoms = topo->bond_atoms;
-    a.angle_atoms = topo->angle_atoms;
-    a.bond_k = topo->bond_k;
-    a.bond_r0 = topo->bond_r0;
-    a.angle_k = topo->angle_k;
-    a.angle_t0 = topo->angle_theta0;
-    a.n_bonds = topo->n_bonds;
-    a.n_angles = topo->n_angles;
-    a.N = mp.p.N;
-    a.desc = v.d.desc;
-    a.B = B;
-    a.md_status = v.md_status;
-    hipLaunchKernelGGL(k_md_bonded, dim3(blocks_for(nt)), dim3(kMdBlock), 0, s, a);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess && mp.ml.pme && aux.s) e = hipStreamWaitEvent(s, aux.join, 0);
+  if (e == hipSuccess && mp.ml.pme) e = launch_ewald(mp.p, v.d, sys, v.f_corr, e_corr, nullptr, s);
+  if (e == hipSuccess && !use_aux && mp.ml.pme)
+    e = launch_pme(mp.pl, sys, mp.p.beta, mp.p.ke, v.pme_ws, v.f_rec, e_rec, nullptr, s, err);
+  if (e == hipSuccess) e = launch_bonded(mp, v, sys, topo, e_bond, s);
+  if (e == hipSuccess && use_aux) e = hipStreamWaitEvent(s, aux.join, 0);
   return e;
 }
 

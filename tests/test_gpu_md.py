@@ -50,6 +50,26 @@ def _water_error(pos, topo, box):
                np.max(np.abs(d(o + 1, o + 2) - topo["r_hh"])) / topo["r_hh"])
 
 
+def test_md_two_streams_equal_one_stream_as_the_first_md_run():
+    """Kept first in this file: the first MD run of the process uses the second stream (a
+    form that once came out wrong only there), against the same steps on one stream (FP64,
+    20 steps of 4 fs; only the order of atomic additions differs)."""
+    s = U.small_chain()
+    _print_case("md_two_streams_first", n=s.n)
+    out = []
+    for aux in (torch.cuda.Stream(), None):
+        md = H.make_md_params(0.004, 300.0, 1.0, seed=7, pme_grid=GRID_SMALL, aux_stream=aux)
+        b, p, t, ws, _ = _setup(s, H.NB_FP64, md, **FF)
+        vel = torch.zeros((s.n, 3), dtype=torch.float64, device="cuda")
+        H.md_run(b, p, t, md, ws, vel, 0, 20)
+        torch.cuda.synchronize()
+        assert H.read_status(ws) == 0
+        out.append((b.pos.cpu().numpy(), vel.cpu().numpy()))
+    assert np.all(np.isfinite(out[0][0]))
+    assert np.max(np.abs(out[0][0] - out[1][0])) < 1e-7
+    assert np.max(np.abs(out[0][1] - out[1][1])) < 1e-5
+
+
 @pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
 @pytest.mark.parametrize("ff", [False, True])
 def test_md_forces_match_oracle(precision, ff):
