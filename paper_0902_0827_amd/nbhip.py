@@ -21,7 +21,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libnbhip.so")
+# NBHIP_LIB selects another build of the library (the host-sanitizer build of the CPU tests)
+LIB_PATH = os.environ.get("NBHIP_LIB") or os.path.join(_HERE, "libnbhip.so")
 
 # Coulomb constant k_e = e^2 N_A / (4 pi eps0), CODATA 2018, kJ mol^-1 A e^-2.
 COULOMB_K = 1389.35457644382
