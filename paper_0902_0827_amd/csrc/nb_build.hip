@@ -13,8 +13,8 @@
 //               double-precision positions only when the FP64 path will read them)
 //
 // When the cell counts fit in LDS the scan and the scatter are one launch
-// (k_scan_scatter), each workgroup scanning the counts itself, and the last one the
-// columns.  Larger grids scan in two launches (k_scan_tiles, k_scan_apply); their
+// (k_scan_scatter), each workgroup scanning the counts itself, and one more workgroup
+// (the last, without atoms) the columns.  Larger grids scan in two launches (k_scan_tiles, k_scan_apply); their
 // column counts are written by k_scatter and scanned by the first workgroup of
 // k_finalize.  Empty batches take k_scan (one workgroup).
 //
@@ -647,7 +647,9 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
     hipLaunchKernelGGL(k_bin<float>, dim3(g), dim3(kBlock), 0, s, d, static_cast<const float *>(sys->pos),
                        sys->type, sys->excl_offset, sys->excl_index, sys->pair14_offset, sys->pair14_index);
   if (plan.n_cells + 1 <= kFuseCells) {
-    const unsigned gs = grid_for(plan.N, kScanBlock);
+    // one workgroup per kScanBlock atoms, and for the cluster kernels one more that scans
+    // the column cluster counts (beside the scatter, not after one workgroup's share of it)
+    const unsigned gs = grid_for(plan.N, kScanBlock) + (clusters ? 1u : 0u);
     hipLaunchKernelGGL(k_scan_scatter, dim3(gs), dim3(kScanBlock), 4 * static_cast<size_t>(plan.n_cells + 1), s, d,
                        clusters, plan.cluster_size);
   } else {
