@@ -227,16 +227,39 @@ __device__ inline void fold_row(const Dev &d, uint4 *masks, const int32_t *__res
   const int n_sys = sd.atom_end - sd.atom_begin;
   const int il = i - sd.atom_begin;
   uint32_t own0 = 0u, own1 = 0u, own2 = 0u, own3 = 0u;
-  for (int k = lo; k < hi; ++k) {
-    const int jl = idx[k];
-    if (jl < 0 || jl >= n_sys) {
-      set_status(d, NB_STATUS_BAD_EXCLUSION);
-      continue;
+  // Entries in batches of kFoldBatch, each stage's loads independent of one another (the
+  // row's partners, then their row bounds, then the first kFoldScan entries of their rows),
+  // so that a row costs a few dependent load latencies instead of one per load.
+  constexpr int kFoldBatch = 4, kFoldScan = 4;
+  for (int k0 = lo; k0 < hi; k0 += kFoldBatch) {
+    int j[kFoldBatch], jlo[kFoldBatch], jhi[kFoldBatch];
+    bool win[kFoldBatch], listed[kFoldBatch];
+#pragma unroll
+    for (int u = 0; u < kFoldBatch; ++u) j[u] = k0 + u < hi ? idx[k0 + u] : -1;
+#pragma unroll
+    for (int u = 0; u < kFoldBatch; ++u) {
+      const int jl = j[u];
+      const bool real = k0 + u < hi;
+      const bool ok = jl >= 0 && jl < n_sys;
+      if (real && !ok) set_status(d, NB_STATUS_BAD_EXCLUSION);
+      j[u] = ok ? sd.atom_begin + jl : i;  // a bad or missing entry acts as j = i (skipped)
+      const int delta = j[u] - i;
+      win[u] = delta != 0 && delta >= -kWindow && delta <= kWindow;
+      if (ok && delta != 0 && !win[u]) far(j[u]);
+      jlo[u] = win[u] ? off[j[u]] : 0;
+      jhi[u] = win[u] ? off[j[u] + 1] : 0;
+      listed[u] = false;
     }
-    const int j = sd.atom_begin + jl;
-    const int delta = j - i;
-    if (delta == 0) continue;
-    if (delta >= -kWindow && delta <= kWindow) {
+#pragma unroll
+    for (int q = 0; q < kFoldScan; ++q)
+#pragma unroll
+      for (int u = 0; u < kFoldBatch; ++u)
+        if (jlo[u] + q < jhi[u]) listed[u] = listed[u] || idx[jlo[u] + q] == il;
+#pragma unroll
+    for (int u = 0; u < kFoldBatch; ++u) {
+      if (!win[u]) continue;
+      for (int q = jlo[u] + kFoldScan; q < jhi[u] && !listed[u]; ++q) listed[u] = idx[q] == il;  // long rows
+      const int delta = j[u] - i;
       const int bit = delta < 0 ? delta + kWindow : delta + kWindow - 1;
       const uint32_t m = 1u << (bit & 31);
       const int ws = bit >> 5;
@@ -244,12 +267,7 @@ __device__ inline void fold_row(const Dev &d, uint4 *masks, const int32_t *__res
       own1 |= ws == 1 ? m : 0u;
       own2 |= ws == 2 ? m : 0u;
       own3 |= ws == 3 ? m : 0u;
-      const int jlo = off[j], jhi = off[j + 1];
-      bool listed = false;
-      for (int q = jlo; q < jhi && !listed; ++q) listed = idx[q] == il;
-      if (!listed) window_set(masks, j, -delta);
-    } else {
-      far(j);
+      if (!listed[u]) window_set(masks, j[u], -delta);
     }
   }
   unsigned int *w = reinterpret_cast<unsigned int *>(&masks[i]);
@@ -285,8 +303,10 @@ __global__ void k_bin(Dev d, const Real *__restrict__ pos, const int32_t *__rest
   for (int a = 0; a < 3; ++a)
     c[a] = static_cast<int>((static_cast<uint64_t>(u[a]) * static_cast<uint64_t>(sd.dims[a])) >> 32);
   const int cell = sd.cell_begin + (c[0] * sd.dims[1] + c[1]) * sd.dims[2] + c[2];
+  // the arrival slot is stored last, so that the exclusion rows' loads below are issued
+  // while the atomic is in flight instead of after it has returned
+  const int slot = atomicAdd(&d.cell_count[cell], 1);
   d.atom_cell[i] = cell;
-  d.atom_slot[i] = atomicAdd(&d.cell_count[cell], 1);
   d.atom_fix[i] = make_uint4(u[0], u[1], u[2], static_cast<uint32_t>(b));
   const int t = type[i];
   if (t < 0 || t >= d.T) set_status(d, NB_STATUS_BAD_TYPE);
@@ -301,6 +321,7 @@ __global__ void k_bin(Dev d, const Real *__restrict__ pos, const int32_t *__rest
   // Scaled 1-4 pairs: the paper's bitmaps hold them within the window only; a farther one
   // is reported and left unscaled.
   if (d.p14_mask) fold_row(d, d.p14_mask, p14_off, p14_idx, i, sd, [&](int) { set_status(d, NB_STATUS_FAR_PAIR14); });
+  d.atom_slot[i] = slot;
 }
 
 // Exclusive scan of count(0 .. n-1) into store(k, prefix) for k < n and store(n, total),
