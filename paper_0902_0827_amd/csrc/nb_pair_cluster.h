@@ -689,7 +689,9 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     // FAR and VIR: the cluster may have far exclusions, the virial may be wanted (both
     // then tested at run time).  The two-group loop has a copy for each combination, so
     // that a pair of groups of the common case is one basic block.
-    auto process_group = [&](int navail, auto far_c, auto vir_c) {
+    // CHECK: test the half-shell stage's room for this group (false: the caller made room
+    // for it beforehand, so that two groups in a row form one basic block).
+    auto process_group = [&](int navail, auto far_c, auto vir_c, auto check_c) {
       constexpr bool FAR = decltype(far_c)::value;
       constexpr bool VIR = decltype(vir_c)::value;
       // head is a multiple of J (only an item's last group is partial) and J divides
@@ -896,7 +898,9 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         // The J candidates' shares: sums over the K rows (K consecutive lanes), staged by row 0.
         if constexpr (MODE == kForces) {
           const auto cx = group_sum<K>(-hgx), cy = group_sum<K>(-hgy), cz = group_sum<K>(-hgz);
-          if (nst + J > kStage<F64>) flush();
+          if constexpr (decltype(check_c)::value) {
+            if (nst + J > kStage<F64>) flush();
+          }
           if (ii == 0 && jv) {
             StageT<F64> &st = ST[nst + jj];
             st.x = cx;
@@ -908,7 +912,9 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         } else if constexpr (MODE == kEnergy) {
           if (o.atom_energy) {  // per-atom energies: half of each pair's energy to j
             const auto cu = group_sum<K>(hu);
-            if (nst + J > kStage<F64>) flush();
+            if constexpr (decltype(check_c)::value) {
+              if (nst + J > kStage<F64>) flush();
+            }
             if (ii == 0 && jv) {
               StageT<F64> &st = ST[nst + jj];
               st.x = static_cast<decltype(st.x)>(0.5) * cu;
@@ -927,11 +933,14 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     auto drain_with = [&](auto far_c, auto vir_c) {
       if constexpr (!F64 && PAIRS2) {
         while (tail - head >= 2u * static_cast<uint32_t>(J)) {
-          process_group(J, far_c, vir_c);
-          process_group(J, far_c, vir_c);
+          if constexpr (HALF) {
+            if (nst + 2 * J > kStage<F64>) flush();  // room for both groups' shares
+          }
+          process_group(J, far_c, vir_c, std::false_type{});
+          process_group(J, far_c, vir_c, std::false_type{});
         }
       }
-      while (tail - head >= static_cast<uint32_t>(J)) process_group(J, far_c, vir_c);
+      while (tail - head >= static_cast<uint32_t>(J)) process_group(J, far_c, vir_c, std::true_type{});
     };
     auto drain = [&]() {
       if constexpr (F64 || (!PAIRS2 && !HALF)) {
@@ -1044,8 +1053,8 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       vj = vj_n;
     }
     if (tail != head) {
-      if (any_far) process_group(static_cast<int>(tail - head), std::true_type{}, std::true_type{});
-      else process_group(static_cast<int>(tail - head), std::false_type{}, std::true_type{});
+      if (any_far) process_group(static_cast<int>(tail - head), std::true_type{}, std::true_type{}, std::true_type{});
+      else process_group(static_cast<int>(tail - head), std::false_type{}, std::true_type{}, std::true_type{});
     }
     if (dynamic && !requested && !(closed & (1u << home))) {  // an item without candidates
       pending = request(home);
@@ -1372,7 +1381,7 @@ void launch_cluster_mode(int mode, bool half, int var, int64_t wgs, int dyn, int
   // the GPU at once at 4 waves per SIMD: then the fifth resident wave has nothing to do
   // and the instruction-level parallelism of two groups is worth more (23.6k-atom box:
   // 64.2 -> 61.0 us; 64-replica batch, 100,000 items: 1,083 against 1,117 us with it).
-  const bool pairs2 = !F64 && !half && !dyn && wgs <= static_cast<int64_t>(compute_units()) * kPairs2WavesPerCu;
+  const bool pairs2 = !F64 && !dyn && wgs <= static_cast<int64_t>(compute_units()) * kPairs2WavesPerCu;
   auto dispatch = [&](auto var_c) {
     constexpr int VAR = decltype(var_c)::value;
     using M0 = std::integral_constant<int, kForces>;
@@ -1380,7 +1389,8 @@ void launch_cluster_mode(int mode, bool half, int var, int64_t wgs, int dyn, int
     using M2 = std::integral_constant<int, kAdjoint>;
     using M3 = std::integral_constant<int, kVJP>;
     if (mode == kForces) {
-      if (half) go(k_pair_cluster<F64, kForces, TABLDS, K, true, false, VAR>, M0{}, std::true_type{});
+      if (half && pairs2) go(k_pair_cluster<F64, kForces, TABLDS, K, true, !F64, VAR>, M0{}, std::true_type{});
+      else if (half) go(k_pair_cluster<F64, kForces, TABLDS, K, true, false, VAR>, M0{}, std::true_type{});
       else if (pairs2) go(k_pair_cluster<F64, kForces, TABLDS, K, false, !F64, VAR>, M0{}, std::false_type{});
       else go(k_pair_cluster<F64, kForces, TABLDS, K, false, false, VAR>, M0{}, std::false_type{});
     } else if (mode == kEnergy) {
