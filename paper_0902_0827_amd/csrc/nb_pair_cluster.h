@@ -345,8 +345,8 @@ __device__ __forceinline__ int xcd_id() {
 // vary from run to run.
 //
 // PAIRS2 (mixed path): the group loop takes two groups per pass, which needs more
-// registers (4 resident waves per SIMD instead of 5); the launcher uses it when every
-// item fits on the GPU at once at that occupancy.
+// registers (held to 128, 4 resident waves per SIMD instead of 5); the launcher uses it
+// when every item fits on the GPU at once at that occupancy.
 // Variants of the pair evaluation (template parameter VAR).
 constexpr int kVarPlain = 0;  // direct evaluation
 constexpr int kVarFF = 1;     // direct, with the LJ switch and scaled 1-4 pairs
@@ -354,7 +354,7 @@ constexpr int kVarLin = 2;    // radial terms linearly interpolated from tables 
 constexpr int kVarCub = 3;    // radial terms from cubic Hermite tables (mixed forces / energy)
 
 template <bool F64, int MODE, bool TABLDS, int K, bool HALF, bool PAIRS2, int VAR>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? kF64WavesPerEu : 1, 8)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((F64 || PAIRS2) ? kF64WavesPerEu : 1, 8)))
 k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   // Products are fused into additions only within one expression (the explicit FMAs
   // aside), so that the copies of the group loop, and the instantiations with one or two
