@@ -125,7 +125,9 @@ constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
 constexpr int kDppHalfMirror = 0x141; // row_half_mirror
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  // every lane of a row reads a lane of its row (full masks), so "old" and bound_ctrl never
+  // take effect: with old = 0 and bound_ctrl set the move folds into the addition
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -673,9 +675,9 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         const StageT<F64> st = ST[e];
         if constexpr (MODE == kForces) {
           if (st.x != 0 || st.y != 0 || st.z != 0) {  // a candidate without a pair in range adds nothing
-            acc_add(0, st.s, static_cast<double>(st.x) * scx);
-            acc_add(1, st.s, static_cast<double>(st.y) * scy);
-            acc_add(2, st.s, static_cast<double>(st.z) * scz);
+            acc_add(0, st.s, static_cast<double>(st.x) * -scx);  // staged: the rows' sums (plus sign)
+            acc_add(1, st.s, static_cast<double>(st.y) * -scy);
+            acc_add(2, st.s, static_cast<double>(st.z) * -scz);
           }
         } else if (st.x != 0) {
           acc_add(3, st.s, static_cast<double>(st.x));
@@ -897,7 +899,8 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       if constexpr (HALF) {
         // The J candidates' shares: sums over the K rows (K consecutive lanes), staged by row 0.
         if constexpr (MODE == kForces) {
-          const auto cx = group_sum<K>(-hgx), cy = group_sum<K>(-hgy), cz = group_sum<K>(-hgz);
+          // the candidates' shares are minus these sums: the sign is applied at the flush
+          const auto cx = group_sum<K>(hgx), cy = group_sum<K>(hgy), cz = group_sum<K>(hgz);
           if constexpr (decltype(check_c)::value) {
             if (nst + J > kStage<F64>) flush();
           }
