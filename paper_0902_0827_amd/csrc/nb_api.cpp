@@ -198,6 +198,11 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   l.p14_mask = p.has14 ? take(16 * static_cast<size_t>(N)) : 0;
   l.rtab = p.table ? take(16 * static_cast<size_t>(p.table_n + 1) * static_cast<size_t>(p.table)) : 0;
   l.vsort = take(32 * static_cast<size_t>(N));
+  // one record per launch slot of the cluster kernels' static grid (at least one round of 8)
+  p.n_item_slots = std::max<int64_t>(cluster_waves, kXcds);
+  l.items = take(sizeof(ItemRec) * static_cast<size_t>(p.n_item_slots));
+  l.col_info = take(16 * static_cast<size_t>(columns));
+  l.atom_col = take(4 * static_cast<size_t>(N));
   l.total = o;
   *plan = std::move(p);
   return NB_OK;
@@ -241,6 +246,10 @@ Dev dev_view(const Plan &p, void *ws) {
   d.p14_mask = p.has14 ? reinterpret_cast<uint4 *>(base + l.p14_mask) : nullptr;
   d.rtab = p.table ? reinterpret_cast<float4 *>(base + l.rtab) : nullptr;
   d.vsort = reinterpret_cast<double4 *>(base + l.vsort);
+  d.items = reinterpret_cast<ItemRec *>(base + l.items);
+  d.n_item_slots = p.n_item_slots;
+  d.col_info = reinterpret_cast<int4 *>(base + l.col_info);
+  d.atom_col = reinterpret_cast<int32_t *>(base + l.atom_col);
   const bool half = p.kernel == NB_KERNEL_CLUSTER_HALF;
   d.jacc_fix = half && p.precision == NB_MIXED ? reinterpret_cast<long long *>(base + l.jacc) : nullptr;
   d.jacc_f64 = half && p.precision == NB_FP64 ? reinterpret_cast<double *>(base + l.jacc) : nullptr;

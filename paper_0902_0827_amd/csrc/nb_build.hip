@@ -10,13 +10,16 @@
 //   k_scatter   atom -> cell_start[cell] + slot (order inside a cell still arbitrary)
 //   k_finalize  rank inside the cell by original index (makes the sort stable and the
 //               result deterministic) and write the sorted per-atom records (the raw
-//               double-precision positions only when the FP64 path will read them)
+//               double-precision positions only when the FP64 path will read them); for
+//               the cluster kernels also the work item of every launch slot (ItemRec),
+//               from the atoms that begin and end each cluster
 //
 // When the cell counts fit in LDS the scan and the scatter are one launch
 // (k_scan_scatter), each workgroup scanning the counts itself, and one more workgroup
 // (the last, without atoms) the columns.  Larger grids scan in two launches (k_scan_tiles, k_scan_apply); their
 // column counts are written by k_scatter and scanned by the first workgroup of
-// k_finalize.  Empty batches take k_scan (one workgroup).
+// k_finalize, and the work items by k_item_records after it.  Empty batches take k_scan
+// (one workgroup).
 //
 // Positions become 32-bit box fractions u = floor(x/L * 2^32) mod 2^32, which wraps
 // every coordinate into the box; the 32-bit difference of two such values is the
@@ -154,7 +157,7 @@ __device__ inline void table_node(const Dev &d, const TableArgs &ta, int k) {
 }
 
 __global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, const double *__restrict__ eps,
-                       int kernel, int f64, TableArgs ta) {
+                       int kernel, int f64, TableArgs ta, uint32_t cluster_key) {
   const int64_t tid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   if (tid < c.count) d.desc[c.first + tid] = unpack_desc(c.d[tid]);
@@ -163,7 +166,11 @@ __global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, con
     d.status[1] = kBuiltMagic;
     d.status[2] = static_cast<uint32_t>(d.N);
     d.status[3] = (uses_clusters(kernel) ? kBuiltClusters : 0u) | (f64 ? kBuiltF64 : 0u) | ((d.jacc_fix || d.jacc_f64) ? kBuiltJacc : 0u);
+    d.status[4] = cluster_key;
   }
+  // work-item slots start empty; the build fills those that have an item
+  if (cluster_key)
+    for (int64_t k = tid; k < d.n_item_slots; k += stride) d.items[k].count = 0;
   if (tid < kXcds) d.queue[tid * kQueueStride] = 0u;
   for (int64_t k = tid; k < d.n_cells; k += stride) d.cell_count[k] = 0;
   for (int64_t k = tid; k < d.N; k += stride) {
@@ -307,6 +314,7 @@ __global__ void k_bin(Dev d, const Real *__restrict__ pos, const int32_t *__rest
   // while the atomic is in flight instead of after it has returned
   const int slot = atomicAdd(&d.cell_count[cell], 1);
   d.atom_cell[i] = cell;
+  d.atom_col[i] = sd.col_begin + c[0] * sd.dims[1] + c[1];
   d.atom_fix[i] = make_uint4(u[0], u[1], u[2], static_cast<uint32_t>(b));
   const int t = type[i];
   if (t < 0 || t >= d.T) set_status(d, NB_STATUS_BAD_TYPE);
@@ -409,28 +417,41 @@ __device__ inline void block_scan(Count count, Store store, int64_t n, int *lds)
   if (threadIdx.x == 0) store(n, run);
 }
 
+// The record of column col for the work-item records: its first cell, its sorted atoms
+// [first, end) and cx | cy << 16.
+__device__ inline int4 column_info(int c0, int s0, int s1, int col_local, int ny) {
+  const int cx = col_local / ny;
+  return make_int4(c0, s0, s1, cx | ((col_local - cx * ny) << 16));
+}
+
 // Clusters of K atoms in column `col` (ceil of its atom count over K), from cell starts
-// held in `cs` (any address space).  A single system's descriptor is read once.
+// held in `cs` (any address space); also stores the column's col_info record.  A single
+// system's descriptor is read once.
 struct ColumnClusters {
   const SysDesc *desc;
+  int4 *info;
   int B, K;
-  int cell_begin0, col_begin0, nz0;
-  __device__ ColumnClusters(const Dev &d, int k) : desc(d.desc), B(d.B), K(k) {
+  int cell_begin0, col_begin0, ny0, nz0;
+  __device__ ColumnClusters(const Dev &d, int k) : desc(d.desc), info(d.col_info), B(d.B), K(k) {
     cell_begin0 = d.desc[0].cell_begin;
     col_begin0 = d.desc[0].col_begin;
+    ny0 = d.desc[0].dims[1];
     nz0 = d.desc[0].dims[2];
   }
   template <typename Starts>
   __device__ int operator()(const Starts &cs, int col) const {
-    int cb = cell_begin0, cbeg = col_begin0, nz = nz0;
+    int cb = cell_begin0, cbeg = col_begin0, ny = ny0, nz = nz0;
     if (B > 1) {
       const SysDesc &sd = desc[column_system(desc, B, col)];
       cb = sd.cell_begin;
       cbeg = sd.col_begin;
+      ny = sd.dims[1];
       nz = sd.dims[2];
     }
     const int c0 = cb + (col - cbeg) * nz;
-    return (cs[c0 + nz] - cs[c0] + K - 1) / K;
+    const int s0 = cs[c0], s1 = cs[c0 + nz];
+    info[col] = column_info(c0, s0, s1, col - cbeg, ny);
+    return (s1 - s0 + K - 1) / K;
   }
 };
 
@@ -504,17 +525,18 @@ constexpr int kColSysLds = 2048;  // systems whose column ranges the column scan
 // col_clu_start (k_finalize scans it in place): a column's system is found by a binary
 // search over the systems' first columns, held in LDS for up to kColSysLds systems.
 __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int clusters, int K) {
-  __shared__ int sys_col[kColSysLds], sys_cell[kColSysLds], sys_nz[kColSysLds];
+  __shared__ int sys_col[kColSysLds], sys_cell[kColSysLds], sys_ny[kColSysLds], sys_nz[kColSysLds];
   const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (clusters && static_cast<int64_t>(blockIdx.x) * kBlock < d.n_columns) {  // workgroup-uniform
     const int B = d.B;
     const int col = static_cast<int>(t);
     const bool in = t < d.n_columns;
-    int cb, cbeg, nz;
+    int cb, cbeg, ny, nz;
     if (B <= kColSysLds) {
       for (int b = threadIdx.x; b < B; b += kBlock) {
         sys_col[b] = d.desc[b].col_begin;
         sys_cell[b] = d.desc[b].cell_begin;
+        sys_ny[b] = d.desc[b].dims[1];
         sys_nz[b] = d.desc[b].dims[2];
       }
       __syncthreads();
@@ -525,30 +547,79 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int clusters, int K) 
       }
       cb = sys_cell[lo];
       cbeg = sys_col[lo];
+      ny = sys_ny[lo];
       nz = sys_nz[lo];
     } else {
       const SysDesc &sd = d.desc[in ? column_system(d.desc, B, col) : 0];
       cb = sd.cell_begin;
       cbeg = sd.col_begin;
+      ny = sd.dims[1];
       nz = sd.dims[2];
     }
     if (in) {
       const int c0 = cb + (col - cbeg) * nz;
-      d.col_clu_start[col] = (d.cell_start[c0 + nz] - d.cell_start[c0] + K - 1) / K;
+      const int s0 = d.cell_start[c0], s1 = d.cell_start[c0 + nz];
+      d.col_clu_start[col] = (s1 - s0 + K - 1) / K;
+      d.col_info[col] = column_info(c0, s0, s1, col - cbeg, ny);
     }
   }
   if (t >= d.N) return;
   d.tmp[d.cell_start[d.atom_cell[t]] + d.atom_slot[t]] = static_cast<int32_t>(t);
 }
 
+// Work-item records of the clusters that begin or end at sorted atom p (in cell `cell`
+// of global column col, system b), once col_info and col_clu_start are complete (M: the
+// work-item count): a cluster's first atom writes the record of each of its Q items but
+// the last atom's z-cell, which its last atom writes.  The column's and the system's
+// loads are issued together.
+__device__ inline void item_records(const Dev &d, int p, int cell, int col, int b, int K, int Q, int64_t M) {
+  const int4 ci = d.col_info[col];
+  const int clu0 = d.col_clu_start[col];
+  const SysDesc &sd = d.desc[b];
+  const int4 dims = make_int4(sd.dims[0], sd.dims[1], sd.dims[2], sd.reach[0]);
+  const int ky = sd.reach[1], kz = sd.reach[2], cell_begin = sd.cell_begin;
+  // (the system's values are used below only by a cluster's first atom: this keeps their
+  // loads beside the column's instead of after the test)
+  asm volatile("" ::"v"(dims.x), "v"(dims.y), "v"(dims.z), "v"(dims.w), "v"(ky), "v"(kz), "v"(cell_begin), "v"(clu0));
+  const int j = p - ci.y;
+  const bool head = j % K == 0, tail = j % K == K - 1 || p == ci.z - 1;
+  if (!head && !tail) return;
+  const int I = clu0 + j / K;
+  const int z = cell - ci.x;
+  for (int q = 0; q < Q; ++q) {
+    const int m = I * Q + q;
+    ItemRec &r = d.items[item_slot(m, M)];
+    if (head) {
+      int4 *w = reinterpret_cast<int4 *>(&r);
+      w[0] = make_int4(p, ci.z - p < K ? ci.z - p : K, m, b);
+      w[1] = make_int4(ci.w & 0xFFFF, ci.w >> 16, z, cell_begin);
+      w[2] = dims;
+      r.ky = ky;
+      r.kz = kz;
+    }
+    if (tail) r.cz1 = z;
+  }
+}
+
+// Large grids, cluster kernels: the work-item records, one thread per sorted atom, after
+// k_finalize has scanned the column cluster counts.
+__global__ void __launch_bounds__(kBlock) k_item_records(Dev d, int K, int Q) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= d.N) return;
+  const int64_t M = static_cast<int64_t>(d.col_clu_start[d.n_columns]) * Q;
+  const int i = static_cast<int>(d.s_fix[p].w);
+  item_records(d, p, d.atom_cell[i], d.atom_col[i], static_cast<int>(d.atom_fix[i].w), K, Q, M);
+}
+
 // With col_scan (large grids, cluster kernel) the first workgroup turns the column
 // cluster counts written by k_scatter into their exclusive scan, in place, while the
-// others place the atoms.
+// others place the atoms.  With K > 0 (cluster kernel, column starts complete) every
+// atom that begins or ends a cluster also writes the records of its work items.
 template <typename Real>
 __global__ void __launch_bounds__(kBlock) k_finalize(Dev d, const Real *__restrict__ pos,
                                                     const Real *__restrict__ charge,
                                                     const int32_t *__restrict__ type, double sqrt_ke, int f64,
-                                                    int have_range, int col_scan) {
+                                                    int have_range, int col_scan, int K, int Q) {
   if (col_scan && blockIdx.x == 0) {
     __shared__ int lds[block_scan_lds<kScanPer, kBlock>()];
     int32_t *ccs = d.col_clu_start;
@@ -559,16 +630,18 @@ __global__ void __launch_bounds__(kBlock) k_finalize(Dev d, const Real *__restri
   const int s = (blockIdx.x - col_scan) * kBlock + threadIdx.x;
   if (s >= d.N) return;
   const int i = d.tmp[s];
+  const int64_t M = K > 0 ? static_cast<int64_t>(d.col_clu_start[d.n_columns]) * Q : 0;
   // The cell's positions: stored per position by the fused scatter (one load away), or
   // looked up through the atom's cell.  (For large batches the extra scattered store
   // costs more than the two dependent loads it saves.)
   int lo, hi;
+  const int cell = (K > 0 || !have_range) ? d.atom_cell[i] : 0;
+  const int col = K > 0 ? d.atom_col[i] : 0;
   if (have_range) {
     const int2 cr = d.s_range[s];
     lo = cr.x;
     hi = cr.y;
   } else {
-    const int cell = d.atom_cell[i];
     lo = d.cell_start[cell];
     hi = d.cell_start[cell + 1];
   }
@@ -585,6 +658,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(Dev d, const Real *__restri
   d.s_q32[dst] = static_cast<float>(q * sqrt_ke);
   int t = type[i];
   d.s_type[dst] = (t < 0 || t >= d.T) ? 0 : t;
+  if (K > 0) item_records(d, dst, cell, col, static_cast<int>(f.w), K, Q, M);
 }
 
 // Scan and scatter in one launch, for grids whose cell counts fit in LDS: every
@@ -646,8 +720,11 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
     ta.two_beta_sqrtpi = 2.0 * plan.beta / 1.7724538509055160273;
     ta.short_erfc = plan.beta * plan.cutoff <= kErfcxShortMax ? 1 : 0;
   }
+  const int clusters = uses_clusters(plan.kernel) ? 1 : 0;
+  const uint32_t cluster_key =
+      clusters ? static_cast<uint32_t>(plan.cluster_size) | (static_cast<uint32_t>(plan.split) << 8) : 0u;
   hipLaunchKernelGGL(k_init, dim3(g_init), dim3(kBlock), 0, s, d, first, sys->lj_sigma, sys->lj_eps, plan.kernel, f64,
-                     ta);
+                     ta, cluster_key);
   for (int b0 = kDescChunk; b0 < plan.B; b0 += kDescChunk) {
     DescChunk c{};
     c.first = b0;
@@ -655,7 +732,6 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
     for (int k = 0; k < c.count; ++k) c.d[k] = pack_desc(plan.desc[b0 + k]);
     hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, c);
   }
-  const int clusters = uses_clusters(plan.kernel) ? 1 : 0;
   if (plan.N == 0) {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, s, d, clusters, plan.cluster_size);
     return hipGetLastError();
@@ -684,12 +760,18 @@ hipError_t launch_build(const Plan &plan, const Dev &d, const nb_system *sys, hi
   const int have_range = plan.n_cells + 1 <= kFuseCells ? 1 : 0;  // written by k_scan_scatter
   const int col_scan = (!have_range && clusters) ? 1 : 0;           // column counts written by k_scatter
   const unsigned gf = g + static_cast<unsigned>(col_scan);
+  // work items written by k_finalize when the column starts are complete before it
+  const int rec_k = clusters && !col_scan ? plan.cluster_size : 0;
   if (sys->pos_is_f64)
     hipLaunchKernelGGL(k_finalize<double>, dim3(gf), dim3(kBlock), 0, s, d, static_cast<const double *>(sys->pos),
-                       static_cast<const double *>(sys->charge), sys->type, sqrt_ke, f64, have_range, col_scan);
+                       static_cast<const double *>(sys->charge), sys->type, sqrt_ke, f64, have_range, col_scan, rec_k,
+                       plan.split);
   else
     hipLaunchKernelGGL(k_finalize<float>, dim3(gf), dim3(kBlock), 0, s, d, static_cast<const float *>(sys->pos),
-                       static_cast<const float *>(sys->charge), sys->type, sqrt_ke, f64, have_range, col_scan);
+                       static_cast<const float *>(sys->charge), sys->type, sqrt_ke, f64, have_range, col_scan, rec_k,
+                       plan.split);
+  if (clusters && col_scan)
+    hipLaunchKernelGGL(k_item_records, dim3(g), dim3(kBlock), 0, s, d, plan.cluster_size, plan.split);
   return hipGetLastError();
 }
 

@@ -31,16 +31,47 @@ __host__ __device__ __forceinline__ bool uses_clusters(int kernel) {
 }
 
 // Workspace header words: status[0] = NB_STATUS_* bits, status[1] = kBuiltMagic,
-// status[2] = atom count, status[3] = what was built (kBuiltClusters | kBuiltF64 | kBuiltJacc).
+// status[2] = atom count, status[3] = what was built (kBuiltClusters | kBuiltF64 | kBuiltJacc),
+// status[4] = cluster size | work items per cluster << 8 of the cluster arrays (0 without them).
 constexpr uint32_t kBuiltClusters = 1u;  // column cluster arrays (cluster kernels)
 constexpr uint32_t kBuiltF64 = 2u;       // double-precision sorted positions (FP64 kernels)
 constexpr uint32_t kBuiltJacc = 4u;      // zeroed half-shell accumulators
+// Words 1-4 are written by the build only, so a later kernel reads them through the
+// constant address space: four scalar loads issued together, and no test waits on
+// another's load.
 __device__ __forceinline__ bool built_for(const uint32_t *status, int64_t n_atoms, bool need_clusters,
-                                          bool need_f64, bool need_jacc = false) {
-  return status[1] == kBuiltMagic && status[2] == static_cast<uint32_t>(n_atoms) &&
-         (!need_clusters || (status[3] & kBuiltClusters)) && (!need_f64 || (status[3] & kBuiltF64)) &&
-         (!need_jacc || (status[3] & kBuiltJacc));
+                                          bool need_f64, bool need_jacc = false, uint32_t cluster_key = 0u) {
+  using ConstU32 = const __attribute__((address_space(4))) uint32_t;
+  ConstU32 *w = (ConstU32 *)status;
+  const uint32_t magic = w[1], n = w[2], what = w[3], key = w[4];
+  const bool ok = (magic == kBuiltMagic) & (n == static_cast<uint32_t>(n_atoms)) &
+                  (!need_clusters | ((what & kBuiltClusters) != 0u)) & (!need_f64 | ((what & kBuiltF64) != 0u)) &
+                  (!need_jacc | ((what & kBuiltJacc) != 0u)) & ((cluster_key == 0u) | (key == cluster_key));
+  return ok;
 }
+
+// Cluster kernels: the M work items are cut into kXcds contiguous ranges, range x being
+// [xcd_range_lo(M, x), xcd_range_lo(M, x + 1)), and launch slot kXcds k + x takes item k
+// of range x (workgroups are dealt to the XCDs round robin, and each XCD has its own L2,
+// so that an XCD works on a compact region of space).
+__host__ __device__ __forceinline__ int xcd_range_lo(int64_t M, int x) {
+  return static_cast<int>((M * x) / kXcds);
+}
+__host__ __device__ inline int item_slot(int m, int64_t M) {
+  int x = kXcds - 1;
+  while (x > 0 && xcd_range_lo(M, x) > m) --x;
+  return kXcds * (m - xcd_range_lo(M, x)) + x;
+}
+
+// The work item of one launch slot of the cluster kernels, written by the build: what a
+// wave needs before it loads its atoms and its neighbour columns' windows, in one 64-byte
+// scalar load.  count 0: the slot has no item.
+struct alignas(64) ItemRec {
+  int32_t first, count, item, sys;  // first sorted atom, atoms, item index m, system
+  int32_t cx, cy, cz0, cell_begin;  // column, z-cell of the first atom, the system's first cell
+  int32_t nx, ny, nz, kx;           // the system's cell grid, stencil reach in x
+  int32_t ky, kz, cz1, pad;         // stencil reach in y and z, z-cell of the last atom
+};
 
 // Per-system descriptor, resident in the workspace.  Sorted atoms of system b are
 // [atom_begin, atom_end) (the sort keeps systems in order), its cells are
@@ -66,7 +97,7 @@ struct alignas(16) TypePair32 { float c6, c12, inv_sig, pad; };
 struct Layout {
   size_t status, desc, tab64, tab32, cell_count, cell_start, atom_cell, atom_slot, atom_fix, tmp, s_range, scan_tiles;
   size_t s_fix, s_pos64, s_q32, s_type, excl_mask, excl_far, partials, adj_partials;
-  size_t col_clu_start, part, queue, jacc, p14_mask, rtab, vsort;
+  size_t col_clu_start, part, queue, jacc, p14_mask, rtab, vsort, items, col_info, atom_col;
   size_t total;
 };
 
@@ -90,6 +121,7 @@ struct Plan {
   // Tabulated variant: 0 direct, 1 linear, 2 cubic Hermite radial tables of table_n intervals.
   int table = 0, table_n = 0;
   int64_t n_cells = 0, n_blocks = 0, n_clusters_max = 0, n_columns = 0;
+  int64_t n_item_slots = 0;  // cluster kernels: launch slots (work items, upper bound, a multiple of 8)
   std::vector<SysDesc> desc;
   Layout lay{};
 };
@@ -128,6 +160,12 @@ struct Dev {
   int64_t n_columns;
   int64_t n_clusters_max;
   uint32_t *queue;         // [kXcds * kQueueStride] work counters of the dynamic schedule
+  ItemRec *items;          // [n_item_slots] the work item of each launch slot (cluster kernels)
+  int64_t n_item_slots;
+  // Cluster kernels, for the work-item records: per (x, y) column its first cell, its sorted
+  // atoms [first, end) and cx | cy << 16; per atom (original order) its global column.
+  int4 *col_info;          // [n_columns]
+  int32_t *atom_col;       // [N]
   // Half-shell cluster kernel: per sorted atom, force x, y, z and energy share, as four
   // arrays of N (component-major, so that the atomic additions of consecutive atoms
   // coalesce), added up by atomics; zero outside a force or energy call (the build zeroes

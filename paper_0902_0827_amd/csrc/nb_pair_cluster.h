@@ -316,6 +316,19 @@ __device__ __forceinline__ int xcd_id() {
   return static_cast<int>(__builtin_amdgcn_s_getreg((20) | (0 << 6) | (15 << 11))) & (kXcds - 1);
 }
 
+// A work item's record, read through the constant address space: the kernel never writes
+// the records, and wave-uniform loads from it are scalar loads into scalar registers.
+__device__ __forceinline__ ItemRec load_item(const ItemRec *items, int slot) {
+  using ConstInt = const __attribute__((address_space(4))) int32_t;
+  ConstInt *q = (ConstInt *)(items + slot);
+  ItemRec r;
+  r.first = q[0], r.count = q[1], r.item = q[2], r.sys = q[3];
+  r.cx = q[4], r.cy = q[5], r.cz0 = q[6], r.cell_begin = q[7];
+  r.nx = q[8], r.ny = q[9], r.nz = q[10], r.kx = q[11];
+  r.ky = q[12], r.kz = q[13], r.cz1 = q[14], r.pad = 0;
+  return r;
+}
+
 // Work item m = (cluster m / Q, part m % Q): part q evaluates the cluster's i atoms
 // against the q-th of Q equal shares of its candidate j atoms (the atoms of the
 // neighbouring columns' z-windows, in run order).  Items of one cluster are
@@ -324,8 +337,11 @@ __device__ __forceinline__ int xcd_id() {
 //
 // The items are cut into 8 contiguous ranges, one per XCD (workgroups are dealt to
 // the XCDs round robin, and each XCD has its own L2).  Every wave (one per workgroup)
-// first takes one item of its XCD's range by its workgroup index.  With the static
-// schedule the grid covers every item and that is all.  With the dynamic schedule the
+// first takes one item of its XCD's range by its workgroup index: the build has written
+// each launch slot's item record (first atom, atom count, column, z-cells, the system's
+// grid), so that a wave starts with one scalar load instead of searching the columns
+// and the cell starts for its cluster.  With the static schedule the grid covers every
+// item and that is all.  With the dynamic schedule the
 // grid is what fits on the GPU at once and each range continues through an atomic
 // counter: a wave that finishes takes the next item of its own XCD's range, requested
 // while the previous item is evaluated, and once that range is exhausted the next
@@ -375,7 +391,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   __shared__ WaveLds<F64, FF> L;
   TypePairLds<F64, MODE> *const TL = reinterpret_cast<TypePairLds<F64, MODE> *>(tab_lds);
   const int lane = static_cast<int>(threadIdx.x);
-  if (!built_for(d.status, d.N, true, F64, HALF)) {
+  if (!built_for(d.status, d.N, true, F64, HALF, static_cast<uint32_t>(K) | (static_cast<uint32_t>(Q) << 8))) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(d.status, NB_STATUS_NOT_BUILT);
     return;
   }
@@ -398,6 +414,11 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       L.ring[k].sidx = make_int2(0, 0);
     }
   }
+  // Every wave first takes the item of its own launch slot (the build wrote each slot's
+  // record); the record's load is issued before the type-pair table's, so that the two
+  // are in flight together.
+  int islot = static_cast<int>(blockIdx.x);
+  ItemRec rec = load_item(d.items, islot);
   if constexpr (TABLDS) {
     for (int k = lane; k < T * T; k += 64) {
       if constexpr (F64 && !ADJ) TL[k] = make_double2(d.tab64[k].c6, d.tab64[k].c12);
@@ -406,28 +427,28 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     }
     wave_lds_sync();
   }
-  const int n_clu = uni(d.col_clu_start[d.n_columns]);
-  const int M = n_clu * Q;
-  auto range_lo = [M](int x) { return static_cast<int>((static_cast<int64_t>(M) * x) / kXcds); };
+  // The dynamic schedule continues through the counters, and only it needs the item count M.
+  const int64_t M = dynamic ? static_cast<int64_t>(uni(d.col_clu_start[d.n_columns])) * Q : 0;
+  auto range_lo = [M](int x) { return xcd_range_lo(M, x); };
   const int per = static_cast<int>(gridDim.x) / kXcds;  // static items per range (grid: multiple of 8)
-  const int bx = static_cast<int>(blockIdx.x) & (kXcds - 1);
-  int m = range_lo(bx) + static_cast<int>(blockIdx.x) / kXcds;
-  if (m >= range_lo(bx + 1)) m = -1;
 
-  // Dynamic items: queue x hands out range_lo(x) + per + counter_x.
+  // Dynamic items: queue x hands out item range_lo(x) + per + counter_x, slot 8 (per + counter_x) + x.
   const int home = dynamic ? xcd_id() : 0;
-  uint32_t closed = 0;  // queues known to be exhausted (wave-uniform bit mask)
-  for (int x = 0; x < kXcds; ++x)  // ranges the static round covers entirely have no dynamic items
-    if (!dynamic || range_lo(x) + per >= range_lo(x + 1)) closed |= 1u << x;
+  uint32_t closed = 0xFFu;  // queues known to be exhausted (wave-uniform bit mask)
+  if (dynamic) {
+    closed = 0u;
+    for (int x = 0; x < kXcds; ++x)  // ranges the static round covers entirely have no dynamic items
+      if (range_lo(x) + per >= range_lo(x + 1)) closed |= 1u << x;
+  }
   auto request = [&](int x) -> uint32_t {
     uint32_t got = 0;
     if (lane == 0) got = atomicAdd(&d.queue[x * kQueueStride], 1u);
     return got;
   };
-  auto item_of = [&](int x, uint32_t got) -> int {
+  auto slot_of = [&](int x, uint32_t got) -> int {
     const int g = uni(static_cast<int>(got));
-    const int it = range_lo(x) + per + g;
-    return (g >= 0 && it < range_lo(x + 1)) ? it : -1;
+    const int k = per + g;
+    return (g >= 0 && range_lo(x) + k < range_lo(x + 1)) ? kXcds * k + x : -1;
   };
   // Next item once the speculative request on the home queue has failed: probe every
   // counter (one load per lane), mark the exhausted ones, request from the nearest open
@@ -441,7 +462,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       if (closed == 0xFFu) break;
       int x = home;
       while (closed & (1u << x)) x = (x + 1) & (kXcds - 1);
-      const int it = item_of(x, request(x));
+      const int it = slot_of(x, request(x));
       if (it >= 0) return it;
       closed |= 1u << x;
     }
@@ -450,21 +471,13 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   uint32_t pending = 0;
   bool have_pending = false;
 
-  while (m >= 0) {
-    // (Q is uniform; with one item per cluster the divisions below are skipped)
-    const int I = Q == 1 ? m : m / Q, part = Q == 1 ? 0 : m - (m / Q) * Q;
-
-    // The cluster: its column, system, and atoms.
-    const int col = cluster_column(d.col_clu_start, static_cast<int>(d.n_columns), I);
-    int sys = 0;
-    {
-      int lo = 0, hi = d.B - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (d.desc[mid].col_begin <= col) lo = mid; else hi = mid - 1;
-      }
-      sys = lo;
-    }
+  for (;;) {
+    // The item: its cluster is K consecutive sorted atoms of one column from `first` on
+    // (count of them), its share part of Q of their candidates.
+    int count = uni(rec.count), m = uni(rec.item), sys = uni(rec.sys), first = uni(rec.first);
+    if (count == 0) break;  // a slot without an item (the last ones of a range)
+    // (Q is uniform; with one item per cluster the division below is skipped)
+    const int part = Q == 1 ? 0 : m - (m / Q) * Q;
     const SysDesc &sd = d.desc[sys];
     // Per-system constants as wave-uniform scalars: nothing in the pair loop below then
     // waits on a vector-memory load (so the next chunk's loads stay in flight).
@@ -472,13 +485,8 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     const double bxx = uni(sd.box[0]), bxy = uni(sd.box[1]), bxz = uni(sd.box[2]);
     const double ibx = uni(sd.inv_box[0]), iby = uni(sd.inv_box[1]), ibz = uni(sd.inv_box[2]);
     const int atom_begin = uni(sd.atom_begin);
-    const int nx = uni(sd.dims[0]), ny = uni(sd.dims[1]), nz = uni(sd.dims[2]);
-    const int col_local = col - uni(sd.col_begin);
-    const int cell_begin = uni(sd.cell_begin);
-    const int cb0 = cell_begin + col_local * nz;
-    const int first = uni(d.cell_start[cb0] + K * (I - d.col_clu_start[col]));
-    const int left = uni(d.cell_start[cb0 + nz]) - first;
-    const int count = left < K ? left : K;
+    const int nx = uni(rec.nx), ny = uni(rec.ny), nz = uni(rec.nz);
+    const int cell_begin = uni(rec.cell_begin);
     const int i = first + ii;
     const bool ivalid = ii < count;
     const int ia = ivalid ? i : first;
@@ -542,10 +550,9 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       half = make_uint4(uni(static_cast<int>(hh[0])), uni(static_cast<int>(hh[1])), uni(static_cast<int>(hh[2])), 0u);
     }
 
-    const int kx = uni(sd.reach[0]), ky = uni(sd.reach[1]), kz = uni(sd.reach[2]);
-    const int cx = col_local / ny, cy = col_local - (col_local / ny) * ny;
-    const int cz0 = static_cast<int>((static_cast<uint64_t>(__shfl(fi.z, 0, 64)) * nz) >> 32);
-    const int cz1 = static_cast<int>((static_cast<uint64_t>(__shfl(fi.z, (count - 1) * (HALF ? 1 : J), 64)) * nz) >> 32);
+    // the column, and the z-cells of the cluster's first and last atom
+    const int kx = uni(rec.kx), ky = uni(rec.ky), kz = uni(rec.kz);
+    const int cx = uni(rec.cx), cy = uni(rec.cy), cz0 = uni(rec.cz0), cz1 = uni(rec.cz1);
     const bool allx = 2 * kx + 1 >= nx, ally = 2 * ky + 1 >= ny;
     const bool allz = (cz1 - cz0) + 2 * kz + 1 >= nz;
     const int xn = allx ? nx : 2 * kx + 1, yn = ally ? ny : 2 * ky + 1;
@@ -1166,15 +1173,18 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         }
       }
     }
-    m = -1;
-    if (dynamic) {
-      if (have_pending) {
-        m = item_of(home, pending);
-        have_pending = false;
-        if (m < 0) closed |= 1u << home;
-      }
-      if (m < 0) m = steal();
+    // The next item (dynamic schedule): the loop leaves before its end when there is none,
+    // so that no record stays live from one item to the next.
+    if (!dynamic) break;
+    islot = -1;
+    if (have_pending) {
+      islot = slot_of(home, pending);
+      have_pending = false;
+      if (islot < 0) closed |= 1u << home;
     }
+    if (islot < 0) islot = steal();
+    if (islot < 0) break;
+    rec = load_item(d.items, islot);
   }
 }
 
