@@ -104,25 +104,37 @@ __device__ __forceinline__ int shfl_rows_max(int v) {
   return v;
 }
 
-// Min / max over the K lanes of one aligned group of consecutive lanes (the rows of the
-// half-shell kernel's lane layout).
-template <int K>
-__device__ __forceinline__ int shfl_group_min(int v) {
-  for (int off = 1; off < K; off <<= 1) v = min(v, __shfl_xor(v, off, 64));
-  return v;
-}
-
-template <int K>
-__device__ __forceinline__ int shfl_group_max(int v) {
-  for (int off = 1; off < K; off <<= 1) v = max(v, __shfl_xor(v, off, 64));
-  return v;
-}
-
 // Cross-lane moves within DPP rows (no LDS): lane l reads lane l ^ 1, l ^ 2, or 7 - (l % 8)
 // of its 8-lane half row.
 constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
 constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
 constexpr int kDppHalfMirror = 0x141; // row_half_mirror
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+
+// Min / max over the K = 4 or 8 lanes of one aligned group of consecutive lanes (the
+// rows of the half-shell kernel's lane layout), by DPP moves: after the two quad
+// exchanges each lane holds its quad's extreme, and the half-row mirror pairs the two
+// quads of an 8-lane group.
+template <int K>
+__device__ __forceinline__ int shfl_group_min(int v) {
+  static_assert(K == 4 || K == 8, "groups of 4 or 8 lanes");
+  v = min(v, dpp_i32<kDppXor1>(v));
+  v = min(v, dpp_i32<kDppXor2>(v));
+  if constexpr (K == 8) v = min(v, dpp_i32<kDppHalfMirror>(v));
+  return v;
+}
+
+template <int K>
+__device__ __forceinline__ int shfl_group_max(int v) {
+  static_assert(K == 4 || K == 8, "groups of 4 or 8 lanes");
+  v = max(v, dpp_i32<kDppXor1>(v));
+  v = max(v, dpp_i32<kDppXor2>(v));
+  if constexpr (K == 8) v = max(v, dpp_i32<kDppHalfMirror>(v));
+  return v;
+}
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v) {
   // every lane of a row reads a lane of its row (full masks), so "old" and bound_ctrl never
@@ -540,10 +552,11 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       const uint32_t base3[3] = {u0.x, u0.y, u0.z};
       uint32_t cc[3], hh[3];
       for (int a = 0; a < 3; ++a) {
-        const int64_t mid = (static_cast<int64_t>(lo3[a]) + hi3[a]) >> 1;  // floor
-        const int64_t h = (hi3[a] - mid) > (mid - lo3[a]) ? (hi3[a] - mid) : (mid - lo3[a]);
-        cc[a] = base3[a] + static_cast<uint32_t>(static_cast<int32_t>(mid));
-        hh[a] = static_cast<uint32_t>(h);
+        // centre floor((lo + hi) / 2) and half-width max(hi - mid, mid - lo) = ceil(extent / 2),
+        // from the extent hi - lo in 32 bits (it is below 2^32)
+        const uint32_t ext = static_cast<uint32_t>(hi3[a]) - static_cast<uint32_t>(lo3[a]);
+        cc[a] = base3[a] + static_cast<uint32_t>(lo3[a]) + (ext >> 1);
+        hh[a] = (ext >> 1) + (ext & 1u);
       }
       // wave-uniform (every row reduced to the same box): keep it in scalar registers
       ctr = make_uint4(uni(static_cast<int>(cc[0])), uni(static_cast<int>(cc[1])), uni(static_cast<int>(cc[2])), 0u);
@@ -568,20 +581,27 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     // then j = i, then mask bits 64-127 (j - i = 1..64); word m holds bits 4m..4m+3 of
     // that 132-bit string, each spread to the low bit of a byte.
     // FF variants: bit 1 of each byte from the 1-4 window, whose self position is 0.
-    for (int m = jj; (!F64 || FF) && m < kExBytes / 4; m += J) {
-      const int w = m >> 3;
-      auto spread = [&](const uint4 &mk, uint32_t self) -> uint32_t {
-        const uint32_t src = w == 0 ? mk.x
-                           : w == 1 ? mk.y
-                           : w == 2 ? (mk.z << 1) | self
-                           : w == 3 ? (mk.w << 1) | (mk.z >> 31)
-                                    : mk.w >> 31;
-        const uint32_t nib = (src >> ((m & 7) * 4)) & 15u;
-        return (nib * 0x00204081u) & 0x01010101u;
+    // Lane jj takes words jj, jj + J, ...: pass t reads 32-bit piece (jj + J t) >> 3 of the
+    // string, which is t for every lane when J = 8 and 2 t or 2 t + 1 when J = 16.
+    if constexpr (!F64 || FF) {
+      static_assert(J == 8 || J == 16, "8 or 16 lanes per row");
+      auto piece = [](const uint4 &mk, uint32_t self, int w) -> uint32_t {
+        return w == 0 ? mk.x : w == 1 ? mk.y : w == 2 ? (mk.z << 1) | self : w == 3 ? (mk.w << 1) | (mk.z >> 31) : mk.w >> 31;
       };
-      uint32_t word = spread(mask_i, 1u);
-      if constexpr (FF) word |= spread(mask14_i, 0u) << 1;
-      if constexpr (!F64 || FF) L.exw[ii * (kExBytes / 4) + m] = word;
+#pragma unroll
+      for (int t = 0; t < (kExBytes / 4 + J - 1) / J; ++t) {
+        const int m = jj + J * t;
+        const int w0 = (J / 8) * t, w1 = w0 + 1 < 4 ? w0 + 1 : 4;  // the pass's pieces
+        const bool second = J == 16 && (jj & 8);
+        auto spread = [&](const uint4 &mk, uint32_t self) -> uint32_t {
+          const uint32_t src = second ? piece(mk, self, w1) : piece(mk, self, w0);
+          const uint32_t nib = (src >> ((m & 7) * 4)) & 15u;
+          return (nib * 0x00204081u) & 0x01010101u;
+        };
+        uint32_t word = spread(mask_i, 1u);
+        if constexpr (FF) word |= spread(mask14_i, 0u) << 1;
+        if (m < kExBytes / 4) L.exw[ii * (kExBytes / 4) + m] = word;
+      }
     }
     for (int k0 = 0; k0 < ncol; k0 += 64) {
       const int k = k0 + lane;
@@ -1184,7 +1204,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     }
     if (islot < 0) islot = steal();
     if (islot < 0) break;
-    rec = load_item(d.items, islot);
+    rec = load_item(d.items, uni(islot));
   }
 }
 
