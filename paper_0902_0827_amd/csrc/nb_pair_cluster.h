@@ -928,6 +928,9 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         if constexpr (MODE == kForces) {
           // the candidates' shares are minus these sums: the sign is applied at the flush
           const auto cx = group_sum<K>(hgx), cy = group_sum<K>(hgy), cz = group_sum<K>(hgz);
+          // (summed in every lane, before the row-0 test: the last DPP move then folds into its
+          // addition instead of being a move of its own beside an addition under the test)
+          if constexpr (!F64) asm volatile("" ::"v"(cx), "v"(cy), "v"(cz));
           if constexpr (decltype(check_c)::value) {
             if (nst + J > kStage<F64>) flush();
           }
