@@ -63,8 +63,9 @@ typedef enum {
 #define NB_STATUS_BAD_TYPE 0x2u       /* a type index outside [0, n_types) (treated as type 0) */
 #define NB_STATUS_BAD_EXCLUSION 0x4u  /* an exclusion row not monotone or an index outside the system */
 #define NB_STATUS_FAR_EXCLUSION 0x8u  /* informational: some exclusion is more than 64 atoms apart in index */
-#define NB_STATUS_NOT_BUILT 0x10u     /* the workspace was not built by nb_build_cells for this system size and
-                                         kernel variant: the pair kernels wrote nothing */
+#define NB_STATUS_NOT_BUILT 0x10u     /* the workspace was not built by nb_build_cells for this system size,
+                                         kernel variant, cluster size and split: the pair kernels wrote
+                                         nothing */
 #define NB_STATUS_FAR_PAIR14 0x20u    /* a 1-4 pair more than 64 atoms apart in index: left unscaled */
 #define NB_STATUS_BAD_TOPOLOGY 0x40u  /* MD calls: a water or a bonded term names atoms outside the batch or
                                          in two systems (the term is skipped; such a water's atoms move
@@ -268,7 +269,7 @@ nb_status nb_pme_reciprocal(const nb_system *sys, const nb_params *params, const
  * the process ends.  The caller still passes the outputs.  No hipMalloc, hipFree or
  * other allocating call is made.  Batches whose workspace (nb_workspace_bytes) exceeds
  * NB_NOALLOC_SCRATCH_BYTES are refused with NB_ERR_CAPACITY before any work is enqueued
- * (about 90,000 atoms at the densities of the configurations here).  The first call on a
+ * (about 72,000 atoms at the densities of the configurations here).  The first call on a
  * device looks up that device's copy of the array (hipGetSymbolAddress).  Every call on
  * a GPU uses the same array, which keeps the last call's contents (the build rewrites
  * everything the pair kernel reads): calls that overlap on one GPU, on different streams

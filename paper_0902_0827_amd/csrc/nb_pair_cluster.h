@@ -1244,11 +1244,13 @@ __device__ inline double sum_component(const double *__restrict__ vals, int64_t 
 template <int MODE>
 __global__ void __launch_bounds__(kFinishBlock) k_finish(Dev d, Out o, int S, int nA, double *energy, double *virial,
                                                         int nv, const double *__restrict__ eps, double *grad_sigma,
-                                                        double *grad_eps, int half) {
+                                                        double *grad_eps, int half, uint32_t cluster_key) {
   __shared__ double lds[kFinishBlock / 64][kPart];
   // The pair kernel is complete: its work counters start again from zero next time.
   if (blockIdx.x == 0 && threadIdx.x < kXcds) d.queue[threadIdx.x * kQueueStride] = 0u;
-  if (!built_for(d.status, d.N, true, false, half != 0)) return;
+  // (the pair kernel's own test: a build for another cluster size or split has another
+  // layout, and then nothing is written)
+  if (!built_for(d.status, d.N, true, false, half != 0, cluster_key)) return;
   const int blk = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (blk < nA) {

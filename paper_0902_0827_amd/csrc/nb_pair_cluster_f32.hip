@@ -22,18 +22,19 @@ void launch_cluster_pair(const Plan &p, const Dev &d, const Consts &c, const Out
   if (mode == kEnergy) nv = 1;
   const int extra = (mode == kAdjoint || mode == kVJP) ? ((grad_sigma || grad_eps) ? 2 * p.T : 0) : 0;
   const dim3 fg(static_cast<unsigned>(nA + kPart * p.B + extra));
+  const uint32_t key = static_cast<uint32_t>(p.cluster_size) | (static_cast<uint32_t>(p.split) << 8);
   if (mode == kForces)
     hipLaunchKernelGGL(k_finish<kForces>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
-                       grad_sigma, grad_eps, half ? 1 : 0);
+                       grad_sigma, grad_eps, half ? 1 : 0, key);
   else if (mode == kEnergy)
     hipLaunchKernelGGL(k_finish<kEnergy>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
-                       grad_sigma, grad_eps, half ? 1 : 0);
+                       grad_sigma, grad_eps, half ? 1 : 0, key);
   else if (mode == kVJP)
     hipLaunchKernelGGL(k_finish<kVJP>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
-                       grad_sigma, grad_eps, 0);
+                       grad_sigma, grad_eps, 0, key);
   else
     hipLaunchKernelGGL(k_finish<kAdjoint>, fg, dim3(kFinishBlock), 0, s, d, o, p.split, nA, energy, virial, nv, eps,
-                       grad_sigma, grad_eps, 0);
+                       grad_sigma, grad_eps, 0, key);
 }
 
 }  // namespace nb

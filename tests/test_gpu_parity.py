@@ -554,6 +554,28 @@ def test_pair_kernels_refuse_a_workspace_built_for_another_kernel(chain):
     assert H.read_status(ws) == 0
 
 
+def test_pair_kernels_refuse_a_build_for_another_cluster_size_or_split(chain):
+    """The build writes each launch slot's work item for one cluster size and one number of
+    items per cluster; a forces call with another of either must not run on it."""
+    b = H.device_batch([chain], dtype=torch.float32)
+    p8 = H.make_params(chain.cutoff, chain.beta, H.NB_MIXED, cluster_size=8, split=1)
+    others = [H.make_params(chain.cutoff, chain.beta, H.NB_MIXED, cluster_size=8, split=2),
+              H.make_params(chain.cutoff, chain.beta, H.NB_MIXED, cluster_size=4, split=1)]
+    ws = torch.zeros(max(H.workspace_bytes(b, p) for p in [p8] + others), dtype=torch.uint8, device="cuda")
+    force = torch.full((chain.n, 3), 7.0, dtype=torch.float64, device="cuda")
+    energy = torch.full((1,), 7.0, dtype=torch.float64, device="cuda")
+    for p in others:
+        H.build_cells(b, p8, ws)
+        H.nonbonded_forces(b, p, ws, force, energy)
+        assert H.read_status(ws) & H.NB_STATUS_NOT_BUILT
+        assert float(force.abs().min()) == 7.0 and float(force.abs().max()) == 7.0 and float(energy[0]) == 7.0
+    for p in [p8] + others:
+        H.build_cells(b, p, ws)
+        H.nonbonded_forces(b, p, ws, force, energy)
+        assert H.read_status(ws) == 0
+        assert U.rel_rms(force.cpu().numpy(), U.oracle_for(chain, H.NB_MIXED)["force"]) <= MIXED_TOL
+
+
 def test_half_shell_kernel_refuses_a_build_without_its_accumulators(chain):
     """A build for the full-shell kernel does not zero the half-shell accumulators, so
     the half-shell kernel must neither run on it nor write the outputs."""
