@@ -111,17 +111,16 @@ typedef struct {
 #define NB_MAX_TYPES 64
 
 /* Kernel variants for nb_params.kernel. */
-#define NB_KERNEL_AUTO 0    /* library default for the precision: NB_KERNEL_CLUSTER_HALF on the mixed path,
-                               NB_KERNEL_CLUSTER on the FP64 path */
+#define NB_KERNEL_AUTO 0    /* library default: NB_KERNEL_CLUSTER_HALF (both precisions) */
 #define NB_KERNEL_ATOM 1    /* one lane per i atom, full neighbour shell, j read through the cache */
 #define NB_KERNEL_CLUSTER 2 /* 4- or 8-atom clusters x box-filtered j atoms staged in LDS, 64 pairs per step */
 #define NB_KERNEL_CLUSTER_HALF 3 /* as NB_KERNEL_CLUSTER, each pair once (half of the column stencil),
                                     the other atom's share added by atomics into per-atom accumulators:
-                                    about half the pair work.  Mixed path: 64-bit fixed-point
-                                    accumulators (2^-32 units), bitwise reproducible; FP64 path: FP64
-                                    atomics, so the last bits vary from run to run.  Forces and energies
-                                    agree with the other kernels to rounding.  The adjoint and the force
-                                    VJP use NB_KERNEL_CLUSTER's form. */
+                                    about half the pair work.  The accumulators are 64-bit fixed point
+                                    (2^-32 units; the FP64 path adds a second limb of 2^-64 units), so
+                                    results are bitwise reproducible.  Forces and energies agree with the
+                                    other kernels to rounding.  The adjoint and the force VJP use
+                                    NB_KERNEL_CLUSTER's form. */
 
 #define NB_SCHED_AUTO 0
 #define NB_SCHED_STATIC 1  /* one work item per wave, a grid covering every item */

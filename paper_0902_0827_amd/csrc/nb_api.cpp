@@ -85,18 +85,21 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   p.N = N;
   p.T = sys->n_types;
   p.precision = prm->precision;
-  // Default: the mixed path evaluates each pair once (the half-shell cluster kernel, its
-  // per-atom sums in 64-bit fixed point, so results stay bitwise reproducible), the FP64
-  // path both ways (full shell).  Measured on the 23.6k-atom box: mixed pair kernel 55
-  // against 66 us.
-  p.kernel = prm->kernel != NB_KERNEL_AUTO ? prm->kernel
-             : prm->precision == NB_MIXED ? NB_KERNEL_CLUSTER_HALF : NB_KERNEL_CLUSTER;
+  // Default: each pair evaluated once (the half-shell cluster kernel, its per-atom sums in
+  // 64-bit fixed point, one limb on the mixed path and two on the FP64 path, so results
+  // stay bitwise reproducible).  Measured on the 23.6k-atom box: mixed pair kernel 55
+  // against 66 us; FP64 85 against 119 us (measured with FP64 atomics, before the two
+  // fixed-point limbs).
+  p.kernel = prm->kernel != NB_KERNEL_AUTO ? prm->kernel : NB_KERNEL_CLUSTER_HALF;
   p.split = prm->split;  // 0: chosen below from the cluster count
   p.schedule = prm->schedule == NB_SCHED_DYNAMIC ? NB_SCHED_DYNAMIC : NB_SCHED_STATIC;  // static measured faster
   p.wg_per_cu = prm->wg_per_cu ? prm->wg_per_cu : 16;
-  // Measured on the 23.6k-atom box: 8-atom clusters are faster for FP32 pair math, 4-atom
-  // clusters (fewer wasted out-of-range pairs per FP64 evaluation) for the FP64 path.
-  p.cluster_size = prm->cluster_size ? prm->cluster_size : (p.precision == NB_MIXED ? 8 : 4);
+  // Measured on the 23.6k-atom box: 8-atom clusters are faster for FP32 pair math and for
+  // the half shell (FP64: 89 us against 125 us with 4-atom clusters, whose candidates are
+  // staged twice as often), 4-atom clusters (fewer wasted out-of-range pairs per FP64
+  // evaluation) for the FP64 full shell.
+  p.cluster_size = prm->cluster_size ? prm->cluster_size
+                   : (p.precision == NB_MIXED || p.kernel == NB_KERNEL_CLUSTER_HALF) ? 8 : 4;
   p.div_xy = prm->cell_div_xy ? prm->cell_div_xy : 2;
   // The cluster kernel wants thin z-cells, so that a column's atoms come out nearly z-sorted.
   p.div_z = prm->cell_div_z ? prm->cell_div_z : (p.kernel == NB_KERNEL_ATOM ? p.div_xy : 8);
@@ -194,7 +197,8 @@ nb_status make_plan(const nb_system *sys, const nb_params *prm, Plan *plan) {
   l.col_clu_start = take(4 * static_cast<size_t>(columns + 1));
   l.part = take(32 * static_cast<size_t>(N) * static_cast<size_t>(p.split));
   l.queue = take(4 * static_cast<size_t>(kXcds * kQueueStride));
-  l.jacc = p.kernel == NB_KERNEL_CLUSTER_HALF ? take(32 * static_cast<size_t>(N)) : 0;
+  // half-shell accumulators: 4 components of one 64-bit limb (mixed) or two (FP64)
+  l.jacc = p.kernel == NB_KERNEL_CLUSTER_HALF ? take((p.precision == NB_FP64 ? 64 : 32) * static_cast<size_t>(N)) : 0;
   l.p14_mask = p.has14 ? take(16 * static_cast<size_t>(N)) : 0;
   l.rtab = p.table ? take(16 * static_cast<size_t>(p.table_n + 1) * static_cast<size_t>(p.table)) : 0;
   l.vsort = take(32 * static_cast<size_t>(N));
@@ -251,8 +255,8 @@ Dev dev_view(const Plan &p, void *ws) {
   d.col_info = reinterpret_cast<int4 *>(base + l.col_info);
   d.atom_col = reinterpret_cast<int32_t *>(base + l.atom_col);
   const bool half = p.kernel == NB_KERNEL_CLUSTER_HALF;
-  d.jacc_fix = half && p.precision == NB_MIXED ? reinterpret_cast<long long *>(base + l.jacc) : nullptr;
-  d.jacc_f64 = half && p.precision == NB_FP64 ? reinterpret_cast<double *>(base + l.jacc) : nullptr;
+  d.jacc_fix = half ? reinterpret_cast<long long *>(base + l.jacc) : nullptr;
+  d.jacc_lo = half && p.precision == NB_FP64 ? d.jacc_fix + 4 * p.N : nullptr;
   return d;
 }
 

@@ -165,7 +165,7 @@ __global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, con
     d.status[0] = 0u;
     d.status[1] = kBuiltMagic;
     d.status[2] = static_cast<uint32_t>(d.N);
-    d.status[3] = (uses_clusters(kernel) ? kBuiltClusters : 0u) | (f64 ? kBuiltF64 : 0u) | ((d.jacc_fix || d.jacc_f64) ? kBuiltJacc : 0u);
+    d.status[3] = (uses_clusters(kernel) ? kBuiltClusters : 0u) | (f64 ? kBuiltF64 : 0u) | (d.jacc_fix ? kBuiltJacc : 0u);
     d.status[4] = cluster_key;
   }
   // work-item slots start empty; the build fills those that have an item
@@ -179,7 +179,7 @@ __global__ void k_init(Dev d, DescChunk c, const double *__restrict__ sigma, con
     d.excl_far[k] = 0u;
     for (int c = 0; c < 4; ++c) {
       if (d.jacc_fix) d.jacc_fix[c * d.N + k] = 0;
-      if (d.jacc_f64) d.jacc_f64[c * d.N + k] = 0.0;
+      if (d.jacc_lo) d.jacc_lo[c * d.N + k] = 0;
     }
   }
   if (ta.kind != 0)

@@ -170,10 +170,11 @@ struct Dev {
   // arrays of N (component-major, so that the atomic additions of consecutive atoms
   // coalesce), added up by atomics; zero outside a force or energy call (the build zeroes
   // them and the finishing pass of every call that used them copies them out and zeroes
-  // them again).  Mixed path: 64-bit fixed point (units of 2^-32 kJ/mol/A or kJ/mol), whose
-  // sums do not depend on the order of the additions; FP64 path: doubles.
-  long long *jacc_fix;     // [4][N], null unless the mixed half-shell kernel is selected
-  double *jacc_f64;        // [4][N], null unless the FP64 half-shell kernel is selected
+  // them again).  64-bit fixed point in units of 2^-32 kJ/mol/A (or kJ/mol), whose sums do
+  // not depend on the order of the additions; the FP64 path adds a second limb in units of
+  // 2^-64 (the part of each value below 2^-32), summed apart from the first.
+  long long *jacc_fix;     // [4][N], null unless the half-shell kernel is selected
+  long long *jacc_lo;      // [4][N], the FP64 path's second limbs (null on the mixed path)
 };
 
 // Per-call constants and outputs of the pair kernels.

@@ -52,6 +52,9 @@ constexpr int kRunPad = 4;           // sentinel entries after the last run
 // 128 VGPRs; a few values outside the loops go to scratch); left alone the compiler
 // takes 134 and 3 waves fit.
 constexpr int kF64WavesPerEu = 4;
+// The FP64 half shell with 8-atom clusters has about three items per SIMD on the 23.6k-atom
+// box: held to 168 registers (3 waves per SIMD) it does not spill (88.1 against 88.9 us).
+constexpr int kF64HalfWavesPerEu = 3;
 constexpr int kFinishBlock = 256;
 constexpr int kPairs2WavesPerCu = 16;  // 4 SIMDs x 4 resident waves of the two-group kernel
 // Exclusion window of one i atom in LDS, one byte per index difference: byte d is 1 when
@@ -182,6 +185,23 @@ __device__ __forceinline__ double from_fixed(long long a) {
   const int hi = static_cast<int>(a >> 32);
   const unsigned lo = static_cast<unsigned>(a);
   return (static_cast<double>(hi) * kFixScale + static_cast<double>(lo)) * (1.0 / kFixScale);
+}
+
+// Two limbs for the FP64 path's half-shell accumulators: hi = floor(v 2^32) and lo =
+// round((v 2^32 - hi) 2^32) in [0, 2^32], each summed by integer additions, so that
+// sum(hi) 2^-32 + sum(lo) 2^-64 is the sum of the v to within 2^-64 per term (far below
+// FP64 rounding of forces of order 1) whatever the order of the additions.
+__device__ __forceinline__ void to_fixed2(double v, long long &hi, long long &lo) {
+  const double t = v * kFixScale;  // exact
+  const double th = floor(t);
+  lo = static_cast<long long>(rint((t - th) * kFixScale));
+  const double h = floor(th * (1.0 / kFixScale));
+  const double l = th - h * kFixScale;  // exact, in [0, 2^32)
+  hi = static_cast<long long>((static_cast<unsigned long long>(static_cast<long long>(static_cast<int>(h))) << 32) +
+                              static_cast<unsigned long long>(static_cast<unsigned>(l)));
+}
+__device__ __forceinline__ double from_fixed2(long long hi, long long lo) {
+  return from_fixed(hi) + static_cast<double>(lo) * (1.0 / (kFixScale * kFixScale));
 }
 
 // One step of reduce_scatter below at lane offset OFF, N values still carried.
@@ -369,10 +389,9 @@ __device__ __forceinline__ ItemRec load_item(const ItemRec *items, int slot) {
 // row 0 stages the sums in LDS, and full stages go to the candidates' accumulators by
 // atomic additions, consecutive sorted atoms in consecutive lanes (so that they
 // coalesce); the rows' own sums go there too at the end of the item, and the finishing
-// pass copies the accumulators out.  The pair work halves.  Mixed path: the
-// accumulators are 64-bit fixed point, so the result is bitwise reproducible whatever
-// the order of the additions; FP64 path: FP64 atomics, whose order makes the last bits
-// vary from run to run.
+// pass copies the accumulators out.  The pair work halves.  The accumulators are 64-bit
+// fixed point (two limbs on the FP64 path), so the result is bitwise reproducible
+// whatever the order of the additions.
 //
 // PAIRS2 (mixed path): the group loop takes two groups per pass, which needs more
 // registers (held to 128, 4 resident waves per SIMD instead of 5); the launcher uses it
@@ -384,7 +403,7 @@ constexpr int kVarLin = 2;    // radial terms linearly interpolated from tables 
 constexpr int kVarCub = 3;    // radial terms from cubic Hermite tables (mixed forces / energy)
 
 template <bool F64, int MODE, bool TABLDS, int K, bool HALF, bool PAIRS2, int VAR>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((F64 || PAIRS2) ? kF64WavesPerEu : 1, 8)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((F64 && HALF && K == 8) ? kF64HalfWavesPerEu : (F64 || PAIRS2) ? kF64WavesPerEu : 1, 8)))
 k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   // Products are fused into additions only within one expression (the explicit FMAs
   // aside), so that the copies of the group loop, and the instantiations with one or two
@@ -687,10 +706,14 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     // Half-shell stage: entries [0, nst) hold candidates' shares not yet added.
     int nst = 0;  // wave-uniform
     // Adds v to component c (0-2 force, 3 energy share) of sorted atom a's half-shell
-    // accumulator: 64-bit fixed point on the mixed path, FP64 on the FP64 path.
+    // accumulator: 64-bit fixed point, in two limbs on the FP64 path.
     auto acc_add = [&](int c, int a, double v) {
       if constexpr (F64) {
-        unsafeAtomicAdd(&d.jacc_f64[static_cast<int64_t>(c) * d.N + a], v);
+        long long hi, lo;
+        to_fixed2(v, hi, lo);
+        const int64_t at = static_cast<int64_t>(c) * d.N + a;
+        __hip_atomic_fetch_add(&d.jacc_fix[at], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&d.jacc_lo[at], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         __hip_atomic_fetch_add(&d.jacc_fix[static_cast<int64_t>(c) * d.N + a], to_fixed(v), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
@@ -1258,17 +1281,18 @@ __global__ void __launch_bounds__(kFinishBlock) k_finish(Dev d, Out o, int S, in
     if (i >= d.N) return;
     if (half) {  // half-shell accumulators: copy out, and zero for the next call
       const int oi = static_cast<int>(d.s_fix[i].w);
-      // component c of atom i's accumulator (64-bit fixed point, or FP64), then zeroed
+      // component c of atom i's accumulator (64-bit fixed point, two limbs on the FP64
+      // path), then zeroed
       auto take = [&](int c) -> double {
         const int64_t at = static_cast<int64_t>(c) * d.N + i;
         double v;
-        if (d.jacc_fix) {
-          v = from_fixed(d.jacc_fix[at]);
-          d.jacc_fix[at] = 0;
+        if (d.jacc_lo) {
+          v = from_fixed2(d.jacc_fix[at], d.jacc_lo[at]);
+          d.jacc_lo[at] = 0;
         } else {
-          v = d.jacc_f64[at];
-          d.jacc_f64[at] = 0.0;
+          v = from_fixed(d.jacc_fix[at]);
         }
+        d.jacc_fix[at] = 0;
         return v;
       };
       if constexpr (MODE == kForces) {

@@ -77,6 +77,17 @@ def test_half_shell_kernel_adds_one_accumulator_per_atom():
     assert half - full == (32 * 23600 + 255) // 256 * 256
 
 
+def test_fp64_half_shell_holds_two_limbs_per_component():
+    """The FP64 path's half-shell accumulators are 64-bit fixed point in two limbs: 64 bytes
+    per atom instead of the mixed path's 32."""
+    s = fake_system((23600,), L=60.0)
+    code, full = ws_bytes(s, H.make_params(9.0, 0.34, H.NB_FP64, kernel=H.NB_KERNEL_CLUSTER, cluster_size=8))
+    assert code == H.NB_OK
+    code, half = ws_bytes(s, H.make_params(9.0, 0.34, H.NB_FP64, kernel=H.NB_KERNEL_CLUSTER_HALF, cluster_size=8))
+    assert code == H.NB_OK
+    assert half - full == (64 * 23600 + 255) // 256 * 256
+
+
 def test_layout_reports_the_grid():
     lib = H.load_library()
     lay = H.nb_layout()
