@@ -916,7 +916,10 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
             p.erfc_over_r = hit ? p.erfc_over_r : 0.f;
             p.dudsig_lj = hit ? p.dudsig_lj : 0.f;
           }
-          const float pu = hit ? p.u_lj + p.u_c : 0.f;  // the pair's energy, one select
+          float pu = hit ? p.u_lj + p.u_c : 0.f;  // the pair's energy, one select
+          // (kept in single precision here: converted after the select, not selected in
+          // double after the conversion, which takes two selects)
+          asm volatile("" : "+v"(pu));
           // Per-atom sums (force, energy, dE/dq) take every pair's single-precision term
           // into a double accumulator; the virial is summed per lane in single precision
           // and reduced in double.
