@@ -136,7 +136,7 @@ typedef struct {
   int32_t kernel;     /* NB_KERNEL_* */
   int32_t split;      /* cluster kernel: work items per cluster, each taking an equal share of
                          its candidate j atoms, 1..8 (0 = 1) */
-  int32_t cluster_size; /* cluster kernel: atoms per i-cluster, 4 or 8 (0 = 8 mixed, 4 FP64) */
+  int32_t cluster_size; /* cluster kernel: atoms per i-cluster, 4 or 8 (0 = 8; 4 for the FP64 full shell) */
   int32_t schedule;   /* cluster kernel: NB_SCHED_* (0 = static) */
   int32_t wg_per_cu;  /* dynamic schedule: resident one-wave workgroups per compute unit, 1..32 (0 = 16) */
   double lj_switch_on;/* r_on (A), 0 <= r_on < R; 0 = no switch.  Otherwise the Lennard-Jones term is
