@@ -422,7 +422,18 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
   __shared__ WaveLds<F64, FF> L;
   TypePairLds<F64, MODE> *const TL = reinterpret_cast<TypePairLds<F64, MODE> *>(tab_lds);
   const int lane = static_cast<int>(threadIdx.x);
-  if (!built_for(d.status, d.N, true, F64, HALF, static_cast<uint32_t>(K) | (static_cast<uint32_t>(Q) << 8))) {
+  // Every wave first takes the item of its own launch slot (the build wrote each slot's
+  // record).  The record is loaded together with the build check's status words: the
+  // launch never has more workgroups than the workspace has slots, so the load stays
+  // inside the workspace whatever it holds, and a failed check discards it.
+  int islot = static_cast<int>(blockIdx.x);
+  ItemRec rec = load_item(d.items, islot);
+  const bool built = built_for(d.status, d.N, true, F64, HALF, static_cast<uint32_t>(K) | (static_cast<uint32_t>(Q) << 8));
+  // (held before the branch: otherwise the record's loads are sunk below it and wait for the check)
+  asm volatile("" ::"s"(rec.first), "s"(rec.count), "s"(rec.item), "s"(rec.sys), "s"(rec.cx), "s"(rec.cy),
+               "s"(rec.cz0), "s"(rec.cell_begin), "s"(rec.nx), "s"(rec.ny), "s"(rec.nz), "s"(rec.kx), "s"(rec.ky),
+               "s"(rec.kz), "s"(rec.cz1));
+  if (!built) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(d.status, NB_STATUS_NOT_BUILT);
     return;
   }
@@ -445,11 +456,6 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
       L.ring[k].sidx = make_int2(0, 0);
     }
   }
-  // Every wave first takes the item of its own launch slot (the build wrote each slot's
-  // record); the record's load is issued before the type-pair table's, so that the two
-  // are in flight together.
-  int islot = static_cast<int>(blockIdx.x);
-  ItemRec rec = load_item(d.items, islot);
   if constexpr (TABLDS) {
     for (int k = lane; k < T * T; k += 64) {
       if constexpr (F64 && !ADJ) TL[k] = make_double2(d.tab64[k].c6, d.tab64[k].c12);
@@ -509,35 +515,22 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     if (count == 0) break;  // a slot without an item (the last ones of a range)
     // (Q is uniform; with one item per cluster the division below is skipped)
     const int part = Q == 1 ? 0 : m - (m / Q) * Q;
-    const SysDesc &sd = d.desc[sys];
-    // Per-system constants as wave-uniform scalars: nothing in the pair loop below then
-    // waits on a vector-memory load (so the next chunk's loads stay in flight).
-    const float s2x = uni(sd.scale2f[0]), s2y = uni(sd.scale2f[1]), s2z = uni(sd.scale2f[2]);
-    const double bxx = uni(sd.box[0]), bxy = uni(sd.box[1]), bxz = uni(sd.box[2]);
-    const double ibx = uni(sd.inv_box[0]), iby = uni(sd.inv_box[1]), ibz = uni(sd.inv_box[2]);
-    const int atom_begin = uni(sd.atom_begin);
+    // Per-system constants by scalar loads (the descriptors do not change during the
+    // launch): nothing in the pair loop below then waits on a vector-memory load (so the
+    // next chunk's loads stay in flight), and the set-up's vector loads are not held up
+    // by them.
+    using ConstDesc = const __attribute__((address_space(4))) SysDesc;
+    ConstDesc *sd = (ConstDesc *)(d.desc + sys);
+    const float s2x = sd->scale2f[0], s2y = sd->scale2f[1], s2z = sd->scale2f[2];
+    const double bxx = sd->box[0], bxy = sd->box[1], bxz = sd->box[2];
+    const double ibx = sd->inv_box[0], iby = sd->inv_box[1], ibz = sd->inv_box[2];
+    const int atom_begin = sd->atom_begin;
     const int nx = uni(rec.nx), ny = uni(rec.ny), nz = uni(rec.nz);
     const int cell_begin = uni(rec.cell_begin);
     const int i = first + ii;
     const bool ivalid = ii < count;
     const int ia = ivalid ? i : first;
     const uint4 fi = d.s_fix[ia];
-    const int oi = static_cast<int>(fi.w);
-    // Mixed path: the window byte of candidate oj is oj - oi_lo (unsigned, clamped) in row
-    // ii's window in LDS.  FP64 path: the mask stays in registers (LDS there is what limits
-    // the resident waves).
-    const uint32_t oi_lo = static_cast<uint32_t>(oi) - static_cast<uint32_t>(kWindow);
-    const uint8_t *ex_row = nullptr;
-    if constexpr (!F64 || FF) ex_row = reinterpret_cast<const uint8_t *>(L.exw) + ii * kExBytes;
-    const uint4 mask_i = d.excl_mask[oi];
-    uint4 mask14_i = make_uint4(0u, 0u, 0u, 0u);
-    if constexpr (FF) {
-      if (d.p14_mask) mask14_i = d.p14_mask[oi];
-    }
-    const uint64_t mask_lo = (static_cast<uint64_t>(mask_i.y) << 32) | mask_i.x;
-    const uint64_t mask_hi = (static_cast<uint64_t>(mask_i.w) << 32) | mask_i.z;
-    const bool far_i = d.excl_far[oi] != 0u;
-    const bool any_far = __ballot(ivalid && far_i) != 0;
     const int ti = d.s_type[ia];
     double4 pi64 = make_double4(0, 0, 0, 0);
     float qi32 = 0.f;
@@ -550,36 +543,6 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     if constexpr (MODE == kVJP) {
       vi64 = d.vsort[ia];
       vi32 = make_float4(static_cast<float>(vi64.x), static_cast<float>(vi64.y), static_cast<float>(vi64.z), 0.f);
-    }
-
-    // Bounding box of the cluster, relative to its first atom (minimum image).
-    uint4 ctr, half;
-    {
-      const uint4 u0 = make_uint4(__shfl(fi.x, 0, 64), __shfl(fi.y, 0, 64), __shfl(fi.z, 0, 64), 0u);
-      const int dx = static_cast<int>(fi.x - u0.x), dy = static_cast<int>(fi.y - u0.y),
-                dz = static_cast<int>(fi.z - u0.z);
-      // rows without an atom repeat the first atom (ia = first), so they do not widen the box
-      int lox, loy, loz, hix, hiy, hiz;
-      if constexpr (HALF) {
-        lox = shfl_group_min<K>(dx), loy = shfl_group_min<K>(dy), loz = shfl_group_min<K>(dz);
-        hix = shfl_group_max<K>(dx), hiy = shfl_group_max<K>(dy), hiz = shfl_group_max<K>(dz);
-      } else {
-        lox = shfl_rows_min<J>(dx), loy = shfl_rows_min<J>(dy), loz = shfl_rows_min<J>(dz);
-        hix = shfl_rows_max<J>(dx), hiy = shfl_rows_max<J>(dy), hiz = shfl_rows_max<J>(dz);
-      }
-      const int lo3[3] = {lox, loy, loz}, hi3[3] = {hix, hiy, hiz};
-      const uint32_t base3[3] = {u0.x, u0.y, u0.z};
-      uint32_t cc[3], hh[3];
-      for (int a = 0; a < 3; ++a) {
-        // centre floor((lo + hi) / 2) and half-width max(hi - mid, mid - lo) = ceil(extent / 2),
-        // from the extent hi - lo in 32 bits (it is below 2^32)
-        const uint32_t ext = static_cast<uint32_t>(hi3[a]) - static_cast<uint32_t>(lo3[a]);
-        cc[a] = base3[a] + static_cast<uint32_t>(lo3[a]) + (ext >> 1);
-        hh[a] = (ext >> 1) + (ext & 1u);
-      }
-      // wave-uniform (every row reduced to the same box): keep it in scalar registers
-      ctr = make_uint4(uni(static_cast<int>(cc[0])), uni(static_cast<int>(cc[1])), uni(static_cast<int>(cc[2])), 0u);
-      half = make_uint4(uni(static_cast<int>(hh[0])), uni(static_cast<int>(hh[1])), uni(static_cast<int>(hh[2])), 0u);
     }
 
     // the column, and the z-cells of the cluster's first and last atom
@@ -596,32 +559,6 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     const int ncol = xn * yn;
     int nrun = 0, total = 0;  // wave-uniform
     wave_lds_sync();  // the previous item's reads of the runs and windows are complete
-    // Row ii's window as bytes, 4 per word: bits 0-63 of the mask are j - i = -64..-1,
-    // then j = i, then mask bits 64-127 (j - i = 1..64); word m holds bits 4m..4m+3 of
-    // that 132-bit string, each spread to the low bit of a byte.
-    // FF variants: bit 1 of each byte from the 1-4 window, whose self position is 0.
-    // Lane jj takes words jj, jj + J, ...: pass t reads 32-bit piece (jj + J t) >> 3 of the
-    // string, which is t for every lane when J = 8 and 2 t or 2 t + 1 when J = 16.
-    if constexpr (!F64 || FF) {
-      static_assert(J == 8 || J == 16, "8 or 16 lanes per row");
-      auto piece = [](const uint4 &mk, uint32_t self, int w) -> uint32_t {
-        return w == 0 ? mk.x : w == 1 ? mk.y : w == 2 ? (mk.z << 1) | self : w == 3 ? (mk.w << 1) | (mk.z >> 31) : mk.w >> 31;
-      };
-#pragma unroll
-      for (int t = 0; t < (kExBytes / 4 + J - 1) / J; ++t) {
-        const int m = jj + J * t;
-        const int w0 = (J / 8) * t, w1 = w0 + 1 < 4 ? w0 + 1 : 4;  // the pass's pieces
-        const bool second = J == 16 && (jj & 8);
-        auto spread = [&](const uint4 &mk, uint32_t self) -> uint32_t {
-          const uint32_t src = second ? piece(mk, self, w1) : piece(mk, self, w0);
-          const uint32_t nib = (src >> ((m & 7) * 4)) & 15u;
-          return (nib * 0x00204081u) & 0x01010101u;
-        };
-        uint32_t word = spread(mask_i, 1u);
-        if constexpr (FF) word |= spread(mask14_i, 0u) << 1;
-        if (m < kExBytes / 4) L.exw[ii * (kExBytes / 4) + m] = word;
-      }
-    }
     for (int k0 = 0; k0 < ncol; k0 += 64) {
       const int k = k0 + lane;
       int2 r0 = make_int2(0, 0), r1 = make_int2(0, 0);
@@ -632,20 +569,24 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
         int y = ally ? oy : cy - ky + oy;
         y += y < 0 ? ny : (y >= ny ? -ny : 0);
         const int cb = cell_begin + (x * ny + y) * nz;
-        if (allz) {
-          r0 = make_int2(d.cell_start[cb], d.cell_start[cb + nz]);
-        } else {
+        // The window's cell starts, [a0, a1) and, where it wraps, [b0, b1): the indices are
+        // chosen first and the four loads issued together, in one round with the row atoms'
+        // loads (b0 = b1 = cb when there is one run).
+        int a0 = cb, a1 = cb + nz, b0 = cb, b1 = cb;
+        bool two = false;
+        if (!allz) {
           const int z0 = cz0 - kz, z1 = cz1 + kz + 1;  // [z0, z1)
           if (z0 < 0) {
-            r0 = make_int2(d.cell_start[cb + z0 + nz], d.cell_start[cb + nz]);
-            r1 = make_int2(d.cell_start[cb], d.cell_start[cb + z1]);
+            a0 = cb + z0 + nz, b1 = cb + z1, two = true;
           } else if (z1 > nz) {
-            r0 = make_int2(d.cell_start[cb + z0], d.cell_start[cb + nz]);
-            r1 = make_int2(d.cell_start[cb], d.cell_start[cb + z1 - nz]);
+            a0 = cb + z0, b1 = cb + z1 - nz, two = true;
           } else {
-            r0 = make_int2(d.cell_start[cb + z0], d.cell_start[cb + z1]);
+            a0 = cb + z0, a1 = cb + z1;
           }
         }
+        r0 = make_int2(d.cell_start[a0], d.cell_start[a1]);
+        const int2 rb = make_int2(d.cell_start[b0], d.cell_start[b1]);
+        if (two) r1 = rb;
       }
       if constexpr (HALF) {
         // Half stencil: a neighbour column is taken when its offset is positive in x,
@@ -683,6 +624,27 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     const int hi_c = Q == 1 ? total : static_cast<int>((static_cast<int64_t>(total) * (part + 1)) / Q);
     wave_lds_sync();  // the runs are visible to every lane
 
+    // The row atom's exclusion windows, by its original index, are loaded once the runs are
+    // built (with the first candidates below, in one round of loads).
+    const int oi = static_cast<int>(fi.w);
+    // Mixed path: the window byte of candidate oj is oj - oi_lo (unsigned, clamped) in row
+    // ii's window in LDS.  FP64 path: the mask stays in registers (LDS there is what limits
+    // the resident waves).
+    const uint32_t oi_lo = static_cast<uint32_t>(oi) - static_cast<uint32_t>(kWindow);
+    const uint8_t *ex_row = nullptr;
+    if constexpr (!F64 || FF) ex_row = reinterpret_cast<const uint8_t *>(L.exw) + ii * kExBytes;
+    const uint4 mask_i = d.excl_mask[oi];
+    uint4 mask14_i = make_uint4(0u, 0u, 0u, 0u);
+    if constexpr (FF) {
+      if (d.p14_mask) mask14_i = d.p14_mask[oi];
+    }
+    const uint64_t mask_lo = (static_cast<uint64_t>(mask_i.y) << 32) | mask_i.x;
+    const uint64_t mask_hi = (static_cast<uint64_t>(mask_i.w) << 32) | mask_i.z;
+    const bool far_i = d.excl_far[oi] != 0u;
+    bool any_far = false;  // (set below, once the first candidates' loads are issued)
+
+    uint4 ctr, half;  // the cluster's bounding box (below)
+
     // Per-lane sums for row ii's atom: force, energy (or dE/dq) and the per-type adjoint
     // sums in double for both paths (the mixed path adds each pair's single-precision
     // terms to them).  The virial: double on the FP64 path; on the mixed path single
@@ -700,8 +662,7 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     uint32_t head = 0, tail = 0;  // wave-uniform ring positions
 
     // Mixed path: fixed-point units -> Angstrom, and phi carries one sqrt(k_e) from q'_j.
-    const double scx = F64 ? 1.0 : uni(sd.scale[0]), scy = F64 ? 1.0 : uni(sd.scale[1]),
-                 scz = F64 ? 1.0 : uni(sd.scale[2]);
+    const double scx = F64 ? 1.0 : sd->scale[0], scy = F64 ? 1.0 : sd->scale[1], scz = F64 ? 1.0 : sd->scale[2];
 
     // Half-shell stage: entries [0, nst) hold candidates' shares not yet added.
     int nst = 0;  // wave-uniform
@@ -1054,9 +1015,67 @@ k_pair_cluster(Dev d, Consts c, Out o, int Q, int dynamic) {
     bool valid = false;
     int sj = 0;
     double4 vj = make_double4(0, 0, 0, 0);  // force VJP: the candidate's v (sorted copy)
-    wait_vm_loads();  // the cluster's own data has arrived before the pair loop starts
+    // The first chunk's loads are issued with the row atoms' windows (above), in one
+    // round; the windows are spread to LDS meanwhile, and the chunk loop's first LDS
+    // barrier makes them visible.
     int P = lo_c;
     if (P < hi_c) load(P, fj, tj, qj, pj64, valid, sj, vj);
+    // Bounding box of the cluster, relative to its first atom (minimum image).
+    {
+      const uint4 u0 = make_uint4(__shfl(fi.x, 0, 64), __shfl(fi.y, 0, 64), __shfl(fi.z, 0, 64), 0u);
+      const int dx = static_cast<int>(fi.x - u0.x), dy = static_cast<int>(fi.y - u0.y),
+                dz = static_cast<int>(fi.z - u0.z);
+      // rows without an atom repeat the first atom (ia = first), so they do not widen the box
+      int lox, loy, loz, hix, hiy, hiz;
+      if constexpr (HALF) {
+        lox = shfl_group_min<K>(dx), loy = shfl_group_min<K>(dy), loz = shfl_group_min<K>(dz);
+        hix = shfl_group_max<K>(dx), hiy = shfl_group_max<K>(dy), hiz = shfl_group_max<K>(dz);
+      } else {
+        lox = shfl_rows_min<J>(dx), loy = shfl_rows_min<J>(dy), loz = shfl_rows_min<J>(dz);
+        hix = shfl_rows_max<J>(dx), hiy = shfl_rows_max<J>(dy), hiz = shfl_rows_max<J>(dz);
+      }
+      const int lo3[3] = {lox, loy, loz}, hi3[3] = {hix, hiy, hiz};
+      const uint32_t base3[3] = {u0.x, u0.y, u0.z};
+      uint32_t cc[3], hh[3];
+      for (int a = 0; a < 3; ++a) {
+        // centre floor((lo + hi) / 2) and half-width max(hi - mid, mid - lo) = ceil(extent / 2),
+        // from the extent hi - lo in 32 bits (it is below 2^32)
+        const uint32_t ext = static_cast<uint32_t>(hi3[a]) - static_cast<uint32_t>(lo3[a]);
+        cc[a] = base3[a] + static_cast<uint32_t>(lo3[a]) + (ext >> 1);
+        hh[a] = (ext >> 1) + (ext & 1u);
+      }
+      // wave-uniform (every row reduced to the same box): keep it in scalar registers
+      ctr = make_uint4(uni(static_cast<int>(cc[0])), uni(static_cast<int>(cc[1])), uni(static_cast<int>(cc[2])), 0u);
+      half = make_uint4(uni(static_cast<int>(hh[0])), uni(static_cast<int>(hh[1])), uni(static_cast<int>(hh[2])), 0u);
+    }
+    any_far = __ballot(ivalid && far_i) != 0;
+    // Row ii's window as bytes, 4 per word: bits 0-63 of the mask are j - i = -64..-1,
+    // then j = i, then mask bits 64-127 (j - i = 1..64); word m holds bits 4m..4m+3 of
+    // that 132-bit string, each spread to the low bit of a byte.
+    // FF variants: bit 1 of each byte from the 1-4 window, whose self position is 0.
+    // Lane jj takes words jj, jj + J, ...: pass t reads 32-bit piece (jj + J t) >> 3 of the
+    // string, which is t for every lane when J = 8 and 2 t or 2 t + 1 when J = 16.
+    if constexpr (!F64 || FF) {
+      static_assert(J == 8 || J == 16, "8 or 16 lanes per row");
+      auto piece = [](const uint4 &mk, uint32_t self, int w) -> uint32_t {
+        return w == 0 ? mk.x : w == 1 ? mk.y : w == 2 ? (mk.z << 1) | self : w == 3 ? (mk.w << 1) | (mk.z >> 31) : mk.w >> 31;
+      };
+#pragma unroll
+      for (int t = 0; t < (kExBytes / 4 + J - 1) / J; ++t) {
+        const int m = jj + J * t;
+        const int w0 = (J / 8) * t, w1 = w0 + 1 < 4 ? w0 + 1 : 4;  // the pass's pieces
+        const bool second = J == 16 && (jj & 8);
+        auto spread = [&](const uint4 &mk, uint32_t self) -> uint32_t {
+          const uint32_t src = second ? piece(mk, self, w1) : piece(mk, self, w0);
+          const uint32_t nib = (src >> ((m & 7) * 4)) & 15u;
+          return (nib * 0x00204081u) & 0x01010101u;
+        };
+        uint32_t word = spread(mask_i, 1u);
+        if constexpr (FF) word |= spread(mask14_i, 0u) << 1;
+        if (m < kExBytes / 4) L.exw[ii * (kExBytes / 4) + m] = word;
+      }
+    }
+    wait_vm_loads();  // the cluster's own data and the first chunk have arrived
     bool requested = false;
     while (P < hi_c) {
       const int Pn = P + 64;

@@ -65,7 +65,10 @@ def _items(system, divs, K, half):
                         idx = [(cb + z0, cb + nz), (cb, cb + z1 - nz)]
                     else:
                         idx = [(cb + z0, cb + z1)]
-                for a, c in idx:
+                # the kernel loads four cell starts for every column: with one run the
+                # second pair is (cb, cb), read and discarded
+                reads = idx if len(idx) == 2 else idx + [(cb, cb)]
+                for a, c in reads:
                     assert 0 <= a <= len(cs) - 1 and 0 <= c <= len(cs) - 1
                     max_index = max(max_index, a, c)
                 rr = [[int(cs[a]), int(cs[c])] for a, c in idx]
