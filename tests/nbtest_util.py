@@ -142,3 +142,20 @@ def oracle_binning(systems, precision, divs):
         atom0 += s.n
     return dict(cell_start=np.concatenate(starts), order=np.concatenate(orders),
                 sorted_fixed=np.concatenate(fixed) if fixed else np.zeros((0, 3), np.uint32))
+
+def lattice_system(box, spacing, seed, cutoff=8.0, beta=0.34):
+    """Atoms on a jittered lattice in an orthorhombic box (no close contacts), two LJ
+    types, alternating charges, and exclusions between consecutive atoms in threes."""
+    rng = np.random.default_rng(seed)
+    n = [int(L // spacing) for L in box]
+    g = np.stack(np.meshgrid(*[np.arange(k) for k in n], indexing="ij"), -1).reshape(-1, 3)
+    pos = (g + 0.5) * (np.asarray(box) / n) + rng.uniform(-0.3, 0.3, g.shape)
+    N = len(pos)
+    rows = [[j for j in (3 * (i // 3) + k for k in range(3)) if j != i and j < N] for i in range(N)]
+    off = np.zeros(N + 1, np.int32)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    return S.System(name="lattice", pos=np.mod(pos, box), charge=np.where(np.arange(N) % 2 == 0, 0.41, -0.41),
+                    type=(rng.random(N) < 0.3).astype(np.int32), sigma=np.array([3.15, 2.5]),
+                    eps=np.array([0.63, 0.2]), excl_offset=off,
+                    excl_index=np.array([j for r in rows for j in r], np.int32),
+                    box=np.asarray(box, np.float64), cutoff=cutoff, beta=beta, seed=seed)

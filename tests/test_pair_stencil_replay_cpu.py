@@ -16,6 +16,7 @@ and the GPU parity tests hold the build to bit for bit."""
 import numpy as np
 import pytest
 
+import nbtest_util as U
 from oracle import binning as OB
 from paper_0902_0827_amd import systems as S
 
@@ -145,3 +146,12 @@ def test_stencil_on_a_box_the_stencil_spans(half):
     """648 atoms, L = 18.6 A, R = 9 A: 4 cells per axis against a 5-column stencil, so
     every column is visited once (the dedupe case) and the half rule uses column order."""
     _check(S.config1(), (2, 2, 8), 8 if half else 4, half)
+
+
+@pytest.mark.parametrize("half", [True, False])
+@pytest.mark.parametrize("box", [(18.5, 19.0, 90.0), (90.0, 88.0, 18.5)])
+def test_stencil_on_elongated_and_slab_boxes(box, half):
+    """R = 8 A: the stencil spans the box in x and y but not in z (elongated), or in z
+    only (slab); the boxes of the GPU geometry tests."""
+    nrun, npairs = _check(U.lattice_system(box, 2.6, seed=31), (2, 2, 8), 8 if half else 4, half)
+    assert nrun <= K_MAX_RUNS and npairs > 0
