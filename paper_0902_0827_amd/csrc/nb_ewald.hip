@@ -177,6 +177,11 @@ __global__ void __launch_bounds__(kBlock) k_ewald_far(Dev d, const T *__restrict
                                                       double *force) {
   const int blk = blockIdx.x;
   if (!built_for(d.status, d.N, false, false)) return;
+  // The build flags every atom with an exclusion beyond the window and, with the first
+  // of them, the status word: without that bit no atom has work here (one scalar load
+  // per workgroup instead of a flag per atom).
+  using ConstU32 = const __attribute__((address_space(4))) uint32_t;
+  if ((((ConstU32 *)d.status)[0] & NB_STATUS_FAR_EXCLUSION) == 0u) return;
   const int b = find_desc<&SysDesc::blk_begin>(d.desc, d.B, blk);
   const SysDesc &sd = d.desc[b];
   const int i = sd.atom_begin + (blk - sd.blk_begin) * kBlock + static_cast<int>(threadIdx.x);
