@@ -661,8 +661,8 @@ def main():
                      "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
                      "launch_us": m["pair_sec"] * 1e6, "flops_per_pair": FLOPS_PER_PAIR,
-                     # the same rate counted with the survey's proposed 55 flops per pair
-                     # (forces + energy, no virial): the unit mapping is in the design notes
+                     # the same rate counted at 55 flops per pair (forces and energy without
+                     # the virial, the dU/dsigma term and the box-unit scaling of r^2)
                      "frac_55_flops_per_pair": pairs * 55 / m["pair_sec"] / 1e12 / FP32_PEAK_TFLOPS},
         "cpu_baseline": cpu,
         # nb_build_cells + nb_nonbonded_backward (dE/dx, dE/dq, dE/dsigma_t, dE/deps_t), errors
