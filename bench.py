@@ -507,6 +507,8 @@ def main():
     log(f"[bench] workload {s.name}: N={s.n} L={s.box[0]} rc={s.cutoff} beta={s.beta}")
 
     results = {}
+    # the force VJP's cotangent v (L = sum_i v_i . F_i), seeded, shared by the GPU and the oracle
+    v_vjp = np.random.default_rng(7).standard_normal((s.n, 3))
     paths = [("mixed", H.NB_MIXED, torch.float32)]
     if args.paths == "both":
         paths.append(("fp64", H.NB_FP64, torch.float64))
@@ -548,12 +550,27 @@ def main():
         adjoint = dict(sec=t_adj["sec"], pair_sec=t_adj["pair_sec"], steps=adj_steps, grad_pos=g_x.cpu().numpy(),
                        grad_charge=g_q.cpu().numpy(), grad_sigma=g_s.cpu().numpy(), grad_eps=g_p.cpu().numpy())
         log(f"[bench] {prec_name} adjoint: {t_adj['sec'] * 1e3:.4f} ms/step, pair kernel {t_adj['pair_sec'] * 1e6:.1f} us")
+        # the force VJP (dL/dq, dL/dsigma_t, dL/deps_t): build + VJP
+        v_dev = torch.as_tensor(v_vjp, dtype=torch.float64, device="cuda").contiguous()
+        v_q = torch.empty(s.n, dtype=torch.float64, device="cuda")
+        v_s = torch.empty(T, dtype=torch.float64, device="cuda")
+        v_e = torch.empty(T, dtype=torch.float64, device="cuda")
+
+        def vjp_step():
+            H.build_cells(b, p, ws)
+            H.nonbonded_force_vjp(b, p, ws, v_dev, v_q, v_s, v_e)
+
+        t_vjp = time_steps(vjp_step, adj_steps, args.warmup, torch, H)
+        vjp = dict(sec=t_vjp["sec"], pair_sec=t_vjp["pair_sec"], steps=adj_steps, q=v_q.cpu().numpy(),
+                   sigma=v_s.cpu().numpy(), eps=v_e.cpu().numpy())
+        log(f"[bench] {prec_name} force VJP: {t_vjp['sec'] * 1e3:.4f} ms/step, pair kernel {t_vjp['pair_sec'] * 1e6:.1f} us")
         ewald = ewald_rate(b, p, ws, prec_name, steps, torch, H)
         log(f"[bench] {prec_name} Ewald corrections: {ewald['us_per_call']:.2f} us per call")
         pme = pme_rate(b, p, prec_name, steps, torch, H)
         log(f"[bench] {prec_name} PME reciprocal {PME_GRID}: {pme['us_per_call']:.2f} us per call")
         results[prec_name] = dict(t, steps=steps, force=force.cpu().numpy(), energy=float(energy.cpu()[0]),
-                                  status=H.read_status(ws), build=build, adjoint=adjoint, ewald=ewald, pme=pme)
+                                  status=H.read_status(ws), build=build, adjoint=adjoint, vjp=vjp, ewald=ewald,
+                                  pme=pme)
         log(f"[bench] {prec_name}: {t['sec'] * 1e3:.4f} ms/step (median {t['median'] * 1e3:.4f}), "
             f"pair kernel {t['pair_sec'] * 1e6:.1f} us over {t['pair_launches']} launches")
 
@@ -567,11 +584,13 @@ def main():
     from oracle import pme as PO
     ref_ew, t_ew = {}, []
     ref_pme, t_pme = {}, []
+    ref_vjp = {}
     for prec_name, sys_in in (("mixed", s.rounded(np.float32)), ("fp64", s))[:len(paths)]:
         t0 = time.perf_counter()
         ref[prec_name] = O.evaluate_system(sys_in, ke=H.COULOMB_K)
         t_cpu.append(time.perf_counter() - t0)
         reps += 1
+        ref_vjp[prec_name] = O.evaluate_system(sys_in, ke=H.COULOMB_K, vjp=v_vjp)
         t0 = time.perf_counter()
         ref_ew[prec_name] = O.ewald_corrections_system(sys_in, ke=H.COULOMB_K)
         t_ew.append(time.perf_counter() - t0)
@@ -614,6 +633,14 @@ def main():
                 "pair_kernel_us": a["pair_sec"] * 1e6,
                 "rel_rms_grad_pos": rel(a["grad_pos"], -r["force"]), "rel_rms_grad_charge": rel(a["grad_charge"], r["phi"]),
                 "rel_grad_sigma": rel(a["grad_sigma"], r["dsigma"]), "rel_grad_eps": rel(a["grad_eps"], r["deps"])}
+    def vjp_entry(res, r):
+        a = res["vjp"]
+        rel = lambda x, y: float(np.linalg.norm(np.asarray(x) - y) / max(np.linalg.norm(y), 1e-300))
+        lj = s.eps > 0
+        return {"value": 1.0 / a["sec"], "unit": "evals/s", "ms_per_step": a["sec"] * 1e3, "steps": a["steps"],
+                "pair_kernel_us": a["pair_sec"] * 1e6, "rel_rms_vjp_charge": rel(a["q"], r["vjp_charge"]),
+                "rel_vjp_sigma": rel(a["sigma"][lj], r["vjp_sigma"][lj]),
+                "rel_vjp_eps": rel(a["eps"][lj], r["vjp_eps"][lj])}
     def ewald_entry(ew, r):
         return {"us_per_call": ew["us_per_call"], "calls": ew["calls"], "bytes_per_call": ew["bytes"],
                 "achieved": ew["achieved"], "frac": ew["frac"],
@@ -668,6 +695,8 @@ def main():
         # nb_build_cells + nb_nonbonded_backward (dE/dx, dE/dq, dE/dsigma_t, dE/deps_t), errors
         # against the oracle's gradients
         "adjoint": {name: adjoint_entry(results[name], ref[name]) for name in results},
+        # nb_nonbonded_force_vjp after a build, v seeded (rng 7), against the oracle's VJP
+        "force_vjp": {name: vjp_entry(results[name], ref_vjp[name]) for name in results},
         "batch": batch,
         # the million-atom box: mixed forward and adjoint, FP64 path, binning at this size,
         # errors on sampled oracle rows and against the FP64 GPU path
