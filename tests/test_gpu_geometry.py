@@ -95,3 +95,33 @@ def test_atoms_exactly_on_the_box_faces(precision, kernel):
         where = {int(o): k for k, o in enumerate(ws["sorted_fixed"][:, 3])}
         assert ws["sorted_fixed"][where[0], 0] == 0
         assert ws["sorted_fixed"][where[1], 1] == 0 and ws["sorted_fixed"][where[2], 2] == 0
+
+
+@pytest.mark.parametrize("precision", [H.NB_FP64, H.NB_MIXED])
+@pytest.mark.parametrize("shape", ["elongated", "slab"])
+def test_adjoint_and_force_vjp_on_elongated_and_slab_boxes(shape, precision):
+    s = U.lattice_system(SHAPES[shape], 2.6, seed=31)
+    _print_case("shape-gradients", shape=shape, precision=precision, n=s.n)
+    out = U.gpu_eval(s, precision, backward=True)
+    v = np.random.default_rng(13).standard_normal((s.n, 3))
+    ref = U.oracle_for(s, precision, vjp=v)
+    tol = 1e-11 if precision == H.NB_FP64 else TOL[precision]
+    U.assert_forces(out["grad_pos"], -ref["force"], precision, tol)
+    assert U.rel_rms(out["grad_charge"], ref["phi"]) <= tol
+    np.testing.assert_allclose(out["grad_sigma"], ref["dsigma"], rtol=tol * 10, atol=tol)
+    np.testing.assert_allclose(out["grad_eps"], ref["deps"], rtol=tol * 10, atol=tol)
+    b, p, ws = out["batch"], out["params"], out["ws"]
+    T = b.sigma.shape[0]
+    vd = torch.as_tensor(v, dtype=torch.float64, device="cuda").contiguous()
+    gq = torch.full((b.n_atoms,), np.nan, dtype=torch.float64, device="cuda")
+    gs = torch.full((T,), np.nan, dtype=torch.float64, device="cuda")
+    ge = torch.full((T,), np.nan, dtype=torch.float64, device="cuda")
+    H.nonbonded_force_vjp(b, p, ws, vd, gq, gs, ge)
+    torch.cuda.synchronize()
+    vtol = 1e-11 if precision == H.NB_FP64 else 2e-5
+    assert U.rel_rms(gq.cpu().numpy(), ref["vjp_charge"]) <= vtol
+    np.testing.assert_allclose(gs.cpu().numpy(), ref["vjp_sigma"], rtol=vtol * 10,
+                               atol=vtol * np.abs(ref["vjp_sigma"]).max())
+    np.testing.assert_allclose(ge.cpu().numpy(), ref["vjp_eps"], rtol=vtol * 10,
+                               atol=vtol * np.abs(ref["vjp_eps"]).max())
+    assert H.read_status(ws) == 0
